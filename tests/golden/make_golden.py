@@ -1,0 +1,78 @@
+"""Writes the stored expected values under tests/golden/.
+
+Calls only the oracle (and the seeded input generators).  Each output file
+records the command and the oracle routine that produced it.
+
+    python tests/golden/make_golden.py [name ...]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import fem, paro, reference  # noqa: E402
+from paper_1405_0260_amd import inputs  # noqa: E402
+
+
+def save(name, arr, header):
+    path = os.path.join(HERE, name)
+    np.savetxt(path, np.atleast_1d(arr), fmt="%.17g",
+               header=header + "\nwritten by: python tests/golden/make_golden.py")
+    print("wrote", path)
+
+
+def harmonic_48c():
+    nc = 48
+    mesh = fem.kuhn_mesh(nc, -6.0, 6.0)
+    H, M = fem.hamiltonian(mesh, inputs.harmonic_potential(nc, -6.0, 6.0))
+    lam, _ = reference.sparse_lowest(H, M, 10, -0.5)
+    save("harmonic_48c_lowest10.txt", lam,
+         "Lowest 10 P1 eigenvalues, V=|x|^2/2, box [-6,6]^3, 48^3 Kuhn cells\n"
+         "oracle.reference.sparse_lowest (shift-invert Lanczos)")
+
+
+def harmonic_24c():
+    """Config of the 30-step plain FP64 run: the converged pairs and the
+    ParO iterate after 30 steps from the seeded start."""
+    w = inputs.harmonic_24()
+    mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+    H, M = fem.hamiltonian(mesh, w.V)
+    lam, _ = reference.sparse_lowest(H, M, 10, -0.5)
+    save("harmonic_24c_lowest10.txt", lam,
+         "Lowest 10 P1 eigenvalues, V=|x|^2/2, box [-6,6]^3, 24^3 Kuhn cells\n"
+         "oracle.reference.sparse_lowest (shift-invert Lanczos)")
+    r = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=30,
+                        rtol=1e-12)
+    save("harmonic_24c_paro30_lambda.txt", r.lam_all,
+         "ParO iterate after 30 steps, N=4, m=0, orbital seed 1, sigma=0,\n"
+         "PCG rtol 1e-12: oracle.paro.paro_solve")
+    hist = np.array(r.lam_history)
+    save("harmonic_24c_paro30_history.txt", hist,
+         "Ritz values per ParO step (row 0 = Rayleigh-Ritz of the seeded "
+         "start)\noracle.paro.paro_solve, same run as paro30_lambda")
+
+
+def molecule_64c():
+    w = inputs.molecule_64()
+    mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+    H, M = fem.hamiltonian(mesh, w.V)
+    s = paro.shift_from_potential(w.V)
+    t = time.time()
+    lam, _ = reference.sparse_lowest(H, M, w.Nt + 1, s)
+    save("softcoulomb_64c_lowest.txt", lam,
+         f"Lowest {w.Nt + 1} P1 eigenvalues of the 8-centre soft-Coulomb "
+         "workload, 64^3 cells on [-10,10]^3\n"
+         f"oracle.reference.sparse_lowest about sigma={s!r} "
+         f"({time.time() - t:.0f} s)")
+
+
+JOBS = {"harmonic_48c": harmonic_48c, "harmonic_24c": harmonic_24c,
+        "molecule_64c": molecule_64c}
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(JOBS)):
+        JOBS[name]()

@@ -1,0 +1,167 @@
+"""Pins for the oracle's mesh and finite-element matrices (CPU).
+
+Each check is fixed by something other than the oracle's own formulas:
+counting, textbook closed forms for the Kuhn stencils, and an independent
+monomial integration over the reference simplex."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_1405_0260_amd import inputs
+
+
+def centre_row(nc):
+    m = nc - 1
+    c = nc // 2 - 1
+    return c + m * (c + m * c), m
+
+
+@pytest.mark.parametrize("nc", [2, 3, 5])
+def test_mesh_counts_and_volumes(nc):
+    mesh = fem.kuhn_mesh(nc, -1.0, 2.0)
+    assert mesh.tets.shape == (6 * nc ** 3, 4)
+    assert mesh.n_dof == (nc - 1) ** 3
+    vol, _ = fem.element_geometry(mesh)
+    h = 3.0 / nc
+    assert np.allclose(vol, h ** 3 / 6.0, rtol=1e-14)
+    assert abs(vol.sum() - 27.0) < 1e-12
+    # Each interior vertex belongs to 24 tetrahedra (8 cubes: 6 + 6 + 6 * 2).
+    counts = np.bincount(mesh.tets.ravel(), minlength=mesh.X.shape[0])
+    assert np.all(counts[mesh.dof >= 0] == 24)
+    # Conformity: every tet face is shared by at most two tets and interior
+    # faces by exactly two.
+    faces = {}
+    for t in mesh.tets:
+        for f in itertools.combinations(sorted(t), 3):
+            faces[f] = faces.get(f, 0) + 1
+    assert max(faces.values()) == 2
+
+
+def test_stiffness_is_seven_point_laplacian():
+    """On the Kuhn mesh the P1 stiffness row is h (6, -1 on axis neighbours,
+    0 elsewhere): the classical 7-point stencil times h."""
+    nc = 8
+    mesh = fem.kuhn_mesh(nc, 0.0, 4.0)
+    h = mesh.h
+    K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    c, m = centre_row(nc)
+    row = K.getrow(c)
+    ref = {0: 6.0, 1: -1.0, -1: -1.0, m: -1.0, -m: -1.0, m * m: -1.0,
+           -m * m: -1.0}
+    got = {int(j - c): v / h for j, v in zip(row.indices, row.data)}
+    for off, v in got.items():
+        assert abs(v - ref.get(off, 0.0)) < 1e-12, (off, v)
+    assert all(off in got for off in ref)
+
+
+def test_mass_stencil_closed_form():
+    """Consistent P1 mass on the Kuhn mesh: h^3 (2/5 centre; 1/20 on the 6
+    axis and 2 body-diagonal neighbours; 1/30 on the 6 face diagonals that
+    follow the cube diagonal).  Derived by counting the tets around each
+    edge (6, 6 and 4) times |T|/20."""
+    nc = 8
+    mesh = fem.kuhn_mesh(nc, -1.0, 1.0)
+    h = mesh.h
+    _, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    c, m = centre_row(nc)
+    ax = [1, m, m * m]
+    ref = {0: 2 / 5}
+    for a in ax:
+        ref[a] = ref[-a] = 1 / 20
+    for a, b in itertools.combinations(ax, 2):
+        ref[a + b] = ref[-(a + b)] = 1 / 30
+    ref[1 + m + m * m] = ref[-(1 + m + m * m)] = 1 / 20
+    row = M.getrow(c)
+    got = {int(j - c): v / h ** 3 for j, v in zip(row.indices, row.data)}
+    assert set(got) == set(ref)
+    for off in ref:
+        assert abs(got[off] - ref[off]) < 1e-14, off
+    # int phi_i = (24 |T|) / 4 = h^3.
+    assert abs(sum(got.values()) - 1.0) < 1e-14
+
+
+def test_nnz_formula_and_symmetry():
+    for nc in (3, 6, 9):
+        mesh = fem.kuhn_mesh(nc, 0.0, 1.0)
+        V = inputs.harmonic_potential(nc, 0.0, 1.0)
+        H, M = fem.hamiltonian(mesh, V)
+        m = nc - 1
+        z = m ** 3 + 6 * m * m * (m - 1) + 6 * m * (m - 1) ** 2 \
+            + 2 * (m - 1) ** 3
+        assert H.nnz == z and M.nnz == z
+        assert abs(H - H.T).max() < 1e-15
+        assert abs(M - M.T).max() < 1e-15
+
+
+def test_potential_mass_constant_is_scaled_mass():
+    nc = 5
+    mesh = fem.kuhn_mesh(nc, -2.0, 2.0)
+    _, M, MV = fem.assemble(mesh, np.full(mesh.X.shape[0], -3.25))
+    assert abs(MV + 3.25 * M).max() < 1e-14
+
+
+def _poly_mul(p, q):
+    out = {}
+    for (a, ca) in p.items():
+        for (b, cb) in q.items():
+            k = (a[0] + b[0], a[1] + b[1], a[2] + b[2])
+            out[k] = out.get(k, 0.0) + ca * cb
+    return out
+
+
+def _simplex_integral(p):
+    """int over the unit simplex of a polynomial {(a,b,c): coeff}, using
+    int x^a y^b z^c = a! b! c! / (a + b + c + 3)!."""
+    return sum(c * math.factorial(a) * math.factorial(b) * math.factorial(d)
+               / math.factorial(a + b + d + 3) for (a, b, d), c in p.items())
+
+
+def test_potential_mass_exact_for_linear_potential():
+    """For linear V the interpolant is exact, so the element matrix equals
+    int_T V phi_a phi_b.  Recomputed here by pulling back to the unit
+    simplex and integrating monomials."""
+    nc = 3
+    mesh = fem.kuhn_mesh(nc, -1.0, 2.0)
+    coef = np.array([0.7, -1.3, 2.1])
+    V = 0.4 + mesh.X @ coef
+    _, _, MV = fem.element_matrices(mesh, V)
+    for t in (0, 17, 5 * nc ** 3 + 3):
+        P = mesh.X[mesh.tets[t]]
+        J = (P[1:] - P[0]).T                 # x = P0 + J xi
+        det = abs(np.linalg.det(J))
+        # Barycentrics on the unit simplex, as polynomials in xi.
+        lam = [{(0, 0, 0): 1.0, (1, 0, 0): -1.0, (0, 1, 0): -1.0,
+                (0, 0, 1): -1.0},
+               {(1, 0, 0): 1.0}, {(0, 1, 0): 1.0}, {(0, 0, 1): 1.0}]
+        g = coef @ J
+        Vp = {(0, 0, 0): 0.4 + coef @ P[0], (1, 0, 0): g[0],
+              (0, 1, 0): g[1], (0, 0, 1): g[2]}
+        for a in range(4):
+            for b in range(4):
+                ref = det * _simplex_integral(_poly_mul(_poly_mul(lam[a],
+                                                                  lam[b]), Vp))
+                assert abs(MV[t, a, b] - ref) < 1e-14 * max(1.0, abs(ref))
+
+
+def test_linear_potential_row_sum_is_point_value():
+    """The star of an interior vertex is centrally symmetric, so for linear
+    V: sum_j (M_V)_ij = int V phi_i = V(x_i) h^3 away from the boundary."""
+    nc = 8
+    mesh = fem.kuhn_mesh(nc, -2.0, 2.0)
+    V = 1.5 + mesh.X @ np.array([0.3, -0.2, 0.9])
+    _, _, MV = fem.assemble(mesh, V)
+    c, m = centre_row(nc)
+    vi = np.where(mesh.dof == c)[0][0]
+    assert abs(MV.getrow(c).sum() - V[vi] * mesh.h ** 3) < 1e-13
+
+
+def test_hamiltonian_positive_definite_for_positive_potential():
+    nc = 6
+    mesh = fem.kuhn_mesh(nc, -6.0, 6.0)
+    H, M = fem.hamiltonian(mesh, inputs.harmonic_potential(nc, -6.0, 6.0))
+    w = np.linalg.eigvalsh(H.toarray())
+    assert w.min() > 0
+    assert np.linalg.eigvalsh(M.toarray()).min() > 0

@@ -1,0 +1,188 @@
+"""Pins for the oracle's ParO iteration (CPU).
+
+The converged result of ParO on a fixed mesh is the lowest N eigenpairs of
+H u = lambda M u (appendix, eq. (fem-eigen)).  The checks below fix it with
+library solvers, closed forms (the harmonic-oscillator spectrum n + 3/2 and
+its O(h^2) convergence), symmetry, and textbook invariants of subspace
+iteration with Rayleigh-Ritz."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import fem, paro, reference
+from paper_1405_0260_amd import inputs
+from paro_checks import m_orthonormality_error, rel_lambda_err, subspace_sine
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def problem(kind, nc, seed=7):
+    if kind == "ho":
+        w = inputs.harmonic(nc=nc, N=4, seed=seed)
+    else:
+        w = inputs.molecule(nc=nc, N=6, m=4, seed=seed, lo=-6.0, hi=6.0)
+    mesh = fem.kuhn_mesh(nc, w.lo, w.hi)
+    H, M = fem.hamiltonian(mesh, w.V)
+    return w, H, M
+
+
+@pytest.mark.parametrize("kind", ["ho", "sc"])
+def test_pcg_matches_direct_solve(kind):
+    w, H, M = problem(kind, 10)
+    s = paro.shift_from_potential(w.V)
+    A = (H - s * M).tocsr()
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(A.shape[0])
+    x, it = paro.jacobi_pcg(A, b, np.zeros_like(b), 1.0 / A.diagonal(),
+                            1e-13, 10000)
+    ref = spla.spsolve(A.tocsc(), b)
+    assert it > 5
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_pcg_zero_iterations_when_start_is_exact():
+    w, H, M = problem("ho", 6)
+    A = H.tocsr()
+    x0 = np.random.default_rng(1).standard_normal(A.shape[0])
+    x, it = paro.jacobi_pcg(A, A @ x0, x0, 1.0 / A.diagonal(), 1e-10, 100)
+    assert it == 0 and np.array_equal(x, x0)
+
+
+def test_pcg_reports_breakdown_on_indefinite_matrix():
+    A = sp.diags([-1.0, -2.0, -3.0]).tocsr()
+    with pytest.raises(paro.NotSPD):
+        paro.jacobi_pcg(A, np.ones(3), np.zeros(3), np.ones(3), 1e-10, 10)
+
+
+def test_shift_keeps_matrix_definite():
+    w, H, M = problem("sc", 8)
+    s = paro.shift_from_potential(w.V)
+    assert s == pytest.approx(w.V.min() - 1.0)
+    lam, _ = reference.dense_lowest(H, M, 1)
+    assert lam[0] > w.V.min() > s
+    assert paro.shift_from_potential(np.array([0.0, 2.0])) == 0.0
+
+
+def test_rayleigh_ritz_recovers_invariant_subspace():
+    w, H, M = problem("sc", 8)
+    lam, U = reference.dense_lowest(H, M, 5)
+    mix = np.random.default_rng(2).standard_normal((5, 5))
+    theta, Ur = paro.rayleigh_ritz(H, M, U @ mix)
+    assert rel_lambda_err(theta, lam) < 1e-12
+    assert m_orthonormality_error(M, Ur) < 1e-12
+    assert subspace_sine(M, Ur, U) < 1e-10
+
+
+@pytest.mark.parametrize("kind,nc", [("ho", 8), ("ho", 10), ("sc", 10)])
+def test_paro_converges_to_dense_eigensolution(kind, nc):
+    w, H, M = problem(kind, nc)
+    r = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=400,
+                        lambda_tol=1e-14, resid_tol=1e-10, rtol=1e-12)
+    lam, U = reference.dense_lowest(H, M, w.Nt + 1)
+    assert r.converged
+    assert rel_lambda_err(r.lam, lam[:w.N]) < 1e-10
+    assert m_orthonormality_error(M, r.U) < 1e-12
+    gap = (lam[w.N] - lam[w.N - 1]) / abs(lam[w.N - 1])
+    assert gap > 1e-3
+    assert subspace_sine(M, r.U, U[:, :w.N]) < 1e-7
+
+
+def test_ritz_values_bound_eigenvalues_from_above():
+    """Poincare / Courant-Fischer: the i-th Ritz value of any subspace is
+    >= the i-th eigenvalue, at every ParO step."""
+    w, H, M = problem("sc", 8)
+    lam, _ = reference.dense_lowest(H, M, w.Nt)
+    r = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=15)
+    for th in r.lam_history:
+        assert np.all(th - lam >= -1e-11 * np.abs(lam).max())
+
+
+def test_exact_eigenpairs_are_a_fixed_point():
+    w, H, M = problem("ho", 8)
+    lam, U = reference.dense_lowest(H, M, 6)
+    s = paro.shift_from_potential(w.V)
+    A = (H - s * M).tocsr()
+    lam1, U1, its = paro.paro_step(H, M, A, 1.0 / A.diagonal(), lam, U, s,
+                                   1e-12, 1000)
+    assert rel_lambda_err(lam1, lam) < 1e-12
+    assert subspace_sine(M, U1[:, :3], U[:, :3]) < 1e-9
+
+
+def test_single_orbital_step_is_inverse_iteration():
+    """N = 1: Step 3 gives w = (lam - s)(H - s M)^{-1} M u and Step 4 its
+    normalised Rayleigh quotient."""
+    w, H, M = problem("sc", 8)
+    s = paro.shift_from_potential(w.V)
+    A = (H - s * M).tocsr()
+    u = w.U0()[:, :1]
+    lam0, u0 = paro.rayleigh_ritz(H, M, u)
+    lam1, u1, _ = paro.paro_step(H, M, A, 1.0 / A.diagonal(), lam0, u0, s,
+                                 1e-13, 10000)
+    x = spla.spsolve(A.tocsc(), M @ u0[:, 0])
+    rq = (x @ (H @ x)) / (x @ (M @ x))
+    assert abs(lam1[0] - rq) < 1e-10 * abs(rq)
+    xn = x / np.sqrt(x @ (M @ x))
+    assert min(np.abs(u1[:, 0] - xn).max(), np.abs(u1[:, 0] + xn).max()) < 1e-9
+
+
+def test_shift_changes_speed_not_the_fixed_point():
+    w, H, M = problem("ho", 8)
+    res = []
+    for s in (0.0, -2.0):
+        res.append(paro.paro_solve(H, M, w.U0(), w.N, sigma=s, max_steps=300,
+                                   lambda_tol=1e-14, resid_tol=1e-10,
+                                   rtol=1e-12))
+    assert rel_lambda_err(res[0].lam, res[1].lam) < 1e-11
+    assert subspace_sine(M, res[0].U, res[1].U) < 1e-8
+    assert res[0].steps < res[1].steps
+
+
+def test_convergence_rate_matches_subspace_iteration_theory():
+    """Lambda error of pair i contracts by ((l_i - s)/(l_{Nt+1} - s))^2 per
+    step once the start has decayed (textbook subspace iteration)."""
+    w, H, M = problem("ho", 10)
+    lam, _ = reference.dense_lowest(H, M, w.Nt + 1)
+    r = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=14,
+                        rtol=1e-13)
+    err = np.array([h[0] - lam[0] for h in r.lam_history])
+    k = 8
+    measured = (err[k + 1] / err[k])
+    theory = (lam[0] / lam[w.Nt]) ** 2
+    assert abs(measured / theory - 1.0) < 0.1
+
+
+def test_harmonic_oscillator_spectrum_converges_at_order_h2():
+    """Continuum 3D oscillator: lambda = n + 3/2 with multiplicity
+    (n+1)(n+2)/2 (closed form, tests/golden/harmonic_spectrum.txt).  The P1
+    eigenvalues converge at O(h^2): halving h divides the error by ~4."""
+    exact = np.loadtxt(os.path.join(GOLDEN, "harmonic_spectrum.txt"))
+    fine = np.loadtxt(os.path.join(GOLDEN, "harmonic_48c_lowest10.txt"))
+    errs = []
+    for nc in (12, 24):
+        mesh = fem.kuhn_mesh(nc, -6.0, 6.0)
+        H, M = fem.hamiltonian(mesh, inputs.harmonic_potential(nc, -6, 6))
+        lam, _ = reference.sparse_lowest(H, M, 10, -0.5)
+        errs.append(lam[:4] - exact[:4])
+    errs.append(fine[:4] - exact[:4])
+    errs = np.array(errs)
+    assert np.all(errs > 0)                    # conforming: from above
+    ratio = errs[:-1] / errs[1:]
+    assert np.all(ratio > 3.4) and np.all(ratio < 4.4), ratio
+    assert np.max(errs[-1]) < 0.07
+
+
+def test_harmonic_p_shell_splits_into_singlet_and_exact_doublet():
+    """The vertex-centred Kuhn mesh of [-6,6]^3 is invariant under axis
+    permutations and central inversion, as is |x|^2/2; the p shell must
+    split into a singlet and an exact doublet."""
+    for nc in (12, 24):
+        mesh = fem.kuhn_mesh(nc, -6.0, 6.0)
+        H, M = fem.hamiltonian(mesh, inputs.harmonic_potential(nc, -6, 6))
+        lam, _ = reference.sparse_lowest(H, M, 5, -0.5)
+        p = np.sort(lam[1:4])
+        d = np.diff(p)
+        assert min(d) < 1e-10 * p[0]
+        assert max(d) > 1e-3 * p[0]
