@@ -1,0 +1,204 @@
+/*
+ * paro.h - C ABI of the MI355X (gfx950) parallel orbital-updating engine.
+ *
+ * The library computes the lowest N eigenpairs of the P1 finite-element
+ * discretisation of  -1/2 Laplace u + V u = lambda u  on a box with
+ * homogeneous Dirichlet data, by the parallel orbital-updating (ParO)
+ * iteration of Dai, Gong, Zhou and Zhu (arXiv:1405.0260):
+ *   Algorithm A.1 (appendix; linear eigenproblem, a(u,v) = int A grad u .
+ *   grad v + c u v with A = I/2 and c = V), with the N + m buffer orbitals of
+ *   Algorithm 3.2, and Step 2 (mesh adaptation) taken as the identity:
+ *     Step 3: for every orbital i independently solve the source problem
+ *             a(u_i^{n+1/2}, v) = lambda_i^n (u_i^n, v) for all v,
+ *     Step 4: Rayleigh-Ritz on span{u_i^{n+1/2}} giving (lambda_i^{n+1},
+ *             u_i^{n+1}) with (u_i, u_j) = delta_ij.
+ *
+ * Conventions for every entry point
+ *   - Return value: PARO_OK (0) or a negative PARO_E* code; nothing aborts
+ *     and no C++ exception crosses the ABI.  paro_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - Pointers named d_* are device (HBM) pointers on the current HIP device;
+ *     h_* are host pointers.  The caller owns every buffer it passes; inputs
+ *     are only read during the call (asynchronously on `stream` for device
+ *     inputs of asynchronous calls: keep them alive until the stream has
+ *     reached the call).
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).
+ *   - Dofs: the interior vertices (i, j, k), 1 <= i <= nx-1 (likewise j, k),
+ *     numbered d = (i-1) + (nx-1)((j-1) + (ny-1)(k-1)) (x fastest).
+ *   - Orbital blocks are row-major n_dof x Nt (orbital index fastest), FP64,
+ *     where Nt = N + m.  lambda arrays hold Nt FP64 values, ascending.
+ *   - The library never allocates device memory after paro_assemble: all
+ *     device state lives in the caller's workspace.
+ */
+#ifndef PARO_H
+#define PARO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PARO_OK = 0,
+  PARO_EINVAL = -1,     /* bad argument: shape, null pointer, non-finite V  */
+  PARO_ENOMEM = -2,     /* workspace smaller than paro_query reports        */
+  PARO_ENOTSPD = -3,    /* CG breakdown p^T A p <= 0 (shift above lambda_1) */
+  PARO_ESINGULAR = -4,  /* Gram matrix W^T M W not positive definite        */
+  PARO_ENOCONV = -5,    /* iteration cap reached; outputs/report still set  */
+  PARO_EDEVICE = -6     /* a HIP runtime call failed                        */
+};
+
+enum { PARO_FP64 = 0, PARO_FP32_INNER = 1 };
+enum { PARO_NT_MAX = 64 };  /* largest N + m */
+
+/* Uniform Kuhn mesh: [lo, hi] cut into nx * ny * nz cubes, each split into
+ * the six tetrahedra sharing the main diagonal (0,0,0)-(1,1,1)
+ * (Sec. 2: conforming shape-regular tetrahedral mesh, P1 space S^{h,1}_0). */
+typedef struct paro_box {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 2 */
+  double lo[3], hi[3];
+} paro_box_t;
+
+typedef struct paro_opts {
+  int32_t N;              /* requested orbitals (Algorithm 3.1/A.1 N) >= 1  */
+  int32_t m;              /* buffer orbitals (Algorithm 3.2 m) >= 0         */
+  int32_t max_steps;      /* ParO iterations in paro_solve                  */
+  int32_t pcg_maxit;      /* CG iteration cap per source problem per step   */
+  int32_t precision;      /* PARO_FP64, or PARO_FP32_INNER: FP32 CG inside
+                             FP64 iterative refinement of the source solve  */
+  int32_t sigma_mode;     /* 0: sigma = min V - 1 if min V < 0 else 0;
+                             1: use `sigma` below                           */
+  double sigma;           /* shift s of (H - s M) w = (lambda - s) M u       */
+  double lambda_tol;      /* stop: max_{i<N} |dlambda_i| / scale_i <= this  */
+  double resid_tol;       /* and max_{i<N} ||H u - l M u|| / (scale ||M u||) */
+  double pcg_rtol;        /* source solves: ||b - A w|| <= rtol ||b||        */
+  double inner_rtol;      /* FP32 inner solves: residual reduction per pass  */
+} paro_opts_t;
+
+typedef struct paro_report {
+  int32_t status;         /* PARO_OK / PARO_ENOCONV / ...                   */
+  int32_t steps;          /* ParO steps taken                                */
+  int64_t pcg_iters;      /* CG iterations summed over steps (max over cols) */
+  int64_t refinements;    /* FP64 refinement passes (FP32_INNER mode)        */
+  int64_t n_dof, nnz;
+  double max_dlambda;     /* last step, over the N requested pairs          */
+  double max_resid;
+  double sigma;
+  double seconds;         /* wall time of the call                          */
+} paro_report_t;
+
+typedef struct paro_problem paro_problem;   /* opaque, host memory only */
+
+/* Fill `opts` with defaults: m = 0, max_steps = 200, pcg_maxit = 10000,
+ * FP64, automatic shift, lambda_tol = 1e-12, resid_tol = 1e-8,
+ * pcg_rtol = 1e-10, inner_rtol = 1e-4.  N must still be set. */
+void paro_default_opts(paro_opts_t* opts);
+
+/* Sizes for a box and options, host only.  n_dof = (nx-1)(ny-1)(nz-1);
+ * nnz = number of stored entries of the 15-point Kuhn P1 pattern;
+ * workspace_bytes = device memory paro_assemble needs (the whole resident
+ * footprint of the problem: matrices, solver blocks, reductions).
+ * Any output pointer may be NULL. */
+int paro_query(const paro_box_t* box, const paro_opts_t* opts,
+               int64_t* n_dof, int64_t* nnz, size_t* workspace_bytes);
+
+/* Assemble the source-problem operator on the device (Sec. 2 finite
+ * elements; eq. (eq-operator-A) with the potential fixed):
+ *   A_s = K/2 + M_V - s M (CSR, FP64 and an FP32 copy), M (CSR, FP64),
+ *   the Jacobi diagonal of A_s,
+ * with K the P1 stiffness, M the consistent mass and M_V the mass weighted
+ * by the nodal interpolant of V, integrated exactly.
+ *   d_V: (nx+1)(ny+1)(nz+1) nodal potential values, x fastest, all vertices
+ *        including the boundary (device pointer, FP64).
+ *   d_workspace/bytes: caller-owned device memory of at least
+ *        paro_query's workspace_bytes, 256-byte aligned; it must outlive the
+ *        problem.  The problem keeps pointers into it.
+ * Synchronises `stream` once (to read the shift back).  *out receives a
+ * host-side handle, freed by paro_destroy.
+ * Errors: PARO_EINVAL (nx < 2, Nt > PARO_NT_MAX, Nt > n_dof, non-finite V),
+ * PARO_ENOMEM, PARO_EDEVICE. */
+int paro_assemble(const paro_box_t* box, const double* d_V,
+                  const paro_opts_t* opts, void* d_workspace, size_t bytes,
+                  void* stream, paro_problem** out);
+
+/* Step 1 of Algorithm A.1: from arbitrary linearly independent orbitals
+ * d_U0 (n_dof x Nt) form the Rayleigh-Ritz pairs of their span, which are
+ * M-orthonormal, into d_lambda (Nt) and d_U (n_dof x Nt).  d_U0 may equal
+ * d_U.  Asynchronous on `stream`.
+ * Errors: PARO_EINVAL; PARO_ESINGULAR is reported through paro_step /
+ * paro_solve status (device-side flag) when U0^T M U0 is singular. */
+int paro_init(paro_problem* p, const double* d_U0, double* d_lambda,
+              double* d_U, void* stream);
+
+/* One ParO iteration, Steps 3 and 4 (eq. (alg-bvp), (alg-evp)), in place:
+ * reads (lambda^n, U^n) from d_lambda / d_U and overwrites them with
+ * (lambda^{n+1}, U^{n+1}).  The Nt source problems
+ *   (H - s M) w_i = (lambda_i - s) M u_i,   w_i^0 = u_i
+ * are solved by Jacobi-preconditioned CG (one CSR pass per CG iteration
+ * serves all Nt columns) to ||r_i|| <= pcg_rtol ||b_i||, then Rayleigh-Ritz
+ * on span W.  A pure function of (lambda, U) and the problem.
+ * If `report` is NULL the call is asynchronous on `stream` except for the
+ * CG loop's convergence polling (one 4-byte read every few iterations);
+ * otherwise it synchronises and fills `report` for this step. */
+int paro_step(paro_problem* p, double* d_lambda, double* d_U, void* stream,
+              paro_report_t* report);
+
+/* Whole solve: paro_init from d_U0, then paro_step until both tolerances
+ * hold for the N requested pairs or opts.max_steps steps were taken.
+ * d_lambda (Nt) and d_U (n_dof x Nt) receive the final Ritz pairs (the
+ * first N are the answer).  Returns PARO_OK, or PARO_ENOCONV if max_steps
+ * was reached first (outputs and report are still filled).  Synchronous. */
+int paro_solve(paro_problem* p, const double* d_U0, double* d_lambda,
+               double* d_U, void* stream, paro_report_t* report);
+
+/* Release the host handle (the workspace stays the caller's). */
+void paro_destroy(paro_problem* p);
+
+/* Message for the last failing call on this thread (never NULL). */
+const char* paro_last_error(void);
+const char* paro_strerror(int status);
+
+/* ---------------------------------------------------------------------
+ * Component entry points (each runs one kernel stage of the step above;
+ * used for kernel-level checking and measurement).  All asynchronous.
+ * --------------------------------------------------------------------- */
+
+/* Copy the assembled CSR (rowptr int32[n+1], col int32[nnz], A_s and M
+ * values FP64[nnz]) into caller device buffers; also the shift. */
+int paro_export_csr(paro_problem* p, int32_t* d_rowptr, int32_t* d_col,
+                    double* d_valA, double* d_valM, double* h_sigma,
+                    void* stream);
+
+/* Y = A_s X (which = 0), Y = M X (which = 1) or Y = H X = A_s X + s M X
+ * (which = 2) for an n_dof x ncols row-major FP64 block, 1 <= ncols <= 64. */
+int paro_spmm(paro_problem* p, int which, const double* d_X, double* d_Y,
+              int ncols, void* stream);
+
+/* G = W^T Y (ncols x ncols, row-major) for n_dof x ncols blocks W, Y,
+ * on FP64 matrix cores; result in device memory d_G. */
+int paro_gram(paro_problem* p, const double* d_W, const double* d_Y,
+              double* d_G, int ncols, void* stream);
+
+/* Dense generalised symmetric eigenproblem A c = theta B c, B positive
+ * definite, n <= 64, on one workgroup: Cholesky B = L L^T, cyclic Jacobi
+ * on L^{-1} A L^{-T}, theta ascending, C = L^{-T} Y (C^T B C = I), each
+ * column's largest-magnitude entry made positive.  Device pointers,
+ * row-major.  d_info (int32) receives 0, or k+1 if the k-th pivot of B
+ * was not positive. */
+int paro_small_geneig(const double* d_A, const double* d_B, int n,
+                      double* d_theta, double* d_C, int32_t* d_info,
+                      void* stream);
+
+/* Solve (H - s M) X = B column by column with the step's block Jacobi-PCG
+ * (FP64 or the FP32-inner refinement per opts.precision) from the start
+ * X (in/out).  h_iters (ncols int32, may be NULL) receives each column's
+ * CG iteration count.  Synchronous. */
+int paro_pcg(paro_problem* p, const double* d_B, double* d_X, int ncols,
+             int32_t* h_iters, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARO_H */

@@ -34,10 +34,10 @@ import scipy.sparse as sp
 
 @dataclass
 class Mesh:
-    nc: int
-    lo: float
-    hi: float
-    h: float
+    nc: tuple            # cells per axis (nx, ny, nz)
+    lo: np.ndarray       # (3,)
+    hi: np.ndarray       # (3,)
+    h: np.ndarray        # (3,) cell sizes
     X: np.ndarray        # (nv, 3) vertex coordinates, x fastest
     tets: np.ndarray     # (nt, 4) vertex indices
     dof: np.ndarray      # (nv,) interior dof number or -1 on the boundary
@@ -47,25 +47,29 @@ class Mesh:
         return int((self.dof >= 0).sum())
 
 
-def kuhn_mesh(nc: int, lo: float, hi: float) -> Mesh:
-    """Uniform Kuhn mesh of [lo, hi]^3 with nc cubes per axis.
+def kuhn_mesh(nc, lo, hi) -> Mesh:
+    """Uniform Kuhn mesh of the box [lo, hi] with nc cubes per axis (nc an
+    int or (nx, ny, nz); lo, hi scalars or 3-vectors).
 
-    Interior dofs are the vertices with all indices in 1..nc-1, numbered
-    x fastest: d = (i-1) + (nc-1) ((j-1) + (nc-1) (k-1)).
+    Interior dofs are the vertices with index 1..n_a-1 on every axis a,
+    numbered x fastest: d = (i-1) + (nx-1) ((j-1) + (ny-1) (k-1)).
     """
-    h = (hi - lo) / nc
-    nv1 = nc + 1
-    t = lo + h * np.arange(nv1, dtype=np.float64)
-    kk, jj, ii = np.meshgrid(np.arange(nv1), np.arange(nv1), np.arange(nv1),
+    ncs = (nc, nc, nc) if np.isscalar(nc) else tuple(int(c) for c in nc)
+    lo = np.broadcast_to(np.asarray(lo, dtype=np.float64), (3,)).copy()
+    hi = np.broadcast_to(np.asarray(hi, dtype=np.float64), (3,)).copy()
+    h = (hi - lo) / np.array(ncs, dtype=np.float64)
+    nvx, nvy, nvz = (c + 1 for c in ncs)
+    kk, jj, ii = np.meshgrid(np.arange(nvz), np.arange(nvy), np.arange(nvx),
                              indexing="ij")
     ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
-    X = np.stack([t[ii], t[jj], t[kk]], axis=1)
+    X = np.stack([lo[0] + h[0] * ii, lo[1] + h[1] * jj, lo[2] + h[2] * kk],
+                 axis=1)
 
     def vid(i, j, k):
-        return i + nv1 * (j + nv1 * k)
+        return i + nvx * (j + nvy * k)
 
-    ci, cj, ck = np.meshgrid(np.arange(nc), np.arange(nc), np.arange(nc),
-                             indexing="ij")
+    ck, cj, ci = np.meshgrid(np.arange(ncs[2]), np.arange(ncs[1]),
+                             np.arange(ncs[0]), indexing="ij")
     ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
     unit = np.eye(3, dtype=np.int64)
     tets = []
@@ -78,13 +82,13 @@ def kuhn_mesh(nc: int, lo: float, hi: float) -> Mesh:
         tets.append(np.stack(verts, axis=1))
     tets = np.concatenate(tets, axis=0)
 
-    m = nc - 1
-    interior = (ii >= 1) & (ii <= nc - 1) & (jj >= 1) & (jj <= nc - 1) \
-        & (kk >= 1) & (kk <= nc - 1)
+    mx, my = ncs[0] - 1, ncs[1] - 1
+    interior = (ii >= 1) & (ii <= ncs[0] - 1) & (jj >= 1) & (jj <= ncs[1] - 1) \
+        & (kk >= 1) & (kk <= ncs[2] - 1)
     dof = np.full(X.shape[0], -1, dtype=np.int64)
-    dof[interior] = (ii[interior] - 1) + m * ((jj[interior] - 1)
-                                              + m * (kk[interior] - 1))
-    return Mesh(nc, lo, hi, h, X, tets, dof)
+    dof[interior] = (ii[interior] - 1) + mx * ((jj[interior] - 1)
+                                               + my * (kk[interior] - 1))
+    return Mesh(ncs, lo, hi, h, X, tets, dof)
 
 
 def barycentric_integral(exponents, volume):

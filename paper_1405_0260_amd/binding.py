@@ -1,0 +1,288 @@
+"""ctypes binding of libparo (argument marshalling only).
+
+Each function mirrors the C entry point of the same name in
+``include/paro.h``: torch tensors on the current HIP device are passed as
+raw device pointers, the current torch stream as the hipStream_t.  No
+arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libparo.so")
+
+PARO_OK, PARO_EINVAL, PARO_ENOMEM, PARO_ENOTSPD = 0, -1, -2, -3
+PARO_ESINGULAR, PARO_ENOCONV, PARO_EDEVICE = -4, -5, -6
+PARO_FP64, PARO_FP32_INNER = 0, 1
+NT_MAX = 64
+
+c_i32, c_i64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_void_p)
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("nx", c_i32), ("ny", c_i32), ("nz", c_i32),
+                ("lo", c_dbl * 3), ("hi", c_dbl * 3)]
+
+    @classmethod
+    def cube(cls, nc, lo, hi):
+        ncs = (nc, nc, nc) if isinstance(nc, int) else tuple(nc)
+        los = (lo,) * 3 if isinstance(lo, (int, float)) else tuple(lo)
+        his = (hi,) * 3 if isinstance(hi, (int, float)) else tuple(hi)
+        return cls(ncs[0], ncs[1], ncs[2], (c_dbl * 3)(*los),
+                   (c_dbl * 3)(*his))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("N", c_i32), ("m", c_i32), ("max_steps", c_i32),
+                ("pcg_maxit", c_i32), ("precision", c_i32),
+                ("sigma_mode", c_i32), ("sigma", c_dbl),
+                ("lambda_tol", c_dbl), ("resid_tol", c_dbl),
+                ("pcg_rtol", c_dbl), ("inner_rtol", c_dbl)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("steps", c_i32), ("pcg_iters", c_i64),
+                ("refinements", c_i64), ("n_dof", c_i64), ("nnz", c_i64),
+                ("max_dlambda", c_dbl), ("max_resid", c_dbl),
+                ("sigma", c_dbl), ("seconds", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ParoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"paro error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libparo.so (raises if it was never built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch must be loaded first: its HIP runtime then satisfies libparo's
+    # libamdhip64 dependency, so the process holds one runtime and device
+    # pointers / streams from torch are valid in libparo.  Loading libparo
+    # first would map a second HIP/HSA runtime that sees no device.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_1405_0260_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_vp
+    sig = {
+        "paro_default_opts": (None, [ctypes.POINTER(Opts)]),
+        "paro_query": (c_i32, [ctypes.POINTER(Box), ctypes.POINTER(Opts),
+                               ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
+                               ctypes.POINTER(ctypes.c_size_t)]),
+        "paro_assemble": (c_i32, [ctypes.POINTER(Box), P,
+                                  ctypes.POINTER(Opts), P, ctypes.c_size_t, P,
+                                  ctypes.POINTER(P)]),
+        "paro_init": (c_i32, [P, P, P, P, P]),
+        "paro_step": (c_i32, [P, P, P, P, ctypes.POINTER(Report)]),
+        "paro_solve": (c_i32, [P, P, P, P, P, ctypes.POINTER(Report)]),
+        "paro_destroy": (None, [P]),
+        "paro_last_error": (ctypes.c_char_p, []),
+        "paro_strerror": (ctypes.c_char_p, [c_i32]),
+        "paro_export_csr": (c_i32, [P, P, P, P, P, ctypes.POINTER(c_dbl), P]),
+        "paro_spmm": (c_i32, [P, c_i32, P, P, c_i32, P]),
+        "paro_gram": (c_i32, [P, P, P, P, c_i32, P]),
+        "paro_small_geneig": (c_i32, [P, P, c_i32, P, P, P, P]),
+        "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc, allow=()):
+    if rc != PARO_OK and rc not in allow:
+        raise ParoError(rc, lib().paro_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _f64(t, shape: Sequence[int], name: str):
+    import torch
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name}: expected float64, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, "
+                         f"got {tuple(t.shape)}")
+
+
+def paro_default_opts() -> Opts:
+    o = Opts()
+    lib().paro_default_opts(ctypes.byref(o))
+    return o
+
+
+def default_opts(**kw) -> Opts:
+    o = paro_default_opts()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def paro_query(box: Box, opts: Opts):
+    n, z, b = c_i64(), c_i64(), ctypes.c_size_t()
+    _check(lib().paro_query(ctypes.byref(box), ctypes.byref(opts),
+                            ctypes.byref(n), ctypes.byref(z), ctypes.byref(b)))
+    return n.value, z.value, b.value
+
+
+class Problem:
+    """An assembled problem: host handle plus the caller-owned workspace."""
+
+    def __init__(self, handle, box, opts, workspace, n, nnz):
+        self.handle = handle
+        self.box = box
+        self.opts = opts
+        self.workspace = workspace
+        self.n = n
+        self.nnz = nnz
+        self.Nt = opts.N + opts.m
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().paro_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def paro_assemble(box: Box, V, opts: Opts, stream=None,
+                  workspace=None) -> Problem:
+    """Assemble on the device; V: float64 device tensor of all vertices."""
+    import torch
+    n, z, nbytes = paro_query(box, opts)
+    _f64(V, ((box.nx + 1) * (box.ny + 1) * (box.nz + 1),), "V")
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                device=V.device)
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    h = c_vp()
+    _check(lib().paro_assemble(ctypes.byref(box), _ptr(V), ctypes.byref(opts),
+                               base + off, workspace.numel() - off,
+                               _stream(stream), ctypes.byref(h)))
+    return Problem(h, box, opts, workspace, n, z)
+
+
+def paro_init(p: Problem, U0, lam, U, stream=None):
+    _f64(U0, (p.n, p.Nt), "U0")
+    _f64(U, (p.n, p.Nt), "U")
+    _f64(lam, (p.Nt,), "lambda")
+    _check(lib().paro_init(p.handle, _ptr(U0), _ptr(lam), _ptr(U),
+                           _stream(stream)))
+
+
+def paro_step(p: Problem, lam, U, stream=None, report=True):
+    _f64(U, (p.n, p.Nt), "U")
+    _f64(lam, (p.Nt,), "lambda")
+    r = Report()
+    _check(lib().paro_step(p.handle, _ptr(lam), _ptr(U), _stream(stream),
+                           ctypes.byref(r) if report else None),
+           allow=(PARO_ENOCONV,))
+    return r if report else None
+
+
+def paro_solve(p: Problem, U0, lam, U, stream=None) -> Report:
+    _f64(U0, (p.n, p.Nt), "U0")
+    _f64(U, (p.n, p.Nt), "U")
+    _f64(lam, (p.Nt,), "lambda")
+    r = Report()
+    _check(lib().paro_solve(p.handle, _ptr(U0), _ptr(lam), _ptr(U),
+                            _stream(stream), ctypes.byref(r)),
+           allow=(PARO_ENOCONV,))
+    return r
+
+
+def paro_destroy(p: Problem):
+    if p.handle:
+        lib().paro_destroy(p.handle)
+        p.handle = None
+
+
+def paro_export_csr(p: Problem, stream=None):
+    import torch
+    dev = p.workspace.device
+    rowptr = torch.empty(p.n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(p.nnz, dtype=torch.int32, device=dev)
+    valA = torch.empty(p.nnz, dtype=torch.float64, device=dev)
+    valM = torch.empty(p.nnz, dtype=torch.float64, device=dev)
+    sigma = c_dbl()
+    _check(lib().paro_export_csr(p.handle, _ptr(rowptr), _ptr(col),
+                                 _ptr(valA), _ptr(valM), ctypes.byref(sigma),
+                                 _stream(stream)))
+    return rowptr, col, valA, valM, sigma.value
+
+
+def paro_spmm(p: Problem, which: int, X, Y, stream=None):
+    ncols = X.shape[1]
+    _f64(X, (p.n, ncols), "X")
+    _f64(Y, (p.n, ncols), "Y")
+    _check(lib().paro_spmm(p.handle, which, _ptr(X), _ptr(Y), ncols,
+                           _stream(stream)))
+
+
+def paro_gram(p: Problem, W, Y, G, stream=None):
+    ncols = W.shape[1]
+    _f64(W, (p.n, ncols), "W")
+    _f64(Y, (p.n, ncols), "Y")
+    _f64(G, (ncols, ncols), "G")
+    _check(lib().paro_gram(p.handle, _ptr(W), _ptr(Y), _ptr(G), ncols,
+                           _stream(stream)))
+
+
+def paro_small_geneig(A, B, theta, C, info, stream=None):
+    n = A.shape[0]
+    _f64(A, (n, n), "A")
+    _f64(B, (n, n), "B")
+    _f64(theta, (n,), "theta")
+    _f64(C, (n, n), "C")
+    _check(lib().paro_small_geneig(_ptr(A), _ptr(B), n, _ptr(theta), _ptr(C),
+                                   _ptr(info), _stream(stream)))
+
+
+def paro_pcg(p: Problem, B, X, stream=None):
+    """Solve (H - s M) X = B from the start X (in place); returns the CG
+    iteration count of every column."""
+    ncols = B.shape[1]
+    _f64(B, (p.n, ncols), "B")
+    _f64(X, (p.n, ncols), "X")
+    iters = (c_i32 * ncols)()
+    _check(lib().paro_pcg(p.handle, _ptr(B), _ptr(X), ncols, iters,
+                          _stream(stream)))
+    return list(iters)

@@ -57,11 +57,15 @@ class Workload:
         return initial_orbitals(self.n_dof, self.Nt, self.orbital_seed)
 
 
-def vertex_coords(nc: int, lo: float, hi: float) -> np.ndarray:
-    """Coordinates of all (nc+1)^3 vertices, x fastest, shape (nv, 3)."""
-    h = (hi - lo) / nc
-    t = lo + h * np.arange(nc + 1, dtype=np.float64)
-    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+def vertex_coords(nc, lo, hi) -> np.ndarray:
+    """Coordinates of all vertices, x fastest, shape (nv, 3).  nc is an int
+    or (nx, ny, nz); lo, hi are scalars or 3-vectors."""
+    ncs = (nc, nc, nc) if np.isscalar(nc) else tuple(int(c) for c in nc)
+    lo = np.broadcast_to(np.asarray(lo, dtype=np.float64), (3,))
+    hi = np.broadcast_to(np.asarray(hi, dtype=np.float64), (3,))
+    axes = [lo[a] + (hi[a] - lo[a]) / ncs[a] * np.arange(ncs[a] + 1)
+            for a in range(3)]
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
 
 

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI (CPU only: no kernel is launched).
+
+The library must load, export every entry point declared in
+include/paro.h, and answer the host-only queries and argument checks."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_1405_0260_amd import binding as pb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "paro.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pb.LIB_PATH):
+        from paper_1405_0260_amd import build
+        build.build()
+    return pb.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(paro_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("paro_query", "paro_assemble", "paro_step", "paro_solve",
+              "paro_init", "paro_destroy"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("ncs", [(2, 2, 2), (3, 3, 3), (24, 24, 24),
+                                 (4, 5, 6), (7, 3, 9)])
+def test_query_matches_oracle_mesh(lib, ncs):
+    mesh = fem.kuhn_mesh(ncs, 0.0, 1.0)
+    K, _, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    box = pb.Box(ncs[0], ncs[1], ncs[2], (ctypes.c_double * 3)(0, 0, 0),
+                 (ctypes.c_double * 3)(1, 1, 1))
+    n, z, ws = pb.paro_query(box, pb.default_opts(N=1))
+    assert n == mesh.n_dof and z == K.nnz
+    assert ws > 8 * 2 * z
+
+
+def test_default_options(lib):
+    o = pb.paro_default_opts()
+    assert (o.N, o.m, o.precision, o.sigma_mode) == (1, 0, pb.PARO_FP64, 0)
+    assert o.pcg_rtol == 1e-10 and o.lambda_tol == 1e-12
+    assert o.max_steps == 200 and o.pcg_maxit == 10000
+
+
+def test_workspace_grows_with_columns_and_precision(lib):
+    box = pb.Box.cube(16, -1, 1)
+    _, _, a = pb.paro_query(box, pb.default_opts(N=4))
+    _, _, b = pb.paro_query(box, pb.default_opts(N=8))
+    _, _, c = pb.paro_query(box, pb.default_opts(N=8, precision=1))
+    assert a < b < c
+
+
+@pytest.mark.parametrize("box,opts,code", [
+    (pb.Box.cube(1, 0, 1), dict(N=1), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 0, 1), dict(N=40, m=30), pb.PARO_EINVAL),
+    (pb.Box.cube(2, 0, 1), dict(N=2), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 0, 1), dict(N=1, precision=7), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 0, 1), dict(N=0), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 1, 0), dict(N=1), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 0, 1), dict(N=1, pcg_rtol=0.0), pb.PARO_EINVAL),
+])
+def test_query_rejects_bad_arguments(lib, box, opts, code):
+    with pytest.raises(pb.ParoError) as e:
+        pb.paro_query(box, pb.default_opts(**opts))
+    assert e.value.code == code
+    assert lib.paro_last_error().decode() not in ("", "no error")
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.paro_strerror(code).decode()

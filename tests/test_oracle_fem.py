@@ -45,7 +45,7 @@ def test_stiffness_is_seven_point_laplacian():
     0 elsewhere): the classical 7-point stencil times h."""
     nc = 8
     mesh = fem.kuhn_mesh(nc, 0.0, 4.0)
-    h = mesh.h
+    h = mesh.h[0]
     K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
     c, m = centre_row(nc)
     row = K.getrow(c)
@@ -64,7 +64,7 @@ def test_mass_stencil_closed_form():
     edge (6, 6 and 4) times |T|/20."""
     nc = 8
     mesh = fem.kuhn_mesh(nc, -1.0, 1.0)
-    h = mesh.h
+    h = mesh.h[0]
     _, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
     c, m = centre_row(nc)
     ax = [1, m, m * m]
@@ -155,7 +155,7 @@ def test_linear_potential_row_sum_is_point_value():
     _, _, MV = fem.assemble(mesh, V)
     c, m = centre_row(nc)
     vi = np.where(mesh.dof == c)[0][0]
-    assert abs(MV.getrow(c).sum() - V[vi] * mesh.h ** 3) < 1e-13
+    assert abs(MV.getrow(c).sum() - V[vi] * np.prod(mesh.h)) < 1e-13
 
 
 def test_hamiltonian_positive_definite_for_positive_potential():
@@ -165,3 +165,27 @@ def test_hamiltonian_positive_definite_for_positive_potential():
     w = np.linalg.eigvalsh(H.toarray())
     assert w.min() > 0
     assert np.linalg.eigvalsh(M.toarray()).min() > 0
+
+
+def test_non_cubic_box_counts_and_row_sums():
+    """Box with 4 x 5 x 6 cells of unequal size: counts, total volume,
+    K 1 = 0 and M 1 = hx hy hz on rows whose star is interior."""
+    ncs, lo, hi = (4, 5, 6), (-1.0, 0.0, 2.0), (1.0, 3.0, 2.5)
+    mesh = fem.kuhn_mesh(ncs, lo, hi)
+    assert mesh.n_dof == 3 * 4 * 5
+    vol, _ = fem.element_geometry(mesh)
+    assert abs(vol.sum() - 2.0 * 3.0 * 0.5) < 1e-13
+    K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    mx, my = 3, 4
+    for (i, j, k) in [(1, 1, 1), (1, 2, 3), (1, 2, 2)]:
+        d = i + mx * (j + my * k)
+        assert abs(K.getrow(d).sum()) < 1e-13
+        assert abs(M.getrow(d).sum() - np.prod(mesh.h)) < 1e-15
+    m = [c - 1 for c in ncs]
+    z = 1
+    z = sum(a * b * c for a, b, c in [
+        (m[0], m[1], m[2]), (m[0] - 1, m[1], m[2]), (m[0], m[1] - 1, m[2]),
+        (m[0], m[1], m[2] - 1), (m[0] - 1, m[1] - 1, m[2]),
+        (m[0] - 1, m[1], m[2] - 1), (m[0], m[1] - 1, m[2] - 1),
+        (m[0] - 1, m[1] - 1, m[2] - 1)]) * 2 - m[0] * m[1] * m[2]
+    assert K.nnz == z
