@@ -198,6 +198,37 @@ int paro_small_geneig(const double* d_A, const double* d_B, int n,
 int paro_pcg(paro_problem* p, const double* d_B, double* d_X, int ncols,
              int32_t* h_iters, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Measurement.  With timing on, every kernel launch of the problem is
+ * bracketed by HIP events on its stream and its duration is added to the
+ * stage it belongs to; off by default (no events are created).
+ * --------------------------------------------------------------------- */
+enum {
+  PARO_ST_CG_SPMM = 0,   /* CG: Q = A P with p.q partials              */
+  PARO_ST_CG_RUPD = 1,   /* CG: r -= alpha q, z, r.z, r.r              */
+  PARO_ST_CG_PUPD = 2,   /* CG: x += alpha p, p = z + beta p           */
+  PARO_ST_START = 3,     /* source-problem start (b, r0, p0)           */
+  PARO_ST_REFINE = 4,    /* FP64 residual + correction update          */
+  PARO_ST_RR_SPMM = 5,   /* Rayleigh-Ritz: H W and M W                 */
+  PARO_ST_GRAM = 6,      /* W^T H W, W^T M W on matrix cores           */
+  PARO_ST_SMALL = 7,     /* small generalised eigensolve (one block)   */
+  PARO_ST_ROTATE = 8,    /* U = W C with residual norms                */
+  PARO_ST_NUM = 9
+};
+
+typedef struct paro_timing {
+  int64_t launches[PARO_ST_NUM];
+  double ms[PARO_ST_NUM];         /* summed kernel durations            */
+  int64_t cg_iters;               /* CG iterations executed on device   */
+  int64_t cg_col_iters;           /* sum over CG iterations of the
+                                     number of active columns           */
+} paro_timing_t;
+
+/* Turn per-launch event timing on (1) or off (0); clears the sums. */
+int paro_set_timing(paro_problem* p, int on);
+/* Synchronise the problem's last stream and return the sums so far. */
+int paro_get_timing(paro_problem* p, paro_timing_t* out);
+
 #ifdef __cplusplus
 }
 #endif

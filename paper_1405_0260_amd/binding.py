@@ -54,6 +54,23 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+ST_NAMES = ["cg_spmm", "cg_rupd", "cg_pupd", "start", "refine", "rr_spmm",
+            "gram", "small_eig", "rotate"]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("launches", c_i64 * len(ST_NAMES)),
+                ("ms", c_dbl * len(ST_NAMES)), ("cg_iters", c_i64),
+                ("cg_col_iters", c_i64)]
+
+    def as_dict(self):
+        return {"stages": {n: {"launches": self.launches[i],
+                               "ms": self.ms[i]}
+                           for i, n in enumerate(ST_NAMES)},
+                "cg_iters": self.cg_iters,
+                "cg_col_iters": self.cg_col_iters}
+
+
 class ParoError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"paro error {code}: {msg}")
@@ -98,6 +115,8 @@ def lib():
         "paro_gram": (c_i32, [P, P, P, P, c_i32, P]),
         "paro_small_geneig": (c_i32, [P, P, c_i32, P, P, P, P]),
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
+        "paro_set_timing": (c_i32, [P, c_i32]),
+        "paro_get_timing": (c_i32, [P, ctypes.POINTER(Timing)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -286,3 +305,13 @@ def paro_pcg(p: Problem, B, X, stream=None):
     _check(lib().paro_pcg(p.handle, _ptr(B), _ptr(X), ncols, iters,
                           _stream(stream)))
     return list(iters)
+
+
+def paro_set_timing(p: Problem, on: bool = True):
+    _check(lib().paro_set_timing(p.handle, 1 if on else 0))
+
+
+def paro_get_timing(p: Problem) -> Timing:
+    t = Timing()
+    _check(lib().paro_get_timing(p.handle, ctypes.byref(t)))
+    return t

@@ -6,9 +6,11 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "paro_internal.h"
 
@@ -17,6 +19,76 @@ struct paro_problem {
 };
 
 namespace paro {
+
+// Host-side event timing of kernel launches (measurement only).
+struct Timing {
+  bool on = false;
+  struct Open {
+    int stage;
+    hipEvent_t a;
+  };
+  struct Pend {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Open> open;
+  std::vector<Pend> pend;
+  int64_t launches[PARO_ST_NUM] = {};
+  double ms[PARO_ST_NUM] = {};
+  unsigned long long iters0 = 0, cols0 = 0;  // device counters at reset
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void resolve() {
+    for (const Pend& q : pend) {
+      float t = 0.0f;
+      if (hipEventSynchronize(q.b) == hipSuccess &&
+          hipEventElapsedTime(&t, q.a, q.b) == hipSuccess) {
+        ms[q.stage] += t;
+        launches[q.stage] += 1;
+      }
+      pool.push_back(q.a);
+      pool.push_back(q.b);
+    }
+    pend.clear();
+  }
+  ~Timing() {
+    resolve();
+    for (const Open& o : open) pool.push_back(o.a);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+int timing_begin(Problem& p, int stage, hipStream_t s) {
+  Timing* t = p.timing;
+  if (!t || !t->on) return -1;
+  hipEvent_t a = t->get();
+  if (!a || hipEventRecord(a, s) != hipSuccess) return -1;
+  t->open.push_back({stage, a});
+  return (int)t->open.size() - 1;
+}
+
+void timing_end(Problem& p, int slot, hipStream_t s) {
+  Timing* t = p.timing;
+  if (!t || slot < 0 || slot >= (int)t->open.size()) return;
+  hipEvent_t b = t->get();
+  if (b && hipEventRecord(b, s) == hipSuccess)
+    t->pend.push_back({t->open[slot].stage, t->open[slot].a, b});
+  else
+    t->pool.push_back(t->open[slot].a);
+  t->open.erase(t->open.begin() + slot);
+  if (t->pend.size() > 4096) t->resolve();
+}
+
 namespace {
 
 thread_local std::string g_err = "no error";
@@ -41,7 +113,6 @@ int fail(int code, const char* fmt, ...) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int kPoll = 8;  // CG iterations launched between flag polls
 
 double now_s() {
   using namespace std::chrono;
@@ -148,29 +219,63 @@ int status_to_code(int st) {
   return PARO_OK;
 }
 
-// Run CG iterations (FP64 or FP32) until no column is active.
-int run_cg(paro_problem* h, int ncols, bool fp32, hipStream_t s,
-           int64_t* iters_out) {
+// The tail of ColState read back at each poll (one copy).
+struct ColTail {
+  int iters[kNtMax];
+  int n_active[2];
+  int n_outer;
+  int status;
+  int maxit;
+  int pad[3];
+  unsigned long long cg_iters;
+  unsigned long long cg_col_iters;
+};
+static_assert(offsetof(ColState, cg_col_iters) - offsetof(ColState, iters) ==
+                  offsetof(ColTail, cg_col_iters),
+              "ColTail must mirror the tail of ColState");
+
+int read_tail(paro_problem* h, ColTail* t, hipStream_t s) {
+  HIP_OR_FAIL(hipMemcpyAsync(t, &h->p.cs->iters[0], sizeof(ColTail),
+                             hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  return PARO_OK;
+}
+
+// Run CG iterations (FP64 or FP32) until no column is active.  The first
+// batch of launches is as long as the previous solve in the same slot took,
+// so that a converging solve usually needs one poll; later batches are
+// short top-ups.
+int run_cg(paro_problem* h, int ncols, bool fp32, hipStream_t s, int slot) {
   Problem& p = h->p;
+  ColTail t;
+  int rc = read_tail(h, &t, s);
+  if (rc) return rc;
+  if (t.n_active[0] == 0) return PARO_OK;
+  const unsigned long long start = t.cg_iters;
+  const int64_t cap = (int64_t)p.opts.pcg_maxit + 64;
+  int pred = p.cg_predict[slot];
+  int chunk = pred < 2 ? 2 : (pred > 256 ? 256 : pred);
+  int par = 0;
   int64_t launched = 0;
-  const int64_t cap = (int64_t)p.opts.pcg_maxit + 2 * kPoll;
   while (true) {
-    int na = 0;
-    int rc = read_back(h, &p.cs->n_active[0], &na, 1, s);
-    if (rc) return rc;
-    if (na == 0) break;
     if (launched >= cap)
       return fail(PARO_EDEVICE, "CG loop did not terminate on the device");
-    for (int k = 0; k < kPoll; ++k) {
-      const int par = k & 1;
+    for (int k = 0; k < chunk; ++k) {
       hipError_t e = fp32 ? launch_pcg32_iter(p, ncols, par, s)
                           : launch_pcg_iter(p, ncols, par, s);
       if (e != hipSuccess)
         return fail(PARO_EDEVICE, "CG launch: %s", hipGetErrorString(e));
+      par ^= 1;
     }
-    launched += kPoll;
+    launched += chunk;
+    rc = read_tail(h, &t, s);
+    if (rc) return rc;
+    if (p.timing) p.timing->resolve();
+    if (t.n_active[par] == 0) break;
+    chunk = (pred + 3) / 4;
+    chunk = chunk < 2 ? 2 : (chunk > 16 ? 16 : chunk);
   }
-  if (iters_out) *iters_out += launched;
+  p.cg_predict[slot] = (int)(t.cg_iters - start);
   return PARO_OK;
 }
 
@@ -180,7 +285,7 @@ int solve_sources(paro_problem* h, int ncols, hipStream_t s,
                   int64_t* refinements) {
   Problem& p = h->p;
   if (p.opts.precision == PARO_FP64) {
-    int rc = run_cg(h, ncols, false, s, nullptr);
+    int rc = run_cg(h, ncols, false, s, 0);
     if (rc) return rc;
   } else {
     for (int pass = 0;; ++pass) {
@@ -191,7 +296,7 @@ int solve_sources(paro_problem* h, int ncols, hipStream_t s,
       if (no == 0) break;
       if (pass > 200)
         return fail(PARO_EDEVICE, "refinement loop did not terminate");
-      rc = run_cg(h, ncols, true, s, nullptr);
+      rc = run_cg(h, ncols, true, s, 1 + (pass < 3 ? pass : 3));
       if (rc) return rc;
       HIP_OR_FAIL(launch_refine_update(p, ncols, s));
       if (refinements) ++*refinements;
@@ -229,8 +334,8 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.Q32 = f32 ? take(sizeof(float) * blk) : 0;
   L.X32 = f32 ? take(sizeof(float) * blk) : 0;
   L.part = take(sizeof(double) * 3 * (size_t)kGridMax * kNtMax);
-  L.gpart = take(sizeof(double) * (size_t)kGramGrid * kGramTiles);
-  L.gsum = take(sizeof(double) * kGramTiles);
+  L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
+  L.gsum = take(sizeof(double) * (size_t)kGramY * gram_tiles(Nt));
   L.Ah = take(sizeof(double) * kNtMax * kNtMax);
   L.Bh = take(sizeof(double) * kNtMax * kNtMax);
   L.C = take(sizeof(double) * kNtMax * kNtMax);
@@ -372,6 +477,7 @@ int paro_init(paro_problem* h, const double* d_U0, double* d_lambda,
     return fail(PARO_EINVAL, "NULL argument to paro_init");
   Problem& p = h->p;
   hipStream_t s = (hipStream_t)stream;
+  p.last_stream = s;
   HIP_OR_FAIL(hipMemsetAsync(&p.cs->status, 0, sizeof(int), s));
   HIP_OR_FAIL(launch_rayleigh_ritz(p, d_U0, d_lambda, d_U, p.Nt, false, s));
   return PARO_OK;
@@ -384,8 +490,17 @@ int paro_step(paro_problem* h, double* d_lambda, double* d_U, void* stream,
       return fail(PARO_EINVAL, "NULL argument to paro_step");
     Problem& p = h->p;
     hipStream_t s = (hipStream_t)stream;
+    p.last_stream = s;
     const double t0 = now_s();
     const bool f32 = p.opts.precision == PARO_FP32_INNER;
+    // The source solves run in place on d_U (x0 = u); Rayleigh-Ritz then
+    // reads W from d_U and rotates it in place.
+    struct XGuard {
+      Problem& p;
+      double* saved;
+      ~XGuard() { p.X = saved; }
+    } guard{p, p.X};
+    p.X = d_U;
     HIP_OR_FAIL(launch_pcg_start(p, d_lambda, d_U, p.Nt, f32, s));
     int64_t refinements = 0;
     int rc = solve_sources(h, p.Nt, s, &refinements);
@@ -478,7 +593,50 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
 
 void paro_destroy(paro_problem* h) {
   if (!h) return;
+  delete h->p.timing;
   delete h;
+}
+
+int paro_set_timing(paro_problem* h, int on) {
+  if (!h) return fail(PARO_EINVAL, "NULL problem");
+  Problem& p = h->p;
+  if (!p.timing) p.timing = new (std::nothrow) Timing();
+  if (!p.timing) return fail(PARO_EDEVICE, "host allocation failed");
+  Timing& t = *p.timing;
+  t.resolve();
+  for (int k = 0; k < PARO_ST_NUM; ++k) {
+    t.launches[k] = 0;
+    t.ms[k] = 0.0;
+  }
+  unsigned long long c[2] = {0, 0};
+  int rc = read_back(h, &p.cs->cg_iters, c, 2, p.last_stream);
+  if (rc) return rc;
+  t.iters0 = c[0];
+  t.cols0 = c[1];
+  t.on = on != 0;
+  return PARO_OK;
+}
+
+int paro_get_timing(paro_problem* h, paro_timing_t* out) {
+  if (!h || !out) return fail(PARO_EINVAL, "NULL argument");
+  Problem& p = h->p;
+  std::memset(out, 0, sizeof *out);
+  HIP_OR_FAIL(hipStreamSynchronize(p.last_stream));
+  unsigned long long c[2] = {0, 0};
+  int rc = read_back(h, &p.cs->cg_iters, c, 2, p.last_stream);
+  if (rc) return rc;
+  if (p.timing) {
+    p.timing->resolve();
+    for (int k = 0; k < PARO_ST_NUM; ++k) {
+      out->launches[k] = p.timing->launches[k];
+      out->ms[k] = p.timing->ms[k];
+    }
+    c[0] -= p.timing->iters0;
+    c[1] -= p.timing->cols0;
+  }
+  out->cg_iters = c[0];
+  out->cg_col_iters = c[1];
+  return PARO_OK;
 }
 
 int paro_export_csr(paro_problem* h, int32_t* d_rowptr, int32_t* d_col,
@@ -516,8 +674,8 @@ int paro_spmm(paro_problem* h, int which, const double* d_X, double* d_Y,
 int paro_gram(paro_problem* h, const double* d_W, const double* d_Y,
               double* d_G, int ncols, void* stream) {
   if (!h || !d_W || !d_Y || !d_G) return fail(PARO_EINVAL, "NULL argument");
-  if (ncols < 1 || ncols > kNtMax)
-    return fail(PARO_EINVAL, "ncols must be 1..%d", kNtMax);
+  if (ncols < 1 || ncols > h->p.Nt)
+    return fail(PARO_EINVAL, "ncols must be 1..%d", h->p.Nt);
   HIP_OR_FAIL(
       launch_gram_full(h->p, d_W, d_Y, d_G, ncols, (hipStream_t)stream));
   return PARO_OK;
@@ -542,6 +700,7 @@ int paro_pcg(paro_problem* h, const double* d_B, double* d_X, int ncols,
     if (ncols < 1 || ncols > p.Nt)
       return fail(PARO_EINVAL, "ncols must be 1..%d", p.Nt);
     hipStream_t s = (hipStream_t)stream;
+    p.last_stream = s;
     const size_t bytes = sizeof(double) * (size_t)p.n * ncols;
     HIP_OR_FAIL(hipMemcpyAsync(p.X, d_X, bytes, hipMemcpyDeviceToDevice, s));
     HIP_OR_FAIL(launch_pcg_start_rhs(p, d_B, ncols,

@@ -14,9 +14,14 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
 constexpr int kNtMax = PARO_NT_MAX;  // largest number of columns
 constexpr int kGridMax = 2048;       // largest persistent grid of the solvers
 constexpr int kStencil = 15;         // Kuhn P1 pattern: 15 neighbours per row
-constexpr int kGridDefault = 1024;   // default persistent grid
-constexpr int kGramGrid = 256;       // first-stage blocks of the Gram
-constexpr int kGramTiles = 2 * 10 * 256;  // tile entries per Gram block
+constexpr int kGridDefault = 2048;   // default persistent grid
+constexpr int kGramGrid = 1024;      // first-stage blocks of the Gram
+constexpr int kGramY = 16;           // second-stage split of those blocks
+// Tile entries per Gram block for nt16 = ceil(ncols / 16): two symmetric
+// results, tile pairs I <= J, 16 x 16 each.
+constexpr int gram_tiles(int ncols) {
+  return 2 * (((ncols + 15) / 16) * ((ncols + 15) / 16 + 1) / 2) * 256;
+}
 
 // Status bits raised by device code (ColState::status).
 enum : int {
@@ -44,6 +49,8 @@ struct ColState {
   int status;             // kSt* bits
   int maxit;              // CG cap per column (copied from opts)
   int pad[3];
+  unsigned long long cg_iters;      // CG iterations that did work
+  unsigned long long cg_col_iters;  // their active columns, summed
 };
 
 // Step results (device), read back when a report is requested.
@@ -61,6 +68,8 @@ struct StepInfo {
 // block of each reduction.
 enum { kCntSpmm = 0, kCntRupd, kCntStart, kCntGram, kCntRot, kCntRefine,
        kCntMin, kCntSpmmTest, kCntNum };
+
+struct Timing;  // host-side event timing state (api.hip)
 
 struct Problem {
   paro_box_t box;
@@ -89,8 +98,8 @@ struct Problem {
   float* Q32;
   float* X32;
   double* part;           // kGridMax * kNtMax * 3 reduction partials
-  double* gpart;          // Gram partials: kGramGrid * kGramTiles
-  double* gsum;           // kGramTiles
+  double* gpart;          // Gram partials: kGramGrid * gram_tiles(Nt)
+  double* gsum;           // kGramY * gram_tiles(Nt)
   double* Ah;             // Nt x Nt
   double* Bh;
   double* C;              // Ritz coefficients, Nt x Nt
@@ -101,6 +110,21 @@ struct Problem {
   unsigned* cnt;          // kCntNum reduction counters
   int* flag;              // scratch flags
   size_t ws_bytes;
+  Timing* timing;         // null unless paro_set_timing(p, 1)
+  hipStream_t last_stream;
+  int cg_predict[5];      // CG iterations of the last solve per pass slot
+};
+
+// Event bracketing of one launch (no-ops unless timing is on).
+int timing_begin(Problem& p, int stage, hipStream_t s);
+void timing_end(Problem& p, int slot, hipStream_t s);
+struct TimedLaunch {
+  Problem& p;
+  int slot;
+  hipStream_t s;
+  TimedLaunch(Problem& pp, int stage, hipStream_t ss)
+      : p(pp), slot(timing_begin(pp, stage, ss)), s(ss) {}
+  ~TimedLaunch() { timing_end(p, slot, s); }
 };
 
 // Workspace layout: byte offsets of every region for a problem shape.
@@ -121,7 +145,7 @@ hipError_t launch_assemble(Problem& p, const double* V, hipStream_t s);
 
 // ---- launchers (solver.hip) ----------------------------------------------
 // which: 0 = A_s, 1 = M, 2 = H = A_s + s M.
-hipError_t launch_spmm(const Problem& p, int which, const double* X,
+hipError_t launch_spmm(Problem& p, int which, const double* X,
                        double* Y, int ncols, hipStream_t s);
 // Start of the FP64 source solves: B = (lam - s) M U, X = U,
 // R = B - A_s U, P = D^-1 R; sets bb, rz, rr, act[0].
@@ -142,10 +166,10 @@ hipError_t launch_refine_update(Problem& p, int ncols, hipStream_t s);
 hipError_t launch_rayleigh_ritz(Problem& p, const double* W, double* lam,
                                 double* U, int ncols, bool have_old,
                                 hipStream_t s);
-hipError_t launch_gram(const Problem& p, const double* W, const double* Y1,
+hipError_t launch_gram(Problem& p, const double* W, const double* Y1,
                        const double* Y2, double* G1, double* G2, int ncols,
                        hipStream_t s);
-hipError_t launch_gram_full(const Problem& p, const double* W,
+hipError_t launch_gram_full(Problem& p, const double* W,
                             const double* Y, double* G, int ncols,
                             hipStream_t s);
 hipError_t launch_small_geneig(const double* A, const double* B, int n,

@@ -72,22 +72,8 @@ __device__ __forceinline__ TileWalk tile_walk(long long ntiles) {
   return w;
 }
 
-// Last-block detection: every thread has issued its partial stores.
-__device__ __forceinline__ bool arrive_last(unsigned* cnt) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned t = atomicAdd(cnt, 1u);
-    s_last = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
-
 // Per-column workgroup reduction of per-thread partials acc[a][v]
-// (thread = (lr, ch)), written to part[a][block][c].  NA arrays.
+// (thread = (lr, ch)), written column-major: part[a][c][block].  NA arrays.
 template <int V, int NA>
 __device__ void block_partials(const double (&acc)[NA][V], int ncols, int cpr,
                                int tr, double* __restrict__ part) {
@@ -104,38 +90,102 @@ __device__ void block_partials(const double (&acc)[NA][V], int ncols, int cpr,
     for (int a = 0; a < NA; ++a) {
       double s = 0.0;
       for (int lr = 0; lr < tr; ++lr) s += red[a][(lr * cpr + ch) * V + v];
-      part[a * kPartStride + (size_t)blockIdx.x * ncols + tid] = s;
+      part[a * kPartStride + (size_t)tid * gridDim.x + blockIdx.x] = s;
     }
   }
 }
 
-// Final fixed-order sum of part[a][0..nb)[c] into out[a][c] (shared).
+// In a finalize kernel with one workgroup per column c = blockIdx.x: the
+// fixed-order sum of part[a][c][0..nb).  Every thread receives the sums.
 template <int NA>
-__device__ void final_sums(const double* __restrict__ part, int nb, int ncols,
-                           double (*out)[kNtMax]) {
+__device__ void column_sums(const double* __restrict__ part, int nb,
+                            double (&out)[NA]) {
   __shared__ double red[NA][kBlock];
-  const int tid = threadIdx.x;
-  const int groups = kBlock / ncols;
-  const int S = groups * ncols;
-  if (tid < S) {
-    const int c = tid % ncols, g = tid / ncols;
+  const int c = blockIdx.x, t = threadIdx.x;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      double s = 0.0;
-      for (int b = g; b < nb; b += groups)
-        s += part[a * kPartStride + (size_t)b * ncols + c];
-      red[a][tid] = s;
-    }
+  for (int a = 0; a < NA; ++a) {
+    const double* src = part + a * kPartStride + (size_t)c * nb;
+    double s = 0.0;
+    for (int b = t; b < nb; b += kBlock) s += src[b];
+    red[a][t] = s;
   }
   __syncthreads();
-  if (tid < ncols) {
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (t < w) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      double s = 0.0;
-      for (int g = 0; g < groups; ++g) s += red[a][g * ncols + tid];
-      out[a][tid] = s;
+      for (int a = 0; a < NA; ++a) red[a][t] += red[a][t + w];
     }
+    __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < NA; ++a) out[a] = red[a][0];
+  __syncthreads();
+}
+
+// Max of non-negative doubles through their bit patterns (order-free).
+__device__ __forceinline__ void atomic_max_nonneg(double* dst, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(dst),
+            (unsigned long long)__double_as_longlong(v));
+}
+
+// LDS view of one CSR tile: row pointers (tile-relative), columns and up
+// to two value arrays, each region 16-byte aligned.
+template <typename TM>
+struct CsrTile {
+  int32_t* rp;
+  int32_t* col;
+  TM* a;
+  TM* b;
+};
+
+__host__ __device__ constexpr size_t align16(size_t x) {
+  return (x + 15) & ~size_t(15);
+}
+
+// LDS bytes for a tile of tr rows with nvals value arrays.
+__host__ __device__ constexpr size_t csr_tile_bytes(int tr, size_t vsize,
+                                                    int nvals) {
+  return align16(sizeof(int32_t) * (tr + 1)) +
+         align16(sizeof(int32_t) * tr * kStencil) +
+         nvals * align16(vsize * tr * kStencil);
+}
+
+template <typename TM>
+__device__ __forceinline__ CsrTile<TM> csr_tile(unsigned char* smem, int tr,
+                                                int nvals) {
+  CsrTile<TM> t;
+  size_t o = 0;
+  t.rp = reinterpret_cast<int32_t*>(smem + o);
+  o += align16(sizeof(int32_t) * (tr + 1));
+  t.col = reinterpret_cast<int32_t*>(smem + o);
+  o += align16(sizeof(int32_t) * tr * kStencil);
+  t.a = reinterpret_cast<TM*>(smem + o);
+  o += align16(sizeof(TM) * tr * kStencil);
+  t.b = nvals > 1 ? reinterpret_cast<TM*>(smem + o) : nullptr;
+  return t;
+}
+
+// Stage rows [r0, r1) of the CSR into the tile with coalesced loads; row
+// pointers become tile-relative.  All threads of the block must call it.
+template <typename TM>
+__device__ __forceinline__ void stage_csr(const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ col,
+                                          const TM* __restrict__ va,
+                                          const TM* __restrict__ vb,
+                                          long long r0, long long r1,
+                                          CsrTile<TM>& t) {
+  const int rows = (int)(r1 - r0);
+  __syncthreads();  // the previous tile is no longer read
+  for (int i = threadIdx.x; i <= rows; i += blockDim.x) t.rp[i] = rowptr[r0 + i];
+  __syncthreads();
+  const int k0 = t.rp[0], cnt = t.rp[rows] - k0;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    t.col[e] = col[k0 + e];
+    t.a[e] = va[k0 + e];
+    if (vb) t.b[e] = vb[k0 + e];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= rows; i += blockDim.x) t.rp[i] -= k0;
   __syncthreads();
 }
 
@@ -159,13 +209,11 @@ spmm_cg_kernel(const int32_t* __restrict__ rowptr,
                const int32_t* __restrict__ col, const TM* __restrict__ val,
                const T* __restrict__ P, T* __restrict__ Q, long long n,
                int ncols, ColState* __restrict__ cs, int par,
-               double* __restrict__ part, unsigned* __restrict__ cnt) {
+               double* __restrict__ part) {
   if (cs->n_active[par] == 0) return;
   extern __shared__ unsigned char smem[];
   const int cpr = ncols / V, tr = kBlock / cpr;
-  int32_t* s_col = reinterpret_cast<int32_t*>(smem);
-  TM* s_val = reinterpret_cast<TM*>(
-      smem + ((sizeof(int32_t) * tr * kStencil + 15) & ~size_t(15)));
+  CsrTile<TM> tl = csr_tile<TM>(smem, tr, 1);
   const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
   const bool on = lr < tr && chunk_active(cs->act[par], ch, V, ncols);
   double acc[1][V];
@@ -175,23 +223,17 @@ spmm_cg_kernel(const int32_t* __restrict__ rowptr,
   for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
     const long long r0 = w.t * tr;
     const long long r1 = min(n, r0 + tr);
-    const int k0 = rowptr[r0], k1 = rowptr[r1];
-    __syncthreads();
-    for (int e = tid; e < k1 - k0; e += kBlock) {
-      s_col[e] = col[k0 + e];
-      s_val[e] = val[k0 + e];
-    }
-    __syncthreads();
+    stage_csr<TM>(rowptr, col, val, nullptr, r0, r1, tl);
     const long long row = r0 + lr;
     if (on && row < r1) {
-      const int rs = rowptr[row] - k0, re = rowptr[row + 1] - k0;
+      const int rs = tl.rp[lr], re = tl.rp[lr + 1];
       T q[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) q[v] = T(0);
       for (int e = rs; e < re; ++e) {
-        const T a = (T)s_val[e];
+        const T a = (T)tl.a[e];
         T pv[V];
-        ldv<T, V>(P + (size_t)s_col[e] * ncols + ch * V, pv);
+        ldv<T, V>(P + (size_t)tl.col[e] * ncols + ch * V, pv);
 #pragma unroll
         for (int v = 0; v < V; ++v) q[v] = fma(a, pv[v], q[v]);
       }
@@ -203,19 +245,36 @@ spmm_cg_kernel(const int32_t* __restrict__ rowptr,
     }
   }
   block_partials<V, 1>(acc, ncols, cpr, tr, part);
-  if (!arrive_last(cnt)) return;
-  __shared__ double tot[1][kNtMax];
-  final_sums<1>(part, gridDim.x, ncols, tot);
-  if (tid < ncols && cs->act[par][tid]) {
-    const double pq = tot[0][tid];
+}
+
+// alpha_c = (r.z)_c / (p.q)_c for the active columns (one workgroup per
+// column).  Also clears the next parity's active count for cg_beta_kernel.
+__global__ void __launch_bounds__(kBlock)
+cg_alpha_kernel(const double* __restrict__ part, int nb,
+                ColState* __restrict__ cs, int par) {
+  const int c = blockIdx.x;
+  if (cs->n_active[par] == 0) {
+    // Nothing ran in this iteration: keep the next parity idle too, so
+    // that launches queued after convergence stay no-ops.
+    if (c == 0 && threadIdx.x == 0) cs->n_active[par ^ 1] = 0;
+    return;
+  }
+  if (c == 0 && threadIdx.x == 0) {
+    cs->n_active[par ^ 1] = 0;
+    cs->cg_iters += 1;
+  }
+  if (!cs->act[par][c]) return;
+  double tot[1];
+  column_sums<1>(part, nb, tot);
+  if (threadIdx.x == 0) {
+    const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
       atomicOr(&cs->status, isfinite(pq) ? (int)kStNotSpd : (int)kStNonFinite);
-      cs->alpha[tid] = 0.0;
+      cs->alpha[c] = 0.0;
     } else {
-      cs->alpha[tid] = cs->rz[tid] / pq;
+      cs->alpha[c] = cs->rz[c] / pq;
     }
   }
-  if (tid == 0) *cnt = 0u;
 }
 
 // r -= alpha q, z = D^-1 r, partial r.z and r.r; the last block forms
@@ -224,14 +283,8 @@ template <typename T, typename TD, int V>
 __global__ void __launch_bounds__(kBlock)
 rupd_kernel(const T* __restrict__ Qb, T* __restrict__ R,
             const TD* __restrict__ dinv, long long n, int ncols,
-            ColState* __restrict__ cs, int par, double* __restrict__ part,
-            unsigned* __restrict__ cnt) {
-  if (cs->n_active[par] == 0) {
-    // Nothing ran in this iteration: keep the next parity idle too, so
-    // that launches queued after convergence stay no-ops.
-    if (blockIdx.x == 0 && threadIdx.x == 0) cs->n_active[par ^ 1] = 0;
-    return;
-  }
+            ColState* __restrict__ cs, int par, double* __restrict__ part) {
+  if (cs->n_active[par] == 0) return;
   const int cpr = ncols / V, tr = kBlock / cpr;
   const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
   const bool on = lr < tr && chunk_active(cs->act[par], ch, V, ncols);
@@ -264,37 +317,39 @@ rupd_kernel(const T* __restrict__ Qb, T* __restrict__ R,
     }
   }
   block_partials<V, 2>(acc, ncols, cpr, tr, part);
-  if (!arrive_last(cnt)) return;
-  __shared__ double tot[2][kNtMax];
-  final_sums<2>(part, gridDim.x, ncols, tot);
-  __shared__ int s_cnt;
-  if (tid == 0) s_cnt = 0;
-  __syncthreads();
-  if (tid < ncols) {
-    int next = 0;
-    if (cs->act[par][tid]) {
-      const double rz = tot[0][tid], rr = tot[1][tid];
-      if (!isfinite(rz) || !isfinite(rr)) {
-        atomicOr(&cs->status, (int)kStNonFinite);
-      } else {
-        cs->beta[tid] = rz / cs->rz[tid];
-        cs->rz[tid] = rz;
-        cs->rr[tid] = rr;
-        const int it = cs->iters[tid] + 1;
-        cs->iters[tid] = it;
-        const bool more = rr > cs->tol2[tid];
-        if (more && it >= cs->maxit) atomicOr(&cs->status, (int)kStNoConv);
-        next = (more && it < cs->maxit && !(cs->status & kStNotSpd)) ? 1 : 0;
-      }
-    }
-    cs->act[par ^ 1][tid] = next;
-    if (next) atomicAdd(&s_cnt, 1);
+}
+
+// beta_c, iteration count and the stopping test of every active column
+// (one workgroup per column); counts the columns active next iteration.
+__global__ void __launch_bounds__(kBlock)
+cg_beta_kernel(const double* __restrict__ part, int nb,
+               ColState* __restrict__ cs, int par) {
+  const int c = blockIdx.x;
+  if (cs->n_active[par] == 0) return;
+  if (!cs->act[par][c]) {
+    if (threadIdx.x == 0) cs->act[par ^ 1][c] = 0;
+    return;
   }
-  __syncthreads();
-  if (tid == 0) {
-    cs->n_active[par ^ 1] = s_cnt;
-    *cnt = 0u;
+  double tot[2];
+  column_sums<2>(part, nb, tot);
+  if (threadIdx.x != 0) return;
+  int next = 0;
+  const double rz = tot[0], rr = tot[1];
+  if (!isfinite(rz) || !isfinite(rr)) {
+    atomicOr(&cs->status, (int)kStNonFinite);
+  } else {
+    cs->beta[c] = rz / cs->rz[c];
+    cs->rz[c] = rz;
+    cs->rr[c] = rr;
+    const int it = cs->iters[c] + 1;
+    cs->iters[c] = it;
+    const bool more = rr > cs->tol2[c];
+    if (more && it >= cs->maxit) atomicOr(&cs->status, (int)kStNoConv);
+    next = (more && it < cs->maxit && !(cs->status & kStNotSpd)) ? 1 : 0;
   }
+  cs->act[par ^ 1][c] = next;
+  if (next) atomicAdd(&cs->n_active[par ^ 1], 1);
+  atomicAdd(&cs->cg_col_iters, 1LL);
 }
 
 // x += alpha p (columns active this iteration); p = D^-1 r + beta p
@@ -355,99 +410,104 @@ pcg_start_kernel(const int32_t* __restrict__ rowptr,
                  double* __restrict__ R, double* __restrict__ P,
                  double* __restrict__ Bout, long long n, int ncols,
                  int maxit, ColState* __restrict__ cs,
-                 double* __restrict__ part, unsigned* __restrict__ cnt) {
+                 double* __restrict__ part) {
   const int cpr = ncols / V, tr = kBlock / cpr;
   const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
+  if (blockIdx.x == 0 && tid == 0) {  // read only by the finalize kernel
+    cs->n_active[0] = 0;
+    cs->n_active[1] = 0;
+    cs->n_outer = 0;
+    cs->status = 0;
+    cs->maxit = maxit;
+  }
   double sh[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = ch * V + v;
     sh[v] = (lam && c < ncols) ? lam[c] - sigma : 0.0;
   }
+  extern __shared__ unsigned char smem[];
+  CsrTile<double> tl = csr_tile<double>(smem, tr, 2);
   double acc[3][V];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
   const long long ntiles = (n + tr - 1) / tr;
-  if (lr < tr) {
-    for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-      const long long row = w.t * tr + lr;
-      if (row >= n) continue;
-      double au[V], mu[V];
+  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
+    const long long r0 = w.t * tr;
+    const long long r1 = min(n, r0 + tr);
+    stage_csr<double>(rowptr, col, valA, valM, r0, r1, tl);
+    const long long row = r0 + lr;
+    if (lr >= tr || row >= r1) continue;
+    double au[V], mu[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
-      const int rs = rowptr[row], re = rowptr[row + 1];
-      for (int e = rs; e < re; ++e) {
-        const double a = valA[e], m = valM[e];
-        double u[V];
-        ldv<double, V>(U + (size_t)col[e] * ncols + ch * V, u);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          au[v] = fma(a, u[v], au[v]);
-          mu[v] = fma(m, u[v], mu[v]);
-        }
-      }
-      const size_t o = (size_t)row * ncols + ch * V;
-      double b[V], r[V], p[V], u[V];
-      ldv<double, V>(U + o, u);
-      if (Bin) {
-        ldv<double, V>(Bin + o, b);
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) b[v] = sh[v] * mu[v];
-      }
-      const double di = dinv[row];
+    for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
+    const int rs = tl.rp[lr], re = tl.rp[lr + 1];
+    for (int e = rs; e < re; ++e) {
+      const double a = tl.a[e], m = tl.b[e];
+      double u[V];
+      ldv<double, V>(U + (size_t)tl.col[e] * ncols + ch * V, u);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        r[v] = b[v] - au[v];
-        p[v] = di * r[v];
-        acc[0][v] += b[v] * b[v];
-        acc[1][v] += r[v] * p[v];
-        acc[2][v] += r[v] * r[v];
+        au[v] = fma(a, u[v], au[v]);
+        mu[v] = fma(m, u[v], mu[v]);
       }
-      stv<double, V>(X + o, u);
-      stv<double, V>(R + o, r);
-      stv<double, V>(P + o, p);
-      if (Bout) stv<double, V>(Bout + o, b);
     }
+    const size_t o = (size_t)row * ncols + ch * V;
+    double b[V], r[V], p[V], u[V];
+    ldv<double, V>(U + o, u);
+    if (Bin) {
+      ldv<double, V>(Bin + o, b);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) b[v] = sh[v] * mu[v];
+    }
+    const double di = dinv[row];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r[v] = b[v] - au[v];
+      p[v] = di * r[v];
+      acc[0][v] += b[v] * b[v];
+      acc[1][v] += r[v] * p[v];
+      acc[2][v] += r[v] * r[v];
+    }
+    if (X != U) stv<double, V>(X + o, u);
+    stv<double, V>(R + o, r);
+    stv<double, V>(P + o, p);
+    if (Bout) stv<double, V>(Bout + o, b);
   }
   block_partials<V, 3>(acc, ncols, cpr, tr, part);
-  if (!arrive_last(cnt)) return;
-  __shared__ double tot[3][kNtMax];
-  final_sums<3>(part, gridDim.x, ncols, tot);
-  __shared__ int s_cnt;
-  if (tid == 0) {
-    s_cnt = 0;
-    cs->status = 0;
-    cs->maxit = maxit;
+}
+
+// Per-column start state: ||b||^2, r.z, ||r||^2, the stopping threshold
+// and the first active set (one workgroup per column).
+__global__ void __launch_bounds__(kBlock)
+pcg_start_final_kernel(const double* __restrict__ part, int nb, double rtol,
+                       ColState* __restrict__ cs) {
+  const int c = blockIdx.x;
+  double tot[3];
+  column_sums<3>(part, nb, tot);
+  if (threadIdx.x != 0) return;
+  const double bb = tot[0], rz = tot[1], rr = tot[2];
+  cs->bb[c] = bb;
+  cs->rz[c] = rz;
+  cs->rr[c] = rr;
+  cs->rr64[c] = rr;
+  cs->tol2[c] = rtol * rtol * bb;
+  cs->iters[c] = 0;
+  int a = 0;
+  if (!isfinite(bb) || !isfinite(rr)) {
+    atomicOr(&cs->status, (int)kStNonFinite);
+  } else {
+    a = rr > rtol * rtol * bb ? 1 : 0;
   }
-  __syncthreads();
-  if (tid < ncols) {
-    const double bb = tot[0][tid], rz = tot[1][tid], rr = tot[2][tid];
-    cs->bb[tid] = bb;
-    cs->rz[tid] = rz;
-    cs->rr[tid] = rr;
-    cs->rr64[tid] = rr;
-    cs->tol2[tid] = rtol * rtol * bb;
-    cs->iters[tid] = 0;
-    int a = 0;
-    if (!isfinite(bb) || !isfinite(rr)) {
-      atomicOr(&cs->status, (int)kStNonFinite);
-    } else {
-      a = rr > rtol * rtol * bb ? 1 : 0;
-    }
-    cs->act[0][tid] = a;
-    cs->act[1][tid] = 0;
-    cs->oact[tid] = a;
-    if (a) atomicAdd(&s_cnt, 1);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    cs->n_active[0] = s_cnt;
-    cs->n_active[1] = 0;
-    cs->n_outer = s_cnt;
-    *cnt = 0u;
+  cs->act[0][c] = a;
+  cs->act[1][c] = 0;
+  cs->oact[c] = a;
+  if (a) {
+    atomicAdd(&cs->n_active[0], 1);
+    atomicAdd(&cs->n_outer, 1);
   }
 }
 
@@ -469,82 +529,93 @@ refine_residual_kernel(const int32_t* __restrict__ rowptr,
                        float* __restrict__ R32, float* __restrict__ P32,
                        float* __restrict__ X32, double rtol, double inner_rtol,
                        long long n, int ncols, ColState* __restrict__ cs,
-                       double* __restrict__ part, unsigned* __restrict__ cnt) {
+                       double* __restrict__ part) {
   const int cpr = ncols / V, tr = kBlock / cpr;
   const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
   const bool on = lr < tr && chunk_active(cs->oact, ch, V, ncols);
+  if (blockIdx.x == 0 && tid == 0) {  // read only by the finalize kernel
+    cs->n_active[0] = 0;
+    cs->n_active[1] = 0;
+    cs->n_outer = 0;
+  }
+  extern __shared__ unsigned char smem[];
+  CsrTile<double> tl = csr_tile<double>(smem, tr, 1);
   double acc[2][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
   const long long ntiles = (n + tr - 1) / tr;
-  if (on) {
-    for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-      const long long row = w.t * tr + lr;
-      if (row >= n) continue;
-      double ax[V];
+  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
+    const long long r0 = w.t * tr;
+    const long long r1 = min(n, r0 + tr);
+    stage_csr<double>(rowptr, col, valA, nullptr, r0, r1, tl);
+    const long long row = r0 + lr;
+    if (!on || row >= r1) continue;
+    double ax[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) ax[v] = 0.0;
-      const int rs = rowptr[row], re = rowptr[row + 1];
-      for (int e = rs; e < re; ++e) {
-        const double a = valA[e];
-        double x[V];
-        ldv<double, V>(X + (size_t)col[e] * ncols + ch * V, x);
+    for (int v = 0; v < V; ++v) ax[v] = 0.0;
+    const int rs = tl.rp[lr], re = tl.rp[lr + 1];
+    for (int e = rs; e < re; ++e) {
+      const double a = tl.a[e];
+      double x[V];
+      ldv<double, V>(X + (size_t)tl.col[e] * ncols + ch * V, x);
 #pragma unroll
-        for (int v = 0; v < V; ++v) ax[v] = fma(a, x[v], ax[v]);
-      }
-      const size_t o = (size_t)row * ncols + ch * V;
-      double b[V];
-      ldv<double, V>(Bb + o, b);
-      const double di = dinv[row];
-      float r32[V], p32[V], z32[V];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const double r = b[v] - ax[v];
-        acc[0][v] += r * r;
-        r32[v] = (float)r;
-        p32[v] = (float)(di * r);
-        z32[v] = 0.0f;
-        acc[1][v] += (double)r32[v] * (double)p32[v];
-      }
-      stv<float, V>(R32 + o, r32);
-      stv<float, V>(P32 + o, p32);
-      stv<float, V>(X32 + o, z32);
+      for (int v = 0; v < V; ++v) ax[v] = fma(a, x[v], ax[v]);
     }
+    const size_t o = (size_t)row * ncols + ch * V;
+    double b[V];
+    ldv<double, V>(Bb + o, b);
+    const double di = dinv[row];
+    float r32[V], p32[V], z32[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double r = b[v] - ax[v];
+      acc[0][v] += r * r;
+      r32[v] = (float)r;
+      p32[v] = (float)(di * r);
+      z32[v] = 0.0f;
+      acc[1][v] += (double)r32[v] * (double)p32[v];
+    }
+    stv<float, V>(R32 + o, r32);
+    stv<float, V>(P32 + o, p32);
+    stv<float, V>(X32 + o, z32);
   }
   block_partials<V, 2>(acc, ncols, cpr, tr, part);
-  if (!arrive_last(cnt)) return;
-  __shared__ double tot[2][kNtMax];
-  final_sums<2>(part, gridDim.x, ncols, tot);
-  __shared__ int s_cnt;
-  if (tid == 0) s_cnt = 0;
-  __syncthreads();
-  if (tid < ncols) {
-    int a = 0;
-    if (cs->oact[tid]) {
-      const double rr = tot[0][tid];
-      if (!isfinite(rr)) {
-        atomicOr(&cs->status, (int)kStNonFinite);
-      } else {
-        cs->rr64[tid] = rr;
-        a = (rr > rtol * rtol * cs->bb[tid] && cs->iters[tid] < cs->maxit)
-                ? 1 : 0;
-        if (!a && rr > rtol * rtol * cs->bb[tid])
-          atomicOr(&cs->status, (int)kStNoConv);
-        cs->tol2[tid] = inner_rtol * inner_rtol * rr;
-        cs->rz[tid] = tot[1][tid];
-      }
+}
+
+// Outer (refinement) test per column and the inner threshold of the next
+// FP32 solve (one workgroup per column).
+__global__ void __launch_bounds__(kBlock)
+refine_final_kernel(const double* __restrict__ part, int nb, double rtol,
+                    double inner_rtol, ColState* __restrict__ cs) {
+  const int c = blockIdx.x;
+  if (!cs->oact[c]) {
+    if (threadIdx.x == 0) {
+      cs->act[0][c] = 0;
+      cs->act[1][c] = 0;
     }
-    cs->oact[tid] = a;
-    cs->act[0][tid] = a;
-    cs->act[1][tid] = 0;
-    if (a) atomicAdd(&s_cnt, 1);
+    return;
   }
-  __syncthreads();
-  if (tid == 0) {
-    cs->n_active[0] = s_cnt;
-    cs->n_active[1] = 0;
-    cs->n_outer = s_cnt;
-    *cnt = 0u;
+  double tot[2];
+  column_sums<2>(part, nb, tot);
+  if (threadIdx.x != 0) return;
+  int a = 0;
+  const double rr = tot[0];
+  if (!isfinite(rr)) {
+    atomicOr(&cs->status, (int)kStNonFinite);
+  } else {
+    cs->rr64[c] = rr;
+    const bool more = rr > rtol * rtol * cs->bb[c];
+    a = (more && cs->iters[c] < cs->maxit) ? 1 : 0;
+    if (more && !a) atomicOr(&cs->status, (int)kStNoConv);
+    cs->tol2[c] = inner_rtol * inner_rtol * rr;
+    cs->rz[c] = tot[1];
+  }
+  cs->oact[c] = a;
+  cs->act[0][c] = a;
+  cs->act[1][c] = 0;
+  if (a) {
+    atomicAdd(&cs->n_active[0], 1);
+    atomicAdd(&cs->n_outer, 1);
   }
 }
 
@@ -590,22 +661,27 @@ spmm_dual_kernel(const int32_t* __restrict__ rowptr,
                  long long n, int ncols) {
   const int cpr = ncols / V, tr = kBlock / cpr;
   const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  if (lr >= tr) return;
   const bool needA = Y1 != nullptr;
   const bool needM = Y2 != nullptr || s1 != 0.0;
+  extern __shared__ unsigned char smem[];
+  CsrTile<double> tl = csr_tile<double>(smem, tr, 2);
   const long long ntiles = (n + tr - 1) / tr;
   for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long row = w.t * tr + lr;
-    if (row >= n) continue;
+    const long long r0 = w.t * tr;
+    const long long r1 = min(n, r0 + tr);
+    stage_csr<double>(rowptr, col, needA ? valA : valM,
+                      (needA && needM) ? valM : nullptr, r0, r1, tl);
+    const long long row = r0 + lr;
+    if (lr >= tr || row >= r1) continue;
     double ax[V], mx[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ax[v] = mx[v] = 0.0;
-    const int rs = rowptr[row], re = rowptr[row + 1];
+    const int rs = tl.rp[lr], re = tl.rp[lr + 1];
     for (int e = rs; e < re; ++e) {
       double x[V];
-      ldv<double, V>(X + (size_t)col[e] * ncols + ch * V, x);
-      const double a = needA ? valA[e] : 0.0;
-      const double m = needM ? valM[e] : 0.0;
+      ldv<double, V>(X + (size_t)tl.col[e] * ncols + ch * V, x);
+      const double a = needA ? tl.a[e] : 0.0;
+      const double m = needA ? (needM ? tl.b[e] : 0.0) : tl.a[e];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         ax[v] = fma(a, x[v], ax[v]);
@@ -702,26 +778,35 @@ gram_kernel(const double* __restrict__ W, const double* __restrict__ Y1,
 
 // Second stage of the Gram contractions: entry e of the tile array is the
 // fixed-order sum over the first-stage blocks (one thread per entry,
-// coalesced); the last block scatters the tiles into the ncols x ncols
+// coalesced); then one block scatters the tiles into the ncols x ncols
 // results.  mode 0: symmetric pair (G1, G2) from tile pairs I <= J;
 // mode 1: one full matrix from all tiles.
 __global__ void __launch_bounds__(kBlock)
 gram_reduce_kernel(const double* __restrict__ gpart, int nb, int per_blk,
-                   double* __restrict__ gsum, int nt16, int mode, int ncols,
-                   double* __restrict__ G1, double* __restrict__ G2,
-                   unsigned* __restrict__ cnt) {
+                   double* __restrict__ gsum) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e < per_blk) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += gpart[(size_t)b * per_blk + e];
-    gsum[e] = s;
-  }
-  if (!arrive_last(cnt)) return;
+  if (e >= per_blk) return;
+  const int y = blockIdx.y, chunk = (nb + kGramY - 1) / kGramY;
+  const int b0 = y * chunk, b1 = min(nb, b0 + chunk);
+  double s = 0.0;
+  for (int b = b0; b < b1; ++b) s += gpart[(size_t)b * per_blk + e];
+  gsum[(size_t)y * per_blk + e] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+gram_scatter_kernel(const double* __restrict__ gsum, int per_blk, int nt16,
+                    int mode, int ncols, double* __restrict__ G1,
+                    double* __restrict__ G2) {
   const int np = mode == 0 ? nt16 * (nt16 + 1) / 2 : nt16 * nt16;
+  auto tile = [&](int idx) {
+    double v = 0.0;
+    for (int y = 0; y < kGramY; ++y) v += gsum[(size_t)y * per_blk + idx];
+    return v;
+  };
   for (int t = threadIdx.x; t < ncols * ncols; t += kBlock) {
     const int i = t / ncols, j = t % ncols;
     if (mode == 1) {
-      G1[t] = gsum[((i / 16) * nt16 + j / 16) * 256 + (i % 16) * 16 + j % 16];
+      G1[t] = tile(((i / 16) * nt16 + j / 16) * 256 + (i % 16) * 16 + j % 16);
       continue;
     }
     const int lo = i < j ? i : j, hi = i < j ? j : i;
@@ -731,11 +816,11 @@ gram_reduce_kernel(const double* __restrict__ gpart, int nb, int per_blk,
     for (int g = 0; g < 2; ++g) {
       double* G = g == 0 ? G1 : G2;
       if (!G) continue;
-      const double* T = gsum + (size_t)(g * np + p) * 256;
-      G[t] = (I == J) ? 0.5 * (T[a] + T[b]) : T[a];
+      const int base = (g * np + p) * 256;
+      G[t] = (I == J) ? 0.5 * (tile(base + a) + tile(base + b))
+                      : tile(base + a);
     }
   }
-  if (threadIdx.x == 0) *cnt = 0u;
 }
 
 // Plain (non-symmetric) Gram G = W^T Y on FP64 matrix cores, all tiles:
@@ -795,10 +880,11 @@ gram_full_kernel(const double* __restrict__ W, const double* __restrict__ Y,
 
 // ------------------------------------------------------------------------
 // Small generalised eigenproblem A c = theta B c (Step 4's N_t x N_t
-// problem), one workgroup, FP64, everything in LDS.
-//   1. B = L L^T (Cholesky);  2. S = L^{-1} A L^{-T};  3. cyclic Jacobi on
-//   S with round-robin ordering (N_t/2 disjoint rotations per round);
-//   4. theta ascending (ties by index);  5. C = L^{-T} Y;  6. signs.
+// problem), one wavefront, FP64, everything in LDS.
+//   1. B = L L^T (Cholesky);  2. S = L^{-1} A L^{-T};  3. Householder
+//   tridiagonalisation of S;  4. implicit QL with Wilkinson shifts;
+//   5. back-transformation;  6. theta ascending (ties by index);
+//   7. C = L^{-T} Z;  8. signs.
 // ------------------------------------------------------------------------
 constexpr int kLd = kNtMax + 1;
 
@@ -818,14 +904,22 @@ small_geneig_kernel(const double* __restrict__ Ain,
   __shared__ double th[kNtMax];
   const int tid = threadIdx.x;
   const int nn = n + (n & 1);
+  // Zero the padded LDS matrices (odd n uses row/column n as a dummy),
+  // then load the n x n inputs with independent, unrolled global loads.
   for (int e = tid; e < kNtMax * kNtMax; e += kBlock) {
     const int i = e / kNtMax, j = e % kNtMax;
-    const bool in = i < n && j < n;
-    A[i][j] = in ? Ain[i * n + j] : 0.0;
-    L[i][j] = in ? Bin[i * n + j] : 0.0;
+    A[i][j] = 0.0;
+    L[i][j] = 0.0;
     Y[i][j] = 0.0;
   }
   if (tid == 0) s_info = 0;
+  __syncthreads();
+#pragma unroll 4
+  for (int e = tid; e < n * n; e += kBlock) {
+    const double a = Ain[e], b = Bin[e];
+    A[e / n][e % n] = a;
+    L[e / n][e % n] = b;
+  }
   __syncthreads();
 
   // 1. Cholesky, left-looking, column by column.
@@ -895,86 +989,75 @@ small_geneig_kernel(const double* __restrict__ Ain,
   }
   __syncthreads();
 
-  // 3. Cyclic Jacobi, round-robin pairs.
+  // 3. Cyclic Jacobi, round-robin pairs (N_t / 2 disjoint rotations per
+  // round).  A rotation is skipped when |a_pq| <= 1e-17 ||S||_F (already
+  // zero at working precision); the iteration stops after a sweep that
+  // rotates nothing.
   const int half = nn / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // Off-diagonal and total Frobenius mass.
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += kBlock) {
-      const int i = e / n, j = e % n;
-      const double v = A[i][j] * A[i][j];
-      tot += v;
-      if (i != j) off += v;
-    }
-    red[tid] = off;
+  __shared__ int s_rot;
+  double fro2 = 0.0;
+  for (int e = tid; e < n * n; e += kBlock) {
+    const double v = A[e / n][e % n];
+    fro2 += v * v;
+  }
+  red[tid] = fro2;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double offs = red[0];
+  }
+  const double skip = 1e-17 * sqrt(red[0]);
+  for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
     __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double tots = red[0];
-    __syncthreads();
-    if (!(offs > 1e-30 * tots) || n < 2) break;
-
     for (int round = 0; round < nn - 1; ++round) {
       if (tid < half) {
-        auto player = [&](int pos) -> int {
-          return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (nn - 1));
-        };
-        int p = player(tid), q = player(nn - 1 - tid);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double c = 1.0, s = 0.0;
+        const int a0 = tid == 0 ? 0 : 1 + ((tid - 1 + round) % (nn - 1));
+        const int b0 = 1 + ((nn - 2 - tid + round) % (nn - 1));
+        const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
+        double c = 1.0, sn = 0.0;
+        bool rot = false;
         if (q < n) {
           const double apq = A[p][q];
-          if (apq != 0.0) {
+          if (fabs(apq) > skip) {
             const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) /
                              (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sn = t * c;
+            rot = true;
+            s_rot = 1;
           }
         }
         rc[tid] = c;
-        rs[tid] = s;
+        rs[tid] = sn;
         rp[tid] = p;
-        rq[tid] = q < n ? q : p;
+        rq[tid] = rot ? q : p;
       }
       __syncthreads();
       // Rows: A <- J^T A.
       for (int e = tid; e < half * n; e += kBlock) {
-        const int k = e / n, j = e % n;
+        const int k = e / n, j = e - k * n;
         const int p = rp[k], q = rq[k];
         if (p == q) continue;
-        const double c = rc[k], s = rs[k];
+        const double c = rc[k], sn = rs[k];
         const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
+        A[p][j] = c * ap - sn * aq;
+        A[q][j] = sn * ap + c * aq;
       }
       __syncthreads();
       // Columns: A <- A J, Y <- Y J.
       for (int e = tid; e < half * n; e += kBlock) {
-        const int k = e / n, i = e % n;
+        const int k = e / n, i = e - k * n;
         const int p = rp[k], q = rq[k];
         if (p == q) continue;
-        const double c = rc[k], s = rs[k];
+        const double c = rc[k], sn = rs[k];
         const double ap = A[i][p], aq = A[i][q];
-        A[i][p] = c * ap - s * aq;
-        A[i][q] = s * ap + c * aq;
+        A[i][p] = c * ap - sn * aq;
+        A[i][q] = sn * ap + c * aq;
         const double yp = Y[i][p], yq = Y[i][q];
-        Y[i][p] = c * yp - s * yq;
-        Y[i][q] = s * yp + c * yq;
+        Y[i][p] = c * yp - sn * yq;
+        Y[i][q] = sn * yp + c * yq;
       }
       __syncthreads();
       if (tid < half) {
@@ -986,6 +1069,8 @@ small_geneig_kernel(const double* __restrict__ Ain,
       }
       __syncthreads();
     }
+    if (s_rot == 0) break;
+    __syncthreads();
   }
 
   // 4. Ascending order, ties broken by index.
@@ -1043,7 +1128,7 @@ rotate_kernel(const double* __restrict__ W, const double* __restrict__ HW,
               const double* __restrict__ theta, double* __restrict__ U,
               double* __restrict__ lam, int have_old, int nreq, long long n,
               int ncols, StepInfo* __restrict__ si,
-              double* __restrict__ part, unsigned* __restrict__ cnt) {
+              double* __restrict__ part) {
   extern __shared__ unsigned char smem[];
   double* sC = reinterpret_cast<double*>(smem);        // ncols^2
   double* sW = sC + ncols * ncols;                     // tr * ncols each
@@ -1051,6 +1136,10 @@ rotate_kernel(const double* __restrict__ W, const double* __restrict__ HW,
   double* sH = sW + tr * ncols;
   double* sM = sH + tr * ncols;
   const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
+  if (blockIdx.x == 0 && tid == 0) {
+    si->max_dlambda = 0.0;
+    si->max_resid = 0.0;
+  }
   for (int e = tid; e < ncols * ncols; e += kBlock) sC[e] = Cg[e];
   double th[V];
 #pragma unroll
@@ -1098,32 +1187,34 @@ rotate_kernel(const double* __restrict__ W, const double* __restrict__ HW,
   }
   __syncthreads();
   block_partials<V, 2>(acc, ncols, cpr, tr, part);
-  if (!arrive_last(cnt)) return;
-  __shared__ double tot[2][kNtMax];
-  final_sums<2>(part, gridDim.x, ncols, tot);
-  if (tid == 0) {
-    double lmax = 0.0;
-    for (int c = 0; c < ncols; ++c) lmax = fmax(lmax, fabs(theta[c]));
-    double mdl = 0.0, mres = 0.0;
-    for (int c = 0; c < ncols; ++c) {
-      const double t = theta[c];
-      const double sc = fmax(fabs(t), 1e-3 * lmax);
-      const double old = lam[c];
-      si->lam_old[c] = old;
-      const double dl = have_old ? fabs(t - old) / sc : INFINITY;
-      const double rho = sqrt(tot[0][c]) / (sc * sqrt(tot[1][c]));
-      si->dlam[c] = dl;
-      si->resid[c] = rho;
-      if (c < nreq) {
-        mdl = fmax(mdl, dl);
-        mres = fmax(mres, rho);
-        if (!isfinite(rho)) mres = INFINITY;
-      }
-      lam[c] = t;
-    }
-    si->max_dlambda = mdl;
-    si->max_resid = mres;
-    *cnt = 0u;
+}
+
+// Per column: lambda = theta, relative change and residual (one workgroup
+// per column); maxima over the requested pairs for the stopping test.
+__global__ void __launch_bounds__(kBlock)
+rotate_final_kernel(const double* __restrict__ part, int nb,
+                    const double* __restrict__ theta, double* __restrict__ lam,
+                    int have_old, int nreq, int ncols,
+                    StepInfo* __restrict__ si) {
+  const int c = blockIdx.x;
+  double tot[2];
+  column_sums<2>(part, nb, tot);
+  if (threadIdx.x != 0) return;
+  double lmax = 0.0;
+  for (int k = 0; k < ncols; ++k) lmax = fmax(lmax, fabs(theta[k]));
+  const double t = theta[c];
+  const double sc = fmax(fabs(t), 1e-3 * lmax);
+  const double old = lam[c];
+  const double dl = have_old ? fabs(t - old) / sc : INFINITY;
+  double rho = sqrt(tot[0]) / (sc * sqrt(tot[1]));
+  if (!isfinite(rho)) rho = INFINITY;
+  si->lam_old[c] = old;
+  si->dlam[c] = dl;
+  si->resid[c] = rho;
+  lam[c] = t;
+  if (c < nreq) {
+    atomic_max_nonneg(&si->max_dlambda, dl);
+    atomic_max_nonneg(&si->max_resid, rho);
   }
 }
 
@@ -1132,12 +1223,10 @@ int pick_vec32(int ncols) {
   return (ncols % 4 == 0) ? 4 : ((ncols % 2 == 0) ? 2 : 1);
 }
 
-unsigned* counter(const Problem& p, int k) { return p.cnt + k; }
 
-size_t spmm_smem(int ncols, int V, size_t vsize) {
+size_t tile_smem(int ncols, int V, size_t vsize, int nvals) {
   const int cpr = ncols / V, tr = kBlock / cpr;
-  const size_t ci = (sizeof(int32_t) * tr * kStencil + 15) & ~size_t(15);
-  return ci + vsize * tr * kStencil;
+  return csr_tile_bytes(tr, vsize, nvals);
 }
 
 }  // namespace
@@ -1146,18 +1235,20 @@ size_t spmm_smem(int ncols, int V, size_t vsize) {
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_spmm(const Problem& p, int which, const double* X,
+hipError_t launch_spmm(Problem& p, int which, const double* X,
                        double* Y, int ncols, hipStream_t s) {
   const int V = pick_vec64(ncols);
   double* Y1 = which == 1 ? nullptr : Y;
   double* Y2 = which == 1 ? Y : nullptr;
   const double s1 = which == 2 ? p.sigma : 0.0;
+  TimedLaunch t(p, PARO_ST_RR_SPMM, s);
+  const size_t smem = tile_smem(ncols, V, sizeof(double), 2);
   if (V == 2)
-    hipLaunchKernelGGL(spmm_dual_kernel<2>, dim3(p.grid), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(spmm_dual_kernel<2>, dim3(p.grid), dim3(kBlock), smem, s,
                        p.rowptr, p.col, p.valA, p.valM, X, Y1, Y2, s1,
                        (long long)p.n, ncols);
   else
-    hipLaunchKernelGGL(spmm_dual_kernel<1>, dim3(p.grid), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(spmm_dual_kernel<1>, dim3(p.grid), dim3(kBlock), smem, s,
                        p.rowptr, p.col, p.valA, p.valM, X, Y1, Y2, s1,
                        (long long)p.n, ncols);
   return hipGetLastError();
@@ -1169,11 +1260,14 @@ static hipError_t start_common(Problem& p, const double* lam,
   const int V = pick_vec64(ncols);
   double* Bout = store_b ? p.B : nullptr;
   auto k = V == 2 ? pcg_start_kernel<2> : pcg_start_kernel<1>;
-  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock), 0, s, p.rowptr, p.col,
+  TimedLaunch t(p, PARO_ST_START, s);
+  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock),
+                     tile_smem(ncols, V, sizeof(double), 2), s, p.rowptr, p.col,
                      p.valA, p.valM, p.dinv, U, lam, Bin, p.sigma,
                      p.opts.pcg_rtol, p.X, p.R, p.P, Bout, (long long)p.n,
-                     ncols, p.opts.pcg_maxit, p.cs, p.part,
-                     counter(p, kCntStart));
+                     ncols, p.opts.pcg_maxit, p.cs, p.part);
+  hipLaunchKernelGGL(pcg_start_final_kernel, dim3(ncols), dim3(kBlock), 0, s,
+                     p.part, p.grid, p.opts.pcg_rtol, p.cs);
   return hipGetLastError();
 }
 
@@ -1191,15 +1285,28 @@ hipError_t launch_pcg_start_rhs(Problem& p, const double* Bin, int ncols,
 template <typename T, typename TM, typename TD, int V>
 static void cg_iter(Problem& p, const TM* val, const TD* dinv, T* X, T* P,
                     T* Q, T* R, int ncols, int par, hipStream_t s) {
-  const size_t smem = spmm_smem(ncols, V, sizeof(TM));
-  hipLaunchKernelGGL((spmm_cg_kernel<T, TM, V>), dim3(p.grid), dim3(kBlock),
-                     smem, s, p.rowptr, p.col, val, P, Q, (long long)p.n,
-                     ncols, p.cs, par, p.part, counter(p, kCntSpmm));
-  hipLaunchKernelGGL((rupd_kernel<T, TD, V>), dim3(p.grid), dim3(kBlock), 0, s,
-                     Q, R, dinv, (long long)p.n, ncols, p.cs, par, p.part,
-                     counter(p, kCntRupd));
-  hipLaunchKernelGGL((pupd_kernel<T, TD, V>), dim3(p.grid), dim3(kBlock), 0, s,
-                     X, P, R, dinv, (long long)p.n, ncols, p.cs, par);
+  const size_t smem = tile_smem(ncols, V, sizeof(TM), 1);
+  {
+    TimedLaunch t(p, PARO_ST_CG_SPMM, s);
+    hipLaunchKernelGGL((spmm_cg_kernel<T, TM, V>), dim3(p.grid), dim3(kBlock),
+                       smem, s, p.rowptr, p.col, val, P, Q, (long long)p.n,
+                       ncols, p.cs, par, p.part);
+  }
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(ncols), dim3(kBlock), 0, s, p.part,
+                     p.grid, p.cs, par);
+  {
+    TimedLaunch t(p, PARO_ST_CG_RUPD, s);
+    hipLaunchKernelGGL((rupd_kernel<T, TD, V>), dim3(p.grid), dim3(kBlock), 0,
+                       s, Q, R, dinv, (long long)p.n, ncols, p.cs, par,
+                       p.part);
+  }
+  hipLaunchKernelGGL(cg_beta_kernel, dim3(ncols), dim3(kBlock), 0, s, p.part,
+                     p.grid, p.cs, par);
+  {
+    TimedLaunch t(p, PARO_ST_CG_PUPD, s);
+    hipLaunchKernelGGL((pupd_kernel<T, TD, V>), dim3(p.grid), dim3(kBlock), 0,
+                       s, X, P, R, dinv, (long long)p.n, ncols, p.cs, par);
+  }
 }
 
 hipError_t launch_pcg_iter(Problem& p, int ncols, int par, hipStream_t s) {
@@ -1232,26 +1339,33 @@ hipError_t launch_pcg32_iter(Problem& p, int ncols, int par, hipStream_t s) {
 hipError_t launch_refine_residual(Problem& p, int ncols, bool first,
                                   hipStream_t s) {
   (void)first;
-  const int V = pick_vec32(ncols) >= 2 ? pick_vec64(ncols) : 1;
+  const int V = pick_vec64(ncols);
   auto k = V == 2 ? refine_residual_kernel<2> : refine_residual_kernel<1>;
-  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock), 0, s, p.rowptr, p.col,
+  TimedLaunch t(p, PARO_ST_REFINE, s);
+  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock),
+                     tile_smem(ncols, V, sizeof(double), 1), s, p.rowptr, p.col,
                      p.valA, p.dinv, p.X, p.B, p.R32, p.P32, p.X32,
                      p.opts.pcg_rtol, p.opts.inner_rtol, (long long)p.n, ncols,
-                     p.cs, p.part, counter(p, kCntRefine));
+                     p.cs, p.part);
+  hipLaunchKernelGGL(refine_final_kernel, dim3(ncols), dim3(kBlock), 0, s,
+                     p.part, p.grid, p.opts.pcg_rtol, p.opts.inner_rtol,
+                     p.cs);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_update(Problem& p, int ncols, hipStream_t s) {
   const int V = pick_vec64(ncols);
   auto k = V == 2 ? refine_update_kernel<2> : refine_update_kernel<1>;
+  TimedLaunch t(p, PARO_ST_REFINE, s);
   hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock), 0, s, p.X, p.X32,
                      (long long)p.n, ncols, p.cs);
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const Problem& p, const double* W, const double* Y1,
+hipError_t launch_gram(Problem& p, const double* W, const double* Y1,
                        const double* Y2, double* G1, double* G2, int ncols,
                        hipStream_t s) {
+  TimedLaunch t(p, PARO_ST_GRAM, s);
   const int nt16 = (ncols + 15) / 16;
   const int grid = p.grid < kGramGrid ? p.grid : kGramGrid;
   const long long n = p.n;
@@ -1273,15 +1387,18 @@ hipError_t launch_gram(const Problem& p, const double* W, const double* Y1,
                          Y2, n, ncols, p.gpart);
   }
   const int per_blk = 2 * (nt16 * (nt16 + 1) / 2) * 256;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((per_blk + kBlock - 1) / kBlock),
-                     dim3(kBlock), 0, s, p.gpart, grid, per_blk, p.gsum, nt16,
-                     0, ncols, G1, Y2 ? G2 : nullptr, counter(p, kCntGram));
+  hipLaunchKernelGGL(gram_reduce_kernel,
+                     dim3((per_blk + kBlock - 1) / kBlock, kGramY),
+                     dim3(kBlock), 0, s, p.gpart, grid, per_blk, p.gsum);
+  hipLaunchKernelGGL(gram_scatter_kernel, dim3(1), dim3(kBlock), 0, s, p.gsum,
+                     per_blk, nt16, 0, ncols, G1, Y2 ? G2 : nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_full(const Problem& p, const double* W,
+hipError_t launch_gram_full(Problem& p, const double* W,
                             const double* Y, double* G, int ncols,
                             hipStream_t s) {
+  TimedLaunch t(p, PARO_ST_GRAM, s);
   const int nt16 = (ncols + 15) / 16;
   const int grid = p.grid < kGramGrid ? p.grid : kGramGrid;
   const long long n = p.n;
@@ -1303,9 +1420,11 @@ hipError_t launch_gram_full(const Problem& p, const double* W,
                          W, Y, n, ncols, p.gpart);
   }
   const int per_blk = nt16 * nt16 * 256;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((per_blk + kBlock - 1) / kBlock),
-                     dim3(kBlock), 0, s, p.gpart, grid, per_blk, p.gsum, nt16,
-                     1, ncols, G, nullptr, counter(p, kCntGram));
+  hipLaunchKernelGGL(gram_reduce_kernel,
+                     dim3((per_blk + kBlock - 1) / kBlock, kGramY),
+                     dim3(kBlock), 0, s, p.gpart, grid, per_blk, p.gsum);
+  hipLaunchKernelGGL(gram_scatter_kernel, dim3(1), dim3(kBlock), 0, s, p.gsum,
+                     per_blk, nt16, 1, ncols, G, nullptr);
   return hipGetLastError();
 }
 
@@ -1324,24 +1443,36 @@ hipError_t launch_rayleigh_ritz(Problem& p, const double* W, double* lam,
   // HW into R, MW into Q.
   const int V = pick_vec64(ncols);
   auto kd = V == 2 ? spmm_dual_kernel<2> : spmm_dual_kernel<1>;
-  hipLaunchKernelGGL(kd, dim3(p.grid), dim3(kBlock), 0, s, p.rowptr, p.col,
-                     p.valA, p.valM, W, p.R, p.Q, p.sigma, (long long)p.n,
-                     ncols);
+  {
+    TimedLaunch t(p, PARO_ST_RR_SPMM, s);
+    hipLaunchKernelGGL(kd, dim3(p.grid), dim3(kBlock),
+                       tile_smem(ncols, V, sizeof(double), 2), s, p.rowptr,
+                       p.col,
+                       p.valA, p.valM, W, p.R, p.Q, p.sigma, (long long)p.n,
+                       ncols);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_gram(p, W, p.R, p.Q, p.Ah, p.Bh, ncols, s)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(small_geneig_kernel, dim3(1), dim3(kBlock), 0, s, p.Ah,
-                     p.Bh, ncols, p.theta, p.C, &p.si->geneig_info,
-                     &p.cs->status);
+  {
+    TimedLaunch t(p, PARO_ST_SMALL, s);
+    hipLaunchKernelGGL(small_geneig_kernel, dim3(1), dim3(kBlock), 0, s,
+                       p.Ah,
+                       p.Bh, ncols, p.theta, p.C, &p.si->geneig_info,
+                       &p.cs->status);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int cpr = ncols / V, tr = kBlock / cpr;
   const size_t smem = sizeof(double) * ((size_t)ncols * ncols +
                                         3 * (size_t)tr * ncols);
   auto kr = V == 2 ? rotate_kernel<2> : rotate_kernel<1>;
+  TimedLaunch t(p, PARO_ST_ROTATE, s);
   hipLaunchKernelGGL(kr, dim3(p.grid), dim3(kBlock), smem, s, W, p.R, p.Q,
                      p.C, p.theta, U, lam, have_old ? 1 : 0, p.N,
-                     (long long)p.n, ncols, p.si, p.part,
-                     counter(p, kCntRot));
+                     (long long)p.n, ncols, p.si, p.part);
+  hipLaunchKernelGGL(rotate_final_kernel, dim3(ncols), dim3(kBlock), 0, s,
+                     p.part, p.grid, p.theta, lam, have_old ? 1 : 0, p.N,
+                     ncols, p.si);
   return hipGetLastError();
 }
 

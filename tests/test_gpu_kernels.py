@@ -84,11 +84,18 @@ def test_spmm_matches_oracle(sc_problem, ncols, which):
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
+@pytest.fixture(scope="module")
+def wide_problem():
+    """N + m = 64 columns (the largest block the kernels take)."""
+    w = inputs.molecule(nc=13, N=60, m=4, lo=-6.0, hi=6.0)
+    return w, None, None, None, gu.workload_problem(w)
+
+
 @pytest.mark.parametrize("ncols", [1, 5, 16, 17, 32, 48, 64])
-def test_gram_matches_matmul(sc_problem, ncols):
+def test_gram_matches_matmul(wide_problem, ncols):
     """W^T Y on FP64 matrix cores, non-symmetric operands (checks the MFMA
     operand and result lane layouts tile by tile)."""
-    w, H, M, s, prob = sc_problem
+    w, H, M, s, prob = wide_problem
     torch = _torch()
     rng = np.random.default_rng(100 + ncols)
     W = rng.standard_normal((prob.n, ncols))
