@@ -156,6 +156,47 @@ int paro_solve(paro_problem* p, const double* d_U0, double* d_lambda,
 /* Release the host handle (the workspace stays the caller's). */
 void paro_destroy(paro_problem* p);
 
+/* ---------------------------------------------------------------------
+ * Batches: many independent problems advanced by the same launches.
+ * Every kernel of a batched call serves all `count` problems at once
+ * (each problem owns a share of the grid proportional to its work), so
+ * uneven problems (different meshes, N, m, potentials) fill the GPU
+ * together.  Each problem's arithmetic, and so its result, is bitwise the
+ * same as when it runs alone.  All problems of a call must use the same
+ * precision.  The caller passes device memory for the launch table:
+ * d_batch_ws of at least paro_batch_workspace_bytes(count) bytes,
+ * 256-byte aligned (it may be reused by later calls on the same stream).
+ * Arrays of pointers are host arrays of `count` device pointers.
+ * --------------------------------------------------------------------- */
+enum { PARO_BATCH_MAX = 1024 };
+
+size_t paro_batch_workspace_bytes(int32_t count);
+
+/* Step 1 for every problem (see paro_init). */
+int paro_batch_init(paro_problem* const* probs, int32_t count,
+                    const double* const* d_U0, double* const* d_lambda,
+                    double* const* d_U, void* d_batch_ws, size_t bytes,
+                    void* stream);
+
+/* One ParO step (Steps 3 and 4, see paro_step) for every problem.
+ * reports: host array of `count` reports (NULL: no per-problem report and
+ * no synchronisation beyond the CG polls).  Returns PARO_OK unless a
+ * launch failed; per-problem failures are in reports[i].status. */
+int paro_batch_step(paro_problem* const* probs, int32_t count,
+                    double* const* d_lambda, double* const* d_U,
+                    void* d_batch_ws, size_t bytes, void* stream,
+                    paro_report_t* reports);
+
+/* Whole solves of every problem (see paro_solve): problems that meet
+ * their tolerances leave the batch, the others keep stepping until their
+ * own max_steps.  reports (count, required) receive each problem's
+ * summary; the return value is PARO_OK if every problem converged, else
+ * the first non-OK status. */
+int paro_batch_solve(paro_problem* const* probs, int32_t count,
+                     const double* const* d_U0, double* const* d_lambda,
+                     double* const* d_U, void* d_batch_ws, size_t bytes,
+                     void* stream, paro_report_t* reports);
+
 /* Message for the last failing call on this thread (never NULL). */
 const char* paro_last_error(void);
 const char* paro_strerror(int status);

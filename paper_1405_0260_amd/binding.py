@@ -96,6 +96,7 @@ def lib():
             "`python -m paper_1405_0260_amd.build` (no CPU fallback exists)")
     L = ctypes.CDLL(LIB_PATH)
     P = c_vp
+    PP = ctypes.POINTER(c_vp)
     sig = {
         "paro_default_opts": (None, [ctypes.POINTER(Opts)]),
         "paro_query": (c_i32, [ctypes.POINTER(Box), ctypes.POINTER(Opts),
@@ -117,6 +118,14 @@ def lib():
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
         "paro_get_timing": (c_i32, [P, ctypes.POINTER(Timing)]),
+        "paro_batch_workspace_bytes": (ctypes.c_size_t, [c_i32]),
+        "paro_batch_init": (c_i32, [PP, c_i32, PP, PP, PP, P,
+                                    ctypes.c_size_t, P]),
+        "paro_batch_step": (c_i32, [PP, c_i32, PP, PP, P, ctypes.c_size_t,
+                                    P, ctypes.POINTER(Report)]),
+        "paro_batch_solve": (c_i32, [PP, c_i32, PP, PP, PP, P,
+                                     ctypes.c_size_t, P,
+                                     ctypes.POINTER(Report)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -315,3 +324,74 @@ def paro_get_timing(p: Problem) -> Timing:
     t = Timing()
     _check(lib().paro_get_timing(p.handle, ctypes.byref(t)))
     return t
+
+
+# ----------------------------------------------------------------- batches
+
+def _ptrs(items):
+    return (c_vp * len(items))(*items)
+
+
+class Batch:
+    """Launch-table memory for batched calls over up to `capacity`
+    problems (device bytes from paro_batch_workspace_bytes)."""
+
+    def __init__(self, capacity: int, device=None):
+        import torch
+        self.capacity = capacity
+        nbytes = lib().paro_batch_workspace_bytes(capacity)
+        if nbytes == 0:
+            raise ValueError("capacity must be >= 1")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                              device=device or "cuda")
+        base = self.ws.data_ptr()
+        self.off = (-base) % 256
+        self.ptr = base + self.off
+        self.bytes = self.ws.numel() - self.off
+
+    def _args(self, probs):
+        if len(probs) > self.capacity:
+            raise ValueError(f"{len(probs)} problems > capacity "
+                             f"{self.capacity}")
+        return _ptrs([p.handle.value if isinstance(p.handle, c_vp)
+                      else p.handle for p in probs])
+
+
+def _batch_checks(probs, U0s, lams, Us):
+    for k, p in enumerate(probs):
+        if U0s is not None:
+            _f64(U0s[k], (p.n, p.Nt), f"U0[{k}]")
+        _f64(Us[k], (p.n, p.Nt), f"U[{k}]")
+        _f64(lams[k], (p.Nt,), f"lambda[{k}]")
+
+
+def paro_batch_init(batch: Batch, probs, U0s, lams, Us, stream=None):
+    _batch_checks(probs, U0s, lams, Us)
+    _check(lib().paro_batch_init(
+        batch._args(probs), len(probs), _ptrs([_ptr(t) for t in U0s]),
+        _ptrs([_ptr(t) for t in lams]), _ptrs([_ptr(t) for t in Us]),
+        batch.ptr, batch.bytes, _stream(stream)))
+
+
+def paro_batch_step(batch: Batch, probs, lams, Us, stream=None, report=True):
+    """One ParO step of every problem; returns per-problem reports."""
+    _batch_checks(probs, None, lams, Us)
+    reps = (Report * len(probs))() if report else None
+    _check(lib().paro_batch_step(
+        batch._args(probs), len(probs), _ptrs([_ptr(t) for t in lams]),
+        _ptrs([_ptr(t) for t in Us]), batch.ptr, batch.bytes,
+        _stream(stream), reps))
+    return list(reps) if report else None
+
+
+def paro_batch_solve(batch: Batch, probs, U0s, lams, Us, stream=None):
+    """Whole solves of every problem; returns per-problem reports (a
+    problem that did not converge has status PARO_ENOCONV)."""
+    _batch_checks(probs, U0s, lams, Us)
+    reps = (Report * len(probs))()
+    _check(lib().paro_batch_solve(
+        batch._args(probs), len(probs), _ptrs([_ptr(t) for t in U0s]),
+        _ptrs([_ptr(t) for t in lams]), _ptrs([_ptr(t) for t in Us]),
+        batch.ptr, batch.bytes, _stream(stream), reps),
+        allow=(PARO_ENOCONV,))
+    return list(reps)

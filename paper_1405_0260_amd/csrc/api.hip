@@ -1,12 +1,14 @@
-// C ABI of libparo: argument checking, workspace layout and the host-side
-// sequencing of one ParO step (Algorithm A.1, Steps 3 and 4) and of a
-// whole solve.  Every arithmetic step runs in the kernels of assemble.hip
-// and solver.hip; the host only launches them and polls small flags.
+// C ABI of libparo: argument checking, workspace layout, launch tables and
+// the host-side sequencing of ParO steps (Algorithm A.1, Steps 3 and 4),
+// for one problem or a batch.  Every arithmetic step runs in the kernels of
+// assemble.hip and solver.hip; the host only launches them and polls small
+// flags.
+#include <algorithm>
 #include <chrono>
-#include <cstdarg>
 #include <cmath>
-#include <cstdio>
+#include <cstdarg>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -68,8 +70,7 @@ struct Timing {
   }
 };
 
-int timing_begin(Problem& p, int stage, hipStream_t s) {
-  Timing* t = p.timing;
+int timing_begin(Timing* t, int stage, hipStream_t s) {
   if (!t || !t->on) return -1;
   hipEvent_t a = t->get();
   if (!a || hipEventRecord(a, s) != hipSuccess) return -1;
@@ -77,8 +78,7 @@ int timing_begin(Problem& p, int stage, hipStream_t s) {
   return (int)t->open.size() - 1;
 }
 
-void timing_end(Problem& p, int slot, hipStream_t s) {
-  Timing* t = p.timing;
+void timing_end(Timing* t, int slot, hipStream_t s) {
   if (!t || slot < 0 || slot >= (int)t->open.size()) return;
   hipEvent_t b = t->get();
   if (b && hipEventRecord(b, s) == hipSuccess)
@@ -112,7 +112,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
+int round8(int64_t x) { return (int)(((x + 7) / 8) * 8); }
 
 double now_s() {
   using namespace std::chrono;
@@ -184,6 +184,9 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.si = (StepInfo*)at(L.si);
   p.cnt = (unsigned*)at(L.cnt);
   p.flag = (int*)at(L.flag);
+  p.dd = (Desc*)at(L.desc);
+  p.dpoll = (int*)at(L.poll);
+  p.dreport = (PollReport*)at(L.report);
 }
 
 int pick_grid(int64_t n, int Nt) {
@@ -195,15 +198,108 @@ int pick_grid(int64_t n, int Nt) {
   return (int)(g < 8 ? 8 : g);
 }
 
-// Host reads of small device values (flags, scalars, the step report).
-template <typename T>
-int read_back(paro_problem* h, const T* dsrc, T* out, size_t count,
-              hipStream_t s) {
-  (void)h;
-  HIP_OR_FAIL(hipMemcpyAsync(out, dsrc, sizeof(T) * count,
-                             hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipStreamSynchronize(s));
-  return PARO_OK;
+// The static part of a problem's descriptor (sizes, operator, workspace).
+void desc_init(Problem& p) {
+  Desc& d = p.hd;
+  std::memset(&d, 0, sizeof d);
+  d.n = p.n;
+  d.nnz = p.nnz;
+  d.ncols = p.Nt;
+  d.nreq = p.N;
+  d.b0 = 0;
+  d.nb = d.ns = p.grid;
+  d.g0 = 0;
+  d.gnb = d.gns = std::min(p.grid, kGramGrid);
+  d.v64 = vec64_of(p.Nt);
+  d.v32 = vec32_of(p.Nt);
+  d.maxit = p.opts.pcg_maxit;
+  d.sigma = p.sigma;
+  d.rtol = p.opts.pcg_rtol;
+  d.inner_rtol = p.opts.inner_rtol;
+  d.rowptr = p.rowptr;
+  d.col = p.col;
+  d.valA = p.valA;
+  d.valM = p.valM;
+  d.valA32 = p.valA32;
+  d.dinv = p.dinv;
+  d.dinv32 = p.dinv32;
+  d.X = d.Uout = p.X;
+  d.U0 = p.X;
+  d.R = p.R;
+  d.P = p.P;
+  d.Q = p.Q;
+  d.B = p.B;
+  d.R32 = p.R32;
+  d.P32 = p.P32;
+  d.Q32 = p.Q32;
+  d.X32 = p.X32;
+  d.part = p.part;
+  d.gpart = p.gpart;
+  d.gsum = p.gsum;
+  d.Ah = p.Ah;
+  d.Bh = p.Bh;
+  d.C = p.C;
+  d.theta = p.theta;
+  d.cs = p.cs;
+  d.si = p.si;
+  d.geneig_info = &p.si->geneig_info;
+}
+
+// Column count of a descriptor (component calls use fewer than N + m).
+void set_cols(Desc& d, int ncols) {
+  d.ncols = ncols;
+  d.v64 = vec64_of(ncols);
+  d.v32 = vec32_of(ncols);
+}
+
+// A launch over `n` descriptors already laid out (b0/nb, g0/gnb) in `tab`.
+Launch make_launch(Desc* dtab, const Desc* tab, int n) {
+  Launch L{};
+  L.d = dtab;
+  L.nprob = n;
+  L.maxcols = 0;
+  L.mincols = kNtMax;
+  L.vmax64 = 1;
+  for (int i = 0; i < n; ++i) {
+    const Desc& d = tab[i];
+    L.blocks = std::max(L.blocks, d.b0 + d.nb);
+    L.gblocks = std::max(L.gblocks, d.g0 + d.gnb);
+    L.maxcols = std::max(L.maxcols, d.ncols);
+    L.mincols = std::min(L.mincols, d.ncols);
+    L.tr64 = std::max(L.tr64, tile_rows(d.ncols, d.v64));
+    L.tr32 = std::max(L.tr32, tile_rows(d.ncols, d.v32));
+    L.vmax64 = std::max(L.vmax64, d.v64);
+  }
+  L.nt16 = (L.maxcols + 15) / 16;
+  L.v64u = n > 0 ? tab[0].v64 : 0;
+  L.v32u = n > 0 ? tab[0].v32 : 0;
+  for (int i = 1; i < n; ++i) {
+    if (tab[i].v64 != L.v64u) L.v64u = 0;
+    if (tab[i].v32 != L.v32u) L.v32u = 0;
+    if ((tab[i].ncols + 15) / 16 != L.nt16) L.nt16_mixed = 1;
+  }
+  if (n > 0 && (tab[0].ncols + 15) / 16 != L.nt16) L.nt16_mixed = 1;
+  return L;
+}
+
+// Shares of the grids for a batch, proportional to each problem's work
+// (n * ncols), each a multiple of 8, at least 8 blocks and at most the
+// problem's own segment counts (ns, gns).
+void layout_batch(std::vector<Desc>& tab) {
+  double total = 0.0;
+  for (const Desc& d : tab) total += (double)d.n * d.ncols;
+  int b = 0, g = 0;
+  for (Desc& d : tab) {
+    const double w = (double)d.n * d.ncols / total;
+    const int nb = std::max(8, std::min(d.ns, round8((int64_t)(w * kGridDefault))));
+    const int gnb = std::max(8, std::min(d.gns, round8((int64_t)(w * kGramGrid))));
+    d.b0 = b;
+    d.nb = nb;
+    d.g0 = g;
+    d.gnb = gnb;
+    b += nb;
+    g += gnb;
+  }
 }
 
 int status_to_code(int st) {
@@ -219,41 +315,46 @@ int status_to_code(int st) {
   return PARO_OK;
 }
 
-// The tail of ColState read back at each poll (one copy).
-struct ColTail {
-  int iters[kNtMax];
-  int n_active[2];
-  int n_outer;
-  int status;
+// Host side of one launch table: where its table, poll words and reports
+// live on the device, and the host copies.
+struct Ctx {
+  Launch L;
+  std::vector<Desc> tab;
+  int* dpoll;
+  PollReport* dreport;
+  Timing* timing;
+  int* predict;           // 5 prediction slots (problem or batch)
   int maxit;
-  int pad[3];
-  unsigned long long cg_iters;
-  unsigned long long cg_col_iters;
+  int precision;
 };
-static_assert(offsetof(ColState, cg_col_iters) - offsetof(ColState, iters) ==
-                  offsetof(ColTail, cg_col_iters),
-              "ColTail must mirror the tail of ColState");
 
-int read_tail(paro_problem* h, ColTail* t, hipStream_t s) {
-  HIP_OR_FAIL(hipMemcpyAsync(t, &h->p.cs->iters[0], sizeof(ColTail),
-                             hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipStreamSynchronize(s));
+int upload(Ctx& c, hipStream_t s) {
+  HIP_OR_FAIL(hipMemcpyAsync(c.L.d, c.tab.data(), sizeof(Desc) * c.tab.size(),
+                             hipMemcpyHostToDevice, s));
+  c.L = make_launch(c.L.d, c.tab.data(), (int)c.tab.size());
   return PARO_OK;
 }
 
-// Run CG iterations (FP64 or FP32) until no column is active.  The first
-// batch of launches is as long as the previous solve in the same slot took,
-// so that a converging solve usually needs one poll; later batches are
-// short top-ups.
-int run_cg(paro_problem* h, int ncols, bool fp32, hipStream_t s, int slot) {
-  Problem& p = h->p;
-  ColTail t;
-  int rc = read_tail(h, &t, s);
+int poll(Ctx& c, int which, int out[2], hipStream_t s) {
+  HIP_OR_FAIL(launch_count_active(c.L, which, c.dpoll, s));
+  HIP_OR_FAIL(hipMemcpyAsync(out, c.dpoll, 2 * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  if (c.timing) c.timing->resolve();
+  return PARO_OK;
+}
+
+// Run CG iterations (FP64 or FP32) until no column of any problem is
+// active.  The first batch of launches is as long as the previous solve in
+// the same slot took, so that a converging solve usually needs one poll;
+// later batches are short top-ups.
+int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
+  int pw[2];
+  int rc = poll(c, 0, pw, s);
   if (rc) return rc;
-  if (t.n_active[0] == 0) return PARO_OK;
-  const unsigned long long start = t.cg_iters;
-  const int64_t cap = (int64_t)p.opts.pcg_maxit + 64;
-  int pred = p.cg_predict[slot];
+  if (pw[0] == 0) return PARO_OK;
+  const int64_t cap = (int64_t)c.maxit + 64;
+  const int pred = c.predict[slot];
   int chunk = pred < 2 ? 2 : (pred > 256 ? 256 : pred);
   int par = 0;
   int64_t launched = 0;
@@ -261,47 +362,161 @@ int run_cg(paro_problem* h, int ncols, bool fp32, hipStream_t s, int slot) {
     if (launched >= cap)
       return fail(PARO_EDEVICE, "CG loop did not terminate on the device");
     for (int k = 0; k < chunk; ++k) {
-      hipError_t e = fp32 ? launch_pcg32_iter(p, ncols, par, s)
-                          : launch_pcg_iter(p, ncols, par, s);
+      hipError_t e = launch_pcg_iter(c.L, fp32, par, s, c.timing);
       if (e != hipSuccess)
         return fail(PARO_EDEVICE, "CG launch: %s", hipGetErrorString(e));
       par ^= 1;
     }
     launched += chunk;
-    rc = read_tail(h, &t, s);
+    rc = poll(c, par, pw, s);
     if (rc) return rc;
-    if (p.timing) p.timing->resolve();
-    if (t.n_active[par] == 0) break;
+    if (pw[0] == 0) break;
     chunk = (pred + 3) / 4;
     chunk = chunk < 2 ? 2 : (chunk > 16 ? 16 : chunk);
   }
-  p.cg_predict[slot] = (int)(t.cg_iters - start);
+  c.predict[slot] = pw[1];
   return PARO_OK;
 }
 
-// Source solves of one step, from the state prepared by a start kernel
-// (X = x0, R, P, B, act[0]).  Returns the device status as a code.
-int solve_sources(paro_problem* h, int ncols, hipStream_t s,
-                  int64_t* refinements) {
-  Problem& p = h->p;
-  if (p.opts.precision == PARO_FP64) {
-    int rc = run_cg(h, ncols, false, s, 0);
+// Source solves of one step, from the state prepared by the start kernel.
+int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
+  if (c.precision == PARO_FP64) return run_cg(c, false, s, 0);
+  for (int pass = 0;; ++pass) {
+    HIP_OR_FAIL(launch_refine_residual(c.L, s, c.timing));
+    int pw[2];
+    int rc = poll(c, 2, pw, s);
     if (rc) return rc;
-  } else {
-    for (int pass = 0;; ++pass) {
-      HIP_OR_FAIL(launch_refine_residual(p, ncols, pass == 0, s));
-      int no = 0;
-      int rc = read_back(h, &p.cs->n_outer, &no, 1, s);
-      if (rc) return rc;
-      if (no == 0) break;
-      if (pass > 200)
-        return fail(PARO_EDEVICE, "refinement loop did not terminate");
-      rc = run_cg(h, ncols, true, s, 1 + (pass < 3 ? pass : 3));
-      if (rc) return rc;
-      HIP_OR_FAIL(launch_refine_update(p, ncols, s));
-      if (refinements) ++*refinements;
-    }
+    if (pw[0] == 0) break;
+    if (pass > 200)
+      return fail(PARO_EDEVICE, "refinement loop did not terminate");
+    rc = run_cg(c, true, s, 1 + (pass < 3 ? pass : 3));
+    if (rc) return rc;
+    HIP_OR_FAIL(launch_refine_update(c.L, s, c.timing));
+    if (refinements) ++*refinements;
   }
+  return PARO_OK;
+}
+
+int read_reports(Ctx& c, std::vector<PollReport>& out, hipStream_t s) {
+  out.resize(c.tab.size());
+  HIP_OR_FAIL(launch_gather_reports(c.L, c.dreport, s));
+  HIP_OR_FAIL(hipMemcpyAsync(out.data(), c.dreport,
+                             sizeof(PollReport) * out.size(),
+                             hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  return PARO_OK;
+}
+
+// One ParO step (Steps 3 and 4) for every problem of the table; the
+// descriptors' U0 = X = Uout (the orbitals, in place) and lam are set.
+// Per-problem status goes into `reps` (if given).  `single`: a CG
+// breakdown stops before the projection and is returned.
+int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single) {
+  const double t0 = now_s();
+  int rc = upload(c, s);
+  if (rc) return rc;
+  HIP_OR_FAIL(launch_pcg_start(c.L, s, c.timing));
+  int64_t refinements = 0;
+  rc = solve_sources(c, s, &refinements);
+  if (rc) return rc;
+  std::vector<PollReport> pr;
+  if (single) {
+    rc = read_reports(c, pr, s);
+    if (rc) return rc;
+    if (pr[0].status & (kStNonFinite | kStNotSpd))
+      return status_to_code(pr[0].status);
+  }
+  HIP_OR_FAIL(launch_rayleigh_ritz(c.L, s, c.timing));
+  if (!reps) return PARO_OK;
+  rc = read_reports(c, pr, s);
+  if (rc) return rc;
+  const double dt = now_s() - t0;
+  int first = PARO_OK;
+  for (size_t i = 0; i < c.tab.size(); ++i) {
+    paro_report_t& r = reps[i];
+    r.steps = 1;
+    r.pcg_iters = pr[i].max_iters;
+    r.refinements = refinements;
+    r.n_dof = c.tab[i].n;
+    r.nnz = c.tab[i].nnz;
+    r.max_dlambda = pr[i].max_dlambda;
+    r.max_resid = pr[i].max_resid;
+    r.sigma = c.tab[i].sigma;
+    r.seconds = dt;
+    r.status = status_to_code(pr[i].status);
+    if (first == PARO_OK) first = r.status;
+  }
+  return single ? first : PARO_OK;
+}
+
+// Step 1 (Rayleigh-Ritz of the start block) for every problem.
+int init_tables(Ctx& c, hipStream_t s) {
+  int rc = upload(c, s);
+  if (rc) return rc;
+  HIP_OR_FAIL(launch_rayleigh_ritz(c.L, s, c.timing));
+  return PARO_OK;
+}
+
+Ctx single_ctx(Problem& p) {
+  Ctx c;
+  c.tab.assign(1, p.hd);
+  c.L = make_launch(p.dd, c.tab.data(), 1);
+  c.dpoll = p.dpoll;
+  c.dreport = p.dreport;
+  c.timing = p.timing;
+  c.predict = p.cg_predict;
+  c.maxit = p.opts.pcg_maxit;
+  c.precision = p.opts.precision;
+  return c;
+}
+
+// Batch workspace: the table, poll words and reports.
+struct BatchLayout {
+  size_t tab, poll, report, total;
+};
+BatchLayout batch_layout(int count) {
+  BatchLayout b;
+  size_t o = 0;
+  b.tab = o;
+  o += align256(sizeof(Desc) * (size_t)count);
+  b.poll = o;
+  o += align256(sizeof(int) * 16);
+  b.report = o;
+  o += align256(sizeof(PollReport) * (size_t)count);
+  b.total = o;
+  return b;
+}
+
+int batch_ctx(Ctx& c, paro_problem* const* probs, int count, void* ws,
+              size_t bytes, int* predict) {
+  if (!probs || count < 1 || count > PARO_BATCH_MAX)
+    return fail(PARO_EINVAL, "batch needs 1..%d problems", PARO_BATCH_MAX);
+  if (!ws || ((uintptr_t)ws & 255))
+    return fail(PARO_EINVAL, "batch workspace must be 256-byte aligned");
+  const BatchLayout bl = batch_layout(count);
+  if (bytes < bl.total)
+    return fail(PARO_ENOMEM, "batch workspace %zu < %zu bytes", bytes,
+                bl.total);
+  c.tab.clear();
+  int prec = -1, maxit = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!probs[i]) return fail(PARO_EINVAL, "NULL problem %d", i);
+    const Problem& p = probs[i]->p;
+    if (prec >= 0 && p.opts.precision != prec)
+      return fail(PARO_EINVAL, "batch mixes precisions");
+    prec = p.opts.precision;
+    maxit = std::max(maxit, p.opts.pcg_maxit);
+    c.tab.push_back(p.hd);
+  }
+  layout_batch(c.tab);
+  char* base = (char*)ws;
+  c.L = make_launch((Desc*)(base + bl.tab), c.tab.data(), count);
+  c.dpoll = (int*)(base + bl.poll);
+  c.dreport = (PollReport*)(base + bl.report);
+  c.timing = nullptr;
+  c.predict = predict;
+  c.maxit = maxit;
+  c.precision = prec;
   return PARO_OK;
 }
 
@@ -345,6 +560,9 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.si = take(sizeof(StepInfo));
   L.cnt = take(sizeof(unsigned) * kCntNum);
   L.flag = take(sizeof(int) * 16);
+  L.desc = take(sizeof(Desc));
+  L.poll = take(sizeof(int) * 16);
+  L.report = take(sizeof(PollReport));
   L.total = off;
   return L;
 }
@@ -438,6 +656,7 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
     p.h[2] = (box->hi[2] - box->lo[2]) / box->nz;
     p.grid = pick_grid(n, p.Nt);
     p.ws_bytes = bytes;
+    p.last_stream = s;
     const Layout L = make_layout(n, z, p.Nt, opts->precision);
     carve(p, (char*)d_ws, L);
     auto bail = [&](int code) {
@@ -445,16 +664,21 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
       return code;
     };
     // Zero the small state (counters, column state, step info).
-    hipError_t he = hipMemsetAsync((char*)d_ws + L.vmin, 0, L.total - L.vmin, s);
+    hipError_t he =
+        hipMemsetAsync((char*)d_ws + L.vmin, 0, L.total - L.vmin, s);
     if (he != hipSuccess)
-      return bail(fail(PARO_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(he)));
+      return bail(fail(PARO_EDEVICE, "hipMemsetAsync: %s",
+                       hipGetErrorString(he)));
     const int64_t nv = (int64_t)(box->nx + 1) * (box->ny + 1) * (box->nz + 1);
     if (launch_potential_range(d_V, nv, p.vmin, p.cnt + kCntMin, p.part, s) !=
         hipSuccess)
       return bail(fail(PARO_EDEVICE, "potential range launch failed"));
     double rng[3];
-    rc = read_back(h, p.vmin, rng, 3, s);
-    if (rc) return bail(rc);
+    he = hipMemcpyAsync(rng, p.vmin, sizeof rng, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess)
+      return bail(fail(PARO_EDEVICE, "reading the potential range: %s",
+                       hipGetErrorString(he)));
     if (rng[2] != 0.0)
       return bail(fail(PARO_EINVAL, "potential has %.0f non-finite values",
                        rng[2]));
@@ -464,6 +688,7 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
       p.sigma = rng[0] >= 0.0 ? 0.0 : rng[0] - 1.0;
     if (launch_assemble(p, d_V, s) != hipSuccess)
       return bail(fail(PARO_EDEVICE, "assembly launch failed"));
+    desc_init(p);
     *out = h;
     return PARO_OK;
   } catch (...) {
@@ -479,8 +704,13 @@ int paro_init(paro_problem* h, const double* d_U0, double* d_lambda,
   hipStream_t s = (hipStream_t)stream;
   p.last_stream = s;
   HIP_OR_FAIL(hipMemsetAsync(&p.cs->status, 0, sizeof(int), s));
-  HIP_OR_FAIL(launch_rayleigh_ritz(p, d_U0, d_lambda, d_U, p.Nt, false, s));
-  return PARO_OK;
+  Ctx c = single_ctx(p);
+  Desc& d = c.tab[0];
+  d.X = const_cast<double*>(d_U0);
+  d.Uout = d_U;
+  d.lam = d_lambda;
+  d.have_old = 0;
+  return init_tables(c, s);
 }
 
 int paro_step(paro_problem* h, double* d_lambda, double* d_U, void* stream,
@@ -491,50 +721,14 @@ int paro_step(paro_problem* h, double* d_lambda, double* d_U, void* stream,
     Problem& p = h->p;
     hipStream_t s = (hipStream_t)stream;
     p.last_stream = s;
-    const double t0 = now_s();
-    const bool f32 = p.opts.precision == PARO_FP32_INNER;
+    Ctx c = single_ctx(p);
     // The source solves run in place on d_U (x0 = u); Rayleigh-Ritz then
     // reads W from d_U and rotates it in place.
-    struct XGuard {
-      Problem& p;
-      double* saved;
-      ~XGuard() { p.X = saved; }
-    } guard{p, p.X};
-    p.X = d_U;
-    HIP_OR_FAIL(launch_pcg_start(p, d_lambda, d_U, p.Nt, f32, s));
-    int64_t refinements = 0;
-    int rc = solve_sources(h, p.Nt, s, &refinements);
-    if (rc) return rc;
-    int st = 0;
-    rc = read_back(h, &p.cs->status, &st, 1, s);
-    if (rc) return rc;
-    if (st & (kStNonFinite | kStNotSpd)) return status_to_code(st);
-    HIP_OR_FAIL(launch_rayleigh_ritz(p, p.X, d_lambda, d_U, p.Nt, true, s));
-    if (report) {
-      rc = read_back(h, &p.cs->status, &st, 1, s);
-      if (rc) return rc;
-      StepInfo si;
-      rc = read_back(h, p.si, &si, 1, s);
-      if (rc) return rc;
-      int iters[kNtMax];
-      rc = read_back(h, p.cs->iters, iters, p.Nt, s);
-      if (rc) return rc;
-      int64_t mx = 0;
-      for (int c = 0; c < p.Nt; ++c) mx = iters[c] > mx ? iters[c] : mx;
-      report->status = 0;
-      report->steps = 1;
-      report->pcg_iters = mx;
-      report->refinements = refinements;
-      report->n_dof = p.n;
-      report->nnz = p.nnz;
-      report->max_dlambda = si.max_dlambda;
-      report->max_resid = si.max_resid;
-      report->sigma = p.sigma;
-      report->seconds = now_s() - t0;
-      report->status = status_to_code(st);
-      return report->status;
-    }
-    return PARO_OK;
+    Desc& d = c.tab[0];
+    d.U0 = d.X = d.Uout = d_U;
+    d.lam = d_lambda;
+    d.have_old = 1;
+    return step_tables(c, s, report, true);
   } catch (...) {
     return fail(PARO_EDEVICE, "unexpected exception in paro_step");
   }
@@ -549,8 +743,9 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
   int rc = paro_init(h, d_U0, d_lambda, d_U, s);
   if (rc) return rc;
   int st = 0;
-  rc = read_back(h, &p.cs->status, &st, 1, s);
-  if (rc) return rc;
+  HIP_OR_FAIL(hipMemcpyAsync(&st, &p.cs->status, sizeof st,
+                             hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
   if (st) return status_to_code(st);
   paro_report_t acc{};
   acc.n_dof = p.n;
@@ -583,8 +778,6 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
   acc.seconds = now_s() - t0;
   acc.status = code;
   if (report) *report = acc;
-  if (code == PARO_ENOCONV && g_err.empty())
-    fail(PARO_ENOCONV, "max_steps reached");
   if (code == PARO_ENOCONV)
     fail(PARO_ENOCONV, "max_steps = %d reached before the tolerances",
          p.opts.max_steps);
@@ -595,6 +788,148 @@ void paro_destroy(paro_problem* h) {
   if (!h) return;
   delete h->p.timing;
   delete h;
+}
+
+size_t paro_batch_workspace_bytes(int32_t count) {
+  if (count < 1) return 0;
+  return batch_layout(count).total;
+}
+
+int paro_batch_init(paro_problem* const* probs, int32_t count,
+                    const double* const* d_U0, double* const* d_lambda,
+                    double* const* d_U, void* d_ws, size_t bytes,
+                    void* stream) {
+  try {
+    if (!d_U0 || !d_lambda || !d_U) return fail(PARO_EINVAL, "NULL arrays");
+    Ctx c;
+    int predict[5] = {0, 0, 0, 0, 0};
+    int rc = batch_ctx(c, probs, count, d_ws, bytes, predict);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) {
+      if (!d_U0[i] || !d_lambda[i] || !d_U[i])
+        return fail(PARO_EINVAL, "NULL device pointer for problem %d", i);
+      probs[i]->p.last_stream = s;
+      HIP_OR_FAIL(hipMemsetAsync(&probs[i]->p.cs->status, 0, sizeof(int), s));
+      Desc& d = c.tab[i];
+      d.X = const_cast<double*>(d_U0[i]);
+      d.Uout = d_U[i];
+      d.lam = d_lambda[i];
+      d.have_old = 0;
+    }
+    return init_tables(c, s);
+  } catch (...) {
+    return fail(PARO_EDEVICE, "unexpected exception in paro_batch_init");
+  }
+}
+
+// Batch steps keep their CG prediction between calls of one thread.
+static thread_local int g_batch_predict[5] = {0, 0, 0, 0, 0};
+
+int paro_batch_step(paro_problem* const* probs, int32_t count,
+                    double* const* d_lambda, double* const* d_U, void* d_ws,
+                    size_t bytes, void* stream, paro_report_t* reports) {
+  try {
+    if (!d_lambda || !d_U) return fail(PARO_EINVAL, "NULL arrays");
+    Ctx c;
+    int rc = batch_ctx(c, probs, count, d_ws, bytes, g_batch_predict);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) {
+      if (!d_lambda[i] || !d_U[i])
+        return fail(PARO_EINVAL, "NULL device pointer for problem %d", i);
+      probs[i]->p.last_stream = s;
+      Desc& d = c.tab[i];
+      d.U0 = d.X = d.Uout = d_U[i];
+      d.lam = d_lambda[i];
+      d.have_old = 1;
+    }
+    return step_tables(c, s, reports, false);
+  } catch (...) {
+    return fail(PARO_EDEVICE, "unexpected exception in paro_batch_step");
+  }
+}
+
+int paro_batch_solve(paro_problem* const* probs, int32_t count,
+                     const double* const* d_U0, double* const* d_lambda,
+                     double* const* d_U, void* d_ws, size_t bytes,
+                     void* stream, paro_report_t* reports) {
+  if (!reports) return fail(PARO_EINVAL, "reports are required");
+  const double t0 = now_s();
+  int rc = paro_batch_init(probs, count, d_U0, d_lambda, d_U, d_ws, bytes,
+                           stream);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int> active;
+  for (int i = 0; i < count; ++i) {
+    reports[i] = paro_report_t{};
+    reports[i].n_dof = probs[i]->p.n;
+    reports[i].nnz = probs[i]->p.nnz;
+    reports[i].sigma = probs[i]->p.sigma;
+    reports[i].status = PARO_ENOCONV;
+    // Start-block failures (dependent start columns).
+    int st = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(&st, &probs[i]->p.cs->status, sizeof st,
+                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (st)
+      reports[i].status = status_to_code(st);
+    else
+      active.push_back(i);
+  }
+  std::vector<paro_problem*> ps;
+  std::vector<double*> ls, us;
+  std::vector<paro_report_t> rs;
+  while (!active.empty()) {
+    ps.clear();
+    ls.clear();
+    us.clear();
+    for (int i : active) {
+      ps.push_back(probs[i]);
+      ls.push_back(d_lambda[i]);
+      us.push_back(d_U[i]);
+    }
+    rs.assign(active.size(), paro_report_t{});
+    rc = paro_batch_step(ps.data(), (int)ps.size(), ls.data(), us.data(),
+                         d_ws, bytes, stream, rs.data());
+    if (rc) return rc;
+    std::vector<int> still;
+    for (size_t k = 0; k < active.size(); ++k) {
+      const int i = active[k];
+      paro_report_t& a = reports[i];
+      const paro_report_t& r = rs[k];
+      const paro_opts_t& o = probs[i]->p.opts;
+      a.steps += 1;
+      a.pcg_iters += r.pcg_iters;
+      a.refinements += r.refinements;
+      a.max_dlambda = r.max_dlambda;
+      a.max_resid = r.max_resid;
+      bool done = false;
+      if (r.status != PARO_OK && r.status != PARO_ENOCONV) {
+        a.status = r.status;
+        done = true;
+      } else if (o.lambda_tol > 0.0 && r.max_dlambda <= o.lambda_tol &&
+                 r.max_resid <= o.resid_tol) {
+        a.status = PARO_OK;
+        done = true;
+      } else if (a.steps >= o.max_steps) {
+        a.status = PARO_ENOCONV;
+        done = true;
+      }
+      a.seconds = now_s() - t0;
+      if (!done) still.push_back(i);
+    }
+    active.swap(still);
+  }
+  int first = PARO_OK;
+  for (int i = 0; i < count; ++i)
+    if (reports[i].status != PARO_OK) {
+      first = reports[i].status;
+      break;
+    }
+  if (first != PARO_OK)
+    fail(first, "problem(s) of the batch ended with status %d", first);
+  return first;
 }
 
 int paro_set_timing(paro_problem* h, int on) {
@@ -609,8 +944,9 @@ int paro_set_timing(paro_problem* h, int on) {
     t.ms[k] = 0.0;
   }
   unsigned long long c[2] = {0, 0};
-  int rc = read_back(h, &p.cs->cg_iters, c, 2, p.last_stream);
-  if (rc) return rc;
+  HIP_OR_FAIL(hipMemcpyAsync(c, &p.cs->cg_iters, sizeof c,
+                             hipMemcpyDeviceToHost, p.last_stream));
+  HIP_OR_FAIL(hipStreamSynchronize(p.last_stream));
   t.iters0 = c[0];
   t.cols0 = c[1];
   t.on = on != 0;
@@ -623,8 +959,9 @@ int paro_get_timing(paro_problem* h, paro_timing_t* out) {
   std::memset(out, 0, sizeof *out);
   HIP_OR_FAIL(hipStreamSynchronize(p.last_stream));
   unsigned long long c[2] = {0, 0};
-  int rc = read_back(h, &p.cs->cg_iters, c, 2, p.last_stream);
-  if (rc) return rc;
+  HIP_OR_FAIL(hipMemcpyAsync(c, &p.cs->cg_iters, sizeof c,
+                             hipMemcpyDeviceToHost, p.last_stream));
+  HIP_OR_FAIL(hipStreamSynchronize(p.last_stream));
   if (p.timing) {
     p.timing->resolve();
     for (int k = 0; k < PARO_ST_NUM; ++k) {
@@ -634,8 +971,8 @@ int paro_get_timing(paro_problem* h, paro_timing_t* out) {
     c[0] -= p.timing->iters0;
     c[1] -= p.timing->cols0;
   }
-  out->cg_iters = c[0];
-  out->cg_col_iters = c[1];
+  out->cg_iters = (int64_t)c[0];
+  out->cg_col_iters = (int64_t)c[1];
   return PARO_OK;
 }
 
@@ -667,7 +1004,18 @@ int paro_spmm(paro_problem* h, int which, const double* d_X, double* d_Y,
   if (which < 0 || which > 2) return fail(PARO_EINVAL, "which must be 0..2");
   if (ncols < 1 || ncols > kNtMax)
     return fail(PARO_EINVAL, "ncols must be 1..%d", kNtMax);
-  HIP_OR_FAIL(launch_spmm(h->p, which, d_X, d_Y, ncols, (hipStream_t)stream));
+  Problem& p = h->p;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c = single_ctx(p);
+  Desc& d = c.tab[0];
+  set_cols(d, ncols);
+  d.X = const_cast<double*>(d_X);
+  d.Y1 = which == 1 ? nullptr : d_Y;
+  d.Y2 = which == 1 ? d_Y : nullptr;
+  d.s1 = which == 2 ? p.sigma : 0.0;
+  int rc = upload(c, s);
+  if (rc) return rc;
+  HIP_OR_FAIL(launch_spmm(c.L, false, s, c.timing));
   return PARO_OK;
 }
 
@@ -676,8 +1024,17 @@ int paro_gram(paro_problem* h, const double* d_W, const double* d_Y,
   if (!h || !d_W || !d_Y || !d_G) return fail(PARO_EINVAL, "NULL argument");
   if (ncols < 1 || ncols > h->p.Nt)
     return fail(PARO_EINVAL, "ncols must be 1..%d", h->p.Nt);
-  HIP_OR_FAIL(
-      launch_gram_full(h->p, d_W, d_Y, d_G, ncols, (hipStream_t)stream));
+  Problem& p = h->p;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c = single_ctx(p);
+  Desc& d = c.tab[0];
+  set_cols(d, ncols);
+  d.X = const_cast<double*>(d_W);
+  d.Y1 = const_cast<double*>(d_Y);
+  d.Y2 = d_G;
+  int rc = upload(c, s);
+  if (rc) return rc;
+  HIP_OR_FAIL(launch_gram_full(c.L, s, c.timing));
   return PARO_OK;
 }
 
@@ -703,20 +1060,27 @@ int paro_pcg(paro_problem* h, const double* d_B, double* d_X, int ncols,
     p.last_stream = s;
     const size_t bytes = sizeof(double) * (size_t)p.n * ncols;
     HIP_OR_FAIL(hipMemcpyAsync(p.X, d_X, bytes, hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(launch_pcg_start_rhs(p, d_B, ncols,
-                                     p.opts.precision == PARO_FP32_INNER, s));
-    int rc = solve_sources(h, ncols, s, nullptr);
+    Ctx c = single_ctx(p);
+    Desc& d = c.tab[0];
+    set_cols(d, ncols);
+    d.U0 = d.X = p.X;
+    d.Bin = d_B;
+    d.lam = nullptr;
+    int rc = upload(c, s);
+    if (rc) return rc;
+    HIP_OR_FAIL(launch_pcg_start(c.L, s, c.timing));
+    rc = solve_sources(c, s, nullptr);
     if (rc) return rc;
     HIP_OR_FAIL(hipMemcpyAsync(d_X, p.X, bytes, hipMemcpyDeviceToDevice, s));
     int st = 0;
-    rc = read_back(h, &p.cs->status, &st, 1, s);
-    if (rc) return rc;
-    if (h_iters) {
-      int iters[kNtMax];
-      rc = read_back(h, p.cs->iters, iters, ncols, s);
-      if (rc) return rc;
-      for (int c = 0; c < ncols; ++c) h_iters[c] = iters[c];
-    }
+    int iters[kNtMax];
+    HIP_OR_FAIL(hipMemcpyAsync(&st, &p.cs->status, sizeof st,
+                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipMemcpyAsync(iters, p.cs->iters, sizeof(int) * ncols,
+                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (h_iters)
+      for (int k = 0; k < ncols; ++k) h_iters[k] = iters[k];
     return status_to_code(st);
   } catch (...) {
     return fail(PARO_EDEVICE, "unexpected exception in paro_pcg");

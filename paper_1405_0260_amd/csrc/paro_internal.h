@@ -51,6 +51,7 @@ struct ColState {
   int pad[3];
   unsigned long long cg_iters;      // CG iterations that did work
   unsigned long long cg_col_iters;  // their active columns, summed
+  unsigned long long cg_mark;       // cg_iters when the current solve began
 };
 
 // Step results (device), read back when a report is requested.
@@ -68,6 +69,99 @@ struct StepInfo {
 // block of each reduction.
 enum { kCntSpmm = 0, kCntRupd, kCntStart, kCntGram, kCntRot, kCntRefine,
        kCntMin, kCntSpmmTest, kCntNum };
+
+// One problem of a launch.  Every solver kernel takes a table of these
+// (device memory) and serves the problem that owns its block: problem p
+// owns blocks [b0, b0 + nb) of the streaming kernels and [g0, g0 + gnb) of
+// the Gram's first stage (b0, nb, g0, gnb multiples of 8, so that a
+// problem's blocks keep the XCD round-robin of the whole grid).
+//
+// Reductions are split into segments fixed by the problem alone: ns
+// "virtual blocks" for the streaming kernels (ns = the problem's own grid)
+// and gns for the Gram.  Real block lb of nb serves virtual blocks lb,
+// lb + nb, ... (nb <= ns), so the summation order, and every result, is
+// the same whatever share of the grid the problem gets in a batch.  The
+// vector widths v64 / v32 (columns per thread, FP64 / FP32) are likewise
+// the problem's own.
+struct Desc {
+  long long n, nnz;
+  int ncols;              // N + m
+  int nreq;               // N
+  int b0, nb;
+  int g0, gnb;
+  int maxit;
+  int have_old;           // Rayleigh-Ritz after a step (1) or at the start
+  int ns, gns;            // reduction segments (virtual blocks)
+  int v64, v32;           // columns per thread
+  double sigma, rtol, inner_rtol;
+  double s1;              // component SpMM: Y1 = A X + s1 M X
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* valA;     // A_s
+  const double* valM;
+  const float* valA32;
+  const double* dinv;
+  const float* dinv32;
+  const double* U0;       // start of the source solves (x0), gathered
+  const double* Bin;      // given right-hand sides, or null
+  double* lam;            // Ritz values (in: previous, out: new), or null
+  double* X;              // source solutions = Rayleigh-Ritz basis W
+  double* Uout;           // rotated orbitals
+  double* R;
+  double* P;
+  double* Q;
+  double* B;              // stored right-hand sides (refinement), or null
+  float* R32;
+  float* P32;
+  float* Q32;
+  float* X32;
+  double* Y1;             // component SpMM / Gram operands
+  double* Y2;
+  double* part;
+  double* gpart;
+  double* gsum;
+  double* Ah;
+  double* Bh;
+  double* C;
+  double* theta;
+  ColState* cs;
+  StepInfo* si;
+  int* geneig_info;
+};
+
+// Columns per thread of a problem with `ncols` columns: the widest vector
+// that divides ncols (FP64: 2 or 1; FP32: 4, 2 or 1).
+constexpr int vec64_of(int ncols) { return ncols % 2 == 0 ? 2 : 1; }
+constexpr int vec32_of(int ncols) {
+  return ncols % 4 == 0 ? 4 : (ncols % 2 == 0 ? 2 : 1);
+}
+// Rows per streaming tile.
+constexpr int tile_rows(int ncols, int V) { return kBlock / (ncols / V); }
+
+// Shape of one batched launch.
+struct Launch {
+  Desc* d;                // device table
+  int nprob;
+  int blocks;             // streaming grid (sum of nb)
+  int gblocks;            // Gram first-stage grid (sum of gnb)
+  int maxcols;            // largest ncols
+  int mincols;            // smallest ncols (largest tile)
+  int nt16;               // ceil(maxcols / 16)
+  int tr64, tr32;         // largest tile rows (FP64 / FP32 widths)
+  int vmax64;             // widest FP64 vector of the table
+  int v64u, v32u;         // common vector width of all problems, or 0
+  int nt16_mixed;         // problems differ in ceil(ncols / 16)
+};
+
+// Per-problem step summary for the host (one PollReport per problem).
+struct PollReport {
+  int status;
+  int max_iters;
+  int geneig_info;
+  int pad;
+  double max_dlambda;
+  double max_resid;
+};
 
 struct Timing;  // host-side event timing state (api.hip)
 
@@ -113,18 +207,22 @@ struct Problem {
   Timing* timing;         // null unless paro_set_timing(p, 1)
   hipStream_t last_stream;
   int cg_predict[5];      // CG iterations of the last solve per pass slot
+  Desc hd;                // host copy of the problem's descriptor
+  Desc* dd;               // its device slot (workspace)
+  int* dpoll;             // device poll words (workspace)
+  PollReport* dreport;    // device report slot (workspace)
 };
 
 // Event bracketing of one launch (no-ops unless timing is on).
-int timing_begin(Problem& p, int stage, hipStream_t s);
-void timing_end(Problem& p, int slot, hipStream_t s);
+int timing_begin(Timing* t, int stage, hipStream_t s);
+void timing_end(Timing* t, int slot, hipStream_t s);
 struct TimedLaunch {
-  Problem& p;
+  Timing* t;
   int slot;
   hipStream_t s;
-  TimedLaunch(Problem& pp, int stage, hipStream_t ss)
-      : p(pp), slot(timing_begin(pp, stage, ss)), s(ss) {}
-  ~TimedLaunch() { timing_end(p, slot, s); }
+  TimedLaunch(Timing* tt, int stage, hipStream_t ss)
+      : t(tt), slot(timing_begin(tt, stage, ss)), s(ss) {}
+  ~TimedLaunch() { timing_end(t, slot, s); }
 };
 
 // Workspace layout: byte offsets of every region for a problem shape.
@@ -132,6 +230,7 @@ struct Layout {
   size_t rowptr, col, valA, valM, valA32, dinv, dinv32;
   size_t X, R, P, Q, B, R32, P32, Q32, X32;
   size_t part, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt, flag;
+  size_t desc, poll, report;
   size_t total;
 };
 
@@ -144,34 +243,30 @@ hipError_t launch_potential_range(const double* V, int64_t nv, double* out,
 hipError_t launch_assemble(Problem& p, const double* V, hipStream_t s);
 
 // ---- launchers (solver.hip) ----------------------------------------------
-// which: 0 = A_s, 1 = M, 2 = H = A_s + s M.
-hipError_t launch_spmm(Problem& p, int which, const double* X,
-                       double* Y, int ncols, hipStream_t s);
-// Start of the FP64 source solves: B = (lam - s) M U, X = U,
-// R = B - A_s U, P = D^-1 R; sets bb, rz, rr, act[0].
-hipError_t launch_pcg_start(Problem& p, const double* lam, const double* U,
-                            int ncols, bool store_b, hipStream_t s);
-// Start of a solve with a given right-hand side block B (paro_pcg).
-hipError_t launch_pcg_start_rhs(Problem& p, const double* Bin, int ncols,
-                                bool store_b, hipStream_t s);
-// One CG iteration of parity `par` (FP64): three kernels.
-hipError_t launch_pcg_iter(Problem& p, int ncols, int par, hipStream_t s);
+// All take a Launch over a descriptor table; a single problem is a table of
+// one.  Every launch is asynchronous on `s`.
+hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t);
+// Start of the source solves: b = (lam - s) M U0 (or Bin), X = U0,
+// R = b - A_s U0, P = D^-1 R; per-column ||b||^2, r.z, ||r||^2 and the
+// first active set.
+hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t);
+// One CG iteration of parity `par` (FP64 or FP32 vectors).
+hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
+                           Timing* t);
 // FP32 inner solves inside FP64 refinement.
-hipError_t launch_refine_residual(Problem& p, int ncols, bool first,
-                                  hipStream_t s);
-hipError_t launch_pcg32_iter(Problem& p, int ncols, int par, hipStream_t s);
-hipError_t launch_refine_update(Problem& p, int ncols, hipStream_t s);
-// Rayleigh-Ritz: R = H X, Q = M X, Ah = X^T R, Bh = X^T Q, eigensolve,
-// U = X C with residual norms and the convergence measures in StepInfo.
-hipError_t launch_rayleigh_ritz(Problem& p, const double* W, double* lam,
-                                double* U, int ncols, bool have_old,
-                                hipStream_t s);
-hipError_t launch_gram(Problem& p, const double* W, const double* Y1,
-                       const double* Y2, double* G1, double* G2, int ncols,
-                       hipStream_t s);
-hipError_t launch_gram_full(Problem& p, const double* W,
-                            const double* Y, double* G, int ncols,
-                            hipStream_t s);
+hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t);
+hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t);
+// Poll of the table: out[0] = active CG columns of parity `which` (0, 1)
+// or refining columns (which = 2) summed over the problems, out[1] = most
+// CG iterations any problem has executed in its current solve.
+hipError_t launch_count_active(Launch& L, int which, int* out,
+                               hipStream_t s);
+hipError_t launch_gather_reports(Launch& L, PollReport* out, hipStream_t s);
+// Rayleigh-Ritz on W = X: H W, M W, the two Grams, the small eigensolve,
+// U = W C with residual norms and the step's convergence measures.
+hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t);
+// Component Gram G = X^T Y1 into Y2 (non-symmetric, all tiles).
+hipError_t launch_gram_full(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_small_geneig(const double* A, const double* B, int n,
                                double* theta, double* C, int* info,
                                hipStream_t s);

@@ -1,17 +1,23 @@
 // Kernels of one ParO step on gfx950: block Jacobi-PCG for the Nt source
 // problems of Step 3 and the Rayleigh-Ritz projection of Step 4.
 //
+// Batching.  Every kernel serves a table of problems (Desc): problem p owns
+// a contiguous range of blocks, so one launch advances all problems of a
+// batch; a single problem is a table of one.  Per-problem arithmetic and
+// summation order do not depend on the other problems of the table.
+//
 // Data layout.  Orbital blocks are row-major n x Nt (orbital fastest), so a
 // CSR neighbour gathered by the SpMM is Nt contiguous values; a thread owns
 // V consecutive columns of one row ("chunk"), a workgroup a tile of
-// kBlock / (Nt / V) rows.  Persistent grids walk the tiles; workgroup b
-// serves the tile slab (b mod 8) so that the eight XCDs each sweep one
-// contiguous slab of rows and keep their halo in their own L2.
+// kBlock / (Nt / V) rows.  A problem's blocks walk its tiles in eight
+// contiguous slabs, slab = block mod 8, so that each XCD sweeps one slab of
+// rows and keeps its halo in its own L2.  The tile's CSR slice is staged in
+// LDS with coalesced loads.
 //
 // Reductions (per-column dot products) are two-stage and deterministic:
-// each workgroup writes its partial sums, the last workgroup to finish
-// (atomic ticket, agent-scope fences) adds the partials in a fixed order
-// and updates the per-column CG scalars in ColState.  No float atomics.
+// each workgroup writes its partial sums, then a finalize kernel with one
+// workgroup per (problem, column) adds them in a fixed order.  No float
+// atomics.
 #include <cmath>
 
 #include "paro_internal.h"
@@ -25,23 +31,33 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kXcd = 8;
 constexpr size_t kPartStride = (size_t)kGridMax * kNtMax;
 
+// V consecutive values loaded or stored as one vector access.
 template <typename T, int V>
-struct VecT;
-template <>
-struct VecT<double, 1> { typedef double type; };
-template <>
-struct VecT<double, 2> { typedef double2 type; };
-template <>
-struct VecT<float, 1> { typedef float type; };
-template <>
-struct VecT<float, 2> { typedef float2 type; };
-template <>
-struct VecT<float, 4> { typedef float4 type; };
+struct VecT {
+  typedef T type __attribute__((ext_vector_type(V)));
+};
+template <typename T>
+struct VecT<T, 1> {
+  typedef T type;
+};
+
+// Pointers read from a descriptor table are generic (flat) to the
+// compiler; re-qualified as global memory they give global_load /
+// global_store, which do not wait on LDS traffic.
+#define PARO_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const PARO_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *(PARO_GLOBAL T*)p = v;
+}
 
 template <typename T, int V>
 __device__ __forceinline__ void ldv(const T* p, T (&o)[V]) {
   typedef typename VecT<T, V>::type W;
-  const W w = *reinterpret_cast<const W*>(p);
+  const W w = *(const PARO_GLOBAL W*)p;
   const T* e = reinterpret_cast<const T*>(&w);
 #pragma unroll
   for (int v = 0; v < V; ++v) o[v] = e[v];
@@ -54,16 +70,30 @@ __device__ __forceinline__ void stv(T* p, const T (&o)[V]) {
   T* e = reinterpret_cast<T*>(&w);
 #pragma unroll
   for (int v = 0; v < V; ++v) e[v] = o[v];
-  *reinterpret_cast<W*>(p) = w;
+  *(PARO_GLOBAL W*)p = w;
 }
 
-// Tiles of workgroup b in an XCD-sliced grid-stride walk.
+// The problem that owns block `bid` (binary search on the first blocks).
+__device__ __forceinline__ int owner(const Desc* D, int nprob, int bid,
+                                     bool gram) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((gram ? D[mid].g0 : D[mid].b0) <= bid)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Tiles of local block lb (of nb) in an XCD-sliced grid-stride walk.
 struct TileWalk {
   long long t, end, step;
 };
-__device__ __forceinline__ TileWalk tile_walk(long long ntiles) {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int x = b % kXcd, l = b / kXcd, gx = G / kXcd;
+__device__ __forceinline__ TileWalk tile_walk(long long ntiles, int lb,
+                                              int nb) {
+  const int x = lb % kXcd, l = lb / kXcd, gx = nb / kXcd;
   const long long chunk = (ntiles + kXcd - 1) / kXcd;
   TileWalk w;
   w.t = (long long)x * chunk + l;
@@ -73,40 +103,45 @@ __device__ __forceinline__ TileWalk tile_walk(long long ntiles) {
 }
 
 // Per-column workgroup reduction of per-thread partials acc[a][v]
-// (thread = (lr, ch)), written column-major: part[a][c][block].  NA arrays.
+// (thread = (lr, ch)), written column-major: part[a][c][vb] (ns segments).
+// red: LDS of NA * kBlock * V doubles, owned by the calling kernel.  Ends
+// with a barrier, so red may be reused at once.
 template <int V, int NA>
 __device__ void block_partials(const double (&acc)[NA][V], int ncols, int cpr,
-                               int tr, double* __restrict__ part) {
-  __shared__ double red[NA][kBlock * V];
+                               int tr, int vb, int ns,
+                               double* __restrict__ part,
+                               double* __restrict__ red) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int v = 0; v < V; ++v) red[a][tid * V + v] = acc[a][v];
+    for (int v = 0; v < V; ++v) red[(a * kBlock + tid) * V + v] = acc[a][v];
   __syncthreads();
   if (tid < ncols) {
     const int ch = tid / V, v = tid % V;
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
+      const double* ra = red + a * kBlock * V;
       double s = 0.0;
-      for (int lr = 0; lr < tr; ++lr) s += red[a][(lr * cpr + ch) * V + v];
-      part[a * kPartStride + (size_t)tid * gridDim.x + blockIdx.x] = s;
+      for (int lr = 0; lr < tr; ++lr) s += ra[(lr * cpr + ch) * V + v];
+      stg(part + a * kPartStride + (size_t)tid * ns + vb, s);
     }
   }
+  __syncthreads();
 }
 
-// In a finalize kernel with one workgroup per column c = blockIdx.x: the
+// In a finalize kernel (one workgroup per column c of a problem): the
 // fixed-order sum of part[a][c][0..nb).  Every thread receives the sums.
 template <int NA>
-__device__ void column_sums(const double* __restrict__ part, int nb,
+__device__ void column_sums(const double* __restrict__ part, int c, int nb,
                             double (&out)[NA]) {
   __shared__ double red[NA][kBlock];
-  const int c = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     const double* src = part + a * kPartStride + (size_t)c * nb;
     double s = 0.0;
-    for (int b = t; b < nb; b += kBlock) s += src[b];
+    for (int b = t; b < nb; b += kBlock) s += ldg(src + b);
     red[a][t] = s;
   }
   __syncthreads();
@@ -165,8 +200,9 @@ __device__ __forceinline__ CsrTile<TM> csr_tile(unsigned char* smem, int tr,
   return t;
 }
 
-// Stage rows [r0, r1) of the CSR into the tile with coalesced loads; row
-// pointers become tile-relative.  All threads of the block must call it.
+// Stage rows [r0, r1) of the CSR into the tile with coalesced loads (up to
+// four entries per thread in flight); row pointers become tile-relative.
+// All threads of the block must call it.
 template <typename TM>
 __device__ __forceinline__ void stage_csr(const int32_t* __restrict__ rowptr,
                                           const int32_t* __restrict__ col,
@@ -175,84 +211,211 @@ __device__ __forceinline__ void stage_csr(const int32_t* __restrict__ rowptr,
                                           long long r0, long long r1,
                                           CsrTile<TM>& t) {
   const int rows = (int)(r1 - r0);
+  const int k0 = ldg(rowptr + r0), cnt = ldg(rowptr + r1) - k0;
   __syncthreads();  // the previous tile is no longer read
-  for (int i = threadIdx.x; i <= rows; i += blockDim.x) t.rp[i] = rowptr[r0 + i];
-  __syncthreads();
-  const int k0 = t.rp[0], cnt = t.rp[rows] - k0;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-    t.col[e] = col[k0 + e];
-    t.a[e] = va[k0 + e];
-    if (vb) t.b[e] = vb[k0 + e];
+  for (int i = threadIdx.x; i <= rows; i += kBlock)
+    t.rp[i] = ldg(rowptr + r0 + i) - k0;
+  for (int e0 = threadIdx.x; e0 < cnt; e0 += 4 * kBlock) {
+    int c[4];
+    TM a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = e0 + k * kBlock;
+      if (e < cnt) {
+        c[k] = ldg(col + k0 + e);
+        a[k] = ldg(va + k0 + e);
+        b[k] = vb ? ldg(vb + k0 + e) : TM(0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = e0 + k * kBlock;
+      if (e < cnt) {
+        t.col[e] = c[k];
+        t.a[e] = a[k];
+        if (vb) t.b[e] = b[k];
+      }
+    }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= rows; i += blockDim.x) t.rp[i] -= k0;
   __syncthreads();
 }
 
+// Whether any of the V columns of chunk ch is set in act (loads issued
+// together: out-of-range columns read the last column and are masked).
 __device__ __forceinline__ bool chunk_active(const int* act, int ch, int V,
                                              int ncols) {
-  bool a = false;
+  int a = 0;
   for (int v = 0; v < V; ++v) {
     const int c = ch * V + v;
-    if (c < ncols) a = a || act[c] != 0;
+    const int x = ldg(act + min(c, ncols - 1));
+    a |= c < ncols ? x : 0;
   }
-  return a;
+  return a != 0;
 }
 
+// Row product over a staged CSR tile: y1 += a_e X[col_e] (and y2 += b_e
+// X[col_e] if TWO) over the entries e of [rs, re) in order, with kGather
+// neighbour rows in flight.  Slots past the row end reload its last
+// column with zero weight (a valid address; the terms add exact zeros).
+constexpr int kGather = 8;
+template <typename T, typename TM, int V, bool TWO>
+__device__ __forceinline__ void row_product(const CsrTile<TM>& tl, int rs,
+                                            int re, const T* X, int ncols,
+                                            int off, T (&y1)[V],
+                                            T (&y2)[V]) {
+  for (int e0 = rs; e0 < re; e0 += kGather) {
+    T x[kGather][V];
+    TM a[kGather], b[kGather];
+#pragma unroll
+    for (int k = 0; k < kGather; ++k) {
+      const bool in = e0 + k < re;
+      const int e = in ? e0 + k : re - 1;
+      ldv<T, V>(X + (size_t)tl.col[e] * ncols + off, x[k]);
+      a[k] = in ? tl.a[e] : TM(0);
+      if (TWO) b[k] = in ? tl.b[e] : TM(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kGather; ++k)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        y1[v] = fma((T)a[k], x[k][v], y1[v]);
+        if (TWO) y2[v] = fma((T)b[k], x[k][v], y2[v]);
+      }
+  }
+}
+
+// Thread geometry of virtual block vb of a problem's streaming kernel.
+struct Geo {
+  int lb, nb;             // virtual block and the problem's segment count
+  int cpr, tr, lr, ch;    // chunks per row, rows per tile, local row, chunk
+  long long ntiles;
+};
+template <int V>
+__device__ __forceinline__ Geo geo_of(const Desc& d, int vb) {
+  Geo g;
+  g.lb = vb;
+  g.nb = d.ns;
+  g.cpr = d.ncols / V;
+  g.tr = kBlock / g.cpr;
+  g.lr = threadIdx.x / g.cpr;
+  g.ch = threadIdx.x % g.cpr;
+  g.ntiles = (d.n + g.tr - 1) / g.tr;
+  return g;
+}
+
+// The virtual blocks of the real block that runs this code: its problem
+// `d` (owner of blockIdx.x) and the segments vb = lb, lb + nb, ... < ns.
+// BODY runs once per segment with VV (constexpr) the problem's vector
+// width; a barrier separates consecutive segments.  Widths 2 / 1 (FP64)
+// or 4 / 2 / 1 (FP32).
+#define PARO_VB_CASE(W, BODY) \
+  {                           \
+    constexpr int VV = W;     \
+    BODY;                     \
+  }
+#define PARO_VB_LOOP_(D, nprob, VWIDTH, DISPATCH)              \
+  {                                                          \
+    const int p_ = owner(D, nprob, blockIdx.x, false);       \
+    const Desc& d = D[p_];                                   \
+    const int vw_ = (VWIDTH);                                \
+    for (int vb = blockIdx.x - d.b0; vb < d.ns; vb += d.nb) { \
+      DISPATCH;                                              \
+      __syncthreads();                                       \
+    }                                                        \
+  }
+// VFIX != 0: every problem of the launch has that width (one code path);
+// VFIX = 0: each block branches on its problem's width.
+#define PARO_VB_LOOP64(D, nprob, VFIX, BODY)                           \
+  PARO_VB_LOOP_(D, nprob, d.v64,                                       \
+                if constexpr (VFIX != 0) PARO_VB_CASE(VFIX, BODY) else if \
+                    (vw_ == 2) PARO_VB_CASE(2, BODY) else PARO_VB_CASE(1, BODY))
+#define PARO_VB_LOOP32(D, nprob, VFIX, BODY)                                 \
+  PARO_VB_LOOP_(D, nprob, d.v32,                                             \
+                if constexpr (VFIX != 0) PARO_VB_CASE(VFIX, BODY) else if      \
+                    (vw_ == 4) PARO_VB_CASE(4, BODY) else if (vw_ == 2)        \
+                        PARO_VB_CASE(2, BODY) else PARO_VB_CASE(1, BODY))
+
+// FP64 or FP32 vectors of a problem's CG.
+template <typename T>
+struct CgVecs;
+template <>
+struct CgVecs<double> {
+  const double* val;
+  const double* dinv;
+  double *X, *R, *P, *Q;
+  __device__ CgVecs(const Desc& d)
+      : val(d.valA), dinv(d.dinv), X(d.X), R(d.R), P(d.P), Q(d.Q) {}
+};
+template <>
+struct CgVecs<float> {
+  const float* val;
+  const float* dinv;
+  float *X, *R, *P, *Q;
+  __device__ CgVecs(const Desc& d)
+      : val(d.valA32), dinv(d.dinv32), X(d.X32), R(d.R32), P(d.P32),
+        Q(d.Q32) {}
+};
+
 // ------------------------------------------------------------------------
-// SpMM for CG: Q = A P on the active columns, with per-column p . q.
-// The tile's CSR slice is staged in LDS with coalesced loads.
+// CG iteration: Q = A P on the active columns, with per-column p . q.
 // ------------------------------------------------------------------------
-template <typename T, typename TM, int V>
-__global__ void __launch_bounds__(kBlock)
-spmm_cg_kernel(const int32_t* __restrict__ rowptr,
-               const int32_t* __restrict__ col, const TM* __restrict__ val,
-               const T* __restrict__ P, T* __restrict__ Q, long long n,
-               int ncols, ColState* __restrict__ cs, int par,
-               double* __restrict__ part) {
-  if (cs->n_active[par] == 0) return;
+template <typename T, int V>
+__device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const int ncols = d.ncols;
+  // Active count and column flags are read together (one round trip).
+  const int nact = ldg(&d.cs->n_active[par]);
+  const bool mine = chunk_active(d.cs->act[par], g.ch, V, ncols);
+  if (nact == 0) return;
+  const CgVecs<T> vs(d);
   extern __shared__ unsigned char smem[];
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  CsrTile<TM> tl = csr_tile<TM>(smem, tr, 1);
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  const bool on = lr < tr && chunk_active(cs->act[par], ch, V, ncols);
+  CsrTile<T> tl = csr_tile<T>(smem, g.tr, 1);
+  const bool on = g.lr < g.tr && mine;
   double acc[1][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long r0 = w.t * tr;
-    const long long r1 = min(n, r0 + tr);
-    stage_csr<TM>(rowptr, col, val, nullptr, r0, r1, tl);
-    const long long row = r0 + lr;
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long r0 = w.t * g.tr;
+    const long long r1 = min(d.n, r0 + g.tr);
+    stage_csr<T>(d.rowptr, d.col, vs.val, nullptr, r0, r1, tl);
+    const long long row = r0 + g.lr;
     if (on && row < r1) {
-      const int rs = tl.rp[lr], re = tl.rp[lr + 1];
-      T q[V];
+      const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
+      T q[V], unused[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) q[v] = T(0);
-      for (int e = rs; e < re; ++e) {
-        const T a = (T)tl.a[e];
-        T pv[V];
-        ldv<T, V>(P + (size_t)tl.col[e] * ncols + ch * V, pv);
-#pragma unroll
-        for (int v = 0; v < V; ++v) q[v] = fma(a, pv[v], q[v]);
-      }
-      stv<T, V>(Q + (size_t)row * ncols + ch * V, q);
+      row_product<T, T, V, false>(tl, rs, re, vs.P, ncols, g.ch * V, q,
+                                  unused);
+      stv<T, V>(vs.Q + (size_t)row * ncols + g.ch * V, q);
       T po[V];
-      ldv<T, V>(P + (size_t)row * ncols + ch * V, po);
+      ldv<T, V>(vs.P + (size_t)row * ncols + g.ch * V, po);
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[0][v] += (double)po[v] * (double)q[v];
     }
   }
-  block_partials<V, 1>(acc, ncols, cpr, tr, part);
+  block_partials<V, 1>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
 }
 
-// alpha_c = (r.z)_c / (p.q)_c for the active columns (one workgroup per
-// column).  Also clears the next parity's active count for cg_beta_kernel.
+template <typename T, int VFIX>
 __global__ void __launch_bounds__(kBlock)
-cg_alpha_kernel(const double* __restrict__ part, int nb,
-                ColState* __restrict__ cs, int par) {
+spmm_cg_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
+  if constexpr (sizeof(T) == 4)
+    PARO_VB_LOOP32(D, nprob, VFIX, (spmm_cg_body<T, VV>(d, vb, par, red)))
+  else
+    PARO_VB_LOOP64(D, nprob, VFIX, (spmm_cg_body<T, VV>(d, vb, par, red)))
+}
+
+// alpha_c = (r.z)_c / (p.q)_c for the active columns (grid: column x
+// problem).  Also clears the next parity's active count for cg_beta.
+__global__ void __launch_bounds__(kBlock)
+cg_alpha_kernel(const Desc* __restrict__ D, int par) {
+  const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
+  ColState* cs = d.cs;
+  if (c >= d.ncols) return;
   if (cs->n_active[par] == 0) {
     // Nothing ran in this iteration: keep the next parity idle too, so
     // that launches queued after convergence stay no-ops.
@@ -265,7 +428,7 @@ cg_alpha_kernel(const double* __restrict__ part, int nb,
   }
   if (!cs->act[par][c]) return;
   double tot[1];
-  column_sums<1>(part, nb, tot);
+  column_sums<1>(d.part, c, d.ns, tot);
   if (threadIdx.x == 0) {
     const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -277,61 +440,78 @@ cg_alpha_kernel(const double* __restrict__ part, int nb,
   }
 }
 
-// r -= alpha q, z = D^-1 r, partial r.z and r.r; the last block forms
-// beta, counts iterations and decides which columns stay active.
-template <typename T, typename TD, int V>
-__global__ void __launch_bounds__(kBlock)
-rupd_kernel(const T* __restrict__ Qb, T* __restrict__ R,
-            const TD* __restrict__ dinv, long long n, int ncols,
-            ColState* __restrict__ cs, int par, double* __restrict__ part) {
-  if (cs->n_active[par] == 0) return;
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  const bool on = lr < tr && chunk_active(cs->act[par], ch, V, ncols);
+// r -= alpha q, z = D^-1 r, partial r.z and r.r.
+template <typename T, int V>
+__device__ __forceinline__ void rupd_body(const Desc& d, int vb, int par,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const ColState* cs = d.cs;
+  const CgVecs<T> vs(d);
+  const int ncols = d.ncols;
+  // Per-column state read with independent (clamped) loads.
+  const int nact = ldg(&cs->n_active[par]);
   T al[V];
+  bool any = false;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const int c = ch * V + v;
-    al[v] = (c < ncols && cs->act[par][c]) ? (T)cs->alpha[c] : T(0);
+    const int c = g.ch * V + v, cc = min(c, ncols - 1);
+    const int a = ldg(&cs->act[par][cc]);
+    const double alpha = ldg(&cs->alpha[cc]);
+    const bool col_on = c < ncols && a != 0;
+    al[v] = col_on ? (T)alpha : T(0);
+    any = any || col_on;
   }
+  if (nact == 0) return;
+  const bool on = g.lr < g.tr && any;
   double acc[2][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
-  const long long ntiles = (n + tr - 1) / tr;
   if (on) {
-    for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-      const long long row = w.t * tr + lr;
-      if (row >= n) continue;
-      const size_t o = (size_t)row * ncols + ch * V;
+    for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+         w.t += w.step) {
+      const long long row = w.t * g.tr + g.lr;
+      if (row >= d.n) continue;
+      const size_t o = (size_t)row * ncols + g.ch * V;
       T r[V], q[V];
-      ldv<T, V>(R + o, r);
-      ldv<T, V>(Qb + o, q);
-      const T di = (T)dinv[row];
+      ldv<T, V>(vs.R + o, r);
+      ldv<T, V>(vs.Q + o, q);
+      const T di = ldg(vs.dinv + row);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         r[v] = fma(-al[v], q[v], r[v]);
         acc[0][v] += (double)r[v] * (double)(di * r[v]);
         acc[1][v] += (double)r[v] * (double)r[v];
       }
-      stv<T, V>(R + o, r);
+      stv<T, V>(vs.R + o, r);
     }
   }
-  block_partials<V, 2>(acc, ncols, cpr, tr, part);
+  block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+}
+
+template <typename T, int VFIX>
+__global__ void __launch_bounds__(kBlock)
+rupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double red[2 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
+  if constexpr (sizeof(T) == 4)
+    PARO_VB_LOOP32(D, nprob, VFIX, (rupd_body<T, VV>(d, vb, par, red)))
+  else
+    PARO_VB_LOOP64(D, nprob, VFIX, (rupd_body<T, VV>(d, vb, par, red)))
 }
 
 // beta_c, iteration count and the stopping test of every active column
-// (one workgroup per column); counts the columns active next iteration.
+// (grid: column x problem); counts the columns active next iteration.
 __global__ void __launch_bounds__(kBlock)
-cg_beta_kernel(const double* __restrict__ part, int nb,
-               ColState* __restrict__ cs, int par) {
+cg_beta_kernel(const Desc* __restrict__ D, int par) {
+  const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
-  if (cs->n_active[par] == 0) return;
+  ColState* cs = d.cs;
+  if (c >= d.ncols || cs->n_active[par] == 0) return;
   if (!cs->act[par][c]) {
     if (threadIdx.x == 0) cs->act[par ^ 1][c] = 0;
     return;
   }
   double tot[2];
-  column_sums<2>(part, nb, tot);
+  column_sums<2>(d.part, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   int next = 0;
   const double rz = tot[0], rr = tot[1];
@@ -349,121 +529,122 @@ cg_beta_kernel(const double* __restrict__ part, int nb,
   }
   cs->act[par ^ 1][c] = next;
   if (next) atomicAdd(&cs->n_active[par ^ 1], 1);
-  atomicAdd(&cs->cg_col_iters, 1LL);
+  atomicAdd(&cs->cg_col_iters, 1ULL);
 }
 
 // x += alpha p (columns active this iteration); p = D^-1 r + beta p
 // (columns active next iteration).
-template <typename T, typename TD, int V>
-__global__ void __launch_bounds__(kBlock)
-pupd_kernel(T* __restrict__ X, T* __restrict__ P, const T* __restrict__ R,
-            const TD* __restrict__ dinv, long long n, int ncols,
-            const ColState* __restrict__ cs, int par) {
-  if (cs->n_active[par] == 0) return;
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  if (lr >= tr || !chunk_active(cs->act[par], ch, V, ncols)) return;
+template <typename T, int V>
+__device__ __forceinline__ void pupd_body(const Desc& d, int vb, int par,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const ColState* cs = d.cs;
+  const int ncols = d.ncols;
+  // Per-column state read with independent (clamped) loads.
+  const int nact = ldg(&cs->n_active[par]);
   T al[V], be[V];
   bool nx[V];
+  bool any = false;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const int c = ch * V + v;
-    const bool a = c < ncols && cs->act[par][c];
-    nx[v] = c < ncols && cs->act[par ^ 1][c];
-    al[v] = a ? (T)cs->alpha[c] : T(0);
-    be[v] = nx[v] ? (T)cs->beta[c] : T(0);
+    const int c = g.ch * V + v, cc = min(c, ncols - 1);
+    const int a0 = ldg(&cs->act[par][cc]), a1 = ldg(&cs->act[par ^ 1][cc]);
+    const double alpha = ldg(&cs->alpha[cc]), beta = ldg(&cs->beta[cc]);
+    const bool a = c < ncols && a0 != 0;
+    nx[v] = c < ncols && a1 != 0;
+    al[v] = a ? (T)alpha : T(0);
+    be[v] = nx[v] ? (T)beta : T(0);
+    any = any || a;
   }
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long row = w.t * tr + lr;
-    if (row >= n) continue;
-    const size_t o = (size_t)row * ncols + ch * V;
+  if (nact == 0) return;
+  if (g.lr >= g.tr || !any) return;
+  const CgVecs<T> vs(d);
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long row = w.t * g.tr + g.lr;
+    if (row >= d.n) continue;
+    const size_t o = (size_t)row * ncols + g.ch * V;
     T x[V], p[V], r[V];
-    ldv<T, V>(X + o, x);
-    ldv<T, V>(P + o, p);
-    ldv<T, V>(R + o, r);
-    const T di = (T)dinv[row];
+    ldv<T, V>(vs.X + o, x);
+    ldv<T, V>(vs.P + o, p);
+    ldv<T, V>(vs.R + o, r);
+    const T di = ldg(vs.dinv + row);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       x[v] = fma(al[v], p[v], x[v]);
       p[v] = nx[v] ? fma(be[v], p[v], di * r[v]) : p[v];
     }
-    stv<T, V>(X + o, x);
-    stv<T, V>(P + o, p);
+    stv<T, V>(vs.X + o, x);
+    stv<T, V>(vs.P + o, p);
   }
+}
+
+template <typename T, int VFIX>
+__global__ void __launch_bounds__(kBlock)
+pupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
+  if constexpr (sizeof(T) == 4)
+    PARO_VB_LOOP32(D, nprob, VFIX, (pupd_body<T, VV>(d, vb, par, red)))
+  else
+    PARO_VB_LOOP64(D, nprob, VFIX, (pupd_body<T, VV>(d, vb, par, red)))
 }
 
 // ------------------------------------------------------------------------
 // Start of the FP64 source solves (eq. (alg-bvp) with the shift):
-//   b = (lam - s) M u  (or a given block B),  x0 = u,
+//   b = (lam - s) M u0  (or the given Bin),  x0 = u0,
 //   r = b - A_s x0,  p = D^-1 r;  partials ||b||^2, r.z, ||r||^2.
 // ------------------------------------------------------------------------
 template <int V>
-__global__ void __launch_bounds__(kBlock)
-pcg_start_kernel(const int32_t* __restrict__ rowptr,
-                 const int32_t* __restrict__ col,
-                 const double* __restrict__ valA,
-                 const double* __restrict__ valM,
-                 const double* __restrict__ dinv, const double* __restrict__ U,
-                 const double* __restrict__ lam, const double* __restrict__ Bin,
-                 double sigma, double rtol, double* __restrict__ X,
-                 double* __restrict__ R, double* __restrict__ P,
-                 double* __restrict__ Bout, long long n, int ncols,
-                 int maxit, ColState* __restrict__ cs,
-                 double* __restrict__ part) {
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  if (blockIdx.x == 0 && tid == 0) {  // read only by the finalize kernel
+__device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const int ncols = d.ncols;
+  if (g.lb == 0 && threadIdx.x == 0) {  // read only by the finalize kernel
+    ColState* cs = d.cs;
     cs->n_active[0] = 0;
     cs->n_active[1] = 0;
     cs->n_outer = 0;
     cs->status = 0;
-    cs->maxit = maxit;
+    cs->maxit = d.maxit;
+    cs->cg_mark = cs->cg_iters;
   }
+  const double* U = d.U0;
   double sh[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const int c = ch * V + v;
-    sh[v] = (lam && c < ncols) ? lam[c] - sigma : 0.0;
+    const int c = g.ch * V + v;
+    sh[v] = (d.lam && c < ncols) ? d.lam[c] - d.sigma : 0.0;
   }
   extern __shared__ unsigned char smem[];
-  CsrTile<double> tl = csr_tile<double>(smem, tr, 2);
+  CsrTile<double> tl = csr_tile<double>(smem, g.tr, 2);
   double acc[3][V];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long r0 = w.t * tr;
-    const long long r1 = min(n, r0 + tr);
-    stage_csr<double>(rowptr, col, valA, valM, r0, r1, tl);
-    const long long row = r0 + lr;
-    if (lr >= tr || row >= r1) continue;
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long r0 = w.t * g.tr;
+    const long long r1 = min(d.n, r0 + g.tr);
+    stage_csr<double>(d.rowptr, d.col, d.valA, d.valM, r0, r1, tl);
+    const long long row = r0 + g.lr;
+    if (g.lr >= g.tr || row >= r1) continue;
     double au[V], mu[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
-    const int rs = tl.rp[lr], re = tl.rp[lr + 1];
-    for (int e = rs; e < re; ++e) {
-      const double a = tl.a[e], m = tl.b[e];
-      double u[V];
-      ldv<double, V>(U + (size_t)tl.col[e] * ncols + ch * V, u);
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        au[v] = fma(a, u[v], au[v]);
-        mu[v] = fma(m, u[v], mu[v]);
-      }
-    }
-    const size_t o = (size_t)row * ncols + ch * V;
+    const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
+    row_product<double, double, V, true>(tl, rs, re, U, ncols, g.ch * V, au,
+                                         mu);
+    const size_t o = (size_t)row * ncols + g.ch * V;
     double b[V], r[V], p[V], u[V];
     ldv<double, V>(U + o, u);
-    if (Bin) {
-      ldv<double, V>(Bin + o, b);
+    if (d.Bin) {
+      ldv<double, V>(d.Bin + o, b);
     } else {
 #pragma unroll
       for (int v = 0; v < V; ++v) b[v] = sh[v] * mu[v];
     }
-    const double di = dinv[row];
+    const double di = ldg(d.dinv + row);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       r[v] = b[v] - au[v];
@@ -472,24 +653,34 @@ pcg_start_kernel(const int32_t* __restrict__ rowptr,
       acc[1][v] += r[v] * p[v];
       acc[2][v] += r[v] * r[v];
     }
-    if (X != U) stv<double, V>(X + o, u);
-    stv<double, V>(R + o, r);
-    stv<double, V>(P + o, p);
-    if (Bout) stv<double, V>(Bout + o, b);
+    if (d.X != U) stv<double, V>(d.X + o, u);
+    stv<double, V>(d.R + o, r);
+    stv<double, V>(d.P + o, p);
+    if (d.B) stv<double, V>(d.B + o, b);
   }
-  block_partials<V, 3>(acc, ncols, cpr, tr, part);
+  block_partials<V, 3>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+}
+
+template <int VFIX>
+__global__ void __launch_bounds__(kBlock)
+pcg_start_kernel(const Desc* __restrict__ D, int nprob) {
+  __shared__ double red[3 * kBlock * (VFIX ? VFIX : 2)];
+  PARO_VB_LOOP64(D, nprob, VFIX, (pcg_start_body<VV>(d, vb, red)))
 }
 
 // Per-column start state: ||b||^2, r.z, ||r||^2, the stopping threshold
-// and the first active set (one workgroup per column).
+// and the first active set (grid: column x problem).
 __global__ void __launch_bounds__(kBlock)
-pcg_start_final_kernel(const double* __restrict__ part, int nb, double rtol,
-                       ColState* __restrict__ cs) {
+pcg_start_final_kernel(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
+  if (c >= d.ncols) return;
+  ColState* cs = d.cs;
   double tot[3];
-  column_sums<3>(part, nb, tot);
+  column_sums<3>(d.part, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   const double bb = tot[0], rz = tot[1], rr = tot[2];
+  const double rtol = d.rtol;
   cs->bb[c] = bb;
   cs->rz[c] = rz;
   cs->rr[c] = rr;
@@ -519,52 +710,41 @@ pcg_start_final_kernel(const double* __restrict__ part, int nb, double rtol,
 //   ||r|| <= inner_rtol ||r64||.
 // ------------------------------------------------------------------------
 template <int V>
-__global__ void __launch_bounds__(kBlock)
-refine_residual_kernel(const int32_t* __restrict__ rowptr,
-                       const int32_t* __restrict__ col,
-                       const double* __restrict__ valA,
-                       const double* __restrict__ dinv,
-                       const double* __restrict__ X,
-                       const double* __restrict__ Bb,
-                       float* __restrict__ R32, float* __restrict__ P32,
-                       float* __restrict__ X32, double rtol, double inner_rtol,
-                       long long n, int ncols, ColState* __restrict__ cs,
-                       double* __restrict__ part) {
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  const bool on = lr < tr && chunk_active(cs->oact, ch, V, ncols);
-  if (blockIdx.x == 0 && tid == 0) {  // read only by the finalize kernel
+__device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  ColState* cs = d.cs;
+  const int ncols = d.ncols;
+  const bool on = g.lr < g.tr && chunk_active(cs->oact, g.ch, V, ncols);
+  if (g.lb == 0 && threadIdx.x == 0) {  // read only by the finalize kernel
     cs->n_active[0] = 0;
     cs->n_active[1] = 0;
     cs->n_outer = 0;
+    cs->cg_mark = cs->cg_iters;
   }
   extern __shared__ unsigned char smem[];
-  CsrTile<double> tl = csr_tile<double>(smem, tr, 1);
+  CsrTile<double> tl = csr_tile<double>(smem, g.tr, 1);
   double acc[2][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long r0 = w.t * tr;
-    const long long r1 = min(n, r0 + tr);
-    stage_csr<double>(rowptr, col, valA, nullptr, r0, r1, tl);
-    const long long row = r0 + lr;
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long r0 = w.t * g.tr;
+    const long long r1 = min(d.n, r0 + g.tr);
+    stage_csr<double>(d.rowptr, d.col, d.valA, nullptr, r0, r1, tl);
+    const long long row = r0 + g.lr;
     if (!on || row >= r1) continue;
     double ax[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ax[v] = 0.0;
-    const int rs = tl.rp[lr], re = tl.rp[lr + 1];
-    for (int e = rs; e < re; ++e) {
-      const double a = tl.a[e];
-      double x[V];
-      ldv<double, V>(X + (size_t)tl.col[e] * ncols + ch * V, x);
-#pragma unroll
-      for (int v = 0; v < V; ++v) ax[v] = fma(a, x[v], ax[v]);
-    }
-    const size_t o = (size_t)row * ncols + ch * V;
+    const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
+    double unused[V];
+    row_product<double, double, V, false>(tl, rs, re, d.X, ncols, g.ch * V,
+                                          ax, unused);
+    const size_t o = (size_t)row * ncols + g.ch * V;
     double b[V];
-    ldv<double, V>(Bb + o, b);
-    const double di = dinv[row];
+    ldv<double, V>(d.B + o, b);
+    const double di = ldg(d.dinv + row);
     float r32[V], p32[V], z32[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -575,19 +755,28 @@ refine_residual_kernel(const int32_t* __restrict__ rowptr,
       z32[v] = 0.0f;
       acc[1][v] += (double)r32[v] * (double)p32[v];
     }
-    stv<float, V>(R32 + o, r32);
-    stv<float, V>(P32 + o, p32);
-    stv<float, V>(X32 + o, z32);
+    stv<float, V>(d.R32 + o, r32);
+    stv<float, V>(d.P32 + o, p32);
+    stv<float, V>(d.X32 + o, z32);
   }
-  block_partials<V, 2>(acc, ncols, cpr, tr, part);
+  block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+}
+
+template <int VFIX>
+__global__ void __launch_bounds__(kBlock)
+refine_residual_kernel(const Desc* __restrict__ D, int nprob) {
+  __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
+  PARO_VB_LOOP64(D, nprob, VFIX, (refine_residual_body<VV>(d, vb, red)))
 }
 
 // Outer (refinement) test per column and the inner threshold of the next
-// FP32 solve (one workgroup per column).
+// FP32 solve (grid: column x problem).
 __global__ void __launch_bounds__(kBlock)
-refine_final_kernel(const double* __restrict__ part, int nb, double rtol,
-                    double inner_rtol, ColState* __restrict__ cs) {
+refine_final_kernel(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
+  if (c >= d.ncols) return;
+  ColState* cs = d.cs;
   if (!cs->oact[c]) {
     if (threadIdx.x == 0) {
       cs->act[0][c] = 0;
@@ -596,10 +785,10 @@ refine_final_kernel(const double* __restrict__ part, int nb, double rtol,
     return;
   }
   double tot[2];
-  column_sums<2>(part, nb, tot);
+  column_sums<2>(d.part, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   int a = 0;
-  const double rr = tot[0];
+  const double rr = tot[0], rtol = d.rtol, irt = d.inner_rtol;
   if (!isfinite(rr)) {
     atomicOr(&cs->status, (int)kStNonFinite);
   } else {
@@ -607,7 +796,7 @@ refine_final_kernel(const double* __restrict__ part, int nb, double rtol,
     const bool more = rr > rtol * rtol * cs->bb[c];
     a = (more && cs->iters[c] < cs->maxit) ? 1 : 0;
     if (more && !a) atomicOr(&cs->status, (int)kStNoConv);
-    cs->tol2[c] = inner_rtol * inner_rtol * rr;
+    cs->tol2[c] = irt * irt * rr;
     cs->rz[c] = tot[1];
   }
   cs->oact[c] = a;
@@ -621,74 +810,129 @@ refine_final_kernel(const double* __restrict__ part, int nb, double rtol,
 
 // X += d (FP32 correction) for columns that refined in this pass.
 template <int V>
-__global__ void __launch_bounds__(kBlock)
-refine_update_kernel(double* __restrict__ X, const float* __restrict__ X32,
-                     long long n, int ncols, const ColState* __restrict__ cs) {
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  if (lr >= tr || !chunk_active(cs->oact, ch, V, ncols)) return;
+__device__ __forceinline__ void refine_update_body(const Desc& d, int vb,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const ColState* cs = d.cs;
+  const int ncols = d.ncols;
+  if (g.lr >= g.tr || !chunk_active(cs->oact, g.ch, V, ncols)) return;
   bool a[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const int c = ch * V + v;
+    const int c = g.ch * V + v;
     a[v] = c < ncols && cs->oact[c];
   }
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long row = w.t * tr + lr;
-    if (row >= n) continue;
-    const size_t o = (size_t)row * ncols + ch * V;
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long row = w.t * g.tr + g.lr;
+    if (row >= d.n) continue;
+    const size_t o = (size_t)row * ncols + g.ch * V;
     double x[V];
-    float d[V];
-    ldv<double, V>(X + o, x);
-    ldv<float, V>(X32 + o, d);
+    float dx[V];
+    ldv<double, V>(d.X + o, x);
+    ldv<float, V>(d.X32 + o, dx);
 #pragma unroll
-    for (int v = 0; v < V; ++v) x[v] += a[v] ? (double)d[v] : 0.0;
-    stv<double, V>(X + o, x);
+    for (int v = 0; v < V; ++v) x[v] += a[v] ? (double)dx[v] : 0.0;
+    stv<double, V>(d.X + o, x);
+  }
+}
+
+template <int VFIX>
+__global__ void __launch_bounds__(kBlock)
+refine_update_kernel(const Desc* __restrict__ D, int nprob) {
+  __shared__ double red[1 * kBlock * (VFIX ? VFIX : 2)];
+  PARO_VB_LOOP64(D, nprob, VFIX, (refine_update_body<VV>(d, vb, red)))
+}
+
+// Sum over the table of the active CG columns (which = 0, parity 0) or of
+// the refining columns (which = 1), for the host's poll (one block).
+__global__ void __launch_bounds__(kBlock)
+count_active_kernel(const Desc* __restrict__ D, int nprob, int which,
+                    int* __restrict__ out) {
+  __shared__ int red[kBlock], mx[kBlock];
+  int s = 0, m = 0;
+  for (int p = threadIdx.x; p < nprob; p += kBlock) {
+    const ColState* cs = D[p].cs;
+    s += which == 2 ? cs->n_outer : cs->n_active[which];
+    m = max(m, (int)(cs->cg_iters - cs->cg_mark));
+  }
+  red[threadIdx.x] = s;
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    out[1] = mx[0];
+  }
+}
+
+// Per-problem status and convergence measures of the last step.
+__global__ void __launch_bounds__(kBlock)
+gather_reports_kernel(const Desc* __restrict__ D, int nprob,
+                      PollReport* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < nprob;
+       p += gridDim.x * kBlock) {
+    const Desc& d = D[p];
+    const ColState* cs = d.cs;
+    int it = 0;
+    for (int c = 0; c < d.ncols; ++c) it = max(it, cs->iters[c]);
+    PollReport r;
+    r.status = cs->status;
+    r.max_iters = it;
+    r.geneig_info = *d.geneig_info;
+    r.pad = 0;
+    r.max_dlambda = d.si->max_dlambda;
+    r.max_resid = d.si->max_resid;
+    out[p] = r;
   }
 }
 
 // ------------------------------------------------------------------------
-// Plain SpMM (FP64): Y1 = A_s X + s1 M X, Y2 = M X (either may be null).
+// SpMM (FP64): Y1 = A_s X + s1 M X, Y2 = M X.  Rayleigh-Ritz form (rr):
+// X -> R = H X (s1 = sigma), Q = M X.  Component form: Y1, Y2, s1 of the
+// descriptor (either output may be null).
 // ------------------------------------------------------------------------
 template <int V>
-__global__ void __launch_bounds__(kBlock)
-spmm_dual_kernel(const int32_t* __restrict__ rowptr,
-                 const int32_t* __restrict__ col,
-                 const double* __restrict__ valA,
-                 const double* __restrict__ valM, const double* __restrict__ X,
-                 double* __restrict__ Y1, double* __restrict__ Y2, double s1,
-                 long long n, int ncols) {
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
+__device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const int ncols = d.ncols;
+  double* Y1 = rr ? d.R : d.Y1;
+  double* Y2 = rr ? d.Q : d.Y2;
+  const double s1 = rr ? d.sigma : d.s1;
+  const double* X = d.X;
   const bool needA = Y1 != nullptr;
   const bool needM = Y2 != nullptr || s1 != 0.0;
   extern __shared__ unsigned char smem[];
-  CsrTile<double> tl = csr_tile<double>(smem, tr, 2);
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long r0 = w.t * tr;
-    const long long r1 = min(n, r0 + tr);
-    stage_csr<double>(rowptr, col, needA ? valA : valM,
-                      (needA && needM) ? valM : nullptr, r0, r1, tl);
-    const long long row = r0 + lr;
-    if (lr >= tr || row >= r1) continue;
+  CsrTile<double> tl = csr_tile<double>(smem, g.tr, 2);
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long r0 = w.t * g.tr;
+    const long long r1 = min(d.n, r0 + g.tr);
+    stage_csr<double>(d.rowptr, d.col, needA ? d.valA : d.valM,
+                      (needA && needM) ? d.valM : nullptr, r0, r1, tl);
+    const long long row = r0 + g.lr;
+    if (g.lr >= g.tr || row >= r1) continue;
     double ax[V], mx[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ax[v] = mx[v] = 0.0;
-    const int rs = tl.rp[lr], re = tl.rp[lr + 1];
-    for (int e = rs; e < re; ++e) {
-      double x[V];
-      ldv<double, V>(X + (size_t)tl.col[e] * ncols + ch * V, x);
-      const double a = needA ? tl.a[e] : 0.0;
-      const double m = needA ? (needM ? tl.b[e] : 0.0) : tl.a[e];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        ax[v] = fma(a, x[v], ax[v]);
-        mx[v] = fma(m, x[v], mx[v]);
-      }
-    }
-    const size_t o = (size_t)row * ncols + ch * V;
+    const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
+    if (needA && needM)
+      row_product<double, double, V, true>(tl, rs, re, X, ncols, g.ch * V,
+                                           ax, mx);
+    else if (needA)
+      row_product<double, double, V, false>(tl, rs, re, X, ncols, g.ch * V,
+                                            ax, mx);
+    else
+      row_product<double, double, V, false>(tl, rs, re, X, ncols, g.ch * V,
+                                            mx, ax);
+    const size_t o = (size_t)row * ncols + g.ch * V;
     if (Y1) {
       double y[V];
 #pragma unroll
@@ -699,32 +943,51 @@ spmm_dual_kernel(const int32_t* __restrict__ rowptr,
   }
 }
 
+template <int VFIX>
+__global__ void __launch_bounds__(kBlock)
+spmm_dual_kernel(const Desc* __restrict__ D, int nprob, int rr) {
+  __shared__ double red[1 * kBlock * (VFIX ? VFIX : 2)];
+  PARO_VB_LOOP64(D, nprob, VFIX, (spmm_dual_body<VV>(d, vb, rr, red)))
+}
+
 // ------------------------------------------------------------------------
 // Gram contractions G1 = W^T Y1, G2 = W^T Y2 on FP64 matrix cores
 // (v_mfma_f64_16x16x4_f64).  Each wavefront consumes 4 rows per MFMA:
 // A = 16 columns of W over the 4 rows (lane l: row l/16, column l%16),
 // B = 16 columns of Y over the same rows; D accumulates 16 x 16 tiles.
-// Only tile pairs I <= J are formed; the last block symmetrises.
+// sym: only tile pairs I <= J of (Y1 = H W, Y2 = M W) in the
+// Rayleigh-Ritz form; otherwise all tiles of G = W^T Y1 (component form).
+// Partial tiles per block; the reduction and scatter follow.
 // ------------------------------------------------------------------------
-template <int NT16>
-__global__ void __launch_bounds__(kBlock)
-gram_kernel(const double* __restrict__ W, const double* __restrict__ Y1,
-            const double* __restrict__ Y2, long long n, int ncols,
-            double* __restrict__ gpart) {
-  constexpr int NP = NT16 * (NT16 + 1) / 2;  // tile pairs I <= J
+// Tiles of one problem's Gram: pairs I <= J (sym) or all I, J, 16 x 16.
+__host__ __device__ constexpr int gram_ntiles(int nt16, bool sym) {
+  return sym ? nt16 * (nt16 + 1) / 2 : nt16 * nt16;
+}
+
+// Virtual block vb (of gns) of a problem: its wavefronts take contiguous
+// ranges of 4-row steps; the block's tiles go to gpart[vb] in the
+// problem's own tile numbering.  sg: LDS of NG * NP * 256 doubles.
+template <int NT16, bool SYM>
+__device__ __forceinline__ void gram_body(const Desc& d, int vb,
+                                          double* __restrict__ sg) {
+  constexpr int NP = gram_ntiles(NT16, SYM);
+  constexpr int NG = SYM ? 2 : 1;
+  const int nb = d.gns;
+  const double* W = d.X;
+  const double* Y1 = SYM ? d.R : d.Y1;
+  const double* Y2 = SYM ? d.Q : nullptr;
+  const long long n = d.n;
+  const int ncols = d.ncols;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const bool two = Y2 != nullptr;
-  v4d acc1[NP], acc2[NP];
+  v4d acc[NG][NP];
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    acc1[p] = v4d{0.0, 0.0, 0.0, 0.0};
-    acc2[p] = v4d{0.0, 0.0, 0.0, 0.0};
-  }
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[g][q] = v4d{0.0, 0.0, 0.0, 0.0};
   const long long nsteps = (n + 3) / 4;
-  const long long gw = (long long)blockIdx.x * 4 + wave;
-  const long long nw = (long long)gridDim.x * 4;
-  // Contiguous range of 4-row steps per wavefront.
+  const long long gw = (long long)vb * 4 + wave;
+  const long long nw = (long long)nb * 4;
   const long long per = (nsteps + nw - 1) / nw;
   const long long s0 = gw * per, s1 = min(nsteps, s0 + per);
   for (long long st = s0; st < s1; ++st) {
@@ -735,164 +998,141 @@ gram_kernel(const double* __restrict__ W, const double* __restrict__ Y1,
       const int c = I * 16 + li;
       const bool ok = row < n && c < ncols;
       const size_t o = (size_t)row * ncols + c;
-      a[I] = ok ? W[o] : 0.0;
-      y1[I] = ok ? Y1[o] : 0.0;
-      y2[I] = (ok && two) ? Y2[o] : 0.0;
+      a[I] = ok ? ldg(W + o) : 0.0;
+      y1[I] = ok ? ldg(Y1 + o) : 0.0;
+      y2[I] = (ok && SYM) ? ldg(Y2 + o) : 0.0;
     }
-    int p = 0;
+    int q = 0;
 #pragma unroll
     for (int I = 0; I < NT16; ++I)
 #pragma unroll
-      for (int J = I; J < NT16; ++J, ++p) {
-        acc1[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], y1[J], acc1[p],
-                                                       0, 0, 0);
-        if (two)
-          acc2[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], y2[J],
-                                                         acc2[p], 0, 0, 0);
+      for (int J = SYM ? I : 0; J < NT16; ++J, ++q) {
+        acc[0][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], y1[J],
+                                                         acc[0][q], 0, 0, 0);
+        if (SYM)
+          acc[NG - 1][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              a[I], y2[J], acc[NG - 1][q], 0, 0, 0);
       }
   }
-  // D layout (measured): lane l, element r holds row l/16 + 4r, column l%16.
-  __shared__ double sg[2][NP][256];
+  // D layout (measured): lane l, element r holds row l/16 + 4r, column
+  // l%16.  The four wavefronts' tiles are added in wave order.
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+      for (int g = 0; g < NG; ++g)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int idx = (lk + 4 * r) * 16 + li;
-          if (w == 0) {
-            sg[0][p][idx] = acc1[p][r];
-            sg[1][p][idx] = acc2[p][r];
-          } else {
-            sg[0][p][idx] += acc1[p][r];
-            sg[1][p][idx] += acc2[p][r];
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = ((g * NP + q) * 16 + lk + 4 * r) * 16 + li;
+            if (w == 0)
+              sg[idx] = acc[g][q][r];
+            else
+              sg[idx] += acc[g][q][r];
           }
-        }
     }
     __syncthreads();
   }
-  const int per_blk = 2 * NP * 256;
+  const int per_blk = NG * NP * 256;
   for (int e = threadIdx.x; e < per_blk; e += kBlock)
-    gpart[(size_t)blockIdx.x * per_blk + e] = (&sg[0][0][0])[e];
+    stg(d.gpart + (size_t)vb * per_blk + e, sg[e]);
+  __syncthreads();
 }
 
-// Second stage of the Gram contractions: entry e of the tile array is the
-// fixed-order sum over the first-stage blocks (one thread per entry,
-// coalesced); then one block scatters the tiles into the ncols x ncols
-// results.  mode 0: symmetric pair (G1, G2) from tile pairs I <= J;
-// mode 1: one full matrix from all tiles.
+// First stage: block lb of the problem's gnb serves virtual blocks lb,
+// lb + gnb, ... < gns, at the problem's own tile count (NT16MAX: the
+// widest problem of the launch; !MIXED: all problems have NT16MAX).
+template <int NT16MAX, bool SYM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-gram_reduce_kernel(const double* __restrict__ gpart, int nb, int per_blk,
-                   double* __restrict__ gsum) {
+gram_kernel(const Desc* __restrict__ D, int nprob) {
+  __shared__ double sg[(SYM ? 2 : 1) * gram_ntiles(NT16MAX, SYM) * 256];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, true)];
+  const int nt16 = (d.ncols + 15) / 16;
+  for (int vb = blockIdx.x - d.g0; vb < d.gns; vb += d.gnb) {
+    if constexpr (!MIXED) {
+      gram_body<NT16MAX, SYM>(d, vb, sg);  // every problem has NT16MAX
+    } else if (nt16 == 1) {
+      gram_body<1, SYM>(d, vb, sg);
+    } else if (nt16 == 2) {
+      if constexpr (NT16MAX >= 2) gram_body<2, SYM>(d, vb, sg);
+    } else if (nt16 == 3) {
+      if constexpr (NT16MAX >= 3) gram_body<3, SYM>(d, vb, sg);
+    } else {
+      if constexpr (NT16MAX >= 4) gram_body<4, SYM>(d, vb, sg);
+    }
+  }
+}
+
+__device__ __forceinline__ int gram_per_blk(int ncols, bool sym) {
+  return (sym ? 2 : 1) * gram_ntiles((ncols + 15) / 16, sym) * 256;
+}
+
+// Second stage: entry e of problem z's tiles is the fixed-order sum over
+// its gns first-stage segments, split into kGramY chunks (grid: entries x
+// chunk x problem).
+__global__ void __launch_bounds__(kBlock)
+gram_reduce_kernel(const Desc* __restrict__ D, int sym) {
+  const Desc& d = D[blockIdx.z];
+  const int per_blk = gram_per_blk(d.ncols, sym != 0);
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= per_blk) return;
+  const int nb = d.gns;
   const int y = blockIdx.y, chunk = (nb + kGramY - 1) / kGramY;
   const int b0 = y * chunk, b1 = min(nb, b0 + chunk);
   double s = 0.0;
-  for (int b = b0; b < b1; ++b) s += gpart[(size_t)b * per_blk + e];
-  gsum[(size_t)y * per_blk + e] = s;
+  for (int b = b0; b < b1; ++b) s += ldg(d.gpart + (size_t)b * per_blk + e);
+  stg(d.gsum + (size_t)y * per_blk + e, s);
 }
 
+// Scatter of the summed tiles into the ncols x ncols results (one block
+// per problem): Ah = W^T H W, Bh = W^T M W symmetrised (sym), or Y2 =
+// W^T Y1 (component form).
 __global__ void __launch_bounds__(kBlock)
-gram_scatter_kernel(const double* __restrict__ gsum, int per_blk, int nt16,
-                    int mode, int ncols, double* __restrict__ G1,
-                    double* __restrict__ G2) {
-  const int np = mode == 0 ? nt16 * (nt16 + 1) / 2 : nt16 * nt16;
+gram_scatter_kernel(const Desc* __restrict__ D, int sym) {
+  const Desc& d = D[blockIdx.x];
+  const int ncols = d.ncols;
+  const int nt16 = (ncols + 15) / 16;
+  const int per_blk = gram_per_blk(ncols, sym != 0);
+  const int np = gram_ntiles(nt16, sym != 0);
   auto tile = [&](int idx) {
     double v = 0.0;
-    for (int y = 0; y < kGramY; ++y) v += gsum[(size_t)y * per_blk + idx];
+    for (int y = 0; y < kGramY; ++y) v += d.gsum[(size_t)y * per_blk + idx];
     return v;
   };
   for (int t = threadIdx.x; t < ncols * ncols; t += kBlock) {
     const int i = t / ncols, j = t % ncols;
-    if (mode == 1) {
-      G1[t] = tile(((i / 16) * nt16 + j / 16) * 256 + (i % 16) * 16 + j % 16);
+    if (!sym) {
+      d.Y2[t] = tile(((i / 16) * nt16 + j / 16) * 256 + (i % 16) * 16 + j % 16);
       continue;
     }
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     const int I = lo / 16, J = hi / 16;
-    const int p = I * nt16 - I * (I - 1) / 2 + (J - I);
+    const int q = I * nt16 - I * (I - 1) / 2 + (J - I);
     const int a = (lo % 16) * 16 + hi % 16, b = (hi % 16) * 16 + lo % 16;
     for (int g = 0; g < 2; ++g) {
-      double* G = g == 0 ? G1 : G2;
-      if (!G) continue;
-      const int base = (g * np + p) * 256;
+      double* G = g == 0 ? d.Ah : d.Bh;
+      const int base = (g * np + q) * 256;
       G[t] = (I == J) ? 0.5 * (tile(base + a) + tile(base + b))
                       : tile(base + a);
     }
   }
 }
 
-// Plain (non-symmetric) Gram G = W^T Y on FP64 matrix cores, all tiles:
-// the component check of the MFMA lane layout.
-template <int NT16>
-__global__ void __launch_bounds__(kBlock)
-gram_full_kernel(const double* __restrict__ W, const double* __restrict__ Y,
-                 long long n, int ncols, double* __restrict__ gpart) {
-  constexpr int NP = NT16 * NT16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  v4d acc[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
-  const long long nsteps = (n + 3) / 4;
-  const long long gw = (long long)blockIdx.x * 4 + wave;
-  const long long nw = (long long)gridDim.x * 4;
-  const long long per = (nsteps + nw - 1) / nw;
-  const long long s0 = gw * per, s1 = min(nsteps, s0 + per);
-  for (long long st = s0; st < s1; ++st) {
-    const long long row = st * 4 + lk;
-    double a[NT16], y[NT16];
-#pragma unroll
-    for (int I = 0; I < NT16; ++I) {
-      const int c = I * 16 + li;
-      const bool ok = row < n && c < ncols;
-      a[I] = ok ? W[(size_t)row * ncols + c] : 0.0;
-      y[I] = ok ? Y[(size_t)row * ncols + c] : 0.0;
-    }
-#pragma unroll
-    for (int I = 0; I < NT16; ++I)
-#pragma unroll
-      for (int J = 0; J < NT16; ++J)
-        acc[I * NT16 + J] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-            a[I], y[J], acc[I * NT16 + J], 0, 0, 0);
-  }
-  __shared__ double sg[NP][256];
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int idx = (lk + 4 * r) * 16 + li;
-          if (w == 0)
-            sg[p][idx] = acc[p][r];
-          else
-            sg[p][idx] += acc[p][r];
-        }
-    }
-    __syncthreads();
-  }
-  const int per_blk = NP * 256;
-  for (int e = threadIdx.x; e < per_blk; e += kBlock)
-    gpart[(size_t)blockIdx.x * per_blk + e] = (&sg[0][0])[e];
-}
-
 // ------------------------------------------------------------------------
 // Small generalised eigenproblem A c = theta B c (Step 4's N_t x N_t
-// problem), one wavefront, FP64, everything in LDS.
-//   1. B = L L^T (Cholesky);  2. S = L^{-1} A L^{-T};  3. Householder
-//   tridiagonalisation of S;  4. implicit QL with Wilkinson shifts;
-//   5. back-transformation;  6. theta ascending (ties by index);
-//   7. C = L^{-T} Z;  8. signs.
+// problem), one workgroup, FP64, everything in LDS.
+//   1. B = L L^T (Cholesky);  2. S = L^{-1} A L^{-T};  3. cyclic Jacobi on
+//   S with round-robin ordering (N_t/2 disjoint rotations per round);
+//   4. theta ascending (ties by index);  5. C = L^{-T} Y;  6. signs.
 // ------------------------------------------------------------------------
 constexpr int kLd = kNtMax + 1;
 
-__global__ void __launch_bounds__(kBlock)
-small_geneig_kernel(const double* __restrict__ Ain,
-                    const double* __restrict__ Bin, int n,
-                    double* __restrict__ theta_out, double* __restrict__ C_out,
-                    int* __restrict__ info_out, int* __restrict__ status) {
+__device__ void geneig_body(const double* __restrict__ Ain,
+                            const double* __restrict__ Bin, int n,
+                            double* __restrict__ theta_out,
+                            double* __restrict__ C_out,
+                            int* __restrict__ info_out,
+                            int* __restrict__ status) {
   __shared__ double A[kNtMax][kLd];
   __shared__ double L[kNtMax][kLd];
   __shared__ double Y[kNtMax][kLd];
@@ -1115,68 +1355,85 @@ small_geneig_kernel(const double* __restrict__ Ain,
   if (tid == 0) *info_out = 0;
 }
 
+
+__global__ void __launch_bounds__(kBlock)
+small_geneig_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                    int n, double* __restrict__ theta, double* __restrict__ C,
+                    int* __restrict__ info) {
+  geneig_body(A, B, n, theta, C, info, nullptr);
+}
+
+// Step 4's small eigenproblem of every problem of the table (one block
+// per problem).
+__global__ void __launch_bounds__(kBlock)
+geneig_batch_kernel(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.x];
+  geneig_body(d.Ah, d.Bh, d.ncols, d.theta, d.C, d.geneig_info,
+              &d.cs->status);
+}
+
 // ------------------------------------------------------------------------
 // Rotation U = W C with HU = (HW) C, MU = (MW) C formed on the fly for the
 // residual norms ||HU_i - theta_i MU_i||, ||MU_i|| (Step 4 output and the
-// stopping test).  Rows of W, HW, MW are staged through LDS.  The last
-// block writes lambda = theta and the step's convergence measures.
+// stopping test).  Rows of W, HW, MW are staged through LDS; W may be the
+// output itself (each tile is read before it is written).
 // ------------------------------------------------------------------------
 template <int V>
-__global__ void __launch_bounds__(kBlock)
-rotate_kernel(const double* __restrict__ W, const double* __restrict__ HW,
-              const double* __restrict__ MW, const double* __restrict__ Cg,
-              const double* __restrict__ theta, double* __restrict__ U,
-              double* __restrict__ lam, int have_old, int nreq, long long n,
-              int ncols, StepInfo* __restrict__ si,
-              double* __restrict__ part) {
+__device__ __forceinline__ void rotate_body(const Desc& d, int vb,
+    double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  const int ncols = d.ncols;
+  const double* W = d.X;
+  const double* HW = d.R;
+  const double* MW = d.Q;
+  double* U = d.Uout;
   extern __shared__ unsigned char smem[];
   double* sC = reinterpret_cast<double*>(smem);        // ncols^2
   double* sW = sC + ncols * ncols;                     // tr * ncols each
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  double* sH = sW + tr * ncols;
-  double* sM = sH + tr * ncols;
-  const int tid = threadIdx.x, lr = tid / cpr, ch = tid % cpr;
-  if (blockIdx.x == 0 && tid == 0) {
-    si->max_dlambda = 0.0;
-    si->max_resid = 0.0;
+  double* sH = sW + g.tr * ncols;
+  double* sM = sH + g.tr * ncols;
+  const int tid = threadIdx.x;
+  if (g.lb == 0 && tid == 0) {
+    d.si->max_dlambda = 0.0;
+    d.si->max_resid = 0.0;
   }
-  for (int e = tid; e < ncols * ncols; e += kBlock) sC[e] = Cg[e];
+  for (int e = tid; e < ncols * ncols; e += kBlock) sC[e] = ldg(d.C + e);
   double th[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) th[v] = theta[min(ch * V + v, ncols - 1)];
+  for (int v = 0; v < V; ++v) th[v] = d.theta[min(g.ch * V + v, ncols - 1)];
   double acc[2][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
-  const long long ntiles = (n + tr - 1) / tr;
-  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.step) {
-    const long long r0 = w.t * tr;
-    const int rows = (int)min((long long)tr, n - r0);
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long r0 = w.t * g.tr;
+    const int rows = (int)min((long long)g.tr, d.n - r0);
     __syncthreads();
     const size_t base = (size_t)r0 * ncols;
     for (int e = tid; e < rows * ncols; e += kBlock) {
-      sW[e] = W[base + e];
-      sH[e] = HW[base + e];
-      sM[e] = MW[base + e];
+      sW[e] = ldg(W + base + e);
+      sH[e] = ldg(HW + base + e);
+      sM[e] = ldg(MW + base + e);
     }
     __syncthreads();
-    if (lr < tr && lr < rows) {
+    if (g.lr < g.tr && g.lr < rows) {
       double u[V], hu[V], mu[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) u[v] = hu[v] = mu[v] = 0.0;
-      const double* wr = sW + lr * ncols;
-      const double* hr = sH + lr * ncols;
-      const double* mr = sM + lr * ncols;
+      const double* wr = sW + g.lr * ncols;
+      const double* hr = sH + g.lr * ncols;
+      const double* mr = sM + g.lr * ncols;
       for (int k = 0; k < ncols; ++k) {
         const double wk = wr[k], hk = hr[k], mk = mr[k];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const double c = sC[k * ncols + ch * V + v];
+          const double c = sC[k * ncols + g.ch * V + v];
           u[v] = fma(wk, c, u[v]);
           hu[v] = fma(hk, c, hu[v]);
           mu[v] = fma(mk, c, mu[v]);
         }
       }
-      stv<double, V>(U + base + (size_t)lr * ncols + ch * V, u);
+      stv<double, V>(U + base + (size_t)g.lr * ncols + g.ch * V, u);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double r = hu[v] - th[v] * mu[v];
@@ -1186,47 +1443,45 @@ rotate_kernel(const double* __restrict__ W, const double* __restrict__ HW,
     }
   }
   __syncthreads();
-  block_partials<V, 2>(acc, ncols, cpr, tr, part);
+  block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
 }
 
-// Per column: lambda = theta, relative change and residual (one workgroup
-// per column); maxima over the requested pairs for the stopping test.
+template <int VFIX>
 __global__ void __launch_bounds__(kBlock)
-rotate_final_kernel(const double* __restrict__ part, int nb,
-                    const double* __restrict__ theta, double* __restrict__ lam,
-                    int have_old, int nreq, int ncols,
-                    StepInfo* __restrict__ si) {
+rotate_kernel(const Desc* __restrict__ D, int nprob) {
+  __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
+  PARO_VB_LOOP64(D, nprob, VFIX, (rotate_body<VV>(d, vb, red)))
+}
+
+// Per column: lambda = theta, relative change and residual; maxima over
+// the requested pairs for the stopping test (grid: column x problem).
+__global__ void __launch_bounds__(kBlock)
+rotate_final_kernel(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
+  const int ncols = d.ncols;
+  if (c >= ncols) return;
   double tot[2];
-  column_sums<2>(part, nb, tot);
+  column_sums<2>(d.part, c, d.ns, tot);
   if (threadIdx.x != 0) return;
+  const double* theta = d.theta;
   double lmax = 0.0;
   for (int k = 0; k < ncols; ++k) lmax = fmax(lmax, fabs(theta[k]));
   const double t = theta[c];
   const double sc = fmax(fabs(t), 1e-3 * lmax);
-  const double old = lam[c];
-  const double dl = have_old ? fabs(t - old) / sc : INFINITY;
+  const double old = d.lam[c];
+  const double dl = d.have_old ? fabs(t - old) / sc : INFINITY;
   double rho = sqrt(tot[0]) / (sc * sqrt(tot[1]));
   if (!isfinite(rho)) rho = INFINITY;
+  StepInfo* si = d.si;
   si->lam_old[c] = old;
   si->dlam[c] = dl;
   si->resid[c] = rho;
-  lam[c] = t;
-  if (c < nreq) {
+  d.lam[c] = t;
+  if (c < d.nreq) {
     atomic_max_nonneg(&si->max_dlambda, dl);
     atomic_max_nonneg(&si->max_resid, rho);
   }
-}
-
-int pick_vec64(int ncols) { return (ncols % 2 == 0) ? 2 : 1; }
-int pick_vec32(int ncols) {
-  return (ncols % 4 == 0) ? 4 : ((ncols % 2 == 0) ? 2 : 1);
-}
-
-
-size_t tile_smem(int ncols, int V, size_t vsize, int nvals) {
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  return csr_tile_bytes(tr, vsize, nvals);
 }
 
 }  // namespace
@@ -1235,244 +1490,194 @@ size_t tile_smem(int ncols, int V, size_t vsize, int nvals) {
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_spmm(Problem& p, int which, const double* X,
-                       double* Y, int ncols, hipStream_t s) {
-  const int V = pick_vec64(ncols);
-  double* Y1 = which == 1 ? nullptr : Y;
-  double* Y2 = which == 1 ? Y : nullptr;
-  const double s1 = which == 2 ? p.sigma : 0.0;
-  TimedLaunch t(p, PARO_ST_RR_SPMM, s);
-  const size_t smem = tile_smem(ncols, V, sizeof(double), 2);
-  if (V == 2)
-    hipLaunchKernelGGL(spmm_dual_kernel<2>, dim3(p.grid), dim3(kBlock), smem, s,
-                       p.rowptr, p.col, p.valA, p.valM, X, Y1, Y2, s1,
-                       (long long)p.n, ncols);
-  else
-    hipLaunchKernelGGL(spmm_dual_kernel<1>, dim3(p.grid), dim3(kBlock), smem, s,
-                       p.rowptr, p.col, p.valA, p.valM, X, Y1, Y2, s1,
-                       (long long)p.n, ncols);
+// LDS of a CSR tile with the launch's largest tile (tr rows).
+static size_t csr_smem(int tr, size_t vsize, int nvals) {
+  return csr_tile_bytes(tr, vsize, nvals);
+}
+
+// Launch KERNEL<W> with W the launch's common FP64 vector width, or
+// W = 0 (per-block branch) when the problems differ.
+#define PARO_LAUNCH_W64(W, KERNEL, ...)                                \
+  switch (W) {                                                         \
+    case 2:                                                            \
+      hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__);                      \
+      break;                                                           \
+    case 1:                                                            \
+      hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__);                      \
+      break;                                                           \
+    default:                                                           \
+      hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__);                      \
+  }
+
+hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t) {
+  TimedLaunch tl(t, PARO_ST_RR_SPMM, s);
+  PARO_LAUNCH_W64(L.v64u, spmm_dual_kernel, dim3(L.blocks), dim3(kBlock),
+                  csr_smem(L.tr64, sizeof(double), 2), s, L.d, L.nprob,
+                  rr ? 1 : 0);
   return hipGetLastError();
 }
 
-static hipError_t start_common(Problem& p, const double* lam,
-                               const double* U, const double* Bin, int ncols,
-                               bool store_b, hipStream_t s) {
-  const int V = pick_vec64(ncols);
-  double* Bout = store_b ? p.B : nullptr;
-  auto k = V == 2 ? pcg_start_kernel<2> : pcg_start_kernel<1>;
-  TimedLaunch t(p, PARO_ST_START, s);
-  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock),
-                     tile_smem(ncols, V, sizeof(double), 2), s, p.rowptr, p.col,
-                     p.valA, p.valM, p.dinv, U, lam, Bin, p.sigma,
-                     p.opts.pcg_rtol, p.X, p.R, p.P, Bout, (long long)p.n,
-                     ncols, p.opts.pcg_maxit, p.cs, p.part);
-  hipLaunchKernelGGL(pcg_start_final_kernel, dim3(ncols), dim3(kBlock), 0, s,
-                     p.part, p.grid, p.opts.pcg_rtol, p.cs);
+hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
+  TimedLaunch tl(t, PARO_ST_START, s);
+  PARO_LAUNCH_W64(L.v64u, pcg_start_kernel, dim3(L.blocks), dim3(kBlock),
+                  csr_smem(L.tr64, sizeof(double), 2), s, L.d, L.nprob);
+  hipLaunchKernelGGL(pcg_start_final_kernel, dim3(L.maxcols, L.nprob),
+                     dim3(kBlock), 0, s, L.d);
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_start(Problem& p, const double* lam, const double* U,
-                            int ncols, bool store_b, hipStream_t s) {
-  return start_common(p, lam, U, nullptr, ncols, store_b, s);
-}
-
-hipError_t launch_pcg_start_rhs(Problem& p, const double* Bin, int ncols,
-                                bool store_b, hipStream_t s) {
-  // x0 = X (already in p.X), b = Bin.
-  return start_common(p, nullptr, p.X, Bin, ncols, store_b, s);
-}
-
-template <typename T, typename TM, typename TD, int V>
-static void cg_iter(Problem& p, const TM* val, const TD* dinv, T* X, T* P,
-                    T* Q, T* R, int ncols, int par, hipStream_t s) {
-  const size_t smem = tile_smem(ncols, V, sizeof(TM), 1);
+template <typename T, int W>
+static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
+  const int tr = sizeof(T) == 4 ? L.tr32 : L.tr64;
+  const size_t smem = csr_smem(tr, sizeof(T), 1);
   {
-    TimedLaunch t(p, PARO_ST_CG_SPMM, s);
-    hipLaunchKernelGGL((spmm_cg_kernel<T, TM, V>), dim3(p.grid), dim3(kBlock),
-                       smem, s, p.rowptr, p.col, val, P, Q, (long long)p.n,
-                       ncols, p.cs, par, p.part);
+    TimedLaunch tl(t, PARO_ST_CG_SPMM, s);
+    hipLaunchKernelGGL((spmm_cg_kernel<T, W>), dim3(L.blocks), dim3(kBlock),
+                       smem, s, L.d, L.nprob, par);
   }
-  hipLaunchKernelGGL(cg_alpha_kernel, dim3(ncols), dim3(kBlock), 0, s, p.part,
-                     p.grid, p.cs, par);
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(L.maxcols, L.nprob), dim3(kBlock),
+                     0, s, L.d, par);
   {
-    TimedLaunch t(p, PARO_ST_CG_RUPD, s);
-    hipLaunchKernelGGL((rupd_kernel<T, TD, V>), dim3(p.grid), dim3(kBlock), 0,
-                       s, Q, R, dinv, (long long)p.n, ncols, p.cs, par,
-                       p.part);
+    TimedLaunch tl(t, PARO_ST_CG_RUPD, s);
+    hipLaunchKernelGGL((rupd_kernel<T, W>), dim3(L.blocks), dim3(kBlock), 0,
+                       s, L.d, L.nprob, par);
   }
-  hipLaunchKernelGGL(cg_beta_kernel, dim3(ncols), dim3(kBlock), 0, s, p.part,
-                     p.grid, p.cs, par);
+  hipLaunchKernelGGL(cg_beta_kernel, dim3(L.maxcols, L.nprob), dim3(kBlock),
+                     0, s, L.d, par);
   {
-    TimedLaunch t(p, PARO_ST_CG_PUPD, s);
-    hipLaunchKernelGGL((pupd_kernel<T, TD, V>), dim3(p.grid), dim3(kBlock), 0,
-                       s, X, P, R, dinv, (long long)p.n, ncols, p.cs, par);
+    TimedLaunch tl(t, PARO_ST_CG_PUPD, s);
+    hipLaunchKernelGGL((pupd_kernel<T, W>), dim3(L.blocks), dim3(kBlock), 0,
+                       s, L.d, L.nprob, par);
   }
 }
 
-hipError_t launch_pcg_iter(Problem& p, int ncols, int par, hipStream_t s) {
-  if (pick_vec64(ncols) == 2)
-    cg_iter<double, double, double, 2>(p, p.valA, p.dinv, p.X, p.P, p.Q, p.R,
-                                       ncols, par, s);
-  else
-    cg_iter<double, double, double, 1>(p, p.valA, p.dinv, p.X, p.P, p.Q, p.R,
-                                       ncols, par, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg32_iter(Problem& p, int ncols, int par, hipStream_t s) {
-  switch (pick_vec32(ncols)) {
-    case 4:
-      cg_iter<float, float, float, 4>(p, p.valA32, p.dinv32, p.X32, p.P32,
-                                      p.Q32, p.R32, ncols, par, s);
-      break;
-    case 2:
-      cg_iter<float, float, float, 2>(p, p.valA32, p.dinv32, p.X32, p.P32,
-                                      p.Q32, p.R32, ncols, par, s);
-      break;
-    default:
-      cg_iter<float, float, float, 1>(p, p.valA32, p.dinv32, p.X32, p.P32,
-                                      p.Q32, p.R32, ncols, par, s);
+hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
+                           Timing* t) {
+  if (fp32) {
+    switch (L.v32u) {
+      case 4: cg_iter_w<float, 4>(L, par, s, t); break;
+      case 2: cg_iter_w<float, 2>(L, par, s, t); break;
+      case 1: cg_iter_w<float, 1>(L, par, s, t); break;
+      default: cg_iter_w<float, 0>(L, par, s, t);
+    }
+  } else {
+    switch (L.v64u) {
+      case 2: cg_iter_w<double, 2>(L, par, s, t); break;
+      case 1: cg_iter_w<double, 1>(L, par, s, t); break;
+      default: cg_iter_w<double, 0>(L, par, s, t);
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_refine_residual(Problem& p, int ncols, bool first,
-                                  hipStream_t s) {
-  (void)first;
-  const int V = pick_vec64(ncols);
-  auto k = V == 2 ? refine_residual_kernel<2> : refine_residual_kernel<1>;
-  TimedLaunch t(p, PARO_ST_REFINE, s);
-  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock),
-                     tile_smem(ncols, V, sizeof(double), 1), s, p.rowptr, p.col,
-                     p.valA, p.dinv, p.X, p.B, p.R32, p.P32, p.X32,
-                     p.opts.pcg_rtol, p.opts.inner_rtol, (long long)p.n, ncols,
-                     p.cs, p.part);
-  hipLaunchKernelGGL(refine_final_kernel, dim3(ncols), dim3(kBlock), 0, s,
-                     p.part, p.grid, p.opts.pcg_rtol, p.opts.inner_rtol,
-                     p.cs);
+hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
+  TimedLaunch tl(t, PARO_ST_REFINE, s);
+  PARO_LAUNCH_W64(L.v64u, refine_residual_kernel, dim3(L.blocks),
+                  dim3(kBlock), csr_smem(L.tr64, sizeof(double), 1), s, L.d,
+                  L.nprob);
+  hipLaunchKernelGGL(refine_final_kernel, dim3(L.maxcols, L.nprob),
+                     dim3(kBlock), 0, s, L.d);
   return hipGetLastError();
 }
 
-hipError_t launch_refine_update(Problem& p, int ncols, hipStream_t s) {
-  const int V = pick_vec64(ncols);
-  auto k = V == 2 ? refine_update_kernel<2> : refine_update_kernel<1>;
-  TimedLaunch t(p, PARO_ST_REFINE, s);
-  hipLaunchKernelGGL(k, dim3(p.grid), dim3(kBlock), 0, s, p.X, p.X32,
-                     (long long)p.n, ncols, p.cs);
+hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t) {
+  TimedLaunch tl(t, PARO_ST_REFINE, s);
+  PARO_LAUNCH_W64(L.v64u, refine_update_kernel, dim3(L.blocks), dim3(kBlock),
+                  0, s, L.d, L.nprob);
   return hipGetLastError();
 }
 
-hipError_t launch_gram(Problem& p, const double* W, const double* Y1,
-                       const double* Y2, double* G1, double* G2, int ncols,
-                       hipStream_t s) {
-  TimedLaunch t(p, PARO_ST_GRAM, s);
-  const int nt16 = (ncols + 15) / 16;
-  const int grid = p.grid < kGramGrid ? p.grid : kGramGrid;
-  const long long n = p.n;
-  switch (nt16) {
+hipError_t launch_gather_reports(Launch& L, PollReport* out, hipStream_t s) {
+  hipLaunchKernelGGL(gather_reports_kernel, dim3((L.nprob + kBlock - 1) / kBlock),
+                     dim3(kBlock), 0, s, L.d, L.nprob, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_active(Launch& L, int which, int* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, s, L.d,
+                     L.nprob, which, out);
+  return hipGetLastError();
+}
+
+template <bool SYM, bool MIXED>
+static void gram_first_m(Launch& L, hipStream_t s) {
+  switch (L.nt16) {
     case 1:
-      hipLaunchKernelGGL(gram_kernel<1>, dim3(grid), dim3(kBlock), 0, s, W, Y1,
-                         Y2, n, ncols, p.gpart);
+      hipLaunchKernelGGL((gram_kernel<1, SYM, MIXED>), dim3(L.gblocks),
+                         dim3(kBlock), 0, s, L.d, L.nprob);
       break;
     case 2:
-      hipLaunchKernelGGL(gram_kernel<2>, dim3(grid), dim3(kBlock), 0, s, W, Y1,
-                         Y2, n, ncols, p.gpart);
+      hipLaunchKernelGGL((gram_kernel<2, SYM, MIXED>), dim3(L.gblocks),
+                         dim3(kBlock), 0, s, L.d, L.nprob);
       break;
     case 3:
-      hipLaunchKernelGGL(gram_kernel<3>, dim3(grid), dim3(kBlock), 0, s, W, Y1,
-                         Y2, n, ncols, p.gpart);
+      hipLaunchKernelGGL((gram_kernel<3, SYM, MIXED>), dim3(L.gblocks),
+                         dim3(kBlock), 0, s, L.d, L.nprob);
       break;
     default:
-      hipLaunchKernelGGL(gram_kernel<4>, dim3(grid), dim3(kBlock), 0, s, W, Y1,
-                         Y2, n, ncols, p.gpart);
+      hipLaunchKernelGGL((gram_kernel<4, SYM, MIXED>), dim3(L.gblocks),
+                         dim3(kBlock), 0, s, L.d, L.nprob);
   }
-  const int per_blk = 2 * (nt16 * (nt16 + 1) / 2) * 256;
+}
+
+template <bool SYM>
+static void gram_first(Launch& L, hipStream_t s) {
+  if (L.nt16_mixed)
+    gram_first_m<SYM, true>(L, s);
+  else
+    gram_first_m<SYM, false>(L, s);
+}
+
+static hipError_t gram(Launch& L, bool sym, hipStream_t s, Timing* t) {
+  TimedLaunch tl(t, PARO_ST_GRAM, s);
+  const int nt16 = L.nt16;
+  const int per_blk = (sym ? 2 : 1) * gram_ntiles(nt16, sym) * 256;
+  if (sym)
+    gram_first<true>(L, s);
+  else
+    gram_first<false>(L, s);
   hipLaunchKernelGGL(gram_reduce_kernel,
-                     dim3((per_blk + kBlock - 1) / kBlock, kGramY),
-                     dim3(kBlock), 0, s, p.gpart, grid, per_blk, p.gsum);
-  hipLaunchKernelGGL(gram_scatter_kernel, dim3(1), dim3(kBlock), 0, s, p.gsum,
-                     per_blk, nt16, 0, ncols, G1, Y2 ? G2 : nullptr);
+                     dim3((per_blk + kBlock - 1) / kBlock, kGramY, L.nprob),
+                     dim3(kBlock), 0, s, L.d, sym ? 1 : 0);
+  hipLaunchKernelGGL(gram_scatter_kernel, dim3(L.nprob), dim3(kBlock), 0, s,
+                     L.d, sym ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_full(Problem& p, const double* W,
-                            const double* Y, double* G, int ncols,
-                            hipStream_t s) {
-  TimedLaunch t(p, PARO_ST_GRAM, s);
-  const int nt16 = (ncols + 15) / 16;
-  const int grid = p.grid < kGramGrid ? p.grid : kGramGrid;
-  const long long n = p.n;
-  switch (nt16) {
-    case 1:
-      hipLaunchKernelGGL(gram_full_kernel<1>, dim3(grid), dim3(kBlock), 0, s,
-                         W, Y, n, ncols, p.gpart);
-      break;
-    case 2:
-      hipLaunchKernelGGL(gram_full_kernel<2>, dim3(grid), dim3(kBlock), 0, s,
-                         W, Y, n, ncols, p.gpart);
-      break;
-    case 3:
-      hipLaunchKernelGGL(gram_full_kernel<3>, dim3(grid), dim3(kBlock), 0, s,
-                         W, Y, n, ncols, p.gpart);
-      break;
-    default:
-      hipLaunchKernelGGL(gram_full_kernel<4>, dim3(grid), dim3(kBlock), 0, s,
-                         W, Y, n, ncols, p.gpart);
-  }
-  const int per_blk = nt16 * nt16 * 256;
-  hipLaunchKernelGGL(gram_reduce_kernel,
-                     dim3((per_blk + kBlock - 1) / kBlock, kGramY),
-                     dim3(kBlock), 0, s, p.gpart, grid, per_blk, p.gsum);
-  hipLaunchKernelGGL(gram_scatter_kernel, dim3(1), dim3(kBlock), 0, s, p.gsum,
-                     per_blk, nt16, 1, ncols, G, nullptr);
-  return hipGetLastError();
+hipError_t launch_gram_full(Launch& L, hipStream_t s, Timing* t) {
+  return gram(L, false, s, t);
 }
 
 hipError_t launch_small_geneig(const double* A, const double* B, int n,
                                double* theta, double* C, int* info,
                                hipStream_t s) {
   hipLaunchKernelGGL(small_geneig_kernel, dim3(1), dim3(kBlock), 0, s, A, B, n,
-                     theta, C, info, nullptr);
+                     theta, C, info);
   return hipGetLastError();
 }
 
-hipError_t launch_rayleigh_ritz(Problem& p, const double* W, double* lam,
-                                double* U, int ncols, bool have_old,
-                                hipStream_t s) {
+hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   hipError_t e;
-  // HW into R, MW into Q.
-  const int V = pick_vec64(ncols);
-  auto kd = V == 2 ? spmm_dual_kernel<2> : spmm_dual_kernel<1>;
+  if ((e = launch_spmm(L, true, s, t)) != hipSuccess) return e;
+  if ((e = gram(L, true, s, t)) != hipSuccess) return e;
   {
-    TimedLaunch t(p, PARO_ST_RR_SPMM, s);
-    hipLaunchKernelGGL(kd, dim3(p.grid), dim3(kBlock),
-                       tile_smem(ncols, V, sizeof(double), 2), s, p.rowptr,
-                       p.col,
-                       p.valA, p.valM, W, p.R, p.Q, p.sigma, (long long)p.n,
-                       ncols);
+    TimedLaunch tl(t, PARO_ST_SMALL, s);
+    hipLaunchKernelGGL(geneig_batch_kernel, dim3(L.nprob), dim3(kBlock), 0, s,
+                       L.d);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_gram(p, W, p.R, p.Q, p.Ah, p.Bh, ncols, s)) != hipSuccess)
-    return e;
+  // Rotation: C (ncols^2) plus three row tiles of tr * ncols = kBlock * V
+  // values each.
+  const size_t smem = sizeof(double) * ((size_t)L.maxcols * L.maxcols +
+                                        3 * (size_t)kBlock * L.vmax64);
   {
-    TimedLaunch t(p, PARO_ST_SMALL, s);
-    hipLaunchKernelGGL(small_geneig_kernel, dim3(1), dim3(kBlock), 0, s,
-                       p.Ah,
-                       p.Bh, ncols, p.theta, p.C, &p.si->geneig_info,
-                       &p.cs->status);
+    TimedLaunch tl(t, PARO_ST_ROTATE, s);
+    PARO_LAUNCH_W64(L.v64u, rotate_kernel, dim3(L.blocks), dim3(kBlock), smem,
+                    s, L.d, L.nprob);
+    hipLaunchKernelGGL(rotate_final_kernel, dim3(L.maxcols, L.nprob),
+                       dim3(kBlock), 0, s, L.d);
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int cpr = ncols / V, tr = kBlock / cpr;
-  const size_t smem = sizeof(double) * ((size_t)ncols * ncols +
-                                        3 * (size_t)tr * ncols);
-  auto kr = V == 2 ? rotate_kernel<2> : rotate_kernel<1>;
-  TimedLaunch t(p, PARO_ST_ROTATE, s);
-  hipLaunchKernelGGL(kr, dim3(p.grid), dim3(kBlock), smem, s, W, p.R, p.Q,
-                     p.C, p.theta, U, lam, have_old ? 1 : 0, p.N,
-                     (long long)p.n, ncols, p.si, p.part);
-  hipLaunchKernelGGL(rotate_final_kernel, dim3(ncols), dim3(kBlock), 0, s,
-                     p.part, p.grid, p.theta, lam, have_old ? 1 : 0, p.N,
-                     ncols, p.si);
   return hipGetLastError();
 }
 

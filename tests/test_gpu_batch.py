@@ -1,0 +1,145 @@
+"""Batched mode (GPU): uneven problems advanced by the same launches.
+
+Each member of a batch must reach the same result as when it runs alone
+(bitwise: the kernels reduce in an order fixed by the problem, not by the
+batch), and that result is the plain definition (lowest eigenpairs of
+H u = l M u on the member's mesh)."""
+import numpy as np
+import pytest
+
+from oracle import reference
+from paper_1405_0260_amd import binding as pb
+from paper_1405_0260_amd import inputs
+import gpu_util as gu
+from paro_checks import (closed_prefix, m_orthonormality_error,
+                         rel_lambda_err, subspace_sine)
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def members(precision=pb.PARO_FP64):
+    """Four small uneven problems: harmonic and soft-Coulomb, cubic and
+    non-cubic meshes, even and odd N + m."""
+    ws = [
+        inputs.harmonic(nc=12, N=4, m=6, seed=21, max_steps=300),
+        inputs.molecule(nc=10, N=4, m=2, lo=-6.0, hi=6.0, seed=22,
+                        pot_seed=23, max_steps=300),
+        inputs.harmonic(nc=14, N=1, m=4, seed=24, max_steps=300),
+        inputs.molecule(nc=16, N=6, m=5, lo=-8.0, hi=8.0, seed=25,
+                        pot_seed=26, max_steps=300),
+    ]
+    probs = []
+    for w in ws:
+        probs.append(gu.workload_problem(
+            w, max_steps=w.max_steps, lambda_tol=1e-12, resid_tol=1e-9,
+            pcg_rtol=1e-10, precision=precision))
+    return ws, probs
+
+
+def outputs(probs):
+    torch = _torch()
+    lams = [torch.zeros(p.Nt, dtype=torch.float64, device=gu.device())
+            for p in probs]
+    Us = [torch.zeros(p.n, p.Nt, dtype=torch.float64, device=gu.device())
+          for p in probs]
+    return lams, Us
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_batch_solve_matches_alone_and_dense(precision):
+    torch = _torch()
+    ws, probs = members(precision)
+    gu.note(f"batch of {len(probs)}, precision {precision}")
+    batch = pb.Batch(len(probs))
+    U0s = [gu.to_dev(w.U0()) for w in ws]
+    lams, Us = outputs(probs)
+    reps = pb.paro_batch_solve(batch, probs, U0s, lams, Us)
+    torch.cuda.synchronize()
+    for k, (w, p, r) in enumerate(zip(ws, probs, reps)):
+        gu.note(f"member {k}: status {r.status}, {r.steps} steps")
+        assert r.status == pb.PARO_OK, (k, r.as_dict())
+        lam_a, U_a, rep_a = gu.solve(p, w.U0())
+        lam_b, U_b = lams[k].cpu().numpy(), Us[k].cpu().numpy()
+        assert rep_a.steps == r.steps, k
+        assert np.array_equal(lam_a, lam_b), k
+        assert np.array_equal(U_a, U_b), k
+        H, M, _ = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+        lam_ref, U_ref = reference.dense_lowest(H, M, w.Nt + 1)
+        assert rel_lambda_err(lam_b[:w.N], lam_ref[:w.N]) < 1e-8, k
+        assert m_orthonormality_error(M, U_b) < 1e-11, k
+        q = closed_prefix(lam_ref, w.N)
+        assert subspace_sine(M, U_b[:, :q], U_ref[:, :q]) < 1e-6, k
+
+
+def test_batch_steps_match_single_steps():
+    """paro_batch_init + paro_batch_step, step for step, against the same
+    problems stepped one by one."""
+    torch = _torch()
+    ws, probs = members()
+    batch = pb.Batch(8)
+    U0s = [gu.to_dev(w.U0()) for w in ws]
+    lams, Us = outputs(probs)
+    pb.paro_batch_init(batch, probs, U0s, lams, Us)
+    lams1, Us1 = outputs(probs)
+    for p, U0, l1, U1 in zip(probs, U0s, lams1, Us1):
+        pb.paro_init(p, U0, l1, U1)
+    torch.cuda.synchronize()
+    for k in range(len(probs)):
+        assert torch.equal(lams[k], lams1[k]), k
+        assert torch.equal(Us[k], Us1[k]), k
+    for step in range(5):
+        reps = pb.paro_batch_step(batch, probs, lams, Us)
+        for k, p in enumerate(probs):
+            r1 = pb.paro_step(p, lams1[k], Us1[k])
+            assert reps[k].status == r1.status == pb.PARO_OK
+            assert reps[k].pcg_iters == r1.pcg_iters, (step, k)
+            assert reps[k].max_dlambda == r1.max_dlambda, (step, k)
+        torch.cuda.synchronize()
+        for k in range(len(probs)):
+            assert torch.equal(lams[k], lams1[k]), (step, k)
+            assert torch.equal(Us[k], Us1[k]), (step, k)
+
+
+def test_batch_subsets_and_order():
+    """The same problem gives the same step in any company and position."""
+    torch = _torch()
+    ws, probs = members()
+    batch = pb.Batch(4)
+    U0s = [gu.to_dev(w.U0()) for w in ws]
+    ref_l, ref_U = outputs(probs)
+    pb.paro_batch_init(batch, probs, U0s, ref_l, ref_U)
+    pb.paro_batch_step(batch, probs, ref_l, ref_U)
+    for order in ([3, 1], [2, 0, 3], [1]):
+        sub = [probs[i] for i in order]
+        ls, Us = outputs(sub)
+        pb.paro_batch_init(batch, sub, [U0s[i] for i in order], ls, Us)
+        pb.paro_batch_step(batch, sub, ls, Us)
+        torch.cuda.synchronize()
+        for j, i in enumerate(order):
+            assert torch.equal(ls[j], ref_l[i]), (order, i)
+            assert torch.equal(Us[j], ref_U[i]), (order, i)
+
+
+def test_batch_argument_errors():
+    torch = _torch()
+    ws, probs = members()
+    with pytest.raises(ValueError):
+        pb.Batch(0)
+    batch = pb.Batch(2)
+    lams, Us = outputs(probs)
+    with pytest.raises(ValueError):
+        pb.paro_batch_step(batch, probs, lams, Us)       # over capacity
+    # Mixed precisions in one call are rejected.
+    w = ws[0]
+    p32 = gu.workload_problem(w, precision=pb.PARO_FP32_INNER)
+    l2, U2 = outputs([probs[0], p32])
+    with pytest.raises(pb.ParoError) as e:
+        pb.paro_batch_init(batch, [probs[0], p32],
+                           [gu.to_dev(w.U0())] * 2, l2, U2)
+    assert e.value.code == pb.PARO_EINVAL
+    torch.cuda.synchronize()
