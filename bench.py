@@ -26,6 +26,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "softcoulomb_64c_lowest.txt")
+TRAFFIC = os.path.join(ROOT, "profiles", "softcoulomb64_mixed_traffic.md")
+SOLVER_SRC = os.path.join(ROOT, "paper_1405_0260_amd", "csrc", "solver.hip")
+
+
+def measured_traffic(kernel_substr):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known
+    size), or None when the summary is missing, covers another kernel, or
+    was taken on a different solver source than the one built now."""
+    import hashlib
+    try:
+        text = open(TRAFFIC).read()
+        sha = hashlib.sha256(open(SOLVER_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("solver_sha256: ", "traffic_kernel: ",
+                                      "traffic_bytes_per_launch: ")))
+    if fields.get("solver_sha256") != sha:
+        return None
+    if kernel_substr not in fields.get("traffic_kernel", ""):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -44,6 +67,14 @@ def parse():
                     help="FP32 inner CG residual reduction per refinement")
     ap.add_argument("--m", type=int, default=None,
                     help="buffer orbitals (default: the workload's)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="with --profile-only: first copy a 256 MiB buffer "
+                         "(a plain copy kernel of known size, the reference "
+                         "for the HBM byte counters)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-problem uneven batch")
+    ap.add_argument("--batch-sequential", action="store_true",
+                    help="also solve the batch members one by one")
     return ap.parse_args()
 
 
@@ -143,6 +174,13 @@ def main():
         }
 
     prec = args.precision
+    if args.copy_probe:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     main_res = run(prec, args.steps, args.warmup)
     if args.profile_only:
         log(json.dumps({"value": main_res["value"]}))
@@ -166,11 +204,17 @@ def main():
                       "gbs": total / (s["ms"] * 1e-3) / 1e9}
     dom = max(stages, key=lambda k: stages[k]["total_ms"])
     d = stages[dom]
+    kernel_names = {"cg_spmm": "spmm_cg_kernel", "cg_rupd": "rupd_kernel",
+                    "cg_pupd": "pupd_kernel"}
+    traffic = measured_traffic(kernel_names[dom])
     all_ms = sum(v["ms"] for v in td["stages"].values())
     roofline = {
         "bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": None if traffic is None else int(traffic),
+        "traffic_over_algorithmic": None if traffic is None else
+        round(traffic / d["bytes_per_launch"], 3),
         "bytes_per_launch": int(d["bytes_per_launch"]),
         "us_per_launch": round(d["us_per_launch"], 2),
         "launches": d["launches"],
@@ -188,6 +232,10 @@ def main():
                 1e3 * float(np.mean(r64["times"])),
                 "paro_steps": r64["reps"][-1].steps,
                 "lambda_err": r64["lambda_err"], "ok": r64["ok"]}
+
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench(args, prec)
 
     cpu = None
     if not args.no_cpu:
@@ -219,10 +267,75 @@ def main():
         "lambda_rel_err_vs_oracle_ref": main_res["lambda_err"],
         "converged": main_res["ok"],
         "fp64_plain": fp64,
+        "batch64": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def batch_bench(args, prec):
+    """The 64-problem uneven batch (meshes 16^3..48^3 cells, N 2..24, half
+    harmonic, half soft-Coulomb): assembly plus whole solves of all members
+    through paro_batch_solve, members leaving the batch as they converge.
+    Throughput counts n_dof * N per ParO step of every member."""
+    import torch
+    from paper_1405_0260_amd import binding as pb
+    from paper_1405_0260_amd import inputs
+
+    dev = torch.device("cuda:0")
+    ws = inputs.batch_64()
+    precision = pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64
+    opts = [pb.default_opts(N=x.N, m=x.m, max_steps=x.max_steps,
+                            lambda_tol=1e-11, resid_tol=1e-7, pcg_rtol=1e-10,
+                            inner_rtol=args.inner_rtol, precision=precision)
+            for x in ws]
+    boxes = [pb.Box.cube(x.nc, x.lo, x.hi) for x in ws]
+    Vs = [torch.from_numpy(x.V).to(dev) for x in ws]
+    U0s = [torch.from_numpy(x.U0()).to(dev) for x in ws]
+    lams = [torch.zeros(x.Nt, dtype=torch.float64, device=dev) for x in ws]
+    Us = [torch.zeros(x.n_dof, x.Nt, dtype=torch.float64, device=dev)
+          for x in ws]
+    wss = [torch.empty(pb.paro_query(b, o)[2] + 256, dtype=torch.uint8,
+                       device=dev) for b, o in zip(boxes, opts)]
+    bt = pb.Batch(len(ws))
+
+    def one():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        probs = [pb.paro_assemble(b, V, o, workspace=m)
+                 for b, V, o, m in zip(boxes, Vs, opts, wss)]
+        reps = pb.paro_batch_solve(bt, probs, U0s, lams, Us)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, reps
+
+    one()  # warm-up
+    dt, reps = one()
+    steps = np.array([r.steps for r in reps])
+    work = np.array([x.n_dof * x.Nt for x in ws], dtype=np.float64)
+    updates = float(sum(r.steps * x.n_dof * x.N for r, x in zip(reps, ws)))
+    log(f"[batch64] {dt:.3f} s, steps {steps.min()}..{steps.max()}, "
+        f"{sum(r.status == 0 for r in reps)}/{len(ws)} converged")
+    out = {"workload": "batch64_uneven", "members": len(ws),
+           "value": updates / dt, "unit": "orbital-updates/s",
+           "seconds": dt, "converged": int(sum(r.status == 0 for r in reps)),
+           "paro_steps_min": int(steps.min()),
+           "paro_steps_max": int(steps.max()),
+           "work_weighted_occupancy": float((work * steps).sum() /
+                                            (work.sum() * steps.max())),
+           "n_dof_range": [int(min(x.n_dof for x in ws)),
+                           int(max(x.n_dof for x in ws))]}
+    if args.batch_sequential:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        upd = 0.0
+        for k in range(len(ws)):
+            p = pb.paro_assemble(boxes[k], Vs[k], opts[k], workspace=wss[k])
+            r = pb.paro_solve(p, U0s[k], lams[k], Us[k])
+            upd += r.steps * ws[k].n_dof * ws[k].N
+        torch.cuda.synchronize()
+        out["sequential_value"] = upd / (time.perf_counter() - t0)
+    return out
 
 
 def cpu_baseline(w):

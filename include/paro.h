@@ -240,9 +240,10 @@ int paro_pcg(paro_problem* p, const double* d_B, double* d_X, int ncols,
              int32_t* h_iters, void* stream);
 
 /* ---------------------------------------------------------------------
- * Measurement.  With timing on, every kernel launch of the problem is
- * bracketed by HIP events on its stream and its duration is added to the
- * stage it belongs to; off by default (no events are created).
+ * Measurement.  With timing on, every kernel launch of the problem gets a
+ * pair of HIP events stamped by the dispatch itself (kernel execution
+ * only, no launch gaps) and its duration is added to the stage it belongs
+ * to; off by default (no events are created).
  * --------------------------------------------------------------------- */
 enum {
   PARO_ST_CG_SPMM = 0,   /* CG: Q = A P with p.q partials              */
@@ -254,7 +255,8 @@ enum {
   PARO_ST_GRAM = 6,      /* W^T H W, W^T M W on matrix cores           */
   PARO_ST_SMALL = 7,     /* small generalised eigensolve (one block)   */
   PARO_ST_ROTATE = 8,    /* U = W C with residual norms                */
-  PARO_ST_NUM = 9
+  PARO_ST_CG_FINAL = 9,  /* CG: per-column alpha, beta and stop test   */
+  PARO_ST_NUM = 10
 };
 
 typedef struct paro_timing {

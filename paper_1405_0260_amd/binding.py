@@ -55,7 +55,7 @@ class Report(ctypes.Structure):
 
 
 ST_NAMES = ["cg_spmm", "cg_rupd", "cg_pupd", "start", "refine", "rr_spmm",
-            "gram", "small_eig", "rotate"]
+            "gram", "small_eig", "rotate", "cg_final"]
 
 
 class Timing(ctypes.Structure):

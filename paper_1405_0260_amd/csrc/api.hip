@@ -22,19 +22,16 @@ struct paro_problem {
 
 namespace paro {
 
-// Host-side event timing of kernel launches (measurement only).
+// Host-side event timing of kernel launches (measurement only).  The
+// events of a launch are stamped by its dispatch (hipExtLaunchKernel), so
+// a duration covers the kernel's execution and no launch gap.
 struct Timing {
   bool on = false;
-  struct Open {
-    int stage;
-    hipEvent_t a;
-  };
   struct Pend {
     int stage;
     hipEvent_t a, b;
   };
   std::vector<hipEvent_t> pool;
-  std::vector<Open> open;
   std::vector<Pend> pend;
   int64_t launches[PARO_ST_NUM] = {};
   double ms[PARO_ST_NUM] = {};
@@ -65,27 +62,22 @@ struct Timing {
   }
   ~Timing() {
     resolve();
-    for (const Open& o : open) pool.push_back(o.a);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
 
-int timing_begin(Timing* t, int stage, hipStream_t s) {
-  if (!t || !t->on) return -1;
-  hipEvent_t a = t->get();
-  if (!a || hipEventRecord(a, s) != hipSuccess) return -1;
-  t->open.push_back({stage, a});
-  return (int)t->open.size() - 1;
+bool timing_pair(Timing* t, hipEvent_t* a, hipEvent_t* b) {
+  if (!t || !t->on) return false;
+  *a = t->get();
+  *b = t->get();
+  if (*a && *b) return true;
+  if (*a) t->pool.push_back(*a);
+  if (*b) t->pool.push_back(*b);
+  return false;
 }
 
-void timing_end(Timing* t, int slot, hipStream_t s) {
-  if (!t || slot < 0 || slot >= (int)t->open.size()) return;
-  hipEvent_t b = t->get();
-  if (b && hipEventRecord(b, s) == hipSuccess)
-    t->pend.push_back({t->open[slot].stage, t->open[slot].a, b});
-  else
-    t->pool.push_back(t->open[slot].a);
-  t->open.erase(t->open.begin() + slot);
+void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b) {
+  t->pend.push_back({stage, a, b});
   if (t->pend.size() > 4096) t->resolve();
 }
 

@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP translation units of libparo.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -213,17 +214,10 @@ struct Problem {
   PollReport* dreport;    // device report slot (workspace)
 };
 
-// Event bracketing of one launch (no-ops unless timing is on).
-int timing_begin(Timing* t, int stage, hipStream_t s);
-void timing_end(Timing* t, int slot, hipStream_t s);
-struct TimedLaunch {
-  Timing* t;
-  int slot;
-  hipStream_t s;
-  TimedLaunch(Timing* tt, int stage, hipStream_t ss)
-      : t(tt), slot(timing_begin(tt, stage, ss)), s(ss) {}
-  ~TimedLaunch() { timing_end(t, slot, s); }
-};
+// Kernel timing (api.hip): a pair of events for one launch when timing is
+// on (false otherwise), and the launch's duration added to a stage.
+bool timing_pair(Timing* t, hipEvent_t* a, hipEvent_t* b);
+void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 
 // Workspace layout: byte offsets of every region for a problem shape.
 struct Layout {

@@ -1495,34 +1495,50 @@ static size_t csr_smem(int tr, size_t vsize, int nvals) {
   return csr_tile_bytes(tr, vsize, nvals);
 }
 
+// Launch a kernel; with timing on, the start and stop events are taken by
+// the dispatch itself (kernel execution only, no launch gaps) and the
+// duration is added to `stage`.
+template <typename F, typename... Args>
+static void klaunch(Timing* t, int stage, F kernel, dim3 grid, dim3 block,
+                    size_t smem, hipStream_t s, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timing_pair(t, &a, &b)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)smem, s, a, b,
+                          0, args...);
+    timing_add(t, stage, a, b);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, smem, s, args...);
+  }
+}
+
 // Launch KERNEL<W> with W the launch's common FP64 vector width, or
 // W = 0 (per-block branch) when the problems differ.
-#define PARO_LAUNCH_W64(W, KERNEL, ...)                                \
+#define PARO_LAUNCH_W64(W, T, ST, KERNEL, ...)                         \
   switch (W) {                                                         \
     case 2:                                                            \
-      hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__);                      \
+      klaunch(T, ST, KERNEL<2>, __VA_ARGS__);                          \
       break;                                                           \
     case 1:                                                            \
-      hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__);                      \
+      klaunch(T, ST, KERNEL<1>, __VA_ARGS__);                          \
       break;                                                           \
     default:                                                           \
-      hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__);                      \
+      klaunch(T, ST, KERNEL<0>, __VA_ARGS__);                          \
   }
 
 hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t) {
-  TimedLaunch tl(t, PARO_ST_RR_SPMM, s);
-  PARO_LAUNCH_W64(L.v64u, spmm_dual_kernel, dim3(L.blocks), dim3(kBlock),
+  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_RR_SPMM, spmm_dual_kernel,
+                  dim3(L.blocks), dim3(kBlock),
                   csr_smem(L.tr64, sizeof(double), 2), s, L.d, L.nprob,
                   rr ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
-  TimedLaunch tl(t, PARO_ST_START, s);
-  PARO_LAUNCH_W64(L.v64u, pcg_start_kernel, dim3(L.blocks), dim3(kBlock),
-                  csr_smem(L.tr64, sizeof(double), 2), s, L.d, L.nprob);
-  hipLaunchKernelGGL(pcg_start_final_kernel, dim3(L.maxcols, L.nprob),
-                     dim3(kBlock), 0, s, L.d);
+  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_START, pcg_start_kernel, dim3(L.blocks),
+                  dim3(kBlock), csr_smem(L.tr64, sizeof(double), 2), s, L.d,
+                  L.nprob);
+  klaunch(t, PARO_ST_START, pcg_start_final_kernel, dim3(L.maxcols, L.nprob),
+          dim3(kBlock), 0, s, L.d);
   return hipGetLastError();
 }
 
@@ -1530,25 +1546,16 @@ template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
   const int tr = sizeof(T) == 4 ? L.tr32 : L.tr64;
   const size_t smem = csr_smem(tr, sizeof(T), 1);
-  {
-    TimedLaunch tl(t, PARO_ST_CG_SPMM, s);
-    hipLaunchKernelGGL((spmm_cg_kernel<T, W>), dim3(L.blocks), dim3(kBlock),
-                       smem, s, L.d, L.nprob, par);
-  }
-  hipLaunchKernelGGL(cg_alpha_kernel, dim3(L.maxcols, L.nprob), dim3(kBlock),
-                     0, s, L.d, par);
-  {
-    TimedLaunch tl(t, PARO_ST_CG_RUPD, s);
-    hipLaunchKernelGGL((rupd_kernel<T, W>), dim3(L.blocks), dim3(kBlock), 0,
-                       s, L.d, L.nprob, par);
-  }
-  hipLaunchKernelGGL(cg_beta_kernel, dim3(L.maxcols, L.nprob), dim3(kBlock),
-                     0, s, L.d, par);
-  {
-    TimedLaunch tl(t, PARO_ST_CG_PUPD, s);
-    hipLaunchKernelGGL((pupd_kernel<T, W>), dim3(L.blocks), dim3(kBlock), 0,
-                       s, L.d, L.nprob, par);
-  }
+  klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W>, dim3(L.blocks),
+          dim3(kBlock), smem, s, (const Desc*)L.d, L.nprob, par);
+  klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
+          dim3(kBlock), 0, s, (const Desc*)L.d, par);
+  klaunch(t, PARO_ST_CG_RUPD, rupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
+          0, s, (const Desc*)L.d, L.nprob, par);
+  klaunch(t, PARO_ST_CG_FINAL, cg_beta_kernel, dim3(L.maxcols, L.nprob),
+          dim3(kBlock), 0, s, (const Desc*)L.d, par);
+  klaunch(t, PARO_ST_CG_PUPD, pupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
+          0, s, (const Desc*)L.d, L.nprob, par);
 }
 
 hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
@@ -1571,19 +1578,17 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
 }
 
 hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
-  TimedLaunch tl(t, PARO_ST_REFINE, s);
-  PARO_LAUNCH_W64(L.v64u, refine_residual_kernel, dim3(L.blocks),
-                  dim3(kBlock), csr_smem(L.tr64, sizeof(double), 1), s, L.d,
-                  L.nprob);
-  hipLaunchKernelGGL(refine_final_kernel, dim3(L.maxcols, L.nprob),
-                     dim3(kBlock), 0, s, L.d);
+  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_kernel,
+                  dim3(L.blocks), dim3(kBlock),
+                  csr_smem(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
+  klaunch(t, PARO_ST_REFINE, refine_final_kernel, dim3(L.maxcols, L.nprob),
+          dim3(kBlock), 0, s, L.d);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t) {
-  TimedLaunch tl(t, PARO_ST_REFINE, s);
-  PARO_LAUNCH_W64(L.v64u, refine_update_kernel, dim3(L.blocks), dim3(kBlock),
-                  0, s, L.d, L.nprob);
+  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_update_kernel,
+                  dim3(L.blocks), dim3(kBlock), 0, s, L.d, L.nprob);
   return hipGetLastError();
 }
 
@@ -1601,47 +1606,47 @@ hipError_t launch_count_active(Launch& L, int which, int* out,
 }
 
 template <bool SYM, bool MIXED>
-static void gram_first_m(Launch& L, hipStream_t s) {
+static void gram_first_m(Launch& L, hipStream_t s, Timing* t) {
+  const Desc* D = L.d;
   switch (L.nt16) {
     case 1:
-      hipLaunchKernelGGL((gram_kernel<1, SYM, MIXED>), dim3(L.gblocks),
-                         dim3(kBlock), 0, s, L.d, L.nprob);
+      klaunch(t, PARO_ST_GRAM, gram_kernel<1, SYM, MIXED>, dim3(L.gblocks),
+              dim3(kBlock), 0, s, D, L.nprob);
       break;
     case 2:
-      hipLaunchKernelGGL((gram_kernel<2, SYM, MIXED>), dim3(L.gblocks),
-                         dim3(kBlock), 0, s, L.d, L.nprob);
+      klaunch(t, PARO_ST_GRAM, gram_kernel<2, SYM, MIXED>, dim3(L.gblocks),
+              dim3(kBlock), 0, s, D, L.nprob);
       break;
     case 3:
-      hipLaunchKernelGGL((gram_kernel<3, SYM, MIXED>), dim3(L.gblocks),
-                         dim3(kBlock), 0, s, L.d, L.nprob);
+      klaunch(t, PARO_ST_GRAM, gram_kernel<3, SYM, MIXED>, dim3(L.gblocks),
+              dim3(kBlock), 0, s, D, L.nprob);
       break;
     default:
-      hipLaunchKernelGGL((gram_kernel<4, SYM, MIXED>), dim3(L.gblocks),
-                         dim3(kBlock), 0, s, L.d, L.nprob);
+      klaunch(t, PARO_ST_GRAM, gram_kernel<4, SYM, MIXED>, dim3(L.gblocks),
+              dim3(kBlock), 0, s, D, L.nprob);
   }
 }
 
 template <bool SYM>
-static void gram_first(Launch& L, hipStream_t s) {
+static void gram_first(Launch& L, hipStream_t s, Timing* t) {
   if (L.nt16_mixed)
-    gram_first_m<SYM, true>(L, s);
+    gram_first_m<SYM, true>(L, s, t);
   else
-    gram_first_m<SYM, false>(L, s);
+    gram_first_m<SYM, false>(L, s, t);
 }
 
 static hipError_t gram(Launch& L, bool sym, hipStream_t s, Timing* t) {
-  TimedLaunch tl(t, PARO_ST_GRAM, s);
   const int nt16 = L.nt16;
   const int per_blk = (sym ? 2 : 1) * gram_ntiles(nt16, sym) * 256;
   if (sym)
-    gram_first<true>(L, s);
+    gram_first<true>(L, s, t);
   else
-    gram_first<false>(L, s);
-  hipLaunchKernelGGL(gram_reduce_kernel,
-                     dim3((per_blk + kBlock - 1) / kBlock, kGramY, L.nprob),
-                     dim3(kBlock), 0, s, L.d, sym ? 1 : 0);
-  hipLaunchKernelGGL(gram_scatter_kernel, dim3(L.nprob), dim3(kBlock), 0, s,
-                     L.d, sym ? 1 : 0);
+    gram_first<false>(L, s, t);
+  klaunch(t, PARO_ST_GRAM, gram_reduce_kernel,
+          dim3((per_blk + kBlock - 1) / kBlock, kGramY, L.nprob), dim3(kBlock),
+          0, s, (const Desc*)L.d, sym ? 1 : 0);
+  klaunch(t, PARO_ST_GRAM, gram_scatter_kernel, dim3(L.nprob), dim3(kBlock),
+          0, s, (const Desc*)L.d, sym ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1661,23 +1666,17 @@ hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   hipError_t e;
   if ((e = launch_spmm(L, true, s, t)) != hipSuccess) return e;
   if ((e = gram(L, true, s, t)) != hipSuccess) return e;
-  {
-    TimedLaunch tl(t, PARO_ST_SMALL, s);
-    hipLaunchKernelGGL(geneig_batch_kernel, dim3(L.nprob), dim3(kBlock), 0, s,
-                       L.d);
-  }
+  klaunch(t, PARO_ST_SMALL, geneig_batch_kernel, dim3(L.nprob), dim3(kBlock),
+          0, s, (const Desc*)L.d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // Rotation: C (ncols^2) plus three row tiles of tr * ncols = kBlock * V
   // values each.
   const size_t smem = sizeof(double) * ((size_t)L.maxcols * L.maxcols +
                                         3 * (size_t)kBlock * L.vmax64);
-  {
-    TimedLaunch tl(t, PARO_ST_ROTATE, s);
-    PARO_LAUNCH_W64(L.v64u, rotate_kernel, dim3(L.blocks), dim3(kBlock), smem,
-                    s, L.d, L.nprob);
-    hipLaunchKernelGGL(rotate_final_kernel, dim3(L.maxcols, L.nprob),
-                       dim3(kBlock), 0, s, L.d);
-  }
+  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_ROTATE, rotate_kernel, dim3(L.blocks),
+                  dim3(kBlock), smem, s, L.d, L.nprob);
+  klaunch(t, PARO_ST_ROTATE, rotate_final_kernel, dim3(L.maxcols, L.nprob),
+          dim3(kBlock), 0, s, (const Desc*)L.d);
   return hipGetLastError();
 }
 

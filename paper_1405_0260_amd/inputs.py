@@ -139,7 +139,9 @@ def batch_64(count: int = 64, seed: int = 4, nc_lo=16, nc_hi=48,
              n_lo=2, n_hi=24) -> List[Workload]:
     """Uneven batch: nc ~ U{nc_lo..nc_hi}, N ~ U{n_lo..n_hi}, half harmonic
     (box +-6), half soft-Coulomb (8 centres, Z 1..6, R in [-3,3]^3, box
-    +-10).  Member j draws its potential and orbitals from seed 4000 + j."""
+    +-10).  Member j draws its potential and orbitals from seed 4000 + j.
+    Buffers: harmonic members close the shell above N; soft-Coulomb
+    members carry N // 2 + 4 buffer orbitals."""
     rng = np.random.default_rng(seed)
     ncs = rng.integers(nc_lo, nc_hi + 1, size=count)
     Ns = rng.integers(n_lo, n_hi + 1, size=count)
@@ -153,8 +155,8 @@ def batch_64(count: int = 64, seed: int = 4, nc_lo=16, nc_hi=48,
             out.append(harmonic(nc=nc, N=N, m=m, seed=s, max_steps=300,
                                 name=f"b{j}_ho_{nc}c_N{N}"))
         else:
-            out.append(molecule(nc=nc, N=N, m=max(4, N // 2), pot_seed=s,
-                                seed=s + 100000, max_steps=400,
+            out.append(molecule(nc=nc, N=N, m=N // 2 + 4, pot_seed=s,
+                                seed=s + 100000, max_steps=1000,
                                 name=f"b{j}_sc_{nc}c_N{N}"))
     return out
 
