@@ -75,6 +75,14 @@ def parse():
                     help="skip the 64-problem uneven batch")
     ap.add_argument("--batch-sequential", action="store_true",
                     help="also solve the batch members one by one")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served request stream")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests per served run")
+    ap.add_argument("--serve-arena-gb", type=float, default=48.0,
+                    help="device arena of the server (admission budget)")
+    ap.add_argument("--serve-slots", type=int, default=64,
+                    help="most requests resident at once")
     return ap.parse_args()
 
 
@@ -237,6 +245,10 @@ def main():
     if not args.no_batch:
         batch = batch_bench(args, prec)
 
+    serve = None
+    if not args.no_serve:
+        serve = serve_bench(args, prec)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w)
@@ -268,6 +280,7 @@ def main():
         "converged": main_res["ok"],
         "fp64_plain": fp64,
         "batch64": batch,
+        "serve": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -335,6 +348,101 @@ def batch_bench(args, prec):
             upd += r.steps * ws[k].n_dof * ws[k].N
         torch.cuda.synchronize()
         out["sequential_value"] = upd / (time.perf_counter() - t0)
+    return out
+
+
+def serve_bench(args, prec):
+    """The served stream: requests mixing 64^3 soft-Coulomb problems (25%)
+    and uneven-batch-style problems, admitted by HBM footprint into the
+    continuous-batching loop.  First a closed loop (all requests at t = 0)
+    gives the saturation rate; then Poisson arrivals at 0.5x and 0.9x of
+    it.  Latency runs from arrival (host arrays ready) to the eigenpairs on
+    the host."""
+    import torch
+    from paper_1405_0260_amd import binding as pb
+    from paper_1405_0260_amd import inputs
+
+    reqs = inputs.serve_requests(args.serve_requests)
+    precision = pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64
+    opts = [pb.default_opts(N=x.N, m=x.m, max_steps=x.max_steps,
+                            lambda_tol=1e-11, resid_tol=1e-7, pcg_rtol=1e-10,
+                            inner_rtol=args.inner_rtol, precision=precision)
+            for x in reqs]
+    boxes = [pb.Box.cube(x.nc, x.lo, x.hi) for x in reqs]
+    U0s = [x.U0() for x in reqs]
+    work = [x.n_dof * x.N for x in reqs]
+    arena = int(args.serve_arena_gb * (1 << 30))
+    srv = pb.Server(arena, args.serve_slots)
+
+    def run(arrive):
+        """arrive: offsets (s) of each request from the start.  Returns
+        (makespan, latencies, updates, reports, results)."""
+        order = np.argsort(arrive, kind="stable")
+        t0 = time.perf_counter()
+        nxt, ids, done_at, reps, res = 0, {}, {}, {}, {}
+        while len(done_at) < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(order) and arrive[order[nxt]] <= now:
+                j = int(order[nxt])
+                ids[srv.submit(boxes[j], reqs[j].V, opts[j], U0s[j])] = j
+                nxt += 1
+            if len(ids) == len(done_at):   # nothing in flight
+                if nxt < len(order):        # idle until the next arrival
+                    time.sleep(max(0.0, arrive[order[nxt]] -
+                                   (time.perf_counter() - t0)))
+                continue
+            done, st = srv.tick()
+            t = time.perf_counter() - t0
+            for rid in done:
+                j = ids[rid]
+                lam, U, rep = srv.result(rid)
+                done_at[j] = t
+                reps[j] = rep
+                res[j] = lam
+        makespan = time.perf_counter() - t0
+        lat = np.array([done_at[j] - arrive[j] for j in range(len(reqs))])
+        upd = float(sum(reps[j].steps * work[j] for j in range(len(reqs))))
+        return makespan, lat, upd, reps, res
+
+    torch.cuda.synchronize()
+    span, lat, upd, reps, res = run(np.zeros(len(reqs)))
+    sat = len(reqs) / span
+    log(f"[serve] closed loop: {span:.2f} s for {len(reqs)} requests "
+        f"({sat:.2f} req/s), p50 {np.percentile(lat, 50):.2f} s")
+    out = {"workload": "served_mix", "requests": len(reqs),
+           "big_requests": int(sum(x.n_dof == 250047 for x in reqs)),
+           "slots": args.serve_slots, "arena_gb": args.serve_arena_gb,
+           "closed_loop": {"req_per_s": sat, "value": upd / span,
+                           "unit": "orbital-updates/s", "seconds": span,
+                           "p50_s": float(np.percentile(lat, 50)),
+                           "p99_s": float(np.percentile(lat, 99))},
+           "converged": int(sum(r.status == 0 for r in reps.values()))}
+    for frac in (0.5, 0.9):
+        rate = frac * sat
+        arrive = inputs.arrivals(len(reqs), rate, seed=5)
+        arrive = arrive - arrive[0]
+        span, lat, upd, reps2, res2 = run(arrive)
+        log(f"[serve] {frac}x saturation ({rate:.2f} req/s): {span:.2f} s, "
+            f"p50 {np.percentile(lat, 50):.3f} s, p99 "
+            f"{np.percentile(lat, 99):.3f} s")
+        out[f"poisson_{frac}x"] = {
+            "rate_req_per_s": rate, "value": upd / span,
+            "unit": "orbital-updates/s", "seconds": span,
+            "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)),
+            "same_as_closed_loop": all(np.array_equal(res[j], res2[j])
+                                       for j in res)}
+    # One request alone against its result in the mix (bitwise).
+    j = next(k for k, x in enumerate(reqs) if x.n_dof == 250047)
+    dev = torch.device("cuda:0")
+    p = pb.paro_assemble(boxes[j], torch.from_numpy(reqs[j].V).to(dev),
+                         opts[j])
+    lam = torch.zeros(reqs[j].Nt, dtype=torch.float64, device=dev)
+    U = torch.zeros(reqs[j].n_dof, reqs[j].Nt, dtype=torch.float64,
+                    device=dev)
+    pb.paro_solve(p, torch.from_numpy(U0s[j]).to(dev), lam, U)
+    out["alone_equals_mix"] = bool(np.array_equal(lam.cpu().numpy(), res[j]))
+    srv.close()
     return out
 
 

@@ -197,6 +197,62 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
                      double* const* d_U, void* d_batch_ws, size_t bytes,
                      void* stream, paro_report_t* reports);
 
+/* ---------------------------------------------------------------------
+ * Serving: a request loop with continuous batching (not in the paper).
+ * Requests (box, nodal potential, options, start orbitals, all on the
+ * host) queue at submit; each tick admits queued requests in arrival
+ * order while a slot is free and their HBM footprint (workspace, potential,
+ * orbitals, eigenvalues) fits in the caller's device arena, assembles and
+ * initialises them, advances every resident problem by one ParO step in
+ * one batched launch sequence, and retires the problems that met their
+ * tolerances (or failed, or reached max_steps), copying their eigenpairs
+ * to the host buffers given at submit and returning the arena space.  A
+ * problem's arithmetic is the same whatever else is resident, so each
+ * result equals the one of paro_solve on the same inputs, bitwise.
+ * --------------------------------------------------------------------- */
+typedef struct paro_server paro_server;     /* opaque, host memory only */
+
+typedef struct paro_server_stats {
+  int32_t queued;           /* submitted, not yet admitted                */
+  int32_t active;           /* resident on the device                     */
+  int64_t done;             /* retired so far                             */
+  size_t arena_used;        /* bytes of the arena held by requests        */
+  size_t arena_bytes;
+  int64_t ticks;
+} paro_server_stats_t;
+
+/* d_arena: device memory the server sub-allocates (256-byte aligned; the
+ * caller keeps it alive until paro_server_destroy).  max_active: most
+ * problems resident at once (1..PARO_BATCH_MAX).  stream: all work of the
+ * server runs on it. */
+int paro_server_create(void* d_arena, size_t arena_bytes, int32_t max_active,
+                       void* stream, paro_server** out);
+
+/* Queue a request.  h_V ((nx+1)(ny+1)(nz+1) values) and h_U0 (n_dof x
+ * (N + m), row-major) are copied at once; h_lambda (N + m) and h_U (n_dof
+ * x (N + m)) receive the result when the request retires and must stay
+ * valid until then.  PARO_ENOMEM if the request could never fit in the
+ * arena.  *id identifies the request. */
+int paro_server_submit(paro_server* s, const paro_box_t* box,
+                       const double* h_V, const paro_opts_t* opts,
+                       const double* h_U0, double* h_lambda, double* h_U,
+                       int64_t* id);
+
+/* One scheduling round (admit, one batched ParO step, retire).  Writes up
+ * to max_done ids of retired, not yet returned requests to done_ids and
+ * their number to *n_done (the rest are returned by later ticks).
+ * Synchronous.  Per-request failures (including a request that cannot be
+ * assembled) do not fail the tick; they are in the request's report. */
+int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
+                     int32_t* n_done, paro_server_stats_t* stats);
+
+/* Report of a retired request (status, steps, CG iterations, ...). */
+int paro_server_report(paro_server* s, int64_t id, paro_report_t* report);
+
+/* Release the server (resident problems are dropped; the arena stays the
+ * caller's). */
+void paro_server_destroy(paro_server* s);
+
 /* Message for the last failing call on this thread (never NULL). */
 const char* paro_last_error(void);
 const char* paro_strerror(int status);

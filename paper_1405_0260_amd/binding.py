@@ -71,6 +71,12 @@ class Timing(ctypes.Structure):
                 "cg_col_iters": self.cg_col_iters}
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", c_i32), ("active", c_i32), ("done", c_i64),
+                ("arena_used", ctypes.c_size_t),
+                ("arena_bytes", ctypes.c_size_t), ("ticks", c_i64)]
+
+
 class ParoError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"paro error {code}: {msg}")
@@ -126,6 +132,16 @@ def lib():
         "paro_batch_solve": (c_i32, [PP, c_i32, PP, PP, PP, P,
                                      ctypes.c_size_t, P,
                                      ctypes.POINTER(Report)]),
+        "paro_server_create": (c_i32, [P, ctypes.c_size_t, c_i32, P,
+                                       ctypes.POINTER(P)]),
+        "paro_server_submit": (c_i32, [P, ctypes.POINTER(Box), P,
+                                       ctypes.POINTER(Opts), P, P, P,
+                                       ctypes.POINTER(c_i64)]),
+        "paro_server_tick": (c_i32, [P, ctypes.POINTER(c_i64), c_i32,
+                                     ctypes.POINTER(c_i32),
+                                     ctypes.POINTER(ServerStats)]),
+        "paro_server_report": (c_i32, [P, c_i64, ctypes.POINTER(Report)]),
+        "paro_server_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -395,3 +411,68 @@ def paro_batch_solve(batch: Batch, probs, U0s, lams, Us, stream=None):
         batch.ptr, batch.bytes, _stream(stream), reps),
         allow=(PARO_ENOCONV,))
     return list(reps)
+
+
+# ----------------------------------------------------------------- serving
+
+class Server:
+    """Continuous-batching request loop (paro_server_*).  The device arena
+    is a torch uint8 tensor of `arena_bytes`; inputs and results are host
+    numpy arrays (results are filled when a request retires)."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 64, device=None,
+                 stream=None):
+        import torch
+        self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8,
+                                 device=device or "cuda")
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self.handle = c_vp()
+        self.max_active = max_active
+        self._keep = {}
+        _check(lib().paro_server_create(base + off, arena_bytes, max_active,
+                                        _stream(stream),
+                                        ctypes.byref(self.handle)))
+
+    def submit(self, box: Box, V, opts: Opts, U0):
+        """Queue a request; V and U0 are float64 numpy arrays (copied)."""
+        import numpy as np
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        U0 = np.ascontiguousarray(U0, dtype=np.float64)
+        Nt = opts.N + opts.m
+        lam = np.zeros(Nt)
+        U = np.zeros((U0.shape[0], Nt))
+        rid = c_i64()
+        _check(lib().paro_server_submit(
+            self.handle, ctypes.byref(box), V.ctypes.data, ctypes.byref(opts),
+            U0.ctypes.data, lam.ctypes.data, U.ctypes.data,
+            ctypes.byref(rid)))
+        self._keep[rid.value] = (lam, U)
+        return rid.value
+
+    def tick(self, max_done: int = 1024):
+        """One scheduling round; returns (retired ids, stats)."""
+        ids = (c_i64 * max_done)()
+        nd = c_i32()
+        st = ServerStats()
+        _check(lib().paro_server_tick(self.handle, ids, max_done,
+                                      ctypes.byref(nd), ctypes.byref(st)))
+        return [ids[k] for k in range(nd.value)], st
+
+    def result(self, rid: int):
+        """(lambda, U, report) of a retired request."""
+        r = Report()
+        _check(lib().paro_server_report(self.handle, rid, ctypes.byref(r)))
+        lam, U = self._keep.pop(rid)
+        return lam, U, r
+
+    def close(self):
+        if self.handle:
+            lib().paro_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

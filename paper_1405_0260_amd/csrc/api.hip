@@ -514,6 +514,8 @@ int batch_ctx(Ctx& c, paro_problem* const* probs, int count, void* ws,
 
 }  // namespace
 
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   Layout L{};
   size_t off = 0;

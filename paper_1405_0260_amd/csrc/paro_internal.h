@@ -229,6 +229,8 @@ struct Layout {
 };
 
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision);
+// Record `msg` as this thread's last error (paro_last_error); returns code.
+int set_error(int code, const char* msg);
 int64_t kuhn_nnz(int mx, int my, int mz);
 
 // ---- launchers (assemble.hip) --------------------------------------------

@@ -173,6 +173,37 @@ def harmonic_buffer(N: int) -> int:
     return nxt - N if nxt - N <= 16 else closure - N + 1
 
 
+def serve_requests(count: int, seed: int = 5, big_fraction: float = 0.25,
+                   big_nc: int = 64) -> List[Workload]:
+    """Request mix of the served stream: a fraction `big_fraction` of
+    soft-Coulomb problems like the 64^3, N = 16 workload (own potential per
+    request), the rest drawn like the members of the uneven batch.
+    Request j draws from seed 5000 + j."""
+    rng = np.random.default_rng(seed)
+    big = rng.random(count) < big_fraction
+    ncs = rng.integers(16, 49, size=count)
+    Ns = rng.integers(2, 25, size=count)
+    kinds = rng.integers(0, 2, size=count)
+    out = []
+    for j in range(count):
+        s = 5000 + j
+        if big[j]:
+            out.append(molecule(nc=big_nc, N=16, m=8, pot_seed=s,
+                                seed=s + 100000, max_steps=1000,
+                                name=f"r{j}_sc_{big_nc}c_N16"))
+        elif kinds[j] == 0:
+            N = int(Ns[j])
+            out.append(harmonic(nc=int(ncs[j]), N=N, m=harmonic_buffer(N),
+                                seed=s, max_steps=300,
+                                name=f"r{j}_ho_{ncs[j]}c_N{N}"))
+        else:
+            N = int(Ns[j])
+            out.append(molecule(nc=int(ncs[j]), N=N, m=N // 2 + 4,
+                                pot_seed=s, seed=s + 100000, max_steps=1000,
+                                name=f"r{j}_sc_{ncs[j]}c_N{N}"))
+    return out
+
+
 def arrivals(count: int, rate_hz: float, seed: int = 5) -> np.ndarray:
     """Poisson arrival times (seconds) of ``count`` requests."""
     rng = np.random.default_rng(seed)

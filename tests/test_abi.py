@@ -88,3 +88,40 @@ def test_query_rejects_bad_arguments(lib, box, opts, code):
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.paro_strerror(code).decode()
+
+
+def test_server_host_side_checks(lib):
+    """Creation and submission are host-only: a fake (never dereferenced)
+    arena address is enough to check sizes and errors."""
+    fake = ctypes.c_void_p(1 << 40)
+    srv = ctypes.c_void_p()
+    assert lib.paro_server_create(fake, 1 << 20, 0, None,
+                                  ctypes.byref(srv)) == pb.PARO_EINVAL
+    assert lib.paro_server_create(ctypes.c_void_p((1 << 40) + 8), 1 << 20, 4,
+                                  None, ctypes.byref(srv)) == pb.PARO_EINVAL
+    assert lib.paro_server_create(fake, 1 << 25, 4, None,
+                                  ctypes.byref(srv)) == pb.PARO_OK
+    box = pb.Box.cube(48, -6.0, 6.0)
+    o = pb.default_opts(N=4, m=2)
+    V = np.zeros(49 ** 3)
+    U0 = np.zeros((47 ** 3, 6))
+    lam = np.zeros(6)
+    U = np.zeros_like(U0)
+    rid = ctypes.c_int64()
+    # 32 MiB cannot hold a 48^3 problem at all.
+    assert lib.paro_server_submit(srv, ctypes.byref(box), V.ctypes.data,
+                                  ctypes.byref(o), U0.ctypes.data,
+                                  lam.ctypes.data, U.ctypes.data,
+                                  ctypes.byref(rid)) == pb.PARO_ENOMEM
+    small = pb.Box.cube(4, -1.0, 1.0)
+    V2 = np.zeros(5 ** 3)
+    U2 = np.zeros((27, 6))
+    assert lib.paro_server_submit(srv, ctypes.byref(small), V2.ctypes.data,
+                                  ctypes.byref(o), U2.ctypes.data,
+                                  lam.ctypes.data, U2.ctypes.data,
+                                  ctypes.byref(rid)) == pb.PARO_OK
+    assert rid.value == 1
+    rep = pb.Report()
+    assert lib.paro_server_report(srv, rid.value,
+                                  ctypes.byref(rep)) == pb.PARO_EINVAL
+    lib.paro_server_destroy(srv)
