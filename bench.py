@@ -194,44 +194,66 @@ def main():
         log(json.dumps({"value": main_res["value"]}))
         return
 
-    # Kernel roofline from one event-timed solve of the same workload.
-    _, rep_t, prob_t, tim = solve(prec, timing=True)
-    td = tim.as_dict()
-    vec_b = 4 if prec == "mixed" else 8
-    stages = {}
-    for st in ("cg_spmm", "cg_rupd", "cg_pupd"):
-        s = td["stages"][st]
-        if s["launches"] == 0:
-            continue
-        fixed, per_col = algorithmic_bytes(st, n, prob_t.nnz, vec_b, vec_b,
-                                           vec_b)
-        total = fixed * td["cg_iters"] + per_col * td["cg_col_iters"]
-        stages[st] = {"total_ms": s["ms"], "launches": s["launches"],
-                      "us_per_launch": 1e3 * s["ms"] / s["launches"],
-                      "bytes_per_launch": total / s["launches"],
-                      "gbs": total / (s["ms"] * 1e-3) / 1e9}
-    dom = max(stages, key=lambda k: stages[k]["total_ms"])
-    d = stages[dom]
-    kernel_names = {"cg_spmm": "spmm_cg_kernel", "cg_rupd": "rupd_kernel",
-                    "cg_pupd": "pupd_kernel"}
-    traffic = measured_traffic(kernel_names[dom])
-    all_ms = sum(v["ms"] for v in td["stages"].values())
-    roofline = {
-        "bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1),
-        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
-        "traffic": None if traffic is None else int(traffic),
-        "traffic_over_algorithmic": None if traffic is None else
-        round(traffic / d["bytes_per_launch"], 3),
-        "bytes_per_launch": int(d["bytes_per_launch"]),
-        "us_per_launch": round(d["us_per_launch"], 2),
-        "launches": d["launches"],
-        "active_cols_avg": round(td["cg_col_iters"] / max(1, td["cg_iters"]),
-                                 2),
-        "cg_stage_gbs": {k: round(v["gbs"], 1) for k, v in stages.items()},
-        "stage_ms_share": {k: round(v["ms"] / all_ms, 4)
-                           for k, v in td["stages"].items() if v["ms"] > 0},
-    }
+    def kernel_roofline(prec):
+        """Roofline of the dominant CG kernel from one event-timed solve
+        of the same workload, plus the whole CG iteration and the Gram's
+        FP64 MFMA rate."""
+        _, rep_t, prob_t, tim = solve(prec, timing=True)
+        td = tim.as_dict()
+        vec_b = 4 if prec == "mixed" else 8
+        stages = {}
+        it_bytes = 0.0
+        for st in ("cg_spmm", "cg_rupd", "cg_pupd"):
+            s = td["stages"][st]
+            if s["launches"] == 0:
+                continue
+            fixed, per_col = algorithmic_bytes(st, n, prob_t.nnz, vec_b,
+                                               vec_b, vec_b)
+            total = fixed * td["cg_iters"] + per_col * td["cg_col_iters"]
+            it_bytes += total
+            stages[st] = {"total_ms": s["ms"], "launches": s["launches"],
+                          "us_per_launch": 1e3 * s["ms"] / s["launches"],
+                          "bytes_per_launch": total / s["launches"],
+                          "gbs": total / (s["ms"] * 1e-3) / 1e9}
+        dom = max(stages, key=lambda k: stages[k]["total_ms"])
+        d = stages[dom]
+        kernel_names = {"cg_spmm": "spmm_cg_kernel", "cg_rupd": "rupd_kernel",
+                        "cg_pupd": "pupd_kernel"}
+        traffic = (measured_traffic(kernel_names[dom]) if prec == "mixed"
+                   else None)
+        all_ms = sum(v["ms"] for v in td["stages"].values())
+        cg_ms = sum(td["stages"][k]["ms"] for k in
+                    ("cg_spmm", "cg_rupd", "cg_pupd", "cg_final"))
+        g = td["stages"]["gram"]
+        gram_flop = 4.0 * n * Nt * Nt * g["launches"] / 3  # 3 kernels/Gram
+        return {
+            "bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else int(traffic),
+            "traffic_over_algorithmic": None if traffic is None else
+            round(traffic / d["bytes_per_launch"], 3),
+            "bytes_per_launch": int(d["bytes_per_launch"]),
+            "us_per_launch": round(d["us_per_launch"], 2),
+            "launches": d["launches"],
+            "active_cols_avg": round(td["cg_col_iters"] /
+                                     max(1, td["cg_iters"]), 2),
+            "cg_stage_gbs": {k: round(v["gbs"], 1) for k, v in stages.items()},
+            "cg_iteration_gbs": round(it_bytes / (cg_ms * 1e-3) / 1e9, 1),
+            "cg_iteration_frac": round(it_bytes / (cg_ms * 1e-3) / 1e9 /
+                                       HBM_PEAK_GBS, 4),
+            "gram_mfma_tflops": round(gram_flop / (g["ms"] * 1e-3) / 1e12, 2)
+            if g["ms"] > 0 else None,
+            "gram_mfma_frac_of_fp64_peak": round(
+                gram_flop / (g["ms"] * 1e-3) / 1e12 / 78.6, 4)
+            if g["ms"] > 0 else None,
+            "stage_ms_share": {k: round(v["ms"] / all_ms, 4)
+                               for k, v in td["stages"].items()
+                               if v["ms"] > 0},
+        }
+
+    roofline = kernel_roofline(prec)
+    nnz = pb.paro_query(box, opts_for(prec))[1]
 
     fp64 = None
     if not args.no_fp64 and prec != "fp64":
@@ -239,7 +261,8 @@ def main():
         fp64 = {"value": r64["value"], "ms_per_solve":
                 1e3 * float(np.mean(r64["times"])),
                 "paro_steps": r64["reps"][-1].steps,
-                "lambda_err": r64["lambda_err"], "ok": r64["ok"]}
+                "lambda_err": r64["lambda_err"], "ok": r64["ok"],
+                "roofline": kernel_roofline("fp64")}
 
     batch = None
     if not args.no_batch:
@@ -266,7 +289,7 @@ def main():
         "dtype": "f32-inner/f64" if prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"softcoulomb_64c_N{N}_m{w.m}", "n_dof": n,
-                   "nnz": prob_t.nnz, "N": N, "m": w.m,
+                   "nnz": nnz, "N": N, "m": w.m,
                    "precision": prec, "inner_rtol": args.inner_rtol,
                    "lambda_tol": 1e-11,
                    "resid_tol": 1e-7, "pcg_rtol": 1e-10,

@@ -12,7 +12,7 @@ import os
 from typing import Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libparo.so")
+LIB_PATH = os.environ.get("PARO_LIB") or os.path.join(HERE, "libparo.so")
 
 PARO_OK, PARO_EINVAL, PARO_ENOMEM, PARO_ENOTSPD = 0, -1, -2, -3
 PARO_ESINGULAR, PARO_ENOCONV, PARO_EDEVICE = -4, -5, -6

@@ -283,8 +283,9 @@ void layout_batch(std::vector<Desc>& tab) {
   int b = 0, g = 0;
   for (Desc& d : tab) {
     const double w = (double)d.n * d.ncols / total;
-    const int nb = std::max(8, std::min(d.ns, round8((int64_t)(w * kGridDefault))));
-    const int gnb = std::max(8, std::min(d.gns, round8((int64_t)(w * kGramGrid))));
+    const int nb = std::max(8, std::min(d.ns, round8((int64_t)(w * kBatchGrid))));
+    const int gnb =
+        std::max(8, std::min(d.gns, round8((int64_t)(w * kBatchGramGrid))));
     d.b0 = b;
     d.nb = nb;
     d.g0 = g;
@@ -339,12 +340,10 @@ int poll(Ctx& c, int which, int out[2], hipStream_t s) {
 // Run CG iterations (FP64 or FP32) until no column of any problem is
 // active.  The first batch of launches is as long as the previous solve in
 // the same slot took, so that a converging solve usually needs one poll;
-// later batches are short top-ups.
+// later batches are short top-ups.  Launches after convergence are no-ops
+// on the device, so no poll precedes the first batch.
 int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
-  int pw[2];
-  int rc = poll(c, 0, pw, s);
-  if (rc) return rc;
-  if (pw[0] == 0) return PARO_OK;
+  int pw[2] = {0, 0};
   const int64_t cap = (int64_t)c.maxit + 64;
   const int pred = c.predict[slot];
   int chunk = pred < 2 ? 2 : (pred > 256 ? 256 : pred);
@@ -360,7 +359,7 @@ int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
       par ^= 1;
     }
     launched += chunk;
-    rc = poll(c, par, pw, s);
+    const int rc = poll(c, par, pw, s);
     if (rc) return rc;
     if (pw[0] == 0) break;
     chunk = (pred + 3) / 4;

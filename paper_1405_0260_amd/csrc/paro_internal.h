@@ -13,10 +13,18 @@ namespace paro {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
 constexpr int kNtMax = PARO_NT_MAX;  // largest number of columns
-constexpr int kGridMax = 2048;       // largest persistent grid of the solvers
+#ifndef PARO_GRID
+#define PARO_GRID 1024
+#endif
+// Largest grid of the streaming kernels (= reduction segments).
+constexpr int kGridMax = PARO_GRID;
 constexpr int kStencil = 15;         // Kuhn P1 pattern: 15 neighbours per row
-constexpr int kGridDefault = 2048;   // default persistent grid
-constexpr int kGramGrid = 1024;      // first-stage blocks of the Gram
+constexpr int kGridDefault = PARO_GRID;  // default grid (4 per CU)
+constexpr int kGramGrid = 512;       // first-stage blocks of the Gram
+// Grids a batch launch shares out among its problems (each problem gets
+// at most its own single-problem grid).
+constexpr int kBatchGrid = 4 * PARO_GRID;
+constexpr int kBatchGramGrid = 4 * kGramGrid;
 constexpr int kGramY = 16;           // second-stage split of those blocks
 // Tile entries per Gram block for nt16 = ceil(ncols / 16): two symmetric
 // results, tile pairs I <= J, 16 x 16 each.

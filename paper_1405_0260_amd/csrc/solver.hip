@@ -41,6 +41,14 @@ struct VecT<T, 1> {
   typedef T type;
 };
 
+// Launch bounds of the streaming kernels: 256 threads; PARO_MIN_WAVES
+// (waves per SIMD the register allocation must allow) is a tuning knob.
+#ifdef PARO_MIN_WAVES
+#define PARO_STREAM_BOUNDS __launch_bounds__(kBlock, PARO_MIN_WAVES)
+#else
+#define PARO_STREAM_BOUNDS __launch_bounds__(kBlock)
+#endif
+
 // Pointers read from a descriptor table are generic (flat) to the
 // compiler; re-qualified as global memory they give global_load /
 // global_store, which do not wait on LDS traffic.
@@ -257,7 +265,10 @@ __device__ __forceinline__ bool chunk_active(const int* act, int ch, int V,
 // X[col_e] if TWO) over the entries e of [rs, re) in order, with kGather
 // neighbour rows in flight.  Slots past the row end reload its last
 // column with zero weight (a valid address; the terms add exact zeros).
-constexpr int kGather = 8;
+#ifndef PARO_KGATHER
+#define PARO_KGATHER 8
+#endif
+constexpr int kGather = PARO_KGATHER;
 template <typename T, typename TM, int V, bool TWO>
 __device__ __forceinline__ void row_product(const CsrTile<TM>& tl, int rs,
                                             int re, const T* X, int ncols,
@@ -399,7 +410,7 @@ __device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
 }
 
 template <typename T, int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 spmm_cg_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
   if constexpr (sizeof(T) == 4)
@@ -489,7 +500,7 @@ __device__ __forceinline__ void rupd_body(const Desc& d, int vb, int par,
 }
 
 template <typename T, int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 rupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double red[2 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
   if constexpr (sizeof(T) == 4)
@@ -580,7 +591,7 @@ __device__ __forceinline__ void pupd_body(const Desc& d, int vb, int par,
 }
 
 template <typename T, int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 pupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
   if constexpr (sizeof(T) == 4)
@@ -662,7 +673,7 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
 }
 
 template <int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 pcg_start_kernel(const Desc* __restrict__ D, int nprob) {
   __shared__ double red[3 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX, (pcg_start_body<VV>(d, vb, red)))
@@ -763,7 +774,7 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
 }
 
 template <int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 refine_residual_kernel(const Desc* __restrict__ D, int nprob) {
   __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX, (refine_residual_body<VV>(d, vb, red)))
@@ -838,7 +849,7 @@ __device__ __forceinline__ void refine_update_body(const Desc& d, int vb,
 }
 
 template <int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 refine_update_kernel(const Desc* __restrict__ D, int nprob) {
   __shared__ double red[1 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX, (refine_update_body<VV>(d, vb, red)))
@@ -944,7 +955,7 @@ __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
 }
 
 template <int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 spmm_dual_kernel(const Desc* __restrict__ D, int nprob, int rr) {
   __shared__ double red[1 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX, (spmm_dual_body<VV>(d, vb, rr, red)))
@@ -1447,7 +1458,7 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
 }
 
 template <int VFIX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void PARO_STREAM_BOUNDS
 rotate_kernel(const Desc* __restrict__ D, int nprob) {
   __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX, (rotate_body<VV>(d, vb, red)))
