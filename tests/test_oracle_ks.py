@@ -1,0 +1,90 @@
+"""Pins of the oracle's Kohn-Sham pieces (CPU).
+
+* Poisson: a manufactured solution that vanishes on the box boundary is
+  recovered at O(h^2) (pins the operator, the 4 pi and the mass matrix).
+* Slater exchange: equals the derivative of the homogeneous-electron-gas
+  exchange energy density (pins prefactor and exponent independently).
+* Density: occupancy 2 and only the N occupied columns.
+* The outer loop: with mixing 0 the Hamiltonian never changes after the
+  first density, so the iteration is the linear ParO on that Hamiltonian;
+  and a converged run is self-consistent (its orbitals are the lowest
+  eigenvectors of the Hamiltonian built from their own density).
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, kohn_sham as ks, paro as oparo, reference
+from paper_1405_0260_amd import inputs
+
+
+def _poisson_error(nc, L=2.0):
+    mesh = fem.kuhn_mesh(nc, 0.0, L)
+    K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    X = mesh.X[mesh.dof >= 0]
+    exact = np.prod(np.sin(np.pi * X / L), axis=1)
+    rho = 3.0 * np.pi * exact / (4.0 * L * L)
+    d = mesh.dof[mesh.dof >= 0]
+    vh = ks.hartree(K, M, rho[np.argsort(d)])
+    return np.max(np.abs(vh - exact[np.argsort(d)]))
+
+
+def test_poisson_manufactured_solution_converges_at_order_h2():
+    e = [_poisson_error(nc) for nc in (8, 16, 32)]
+    assert e[2] < 5e-3          # of max |V*| = 1
+    r1, r2 = e[0] / e[1], e[1] / e[2]
+    assert 3.3 < r1 < 4.7 and 3.6 < r2 < 4.4, (e, r1, r2)
+
+
+def test_slater_exchange_is_derivative_of_gas_exchange_energy():
+    rho = np.array([1e-4, 0.01, 0.3, 1.0, 7.5])
+    energy = lambda r: -0.75 * (3.0 / np.pi) ** (1.0 / 3.0) * r ** (4.0 / 3.0)
+    h = 1e-6 * rho
+    deriv = (energy(rho + h) - energy(rho - h)) / (2 * h)
+    assert np.allclose(ks.slater_exchange(rho), deriv, rtol=1e-8)
+    assert ks.slater_exchange(np.array([0.0, -1e-20]))[0] == 0.0
+
+
+def test_density_counts_two_electrons_per_occupied_orbital():
+    U = np.array([[1.0, 2.0, 5.0], [0.5, -1.0, 7.0]])
+    assert np.allclose(ks.density(U, 2), [2 * (1 + 4), 2 * (0.25 + 1)])
+
+
+def small_molecule(nc=10, N=2, m=4):
+    return inputs.molecule(nc=nc, N=N, m=m, lo=-6.0, hi=6.0, pot_seed=41,
+                           seed=42, centres=2, zmax=3, spread=1.5)
+
+
+def test_zero_mixing_is_linear_paro_on_the_first_hamiltonian():
+    w = small_molecule()
+    mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+    r = ks.scf(mesh, w.V, w.U0(), w.N, iterations=4, mixing=0.0,
+               rtol=1e-12)
+    # Rebuild the first Hamiltonian from the Step-1 orbitals by hand.
+    K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    H0, _ = fem.hamiltonian(mesh, w.V)
+    lam, U = oparo.rayleigh_ritz(H0, M, w.U0())
+    rho = ks.density(U, w.N)
+    V = ks.effective_potential(mesh, w.V, rho, ks.hartree(K, M, rho))
+    H, _ = fem.hamiltonian(mesh, V)
+    s = oparo.shift_from_potential(V)
+    A = (H - s * M).tocsr()
+    for k in range(4):
+        lam, U, _ = oparo.paro_step(H, M, A, 1.0 / A.diagonal(), lam, U, s,
+                                    1e-12, 10 * U.shape[0])
+        assert np.allclose(lam, r.lam_history[k + 1], rtol=1e-11, atol=0)
+
+
+def test_converged_scf_is_self_consistent():
+    w = small_molecule()
+    mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+    r = ks.scf(mesh, w.V, w.U0(), w.N, iterations=220, rtol=1e-12)
+    assert r.residual_history[-1] < 1e-8, r.residual_history[-5:]
+    # The last Hamiltonian was built from rho_in; its lowest eigenpairs are
+    # the final Ritz pairs.
+    H, M = fem.hamiltonian(mesh, r.V_eff)
+    lam_ref, _ = reference.dense_lowest(H, M, w.Nt)
+    assert np.allclose(r.lam[:w.N], lam_ref[:w.N], rtol=1e-10)
+    # and the output density equals the input density.
+    rho_out = ks.density(r.U, w.N)
+    assert np.linalg.norm(rho_out - r.rho_in) / np.linalg.norm(r.rho_in) \
+        < 1e-7
