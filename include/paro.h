@@ -198,6 +198,62 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
                      void* stream, paro_report_t* reports);
 
 /* ---------------------------------------------------------------------
+ * Kohn-Sham outer iteration (Sec. 2, eqs. (eq-ks), (weak-ks),
+ * (eq-operator-A); Algorithm 3.1).  The problem's potential becomes the
+ * effective potential V_ext + V_H(rho) + v_x(rho) of the mixed density
+ * rho = occupancy * sum_{i<=N} u_i^2 (interior vertices), V_H from the P1
+ * Poisson problem -Lap V_H = 4 pi rho with V_H = 0 on the boundary (solved
+ * by the library's Jacobi-PCG), v_x the Slater exchange -(3 rho/pi)^(1/3).
+ * Outer iteration n: density of U^(n); rho_in = that density at n = 0,
+ * else (1 - mixing) rho_in + mixing * density; V_eff; values-only
+ * re-assembly (shift recomputed unless sigma_mode = 1); one ParO step.
+ * --------------------------------------------------------------------- */
+typedef struct paro_ks_opts {
+  int32_t max_iter;       /* outer iterations at most                    */
+  int32_t poisson_maxit;  /* CG cap of the Hartree solve                 */
+  double mixing;          /* linear density mixing, (0, 1]               */
+  double occupancy;       /* electrons per orbital (2: spin-unpolarised) */
+  double scf_tol;         /* stop when ||rho_out - rho_in|| / ||rho_in||
+                             <= scf_tol and the problem's lambda_tol and
+                             resid_tol hold for the step                  */
+  double poisson_rtol;    /* relative CG tolerance of the Hartree solve  */
+} paro_ks_opts_t;
+
+typedef struct paro_ks_report {
+  int32_t status;         /* PARO_OK, PARO_ENOCONV (max_iter), or error  */
+  int32_t iterations;
+  int64_t paro_pcg_iters; /* CG iterations of the ParO steps              */
+  int64_t poisson_iters;  /* CG iterations of the Hartree solves          */
+  double residual;        /* last density residual                       */
+  double max_dlambda, max_resid, sigma;  /* of the last ParO step         */
+  double seconds;
+} paro_ks_report_t;
+
+void paro_ks_default_opts(paro_ks_opts_t* opts);
+
+/* Device workspace of paro_ks_solve for a box (Poisson operator, densities,
+ * potentials). */
+int paro_ks_query(const paro_box_t* box, size_t* workspace_bytes);
+
+/* Values-only re-assembly of a problem for a new nodal potential d_V (all
+ * (nx+1)(ny+1)(nz+1) vertices); the shift is recomputed as at assembly
+ * unless opts.sigma_mode = 1.  Synchronous (reads the potential's range). */
+int paro_update_potential(paro_problem* p, const double* d_V, void* stream);
+
+/* The problem's current shift. */
+double paro_sigma(const paro_problem* p);
+
+/* Self-consistent iteration from the start block d_U0 (n_dof x (N + m));
+ * d_Vext: the external potential at all vertices.  Outputs as paro_solve;
+ * d_rho (n_dof, nullable) receives the last input density.  Synchronous.
+ * Returns PARO_OK when converged, PARO_ENOCONV at max_iter (outputs and
+ * report filled). */
+int paro_ks_solve(paro_problem* p, const double* d_Vext,
+                  const paro_ks_opts_t* opts, void* d_ks_ws, size_t bytes,
+                  const double* d_U0, double* d_lambda, double* d_U,
+                  double* d_rho, void* stream, paro_ks_report_t* report);
+
+/* ---------------------------------------------------------------------
  * Serving: a request loop with continuous batching (not in the paper).
  * Requests (box, nodal potential, options, start orbitals, all on the
  * host) queue at submit; each tick admits queued requests in arrival

@@ -11,6 +11,8 @@ from .binding import (  # noqa: F401
     paro_pcg, paro_query, paro_set_timing, paro_get_timing, Timing,
     paro_small_geneig, paro_solve, paro_spmm, paro_step, Batch,
     paro_batch_init, paro_batch_step, paro_batch_solve, Server, ServerStats,
+    KsOpts, KsReport, ks_default_opts, paro_update_potential, paro_sigma,
+    paro_ks_solve,
     PARO_OK, PARO_EINVAL, PARO_ENOMEM, PARO_ENOTSPD, PARO_ESINGULAR,
     PARO_ENOCONV, PARO_EDEVICE, PARO_FP64, PARO_FP32_INNER,
 )

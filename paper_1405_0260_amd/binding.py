@@ -77,6 +77,22 @@ class ServerStats(ctypes.Structure):
                 ("arena_bytes", ctypes.c_size_t), ("ticks", c_i64)]
 
 
+class KsOpts(ctypes.Structure):
+    _fields_ = [("max_iter", c_i32), ("poisson_maxit", c_i32),
+                ("mixing", c_dbl), ("occupancy", c_dbl), ("scf_tol", c_dbl),
+                ("poisson_rtol", c_dbl)]
+
+
+class KsReport(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("iterations", c_i32),
+                ("paro_pcg_iters", c_i64), ("poisson_iters", c_i64),
+                ("residual", c_dbl), ("max_dlambda", c_dbl),
+                ("max_resid", c_dbl), ("sigma", c_dbl), ("seconds", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ParoError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"paro error {code}: {msg}")
@@ -142,6 +158,14 @@ def lib():
                                      ctypes.POINTER(ServerStats)]),
         "paro_server_report": (c_i32, [P, c_i64, ctypes.POINTER(Report)]),
         "paro_server_destroy": (None, [P]),
+        "paro_ks_default_opts": (None, [ctypes.POINTER(KsOpts)]),
+        "paro_ks_query": (c_i32, [ctypes.POINTER(Box),
+                                  ctypes.POINTER(ctypes.c_size_t)]),
+        "paro_update_potential": (c_i32, [P, P, P]),
+        "paro_sigma": (c_dbl, [P]),
+        "paro_ks_solve": (c_i32, [P, P, ctypes.POINTER(KsOpts), P,
+                                  ctypes.c_size_t, P, P, P, P, P,
+                                  ctypes.POINTER(KsReport)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -476,3 +500,52 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- Kohn-Sham
+
+def ks_default_opts(**kw) -> KsOpts:
+    o = KsOpts()
+    lib().paro_ks_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def paro_update_potential(p: Problem, V, stream=None):
+    _f64(V, ((p.box.nx + 1) * (p.box.ny + 1) * (p.box.nz + 1),), "V")
+    _check(lib().paro_update_potential(p.handle, _ptr(V), _stream(stream)))
+
+
+def paro_sigma(p: Problem) -> float:
+    return lib().paro_sigma(p.handle)
+
+
+def paro_ks_solve(p: Problem, Vext, U0, lam, U, opts: KsOpts = None,
+                  rho=None, stream=None, workspace=None) -> KsReport:
+    """Kohn-Sham outer iteration (see paro_ks_solve in include/paro.h);
+    returns the report (status PARO_ENOCONV if max_iter was reached)."""
+    import torch
+    opts = opts or ks_default_opts()
+    _f64(Vext, ((p.box.nx + 1) * (p.box.ny + 1) * (p.box.nz + 1),), "Vext")
+    _f64(U0, (p.n, p.Nt), "U0")
+    _f64(U, (p.n, p.Nt), "U")
+    _f64(lam, (p.Nt,), "lambda")
+    if rho is not None:
+        _f64(rho, (p.n,), "rho")
+    nbytes = ctypes.c_size_t()
+    _check(lib().paro_ks_query(ctypes.byref(p.box), ctypes.byref(nbytes)))
+    if workspace is None:
+        workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8,
+                                device=U.device)
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    rep = KsReport()
+    _check(lib().paro_ks_solve(p.handle, _ptr(Vext), ctypes.byref(opts),
+                               base + off, workspace.numel() - off, _ptr(U0),
+                               _ptr(lam), _ptr(U), _ptr(rho), _stream(stream),
+                               ctypes.byref(rep)),
+           allow=(PARO_ENOCONV,))
+    return rep

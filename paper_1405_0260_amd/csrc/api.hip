@@ -16,10 +16,6 @@
 
 #include "paro_internal.h"
 
-struct paro_problem {
-  paro::Problem p;
-};
-
 namespace paro {
 
 // Host-side event timing of kernel launches (measurement only).  The
@@ -776,6 +772,34 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
          p.opts.max_steps);
   return code;
 }
+
+int paro_update_potential(paro_problem* h, const double* d_V, void* stream) {
+  try {
+    if (!h || !d_V) return fail(PARO_EINVAL, "NULL argument");
+    Problem& p = h->p;
+    hipStream_t s = (hipStream_t)stream;
+    p.last_stream = s;
+    const int64_t nv =
+        (int64_t)(p.box.nx + 1) * (p.box.ny + 1) * (p.box.nz + 1);
+    HIP_OR_FAIL(
+        launch_potential_range(d_V, nv, p.vmin, p.cnt + kCntMin, p.part, s));
+    double rng[3];
+    HIP_OR_FAIL(hipMemcpyAsync(rng, p.vmin, sizeof rng, hipMemcpyDeviceToHost,
+                               s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (rng[2] != 0.0)
+      return fail(PARO_EINVAL, "potential has %.0f non-finite values",
+                  rng[2]);
+    if (p.opts.sigma_mode != 1) p.sigma = rng[0] >= 0.0 ? 0.0 : rng[0] - 1.0;
+    HIP_OR_FAIL(launch_assemble(p, d_V, s));
+    p.hd.sigma = p.sigma;
+    return PARO_OK;
+  } catch (...) {
+    return fail(PARO_EDEVICE, "unexpected exception in paro_update_potential");
+  }
+}
+
+double paro_sigma(const paro_problem* h) { return h ? h->p.sigma : 0.0; }
 
 void paro_destroy(paro_problem* h) {
   if (!h) return;

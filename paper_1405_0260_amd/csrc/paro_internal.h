@@ -276,3 +276,8 @@ hipError_t launch_small_geneig(const double* A, const double* B, int n,
                                hipStream_t s);
 
 }  // namespace paro
+
+// The opaque handle of the C ABI: host metadata of one assembled problem.
+struct paro_problem {
+  paro::Problem p;
+};
