@@ -245,13 +245,16 @@ double paro_sigma(const paro_problem* p);
 
 /* Self-consistent iteration from the start block d_U0 (n_dof x (N + m));
  * d_Vext: the external potential at all vertices.  Outputs as paro_solve;
- * d_rho (n_dof, nullable) receives the last input density.  Synchronous.
+ * d_rho (n_dof, nullable) receives the last input density; h_history
+ * (host, max_iter values, nullable) the density residual of every outer
+ * iteration (0 for the first, which has none).  Synchronous.
  * Returns PARO_OK when converged, PARO_ENOCONV at max_iter (outputs and
  * report filled). */
 int paro_ks_solve(paro_problem* p, const double* d_Vext,
                   const paro_ks_opts_t* opts, void* d_ks_ws, size_t bytes,
                   const double* d_U0, double* d_lambda, double* d_U,
-                  double* d_rho, void* stream, paro_ks_report_t* report);
+                  double* d_rho, double* h_history, void* stream,
+                  paro_ks_report_t* report);
 
 /* ---------------------------------------------------------------------
  * Serving: a request loop with continuous batching (not in the paper).

@@ -164,7 +164,7 @@ def lib():
         "paro_update_potential": (c_i32, [P, P, P]),
         "paro_sigma": (c_dbl, [P]),
         "paro_ks_solve": (c_i32, [P, P, ctypes.POINTER(KsOpts), P,
-                                  ctypes.c_size_t, P, P, P, P, P,
+                                  ctypes.c_size_t, P, P, P, P, P, P,
                                   ctypes.POINTER(KsReport)]),
     }
     for name, (res, args) in sig.items():
@@ -524,9 +524,12 @@ def paro_sigma(p: Problem) -> float:
 
 
 def paro_ks_solve(p: Problem, Vext, U0, lam, U, opts: KsOpts = None,
-                  rho=None, stream=None, workspace=None) -> KsReport:
+                  rho=None, stream=None, workspace=None, history=None):
     """Kohn-Sham outer iteration (see paro_ks_solve in include/paro.h);
-    returns the report (status PARO_ENOCONV if max_iter was reached)."""
+    returns the report (status PARO_ENOCONV if max_iter was reached).
+    history: optional float64 numpy array of max_iter values that receives
+    the density residual of every outer iteration."""
+    import numpy as np
     import torch
     opts = opts or ks_default_opts()
     _f64(Vext, ((p.box.nx + 1) * (p.box.ny + 1) * (p.box.nz + 1),), "Vext")
@@ -543,9 +546,16 @@ def paro_ks_solve(p: Problem, Vext, U0, lam, U, opts: KsOpts = None,
     base = workspace.data_ptr()
     off = (-base) % 256
     rep = KsReport()
+    hptr = None
+    if history is not None:
+        if not (isinstance(history, np.ndarray) and history.dtype ==
+                np.float64 and history.size >= opts.max_iter and
+                history.flags.c_contiguous):
+            raise ValueError("history: contiguous float64, max_iter values")
+        hptr = history.ctypes.data
     _check(lib().paro_ks_solve(p.handle, _ptr(Vext), ctypes.byref(opts),
                                base + off, workspace.numel() - off, _ptr(U0),
-                               _ptr(lam), _ptr(U), _ptr(rho), _stream(stream),
-                               ctypes.byref(rep)),
+                               _ptr(lam), _ptr(U), _ptr(rho), hptr,
+                               _stream(stream), ctypes.byref(rep)),
            allow=(PARO_ENOCONV,))
     return rep

@@ -216,7 +216,8 @@ int paro_ks_query(const paro_box_t* box, size_t* workspace_bytes) {
 int paro_ks_solve(paro_problem* p, const double* d_Vext,
                   const paro_ks_opts_t* kopt, void* d_ws, size_t bytes,
                   const double* d_U0, double* d_lambda, double* d_U,
-                  double* d_rho, void* stream, paro_ks_report_t* report) {
+                  double* d_rho, double* h_history, void* stream,
+                  paro_ks_report_t* report) {
   try {
     if (!p || !d_Vext || !kopt || !d_ws || !d_U0 || !d_lambda || !d_U)
       return set_error(PARO_EINVAL, "NULL argument to paro_ks_solve");
@@ -268,6 +269,7 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
     const auto t0 = std::chrono::steady_clock::now();
     const int gd = grid_for(n);
     const int gv = grid_for((long long)nv);
+    if (h_history) h_history[0] = 0.0;
     for (int it = 0; it < kopt->max_iter; ++it) {
       // Density of the current orbitals, residual, mixing.
       hipLaunchKernelGGL(ks_density_kernel, dim3(gd), dim3(kBlock), 0, s,
@@ -310,6 +312,7 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
       rep.sigma = r.sigma;
       if (it > 0) {
         rep.residual = hres[1] > 0.0 ? std::sqrt(hres[0] / hres[1]) : 0.0;
+        if (h_history) h_history[it] = rep.residual;
         if (rep.residual <= kopt->scf_tol && r.max_dlambda <= eig.lambda_tol &&
             r.max_resid <= eig.resid_tol) {
           rep.status = PARO_OK;
