@@ -151,6 +151,9 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.valA32 = L.valA32 ? (float*)at(L.valA32) : nullptr;
   p.dinv = (double*)at(L.dinv);
   p.dinv32 = L.dinv32 ? (float*)at(L.dinv32) : nullptr;
+  p.diagA = (double*)at(L.diagA);
+  p.diagM = (double*)at(L.diagM);
+  p.diagA32 = L.diagA32 ? (float*)at(L.diagA32) : nullptr;
   p.X = (double*)at(L.X);
   p.R = (double*)at(L.R);
   p.P = (double*)at(L.P);
@@ -211,6 +214,12 @@ void desc_init(Problem& p) {
   d.valA32 = p.valA32;
   d.dinv = p.dinv;
   d.dinv32 = p.dinv32;
+  d.diagA = p.diagA;
+  d.diagM = p.diagM;
+  d.diagA32 = p.diagA32;
+  d.mx = p.mx;
+  d.my = p.my;
+  d.mz = p.mz;
   d.X = d.Uout = p.X;
   d.U0 = p.X;
   d.R = p.R;
@@ -528,6 +537,9 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.valA32 = f32 ? take(sizeof(float) * nnz) : 0;
   L.dinv = take(sizeof(double) * n);
   L.dinv32 = f32 ? take(sizeof(float) * n) : 0;
+  L.diagA = take(sizeof(double) * kStencil * n);
+  L.diagM = take(sizeof(double) * kStencil * n);
+  L.diagA32 = f32 ? take(sizeof(float) * kStencil * n) : 0;
   L.X = take(sizeof(double) * blk);
   L.R = take(sizeof(double) * blk);
   L.P = take(sizeof(double) * blk);

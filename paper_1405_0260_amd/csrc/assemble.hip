@@ -8,6 +8,10 @@
 // matrix row (one interior vertex) and sums the contributions of the 24
 // tetrahedra around it in a fixed order: no atomics, bitwise reproducible.
 //
+// Besides CSR, every value is also written in stencil order: diag[s][d] is
+// the coefficient of row d and neighbour offset s (0 when the neighbour is
+// outside the box), the layout the solver kernels stream.
+//
 // Pattern: every edge of a Kuhn tetrahedron is a multiple-free difference
 // of e_x, e_y, e_z, e_i + e_j or (1,1,1), so a row couples its vertex to at
 // most 15 vertices (itself included), listed in ascending column order in
@@ -105,7 +109,8 @@ assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
                 int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
                 double* __restrict__ valA, double* __restrict__ valM,
                 float* __restrict__ valA32, double* __restrict__ dinv,
-                float* __restrict__ dinv32) {
+                float* __restrict__ dinv32, double* __restrict__ diagA,
+                double* __restrict__ diagM, float* __restrict__ diagA32) {
   const long long n = (long long)mx * my * mz;
   const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (d > n) return;
@@ -144,7 +149,13 @@ assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
   int slot = (int)start;
   for (int s = 0; s < kStencil; ++s) {
     const int ox = kOff[s][0], oy = kOff[s][1], oz = kOff[s][2];
-    if (!valid(i, ox, mx) || !valid(j, oy, my) || !valid(k, oz, mz)) continue;
+    if (!valid(i, ox, mx) || !valid(j, oy, my) || !valid(k, oz, mz)) {
+      // Stencil order: a neighbour outside the box has coefficient 0.
+      diagA[(size_t)s * n + d] = 0.0;
+      diagM[(size_t)s * n + d] = 0.0;
+      if (diagA32) diagA32[(size_t)s * n + d] = 0.0f;
+      continue;
+    }
     double a_sum = 0.0, m_sum = 0.0;
     for (int e = inc.first[s]; e < inc.first[s + 1]; ++e) {
       const int c = inc.corner[e], q = inc.perm[e];
@@ -207,6 +218,9 @@ assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
     valA[slot] = a_sum;
     valM[slot] = m_sum;
     if (valA32) valA32[slot] = (float)a_sum;
+    diagA[(size_t)s * n + d] = a_sum;
+    diagM[(size_t)s * n + d] = m_sum;
+    if (diagA32) diagA32[(size_t)s * n + d] = (float)a_sum;
     if (ox == 0 && oy == 0 && oz == 0) {
       dinv[d] = 1.0 / a_sum;
       if (dinv32) dinv32[d] = (float)(1.0 / a_sum);
@@ -288,7 +302,7 @@ hipError_t launch_assemble(Problem& p, const double* V, hipStream_t s) {
   hipLaunchKernelGGL(assemble_kernel, dim3(grid), dim3(kBlock), 0, s, inc, V,
                      p.mx, p.my, p.mz, p.h[0], p.h[1], p.h[2], p.sigma,
                      p.rowptr, p.col, p.valA, p.valM, p.valA32, p.dinv,
-                     p.dinv32);
+                     p.dinv32, p.diagA, p.diagM, p.diagA32);
   return hipGetLastError();
 }
 

@@ -111,6 +111,10 @@ struct Desc {
   const float* valA32;
   const double* dinv;
   const float* dinv32;
+  const double* diagA;    // stencil order: [kStencil][n], 0 outside the box
+  const double* diagM;
+  const float* diagA32;
+  int mx, my, mz, pad0;   // interior vertices per axis (rows = mx my mz)
   const double* U0;       // start of the source solves (x0), gathered
   const double* Bin;      // given right-hand sides, or null
   double* lam;            // Ritz values (in: previous, out: new), or null
@@ -191,6 +195,9 @@ struct Problem {
   float* valA32;          // FP32 copy of A_s
   double* dinv;           // 1 / diag(A_s)
   float* dinv32;
+  double* diagA;          // A_s, M (and FP32 A_s) in stencil order
+  double* diagM;
+  float* diagA32;
   double* X;              // n x Nt blocks (FP64)
   double* R;
   double* P;
@@ -229,7 +236,8 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 
 // Workspace layout: byte offsets of every region for a problem shape.
 struct Layout {
-  size_t rowptr, col, valA, valM, valA32, dinv, dinv32;
+  size_t rowptr, col, valA, valM, valA32, dinv, dinv32, diagA, diagM,
+      diagA32;
   size_t X, R, P, Q, B, R32, P32, Q32, X32;
   size_t part, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt, flag;
   size_t desc, poll, report;

@@ -171,83 +171,6 @@ __device__ __forceinline__ void atomic_max_nonneg(double* dst, double v) {
             (unsigned long long)__double_as_longlong(v));
 }
 
-// LDS view of one CSR tile: row pointers (tile-relative), columns and up
-// to two value arrays, each region 16-byte aligned.
-template <typename TM>
-struct CsrTile {
-  int32_t* rp;
-  int32_t* col;
-  TM* a;
-  TM* b;
-};
-
-__host__ __device__ constexpr size_t align16(size_t x) {
-  return (x + 15) & ~size_t(15);
-}
-
-// LDS bytes for a tile of tr rows with nvals value arrays.
-__host__ __device__ constexpr size_t csr_tile_bytes(int tr, size_t vsize,
-                                                    int nvals) {
-  return align16(sizeof(int32_t) * (tr + 1)) +
-         align16(sizeof(int32_t) * tr * kStencil) +
-         nvals * align16(vsize * tr * kStencil);
-}
-
-template <typename TM>
-__device__ __forceinline__ CsrTile<TM> csr_tile(unsigned char* smem, int tr,
-                                                int nvals) {
-  CsrTile<TM> t;
-  size_t o = 0;
-  t.rp = reinterpret_cast<int32_t*>(smem + o);
-  o += align16(sizeof(int32_t) * (tr + 1));
-  t.col = reinterpret_cast<int32_t*>(smem + o);
-  o += align16(sizeof(int32_t) * tr * kStencil);
-  t.a = reinterpret_cast<TM*>(smem + o);
-  o += align16(sizeof(TM) * tr * kStencil);
-  t.b = nvals > 1 ? reinterpret_cast<TM*>(smem + o) : nullptr;
-  return t;
-}
-
-// Stage rows [r0, r1) of the CSR into the tile with coalesced loads (up to
-// four entries per thread in flight); row pointers become tile-relative.
-// All threads of the block must call it.
-template <typename TM>
-__device__ __forceinline__ void stage_csr(const int32_t* __restrict__ rowptr,
-                                          const int32_t* __restrict__ col,
-                                          const TM* __restrict__ va,
-                                          const TM* __restrict__ vb,
-                                          long long r0, long long r1,
-                                          CsrTile<TM>& t) {
-  const int rows = (int)(r1 - r0);
-  const int k0 = ldg(rowptr + r0), cnt = ldg(rowptr + r1) - k0;
-  __syncthreads();  // the previous tile is no longer read
-  for (int i = threadIdx.x; i <= rows; i += kBlock)
-    t.rp[i] = ldg(rowptr + r0 + i) - k0;
-  for (int e0 = threadIdx.x; e0 < cnt; e0 += 4 * kBlock) {
-    int c[4];
-    TM a[4], b[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = e0 + k * kBlock;
-      if (e < cnt) {
-        c[k] = ldg(col + k0 + e);
-        a[k] = ldg(va + k0 + e);
-        b[k] = vb ? ldg(vb + k0 + e) : TM(0);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = e0 + k * kBlock;
-      if (e < cnt) {
-        t.col[e] = c[k];
-        t.a[e] = a[k];
-        if (vb) t.b[e] = b[k];
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // Whether any of the V columns of chunk ch is set in act (loads issued
 // together: out-of-range columns read the last column and are masked).
 __device__ __forceinline__ bool chunk_active(const int* act, int ch, int V,
@@ -261,38 +184,102 @@ __device__ __forceinline__ bool chunk_active(const int* act, int ch, int V,
   return a != 0;
 }
 
-// Row product over a staged CSR tile: y1 += a_e X[col_e] (and y2 += b_e
-// X[col_e] if TWO) over the entries e of [rs, re) in order, with kGather
-// neighbour rows in flight.  Slots past the row end reload its last
-// column with zero weight (a valid address; the terms add exact zeros).
-#ifndef PARO_KGATHER
-#define PARO_KGATHER 8
-#endif
-constexpr int kGather = PARO_KGATHER;
-template <typename T, typename TM, int V, bool TWO>
-__device__ __forceinline__ void row_product(const CsrTile<TM>& tl, int rs,
-                                            int re, const T* X, int ncols,
-                                            int off, T (&y1)[V],
-                                            T (&y2)[V]) {
-  for (int e0 = rs; e0 < re; e0 += kGather) {
-    T x[kGather][V];
-    TM a[kGather], b[kGather];
+// The 15-point Kuhn stencil: neighbour offsets (x, y, z) in ascending
+// linear order (x fastest); offset 7 is the row itself.
+__host__ __device__ constexpr int st_off(int s, int a) {
+  constexpr int t[kStencil][3] = {
+      {-1, -1, -1}, {0, -1, -1}, {-1, 0, -1}, {0, 0, -1}, {-1, -1, 0},
+      {0, -1, 0},   {-1, 0, 0},  {0, 0, 0},   {1, 0, 0},  {0, 1, 0},
+      {1, 1, 0},    {0, 0, 1},   {1, 0, 1},   {0, 1, 1},  {1, 1, 1}};
+  return t[s][a];
+}
+constexpr int kSelf = 7;
+
+
+// Stencil product of one row (interior vertex (i, j, k) of an mx x my x mz
+// grid): y1 += a_s X[row + off_s] (and y2 += b_s X[row + off_s] if TWO)
+// over the 15 offsets in ascending order, the gathers issued in groups of
+// G (more overlap against more registers).  wa, wb: the row's first
+// coefficient, either in a staged LDS tile (STAGED, stride tr) or in the
+// stencil-order matrix itself (stride n); a coefficient is 0 where the
+// neighbour lies outside the box, whose slot then reads the row itself.
+// self receives X[row].
+template <typename T, typename TM, int V, bool TWO, int G, bool STAGED>
+__device__ __forceinline__ void stencil_product(
+    const TM* __restrict__ wa, const TM* __restrict__ wb, long long stride,
+    int mx, int my, int mz, long long row, const T* X, int ncols, int off,
+    T (&y1)[V], T (&y2)[V], T (&self)[V]) {
+  const unsigned r = (unsigned)row;
+  const unsigned q = r / (unsigned)mx;
+  const int i = (int)(r - q * (unsigned)mx);
+  const unsigned k = q / (unsigned)my;
+  const int j = (int)(q - k * (unsigned)my);
+  // Row base; neighbour steps are uniform offsets from it.
+  const T* xr = X + (size_t)row * ncols + off;
 #pragma unroll
-    for (int k = 0; k < kGather; ++k) {
-      const bool in = e0 + k < re;
-      const int e = in ? e0 + k : re - 1;
-      ldv<T, V>(X + (size_t)tl.col[e] * ncols + off, x[k]);
-      a[k] = in ? tl.a[e] : TM(0);
-      if (TWO) b[k] = in ? tl.b[e] : TM(0);
+  for (int s0 = 0; s0 < kStencil; s0 += G) {
+    T x[G][V];
+    TM a[G], b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int s = s0 + g;
+      if (s >= kStencil) break;
+      const int ox = st_off(s, 0), oy = st_off(s, 1), oz = st_off(s, 2);
+      const bool ok = (unsigned)(i + ox) < (unsigned)mx &&
+                      (unsigned)(j + oy) < (unsigned)my &&
+                      (unsigned)((int)k + oz) < (unsigned)mz;
+      const int step = (ox + mx * (oy + my * oz)) * ncols;
+      ldv<T, V>(xr + (ok ? step : 0), x[g]);
+      if (STAGED) {
+        a[g] = wa[s * stride];
+        if (TWO) b[g] = wb[s * stride];
+      } else {
+        a[g] = ldg(wa + (size_t)s * stride);
+        if (TWO) b[g] = ldg(wb + (size_t)s * stride);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < kGather; ++k)
+    for (int g = 0; g < G; ++g) {
+      const int s = s0 + g;
+      if (s >= kStencil) break;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        y1[v] = fma((T)a[k], x[k][v], y1[v]);
-        if (TWO) y2[v] = fma((T)b[k], x[k][v], y2[v]);
+        y1[v] = fma((T)a[g], x[g][v], y1[v]);
+        if (TWO) y2[v] = fma((T)b[g], x[g][v], y2[v]);
       }
+      if (s == kSelf) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) self[v] = x[g][v];
+      }
+    }
+    // Keep the groups apart: the next group's loads are not hoisted above
+    // this group's arithmetic (bounds the registers in flight).
+    if (G < kStencil) __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// Stage the stencil-order coefficients of rows [r0, r0 + rows) into LDS,
+// w[s * tr + (row - r0)], with coalesced loads.  All threads of the block
+// call it; the first barrier protects the previous tile.
+template <typename TM, bool TWO>
+__device__ __forceinline__ void stage_weights(const TM* __restrict__ da,
+                                              const TM* __restrict__ db,
+                                              long long n, long long r0,
+                                              int rows, int tr,
+                                              TM* __restrict__ wa,
+                                              TM* __restrict__ wb) {
+  __syncthreads();
+  for (int e = threadIdx.x; e < kStencil * rows; e += kBlock) {
+    const int s = e / rows, lr = e - s * rows;
+    wa[s * tr + lr] = ldg(da + (size_t)s * n + r0 + lr);
+    if (TWO) wb[s * tr + lr] = ldg(db + (size_t)s * n + r0 + lr);
+  }
+  __syncthreads();
+}
+
+// LDS bytes of a staged coefficient tile (tr rows, nmat matrices).
+constexpr size_t weights_bytes(int tr, size_t vsize, int nmat) {
+  return (size_t)kStencil * tr * vsize * nmat;
 }
 
 // Thread geometry of virtual block vb of a problem's streaming kernel.
@@ -351,21 +338,25 @@ template <typename T>
 struct CgVecs;
 template <>
 struct CgVecs<double> {
-  const double* val;
+  const double* diag;
   const double* dinv;
   double *X, *R, *P, *Q;
   __device__ CgVecs(const Desc& d)
-      : val(d.valA), dinv(d.dinv), X(d.X), R(d.R), P(d.P), Q(d.Q) {}
+      : diag(d.diagA), dinv(d.dinv), X(d.X), R(d.R), P(d.P), Q(d.Q) {}
 };
 template <>
 struct CgVecs<float> {
-  const float* val;
+  const float* diag;
   const float* dinv;
   float *X, *R, *P, *Q;
   __device__ CgVecs(const Desc& d)
-      : val(d.valA32), dinv(d.dinv32), X(d.X32), R(d.R32), P(d.P32),
+      : diag(d.diagA32), dinv(d.dinv32), X(d.X32), R(d.R32), P(d.P32),
         Q(d.Q32) {}
 };
+
+// Whether the CG SpMM stages its coefficients in LDS (per precision).
+template <typename T>
+constexpr bool kStageCg = sizeof(T) == 8;
 
 // ------------------------------------------------------------------------
 // CG iteration: Q = A P on the active columns, with per-column p . q.
@@ -380,31 +371,37 @@ __device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
   const bool mine = chunk_active(d.cs->act[par], g.ch, V, ncols);
   if (nact == 0) return;
   const CgVecs<T> vs(d);
-  extern __shared__ unsigned char smem[];
-  CsrTile<T> tl = csr_tile<T>(smem, g.tr, 1);
   const bool on = g.lr < g.tr && mine;
+  extern __shared__ unsigned char smem[];
+  T* wa = reinterpret_cast<T*>(smem);
   double acc[1][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
   for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
        w.t += w.step) {
     const long long r0 = w.t * g.tr;
-    const long long r1 = min(d.n, r0 + g.tr);
-    stage_csr<T>(d.rowptr, d.col, vs.val, nullptr, r0, r1, tl);
+    const int rows = (int)min((long long)g.tr, d.n - r0);
+    // FP64: coefficients staged per tile; FP32: read directly (measured
+    // faster: no barrier per tile).
+    if (kStageCg<T>)
+      stage_weights<T, false>(vs.diag, nullptr, d.n, r0, rows, g.tr, wa,
+                              nullptr);
+    if (!on || g.lr >= rows) continue;
     const long long row = r0 + g.lr;
-    if (on && row < r1) {
-      const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
-      T q[V], unused[V];
+    T q[V], unused[V], po[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) q[v] = T(0);
-      row_product<T, T, V, false>(tl, rs, re, vs.P, ncols, g.ch * V, q,
-                                  unused);
-      stv<T, V>(vs.Q + (size_t)row * ncols + g.ch * V, q);
-      T po[V];
-      ldv<T, V>(vs.P + (size_t)row * ncols + g.ch * V, po);
+    for (int v = 0; v < V; ++v) q[v] = T(0);
+    if (kStageCg<T>)
+      stencil_product<T, T, V, false, kStencil, true>(
+          wa + g.lr, nullptr, g.tr, d.mx, d.my, d.mz, row, vs.P, ncols,
+          g.ch * V, q, unused, po);
+    else
+      stencil_product<T, T, V, false, kStencil, false>(
+          vs.diag + row, nullptr, d.n, d.mx, d.my, d.mz, row, vs.P, ncols,
+          g.ch * V, q, unused, po);
+    stv<T, V>(vs.Q + (size_t)row * ncols + g.ch * V, q);
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[0][v] += (double)po[v] * (double)q[v];
-    }
+    for (int v = 0; v < V; ++v) acc[0][v] += (double)po[v] * (double)q[v];
   }
   block_partials<V, 1>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
 }
@@ -626,29 +623,30 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
     const int c = g.ch * V + v;
     sh[v] = (d.lam && c < ncols) ? d.lam[c] - d.sigma : 0.0;
   }
-  extern __shared__ unsigned char smem[];
-  CsrTile<double> tl = csr_tile<double>(smem, g.tr, 2);
   double acc[3][V];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
+  extern __shared__ unsigned char smem[];
+  double* wa = reinterpret_cast<double*>(smem);
+  double* wb = wa + kStencil * g.tr;
   for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
        w.t += w.step) {
     const long long r0 = w.t * g.tr;
-    const long long r1 = min(d.n, r0 + g.tr);
-    stage_csr<double>(d.rowptr, d.col, d.valA, d.valM, r0, r1, tl);
+    const int rows = (int)min((long long)g.tr, d.n - r0);
+    stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
+                                wb);
+    if (g.lr >= rows) continue;
     const long long row = r0 + g.lr;
-    if (g.lr >= g.tr || row >= r1) continue;
-    double au[V], mu[V];
+    double au[V], mu[V], u[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
-    const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
-    row_product<double, double, V, true>(tl, rs, re, U, ncols, g.ch * V, au,
-                                         mu);
+    stencil_product<double, double, V, true, 8, true>(
+        wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
+        g.ch * V, au, mu, u);
     const size_t o = (size_t)row * ncols + g.ch * V;
-    double b[V], r[V], p[V], u[V];
-    ldv<double, V>(U + o, u);
+    double b[V], r[V], p[V];
     if (d.Bin) {
       ldv<double, V>(d.Bin + o, b);
     } else {
@@ -733,25 +731,25 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
     cs->n_outer = 0;
     cs->cg_mark = cs->cg_iters;
   }
-  extern __shared__ unsigned char smem[];
-  CsrTile<double> tl = csr_tile<double>(smem, g.tr, 1);
   double acc[2][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
+  extern __shared__ unsigned char smem[];
+  double* wa = reinterpret_cast<double*>(smem);
   for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
        w.t += w.step) {
     const long long r0 = w.t * g.tr;
-    const long long r1 = min(d.n, r0 + g.tr);
-    stage_csr<double>(d.rowptr, d.col, d.valA, nullptr, r0, r1, tl);
+    const int rows = (int)min((long long)g.tr, d.n - r0);
+    stage_weights<double, false>(d.diagA, nullptr, d.n, r0, rows, g.tr, wa,
+                                 nullptr);
+    if (!on || g.lr >= rows) continue;
     const long long row = r0 + g.lr;
-    if (!on || row >= r1) continue;
-    double ax[V];
+    double ax[V], unused[V], self[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ax[v] = 0.0;
-    const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
-    double unused[V];
-    row_product<double, double, V, false>(tl, rs, re, d.X, ncols, g.ch * V,
-                                          ax, unused);
+    stencil_product<double, double, V, false, kStencil, true>(
+        wa + g.lr, nullptr, g.tr, d.mx, d.my, d.mz, row, d.X, ncols,
+        g.ch * V, ax, unused, self);
     const size_t o = (size_t)row * ncols + g.ch * V;
     double b[V];
     ldv<double, V>(d.B + o, b);
@@ -921,28 +919,36 @@ __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
   const bool needA = Y1 != nullptr;
   const bool needM = Y2 != nullptr || s1 != 0.0;
   extern __shared__ unsigned char smem[];
-  CsrTile<double> tl = csr_tile<double>(smem, g.tr, 2);
+  double* wa = reinterpret_cast<double*>(smem);
+  double* wb = wa + kStencil * g.tr;
+  const bool two = needA && needM;
   for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
        w.t += w.step) {
     const long long r0 = w.t * g.tr;
-    const long long r1 = min(d.n, r0 + g.tr);
-    stage_csr<double>(d.rowptr, d.col, needA ? d.valA : d.valM,
-                      (needA && needM) ? d.valM : nullptr, r0, r1, tl);
+    const int rows = (int)min((long long)g.tr, d.n - r0);
+    if (two)
+      stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
+                                  wb);
+    else
+      stage_weights<double, false>(needA ? d.diagA : d.diagM, nullptr, d.n,
+                                   r0, rows, g.tr, wa, nullptr);
+    if (g.lr >= rows) continue;
     const long long row = r0 + g.lr;
-    if (g.lr >= g.tr || row >= r1) continue;
-    double ax[V], mx[V];
+    double ax[V], mx[V], self[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ax[v] = mx[v] = 0.0;
-    const int rs = tl.rp[g.lr], re = tl.rp[g.lr + 1];
-    if (needA && needM)
-      row_product<double, double, V, true>(tl, rs, re, X, ncols, g.ch * V,
-                                           ax, mx);
+    if (two)
+      stencil_product<double, double, V, true, 8, true>(
+          wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, X, ncols,
+          g.ch * V, ax, mx, self);
     else if (needA)
-      row_product<double, double, V, false>(tl, rs, re, X, ncols, g.ch * V,
-                                            ax, mx);
+      stencil_product<double, double, V, false, 8, true>(
+          wa + g.lr, nullptr, g.tr, d.mx, d.my, d.mz, row, X, ncols,
+          g.ch * V, ax, mx, self);
     else
-      row_product<double, double, V, false>(tl, rs, re, X, ncols, g.ch * V,
-                                            mx, ax);
+      stencil_product<double, double, V, false, 8, true>(
+          wa + g.lr, nullptr, g.tr, d.mx, d.my, d.mz, row, X, ncols,
+          g.ch * V, mx, ax, self);
     const size_t o = (size_t)row * ncols + g.ch * V;
     if (Y1) {
       double y[V];
@@ -1133,7 +1139,8 @@ gram_scatter_kernel(const Desc* __restrict__ D, int sym) {
 // Small generalised eigenproblem A c = theta B c (Step 4's N_t x N_t
 // problem), one workgroup, FP64, everything in LDS.
 //   1. B = L L^T (Cholesky);  2. S = L^{-1} A L^{-T};  3. cyclic Jacobi on
-//   S with round-robin ordering (N_t/2 disjoint rotations per round);
+//   S with round-robin ordering (N_t/2 disjoint rotations per round,
+//   applied as independent 2 x 2 blocks: two barriers per round);
 //   4. theta ascending (ties by index);  5. C = L^{-T} Y;  6. signs.
 // ------------------------------------------------------------------------
 constexpr int kLd = kNtMax + 1;
@@ -1148,7 +1155,7 @@ __device__ void geneig_body(const double* __restrict__ Ain,
   __shared__ double L[kNtMax][kLd];
   __shared__ double Y[kNtMax][kLd];
   __shared__ double rc[kNtMax / 2], rs[kNtMax / 2];
-  __shared__ int rp[kNtMax / 2], rq[kNtMax / 2];
+  __shared__ int rp[kNtMax / 2], rq[kNtMax / 2], rr[kNtMax / 2];
   __shared__ double red[kBlock];
   __shared__ int s_info;
   __shared__ int perm[kNtMax];
@@ -1267,7 +1274,7 @@ __device__ void geneig_body(const double* __restrict__ Ain,
         const int b0 = 1 + ((nn - 2 - tid + round) % (nn - 1));
         const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
         double c = 1.0, sn = 0.0;
-        bool rot = false;
+        int rot = 0;
         if (q < n) {
           const double apq = A[p][q];
           if (fabs(apq) > skip) {
@@ -1276,46 +1283,43 @@ __device__ void geneig_body(const double* __restrict__ Ain,
                              (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             sn = t * c;
-            rot = true;
+            rot = 1;
             s_rot = 1;
           }
         }
         rc[tid] = c;
         rs[tid] = sn;
         rp[tid] = p;
-        rq[tid] = rot ? q : p;
+        rq[tid] = q;
+        rr[tid] = rot;
       }
       __syncthreads();
-      // Rows: A <- J^T A.
-      for (int e = tid; e < half * n; e += kBlock) {
-        const int k = e / n, j = e - k * n;
-        const int p = rp[k], q = rq[k];
-        if (p == q) continue;
-        const double c = rc[k], sn = rs[k];
-        const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - sn * aq;
-        A[q][j] = sn * ap + c * aq;
-      }
-      __syncthreads();
-      // Columns: A <- A J, Y <- Y J.
-      for (int e = tid; e < half * n; e += kBlock) {
-        const int k = e / n, i = e - k * n;
-        const int p = rp[k], q = rq[k];
-        if (p == q) continue;
-        const double c = rc[k], sn = rs[k];
-        const double ap = A[i][p], aq = A[i][q];
-        A[i][p] = c * ap - sn * aq;
-        A[i][q] = sn * ap + c * aq;
-        const double yp = Y[i][p], yq = Y[i][q];
-        Y[i][p] = c * yp - sn * yq;
-        Y[i][q] = sn * yp + c * yq;
-      }
-      __syncthreads();
-      if (tid < half) {
-        const int p = rp[tid], q = rq[tid];
-        if (p != q) {
-          A[p][q] = 0.0;
-          A[q][p] = 0.0;
+      // A <- J^T A J as independent 2 x 2 blocks (row pair k, column pair
+      // l): the row rotation, then the column rotation; Y <- Y J.  A pair
+      // that does not rotate has c = 1, s = 0 (exact identity).
+      const int nblk = half * half;
+      for (int e = tid; e < nblk + n * half; e += kBlock) {
+        if (e < nblk) {
+          const int k = e / half, l = e - k * half;
+          const int p = rp[k], q = rq[k], r = rp[l], t = rq[l];
+          const double c1 = rc[k], s1 = rs[k], c2 = rc[l], s2 = rs[l];
+          const double apr = A[p][r], apt = A[p][t];
+          const double aqr = A[q][r], aqt = A[q][t];
+          const double bpr = c1 * apr - s1 * aqr, bpt = c1 * apt - s1 * aqt;
+          const double bqr = s1 * apr + c1 * aqr, bqt = s1 * apt + c1 * aqt;
+          double cpt = s2 * bpr + c2 * bpt, cqr = c2 * bqr - s2 * bqt;
+          if (k == l && rr[k]) cpt = cqr = 0.0;  // the annihilated pair
+          A[p][r] = c2 * bpr - s2 * bpt;
+          A[p][t] = cpt;
+          A[q][r] = cqr;
+          A[q][t] = s2 * bqr + c2 * bqt;
+        } else {
+          const int e2 = e - nblk, l = e2 / n, i = e2 - l * n;
+          const int p = rp[l], q = rq[l];
+          const double c = rc[l], sn = rs[l];
+          const double yp = Y[i][p], yq = Y[i][q];
+          Y[i][p] = c * yp - sn * yq;
+          Y[i][q] = sn * yp + c * yq;
         }
       }
       __syncthreads();
@@ -1501,11 +1505,6 @@ rotate_final_kernel(const Desc* __restrict__ D) {
 // Launchers
 // ---------------------------------------------------------------------------
 
-// LDS of a CSR tile with the launch's largest tile (tr rows).
-static size_t csr_smem(int tr, size_t vsize, int nvals) {
-  return csr_tile_bytes(tr, vsize, nvals);
-}
-
 // Launch a kernel; with timing on, the start and stop events are taken by
 // the dispatch itself (kernel execution only, no launch gaps) and the
 // duration is added to `stage`.
@@ -1539,15 +1538,15 @@ static void klaunch(Timing* t, int stage, F kernel, dim3 grid, dim3 block,
 hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_RR_SPMM, spmm_dual_kernel,
                   dim3(L.blocks), dim3(kBlock),
-                  csr_smem(L.tr64, sizeof(double), 2), s, L.d, L.nprob,
+                  weights_bytes(L.tr64, sizeof(double), 2), s, L.d, L.nprob,
                   rr ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_START, pcg_start_kernel, dim3(L.blocks),
-                  dim3(kBlock), csr_smem(L.tr64, sizeof(double), 2), s, L.d,
-                  L.nprob);
+                  dim3(kBlock), weights_bytes(L.tr64, sizeof(double), 2), s,
+                  L.d, L.nprob);
   klaunch(t, PARO_ST_START, pcg_start_final_kernel, dim3(L.maxcols, L.nprob),
           dim3(kBlock), 0, s, L.d);
   return hipGetLastError();
@@ -1555,10 +1554,10 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
 
 template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
-  const int tr = sizeof(T) == 4 ? L.tr32 : L.tr64;
-  const size_t smem = csr_smem(tr, sizeof(T), 1);
   klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W>, dim3(L.blocks),
-          dim3(kBlock), smem, s, (const Desc*)L.d, L.nprob, par);
+          dim3(kBlock),
+          kStageCg<T> ? weights_bytes(L.tr64, sizeof(T), 1) : 0, s,
+          (const Desc*)L.d, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
           dim3(kBlock), 0, s, (const Desc*)L.d, par);
   klaunch(t, PARO_ST_CG_RUPD, rupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
@@ -1591,7 +1590,7 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
 hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_kernel,
                   dim3(L.blocks), dim3(kBlock),
-                  csr_smem(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
+                  weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
   klaunch(t, PARO_ST_REFINE, refine_final_kernel, dim3(L.maxcols, L.nprob),
           dim3(kBlock), 0, s, L.d);
   return hipGetLastError();
