@@ -1145,6 +1145,13 @@ gram_scatter_kernel(const Desc* __restrict__ D, int sym) {
 // ------------------------------------------------------------------------
 constexpr int kLd = kNtMax + 1;
 
+// Maximum over a wavefront (every lane receives it).
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ void geneig_body(const double* __restrict__ Ain,
                             const double* __restrict__ Bin, int n,
                             double* __restrict__ theta_out,
@@ -1160,6 +1167,7 @@ __device__ void geneig_body(const double* __restrict__ Ain,
   __shared__ int s_info;
   __shared__ int perm[kNtMax];
   __shared__ double th[kNtMax];
+  __shared__ double dl[kNtMax];
   const int tid = threadIdx.x;
   const int nn = n + (n & 1);
   // Zero the padded LDS matrices (odd n uses row/column n as a dummy),
@@ -1180,25 +1188,28 @@ __device__ void geneig_body(const double* __restrict__ Ain,
   }
   __syncthreads();
 
-  // 1. Cholesky, left-looking, column by column.
+  // 1. Cholesky B = L L^T, right-looking: at step k every thread reads the
+  // pivot, column k is scaled, then the trailing lower triangle is
+  // updated (entries see their updates in ascending k, as a left-looking
+  // dot product would).
+  if (tid < n) th[tid] = L[tid][tid];  // diagonal of B (pivot test)
+  __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double bkk = L[k][k];
-      double d = bkk;
-      for (int j = 0; j < k; ++j) d -= L[k][j] * L[k][j];
-      // A pivot at rounding level of the diagonal means the columns are
-      // linearly dependent in the M inner product.
-      if (!(d > 1e-14 * bkk) || !isfinite(d)) {
-        s_info = k + 1;
-        d = 1.0;
-      }
-      L[k][k] = sqrt(d);
-    }
+    const double piv = L[k][k];
+    // A pivot at rounding level of the diagonal means the columns are
+    // linearly dependent in the M inner product.
+    const bool bad = !(piv > 1e-14 * th[k]) || !isfinite(piv);
+    const double lkk = sqrt(bad ? 1.0 : piv);
+    for (int i = k + 1 + tid; i < n; i += kBlock) L[i][k] = L[i][k] / lkk;
     __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += kBlock) {
-      double v = L[i][k];
-      for (int j = 0; j < k; ++j) v -= L[i][j] * L[k][j];
-      L[i][k] = v / L[k][k];
+    if (tid == 0) {
+      L[k][k] = lkk;
+      if (bad && s_info == 0) s_info = k + 1;
+    }
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += kBlock) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) L[i][j] -= L[i][k] * L[j][k];
     }
     __syncthreads();
   }
@@ -1212,26 +1223,31 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     for (int e = tid; e < n; e += kBlock) theta_out[e] = Ain[e * n + e];
     return;
   }
+  if (tid < n) dl[tid] = 1.0 / L[tid][tid];
 
-  // 2. Y = L^{-1} A (columns in parallel), then S = L^{-1} Y^T into A.
-  if (tid < n) {
-    const int j = tid;
+  // 2. S = L^{-1} A L^{-T}: two forward substitutions, each row-parallel
+  // with one barrier per step (step i finalises row i into the output and
+  // removes it from the rows below).  First Y := A, A := L^{-1} Y; then
+  // Y := A^T, A := L^{-1} Y.
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int e = tid; e < n * n; e += kBlock) {
+      const int i = e / n, j = e % n;
+      Y[i][j] = pass == 0 ? A[i][j] : A[j][i];
+    }
+    __syncthreads();
     for (int i = 0; i < n; ++i) {
-      double v = A[i][j];
-      for (int k = 0; k < i; ++k) v -= L[i][k] * Y[k][j];
-      Y[i][j] = v / L[i][i];
+      const double di = dl[i];
+      for (int e = tid; e < (n - i) * n; e += kBlock) {
+        const int r = i + e / n, j = e % n;
+        const double x = Y[i][j] * di;
+        if (r == i)
+          A[i][j] = x;
+        else
+          Y[r][j] -= L[r][i] * x;
+      }
+      __syncthreads();
     }
   }
-  __syncthreads();
-  if (tid < n) {
-    const int j = tid;
-    for (int i = 0; i < n; ++i) {
-      double v = Y[j][i];
-      for (int k = 0; k < i; ++k) v -= L[i][k] * A[k][j];
-      A[i][j] = v / L[i][i];
-    }
-  }
-  __syncthreads();
   for (int e = tid; e < n * n; e += kBlock) {
     const int i = e / n, j = e % n;
     if (i < j) {
@@ -1265,9 +1281,19 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     __syncthreads();
   }
   const double skip = 1e-17 * sqrt(red[0]);
+  __syncthreads();  // red is reused below
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    // Stop before a sweep that would rotate nothing: every |a_pq| <= skip.
+    double off = 0.0;
+    for (int e = tid; e < n * n; e += kBlock) {
+      const int i = e / n, j = e % n;
+      if (i < j) off = fmax(off, fabs(A[i][j]));
+    }
+    off = wave_max(off);
+    if ((tid & 63) == 0) red[tid >> 6] = off;
     if (tid == 0) s_rot = 0;
     __syncthreads();
+    if (fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) <= skip) break;
     for (int round = 0; round < nn - 1; ++round) {
       if (tid < half) {
         const int a0 = tid == 0 ? 0 : 1 + ((tid - 1 + round) % (nn - 1));
@@ -1339,18 +1365,21 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     perm[rank] = tid;
   }
   __syncthreads();
-  // 5. C[:, r] = L^{-T} Y[:, perm[r]] (back substitution), stored in A
-  // (its diagonal was saved in th).
+  // 5. C[:, r] = L^{-T} Y[:, perm[r]] (back substitution, row-parallel,
+  // one barrier per step), stored in A (its diagonal was saved in th).
   double (*Cs)[kLd] = A;
-  if (tid < n) {
-    const int r = tid, src = perm[r];
-    for (int i = n - 1; i >= 0; --i) {
-      double v = Y[i][src];
-      for (int k = i + 1; k < n; ++k) v -= L[k][i] * Cs[k][r];
-      Cs[i][r] = v / L[i][i];
+  for (int i = n - 1; i >= 0; --i) {
+    const double di = dl[i];
+    for (int e = tid; e < (i + 1) * n; e += kBlock) {
+      const int r = e / n, c = e % n, src = perm[c];
+      const double x = Y[i][src] * di;
+      if (r == i)
+        Cs[i][c] = x;
+      else
+        Y[r][src] -= L[i][r] * x;
     }
+    __syncthreads();
   }
-  __syncthreads();
   // 6. Sign: largest-magnitude entry of each column positive.
   if (tid < n) {
     const int r = tid;
