@@ -312,6 +312,10 @@ int paro_server_report(paro_server* s, int64_t id, paro_report_t* report);
  * caller's). */
 void paro_server_destroy(paro_server* s);
 
+/* Polls and step reports reach the host through a small pinned host
+ * buffer per calling thread (64 KB, hipHostMalloc'd on first use and kept
+ * until the process ends) that the device writes directly. */
+
 /* Message for the last failing call on this thread (never NULL). */
 const char* paro_last_error(void);
 const char* paro_strerror(int status);
@@ -381,6 +385,12 @@ typedef struct paro_timing {
   int64_t cg_col_iters;           /* sum over CG iterations of the
                                      number of active columns           */
 } paro_timing_t;
+
+/* CG iterations of single-problem calls run as captured HIP graphs
+ * (instantiated once per launch shape and replayed) when on, or kernel by
+ * kernel (the default).  Process-wide.  Timing mode always launches
+ * kernel by kernel. */
+void paro_set_graphs(int on);
 
 /* Turn per-launch event timing on (1) or off (0); clears the sums. */
 int paro_set_timing(paro_problem* p, int on);

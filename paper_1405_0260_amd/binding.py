@@ -139,6 +139,7 @@ def lib():
         "paro_small_geneig": (c_i32, [P, P, c_i32, P, P, P, P]),
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
+        "paro_set_graphs": (None, [c_i32]),
         "paro_get_timing": (c_i32, [P, ctypes.POINTER(Timing)]),
         "paro_batch_workspace_bytes": (ctypes.c_size_t, [c_i32]),
         "paro_batch_init": (c_i32, [PP, c_i32, PP, PP, PP, P,
@@ -354,6 +355,11 @@ def paro_pcg(p: Problem, B, X, stream=None):
     _check(lib().paro_pcg(p.handle, _ptr(B), _ptr(X), ncols, iters,
                           _stream(stream)))
     return list(iters)
+
+
+def paro_set_graphs(on: bool = True):
+    """Run CG chunks as captured HIP graphs (default) or kernel by kernel."""
+    lib().paro_set_graphs(1 if on else 0)
 
 
 def paro_set_timing(p: Problem, on: bool = True):

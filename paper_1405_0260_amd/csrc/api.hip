@@ -4,7 +4,10 @@
 // assemble.hip and solver.hip; the host only launches them and polls small
 // flags.
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -77,9 +80,25 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b) {
   if (t->pend.size() > 4096) t->resolve();
 }
 
+// Instantiated launch graphs of CG chunks (hipGraph), keyed by the launch
+// shape, the precision, the starting parity and the chunk length.  The
+// kernels read their descriptors from device memory at run time, so a
+// graph stays valid while the launch shape (table address, grid, vector
+// widths, problem count) is unchanged.
+struct GraphCache {
+  std::map<std::array<int64_t, 12>, hipGraphExec_t> m;
+  ~GraphCache() {
+    for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
+  }
+};
+
 namespace {
 
 thread_local std::string g_err = "no error";
+// Off by default: measured no faster than kernel-by-kernel launches once
+// polls go through the host mailbox (the GPU-side dispatch gap between
+// dependent kernels is what remains, and graphs do not shorten it).
+std::atomic<int> g_graphs_on{0};
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
@@ -176,8 +195,6 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.cnt = (unsigned*)at(L.cnt);
   p.flag = (int*)at(L.flag);
   p.dd = (Desc*)at(L.desc);
-  p.dpoll = (int*)at(L.poll);
-  p.dreport = (PollReport*)at(L.report);
 }
 
 int pick_grid(int64_t n, int Nt) {
@@ -318,13 +335,75 @@ int status_to_code(int st) {
 struct Ctx {
   Launch L;
   std::vector<Desc> tab;
-  int* dpoll;
-  PollReport* dreport;
   Timing* timing;
   int* predict;           // 5 prediction slots (problem or batch)
   int maxit;
   int precision;
+  GraphCache* graphs;     // null: launch kernel by kernel
+  int last_status = 0;    // status bits seen by the last poll
 };
+
+// The stream CG chunks are captured on (capture only records; the graphs
+// run on the caller's stream, which may be the null stream).
+hipStream_t capture_stream() {
+  thread_local hipStream_t cs = nullptr;
+  if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    cs = nullptr;
+  return cs;
+}
+
+// Launch `k` CG iterations from parity `par` as one cached graph.
+int cg_graph(Ctx& c, bool fp32, int par, int k, hipStream_t s) {
+  const Launch& L = c.L;
+  const std::array<int64_t, 12> key = {
+      (int64_t)(uintptr_t)L.d, L.nprob, L.blocks, L.gblocks, L.maxcols,
+      L.v64u, L.v32u, L.tr64, L.tr32, fp32 ? 1 : 0, par, k};
+  auto it = c.graphs->m.find(key);
+  if (it == c.graphs->m.end()) {
+    hipStream_t cs = capture_stream();
+    if (!cs) return fail(PARO_EDEVICE, "no capture stream");
+    HIP_OR_FAIL(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int q = par;
+    for (int i = 0; i < k; ++i) {
+      (void)launch_pcg_iter(c.L, fp32, q, cs, nullptr);
+      q ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    HIP_OR_FAIL(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+      return fail(PARO_EDEVICE, "hipGraphInstantiate: %s",
+                  hipGetErrorString(e));
+    it = c.graphs->m.emplace(key, exec).first;
+  }
+  HIP_OR_FAIL(hipGraphLaunch(it->second, s));
+  return PARO_OK;
+}
+
+// k CG iterations from parity par: graphs of 1, 2, 4, ... iterations (the
+// binary digits of k), or kernel by kernel when timing or no cache.
+int cg_launches(Ctx& c, bool fp32, int par, int k, hipStream_t s) {
+  if (c.graphs && !(c.timing && c.timing->on) && g_graphs_on.load()) {
+    for (int b = 1 << 8; b > 0; b >>= 1) {
+      while (k >= b) {
+        const int rc = cg_graph(c, fp32, par, b, s);
+        if (rc) return rc;
+        if (b & 1) par ^= 1;
+        k -= b;
+      }
+    }
+    return PARO_OK;
+  }
+  for (int i = 0; i < k; ++i) {
+    hipError_t e = launch_pcg_iter(c.L, fp32, par, s, c.timing);
+    if (e != hipSuccess)
+      return fail(PARO_EDEVICE, "CG launch: %s", hipGetErrorString(e));
+    par ^= 1;
+  }
+  return PARO_OK;
+}
 
 int upload(Ctx& c, hipStream_t s) {
   HIP_OR_FAIL(hipMemcpyAsync(c.L.d, c.tab.data(), sizeof(Desc) * c.tab.size(),
@@ -333,11 +412,75 @@ int upload(Ctx& c, hipStream_t s) {
   return PARO_OK;
 }
 
+// Host mailbox of the calling thread: pinned, coherent host memory that
+// the poll and report kernels write directly, so that the host learns a
+// result by spinning on a sequence word rather than through a
+// device-to-host copy and a stream synchronisation (which leave the GPU
+// idle for tens of microseconds per poll).  Allocated once per thread on
+// first use and kept for the life of the process.
+struct Mailbox {
+  char* h = nullptr;  // host address
+  char* d = nullptr;  // device address of the same memory
+  int seq = 0;
+};
+constexpr size_t kMbPoll = 0;       // poll words: seq, count, iters, status
+constexpr size_t kMbRepSeq = 64;    // report sequence word
+constexpr size_t kMbReports = 128;  // PollReport[PARO_BATCH_MAX]
+constexpr size_t kMailboxBytes = kMbReports + 32 * PARO_BATCH_MAX;
+
+Mailbox* mailbox() {
+  static_assert(sizeof(PollReport) <= 32, "report slot");
+  thread_local Mailbox mb;
+  if (!mb.h) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, kMailboxBytes,
+                      hipHostMallocCoherent | hipHostMallocMapped) !=
+        hipSuccess)
+      return nullptr;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipHostFree(h);
+      return nullptr;
+    }
+    std::memset(h, 0, kMailboxBytes);
+    mb.h = static_cast<char*>(h);
+    mb.d = static_cast<char*>(d);
+  }
+  return &mb;
+}
+
+// Spin until the device has written `seq` to the host word w.  Every 1024
+// spins the stream is queried, so that a failed or finished stream that
+// never wrote the word ends the wait with an error.
+int wait_word(const int* w, int seq, hipStream_t s) {
+  for (uint64_t it = 1;; ++it) {
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return PARO_OK;
+    if ((it & 1023) == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return PARO_OK;
+        return fail(PARO_EDEVICE, "poll word not written by the device");
+      }
+      if (e != hipErrorNotReady)
+        return fail(PARO_EDEVICE, "stream failed while polling: %s",
+                    hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 int poll(Ctx& c, int which, int out[2], hipStream_t s) {
-  HIP_OR_FAIL(launch_count_active(c.L, which, c.dpoll, s));
-  HIP_OR_FAIL(hipMemcpyAsync(out, c.dpoll, 2 * sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipStreamSynchronize(s));
+  Mailbox* mb = mailbox();
+  if (!mb) return fail(PARO_EDEVICE, "pinned host mailbox unavailable");
+  const int seq = ++mb->seq;
+  int* hw = reinterpret_cast<int*>(mb->h + kMbPoll);
+  HIP_OR_FAIL(launch_count_active(
+      c.L, which, reinterpret_cast<int*>(mb->d + kMbPoll), seq, s));
+  const int rc = wait_word(hw, seq, s);
+  if (rc) return rc;
+  out[0] = hw[1];
+  out[1] = hw[2];
+  c.last_status = hw[3];
   if (c.timing) c.timing->resolve();
   return PARO_OK;
 }
@@ -357,12 +500,9 @@ int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
   while (true) {
     if (launched >= cap)
       return fail(PARO_EDEVICE, "CG loop did not terminate on the device");
-    for (int k = 0; k < chunk; ++k) {
-      hipError_t e = launch_pcg_iter(c.L, fp32, par, s, c.timing);
-      if (e != hipSuccess)
-        return fail(PARO_EDEVICE, "CG launch: %s", hipGetErrorString(e));
-      par ^= 1;
-    }
+    const int rc0 = cg_launches(c, fp32, par, chunk, s);
+    if (rc0) return rc0;
+    if (chunk & 1) par ^= 1;
     launched += chunk;
     const int rc = poll(c, par, pw, s);
     if (rc) return rc;
@@ -394,12 +534,17 @@ int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
 }
 
 int read_reports(Ctx& c, std::vector<PollReport>& out, hipStream_t s) {
+  Mailbox* mb = mailbox();
+  if (!mb) return fail(PARO_EDEVICE, "pinned host mailbox unavailable");
   out.resize(c.tab.size());
-  HIP_OR_FAIL(launch_gather_reports(c.L, c.dreport, s));
-  HIP_OR_FAIL(hipMemcpyAsync(out.data(), c.dreport,
-                             sizeof(PollReport) * out.size(),
-                             hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipStreamSynchronize(s));
+  const int seq = ++mb->seq;
+  HIP_OR_FAIL(launch_gather_reports(
+      c.L, reinterpret_cast<PollReport*>(mb->d + kMbReports),
+      reinterpret_cast<int*>(mb->d + kMbRepSeq), seq, s));
+  const int rc =
+      wait_word(reinterpret_cast<const int*>(mb->h + kMbRepSeq), seq, s);
+  if (rc) return rc;
+  std::memcpy(out.data(), mb->h + kMbReports, sizeof(PollReport) * out.size());
   return PARO_OK;
 }
 
@@ -416,12 +561,9 @@ int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single) {
   rc = solve_sources(c, s, &refinements);
   if (rc) return rc;
   std::vector<PollReport> pr;
-  if (single) {
-    rc = read_reports(c, pr, s);
-    if (rc) return rc;
-    if (pr[0].status & (kStNonFinite | kStNotSpd))
-      return status_to_code(pr[0].status);
-  }
+  // The last poll of the source solves carries the status bits.
+  if (single && (c.last_status & (kStNonFinite | kStNotSpd)))
+    return status_to_code(c.last_status);
   HIP_OR_FAIL(launch_rayleigh_ritz(c.L, s, c.timing));
   if (!reps) return PARO_OK;
   rc = read_reports(c, pr, s);
@@ -457,29 +599,23 @@ Ctx single_ctx(Problem& p) {
   Ctx c;
   c.tab.assign(1, p.hd);
   c.L = make_launch(p.dd, c.tab.data(), 1);
-  c.dpoll = p.dpoll;
-  c.dreport = p.dreport;
   c.timing = p.timing;
   c.predict = p.cg_predict;
   c.maxit = p.opts.pcg_maxit;
   c.precision = p.opts.precision;
+  if (!p.graphs) p.graphs = new (std::nothrow) GraphCache();
+  c.graphs = p.graphs;
   return c;
 }
 
-// Batch workspace: the table, poll words and reports.
+// Batch workspace: the descriptor table.
 struct BatchLayout {
-  size_t tab, poll, report, total;
+  size_t tab, total;
 };
 BatchLayout batch_layout(int count) {
   BatchLayout b;
-  size_t o = 0;
-  b.tab = o;
-  o += align256(sizeof(Desc) * (size_t)count);
-  b.poll = o;
-  o += align256(sizeof(int) * 16);
-  b.report = o;
-  o += align256(sizeof(PollReport) * (size_t)count);
-  b.total = o;
+  b.tab = 0;
+  b.total = align256(sizeof(Desc) * (size_t)count);
   return b;
 }
 
@@ -507,12 +643,11 @@ int batch_ctx(Ctx& c, paro_problem* const* probs, int count, void* ws,
   layout_batch(c.tab);
   char* base = (char*)ws;
   c.L = make_launch((Desc*)(base + bl.tab), c.tab.data(), count);
-  c.dpoll = (int*)(base + bl.poll);
-  c.dreport = (PollReport*)(base + bl.report);
   c.timing = nullptr;
   c.predict = predict;
   c.maxit = maxit;
   c.precision = prec;
+  c.graphs = nullptr;
   return PARO_OK;
 }
 
@@ -562,8 +697,6 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.cnt = take(sizeof(unsigned) * kCntNum);
   L.flag = take(sizeof(int) * 16);
   L.desc = take(sizeof(Desc));
-  L.poll = take(sizeof(int) * 16);
-  L.report = take(sizeof(PollReport));
   L.total = off;
   return L;
 }
@@ -816,6 +949,7 @@ double paro_sigma(const paro_problem* h) { return h ? h->p.sigma : 0.0; }
 void paro_destroy(paro_problem* h) {
   if (!h) return;
   delete h->p.timing;
+  delete h->p.graphs;
   delete h;
 }
 
@@ -960,6 +1094,8 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
     fail(first, "problem(s) of the batch ended with status %d", first);
   return first;
 }
+
+void paro_set_graphs(int on) { g_graphs_on.store(on ? 1 : 0); }
 
 int paro_set_timing(paro_problem* h, int on) {
   if (!h) return fail(PARO_EINVAL, "NULL problem");

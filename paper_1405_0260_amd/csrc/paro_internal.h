@@ -176,7 +176,8 @@ struct PollReport {
   double max_resid;
 };
 
-struct Timing;  // host-side event timing state (api.hip)
+struct Timing;      // host-side event timing state (api.hip)
+struct GraphCache;  // captured CG launch graphs (api.hip)
 
 struct Problem {
   paro_box_t box;
@@ -221,12 +222,11 @@ struct Problem {
   int* flag;              // scratch flags
   size_t ws_bytes;
   Timing* timing;         // null unless paro_set_timing(p, 1)
+  GraphCache* graphs;     // CG chunk graphs of this problem (lazy)
   hipStream_t last_stream;
   int cg_predict[5];      // CG iterations of the last solve per pass slot
   Desc hd;                // host copy of the problem's descriptor
   Desc* dd;               // its device slot (workspace)
-  int* dpoll;             // device poll words (workspace)
-  PollReport* dreport;    // device report slot (workspace)
 };
 
 // Kernel timing (api.hip): a pair of events for one launch when timing is
@@ -240,7 +240,7 @@ struct Layout {
       diagA32;
   size_t X, R, P, Q, B, R32, P32, Q32, X32;
   size_t part, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt, flag;
-  size_t desc, poll, report;
+  size_t desc;
   size_t total;
 };
 
@@ -268,12 +268,16 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
 // FP32 inner solves inside FP64 refinement.
 hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t);
-// Poll of the table: out[0] = active CG columns of parity `which` (0, 1)
-// or refining columns (which = 2) summed over the problems, out[1] = most
-// CG iterations any problem has executed in its current solve.
-hipError_t launch_count_active(Launch& L, int which, int* out,
+// Poll of the table into host-visible memory: out[1] = active CG columns
+// of parity `which` (0, 1) or refining columns (which = 2) summed over the
+// problems, out[2] = most CG iterations any problem has executed in its
+// current solve, out[3] = OR of the problems' status bits; then out[0] =
+// seq (system-scope release, for a host spinning on it).
+hipError_t launch_count_active(Launch& L, int which, int* out, int seq,
                                hipStream_t s);
-hipError_t launch_gather_reports(Launch& L, PollReport* out, hipStream_t s);
+// Per-problem reports into out[0 .. nprob), then *seqp = seq.
+hipError_t launch_gather_reports(Launch& L, PollReport* out, int* seqp,
+                                 int seq, hipStream_t s);
 // Rayleigh-Ritz on W = X: H W, M W, the two Grams, the small eigensolve,
 // U = W C with residual norms and the step's convergence measures.
 hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t);

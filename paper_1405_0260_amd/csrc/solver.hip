@@ -857,36 +857,45 @@ refine_update_kernel(const Desc* __restrict__ D, int nprob) {
 // the refining columns (which = 1), for the host's poll (one block).
 __global__ void __launch_bounds__(kBlock)
 count_active_kernel(const Desc* __restrict__ D, int nprob, int which,
-                    int* __restrict__ out) {
-  __shared__ int red[kBlock], mx[kBlock];
-  int s = 0, m = 0;
+                    int* __restrict__ out, int seq) {
+  __shared__ int red[kBlock], mx[kBlock], st[kBlock];
+  int s = 0, m = 0, f = 0;
   for (int p = threadIdx.x; p < nprob; p += kBlock) {
     const ColState* cs = D[p].cs;
     s += which == 2 ? cs->n_outer : cs->n_active[which];
     m = max(m, (int)(cs->cg_iters - cs->cg_mark));
+    f |= cs->status;
   }
   red[threadIdx.x] = s;
   mx[threadIdx.x] = m;
+  st[threadIdx.x] = f;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       red[threadIdx.x] += red[threadIdx.x + w];
       mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + w]);
+      st[threadIdx.x] |= st[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = red[0];
-    out[1] = mx[0];
+    out[1] = red[0];
+    out[2] = mx[0];
+    out[3] = st[0];
+    // out is host memory the caller spins on: the values, then the
+    // sequence number with system-scope release.
+    __hip_atomic_store(&out[0], seq, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
-// Per-problem status and convergence measures of the last step.
+// Per-problem status and convergence measures of the last step (one
+// block), then the sequence number *seqp = seq (system-scope release).
 __global__ void __launch_bounds__(kBlock)
 gather_reports_kernel(const Desc* __restrict__ D, int nprob,
-                      PollReport* __restrict__ out) {
-  for (int p = blockIdx.x * kBlock + threadIdx.x; p < nprob;
-       p += gridDim.x * kBlock) {
+                      PollReport* __restrict__ out, int* __restrict__ seqp,
+                      int seq) {
+  for (int p = threadIdx.x; p < nprob; p += kBlock) {
     const Desc& d = D[p];
     const ColState* cs = d.cs;
     int it = 0;
@@ -900,6 +909,9 @@ gather_reports_kernel(const Desc* __restrict__ D, int nprob,
     r.max_resid = d.si->max_resid;
     out[p] = r;
   }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(seqp, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ------------------------------------------------------------------------
@@ -1631,16 +1643,17 @@ hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t) {
   return hipGetLastError();
 }
 
-hipError_t launch_gather_reports(Launch& L, PollReport* out, hipStream_t s) {
-  hipLaunchKernelGGL(gather_reports_kernel, dim3((L.nprob + kBlock - 1) / kBlock),
-                     dim3(kBlock), 0, s, L.d, L.nprob, out);
+hipError_t launch_gather_reports(Launch& L, PollReport* out, int* seqp,
+                                 int seq, hipStream_t s) {
+  hipLaunchKernelGGL(gather_reports_kernel, dim3(1), dim3(kBlock), 0, s, L.d,
+                     L.nprob, out, seqp, seq);
   return hipGetLastError();
 }
 
-hipError_t launch_count_active(Launch& L, int which, int* out,
+hipError_t launch_count_active(Launch& L, int which, int* out, int seq,
                                hipStream_t s) {
   hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(kBlock), 0, s, L.d,
-                     L.nprob, which, out);
+                     L.nprob, which, out, seq);
   return hipGetLastError();
 }
 
