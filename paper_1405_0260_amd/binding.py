@@ -140,6 +140,10 @@ def lib():
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
         "paro_set_graphs": (None, [c_i32]),
+        "paro_set_autotune": (None, [c_i32]),
+        "paro_tuned": (c_i32, [P, ctypes.POINTER(c_i32),
+                               ctypes.POINTER(c_i32)]),
+        "paro_set_tuning": (c_i32, [P, c_i32, c_i32]),
         "paro_get_timing": (c_i32, [P, ctypes.POINTER(Timing)]),
         "paro_batch_workspace_bytes": (ctypes.c_size_t, [c_i32]),
         "paro_batch_init": (c_i32, [PP, c_i32, PP, PP, PP, P,
@@ -360,6 +364,23 @@ def paro_pcg(p: Problem, B, X, stream=None):
 def paro_set_graphs(on: bool = True):
     """Run CG chunks as captured HIP graphs (default) or kernel by kernel."""
     lib().paro_set_graphs(1 if on else 0)
+
+
+def paro_set_autotune(on: bool = True):
+    """Autotune the CG SpMM per problem shape at assembly (default on)."""
+    lib().paro_set_autotune(1 if on else 0)
+
+
+def paro_tuned(p: Problem):
+    """(kernel variant, real block count) chosen for the problem."""
+    v, b = c_i32(), c_i32()
+    _check(lib().paro_tuned(p.handle, ctypes.byref(v), ctypes.byref(b)))
+    return v.value, b.value
+
+
+def paro_set_tuning(p: Problem, variant: int, blocks: int):
+    """Pin the CG SpMM variant and real block count of a problem."""
+    _check(lib().paro_set_tuning(p.handle, variant, blocks))
 
 
 def paro_set_timing(p: Problem, on: bool = True):

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -220,6 +221,7 @@ void desc_init(Problem& p) {
   d.gnb = d.gns = std::min(p.grid, kGramGrid);
   d.v64 = vec64_of(p.Nt);
   d.v32 = vec32_of(p.Nt);
+  d.cg_var = -1;
   d.maxit = p.opts.pcg_maxit;
   d.sigma = p.sigma;
   d.rtol = p.opts.pcg_rtol;
@@ -293,6 +295,9 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
     if ((tab[i].ncols + 15) / 16 != L.nt16) L.nt16_mixed = 1;
   }
   if (n > 0 && (tab[0].ncols + 15) / 16 != L.nt16) L.nt16_mixed = 1;
+  L.cgvar = n > 0 ? tab[0].cg_var : -1;
+  for (int i = 1; i < n; ++i)
+    if (tab[i].cg_var != L.cgvar) L.cgvar = -1;
   return L;
 }
 
@@ -305,7 +310,8 @@ void layout_batch(std::vector<Desc>& tab) {
   int b = 0, g = 0;
   for (Desc& d : tab) {
     const double w = (double)d.n * d.ncols / total;
-    const int nb = std::max(8, std::min(d.ns, round8((int64_t)(w * kBatchGrid))));
+    // d.nb: the problem's (tuned) single-problem block count.
+    const int nb = std::max(8, std::min(d.nb, round8((int64_t)(w * kBatchGrid))));
     const int gnb =
         std::max(8, std::min(d.gns, round8((int64_t)(w * kBatchGramGrid))));
     d.b0 = b;
@@ -651,6 +657,82 @@ int batch_ctx(Ctx& c, paro_problem* const* probs, int count, void* ws,
   return PARO_OK;
 }
 
+// Autotuner of the CG SpMM: for a problem shape (grid, columns,
+// precision) time every kernel variant with the full and the halved real
+// block count on the problem's own operator (all columns active, scratch
+// vectors), keep the fastest, and cache it for the process.  Neither
+// choice changes the arithmetic: variants differ only in staging and
+// gather depth, and the reduction segments stay the problem's own.
+std::atomic<int> g_autotune_on{1};
+std::mutex g_tune_mu;
+std::map<std::array<int, 5>, std::pair<int, int>> g_tune;
+
+int autotune(Problem& p, hipStream_t s) {
+  const std::array<int, 5> key = {p.mx, p.my, p.mz, p.Nt,
+                                  p.opts.precision};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      p.hd.cg_var = it->second.first;
+      p.hd.nb = it->second.second;
+      return PARO_OK;
+    }
+  }
+  const bool fp32 = p.opts.precision == PARO_FP32_INNER;
+  const size_t vbytes = (fp32 ? 4 : 8) * (size_t)p.n * p.Nt;
+  HIP_OR_FAIL(hipMemsetAsync(fp32 ? (void*)p.P32 : (void*)p.P, 0, vbytes, s));
+  Ctx c;
+  c.tab.assign(1, p.hd);
+  c.L = make_launch(p.dd, c.tab.data(), 1);
+  int rc = upload(c, s);
+  if (rc) return rc;
+  HIP_OR_FAIL(launch_all_active(c.L, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OR_FAIL(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(PARO_EDEVICE, "hipEventCreate failed");
+  }
+  const int ns = p.hd.ns;
+  const int half = std::max(8, ns / 2 / 8 * 8);
+  float best = 1e30f;
+  int best_var = -1, best_nb = ns;
+  hipError_t err = hipSuccess;
+  for (int var = 0; var < 3 && err == hipSuccess; ++var) {
+    for (int nb : {ns, half}) {
+      if (nb == half && half == ns) continue;
+      c.tab[0].nb = nb;
+      if ((rc = upload(c, s)) != PARO_OK) break;
+      if ((err = launch_cg_spmm(c.L, fp32, var, s)) != hipSuccess) break;
+      if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+      for (int k = 0; k < 5 && err == hipSuccess; ++k)
+        err = launch_cg_spmm(c.L, fp32, var, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (ms < best) {
+        best = ms;
+        best_var = var;
+        best_nb = nb;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (err != hipSuccess)
+    return fail(PARO_EDEVICE, "autotune: %s", hipGetErrorString(err));
+  p.hd.cg_var = best_var;
+  p.hd.nb = best_nb;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = {best_var, best_nb};
+  return PARO_OK;
+}
+
 }  // namespace
 
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
@@ -823,6 +905,10 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
     if (launch_assemble(p, d_V, s) != hipSuccess)
       return bail(fail(PARO_EDEVICE, "assembly launch failed"));
     desc_init(p);
+    if (g_autotune_on.load()) {
+      const int rc2 = autotune(p, s);
+      if (rc2) return bail(rc2);
+    }
     *out = h;
     return PARO_OK;
   } catch (...) {
@@ -1096,6 +1182,28 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
 }
 
 void paro_set_graphs(int on) { g_graphs_on.store(on ? 1 : 0); }
+
+void paro_set_autotune(int on) { g_autotune_on.store(on ? 1 : 0); }
+
+int paro_set_tuning(paro_problem* h, int32_t variant, int32_t blocks) {
+  if (!h) return fail(PARO_EINVAL, "NULL problem");
+  Problem& p = h->p;
+  if (variant < -1 || variant > 2)
+    return fail(PARO_EINVAL, "variant must be -1..2");
+  if (blocks < 8 || blocks > p.hd.ns || blocks % 8)
+    return fail(PARO_EINVAL, "blocks must be a multiple of 8 in [8, %d]",
+                p.hd.ns);
+  p.hd.cg_var = variant;
+  p.hd.nb = blocks;
+  return PARO_OK;
+}
+
+int paro_tuned(const paro_problem* h, int32_t* variant, int32_t* blocks) {
+  if (!h) return fail(PARO_EINVAL, "NULL problem");
+  if (variant) *variant = h->p.hd.cg_var;
+  if (blocks) *blocks = h->p.hd.nb;
+  return PARO_OK;
+}
 
 int paro_set_timing(paro_problem* h, int on) {
   if (!h) return fail(PARO_EINVAL, "NULL problem");

@@ -114,7 +114,8 @@ struct Desc {
   const double* diagA;    // stencil order: [kStencil][n], 0 outside the box
   const double* diagM;
   const float* diagA32;
-  int mx, my, mz, pad0;   // interior vertices per axis (rows = mx my mz)
+  int mx, my, mz;         // interior vertices per axis (rows = mx my mz)
+  int cg_var;             // CG SpMM variant (autotuner), -1: default
   const double* U0;       // start of the source solves (x0), gathered
   const double* Bin;      // given right-hand sides, or null
   double* lam;            // Ritz values (in: previous, out: new), or null
@@ -164,6 +165,7 @@ struct Launch {
   int vmax64;             // widest FP64 vector of the table
   int v64u, v32u;         // common vector width of all problems, or 0
   int nt16_mixed;         // problems differ in ceil(ncols / 16)
+  int cgvar;              // common CG SpMM variant, or -1 (default)
 };
 
 // Per-problem step summary for the host (one PollReport per problem).
@@ -267,6 +269,10 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
                            Timing* t);
 // FP32 inner solves inside FP64 refinement.
 hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t);
+// Autotuner: the CG SpMM alone (parity 0) in variant `var`, and a set-up
+// making every column active.
+hipError_t launch_cg_spmm(Launch& L, bool fp32, int var, hipStream_t s);
+hipError_t launch_all_active(Launch& L, hipStream_t s);
 hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t);
 // Poll of the table into host-visible memory: out[1] = active CG columns
 // of parity `which` (0, 1) or refining columns (which = 2) summed over the

@@ -138,31 +138,27 @@ __device__ void block_partials(const double (&acc)[NA][V], int ncols, int cpr,
   __syncthreads();
 }
 
-// In a finalize kernel (one workgroup per column c of a problem): the
-// fixed-order sum of part[a][c][0..nb).  Every thread receives the sums.
+// Finalisers run one wavefront per (column, problem).
+constexpr int kFinal = 64;
+
+// In a finalize kernel: the fixed-order sum of part[a][c][0..nb) (lane l
+// adds segments l, l + 64, ..., then a butterfly over the wavefront, whose
+// lanes all end with the same bits).  Every lane receives the sums.
 template <int NA>
-__device__ void column_sums(const double* __restrict__ part, int c, int nb,
-                            double (&out)[NA]) {
-  __shared__ double red[NA][kBlock];
+__device__ __forceinline__ void column_sums(const double* __restrict__ part,
+                                            int c, int nb,
+                                            double (&out)[NA]) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     const double* src = part + a * kPartStride + (size_t)c * nb;
-    double s = 0.0;
-    for (int b = t; b < nb; b += kBlock) s += ldg(src + b);
-    red[a][t] = s;
-  }
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (t < w) {
+    double v = 0.0;
+#pragma unroll 4
+    for (int b = t; b < nb; b += kFinal) v += ldg(src + b);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) red[a][t] += red[a][t + w];
-    }
-    __syncthreads();
+    for (int o = kFinal / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kFinal);
+    out[a] = v;
   }
-#pragma unroll
-  for (int a = 0; a < NA; ++a) out[a] = red[a][0];
-  __syncthreads();
 }
 
 // Max of non-negative doubles through their bit patterns (order-free).
@@ -354,16 +350,23 @@ struct CgVecs<float> {
         Q(d.Q32) {}
 };
 
-// Whether the CG SpMM stages its coefficients in LDS (per precision).
+// Variants of the CG SpMM, chosen per problem shape by the autotuner: the
+// coefficients read directly (0) or staged per tile in LDS (1, 2), with
+// 15 (0, 1) or 8 (2) neighbour gathers in flight.  All variants perform
+// the same operations in the same order (identical results).
+constexpr bool cg_staged(int var) { return var != 0; }
+constexpr int cg_group(int var) { return var == 2 ? 8 : kStencil; }
 template <typename T>
-constexpr bool kStageCg = sizeof(T) == 8;
+constexpr int kCgDefaultVar = sizeof(T) == 8 ? 1 : 0;
 
 // ------------------------------------------------------------------------
 // CG iteration: Q = A P on the active columns, with per-column p . q.
 // ------------------------------------------------------------------------
-template <typename T, int V>
+template <typename T, int V, int VAR>
 __device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
     double* __restrict__ red) {
+  constexpr bool kStaged = cg_staged(VAR);
+  constexpr int kG = cg_group(VAR);
   const Geo g = geo_of<V>(d, vb);
   const int ncols = d.ncols;
   // Active count and column flags are read together (one round trip).
@@ -381,9 +384,7 @@ __device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
        w.t += w.step) {
     const long long r0 = w.t * g.tr;
     const int rows = (int)min((long long)g.tr, d.n - r0);
-    // FP64: coefficients staged per tile; FP32: read directly (measured
-    // faster: no barrier per tile).
-    if (kStageCg<T>)
+    if (kStaged)
       stage_weights<T, false>(vs.diag, nullptr, d.n, r0, rows, g.tr, wa,
                               nullptr);
     if (!on || g.lr >= rows) continue;
@@ -391,12 +392,12 @@ __device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
     T q[V], unused[V], po[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) q[v] = T(0);
-    if (kStageCg<T>)
-      stencil_product<T, T, V, false, kStencil, true>(
+    if (kStaged)
+      stencil_product<T, T, V, false, kG, true>(
           wa + g.lr, nullptr, g.tr, d.mx, d.my, d.mz, row, vs.P, ncols,
           g.ch * V, q, unused, po);
     else
-      stencil_product<T, T, V, false, kStencil, false>(
+      stencil_product<T, T, V, false, kG, false>(
           vs.diag + row, nullptr, d.n, d.mx, d.my, d.mz, row, vs.P, ncols,
           g.ch * V, q, unused, po);
     stv<T, V>(vs.Q + (size_t)row * ncols + g.ch * V, q);
@@ -406,19 +407,21 @@ __device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
   block_partials<V, 1>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
 }
 
-template <typename T, int VFIX>
+template <typename T, int VFIX, int VAR>
 __global__ void PARO_STREAM_BOUNDS
 spmm_cg_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
   if constexpr (sizeof(T) == 4)
-    PARO_VB_LOOP32(D, nprob, VFIX, (spmm_cg_body<T, VV>(d, vb, par, red)))
+    PARO_VB_LOOP32(D, nprob, VFIX,
+                   (spmm_cg_body<T, VV, VAR>(d, vb, par, red)))
   else
-    PARO_VB_LOOP64(D, nprob, VFIX, (spmm_cg_body<T, VV>(d, vb, par, red)))
+    PARO_VB_LOOP64(D, nprob, VFIX,
+                   (spmm_cg_body<T, VV, VAR>(d, vb, par, red)))
 }
 
 // alpha_c = (r.z)_c / (p.q)_c for the active columns (grid: column x
 // problem).  Also clears the next parity's active count for cg_beta.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinal)
 cg_alpha_kernel(const Desc* __restrict__ D, int par) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
@@ -508,7 +511,7 @@ rupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
 
 // beta_c, iteration count and the stopping test of every active column
 // (grid: column x problem); counts the columns active next iteration.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinal)
 cg_beta_kernel(const Desc* __restrict__ D, int par) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
@@ -679,7 +682,7 @@ pcg_start_kernel(const Desc* __restrict__ D, int nprob) {
 
 // Per-column start state: ||b||^2, r.z, ||r||^2, the stopping threshold
 // and the first active set (grid: column x problem).
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinal)
 pcg_start_final_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
@@ -780,7 +783,7 @@ refine_residual_kernel(const Desc* __restrict__ D, int nprob) {
 
 // Outer (refinement) test per column and the inner threshold of the next
 // FP32 solve (grid: column x problem).
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinal)
 refine_final_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
@@ -1511,7 +1514,7 @@ rotate_kernel(const Desc* __restrict__ D, int nprob) {
 
 // Per column: lambda = theta, relative change and residual; maxima over
 // the requested pairs for the stopping test (grid: column x problem).
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinal)
 rotate_final_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
@@ -1589,22 +1592,40 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
                   dim3(kBlock), weights_bytes(L.tr64, sizeof(double), 2), s,
                   L.d, L.nprob);
   klaunch(t, PARO_ST_START, pcg_start_final_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kBlock), 0, s, L.d);
+          dim3(kFinal), 0, s, L.d);
   return hipGetLastError();
 }
 
 template <typename T, int W>
+static void cg_spmm(Launch& L, int var, int par, hipStream_t s, Timing* t) {
+  const int tr = sizeof(T) == 4 ? L.tr32 : L.tr64;
+  const size_t smem = weights_bytes(tr, sizeof(T), 1);
+  const Desc* D = L.d;
+  if (var < 0) var = kCgDefaultVar<T>;
+  switch (var) {
+    case 0:
+      klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 0>, dim3(L.blocks),
+              dim3(kBlock), 0, s, D, L.nprob, par);
+      break;
+    case 1:
+      klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 1>, dim3(L.blocks),
+              dim3(kBlock), smem, s, D, L.nprob, par);
+      break;
+    default:
+      klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 2>, dim3(L.blocks),
+              dim3(kBlock), smem, s, D, L.nprob, par);
+  }
+}
+
+template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
-  klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W>, dim3(L.blocks),
-          dim3(kBlock),
-          kStageCg<T> ? weights_bytes(L.tr64, sizeof(T), 1) : 0, s,
-          (const Desc*)L.d, L.nprob, par);
+  cg_spmm<T, W>(L, L.cgvar, par, s, t);
   klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kBlock), 0, s, (const Desc*)L.d, par);
+          dim3(kFinal), 0, s, (const Desc*)L.d, par);
   klaunch(t, PARO_ST_CG_RUPD, rupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
           0, s, (const Desc*)L.d, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_beta_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kBlock), 0, s, (const Desc*)L.d, par);
+          dim3(kFinal), 0, s, (const Desc*)L.d, par);
   klaunch(t, PARO_ST_CG_PUPD, pupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
           0, s, (const Desc*)L.d, L.nprob, par);
 }
@@ -1628,12 +1649,45 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
   return hipGetLastError();
 }
 
+hipError_t launch_cg_spmm(Launch& L, bool fp32, int var, hipStream_t s) {
+  if (fp32) {
+    switch (L.v32u) {
+      case 4: cg_spmm<float, 4>(L, var, 0, s, nullptr); break;
+      case 2: cg_spmm<float, 2>(L, var, 0, s, nullptr); break;
+      case 1: cg_spmm<float, 1>(L, var, 0, s, nullptr); break;
+      default: cg_spmm<float, 0>(L, var, 0, s, nullptr);
+    }
+  } else {
+    switch (L.v64u) {
+      case 2: cg_spmm<double, 2>(L, var, 0, s, nullptr); break;
+      case 1: cg_spmm<double, 1>(L, var, 0, s, nullptr); break;
+      default: cg_spmm<double, 0>(L, var, 0, s, nullptr);
+    }
+  }
+  return hipGetLastError();
+}
+
+// Every column of every problem active in parity 0 (autotuner set-up; the
+// next source-solve start resets the column state).
+__global__ void __launch_bounds__(kFinal)
+all_active_kernel(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.x];
+  for (int c = threadIdx.x; c < d.ncols; c += kFinal) d.cs->act[0][c] = 1;
+  if (threadIdx.x == 0) d.cs->n_active[0] = d.ncols;
+}
+
+hipError_t launch_all_active(Launch& L, hipStream_t s) {
+  hipLaunchKernelGGL(all_active_kernel, dim3(L.nprob), dim3(kFinal), 0, s,
+                     (const Desc*)L.d);
+  return hipGetLastError();
+}
+
 hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_kernel,
                   dim3(L.blocks), dim3(kBlock),
                   weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
   klaunch(t, PARO_ST_REFINE, refine_final_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kBlock), 0, s, L.d);
+          dim3(kFinal), 0, s, L.d);
   return hipGetLastError();
 }
 
@@ -1728,7 +1782,7 @@ hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_ROTATE, rotate_kernel, dim3(L.blocks),
                   dim3(kBlock), smem, s, L.d, L.nprob);
   klaunch(t, PARO_ST_ROTATE, rotate_final_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kBlock), 0, s, (const Desc*)L.d);
+          dim3(kFinal), 0, s, (const Desc*)L.d);
   return hipGetLastError();
 }
 
