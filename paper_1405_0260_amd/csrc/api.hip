@@ -184,6 +184,7 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.Q32 = L.Q32 ? (float*)at(L.Q32) : nullptr;
   p.X32 = L.X32 ? (float*)at(L.X32) : nullptr;
   p.part = (double*)at(L.part);
+  p.cpart = L.cpart ? (double*)at(L.cpart) : nullptr;
   p.gpart = (double*)at(L.gpart);
   p.gsum = (double*)at(L.gsum);
   p.Ah = (double*)at(L.Ah);
@@ -249,6 +250,18 @@ void desc_init(Problem& p) {
   d.P32 = p.P32;
   d.Q32 = p.Q32;
   d.X32 = p.X32;
+  d.ntc = (int)cm_tiles(p.n);
+  if (p.X32) {  // the FP32 CG writes one partial per (column, tile)
+    d.cgp = p.cpart;
+    d.cgn = d.ntc;
+    d.cgstride = (long long)p.Nt * d.ntc;
+    d.pqp = p.cpart + 2 * d.cgstride;
+    d.pqn = (int)((p.n + kBlock - 1) / kBlock);
+  } else {
+    d.cgp = d.pqp = p.part;
+    d.cgn = d.pqn = d.ns;
+    d.cgstride = (long long)kGridMax * kNtMax;
+  }
   d.part = p.part;
   d.gpart = p.gpart;
   d.gsum = p.gsum;
@@ -699,7 +712,9 @@ int autotune(Problem& p, hipStream_t s) {
   float best = 1e30f;
   int best_var = -1, best_nb = ns;
   hipError_t err = hipSuccess;
-  for (int var = 0; var < 3 && err == hipSuccess; ++var) {
+  // FP64: three row-major variants; FP32: one kernel (grid only).
+  const int nvar = fp32 ? 1 : 3;
+  for (int var = 0; var < nvar && err == hipSuccess; ++var) {
     for (int nb : {ns, half}) {
       if (nb == half && half == ns) continue;
       c.tab[0].nb = nb;
@@ -767,6 +782,9 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.Q32 = f32 ? take(sizeof(float) * blk) : 0;
   L.X32 = f32 ? take(sizeof(float) * blk) : 0;
   L.part = take(sizeof(double) * 3 * (size_t)kGridMax * kNtMax);
+  L.cpart = f32 ? take(sizeof(double) * (size_t)Nt *
+                       (2 * cm_tiles(n) + (n + kBlock - 1) / kBlock))
+                : 0;
   L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
   L.gsum = take(sizeof(double) * (size_t)kGramY * gram_tiles(Nt));
   L.Ah = take(sizeof(double) * kNtMax * kNtMax);

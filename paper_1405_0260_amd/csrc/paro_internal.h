@@ -125,10 +125,16 @@ struct Desc {
   double* P;
   double* Q;
   double* B;              // stored right-hand sides (refinement), or null
-  float* R32;
+  float* R32;             // FP32 CG vectors, chunk-major (see cm_index)
   float* P32;
   float* Q32;
   float* X32;
+  int ntc;                // chunk-major tiles: ceil(n / kCmRows)
+  int cgn;                // partials per column of r.z and r.r (CG)
+  long long cgstride;     // ... the stride between the two quantities
+  double* cgp;            // ... and where they are (part, or cpart)
+  int pqn;                // partials per column of p.q (CG SpMM)
+  double* pqp;            // ... and where they are
   double* Y1;             // component SpMM / Gram operands
   double* Y2;
   double* part;
@@ -151,6 +157,15 @@ constexpr int vec32_of(int ncols) {
 }
 // Rows per streaming tile.
 constexpr int tile_rows(int ncols, int V) { return kBlock / (ncols / V); }
+
+// Tiles of the chunk-major FP32 CG kernels: kCmRpt rows per thread.
+// Element (row, c) of an FP32 CG vector with vector width V sits at
+// ((c / V) n + row) V + c % V: V-column chunks, each an n x V array.
+constexpr int kCmRpt = 4;
+constexpr int kCmRows = kBlock * kCmRpt;
+__host__ __device__ constexpr long long cm_tiles(long long n) {
+  return (n + kCmRows - 1) / kCmRows;
+}
 
 // Shape of one batched launch.
 struct Launch {
@@ -206,11 +221,13 @@ struct Problem {
   double* P;
   double* Q;
   double* B;              // right-hand sides (refinement mode)
-  float* R32;             // n x Nt blocks (FP32 inner solves)
+  float* R32;             // n x Nt blocks (FP32 inner solves, chunk-major)
   float* P32;
   float* Q32;
   float* X32;
   double* part;           // kGridMax * kNtMax * 3 reduction partials
+  double* cpart;          // FP32 CG partials: 2 Nt cm_tiles(n) (r.z, r.r),
+                          // then Nt ceil(n / kBlock) (p.q)
   double* gpart;          // Gram partials: kGramGrid * gram_tiles(Nt)
   double* gsum;           // kGramY * gram_tiles(Nt)
   double* Ah;             // Nt x Nt
@@ -241,7 +258,8 @@ struct Layout {
   size_t rowptr, col, valA, valM, valA32, dinv, dinv32, diagA, diagM,
       diagA32;
   size_t X, R, P, Q, B, R32, P32, Q32, X32;
-  size_t part, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt, flag;
+  size_t part, cpart, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt,
+      flag;
   size_t desc;
   size_t total;
 };

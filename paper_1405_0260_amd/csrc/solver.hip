@@ -142,22 +142,41 @@ __device__ void block_partials(const double (&acc)[NA][V], int ncols, int cpr,
 constexpr int kFinal = 64;
 
 // In a finalize kernel: the fixed-order sum of part[a][c][0..nb) (lane l
-// adds segments l, l + 64, ..., then a butterfly over the wavefront, whose
-// lanes all end with the same bits).  Every lane receives the sums.
+// adds segments l, l + 64, ... in ascending order, then a butterfly over
+// the wavefront, whose lanes all end with the same bits).  The loads of 16
+// segments per lane are issued together (clamped addresses, masked adds):
+// the partials come from every XCD, so each round trip costs the full
+// fabric latency.  Every lane receives the sums.
 template <int NA>
 __device__ __forceinline__ void column_sums(const double* __restrict__ part,
-                                            int c, int nb,
+                                            size_t stride, int c, int nb,
                                             double (&out)[NA]) {
+  constexpr int kU = 16;
   const int t = threadIdx.x;
+  double v[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) v[a] = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += kU * kFinal) {
+    double x[NA][kU];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const double* src = part + a * stride + (size_t)c * nb;
+#pragma unroll
+      for (int i = 0; i < kU; ++i)
+        x[a][i] = ldg(src + min(b0 + t + i * kFinal, nb - 1));
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int i = 0; i < kU; ++i)
+        v[a] = (b0 + t + i * kFinal < nb) ? v[a] + x[a][i] : v[a];
+  }
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
-    const double* src = part + a * kPartStride + (size_t)c * nb;
-    double v = 0.0;
-#pragma unroll 4
-    for (int b = t; b < nb; b += kFinal) v += ldg(src + b);
 #pragma unroll
-    for (int o = kFinal / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kFinal);
-    out[a] = v;
+    for (int o = kFinal / 2; o > 0; o >>= 1)
+      v[a] += __shfl_xor(v[a], o, kFinal);
+    out[a] = v[a];
   }
 }
 
@@ -329,7 +348,7 @@ __device__ __forceinline__ Geo geo_of(const Desc& d, int vb) {
                     (vw_ == 4) PARO_VB_CASE(4, BODY) else if (vw_ == 2)        \
                         PARO_VB_CASE(2, BODY) else PARO_VB_CASE(1, BODY))
 
-// FP64 or FP32 vectors of a problem's CG.
+// FP64 vectors of a problem's CG (row-major, like the orbitals).
 template <typename T>
 struct CgVecs;
 template <>
@@ -340,24 +359,16 @@ struct CgVecs<double> {
   __device__ CgVecs(const Desc& d)
       : diag(d.diagA), dinv(d.dinv), X(d.X), R(d.R), P(d.P), Q(d.Q) {}
 };
-template <>
-struct CgVecs<float> {
-  const float* diag;
-  const float* dinv;
-  float *X, *R, *P, *Q;
-  __device__ CgVecs(const Desc& d)
-      : diag(d.diagA32), dinv(d.dinv32), X(d.X32), R(d.R32), P(d.P32),
-        Q(d.Q32) {}
-};
 
-// Variants of the CG SpMM, chosen per problem shape by the autotuner: the
-// coefficients read directly (0) or staged per tile in LDS (1, 2), with
-// 15 (0, 1) or 8 (2) neighbour gathers in flight.  All variants perform
-// the same operations in the same order (identical results).
+
+// Variants of the FP64 CG SpMM, chosen per problem shape by the
+// autotuner: the coefficients read directly (0) or staged per tile in LDS
+// (1, 2), with 15 (0, 1) or 8 (2) neighbour gathers in flight.  All
+// variants perform the same operations in the same order (identical
+// results).  The FP32 CG has its own chunk-major kernels (below).
 constexpr bool cg_staged(int var) { return var != 0; }
 constexpr int cg_group(int var) { return var == 2 ? 8 : kStencil; }
-template <typename T>
-constexpr int kCgDefaultVar = sizeof(T) == 8 ? 1 : 0;
+constexpr int kCgDefaultVar = 1;
 
 // ------------------------------------------------------------------------
 // CG iteration: Q = A P on the active columns, with per-column p . q.
@@ -439,7 +450,7 @@ cg_alpha_kernel(const Desc* __restrict__ D, int par) {
   }
   if (!cs->act[par][c]) return;
   double tot[1];
-  column_sums<1>(d.part, c, d.ns, tot);
+  column_sums<1>(d.pqp, 0, c, d.pqn, tot);
   if (threadIdx.x == 0) {
     const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -522,7 +533,7 @@ cg_beta_kernel(const Desc* __restrict__ D, int par) {
     return;
   }
   double tot[2];
-  column_sums<2>(d.part, c, d.ns, tot);
+  column_sums<2>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
   if (threadIdx.x != 0) return;
   int next = 0;
   const double rz = tot[0], rr = tot[1];
@@ -598,6 +609,305 @@ pupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
     PARO_VB_LOOP32(D, nprob, VFIX, (pupd_body<T, VV>(d, vb, par, red)))
   else
     PARO_VB_LOOP64(D, nprob, VFIX, (pupd_body<T, VV>(d, vb, par, red)))
+}
+
+// ------------------------------------------------------------------------
+// FP32 inner CG in chunk-major layout.
+//
+// The FP32 CG vectors are internal to the library and stored as Nt / V
+// chunks of V columns, each an n x V array (cm_index), so a chunk of a
+// row range is contiguous and a neighbour gather of a wavefront reads one
+// contiguous kilobyte.  The work unit is (tile of kCmRows rows, chunk): a
+// thread owns kCmRpt rows of the tile (rows tid, tid + 256, ...) in one
+// chunk, accumulates its per-column products over them, and the unit ends
+// with one wavefront reduction.  Converged chunks are skipped whole.
+// Per-column partial sums are kept per (column, tile): cm_tiles(n) of them
+// per column whatever the grid, so no result depends on the block count or
+// on the batch.
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ size_t cm_index(long long n, long long row, int c,
+                                           int V) {
+  return ((size_t)(c / V) * n + row) * V + (c % V);
+}
+
+// Sum K values per lane over the wavefront (K a power of two, K <= 64).
+// The first log2 K steps halve the values each lane holds (a lane keeps
+// one half and adds its partner's copy of it), the rest are a butterfly;
+// lane l ends with the total of value l >> (6 - log2 K), with the same
+// bits on every lane that holds it.
+template <int K>
+__device__ __forceinline__ double wave_reduce_scatter(const double (&x)[K]) {
+  const int lane = threadIdx.x & 63;
+  double cur[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) cur[i] = x[i];
+#pragma unroll
+  for (int step = 0; step < 6; ++step) {
+    const int o = 32 >> step;
+    const int m = K >> step;
+    if (m > 1) {
+      const bool hi = (lane & o) != 0;
+      double keep[K / 2 > 0 ? K / 2 : 1], got[K / 2 > 0 ? K / 2 : 1];
+#pragma unroll
+      for (int i = 0; i < m / 2; ++i) {
+        const double send = hi ? cur[i] : cur[m / 2 + i];
+        keep[i] = hi ? cur[m / 2 + i] : cur[i];
+        got[i] = __shfl_xor(send, o, 64);
+      }
+#pragma unroll
+      for (int i = 0; i < m / 2; ++i) cur[i] = keep[i] + got[i];
+    } else {
+      cur[0] += __shfl_xor(cur[0], o, 64);
+    }
+  }
+  return cur[0];
+}
+
+// Per (column, tile) partials of a unit: K = NA * V values per lane
+// (quantity-major), reduced over the wavefront, then over the four
+// wavefronts in a fixed order; ws holds 4 * K doubles.  Ends with a
+// barrier, so ws may be reused at once.
+template <int NA, int V>
+__device__ __forceinline__ void cm_unit_partials(const double (&x)[NA * V],
+                                                 const Desc& d, int ch,
+                                                 long long t,
+                                                 double* __restrict__ ws) {
+  constexpr int K = NA * V;
+  constexpr int kGroup = 64 / K;
+  const double tot = wave_reduce_scatter<K>(x);
+  const int lane = threadIdx.x & 63;
+  if ((lane & (kGroup - 1)) == 0) ws[(threadIdx.x >> 6) * K + lane / kGroup] = tot;
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < K) {
+    const double s = ((ws[k] + ws[K + k]) + ws[2 * K + k]) + ws[3 * K + k];
+    const int a = k / V, c = ch * V + k % V;
+    stg(d.cgp + a * d.cgstride + (size_t)c * d.cgn + t, s);
+  }
+  __syncthreads();
+}
+
+// Unit u of a problem: tile u / cpr, chunk u % cpr.
+struct CmUnit {
+  long long t;
+  int ch;
+};
+__device__ __forceinline__ CmUnit cm_unit(long long u, int cpr) {
+  CmUnit r;
+  r.t = u / cpr;
+  r.ch = (int)(u - r.t * cpr);
+  return r;
+}
+
+// Q = A P on the active chunks of SpMM tile t (kBlock rows, one per
+// thread); per (column, tile) p . q.  The row's 15 coefficients stay in
+// registers across the chunks; each chunk ends with one wavefront
+// reduction of the thread's V products.
+template <int V>
+__device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
+                                             int par,
+                                             double* __restrict__ ws) {
+  const int tid = threadIdx.x;
+  const long long n = d.n;
+  const int mx = d.mx, my = d.my, mz = d.mz, ncols = d.ncols;
+  const int cpr = ncols / V;
+  const long long row = t * kBlock + tid;
+  const bool valid = row < n;
+  const long long rr = valid ? row : n - 1;
+  const int* act = d.cs->act[par];
+  const unsigned ur = (unsigned)rr;
+  const unsigned uq = ur / (unsigned)mx;
+  const int i = (int)(ur - uq * (unsigned)mx);
+  const unsigned uk = uq / (unsigned)my;
+  const int j = (int)(uq - uk * (unsigned)my);
+  const int k = (int)uk;
+  float a[kStencil];
+  int off[kStencil];
+#pragma unroll
+  for (int s = 0; s < kStencil; ++s) {
+    const int ox = st_off(s, 0), oy = st_off(s, 1), oz = st_off(s, 2);
+    const bool ok = (unsigned)(i + ox) < (unsigned)mx &&
+                    (unsigned)(j + oy) < (unsigned)my &&
+                    (unsigned)(k + oz) < (unsigned)mz;
+    off[s] = ok ? (ox + mx * (oy + my * oz)) * V : 0;
+    a[s] = ldg(d.diagA32 + (size_t)s * n + rr);
+  }
+  for (int ch = 0; ch < cpr; ++ch) {
+    if (!chunk_active(act, ch, V, ncols)) continue;
+    const float* Pr = d.P32 + ((size_t)ch * n + rr) * V;
+    float q[V], self[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) q[u] = self[u] = 0.0f;
+    if (valid) {
+      float x[kStencil][V];
+#pragma unroll
+      for (int s = 0; s < kStencil; ++s) ldv<float, V>(Pr + off[s], x[s]);
+#pragma unroll
+      for (int s = 0; s < kStencil; ++s)
+#pragma unroll
+        for (int u = 0; u < V; ++u) q[u] = fmaf(a[s], x[s][u], q[u]);
+#pragma unroll
+      for (int u = 0; u < V; ++u) self[u] = x[kSelf][u];
+      stv<float, V>(d.Q32 + ((size_t)ch * n + row) * V, q);
+    }
+    double pq[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) pq[u] = (double)self[u] * (double)q[u];
+    const double tot = wave_reduce_scatter<V>(pq);
+    constexpr int kGroup = 64 / V;
+    const int lane = tid & 63;
+    if ((lane & (kGroup - 1)) == 0)
+      ws[(tid >> 6) * ncols + ch * V + lane / kGroup] = tot;
+  }
+  __syncthreads();
+  for (int c = tid; c < ncols; c += kBlock) {
+    if (!ldg(act + c)) continue;
+    const double s = ((ws[c] + ws[ncols + c]) + ws[2 * ncols + c]) +
+                     ws[3 * ncols + c];
+    stg(d.pqp + (size_t)c * d.pqn + t, s);
+  }
+  __syncthreads();  // ws is reused by the next tile
+}
+
+// r -= alpha q, z = D^-1 r for chunk ch of tile t; r . z and r . r.
+template <int V>
+__device__ __forceinline__ void rupd_cm_unit(const Desc& d, long long t,
+                                             int ch, const float (&al)[V],
+                                             double* __restrict__ ws) {
+  const long long n = d.n;
+  double x[2 * V];
+#pragma unroll
+  for (int u = 0; u < 2 * V; ++u) x[u] = 0.0;
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const long long row = t * kCmRows + threadIdx.x + k * kBlock;
+    if (row >= n) break;
+    const size_t o = ((size_t)ch * n + row) * V;
+    float r[V], q[V];
+    ldv<float, V>(d.R32 + o, r);
+    ldv<float, V>(d.Q32 + o, q);
+    const float di = ldg(d.dinv32 + row);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      r[u] = fmaf(-al[u], q[u], r[u]);
+      x[u] += (double)r[u] * (double)(di * r[u]);
+      x[V + u] += (double)r[u] * (double)r[u];
+    }
+    stv<float, V>(d.R32 + o, r);
+  }
+  cm_unit_partials<2, V>(x, d, ch, t, ws);
+}
+
+// x += alpha p (columns active this iteration); p = D^-1 r + beta p
+// (columns active next iteration), chunk ch of tile t.
+template <int V>
+__device__ __forceinline__ void pupd_cm_unit(const Desc& d, long long t,
+                                             int ch, const float (&al)[V],
+                                             const float (&be)[V],
+                                             const bool (&nx)[V]) {
+  const long long n = d.n;
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const long long row = t * kCmRows + threadIdx.x + k * kBlock;
+    if (row >= n) break;
+    const size_t o = ((size_t)ch * n + row) * V;
+    float x[V], p[V], r[V];
+    ldv<float, V>(d.X32 + o, x);
+    ldv<float, V>(d.P32 + o, p);
+    ldv<float, V>(d.R32 + o, r);
+    const float di = ldg(d.dinv32 + row);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      x[u] = fmaf(al[u], p[u], x[u]);
+      p[u] = nx[u] ? fmaf(be[u], p[u], di * r[u]) : p[u];
+    }
+    stv<float, V>(d.X32 + o, x);
+    stv<float, V>(d.P32 + o, p);
+  }
+}
+
+// The units of the real block that runs this code, in its problem `d`
+// (owner of blockIdx.x), with VV (constexpr) the problem's FP32 width.
+// Launches queued after convergence (no active column) do nothing: the
+// column flags may be stale then.
+#define PARO_CM_LOOP(D, nprob, par, VFIX, BODY)                            \
+  {                                                                        \
+    const Desc& d = D[owner(D, nprob, blockIdx.x, false)];                 \
+    if (ldg(&d.cs->n_active[par]) == 0) return;                            \
+    const int lb_ = blockIdx.x - d.b0;                                     \
+    const int vw_ = VFIX ? VFIX : d.v32;                                   \
+    const int cpr_ = d.ncols / vw_;                                        \
+    for (TileWalk w_ = tile_walk((long long)d.ntc * cpr_, lb_, d.nb);      \
+         w_.t < w_.end; w_.t += w_.step) {                                 \
+      const CmUnit un = cm_unit(w_.t, cpr_);                               \
+      if (vw_ == 4) PARO_VB_CASE(4, BODY)                                  \
+      else if (vw_ == 2) PARO_VB_CASE(2, BODY)                             \
+      else PARO_VB_CASE(1, BODY)                                           \
+    }                                                                      \
+  }
+
+// The per-column CG scalars of chunk ch (uniform loads).
+template <int V>
+__device__ __forceinline__ bool cm_alpha(const ColState* cs, int par, int ch,
+                                         float (&al)[V]) {
+  bool any = false;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int c = ch * V + u;
+    const bool on = ldg(&cs->act[par][c]) != 0;
+    al[u] = on ? (float)ldg(&cs->alpha[c]) : 0.0f;
+    any = any || on;
+  }
+  return any;
+}
+
+template <int V>
+__device__ __forceinline__ void pupd_cm_chunk(const Desc& d, CmUnit un,
+                                              int par) {
+  const ColState* cs = d.cs;
+  float al[V], be[V];
+  bool nx[V];
+  if (!cm_alpha<V>(cs, par, un.ch, al)) return;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int c = un.ch * V + u;
+    nx[u] = ldg(&cs->act[par ^ 1][c]) != 0;
+    be[u] = nx[u] ? (float)ldg(&cs->beta[c]) : 0.0f;
+  }
+  pupd_cm_unit<V>(d, un.t, un.ch, al, be, nx);
+}
+
+template <int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * kNtMax];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (ldg(&d.cs->n_active[par]) == 0) return;  // queued after convergence
+  const int lb = blockIdx.x - d.b0;
+  const int vw = VFIX ? VFIX : d.v32;
+  for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end; w.t += w.step) {
+    if (vw == 4) PARO_VB_CASE(4, (spmm_cm_tile<VV>(d, w.t, par, ws)))
+    else if (vw == 2) PARO_VB_CASE(2, (spmm_cm_tile<VV>(d, w.t, par, ws)))
+    else PARO_VB_CASE(1, (spmm_cm_tile<VV>(d, w.t, par, ws)))
+  }
+}
+
+template <int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+rupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * 8];
+  PARO_CM_LOOP(D, nprob, par, VFIX, ({
+    float al[VV];
+    if (cm_alpha<VV>(d.cs, par, un.ch, al))
+      rupd_cm_unit<VV>(d, un.t, un.ch, al, ws);
+  }))
+}
+
+template <int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+pupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  PARO_CM_LOOP(D, nprob, par, VFIX, (pupd_cm_chunk<VV>(d, un, par)))
 }
 
 // ------------------------------------------------------------------------
@@ -689,7 +999,7 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
   if (c >= d.ncols) return;
   ColState* cs = d.cs;
   double tot[3];
-  column_sums<3>(d.part, c, d.ns, tot);
+  column_sums<3>(d.part, kPartStride, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   const double bb = tot[0], rz = tot[1], rr = tot[2];
   const double rtol = d.rtol;
@@ -767,9 +1077,12 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
       z32[v] = 0.0f;
       acc[1][v] += (double)r32[v] * (double)p32[v];
     }
-    stv<float, V>(d.R32 + o, r32);
-    stv<float, V>(d.P32 + o, p32);
-    stv<float, V>(d.X32 + o, z32);
+    // FP32 vectors are chunk-major; the V FP64 columns of this thread lie
+    // in one FP32 chunk (the FP32 width is a multiple of the FP64 one).
+    const size_t o32 = cm_index(d.n, row, g.ch * V, d.v32);
+    stv<float, V>(d.R32 + o32, r32);
+    stv<float, V>(d.P32 + o32, p32);
+    stv<float, V>(d.X32 + o32, z32);
   }
   block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
 }
@@ -797,7 +1110,7 @@ refine_final_kernel(const Desc* __restrict__ D) {
     return;
   }
   double tot[2];
-  column_sums<2>(d.part, c, d.ns, tot);
+  column_sums<2>(d.part, kPartStride, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   int a = 0;
   const double rr = tot[0], rtol = d.rtol, irt = d.inner_rtol;
@@ -842,7 +1155,7 @@ __device__ __forceinline__ void refine_update_body(const Desc& d, int vb,
     double x[V];
     float dx[V];
     ldv<double, V>(d.X + o, x);
-    ldv<float, V>(d.X32 + o, dx);
+    ldv<float, V>(d.X32 + cm_index(d.n, row, g.ch * V, d.v32), dx);
 #pragma unroll
     for (int v = 0; v < V; ++v) x[v] += a[v] ? (double)dx[v] : 0.0;
     stv<double, V>(d.X + o, x);
@@ -1521,7 +1834,7 @@ rotate_final_kernel(const Desc* __restrict__ D) {
   const int ncols = d.ncols;
   if (c >= ncols) return;
   double tot[2];
-  column_sums<2>(d.part, c, d.ns, tot);
+  column_sums<2>(d.part, kPartStride, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   const double* theta = d.theta;
   double lmax = 0.0;
@@ -1596,24 +1909,34 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
   return hipGetLastError();
 }
 
+// FP32 (chunk-major) CG SpMM (one kernel; the tuner picks the grid).
+template <int W>
+static void cg_spmm_cm(Launch& L, int par, hipStream_t s, Timing* t) {
+  klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<W>, dim3(L.blocks),
+          dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
+}
+
 template <typename T, int W>
 static void cg_spmm(Launch& L, int var, int par, hipStream_t s, Timing* t) {
-  const int tr = sizeof(T) == 4 ? L.tr32 : L.tr64;
-  const size_t smem = weights_bytes(tr, sizeof(T), 1);
-  const Desc* D = L.d;
-  if (var < 0) var = kCgDefaultVar<T>;
-  switch (var) {
-    case 0:
-      klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 0>, dim3(L.blocks),
-              dim3(kBlock), 0, s, D, L.nprob, par);
-      break;
-    case 1:
-      klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 1>, dim3(L.blocks),
-              dim3(kBlock), smem, s, D, L.nprob, par);
-      break;
-    default:
-      klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 2>, dim3(L.blocks),
-              dim3(kBlock), smem, s, D, L.nprob, par);
+  if constexpr (sizeof(T) == 4) {
+    cg_spmm_cm<W>(L, par, s, t);
+  } else {
+    const size_t smem = weights_bytes(L.tr64, sizeof(T), 1);
+    const Desc* D = L.d;
+    if (var < 0) var = kCgDefaultVar;
+    switch (var) {
+      case 0:
+        klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 0>, dim3(L.blocks),
+                dim3(kBlock), 0, s, D, L.nprob, par);
+        break;
+      case 1:
+        klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 1>, dim3(L.blocks),
+                dim3(kBlock), smem, s, D, L.nprob, par);
+        break;
+      default:
+        klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 2>, dim3(L.blocks),
+                dim3(kBlock), smem, s, D, L.nprob, par);
+    }
   }
 }
 
@@ -1622,12 +1945,20 @@ static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
   cg_spmm<T, W>(L, L.cgvar, par, s, t);
   klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
           dim3(kFinal), 0, s, (const Desc*)L.d, par);
-  klaunch(t, PARO_ST_CG_RUPD, rupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
-          0, s, (const Desc*)L.d, L.nprob, par);
+  if constexpr (sizeof(T) == 4)
+    klaunch(t, PARO_ST_CG_RUPD, rupd_cm_kernel<W>, dim3(L.blocks),
+            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
+  else
+    klaunch(t, PARO_ST_CG_RUPD, rupd_kernel<T, W>, dim3(L.blocks),
+            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_beta_kernel, dim3(L.maxcols, L.nprob),
           dim3(kFinal), 0, s, (const Desc*)L.d, par);
-  klaunch(t, PARO_ST_CG_PUPD, pupd_kernel<T, W>, dim3(L.blocks), dim3(kBlock),
-          0, s, (const Desc*)L.d, L.nprob, par);
+  if constexpr (sizeof(T) == 4)
+    klaunch(t, PARO_ST_CG_PUPD, pupd_cm_kernel<W>, dim3(L.blocks),
+            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
+  else
+    klaunch(t, PARO_ST_CG_PUPD, pupd_kernel<T, W>, dim3(L.blocks),
+            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
 }
 
 hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
