@@ -393,17 +393,16 @@ typedef struct paro_timing {
 void paro_set_graphs(int on);
 
 /* Autotuner (on by default): at assembly, the CG SpMM of each new problem
- * shape (grid, N + m, precision) is timed in every kernel variant
- * (coefficients staged in LDS or read directly; 15 or 8 neighbour gathers
- * in flight) with the full and the halved real block count, and the
- * fastest is kept for the shape for the rest of the process.  No choice
- * changes the arithmetic or the results.  paro_set_autotune(0) keeps the
- * defaults; paro_tuned reports a problem's variant (-1: default) and its
- * real block count. */
+ * shape (grid, N + m, precision) is timed with the full and the halved
+ * real block count, and the faster is kept for the shape for the rest of
+ * the process.  The choice never changes the arithmetic or the results
+ * (reductions run over per-tile partial sums fixed by the problem).
+ * paro_set_autotune(0) keeps the defaults; paro_tuned reports a problem's
+ * real block count (and a reserved variant field: -1 untuned, else 0). */
 void paro_set_autotune(int on);
 int paro_tuned(const paro_problem* p, int32_t* variant, int32_t* blocks);
-/* Pin a problem's CG SpMM variant (-1 default, 0..2) and real block count
- * (a multiple of 8, at most its reduction segment count). */
+/* Pin a problem's real block count (a multiple of 8, at most its
+ * reduction segment count); variant is reserved and must be -1 or 0. */
 int paro_set_tuning(paro_problem* p, int32_t variant, int32_t blocks);
 
 /* Turn per-launch event timing on (1) or off (0); clears the sums. */

@@ -372,14 +372,14 @@ def paro_set_autotune(on: bool = True):
 
 
 def paro_tuned(p: Problem):
-    """(kernel variant, real block count) chosen for the problem."""
+    """(reserved variant field, real block count) chosen for the problem."""
     v, b = c_i32(), c_i32()
     _check(lib().paro_tuned(p.handle, ctypes.byref(v), ctypes.byref(b)))
     return v.value, b.value
 
 
 def paro_set_tuning(p: Problem, variant: int, blocks: int):
-    """Pin the CG SpMM variant and real block count of a problem."""
+    """Pin the real block count of a problem (variant: -1 or 0)."""
     _check(lib().paro_set_tuning(p.handle, variant, blocks))
 
 

@@ -179,12 +179,13 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.P = (double*)at(L.P);
   p.Q = (double*)at(L.Q);
   p.B = L.B ? (double*)at(L.B) : nullptr;
+  p.Xc = L.Xc ? (double*)at(L.Xc) : nullptr;
   p.R32 = L.R32 ? (float*)at(L.R32) : nullptr;
   p.P32 = L.P32 ? (float*)at(L.P32) : nullptr;
   p.Q32 = L.Q32 ? (float*)at(L.Q32) : nullptr;
   p.X32 = L.X32 ? (float*)at(L.X32) : nullptr;
   p.part = (double*)at(L.part);
-  p.cpart = L.cpart ? (double*)at(L.cpart) : nullptr;
+  p.cpart = (double*)at(L.cpart);
   p.gpart = (double*)at(L.gpart);
   p.gsum = (double*)at(L.gsum);
   p.Ah = (double*)at(L.Ah);
@@ -246,22 +247,18 @@ void desc_init(Problem& p) {
   d.P = p.P;
   d.Q = p.Q;
   d.B = p.B;
+  d.Xc = p.Xc;
   d.R32 = p.R32;
   d.P32 = p.P32;
   d.Q32 = p.Q32;
   d.X32 = p.X32;
   d.ntc = (int)cm_tiles(p.n);
-  if (p.X32) {  // the FP32 CG writes one partial per (column, tile)
-    d.cgp = p.cpart;
-    d.cgn = d.ntc;
-    d.cgstride = (long long)p.Nt * d.ntc;
-    d.pqp = p.cpart + 2 * d.cgstride;
-    d.pqn = (int)((p.n + kBlock - 1) / kBlock);
-  } else {
-    d.cgp = d.pqp = p.part;
-    d.cgn = d.pqn = d.ns;
-    d.cgstride = (long long)kGridMax * kNtMax;
-  }
+  // The CG kernels write one partial per (column, tile).
+  d.cgp = p.cpart;
+  d.cgn = d.ntc;
+  d.cgstride = (long long)p.Nt * d.ntc;
+  d.pqp = p.cpart + 2 * d.cgstride;
+  d.pqn = (int)((p.n + kBlock - 1) / kBlock);
   d.part = p.part;
   d.gpart = p.gpart;
   d.gsum = p.gsum;
@@ -308,9 +305,6 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
     if ((tab[i].ncols + 15) / 16 != L.nt16) L.nt16_mixed = 1;
   }
   if (n > 0 && (tab[0].ncols + 15) / 16 != L.nt16) L.nt16_mixed = 1;
-  L.cgvar = n > 0 ? tab[0].cg_var : -1;
-  for (int i = 1; i < n; ++i)
-    if (tab[i].cg_var != L.cgvar) L.cgvar = -1;
   return L;
 }
 
@@ -535,7 +529,12 @@ int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
 
 // Source solves of one step, from the state prepared by the start kernel.
 int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
-  if (c.precision == PARO_FP64) return run_cg(c, false, s, 0);
+  if (c.precision == PARO_FP64) {
+    const int rc = run_cg(c, false, s, 0);
+    if (rc) return rc;
+    HIP_OR_FAIL(launch_cm_unpack(c.L, s, c.timing));
+    return PARO_OK;
+  }
   for (int pass = 0;; ++pass) {
     HIP_OR_FAIL(launch_refine_residual(c.L, s, c.timing));
     int pw[2];
@@ -693,6 +692,8 @@ int autotune(Problem& p, hipStream_t s) {
     }
   }
   const bool fp32 = p.opts.precision == PARO_FP32_INNER;
+  // Timing runs on zero vectors (the next source-solve start overwrites
+  // them).
   const size_t vbytes = (fp32 ? 4 : 8) * (size_t)p.n * p.Nt;
   HIP_OR_FAIL(hipMemsetAsync(fp32 ? (void*)p.P32 : (void*)p.P, 0, vbytes, s));
   Ctx c;
@@ -710,31 +711,25 @@ int autotune(Problem& p, hipStream_t s) {
   const int ns = p.hd.ns;
   const int half = std::max(8, ns / 2 / 8 * 8);
   float best = 1e30f;
-  int best_var = -1, best_nb = ns;
+  int best_var = 0, best_nb = ns;
   hipError_t err = hipSuccess;
-  // FP64: three row-major variants; FP32: one kernel (grid only).
-  const int nvar = fp32 ? 1 : 3;
-  for (int var = 0; var < nvar && err == hipSuccess; ++var) {
-    for (int nb : {ns, half}) {
-      if (nb == half && half == ns) continue;
-      c.tab[0].nb = nb;
-      if ((rc = upload(c, s)) != PARO_OK) break;
-      if ((err = launch_cg_spmm(c.L, fp32, var, s)) != hipSuccess) break;
-      if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
-      for (int k = 0; k < 5 && err == hipSuccess; ++k)
-        err = launch_cg_spmm(c.L, fp32, var, s);
-      if (err == hipSuccess) err = hipEventRecord(e1, s);
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-      if (err != hipSuccess) break;
-      if (ms < best) {
-        best = ms;
-        best_var = var;
-        best_nb = nb;
-      }
+  for (int nb : {ns, half}) {
+    if (nb == half && half == ns) continue;
+    c.tab[0].nb = nb;
+    if ((rc = upload(c, s)) != PARO_OK) break;
+    if ((err = launch_cg_spmm(c.L, fp32, s)) != hipSuccess) break;
+    if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+    for (int k = 0; k < 5 && err == hipSuccess; ++k)
+      err = launch_cg_spmm(c.L, fp32, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) break;
+    if (ms < best) {
+      best = ms;
+      best_nb = nb;
     }
-    if (rc) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -777,14 +772,14 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.P = take(sizeof(double) * blk);
   L.Q = take(sizeof(double) * blk);
   L.B = f32 ? take(sizeof(double) * blk) : 0;
+  L.Xc = f32 ? 0 : take(sizeof(double) * blk);
   L.R32 = f32 ? take(sizeof(float) * blk) : 0;
   L.P32 = f32 ? take(sizeof(float) * blk) : 0;
   L.Q32 = f32 ? take(sizeof(float) * blk) : 0;
   L.X32 = f32 ? take(sizeof(float) * blk) : 0;
   L.part = take(sizeof(double) * 3 * (size_t)kGridMax * kNtMax);
-  L.cpart = f32 ? take(sizeof(double) * (size_t)Nt *
-                       (2 * cm_tiles(n) + (n + kBlock - 1) / kBlock))
-                : 0;
+  L.cpart = take(sizeof(double) * (size_t)Nt *
+                 (2 * cm_tiles(n) + (n + kBlock - 1) / kBlock));
   L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
   L.gsum = take(sizeof(double) * (size_t)kGramY * gram_tiles(Nt));
   L.Ah = take(sizeof(double) * kNtMax * kNtMax);
@@ -1206,8 +1201,8 @@ void paro_set_autotune(int on) { g_autotune_on.store(on ? 1 : 0); }
 int paro_set_tuning(paro_problem* h, int32_t variant, int32_t blocks) {
   if (!h) return fail(PARO_EINVAL, "NULL problem");
   Problem& p = h->p;
-  if (variant < -1 || variant > 2)
-    return fail(PARO_EINVAL, "variant must be -1..2");
+  if (variant < -1 || variant > 0)
+    return fail(PARO_EINVAL, "variant must be -1 or 0");
   if (blocks < 8 || blocks > p.hd.ns || blocks % 8)
     return fail(PARO_EINVAL, "blocks must be a multiple of 8 in [8, %d]",
                 p.hd.ns);

@@ -115,7 +115,7 @@ struct Desc {
   const double* diagM;
   const float* diagA32;
   int mx, my, mz;         // interior vertices per axis (rows = mx my mz)
-  int cg_var;             // CG SpMM variant (autotuner), -1: default
+  int cg_var;             // reserved (one CG SpMM kernel): -1 or 0
   const double* U0;       // start of the source solves (x0), gathered
   const double* Bin;      // given right-hand sides, or null
   double* lam;            // Ritz values (in: previous, out: new), or null
@@ -125,6 +125,7 @@ struct Desc {
   double* P;
   double* Q;
   double* B;              // stored right-hand sides (refinement), or null
+  double* Xc;             // FP64 CG iterate, chunk-major (FP64 mode only)
   float* R32;             // FP32 CG vectors, chunk-major (see cm_index)
   float* P32;
   float* Q32;
@@ -180,7 +181,6 @@ struct Launch {
   int vmax64;             // widest FP64 vector of the table
   int v64u, v32u;         // common vector width of all problems, or 0
   int nt16_mixed;         // problems differ in ceil(ncols / 16)
-  int cgvar;              // common CG SpMM variant, or -1 (default)
 };
 
 // Per-problem step summary for the host (one PollReport per problem).
@@ -221,6 +221,7 @@ struct Problem {
   double* P;
   double* Q;
   double* B;              // right-hand sides (refinement mode)
+  double* Xc;             // chunk-major FP64 CG iterate (FP64 mode)
   float* R32;             // n x Nt blocks (FP32 inner solves, chunk-major)
   float* P32;
   float* Q32;
@@ -257,7 +258,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 struct Layout {
   size_t rowptr, col, valA, valM, valA32, dinv, dinv32, diagA, diagM,
       diagA32;
-  size_t X, R, P, Q, B, R32, P32, Q32, X32;
+  size_t X, R, P, Q, B, Xc, R32, P32, Q32, X32;
   size_t part, cpart, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
   size_t desc;
@@ -287,9 +288,11 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
                            Timing* t);
 // FP32 inner solves inside FP64 refinement.
 hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t);
-// Autotuner: the CG SpMM alone (parity 0) in variant `var`, and a set-up
-// making every column active.
-hipError_t launch_cg_spmm(Launch& L, bool fp32, int var, hipStream_t s);
+// Autotuner: the CG SpMM alone (parity 0), and a set-up making every
+// column active.
+hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s);
+// FP64 source solves: the orbitals X receive the chunk-major iterate Xc.
+hipError_t launch_cm_unpack(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_all_active(Launch& L, hipStream_t s);
 hipError_t launch_refine_update(Launch& L, hipStream_t s, Timing* t);
 // Poll of the table into host-visible memory: out[1] = active CG columns

@@ -348,88 +348,6 @@ __device__ __forceinline__ Geo geo_of(const Desc& d, int vb) {
                     (vw_ == 4) PARO_VB_CASE(4, BODY) else if (vw_ == 2)        \
                         PARO_VB_CASE(2, BODY) else PARO_VB_CASE(1, BODY))
 
-// FP64 vectors of a problem's CG (row-major, like the orbitals).
-template <typename T>
-struct CgVecs;
-template <>
-struct CgVecs<double> {
-  const double* diag;
-  const double* dinv;
-  double *X, *R, *P, *Q;
-  __device__ CgVecs(const Desc& d)
-      : diag(d.diagA), dinv(d.dinv), X(d.X), R(d.R), P(d.P), Q(d.Q) {}
-};
-
-
-// Variants of the FP64 CG SpMM, chosen per problem shape by the
-// autotuner: the coefficients read directly (0) or staged per tile in LDS
-// (1, 2), with 15 (0, 1) or 8 (2) neighbour gathers in flight.  All
-// variants perform the same operations in the same order (identical
-// results).  The FP32 CG has its own chunk-major kernels (below).
-constexpr bool cg_staged(int var) { return var != 0; }
-constexpr int cg_group(int var) { return var == 2 ? 8 : kStencil; }
-constexpr int kCgDefaultVar = 1;
-
-// ------------------------------------------------------------------------
-// CG iteration: Q = A P on the active columns, with per-column p . q.
-// ------------------------------------------------------------------------
-template <typename T, int V, int VAR>
-__device__ __forceinline__ void spmm_cg_body(const Desc& d, int vb, int par,
-    double* __restrict__ red) {
-  constexpr bool kStaged = cg_staged(VAR);
-  constexpr int kG = cg_group(VAR);
-  const Geo g = geo_of<V>(d, vb);
-  const int ncols = d.ncols;
-  // Active count and column flags are read together (one round trip).
-  const int nact = ldg(&d.cs->n_active[par]);
-  const bool mine = chunk_active(d.cs->act[par], g.ch, V, ncols);
-  if (nact == 0) return;
-  const CgVecs<T> vs(d);
-  const bool on = g.lr < g.tr && mine;
-  extern __shared__ unsigned char smem[];
-  T* wa = reinterpret_cast<T*>(smem);
-  double acc[1][V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
-  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-       w.t += w.step) {
-    const long long r0 = w.t * g.tr;
-    const int rows = (int)min((long long)g.tr, d.n - r0);
-    if (kStaged)
-      stage_weights<T, false>(vs.diag, nullptr, d.n, r0, rows, g.tr, wa,
-                              nullptr);
-    if (!on || g.lr >= rows) continue;
-    const long long row = r0 + g.lr;
-    T q[V], unused[V], po[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) q[v] = T(0);
-    if (kStaged)
-      stencil_product<T, T, V, false, kG, true>(
-          wa + g.lr, nullptr, g.tr, d.mx, d.my, d.mz, row, vs.P, ncols,
-          g.ch * V, q, unused, po);
-    else
-      stencil_product<T, T, V, false, kG, false>(
-          vs.diag + row, nullptr, d.n, d.mx, d.my, d.mz, row, vs.P, ncols,
-          g.ch * V, q, unused, po);
-    stv<T, V>(vs.Q + (size_t)row * ncols + g.ch * V, q);
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[0][v] += (double)po[v] * (double)q[v];
-  }
-  block_partials<V, 1>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
-}
-
-template <typename T, int VFIX, int VAR>
-__global__ void PARO_STREAM_BOUNDS
-spmm_cg_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
-  if constexpr (sizeof(T) == 4)
-    PARO_VB_LOOP32(D, nprob, VFIX,
-                   (spmm_cg_body<T, VV, VAR>(d, vb, par, red)))
-  else
-    PARO_VB_LOOP64(D, nprob, VFIX,
-                   (spmm_cg_body<T, VV, VAR>(d, vb, par, red)))
-}
-
 // alpha_c = (r.z)_c / (p.q)_c for the active columns (grid: column x
 // problem).  Also clears the next parity's active count for cg_beta.
 __global__ void __launch_bounds__(kFinal)
@@ -460,64 +378,6 @@ cg_alpha_kernel(const Desc* __restrict__ D, int par) {
       cs->alpha[c] = cs->rz[c] / pq;
     }
   }
-}
-
-// r -= alpha q, z = D^-1 r, partial r.z and r.r.
-template <typename T, int V>
-__device__ __forceinline__ void rupd_body(const Desc& d, int vb, int par,
-    double* __restrict__ red) {
-  const Geo g = geo_of<V>(d, vb);
-  const ColState* cs = d.cs;
-  const CgVecs<T> vs(d);
-  const int ncols = d.ncols;
-  // Per-column state read with independent (clamped) loads.
-  const int nact = ldg(&cs->n_active[par]);
-  T al[V];
-  bool any = false;
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const int c = g.ch * V + v, cc = min(c, ncols - 1);
-    const int a = ldg(&cs->act[par][cc]);
-    const double alpha = ldg(&cs->alpha[cc]);
-    const bool col_on = c < ncols && a != 0;
-    al[v] = col_on ? (T)alpha : T(0);
-    any = any || col_on;
-  }
-  if (nact == 0) return;
-  const bool on = g.lr < g.tr && any;
-  double acc[2][V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
-  if (on) {
-    for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-         w.t += w.step) {
-      const long long row = w.t * g.tr + g.lr;
-      if (row >= d.n) continue;
-      const size_t o = (size_t)row * ncols + g.ch * V;
-      T r[V], q[V];
-      ldv<T, V>(vs.R + o, r);
-      ldv<T, V>(vs.Q + o, q);
-      const T di = ldg(vs.dinv + row);
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        r[v] = fma(-al[v], q[v], r[v]);
-        acc[0][v] += (double)r[v] * (double)(di * r[v]);
-        acc[1][v] += (double)r[v] * (double)r[v];
-      }
-      stv<T, V>(vs.R + o, r);
-    }
-  }
-  block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
-}
-
-template <typename T, int VFIX>
-__global__ void PARO_STREAM_BOUNDS
-rupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double red[2 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
-  if constexpr (sizeof(T) == 4)
-    PARO_VB_LOOP32(D, nprob, VFIX, (rupd_body<T, VV>(d, vb, par, red)))
-  else
-    PARO_VB_LOOP64(D, nprob, VFIX, (rupd_body<T, VV>(d, vb, par, red)))
 }
 
 // beta_c, iteration count and the stopping test of every active column
@@ -554,70 +414,14 @@ cg_beta_kernel(const Desc* __restrict__ D, int par) {
   atomicAdd(&cs->cg_col_iters, 1ULL);
 }
 
-// x += alpha p (columns active this iteration); p = D^-1 r + beta p
-// (columns active next iteration).
-template <typename T, int V>
-__device__ __forceinline__ void pupd_body(const Desc& d, int vb, int par,
-    double* __restrict__ red) {
-  const Geo g = geo_of<V>(d, vb);
-  const ColState* cs = d.cs;
-  const int ncols = d.ncols;
-  // Per-column state read with independent (clamped) loads.
-  const int nact = ldg(&cs->n_active[par]);
-  T al[V], be[V];
-  bool nx[V];
-  bool any = false;
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const int c = g.ch * V + v, cc = min(c, ncols - 1);
-    const int a0 = ldg(&cs->act[par][cc]), a1 = ldg(&cs->act[par ^ 1][cc]);
-    const double alpha = ldg(&cs->alpha[cc]), beta = ldg(&cs->beta[cc]);
-    const bool a = c < ncols && a0 != 0;
-    nx[v] = c < ncols && a1 != 0;
-    al[v] = a ? (T)alpha : T(0);
-    be[v] = nx[v] ? (T)beta : T(0);
-    any = any || a;
-  }
-  if (nact == 0) return;
-  if (g.lr >= g.tr || !any) return;
-  const CgVecs<T> vs(d);
-  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-       w.t += w.step) {
-    const long long row = w.t * g.tr + g.lr;
-    if (row >= d.n) continue;
-    const size_t o = (size_t)row * ncols + g.ch * V;
-    T x[V], p[V], r[V];
-    ldv<T, V>(vs.X + o, x);
-    ldv<T, V>(vs.P + o, p);
-    ldv<T, V>(vs.R + o, r);
-    const T di = ldg(vs.dinv + row);
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      x[v] = fma(al[v], p[v], x[v]);
-      p[v] = nx[v] ? fma(be[v], p[v], di * r[v]) : p[v];
-    }
-    stv<T, V>(vs.X + o, x);
-    stv<T, V>(vs.P + o, p);
-  }
-}
-
-template <typename T, int VFIX>
-__global__ void PARO_STREAM_BOUNDS
-pupd_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double red[1 * kBlock * (VFIX ? VFIX : (sizeof(T) == 4 ? 4 : 2))];
-  if constexpr (sizeof(T) == 4)
-    PARO_VB_LOOP32(D, nprob, VFIX, (pupd_body<T, VV>(d, vb, par, red)))
-  else
-    PARO_VB_LOOP64(D, nprob, VFIX, (pupd_body<T, VV>(d, vb, par, red)))
-}
-
 // ------------------------------------------------------------------------
-// FP32 inner CG in chunk-major layout.
+// The CG of the source solves, in chunk-major layout.
 //
-// The FP32 CG vectors are internal to the library and stored as Nt / V
-// chunks of V columns, each an n x V array (cm_index), so a chunk of a
-// row range is contiguous and a neighbour gather of a wavefront reads one
-// contiguous kilobyte.  The work unit is (tile of kCmRows rows, chunk): a
+// The CG vectors (FP64: R, P, Q and Xc, a copy of the iterate; FP32 inner
+// solves: R32, P32, Q32, X32) are internal to the library and stored as
+// Nt / V chunks of V columns (V values = 16 bytes at full width), each an
+// n x V array (cm_index), so a chunk of a row range is contiguous and a
+// neighbour gather of a wavefront reads one contiguous kilobyte.  The work unit is (tile of kCmRows rows, chunk): a
 // thread owns kCmRpt rows of the tile (rows tid, tid + 256, ...) in one
 // chunk, accumulates its per-column products over them, and the unit ends
 // with one wavefront reduction.  Converged chunks are skipped whole.
@@ -688,6 +492,31 @@ __device__ __forceinline__ void cm_unit_partials(const double (&x)[NA * V],
   __syncthreads();
 }
 
+// The CG operands of a problem in value type T.
+template <typename T>
+struct CmVecs;
+template <>
+struct CmVecs<double> {
+  const double* diag;
+  const double* dinv;
+  double *X, *R, *P, *Q;
+  __device__ CmVecs(const Desc& d)
+      : diag(d.diagA), dinv(d.dinv), X(d.Xc), R(d.R), P(d.P), Q(d.Q) {}
+};
+template <>
+struct CmVecs<float> {
+  const float* diag;
+  const float* dinv;
+  float *X, *R, *P, *Q;
+  __device__ CmVecs(const Desc& d)
+      : diag(d.diagA32), dinv(d.dinv32), X(d.X32), R(d.R32), P(d.P32),
+        Q(d.Q32) {}
+};
+template <typename T>
+__device__ __forceinline__ int cm_width(const Desc& d) {
+  return sizeof(T) == 4 ? d.v32 : d.v64;
+}
+
 // Unit u of a problem: tile u / cpr, chunk u % cpr.
 struct CmUnit {
   long long t;
@@ -704,10 +533,11 @@ __device__ __forceinline__ CmUnit cm_unit(long long u, int cpr) {
 // thread); per (column, tile) p . q.  The row's 15 coefficients stay in
 // registers across the chunks; each chunk ends with one wavefront
 // reduction of the thread's V products.
-template <int V>
+template <typename T, int V>
 __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
                                              int par,
                                              double* __restrict__ ws) {
+  const CmVecs<T> vs(d);
   const int tid = threadIdx.x;
   const long long n = d.n;
   const int mx = d.mx, my = d.my, mz = d.mz, ncols = d.ncols;
@@ -722,7 +552,7 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
   const unsigned uk = uq / (unsigned)my;
   const int j = (int)(uq - uk * (unsigned)my);
   const int k = (int)uk;
-  float a[kStencil];
+  T a[kStencil];
   int off[kStencil];
 #pragma unroll
   for (int s = 0; s < kStencil; ++s) {
@@ -731,25 +561,25 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
                     (unsigned)(j + oy) < (unsigned)my &&
                     (unsigned)(k + oz) < (unsigned)mz;
     off[s] = ok ? (ox + mx * (oy + my * oz)) * V : 0;
-    a[s] = ldg(d.diagA32 + (size_t)s * n + rr);
+    a[s] = ldg(vs.diag + (size_t)s * n + rr);
   }
   for (int ch = 0; ch < cpr; ++ch) {
     if (!chunk_active(act, ch, V, ncols)) continue;
-    const float* Pr = d.P32 + ((size_t)ch * n + rr) * V;
-    float q[V], self[V];
+    const T* Pr = vs.P + ((size_t)ch * n + rr) * V;
+    T q[V], self[V];
 #pragma unroll
-    for (int u = 0; u < V; ++u) q[u] = self[u] = 0.0f;
+    for (int u = 0; u < V; ++u) q[u] = self[u] = T(0);
     if (valid) {
-      float x[kStencil][V];
+      T x[kStencil][V];
 #pragma unroll
-      for (int s = 0; s < kStencil; ++s) ldv<float, V>(Pr + off[s], x[s]);
+      for (int s = 0; s < kStencil; ++s) ldv<T, V>(Pr + off[s], x[s]);
 #pragma unroll
       for (int s = 0; s < kStencil; ++s)
 #pragma unroll
-        for (int u = 0; u < V; ++u) q[u] = fmaf(a[s], x[s][u], q[u]);
+        for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
 #pragma unroll
       for (int u = 0; u < V; ++u) self[u] = x[kSelf][u];
-      stv<float, V>(d.Q32 + ((size_t)ch * n + row) * V, q);
+      stv<T, V>(vs.Q + ((size_t)ch * n + row) * V, q);
     }
     double pq[V];
 #pragma unroll
@@ -771,11 +601,12 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
 }
 
 // r -= alpha q, z = D^-1 r for chunk ch of tile t; r . z and r . r.
-template <int V>
+template <typename T, int V>
 __device__ __forceinline__ void rupd_cm_unit(const Desc& d, long long t,
-                                             int ch, const float (&al)[V],
+                                             int ch, const T (&al)[V],
                                              double* __restrict__ ws) {
   const long long n = d.n;
+  const CmVecs<T> vs(d);
   double x[2 * V];
 #pragma unroll
   for (int u = 0; u < 2 * V; ++u) x[u] = 0.0;
@@ -784,130 +615,170 @@ __device__ __forceinline__ void rupd_cm_unit(const Desc& d, long long t,
     const long long row = t * kCmRows + threadIdx.x + k * kBlock;
     if (row >= n) break;
     const size_t o = ((size_t)ch * n + row) * V;
-    float r[V], q[V];
-    ldv<float, V>(d.R32 + o, r);
-    ldv<float, V>(d.Q32 + o, q);
-    const float di = ldg(d.dinv32 + row);
+    T r[V], q[V];
+    ldv<T, V>(vs.R + o, r);
+    ldv<T, V>(vs.Q + o, q);
+    const T di = ldg(vs.dinv + row);
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-      r[u] = fmaf(-al[u], q[u], r[u]);
+      r[u] = fma(-al[u], q[u], r[u]);
       x[u] += (double)r[u] * (double)(di * r[u]);
       x[V + u] += (double)r[u] * (double)r[u];
     }
-    stv<float, V>(d.R32 + o, r);
+    stv<T, V>(vs.R + o, r);
   }
   cm_unit_partials<2, V>(x, d, ch, t, ws);
 }
 
 // x += alpha p (columns active this iteration); p = D^-1 r + beta p
 // (columns active next iteration), chunk ch of tile t.
-template <int V>
+template <typename T, int V>
 __device__ __forceinline__ void pupd_cm_unit(const Desc& d, long long t,
-                                             int ch, const float (&al)[V],
-                                             const float (&be)[V],
+                                             int ch, const T (&al)[V],
+                                             const T (&be)[V],
                                              const bool (&nx)[V]) {
   const long long n = d.n;
+  const CmVecs<T> vs(d);
 #pragma unroll
   for (int k = 0; k < kCmRpt; ++k) {
     const long long row = t * kCmRows + threadIdx.x + k * kBlock;
     if (row >= n) break;
     const size_t o = ((size_t)ch * n + row) * V;
-    float x[V], p[V], r[V];
-    ldv<float, V>(d.X32 + o, x);
-    ldv<float, V>(d.P32 + o, p);
-    ldv<float, V>(d.R32 + o, r);
-    const float di = ldg(d.dinv32 + row);
+    T x[V], p[V], r[V];
+    ldv<T, V>(vs.X + o, x);
+    ldv<T, V>(vs.P + o, p);
+    ldv<T, V>(vs.R + o, r);
+    const T di = ldg(vs.dinv + row);
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-      x[u] = fmaf(al[u], p[u], x[u]);
-      p[u] = nx[u] ? fmaf(be[u], p[u], di * r[u]) : p[u];
+      x[u] = fma(al[u], p[u], x[u]);
+      p[u] = nx[u] ? fma(be[u], p[u], di * r[u]) : p[u];
     }
-    stv<float, V>(d.X32 + o, x);
-    stv<float, V>(d.P32 + o, p);
+    stv<T, V>(vs.X + o, x);
+    stv<T, V>(vs.P + o, p);
   }
 }
+
+// Run BODY with VV (constexpr) the vector width vw: 4, 2, 1 (FP32) or
+// 2, 1 (FP64), or VFIX when it is not 0.
+#define PARO_CM_WIDTH(T, VFIX, vw, BODY)                                   \
+  if constexpr (VFIX != 0) PARO_VB_CASE(VFIX, BODY)                        \
+  else if constexpr (sizeof(T) == 4) {                                     \
+    if (vw == 4) PARO_VB_CASE(4, BODY)                                     \
+    else if (vw == 2) PARO_VB_CASE(2, BODY)                                \
+    else PARO_VB_CASE(1, BODY)                                             \
+  } else {                                                                 \
+    if (vw == 2) PARO_VB_CASE(2, BODY)                                     \
+    else PARO_VB_CASE(1, BODY)                                             \
+  }
 
 // The units of the real block that runs this code, in its problem `d`
 // (owner of blockIdx.x), with VV (constexpr) the problem's FP32 width.
 // Launches queued after convergence (no active column) do nothing: the
 // column flags may be stale then.
-#define PARO_CM_LOOP(D, nprob, par, VFIX, BODY)                            \
+#define PARO_CM_LOOP(T, D, nprob, par, VFIX, BODY)                         \
   {                                                                        \
     const Desc& d = D[owner(D, nprob, blockIdx.x, false)];                 \
     if (ldg(&d.cs->n_active[par]) == 0) return;                            \
     const int lb_ = blockIdx.x - d.b0;                                     \
-    const int vw_ = VFIX ? VFIX : d.v32;                                   \
+    const int vw_ = VFIX ? VFIX : cm_width<T>(d);                          \
     const int cpr_ = d.ncols / vw_;                                        \
     for (TileWalk w_ = tile_walk((long long)d.ntc * cpr_, lb_, d.nb);      \
          w_.t < w_.end; w_.t += w_.step) {                                 \
       const CmUnit un = cm_unit(w_.t, cpr_);                               \
-      if (vw_ == 4) PARO_VB_CASE(4, BODY)                                  \
-      else if (vw_ == 2) PARO_VB_CASE(2, BODY)                             \
-      else PARO_VB_CASE(1, BODY)                                           \
+      PARO_CM_WIDTH(T, VFIX, vw_, BODY)                                    \
     }                                                                      \
   }
 
 // The per-column CG scalars of chunk ch (uniform loads).
-template <int V>
+template <typename T, int V>
 __device__ __forceinline__ bool cm_alpha(const ColState* cs, int par, int ch,
-                                         float (&al)[V]) {
+                                         T (&al)[V]) {
   bool any = false;
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int c = ch * V + u;
     const bool on = ldg(&cs->act[par][c]) != 0;
-    al[u] = on ? (float)ldg(&cs->alpha[c]) : 0.0f;
+    al[u] = on ? (T)ldg(&cs->alpha[c]) : T(0);
     any = any || on;
   }
   return any;
 }
 
-template <int V>
+template <typename T, int V>
 __device__ __forceinline__ void pupd_cm_chunk(const Desc& d, CmUnit un,
                                               int par) {
   const ColState* cs = d.cs;
-  float al[V], be[V];
+  T al[V], be[V];
   bool nx[V];
-  if (!cm_alpha<V>(cs, par, un.ch, al)) return;
+  if (!cm_alpha<T, V>(cs, par, un.ch, al)) return;
 #pragma unroll
   for (int u = 0; u < V; ++u) {
     const int c = un.ch * V + u;
     nx[u] = ldg(&cs->act[par ^ 1][c]) != 0;
-    be[u] = nx[u] ? (float)ldg(&cs->beta[c]) : 0.0f;
+    be[u] = nx[u] ? (T)ldg(&cs->beta[c]) : T(0);
   }
-  pupd_cm_unit<V>(d, un.t, un.ch, al, be, nx);
+  pupd_cm_unit<T, V>(d, un.t, un.ch, al, be, nx);
 }
 
-template <int VFIX>
+template <typename T, int V>
+__device__ __forceinline__ void rupd_cm_chunk(const Desc& d, CmUnit un,
+                                              int par, double* ws) {
+  T al[V];
+  if (cm_alpha<T, V>(d.cs, par, un.ch, al))
+    rupd_cm_unit<T, V>(d, un.t, un.ch, al, ws);
+}
+
+// VFIX: the common vector width of the launch's problems, or 0 (each
+// block branches on its problem's width: 4, 2, 1 FP32 or 2, 1 FP64).
+template <typename T, int VFIX>
 __global__ void PARO_STREAM_BOUNDS
 spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double ws[4 * kNtMax];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
   if (ldg(&d.cs->n_active[par]) == 0) return;  // queued after convergence
   const int lb = blockIdx.x - d.b0;
-  const int vw = VFIX ? VFIX : d.v32;
+  const int vw = cm_width<T>(d);
   for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end; w.t += w.step) {
-    if (vw == 4) PARO_VB_CASE(4, (spmm_cm_tile<VV>(d, w.t, par, ws)))
-    else if (vw == 2) PARO_VB_CASE(2, (spmm_cm_tile<VV>(d, w.t, par, ws)))
-    else PARO_VB_CASE(1, (spmm_cm_tile<VV>(d, w.t, par, ws)))
+    PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, par, ws)))
+  }
+}
+
+template <typename T, int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+rupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * 8];
+  PARO_CM_LOOP(T, D, nprob, par, VFIX, (rupd_cm_chunk<T, VV>(d, un, par, ws)))
+}
+
+template <typename T, int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+pupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  PARO_CM_LOOP(T, D, nprob, par, VFIX, (pupd_cm_chunk<T, VV>(d, un, par)))
+}
+
+// FP64 source solves: the orbitals (row-major) receive the chunk-major
+// iterate Xc of the CG.
+template <int V>
+__device__ __forceinline__ void cm_unpack_body(const Desc& d, int vb,
+                                               double* __restrict__ red) {
+  const Geo g = geo_of<V>(d, vb);
+  if (g.lr >= g.tr) return;
+  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+       w.t += w.step) {
+    const long long row = w.t * g.tr + g.lr;
+    if (row >= d.n) continue;
+    double x[V];
+    ldv<double, V>(d.Xc + cm_index(d.n, row, g.ch * V, V), x);
+    stv<double, V>(d.X + (size_t)row * d.ncols + g.ch * V, x);
   }
 }
 
 template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
-rupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double ws[4 * 8];
-  PARO_CM_LOOP(D, nprob, par, VFIX, ({
-    float al[VV];
-    if (cm_alpha<VV>(d.cs, par, un.ch, al))
-      rupd_cm_unit<VV>(d, un.t, un.ch, al, ws);
-  }))
-}
-
-template <int VFIX>
-__global__ void PARO_STREAM_BOUNDS
-pupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  PARO_CM_LOOP(D, nprob, par, VFIX, (pupd_cm_chunk<VV>(d, un, par)))
+cm_unpack_kernel(const Desc* __restrict__ D, int nprob) {
+  __shared__ double red[1];
+  PARO_VB_LOOP64(D, nprob, VFIX, (cm_unpack_body<VV>(d, vb, red)))
 }
 
 // ------------------------------------------------------------------------
@@ -976,8 +847,12 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
       acc[2][v] += r[v] * r[v];
     }
     if (d.X != U) stv<double, V>(d.X + o, u);
-    stv<double, V>(d.R + o, r);
-    stv<double, V>(d.P + o, p);
+    if (d.Xc) {  // FP64 CG: its chunk-major start state
+      const size_t oc = cm_index(d.n, row, g.ch * V, V);
+      stv<double, V>(d.Xc + oc, u);
+      stv<double, V>(d.R + oc, r);
+      stv<double, V>(d.P + oc, p);
+    }
     if (d.B) stv<double, V>(d.B + o, b);
   }
   block_partials<V, 3>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
@@ -1596,6 +1471,7 @@ __device__ void geneig_body(const double* __restrict__ Ain,
   // zero at working precision); the iteration stops after a sweep that
   // rotates nothing.
   const int half = nn / 2;
+  const int nblk = half * half;
   __shared__ int s_rot;
   double fro2 = 0.0;
   for (int e = tid; e < n * n; e += kBlock) {
@@ -1624,8 +1500,12 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     if (fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) <= skip) break;
     for (int round = 0; round < nn - 1; ++round) {
       if (tid < half) {
-        const int a0 = tid == 0 ? 0 : 1 + ((tid - 1 + round) % (nn - 1));
-        const int b0 = 1 + ((nn - 2 - tid + round) % (nn - 1));
+        // Round-robin pairing: slot 0 pairs index 0 with the rotating
+        // ring's head; the ring 1 .. nn-1 advances by one per round.
+        int a0 = tid == 0 ? 0 : tid + round;
+        a0 = a0 > nn - 1 ? a0 - (nn - 1) : a0;
+        int b0 = nn - 1 - tid + round;
+        b0 = b0 > nn - 1 ? b0 - (nn - 1) : b0;
         const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
         double c = 1.0, sn = 0.0;
         int rot = 0;
@@ -1651,7 +1531,6 @@ __device__ void geneig_body(const double* __restrict__ Ain,
       // A <- J^T A J as independent 2 x 2 blocks (row pair k, column pair
       // l): the row rotation, then the column rotation; Y <- Y J.  A pair
       // that does not rotate has c = 1, s = 0 (exact identity).
-      const int nblk = half * half;
       for (int e = tid; e < nblk + n * half; e += kBlock) {
         if (e < nblk) {
           const int k = e / half, l = e - k * half;
@@ -1909,56 +1788,20 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
   return hipGetLastError();
 }
 
-// FP32 (chunk-major) CG SpMM (one kernel; the tuner picks the grid).
-template <int W>
-static void cg_spmm_cm(Launch& L, int par, hipStream_t s, Timing* t) {
-  klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<W>, dim3(L.blocks),
-          dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
-}
-
-template <typename T, int W>
-static void cg_spmm(Launch& L, int var, int par, hipStream_t s, Timing* t) {
-  if constexpr (sizeof(T) == 4) {
-    cg_spmm_cm<W>(L, par, s, t);
-  } else {
-    const size_t smem = weights_bytes(L.tr64, sizeof(T), 1);
-    const Desc* D = L.d;
-    if (var < 0) var = kCgDefaultVar;
-    switch (var) {
-      case 0:
-        klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 0>, dim3(L.blocks),
-                dim3(kBlock), 0, s, D, L.nprob, par);
-        break;
-      case 1:
-        klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 1>, dim3(L.blocks),
-                dim3(kBlock), smem, s, D, L.nprob, par);
-        break;
-      default:
-        klaunch(t, PARO_ST_CG_SPMM, spmm_cg_kernel<T, W, 2>, dim3(L.blocks),
-                dim3(kBlock), smem, s, D, L.nprob, par);
-    }
-  }
-}
-
+// One CG iteration of every problem of the table (chunk-major kernels).
 template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
-  cg_spmm<T, W>(L, L.cgvar, par, s, t);
+  const Desc* D = L.d;
+  klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W>, dim3(L.blocks),
+          dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kFinal), 0, s, (const Desc*)L.d, par);
-  if constexpr (sizeof(T) == 4)
-    klaunch(t, PARO_ST_CG_RUPD, rupd_cm_kernel<W>, dim3(L.blocks),
-            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
-  else
-    klaunch(t, PARO_ST_CG_RUPD, rupd_kernel<T, W>, dim3(L.blocks),
-            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
+          dim3(kFinal), 0, s, D, par);
+  klaunch(t, PARO_ST_CG_RUPD, rupd_cm_kernel<T, W>, dim3(L.blocks),
+          dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_beta_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kFinal), 0, s, (const Desc*)L.d, par);
-  if constexpr (sizeof(T) == 4)
-    klaunch(t, PARO_ST_CG_PUPD, pupd_cm_kernel<W>, dim3(L.blocks),
-            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
-  else
-    klaunch(t, PARO_ST_CG_PUPD, pupd_kernel<T, W>, dim3(L.blocks),
-            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
+          dim3(kFinal), 0, s, D, par);
+  klaunch(t, PARO_ST_CG_PUPD, pupd_cm_kernel<T, W>, dim3(L.blocks),
+          dim3(kBlock), 0, s, D, L.nprob, par);
 }
 
 hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
@@ -1980,21 +1823,30 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
   return hipGetLastError();
 }
 
-hipError_t launch_cg_spmm(Launch& L, bool fp32, int var, hipStream_t s) {
+// The CG SpMM alone (autotuner timing).
+hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s) {
+  const Desc* D = L.d;
+  const dim3 g(L.blocks), b(kBlock);
   if (fp32) {
     switch (L.v32u) {
-      case 4: cg_spmm<float, 4>(L, var, 0, s, nullptr); break;
-      case 2: cg_spmm<float, 2>(L, var, 0, s, nullptr); break;
-      case 1: cg_spmm<float, 1>(L, var, 0, s, nullptr); break;
-      default: cg_spmm<float, 0>(L, var, 0, s, nullptr);
+      case 4: hipLaunchKernelGGL((spmm_cm_kernel<float, 4>), g, b, 0, s, D, L.nprob, 0); break;
+      case 2: hipLaunchKernelGGL((spmm_cm_kernel<float, 2>), g, b, 0, s, D, L.nprob, 0); break;
+      case 1: hipLaunchKernelGGL((spmm_cm_kernel<float, 1>), g, b, 0, s, D, L.nprob, 0); break;
+      default: hipLaunchKernelGGL((spmm_cm_kernel<float, 0>), g, b, 0, s, D, L.nprob, 0);
     }
   } else {
     switch (L.v64u) {
-      case 2: cg_spmm<double, 2>(L, var, 0, s, nullptr); break;
-      case 1: cg_spmm<double, 1>(L, var, 0, s, nullptr); break;
-      default: cg_spmm<double, 0>(L, var, 0, s, nullptr);
+      case 2: hipLaunchKernelGGL((spmm_cm_kernel<double, 2>), g, b, 0, s, D, L.nprob, 0); break;
+      case 1: hipLaunchKernelGGL((spmm_cm_kernel<double, 1>), g, b, 0, s, D, L.nprob, 0); break;
+      default: hipLaunchKernelGGL((spmm_cm_kernel<double, 0>), g, b, 0, s, D, L.nprob, 0);
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_cm_unpack(Launch& L, hipStream_t s, Timing* t) {
+  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, cm_unpack_kernel, dim3(L.blocks),
+                  dim3(kBlock), 0, s, L.d, L.nprob);
   return hipGetLastError();
 }
 
