@@ -63,7 +63,7 @@ def parse():
                     help="skip the plain FP64 comparison solves")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed solves only (for rocprofv3)")
-    ap.add_argument("--inner-rtol", type=float, default=1e-4,
+    ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="FP32 inner CG residual reduction per refinement")
     ap.add_argument("--m", type=int, default=None,
                     help="buffer orbitals (default: the workload's)")
@@ -235,8 +235,9 @@ def main():
                           "own_gbs": own / (s["ms"] * 1e-3) / 1e9}
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
-        kernel_names = {"cg_spmm": "spmm_cg_kernel", "cg_rupd": "rupd_kernel",
-                        "cg_pupd": "pupd_kernel"}
+        kernel_names = {"cg_spmm": "spmm_cm_kernel",
+                        "cg_rupd": "rupd_cm_kernel",
+                        "cg_pupd": "pupd_cm_kernel"}
         traffic = (measured_traffic(kernel_names[dom]) if prec == "mixed"
                    else None)
         all_ms = sum(v["ms"] for v in td["stages"].values())

@@ -74,7 +74,8 @@ typedef struct paro_opts {
   double lambda_tol;      /* stop: max_{i<N} |dlambda_i| / scale_i <= this  */
   double resid_tol;       /* and max_{i<N} ||H u - l M u|| / (scale ||M u||) */
   double pcg_rtol;        /* source solves: ||b - A w|| <= rtol ||b||        */
-  double inner_rtol;      /* FP32 inner solves: residual reduction per pass  */
+  double inner_rtol;      /* FP32 inner solves: residual reduction per pass
+                             (never below what pcg_rtol needs)             */
 } paro_opts_t;
 
 typedef struct paro_report {
@@ -93,7 +94,7 @@ typedef struct paro_problem paro_problem;   /* opaque, host memory only */
 
 /* Fill `opts` with defaults: m = 0, max_steps = 200, pcg_maxit = 10000,
  * FP64, automatic shift, lambda_tol = 1e-12, resid_tol = 1e-8,
- * pcg_rtol = 1e-10, inner_rtol = 1e-4.  N must still be set. */
+ * pcg_rtol = 1e-10, inner_rtol = 1e-5.  N must still be set. */
 void paro_default_opts(paro_opts_t* opts);
 
 /* Sizes for a box and options, host only.  n_dof = (nx-1)(ny-1)(nz-1);

@@ -536,13 +536,14 @@ int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
     return PARO_OK;
   }
   for (int pass = 0;; ++pass) {
-    HIP_OR_FAIL(launch_refine_residual(c.L, s, c.timing));
+    HIP_OR_FAIL(launch_refine_residual(c.L, pass == 0, s, c.timing));
     int pw[2];
     int rc = poll(c, 2, pw, s);
     if (rc) return rc;
     if (pw[0] == 0) break;
     if (pass > 200)
       return fail(PARO_EDEVICE, "refinement loop did not terminate");
+    if (pass > 0) HIP_OR_FAIL(launch_redirect(c.L, s, c.timing));
     rc = run_cg(c, true, s, 1 + (pass < 3 ? pass : 3));
     if (rc) return rc;
     HIP_OR_FAIL(launch_refine_update(c.L, s, c.timing));
@@ -815,7 +816,7 @@ void paro_default_opts(paro_opts_t* o) {
   o->lambda_tol = 1e-12;
   o->resid_tol = 1e-8;
   o->pcg_rtol = 1e-10;
-  o->inner_rtol = 1e-4;
+  o->inner_rtol = 1e-5;
 }
 
 const char* paro_last_error(void) { return g_err.c_str(); }

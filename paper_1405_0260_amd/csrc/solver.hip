@@ -757,6 +757,44 @@ pupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   PARO_CM_LOOP(T, D, nprob, par, VFIX, (pupd_cm_chunk<T, VV>(d, un, par)))
 }
 
+// Continuing FP32 pass after residual replacement: p = D^-1 r + beta p on
+// the columns that refine (parity 0 of the coming CG iterations).
+template <int V>
+__device__ __forceinline__ void redirect_cm_chunk(const Desc& d, CmUnit un) {
+  const ColState* cs = d.cs;
+  const long long n = d.n;
+  float be[V];
+  bool on[V];
+  bool any = false;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int c = un.ch * V + u;
+    on[u] = ldg(&cs->act[0][c]) != 0;
+    be[u] = on[u] ? (float)ldg(&cs->beta[c]) : 0.0f;
+    any = any || on[u];
+  }
+  if (!any) return;
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const long long row = un.t * kCmRows + threadIdx.x + k * kBlock;
+    if (row >= n) break;
+    const size_t o = ((size_t)un.ch * n + row) * V;
+    float p[V], r[V];
+    ldv<float, V>(d.P32 + o, p);
+    ldv<float, V>(d.R32 + o, r);
+    const float di = ldg(d.dinv32 + row);
+#pragma unroll
+    for (int u = 0; u < V; ++u) p[u] = on[u] ? fmaf(be[u], p[u], di * r[u]) : p[u];
+    stv<float, V>(d.P32 + o, p);
+  }
+}
+
+template <int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+redirect_cm_kernel(const Desc* __restrict__ D, int nprob) {
+  PARO_CM_LOOP(float, D, nprob, 0, VFIX, (redirect_cm_chunk<VV>(d, un)))
+}
+
 // FP64 source solves: the orbitals (row-major) receive the chunk-major
 // iterate Xc of the CG.
 template <int V>
@@ -901,14 +939,17 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
 
 // ------------------------------------------------------------------------
 // Mixed precision: FP64 residual of the outer (refinement) iteration and
-// the start of an FP32 inner CG solve for the correction.
+// the next FP32 inner CG pass for the correction.
 //   r64 = B - A_s X;  converged columns (||r64|| <= rtol ||b||) retire;
-//   the others restart CG on A d = r64 in FP32 from d = 0, to
-//   ||r|| <= inner_rtol ||r64||.
+//   the others solve A d = r64 in FP32 from d = 0, to
+//   ||r|| <= inner_rtol ||r64||.  The first pass of a solve starts CG
+//   (p = D^-1 r); later passes keep the search direction p and only
+//   replace the recursively updated residual by the FP64 one (residual
+//   replacement), so CG continues instead of restarting.
 // ------------------------------------------------------------------------
 template <int V>
 __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
-    double* __restrict__ red) {
+    int restart, double* __restrict__ red) {
   const Geo g = geo_of<V>(d, vb);
   ColState* cs = d.cs;
   const int ncols = d.ncols;
@@ -956,7 +997,7 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
     // in one FP32 chunk (the FP32 width is a multiple of the FP64 one).
     const size_t o32 = cm_index(d.n, row, g.ch * V, d.v32);
     stv<float, V>(d.R32 + o32, r32);
-    stv<float, V>(d.P32 + o32, p32);
+    if (restart) stv<float, V>(d.P32 + o32, p32);
     stv<float, V>(d.X32 + o32, z32);
   }
   block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
@@ -964,15 +1005,16 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
 
 template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
-refine_residual_kernel(const Desc* __restrict__ D, int nprob) {
+refine_residual_kernel(const Desc* __restrict__ D, int nprob, int restart) {
   __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
-  PARO_VB_LOOP64(D, nprob, VFIX, (refine_residual_body<VV>(d, vb, red)))
+  PARO_VB_LOOP64(D, nprob, VFIX,
+                 (refine_residual_body<VV>(d, vb, restart, red)))
 }
 
 // Outer (refinement) test per column and the inner threshold of the next
 // FP32 solve (grid: column x problem).
 __global__ void __launch_bounds__(kFinal)
-refine_final_kernel(const Desc* __restrict__ D) {
+refine_final_kernel(const Desc* __restrict__ D, int restart) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= d.ncols) return;
@@ -996,7 +1038,13 @@ refine_final_kernel(const Desc* __restrict__ D) {
     const bool more = rr > rtol * rtol * cs->bb[c];
     a = (more && cs->iters[c] < cs->maxit) ? 1 : 0;
     if (more && !a) atomicOr(&cs->status, (int)kStNoConv);
-    cs->tol2[c] = irt * irt * rr;
+    // Inner target: inner_rtol ||r64||, but no lower than what the outer
+    // test needs (0.3 rtol ||b||: the margin covers the drift between the
+    // FP32 recursive residual and the FP64 one).
+    cs->tol2[c] = fmax(irt * irt * rr, 0.09 * rtol * rtol * cs->bb[c]);
+    // A continuing pass takes the last step's beta with the replaced
+    // residual: beta = (r.z)_new / (r.z) of the step before.
+    if (!restart && a) cs->beta[c] = cs->beta[c] * (tot[1] / cs->rz[c]);
     cs->rz[c] = tot[1];
   }
   cs->oact[c] = a;
@@ -1865,12 +1913,25 @@ hipError_t launch_all_active(Launch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
+hipError_t launch_refine_residual(Launch& L, bool restart, hipStream_t s,
+                                  Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_kernel,
                   dim3(L.blocks), dim3(kBlock),
-                  weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
+                  weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob,
+                  restart ? 1 : 0);
   klaunch(t, PARO_ST_REFINE, refine_final_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kFinal), 0, s, L.d);
+          dim3(kFinal), 0, s, L.d, restart ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_redirect(Launch& L, hipStream_t s, Timing* t) {
+  const Desc* D = L.d;
+  switch (L.v32u) {
+    case 4: klaunch(t, PARO_ST_REFINE, redirect_cm_kernel<4>, dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob); break;
+    case 2: klaunch(t, PARO_ST_REFINE, redirect_cm_kernel<2>, dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob); break;
+    case 1: klaunch(t, PARO_ST_REFINE, redirect_cm_kernel<1>, dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob); break;
+    default: klaunch(t, PARO_ST_REFINE, redirect_cm_kernel<0>, dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob);
+  }
   return hipGetLastError();
 }
 
