@@ -30,15 +30,26 @@ TRAFFIC = os.path.join(ROOT, "profiles", "softcoulomb64_mixed_traffic.md")
 SOLVER_SRC = os.path.join(ROOT, "paper_1405_0260_amd", "csrc", "solver.hip")
 
 
+def solver_code_sha():
+    """SHA-256 of the kernel source with comments and blank lines removed
+    (a comment edit does not invalidate measured counters)."""
+    import hashlib
+    import re
+    src = open(SOLVER_SRC).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in src.splitlines()]
+    code = "\n".join(ln for ln in lines if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()
+
+
 def measured_traffic(kernel_substr):
     """HBM bytes per launch of the dominant kernel from the committed PMC
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known
     size), or None when the summary is missing, covers another kernel, or
     was taken on a different solver source than the one built now."""
-    import hashlib
     try:
         text = open(TRAFFIC).read()
-        sha = hashlib.sha256(open(SOLVER_SRC, "rb").read()).hexdigest()
+        sha = solver_code_sha()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()

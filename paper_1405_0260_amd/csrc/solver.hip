@@ -7,12 +7,14 @@
 // summation order do not depend on the other problems of the table.
 //
 // Data layout.  Orbital blocks are row-major n x Nt (orbital fastest), so a
-// CSR neighbour gathered by the SpMM is Nt contiguous values; a thread owns
-// V consecutive columns of one row ("chunk"), a workgroup a tile of
-// kBlock / (Nt / V) rows.  A problem's blocks walk its tiles in eight
-// contiguous slabs, slab = block mod 8, so that each XCD sweeps one slab of
-// rows and keeps its halo in its own L2.  The tile's CSR slice is staged in
-// LDS with coalesced loads.
+// stencil neighbour gathered by the once-per-step kernels is Nt contiguous
+// values; there a thread owns V consecutive columns of one row ("chunk"),
+// a workgroup a tile of kBlock / (Nt / V) rows.  The CG vectors are
+// chunk-major (see the CG section): a thread owns one row of one chunk.
+// A problem's blocks walk its tiles in eight contiguous slabs, slab =
+// block mod 8, so that each XCD sweeps one slab of rows and keeps its halo
+// in its own L2.  The operators are stored in stencil order (15
+// coefficients per row, implicit neighbours).
 //
 // Reductions (per-column dot products) are two-stage and deterministic:
 // each workgroup writes its partial sums, then a finalize kernel with one
