@@ -393,6 +393,16 @@ typedef struct paro_timing {
  * kernel by kernel. */
 void paro_set_graphs(int on);
 
+/* Persistent CG (off by default): every CG iteration of a call's problems
+ * (one problem or a whole batch) runs in one cooperative launch whose
+ * phases -- SpMM, alpha, r-update, beta, p-update -- are separated by
+ * grid-wide barriers instead of kernel boundaries, and which exits by
+ * itself once every column has converged.  Results are bitwise those of
+ * the kernel-by-kernel path.  When the grid cannot be co-resident (more
+ * than 96 problems, or a device with fewer CUs) the call falls back to
+ * kernel-by-kernel launches.  Process-wide. */
+void paro_set_persistent(int on);
+
 /* Autotuner (on by default): at assembly, the CG SpMM of each new problem
  * shape (grid, N + m, precision) is timed with the full and the halved
  * real block count, and the faster is kept for the shape for the rest of

@@ -140,6 +140,7 @@ def lib():
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
         "paro_set_graphs": (None, [c_i32]),
+        "paro_set_persistent": (None, [c_i32]),
         "paro_set_autotune": (None, [c_i32]),
         "paro_tuned": (c_i32, [P, ctypes.POINTER(c_i32),
                                ctypes.POINTER(c_i32)]),
@@ -364,6 +365,11 @@ def paro_pcg(p: Problem, B, X, stream=None):
 def paro_set_graphs(on: bool = True):
     """Run CG chunks as captured HIP graphs (default) or kernel by kernel."""
     lib().paro_set_graphs(1 if on else 0)
+
+
+def paro_set_persistent(on: bool = True):
+    """Run every CG iteration of a call in one cooperative launch."""
+    lib().paro_set_persistent(1 if on else 0)
 
 
 def paro_set_autotune(on: bool = True):

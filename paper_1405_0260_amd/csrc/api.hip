@@ -100,6 +100,10 @@ thread_local std::string g_err = "no error";
 // polls go through the host mailbox (the GPU-side dispatch gap between
 // dependent kernels is what remains, and graphs do not shorten it).
 std::atomic<int> g_graphs_on{0};
+std::atomic<int> g_persistent_on{0};
+// Co-resident workgroups of the persistent CG kernel (three per CU on 256
+// CUs); the launcher checks the device's actual capacity.
+constexpr int kPersistGrid = 768;
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
@@ -354,6 +358,7 @@ struct Ctx {
   int precision;
   GraphCache* graphs;     // null: launch kernel by kernel
   int last_status = 0;    // status bits seen by the last poll
+  std::vector<Desc> ptab; // table laid out for the persistent CG grid
 };
 
 // The stream CG chunks are captured on (capture only records; the graphs
@@ -503,7 +508,56 @@ int poll(Ctx& c, int which, int out[2], hipStream_t s) {
 // the same slot took, so that a converging solve usually needs one poll;
 // later batches are short top-ups.  Launches after convergence are no-ops
 // on the device, so no poll precedes the first batch.
+// Shares of a persistent grid of `grid` blocks, proportional to each
+// problem's work, multiples of 8, at least 8 and at most the problem's
+// own block count (work distribution only: results do not depend on it).
+void layout_persistent(std::vector<Desc>& tab, int grid) {
+  double total = 0.0;
+  for (const Desc& d : tab) total += (double)d.n * d.ncols;
+  int b = 0;
+  for (Desc& d : tab) {
+    const double w = (double)d.n * d.ncols / total;
+    const int nb = std::max(8, std::min(d.nb, (int)(w * grid) / 8 * 8));
+    d.b0 = b;
+    d.nb = nb;
+    b += nb;
+  }
+}
+
+// All CG iterations of the table in one persistent launch.  Returns 1
+// (nothing launched) when the grid cannot be co-resident.
+int run_cg_persistent(Ctx& c, bool fp32, hipStream_t s, int slot) {
+  c.ptab = c.tab;
+  layout_persistent(c.ptab, kPersistGrid);
+  HIP_OR_FAIL(hipMemcpyAsync(c.L.d, c.ptab.data(),
+                             sizeof(Desc) * c.ptab.size(),
+                             hipMemcpyHostToDevice, s));
+  Launch PL = make_launch(c.L.d, c.ptab.data(), (int)c.ptab.size());
+  const int iters = (int)std::min<int64_t>(((int64_t)c.maxit + 65) / 2 * 2,
+                                           1 << 30);
+  bool fits = false;
+  const hipError_t e = launch_cg_persistent(PL, fp32, iters, s, c.timing,
+                                            &fits);
+  int rc = upload(c, s);  // the per-kernel layout again (stream-ordered)
+  if (e != hipSuccess)
+    return fail(PARO_EDEVICE, "persistent CG launch: %s",
+                hipGetErrorString(e));
+  if (rc) return rc;
+  if (!fits) return 1;
+  int pw[2] = {0, 0};
+  rc = poll(c, 0, pw, s);
+  if (rc) return rc;
+  if (pw[0] != 0)
+    return fail(PARO_EDEVICE, "persistent CG stopped at its iteration cap");
+  c.predict[slot] = pw[1];
+  return PARO_OK;
+}
+
 int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
+  if (g_persistent_on.load()) {
+    const int rc = run_cg_persistent(c, fp32, s, slot);
+    if (rc != 1) return rc;  // 1: does not fit, run kernel by kernel
+  }
   int pw[2] = {0, 0};
   const int64_t cap = (int64_t)c.maxit + 64;
   const int pred = c.predict[slot];
@@ -1196,6 +1250,8 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
 }
 
 void paro_set_graphs(int on) { g_graphs_on.store(on ? 1 : 0); }
+
+void paro_set_persistent(int on) { g_persistent_on.store(on ? 1 : 0); }
 
 void paro_set_autotune(int on) { g_autotune_on.store(on ? 1 : 0); }
 

@@ -296,6 +296,11 @@ hipError_t launch_redirect(Launch& L, hipStream_t s, Timing* t);
 // Autotuner: the CG SpMM alone (parity 0), and a set-up making every
 // column active.
 hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s);
+// All CG iterations of the table in one cooperative (persistent) launch,
+// at most `iters` (even) of them; *fits = false, and nothing launched, if
+// the grid cannot be co-resident on the device.
+hipError_t launch_cg_persistent(Launch& L, bool fp32, int iters,
+                                hipStream_t s, Timing* t, bool* fits);
 // FP64 source solves: the orbitals X receive the chunk-major iterate Xc.
 hipError_t launch_cm_unpack(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_all_active(Launch& L, hipStream_t s);

@@ -20,6 +20,8 @@
 // each workgroup writes its partial sums, then a finalize kernel with one
 // workgroup per (problem, column) adds them in a fixed order.  No float
 // atomics.
+#include <hip/hip_cooperative_groups.h>
+
 #include <cmath>
 
 #include "paro_internal.h"
@@ -154,7 +156,7 @@ __device__ __forceinline__ void column_sums(const double* __restrict__ part,
                                             size_t stride, int c, int nb,
                                             double (&out)[NA]) {
   constexpr int kU = 16;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x & (kFinal - 1);  // lane of the wavefront
   double v[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a) v[a] = 0.0;
@@ -352,26 +354,24 @@ __device__ __forceinline__ Geo geo_of(const Desc& d, int vb) {
 
 // alpha_c = (r.z)_c / (p.q)_c for the active columns (grid: column x
 // problem).  Also clears the next parity's active count for cg_beta.
-__global__ void __launch_bounds__(kFinal)
-cg_alpha_kernel(const Desc* __restrict__ D, int par) {
-  const Desc& d = D[blockIdx.y];
-  const int c = blockIdx.x;
+__device__ __forceinline__ void alpha_pair(const Desc& d, int c, int par) {
+  const int lane = threadIdx.x & (kFinal - 1);
   ColState* cs = d.cs;
   if (c >= d.ncols) return;
   if (cs->n_active[par] == 0) {
     // Nothing ran in this iteration: keep the next parity idle too, so
     // that launches queued after convergence stay no-ops.
-    if (c == 0 && threadIdx.x == 0) cs->n_active[par ^ 1] = 0;
+    if (c == 0 && lane == 0) cs->n_active[par ^ 1] = 0;
     return;
   }
-  if (c == 0 && threadIdx.x == 0) {
+  if (c == 0 && lane == 0) {
     cs->n_active[par ^ 1] = 0;
     cs->cg_iters += 1;
   }
   if (!cs->act[par][c]) return;
   double tot[1];
   column_sums<1>(d.pqp, 0, c, d.pqn, tot);
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
       atomicOr(&cs->status, isfinite(pq) ? (int)kStNotSpd : (int)kStNonFinite);
@@ -382,21 +382,24 @@ cg_alpha_kernel(const Desc* __restrict__ D, int par) {
   }
 }
 
+__global__ void __launch_bounds__(kFinal)
+cg_alpha_kernel(const Desc* __restrict__ D, int par) {
+  alpha_pair(D[blockIdx.y], blockIdx.x, par);
+}
+
 // beta_c, iteration count and the stopping test of every active column
 // (grid: column x problem); counts the columns active next iteration.
-__global__ void __launch_bounds__(kFinal)
-cg_beta_kernel(const Desc* __restrict__ D, int par) {
-  const Desc& d = D[blockIdx.y];
-  const int c = blockIdx.x;
+__device__ __forceinline__ void beta_pair(const Desc& d, int c, int par) {
+  const int lane = threadIdx.x & (kFinal - 1);
   ColState* cs = d.cs;
   if (c >= d.ncols || cs->n_active[par] == 0) return;
   if (!cs->act[par][c]) {
-    if (threadIdx.x == 0) cs->act[par ^ 1][c] = 0;
+    if (lane == 0) cs->act[par ^ 1][c] = 0;
     return;
   }
   double tot[2];
   column_sums<2>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
-  if (threadIdx.x != 0) return;
+  if (lane != 0) return;
   int next = 0;
   const double rz = tot[0], rr = tot[1];
   if (!isfinite(rz) || !isfinite(rr)) {
@@ -416,6 +419,11 @@ cg_beta_kernel(const Desc* __restrict__ D, int par) {
   atomicAdd(&cs->cg_col_iters, 1ULL);
 }
 
+__global__ void __launch_bounds__(kFinal)
+cg_beta_kernel(const Desc* __restrict__ D, int par) {
+  beta_pair(D[blockIdx.y], blockIdx.x, par);
+}
+
 // ------------------------------------------------------------------------
 // The CG of the source solves, in chunk-major layout.
 //
@@ -423,7 +431,8 @@ cg_beta_kernel(const Desc* __restrict__ D, int par) {
 // solves: R32, P32, Q32, X32) are internal to the library and stored as
 // Nt / V chunks of V columns (V values = 16 bytes at full width), each an
 // n x V array (cm_index), so a chunk of a row range is contiguous and a
-// neighbour gather of a wavefront reads one contiguous kilobyte.  The work unit is (tile of kCmRows rows, chunk): a
+// neighbour gather of a wavefront reads one contiguous kilobyte.  The work
+// unit of the updates is (tile of kCmRows rows, chunk): a
 // thread owns kCmRpt rows of the tile (rows tid, tid + 256, ...) in one
 // chunk, accumulates its per-column products over them, and the unit ends
 // with one wavefront reduction.  Converged chunks are skipped whole.
@@ -795,6 +804,80 @@ template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
 redirect_cm_kernel(const Desc* __restrict__ D, int nprob) {
   PARO_CM_LOOP(float, D, nprob, 0, VFIX, (redirect_cm_chunk<VV>(d, un)))
+}
+
+// ------------------------------------------------------------------------
+// Persistent CG: every iteration of every problem of the table in one
+// cooperative launch.  The phases of an iteration -- SpMM, alpha, r-update,
+// beta, p-update -- are the same device functions as the per-kernel path
+// (same partial slots, same summation order: identical results), separated
+// by grid-wide barriers instead of kernel boundaries.  A block keeps its
+// problem's block range; the per-column scalar phases spread the (problem,
+// column) pairs over all wavefronts of the grid.  Every block takes the
+// same exit decision: after the beta phase it reads the next-parity active
+// counts of all problems (final at that barrier); `iters` (even) bounds the
+// loop, so every wavefront reaches the end.
+// ------------------------------------------------------------------------
+// Registers capped for three workgroups per CU (768 co-resident blocks).
+template <typename T, int VFIX>
+__global__ void __launch_bounds__(kBlock, 3)
+cg_persistent_kernel(const Desc* __restrict__ D, int nprob, int iters) {
+  namespace cgr = cooperative_groups;
+  cgr::grid_group grid = cgr::this_grid();
+  __shared__ double ws[4 * kNtMax];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  const int lb = blockIdx.x - d.b0;
+  const int vw = cm_width<T>(d);
+  const int cpr = d.ncols / vw;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  const int npairs = nprob * kNtMax;
+  int par = 0;
+  bool done = false;
+  for (int it = 0; it < iters; ++it) {
+    const bool on = ldg(&d.cs->n_active[par]) != 0;
+    if (on)
+      for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end;
+           w.t += w.step) {
+        PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, par, ws)))
+      }
+    grid.sync();
+    for (int q = blockIdx.x * (kBlock / 64) + wave; q < npairs; q += nwaves)
+      alpha_pair(D[q / kNtMax], q % kNtMax, par);
+    grid.sync();
+    if (on)
+      for (TileWalk w = tile_walk((long long)d.ntc * cpr, lb, d.nb);
+           w.t < w.end; w.t += w.step) {
+        const CmUnit un = cm_unit(w.t, cpr);
+        PARO_CM_WIDTH(T, VFIX, vw, (rupd_cm_chunk<T, VV>(d, un, par, ws)))
+      }
+    grid.sync();
+    for (int q = blockIdx.x * (kBlock / 64) + wave; q < npairs; q += nwaves)
+      beta_pair(D[q / kNtMax], q % kNtMax, par);
+    grid.sync();
+    int more = 0;
+    for (int p = threadIdx.x; p < nprob; p += kBlock)
+      more |= ldg(&D[p].cs->n_active[par ^ 1]) != 0;
+    more = __syncthreads_or(more);
+    if (on)
+      for (TileWalk w = tile_walk((long long)d.ntc * cpr, lb, d.nb);
+           w.t < w.end; w.t += w.step) {
+        const CmUnit un = cm_unit(w.t, cpr);
+        PARO_CM_WIDTH(T, VFIX, vw, (pupd_cm_chunk<T, VV>(d, un, par)))
+      }
+    grid.sync();
+    par ^= 1;
+    if (!more) {
+      done = true;
+      break;
+    }
+  }
+  // Converged: keep both parities idle, the state the per-kernel path
+  // reaches through its queued no-op iterations.  At the cap (an even
+  // count) `par` is back at 0 and the counts stay, for the host to see.
+  if (done && blockIdx.x == 0)
+    for (int p = threadIdx.x; p < nprob; p += kBlock)
+      D[p].cs->n_active[par ^ 1] = 0;
 }
 
 // FP64 source solves: the orbitals (row-major) receive the chunk-major
@@ -1892,6 +1975,59 @@ hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s) {
     }
   }
   return hipGetLastError();
+}
+
+// Persistent CG launch; *fits = false (nothing launched) when the grid
+// cannot be co-resident.
+template <typename T, int W>
+static hipError_t cg_persistent_w(Launch& L, int iters, hipStream_t s,
+                                  Timing* t, bool* fits) {
+  static int per_cu = -1, cus = 0;
+  if (per_cu < 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(cg_persistent_kernel<T, W>),
+          kBlock, 0);
+    if (e != hipSuccess) return e;
+  }
+  *fits = (long long)per_cu * cus >= L.blocks;
+  if (!*fits) return hipSuccess;
+  const Desc* D = L.d;
+  int nprob = L.nprob;
+  void* args[] = {(void*)&D, (void*)&nprob, (void*)&iters};
+  hipEvent_t a = nullptr, b = nullptr;
+  const bool timed = timing_pair(t, &a, &b);
+  if (timed) (void)hipEventRecord(a, s);
+  const hipError_t e = hipLaunchCooperativeKernel(
+      reinterpret_cast<const void*>(cg_persistent_kernel<T, W>),
+      dim3(L.blocks), dim3(kBlock), args, 0, s);
+  if (timed) {
+    (void)hipEventRecord(b, s);
+    timing_add(t, PARO_ST_CG_SPMM, a, b);
+  }
+  return e;
+}
+
+hipError_t launch_cg_persistent(Launch& L, bool fp32, int iters,
+                                hipStream_t s, Timing* t, bool* fits) {
+  if (fp32) {
+    switch (L.v32u) {
+      case 4: return cg_persistent_w<float, 4>(L, iters, s, t, fits);
+      case 2: return cg_persistent_w<float, 2>(L, iters, s, t, fits);
+      case 1: return cg_persistent_w<float, 1>(L, iters, s, t, fits);
+      default: return cg_persistent_w<float, 0>(L, iters, s, t, fits);
+    }
+  }
+  switch (L.v64u) {
+    case 2: return cg_persistent_w<double, 2>(L, iters, s, t, fits);
+    case 1: return cg_persistent_w<double, 1>(L, iters, s, t, fits);
+    default: return cg_persistent_w<double, 0>(L, iters, s, t, fits);
+  }
 }
 
 hipError_t launch_cm_unpack(Launch& L, hipStream_t s, Timing* t) {
