@@ -94,6 +94,8 @@ def parse():
                     help="cells per axis of the Kohn-Sham run")
     ap.add_argument("--ks-iters", type=int, default=300,
                     help="outer iterations at most")
+    ap.add_argument("--ks-poisson-cg", action="store_true",
+                    help="Hartree by Jacobi-PCG instead of the direct solve")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests per served run")
     ap.add_argument("--serve-arena-gb", type=float, default=48.0,
@@ -509,8 +511,9 @@ def serve_bench(args, prec):
 def ks_bench(args, prec):
     """Self-consistent Kohn-Sham around ParO on the 96^3 workload (20
     soft-Coulomb centres, N = 32 occupied orbitals, 8 buffer orbitals,
-    mixing 0.3): one ParO step per outer iteration, Hartree by PCG,
-    Slater exchange.  Throughput counts n_dof * N per ParO step."""
+    mixing 0.3): one ParO step per outer iteration, Hartree by the direct
+    sine-transform solve (--ks-poisson-cg: by Jacobi-PCG), Slater exchange.
+    Throughput counts n_dof * N per ParO step."""
     import torch
     from paper_1405_0260_amd import binding as pb
     from paper_1405_0260_amd import inputs
@@ -527,7 +530,8 @@ def ks_bench(args, prec):
     lam = torch.zeros(w.Nt, dtype=torch.float64, device=dev)
     U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=dev)
     ko = pb.ks_default_opts(max_iter=args.ks_iters, scf_tol=1e-7,
-                            poisson_rtol=1e-10)
+                            poisson_rtol=1e-10,
+                            poisson_maxit=20000 if args.ks_poisson_cg else 0)
     hist = np.zeros(args.ks_iters)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -544,6 +548,7 @@ def ks_bench(args, prec):
             "converged": rep.status == 0, "density_residual": rep.residual,
             "max_dlambda": rep.max_dlambda, "max_resid": rep.max_resid,
             "paro_cg_iters": rep.paro_pcg_iters,
+            "hartree": "pcg" if args.ks_poisson_cg else "sine transform",
             "poisson_cg_iters": rep.poisson_iters,
             "lambda_lowest": lam[:4].cpu().tolist(),
             "residual_every_50": [float(x) for x in

@@ -203,28 +203,33 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
  * (eq-operator-A); Algorithm 3.1).  The problem's potential becomes the
  * effective potential V_ext + V_H(rho) + v_x(rho) of the mixed density
  * rho = occupancy * sum_{i<=N} u_i^2 (interior vertices), V_H from the P1
- * Poisson problem -Lap V_H = 4 pi rho with V_H = 0 on the boundary (solved
- * by the library's Jacobi-PCG), v_x the Slater exchange -(3 rho/pi)^(1/3).
+ * Poisson problem -Lap V_H = 4 pi rho with V_H = 0 on the boundary, i.e.
+ * K V_H = 4 pi M rho (solved directly by the 3-D discrete sine transform,
+ * which diagonalises the P1 stiffness matrix of the uniform box grid, or
+ * by the library's Jacobi-PCG when poisson_maxit > 0), v_x the Slater
+ * exchange -(3 rho/pi)^(1/3).
  * Outer iteration n: density of U^(n); rho_in = that density at n = 0,
  * else (1 - mixing) rho_in + mixing * density; V_eff; values-only
  * re-assembly (shift recomputed unless sigma_mode = 1); one ParO step.
  * --------------------------------------------------------------------- */
 typedef struct paro_ks_opts {
   int32_t max_iter;       /* outer iterations at most                    */
-  int32_t poisson_maxit;  /* CG cap of the Hartree solve                 */
+  int32_t poisson_maxit;  /* 0: direct Hartree solve (default); > 0: CG
+                             of the Hartree solve, capped at this        */
   double mixing;          /* linear density mixing, (0, 1]               */
   double occupancy;       /* electrons per orbital (2: spin-unpolarised) */
   double scf_tol;         /* stop when ||rho_out - rho_in|| / ||rho_in||
                              <= scf_tol and the problem's lambda_tol and
                              resid_tol hold for the step                  */
-  double poisson_rtol;    /* relative CG tolerance of the Hartree solve  */
+  double poisson_rtol;    /* relative CG tolerance (CG Hartree only)     */
 } paro_ks_opts_t;
 
 typedef struct paro_ks_report {
   int32_t status;         /* PARO_OK, PARO_ENOCONV (max_iter), or error  */
   int32_t iterations;
   int64_t paro_pcg_iters; /* CG iterations of the ParO steps              */
-  int64_t poisson_iters;  /* CG iterations of the Hartree solves          */
+  int64_t poisson_iters;  /* CG iterations of the Hartree solves (0 when
+                             solved directly)                            */
   double residual;        /* last density residual                       */
   double max_dlambda, max_resid, sigma;  /* of the last ParO step         */
   double seconds;

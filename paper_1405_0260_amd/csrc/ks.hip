@@ -2,8 +2,9 @@
 // (eq-operator-A); Algorithm 3.1): each outer iteration forms the density
 // of the current orbitals, mixes it into the input density, solves the
 // Poisson equation -Lap V_H = 4 pi rho for the Hartree potential (P1, zero
-// on the box boundary: (1/2) K V_H = 2 pi M rho with the library's own
-// Jacobi-PCG on the potential-free operator (1/2) K), adds the Slater
+// on the box boundary: K V_H = 4 pi M rho, solved directly with the 3-D
+// discrete sine transform that diagonalises K on the uniform box grid, or
+// optionally by the library's Jacobi-PCG on (1/2) K), adds the Slater
 // exchange potential -(3 rho / pi)^(1/3), re-assembles the Hamiltonian with
 // the effective potential and takes one ParO step with it.
 //
@@ -125,6 +126,133 @@ ks_potential_kernel(const double* __restrict__ Vext,
   }
 }
 
+// ---- Direct Hartree solve by the discrete sine transform ---------------
+// On a uniform box grid the Kuhn P1 stiffness matrix is exactly the 7-point
+// operator K = sum_a c_a T_a (T_a = tridiag(-1, 2, -1) along axis a, c_x =
+// hy hz / hx and cyclically), so K V = f is diagonal in the sine basis:
+// with S_a[p][q] = sin(pi (p + 1)(q + 1) / (m_a + 1)), S_a S_a =
+// (m_a + 1) / 2 I and K = S^-1 diag(lambda) S, lambda_pqr = sum_a c_a
+// 2 (1 - cos(pi (p_a + 1) / (m_a + 1))).  The transform along each axis is
+// a small dense product, done by dgemm_kernel.
+
+// Sine matrices of the three axes and the 1-D eigenvalue parts.
+__global__ void __launch_bounds__(kBlock)
+dst_tables_kernel(int mx, int my, int mz, double cx, double cy, double cz,
+                  double* __restrict__ Sx, double* __restrict__ Sy,
+                  double* __restrict__ Sz, double* __restrict__ ev) {
+  const int m[3] = {mx, my, mz};
+  const double c[3] = {cx, cy, cz};
+  double* S[3] = {Sx, Sy, Sz};
+  int evo = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int ma = m[a];
+    const double w = M_PI / (ma + 1);
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < ma * ma;
+         e += gridDim.x * kBlock) {
+      const int p = e / ma, q = e % ma;
+      // (p+1)(q+1) mod 2(m+1) keeps the sine argument small and exact.
+      const long long k = ((long long)(p + 1) * (q + 1)) % (2 * (ma + 1));
+      S[a][e] = sin(w * (double)k);
+    }
+    for (int p = blockIdx.x * kBlock + threadIdx.x; p < ma;
+         p += gridDim.x * kBlock)
+      ev[evo + p] = c[a] * 2.0 * (1.0 - cos(w * (p + 1)));
+    evo += ma;
+  }
+}
+
+// C_b = alpha A_b B_b for a batch of row-major FP64 matrices (M x K times
+// K x N), 64 x 64 output tiles, K in steps of 16 through LDS; thread
+// (ty, tx) owns rows ty + 16 i and columns tx + 16 j, i, j < 4.
+__global__ void __launch_bounds__(kBlock)
+dgemm_kernel(int M, int N, int K, const double* __restrict__ A,
+             long long lda, long long sA, const double* __restrict__ B,
+             long long ldb, long long sB, double* __restrict__ C,
+             long long ldc, long long sC, double alpha) {
+  __shared__ double As[16][64 + 1], Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  A += blockIdx.z * sA;
+  B += blockIdx.z * sB;
+  C += blockIdx.z * sC;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += kBlock) {
+      const int r = e / 16, k = e % 16;  // A: row r, column k
+      const int gm = m0 + r, gk = k0 + k;
+      As[k][r] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
+      const int kb = e / 64, c = e % 64;  // B: row kb, column c
+      const int gkb = k0 + kb, gn = n0 + c;
+      Bs[kb][c] = (gkb < K && gn < N) ? B[(size_t)gkb * ldb + gn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + ty + 16 * i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tx + 16 * j;
+      if (gn < N) C[(size_t)gm * ldc + gn] = alpha * acc[i][j];
+    }
+  }
+}
+
+// g[x, y, z] /= lambda_xyz (sine coefficients).
+__global__ void __launch_bounds__(kBlock)
+dst_divide_kernel(double* __restrict__ g, int mx, int my, int mz,
+                  const double* __restrict__ ev) {
+  const long long n = (long long)mx * my * mz;
+  for (long long d = (long long)blockIdx.x * kBlock + threadIdx.x; d < n;
+       d += (long long)gridDim.x * kBlock) {
+    const int x = (int)(d % mx);
+    const int y = (int)((d / mx) % my);
+    const int z = (int)(d / ((long long)mx * my));
+    g[d] /= ev[x] + ev[mx + y] + ev[mx + my + z];
+  }
+}
+
+hipError_t dgemm(hipStream_t s, int M, int N, int K, const double* A,
+                 long long lda, long long sA, const double* B, long long ldb,
+                 long long sB, double* C, long long ldc, long long sC,
+                 int batch, double alpha) {
+  hipLaunchKernelGGL(dgemm_kernel, dim3((N + 63) / 64, (M + 63) / 64, batch),
+                     dim3(kBlock), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C,
+                     ldc, sC, alpha);
+  return hipGetLastError();
+}
+
+// out = (S_x (x) S_y (x) S_z) in, scaled by alpha (in and out distinct;
+// tmp a third n-vector).  x is the fastest index.
+hipError_t dst3(hipStream_t s, int mx, int my, int mz, const double* Sx,
+                const double* Sy, const double* Sz, const double* in,
+                double* tmp, double* out, double alpha) {
+  const long long P = (long long)mx * my;
+  // along x: rows of length mx times S_x (symmetric)
+  hipError_t e = dgemm(s, (int)(P / mx * mz), mx, mx, in, mx, 0, Sx, mx, 0,
+                       out, mx, 0, 1, 1.0);
+  if (e != hipSuccess) return e;
+  // along y: for each z plane, S_y times the my x mx plane
+  e = dgemm(s, my, mx, my, Sy, my, 0, out, mx, P, tmp, mx, P, mz, 1.0);
+  if (e != hipSuccess) return e;
+  // along z: S_z times the mz x P matrix
+  return dgemm(s, mz, (int)P, mz, Sz, mz, 0, tmp, P, 0, out, P, 0, 1, alpha);
+}
+
 int grid_for(long long n) {
   long long g = (n + kBlock - 1) / kBlock;
   if (g > kKsGrid) g = kKsGrid;
@@ -134,7 +262,8 @@ int grid_for(long long n) {
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct KsLayout {
-  size_t poisson, vzero, rho_in, rho_out, vh, b, veff, part, res, total;
+  size_t poisson, vzero, rho_in, rho_out, vh, b, t1, veff, part, res, sx, sy,
+      sz, ev, total;
 };
 
 KsLayout ks_layout(const paro_box_t* box, size_t poisson_ws) {
@@ -153,9 +282,15 @@ KsLayout ks_layout(const paro_box_t* box, size_t poisson_ws) {
   L.rho_out = take(8 * n);
   L.vh = take(8 * n);
   L.b = take(8 * n);
+  L.t1 = take(8 * n);
   L.veff = take(8 * nv);
   L.part = take(8 * 2 * kKsGrid);
   L.res = take(8 * 4);
+  const size_t mx = box->nx - 1, my = box->ny - 1, mz = box->nz - 1;
+  L.sx = take(8 * mx * mx);
+  L.sy = take(8 * my * my);
+  L.sz = take(8 * mz * mz);
+  L.ev = take(8 * (mx + my + mz));
   L.total = o;
   return L;
 }
@@ -169,7 +304,7 @@ paro_opts_t poisson_opts(const paro_ks_opts_t* k) {
   o.sigma_mode = 1;  // (1/2) K exactly: no shift
   o.sigma = 0.0;
   o.pcg_rtol = k->poisson_rtol;
-  o.pcg_maxit = k->poisson_maxit;
+  o.pcg_maxit = k->poisson_maxit > 0 ? k->poisson_maxit : 1;  // 0: direct
   return o;
 }
 
@@ -197,7 +332,7 @@ void paro_ks_default_opts(paro_ks_opts_t* o) {
   o->occupancy = 2.0;
   o->scf_tol = 1e-8;
   o->poisson_rtol = 1e-12;
-  o->poisson_maxit = 20000;
+  o->poisson_maxit = 0;  // direct sine-transform solve
 }
 
 int paro_ks_query(const paro_box_t* box, size_t* workspace_bytes) {
@@ -249,6 +384,22 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
     double* veff = (double*)(base + L.veff);
     double* part = (double*)(base + L.part);
     double* res = (double*)(base + L.res);
+    double* t1 = (double*)(base + L.t1);
+    double* Sx = (double*)(base + L.sx);
+    double* Sy = (double*)(base + L.sy);
+    double* Sz = (double*)(base + L.sz);
+    double* ev = (double*)(base + L.ev);
+    const int mx = box.nx - 1, my = box.ny - 1, mz = box.nz - 1;
+    const bool direct = kopt->poisson_maxit <= 0;
+    if (direct) {
+      const double hx = (box.hi[0] - box.lo[0]) / box.nx;
+      const double hy = (box.hi[1] - box.lo[1]) / box.ny;
+      const double hz = (box.hi[2] - box.lo[2]) / box.nz;
+      hipLaunchKernelGGL(dst_tables_kernel, dim3(64), dim3(kBlock), 0, s, mx,
+                         my, mz, hy * hz / hx, hz * hx / hy, hx * hy / hz, Sx,
+                         Sy, Sz, ev);
+      KS_HIP(hipGetLastError());
+    }
     KS_HIP(hipMemsetAsync(vzero, 0, 8 * nv, s));
     KS_HIP(hipMemsetAsync(vh, 0, 8 * n, s));
     // The potential-free operator (1/2) K of the Poisson problem.
@@ -281,16 +432,29 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
       hipLaunchKernelGGL(ks_residual_kernel, dim3(1), dim3(kBlock), 0, s,
                          (const double*)part, res);
       KS_HIP(hipGetLastError());
-      // Hartree: (1/2) K V_H = 2 pi M rho_in, warm-started from the last V_H.
+      // Hartree: K V_H = 4 pi M rho_in.
       rc = paro_spmm(pois, 1, rho_in, b, 1, s);
       if (rc) return rc;
-      hipLaunchKernelGGL(ks_scale_kernel, dim3(gd), dim3(kBlock), 0, s, b,
-                         (long long)n, 2.0 * M_PI);
-      KS_HIP(hipGetLastError());
-      int32_t pit = 0;
-      rc = paro_pcg(pois, b, vh, 1, &pit, s);
-      if (rc) return rc;
-      rep.poisson_iters += pit;
+      if (direct) {
+        // V_H = S^-1 diag(lambda)^-1 S (4 pi M rho), S^-1 = prod_a
+        // 2 / (m_a + 1) S.
+        KS_HIP(dst3(s, mx, my, mz, Sx, Sy, Sz, b, t1, vh, 4.0 * M_PI));
+        hipLaunchKernelGGL(dst_divide_kernel, dim3(gd), dim3(kBlock), 0, s,
+                           vh, mx, my, mz, (const double*)ev);
+        KS_HIP(hipGetLastError());
+        const double inv = 8.0 / ((double)(mx + 1) * (my + 1) * (mz + 1));
+        KS_HIP(dst3(s, mx, my, mz, Sx, Sy, Sz, vh, t1, b, inv));
+        KS_HIP(hipMemcpyAsync(vh, b, 8 * n, hipMemcpyDeviceToDevice, s));
+      } else {
+        // (1/2) K V_H = 2 pi M rho_in by PCG, warm-started from the last V_H.
+        hipLaunchKernelGGL(ks_scale_kernel, dim3(gd), dim3(kBlock), 0, s, b,
+                           (long long)n, 2.0 * M_PI);
+        KS_HIP(hipGetLastError());
+        int32_t pit = 0;
+        rc = paro_pcg(pois, b, vh, 1, &pit, s);
+        if (rc) return rc;
+        rep.poisson_iters += pit;
+      }
       // Effective potential and the values-only re-assembly.
       hipLaunchKernelGGL(ks_potential_kernel, dim3(gv), dim3(kBlock), 0, s,
                          d_Vext, (const double*)vh, (const double*)rho_in,

@@ -125,3 +125,16 @@ def test_server_host_side_checks(lib):
     assert lib.paro_server_report(srv, rid.value,
                                   ctypes.byref(rep)) == pb.PARO_EINVAL
     lib.paro_server_destroy(srv)
+
+
+def test_kohn_sham_defaults_and_workspace_query(lib):
+    o = pb.ks_default_opts()
+    assert o.poisson_maxit == 0 and o.mixing == 0.3 and o.occupancy == 2.0
+    small = ctypes.c_size_t(0)
+    big = ctypes.c_size_t(0)
+    assert lib.paro_ks_query(ctypes.byref(pb.Box.cube(10, -6.0, 6.0)),
+                             ctypes.byref(small)) == pb.PARO_OK
+    assert lib.paro_ks_query(ctypes.byref(pb.Box.cube(20, -6.0, 6.0)),
+                             ctypes.byref(big)) == pb.PARO_OK
+    # densities, potentials and the sine tables grow with the grid
+    assert big.value > small.value > 8 * 9 ** 3 * 4

@@ -82,3 +82,27 @@ def test_update_potential_equals_fresh_assembly():
     for x, y in zip(a[:4], b[:4]):
         assert torch.equal(x, y)
     assert a[4] == b[4] == pb.paro_sigma(q)
+
+
+def test_direct_hartree_equals_pcg_hartree():
+    """The sine-transform Hartree solve and the Jacobi-PCG one (tight
+    tolerance) give the same outer iterates."""
+    w = small_molecule(nc=12)
+    out = []
+    for maxit in (0, 20000):
+        import torch
+        p = gu.workload_problem(w, precision=pb.PARO_FP64, pcg_rtol=1e-12,
+                                lambda_tol=1e-12, resid_tol=1e-9)
+        lam = torch.zeros(w.Nt, dtype=torch.float64, device=gu.device())
+        U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=gu.device())
+        rho = torch.zeros(w.n_dof, dtype=torch.float64, device=gu.device())
+        o = pb.ks_default_opts(max_iter=6, scf_tol=0.0, poisson_rtol=1e-14,
+                               poisson_maxit=maxit)
+        rep = pb.paro_ks_solve(p, gu.to_dev(w.V), gu.to_dev(w.U0()), lam, U,
+                               o, rho=rho)
+        torch.cuda.synchronize()
+        out.append((lam.cpu().numpy(), rho.cpu().numpy(), rep))
+    (l0, r0, rep0), (l1, r1, rep1) = out
+    assert rep0.poisson_iters == 0 and rep1.poisson_iters > 0
+    assert np.max(np.abs(l0 - l1) / np.abs(l1)) < 1e-10
+    assert np.linalg.norm(r0 - r1) / np.linalg.norm(r1) < 1e-10
