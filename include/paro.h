@@ -408,6 +408,22 @@ void paro_set_graphs(int on);
  * kernel-by-kernel launches.  Process-wide. */
 void paro_set_persistent(int on);
 
+/* Cluster-wise projection, the eigenvalue-separation variant of Sec. 3
+ * (remarks after Algorithm 3.1): the N + m columns form `count`
+ * consecutive clusters of sizes[0..count) (each >= 1, summing to N + m),
+ * and every following Rayleigh-Ritz step (paro_step, paro_solve, batch
+ * steps) projects each cluster's updated orbitals on its own span: the
+ * Gram blocks coupling different clusters are dropped, the small problem
+ * separates into one problem per cluster, and Ritz pairs are ordered
+ * within each cluster, which keeps its columns.  The paper assumes initial
+ * data close to each cluster's eigenspace.  In floating point, components
+ * along lower eigenvectors grow (inverse iteration amplifies them by
+ * (lambda_i - s) / (lambda_j - s) per step), so clustered steps must be
+ * interleaved with full ones; count = 0 restores the full projection.
+ * Synchronises `stream`; EINVAL on bad sizes. */
+int paro_set_clusters(paro_problem* p, const int32_t* sizes, int32_t count,
+                      void* stream);
+
 /* Autotuner (on by default): at assembly, the CG SpMM of each new problem
  * shape (grid, N + m, precision) is timed with the full and the halved
  * real block count, and the faster is kept for the shape for the rest of

@@ -141,6 +141,7 @@ def lib():
         "paro_set_timing": (c_i32, [P, c_i32]),
         "paro_set_graphs": (None, [c_i32]),
         "paro_set_persistent": (None, [c_i32]),
+        "paro_set_clusters": (c_i32, [P, P, c_i32, P]),
         "paro_set_autotune": (None, [c_i32]),
         "paro_tuned": (c_i32, [P, ctypes.POINTER(c_i32),
                                ctypes.POINTER(c_i32)]),
@@ -365,6 +366,14 @@ def paro_pcg(p: Problem, B, X, stream=None):
 def paro_set_graphs(on: bool = True):
     """Run CG chunks as captured HIP graphs (default) or kernel by kernel."""
     lib().paro_set_graphs(1 if on else 0)
+
+
+def paro_set_clusters(p: Problem, sizes=(), stream=None):
+    """Cluster-wise projection over consecutive column clusters of the given
+    sizes (summing to N + m); an empty sequence restores the full one."""
+    arr = (c_i32 * max(1, len(sizes)))(*sizes)
+    _check(lib().paro_set_clusters(p.handle, ctypes.cast(arr, ctypes.c_void_p),
+                                   len(sizes), _stream(stream)))
 
 
 def paro_set_persistent(on: bool = True):

@@ -202,6 +202,8 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.cnt = (unsigned*)at(L.cnt);
   p.flag = (int*)at(L.flag);
   p.dd = (Desc*)at(L.desc);
+  p.clus = (int*)at(L.clus);
+  p.clustered = false;
 }
 
 int pick_grid(int64_t n, int Nt) {
@@ -273,6 +275,7 @@ void desc_init(Problem& p) {
   d.cs = p.cs;
   d.si = p.si;
   d.geneig_info = &p.si->geneig_info;
+  d.clus = p.clustered ? p.clus : nullptr;
 }
 
 // Column count of a descriptor (component calls use fewer than N + m).
@@ -847,6 +850,7 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.cnt = take(sizeof(unsigned) * kCntNum);
   L.flag = take(sizeof(int) * 16);
   L.desc = take(sizeof(Desc));
+  L.clus = take(sizeof(int) * kNtMax);
   L.total = off;
   return L;
 }
@@ -1252,6 +1256,36 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
 void paro_set_graphs(int on) { g_graphs_on.store(on ? 1 : 0); }
 
 void paro_set_persistent(int on) { g_persistent_on.store(on ? 1 : 0); }
+
+int paro_set_clusters(paro_problem* h, const int32_t* sizes, int32_t count,
+                      void* stream) {
+  if (!h) return fail(PARO_EINVAL, "NULL problem");
+  Problem& p = h->p;
+  if (count == 0) {
+    p.clustered = false;
+    p.hd.clus = nullptr;
+    return PARO_OK;
+  }
+  if (count < 0 || count > p.Nt || !sizes)
+    return fail(PARO_EINVAL, "cluster count must be 0..%d", p.Nt);
+  int ids[kNtMax];
+  int c = 0;
+  for (int k = 0; k < count; ++k) {
+    if (sizes[k] < 1 || c + sizes[k] > p.Nt)
+      return fail(PARO_EINVAL, "cluster sizes must be >= 1 and sum to %d",
+                  p.Nt);
+    for (int j = 0; j < sizes[k]; ++j) ids[c++] = k;
+  }
+  if (c != p.Nt)
+    return fail(PARO_EINVAL, "cluster sizes must sum to N + m = %d", p.Nt);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(hipMemcpyAsync(p.clus, ids, sizeof(int) * p.Nt,
+                             hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));  // ids is a stack array
+  p.clustered = true;
+  p.hd.clus = p.clus;
+  return PARO_OK;
+}
 
 void paro_set_autotune(int on) { g_autotune_on.store(on ? 1 : 0); }
 

@@ -148,6 +148,8 @@ struct Desc {
   ColState* cs;
   StepInfo* si;
   int* geneig_info;
+  const int* clus;        // cluster id per column (cluster-wise Step 4),
+                          // or null (full projection)
 };
 
 // Columns per thread of a problem with `ncols` columns: the widest vector
@@ -227,6 +229,8 @@ struct Problem {
   float* Q32;
   float* X32;
   double* part;           // kGridMax * kNtMax * 3 reduction partials
+  int* clus;              // kNtMax cluster ids (paro_set_clusters)
+  bool clustered;
   double* cpart;          // FP32 CG partials: 2 Nt cm_tiles(n) (r.z, r.r),
                           // then Nt ceil(n / kBlock) (p.q)
   double* gpart;          // Gram partials: kGramGrid * gram_tiles(Nt)
@@ -261,7 +265,7 @@ struct Layout {
   size_t X, R, P, Q, B, Xc, R32, P32, Q32, X32;
   size_t part, cpart, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
-  size_t desc;
+  size_t desc, clus;
   size_t total;
 };
 

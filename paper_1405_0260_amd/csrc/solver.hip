@@ -1493,7 +1493,8 @@ __device__ void geneig_body(const double* __restrict__ Ain,
                             double* __restrict__ theta_out,
                             double* __restrict__ C_out,
                             int* __restrict__ info_out,
-                            int* __restrict__ status) {
+                            int* __restrict__ status,
+                            const int* __restrict__ clus) {
   __shared__ double A[kNtMax][kLd];
   __shared__ double L[kNtMax][kLd];
   __shared__ double Y[kNtMax][kLd];
@@ -1516,11 +1517,15 @@ __device__ void geneig_body(const double* __restrict__ Ain,
   }
   if (tid == 0) s_info = 0;
   __syncthreads();
+  // Cluster-wise projection: entries coupling different clusters are
+  // dropped, so every step below works block by block (rotations and
+  // substitutions never mix blocks of a block-diagonal pencil).
 #pragma unroll 4
   for (int e = tid; e < n * n; e += kBlock) {
-    const double a = Ain[e], b = Bin[e];
-    A[e / n][e % n] = a;
-    L[e / n][e % n] = b;
+    const int i = e / n, j = e % n;
+    const bool keep = !clus || clus[i] == clus[j];
+    A[i][j] = keep ? Ain[e] : 0.0;
+    L[i][j] = keep ? Bin[e] : 0.0;
   }
   __syncthreads();
 
@@ -1694,14 +1699,21 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     __syncthreads();
   }
 
-  // 4. Ascending order, ties broken by index.
+  // 4. Ascending order, ties broken by index (with clusters: within each
+  // cluster, which keeps its columns).
   if (tid < n) th[tid] = A[tid][tid];
   __syncthreads();
   if (tid < n) {
     int rank = 0;
     const double t = th[tid];
-    for (int j = 0; j < n; ++j)
-      rank += (th[j] < t || (th[j] == t && j < tid)) ? 1 : 0;
+    const int c = clus ? clus[tid] : 0;
+    for (int j = 0; j < n; ++j) {
+      const int cj = clus ? clus[j] : 0;
+      if (cj < c)
+        ++rank;
+      else if (cj == c)
+        rank += (th[j] < t || (th[j] == t && j < tid)) ? 1 : 0;
+    }
     perm[rank] = tid;
   }
   __syncthreads();
@@ -1744,7 +1756,7 @@ __global__ void __launch_bounds__(kBlock)
 small_geneig_kernel(const double* __restrict__ A, const double* __restrict__ B,
                     int n, double* __restrict__ theta, double* __restrict__ C,
                     int* __restrict__ info) {
-  geneig_body(A, B, n, theta, C, info, nullptr);
+  geneig_body(A, B, n, theta, C, info, nullptr, nullptr);
 }
 
 // Step 4's small eigenproblem of every problem of the table (one block
@@ -1753,7 +1765,7 @@ __global__ void __launch_bounds__(kBlock)
 geneig_batch_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.x];
   geneig_body(d.Ah, d.Bh, d.ncols, d.theta, d.C, d.geneig_info,
-              &d.cs->status);
+              &d.cs->status, d.clus);
 }
 
 // ------------------------------------------------------------------------
