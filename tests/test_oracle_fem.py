@@ -189,3 +189,24 @@ def test_non_cubic_box_counts_and_row_sums():
         (m[0] - 1, m[1], m[2] - 1), (m[0], m[1] - 1, m[2] - 1),
         (m[0] - 1, m[1] - 1, m[2] - 1)]) * 2 - m[0] * m[1] * m[2]
     assert K.nnz == z
+
+
+def test_stiffness_is_the_anisotropic_seven_point_operator():
+    """On a box with unequal spacings the Kuhn P1 stiffness matrix is still
+    sum_a c_a T_a (T_a = tridiag(-1, 2, -1) along axis a, c_x = hy hz / hx
+    and cyclically): the direct Hartree solve relies on it."""
+    import scipy.sparse as sp
+    ncs, lo, hi = (5, 6, 7), (0.0, -1.0, 0.5), (1.0, 0.7, 3.4)
+    mesh = fem.kuhn_mesh(ncs, lo, hi)
+    K, _, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    h = [(hi[a] - lo[a]) / ncs[a] for a in range(3)]
+    m = [c - 1 for c in ncs]
+    T = [sp.diags([-np.ones(k - 1), 2 * np.ones(k), -np.ones(k - 1)],
+                  [-1, 0, 1]) for k in m]
+    I = [sp.identity(k) for k in m]
+    c = [h[1] * h[2] / h[0], h[2] * h[0] / h[1], h[0] * h[1] / h[2]]
+    # rows: x fastest, so the Kronecker order is z (x) y (x) x
+    ref = (c[0] * sp.kron(I[2], sp.kron(I[1], T[0])) +
+           c[1] * sp.kron(I[2], sp.kron(T[1], I[0])) +
+           c[2] * sp.kron(T[2], sp.kron(I[1], I[0])))
+    assert abs(K - ref).max() < 1e-13 * abs(ref).max()
