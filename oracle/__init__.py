@@ -19,4 +19,6 @@ calculations", arXiv:1405.0260, that it follows):
              library eigensolvers.
   kohn_sham  Density, Hartree (Poisson) and Slater-exchange potentials for a
              self-consistent ParO (Sec. 2 Kohn-Sham equation; Algorithm 3.1).
+  nonlocal_  The nonlocal pseudopotential term V_nl u = sum_j (u, zeta_j)
+             zeta_j as the rank-k Galerkin operator Z Z^T (Sec. 2).
 """

@@ -173,6 +173,20 @@ def harmonic_buffer(N: int) -> int:
     return nxt - N if nxt - N <= 16 else closure - N + 1
 
 
+def gaussian_projectors(nc: int, lo: float, hi: float, centres: np.ndarray,
+                        width: float = 1.0, height: float = 1.0) -> np.ndarray:
+    """Synthetic nonlocal projectors: one Gaussian per centre,
+    zeta_j(x) = height exp(-|x - R_j|^2 / (2 width^2)), sampled at the
+    interior vertices (n_dof x len(centres), x fastest)."""
+    X = vertex_coords(nc, lo, hi)
+    m = nc + 1
+    inner = np.zeros((m, m, m), dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    Xi = X[inner.reshape(-1)]
+    d2 = ((Xi[:, None, :] - np.asarray(centres)[None, :, :]) ** 2).sum(-1)
+    return height * np.exp(-d2 / (2.0 * width * width))
+
+
 def serve_requests(count: int, seed: int = 5, big_fraction: float = 0.25,
                    big_nc: int = 64) -> List[Workload]:
     """Request mix of the served stream: a fraction `big_fraction` of
