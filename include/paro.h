@@ -424,6 +424,23 @@ void paro_set_persistent(int on);
 int paro_set_clusters(paro_problem* p, const int32_t* sizes, int32_t count,
                       void* stream);
 
+/* Nonlocal pseudopotential term (Sec. 2, the pseudopotential model):
+ * V_nl u = sum_j (u, zeta_j) zeta_j with k projector functions zeta_j,
+ * given by their values at the interior vertices, d_zeta n x k row-major
+ * (device).  Its Galerkin matrix is Z Z^T with Z = M zeta, which the
+ * library forms in the caller's workspace d_ws (size from
+ * paro_nonlocal_query, 256-byte aligned, kept alive and unmodified while
+ * the term is set); the Hamiltonian of every later source solve and
+ * projection is H + Z Z^T (the Jacobi preconditioner keeps the local
+ * diagonal; the shift stays valid since Z Z^T is positive semidefinite).
+ * FP64 precision only (EINVAL otherwise); 1 <= k <= 64; k = 0 removes the
+ * term.  Asynchronous on `stream`.  The component calls (paro_spmm,
+ * paro_pcg) and the persistent CG apply the local operator only; with the
+ * term set, CG runs kernel by kernel. */
+int paro_nonlocal_query(const paro_problem* p, int32_t k, size_t* bytes);
+int paro_set_nonlocal(paro_problem* p, const double* d_zeta, int32_t k,
+                      void* d_ws, size_t bytes, void* stream);
+
 /* Autotuner (on by default): at assembly, the CG SpMM of each new problem
  * shape (grid, N + m, precision) is timed with the full and the halved
  * real block count, and the faster is kept for the shape for the rest of

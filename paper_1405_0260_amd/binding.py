@@ -142,6 +142,8 @@ def lib():
         "paro_set_graphs": (None, [c_i32]),
         "paro_set_persistent": (None, [c_i32]),
         "paro_set_clusters": (c_i32, [P, P, c_i32, P]),
+        "paro_nonlocal_query": (c_i32, [P, c_i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "paro_set_nonlocal": (c_i32, [P, P, c_i32, P, ctypes.c_size_t, P]),
         "paro_set_autotune": (None, [c_i32]),
         "paro_tuned": (c_i32, [P, ctypes.POINTER(c_i32),
                                ctypes.POINTER(c_i32)]),
@@ -374,6 +376,28 @@ def paro_set_clusters(p: Problem, sizes=(), stream=None):
     arr = (c_i32 * max(1, len(sizes)))(*sizes)
     _check(lib().paro_set_clusters(p.handle, ctypes.cast(arr, ctypes.c_void_p),
                                    len(sizes), _stream(stream)))
+
+
+def paro_set_nonlocal(p: Problem, zeta=None, stream=None):
+    """Add the nonlocal term with projector values zeta (n x k device
+    tensor, FP64); None removes it.  The workspace is allocated here and
+    kept on the problem object."""
+    import torch
+    if zeta is None:
+        _check(lib().paro_set_nonlocal(p.handle, None, 0, None, 0,
+                                       _stream(stream)))
+        p._nl_ws = None
+        return
+    k = zeta.shape[1]
+    _f64(zeta, (p.n, k), "zeta")
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().paro_nonlocal_query(p.handle, k, ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=zeta.device)
+    off = (-ws.data_ptr()) % 256
+    _check(lib().paro_set_nonlocal(p.handle, _ptr(zeta), k,
+                                   ws.data_ptr() + off, nbytes.value,
+                                   _stream(stream)))
+    p._nl_ws = ws
 
 
 def paro_set_persistent(on: bool = True):

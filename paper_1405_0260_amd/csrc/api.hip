@@ -204,6 +204,9 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.dd = (Desc*)at(L.desc);
   p.clus = (int*)at(L.clus);
   p.clustered = false;
+  p.Zp = nullptr;
+  p.kz = 0;
+  p.zy = p.zpart = nullptr;
 }
 
 int pick_grid(int64_t n, int Nt) {
@@ -276,6 +279,10 @@ void desc_init(Problem& p) {
   d.si = p.si;
   d.geneig_info = &p.si->geneig_info;
   d.clus = p.clustered ? p.clus : nullptr;
+  d.Zp = p.Zp;
+  d.kz = p.kz;
+  d.zy = p.zy;
+  d.zpart = p.zpart;
 }
 
 // Column count of a descriptor (component calls use fewer than N + m).
@@ -304,6 +311,7 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
     L.vmax64 = std::max(L.vmax64, d.v64);
   }
   L.nt16 = (L.maxcols + 15) / 16;
+  for (int i = 0; i < n; ++i) L.maxkz = std::max(L.maxkz, tab[i].kz);
   L.v64u = n > 0 ? tab[0].v64 : 0;
   L.v32u = n > 0 ? tab[0].v32 : 0;
   for (int i = 1; i < n; ++i) {
@@ -557,7 +565,7 @@ int run_cg_persistent(Ctx& c, bool fp32, hipStream_t s, int slot) {
 }
 
 int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
-  if (g_persistent_on.load()) {
+  if (g_persistent_on.load() && c.L.maxkz == 0) {
     const int rc = run_cg_persistent(c, fp32, s, slot);
     if (rc != 1) return rc;  // 1: does not fit, run kernel by kernel
   }
@@ -1256,6 +1264,60 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
 void paro_set_graphs(int on) { g_graphs_on.store(on ? 1 : 0); }
 
 void paro_set_persistent(int on) { g_persistent_on.store(on ? 1 : 0); }
+
+namespace {
+size_t up256n(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+int paro_nonlocal_query(const paro_problem* h, int32_t k, size_t* bytes) {
+  if (!h || !bytes) return fail(PARO_EINVAL, "NULL argument");
+  const Problem& p = h->p;
+  if (k < 0 || k > kNtMax)
+    return fail(PARO_EINVAL, "projector count must be 0..%d", kNtMax);
+  *bytes = up256n(sizeof(double) * (size_t)p.n * k) +
+           up256n(sizeof(double) * (size_t)k * kNtMax) +
+           up256n(sizeof(double) * (size_t)k * kNtMax * cm_tiles(p.n));
+  return PARO_OK;
+}
+
+int paro_set_nonlocal(paro_problem* h, const double* d_zeta, int32_t k,
+                      void* d_ws, size_t bytes, void* stream) {
+  if (!h) return fail(PARO_EINVAL, "NULL problem");
+  Problem& p = h->p;
+  if (k == 0) {
+    p.Zp = nullptr;
+    p.kz = 0;
+    p.zy = p.zpart = nullptr;
+    p.hd.Zp = nullptr;
+    p.hd.kz = 0;
+    return PARO_OK;
+  }
+  if (p.opts.precision != PARO_FP64)
+    return fail(PARO_EINVAL, "the nonlocal term needs precision PARO_FP64");
+  size_t need = 0;
+  const int rc = paro_nonlocal_query(h, k, &need);
+  if (rc) return rc;
+  if (!d_zeta || !d_ws) return fail(PARO_EINVAL, "NULL argument");
+  if (((uintptr_t)d_ws & 255) != 0)
+    return fail(PARO_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(PARO_ENOMEM, "nonlocal workspace too small: %zu < %zu",
+                bytes, need);
+  char* base = (char*)d_ws;
+  double* Z = (double*)base;
+  base += up256n(sizeof(double) * (size_t)p.n * k);
+  p.zy = (double*)base;
+  base += up256n(sizeof(double) * (size_t)k * kNtMax);
+  p.zpart = (double*)base;
+  HIP_OR_FAIL(launch_nl_mass(p.hd, d_zeta, Z, k, (hipStream_t)stream));
+  p.Zp = Z;
+  p.kz = k;
+  p.hd.Zp = p.Zp;
+  p.hd.kz = k;
+  p.hd.zy = p.zy;
+  p.hd.zpart = p.zpart;
+  return PARO_OK;
+}
 
 int paro_set_clusters(paro_problem* h, const int32_t* sizes, int32_t count,
                       void* stream) {

@@ -150,6 +150,11 @@ struct Desc {
   int* geneig_info;
   const int* clus;        // cluster id per column (cluster-wise Step 4),
                           // or null (full projection)
+  const double* Zp;       // nonlocal term: Z = M zeta (n x kz, row-major),
+                          // or null
+  int kz;                 // number of projectors (0: none)
+  double* zy;             // kz x ncols: Z^T X of the current phase
+  double* zpart;          // kz ncols x ntc partial sums of Z^T X
 };
 
 // Columns per thread of a problem with `ncols` columns: the widest vector
@@ -183,6 +188,7 @@ struct Launch {
   int vmax64;             // widest FP64 vector of the table
   int v64u, v32u;         // common vector width of all problems, or 0
   int nt16_mixed;         // problems differ in ceil(ncols / 16)
+  int maxkz;              // most nonlocal projectors of a problem (0: none)
 };
 
 // Per-problem step summary for the host (one PollReport per problem).
@@ -231,6 +237,10 @@ struct Problem {
   double* part;           // kGridMax * kNtMax * 3 reduction partials
   int* clus;              // kNtMax cluster ids (paro_set_clusters)
   bool clustered;
+  const double* Zp;       // nonlocal projectors (caller's workspace)
+  int kz;
+  double* zy;
+  double* zpart;
   double* cpart;          // FP32 CG partials: 2 Nt cm_tiles(n) (r.z, r.r),
                           // then Nt ceil(n / kBlock) (p.q)
   double* gpart;          // Gram partials: kGramGrid * gram_tiles(Nt)
@@ -305,6 +315,9 @@ hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s);
 // the grid cannot be co-resident on the device.
 hipError_t launch_cg_persistent(Launch& L, bool fp32, int iters,
                                 hipStream_t s, Timing* t, bool* fits);
+// Nonlocal term: Z = M zeta for one problem (zeta n x k, row-major).
+hipError_t launch_nl_mass(const Desc& d, const double* zeta, double* Z,
+                          int k, hipStream_t s);
 // FP64 source solves: the orbitals X receive the chunk-major iterate Xc.
 hipError_t launch_cm_unpack(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_all_active(Launch& L, hipStream_t s);

@@ -372,7 +372,11 @@ __device__ __forceinline__ void alpha_pair(const Desc& d, int c, int par) {
   double tot[1];
   column_sums<1>(d.pqp, 0, c, d.pqn, tot);
   if (lane == 0) {
-    const double pq = tot[0];
+    double pq = tot[0];
+    for (int j = 0; j < d.kz; ++j) {  // nonlocal share: ||Z^T p||^2
+      const double y = d.zy[j * d.ncols + c];
+      pq = fma(y, y, pq);
+    }
     if (!(pq > 0.0) || !isfinite(pq)) {
       atomicOr(&cs->status, isfinite(pq) ? (int)kStNotSpd : (int)kStNonFinite);
       cs->alpha[c] = 0.0;
@@ -807,6 +811,156 @@ redirect_cm_kernel(const Desc* __restrict__ D, int nprob) {
 }
 
 // ------------------------------------------------------------------------
+// Nonlocal pseudopotential term (Sec. 2): V_nl u = sum_j (u, zeta_j) zeta_j
+// has the Galerkin matrix Z Z^T with Z = M zeta (n x k), so the operator of
+// the source problems and of the projection becomes A + Z Z^T.  It is
+// applied as a low-rank correction around the stencil kernels: Y = Z^T X
+// (per-tile partials over kCmRows rows, then one wavefront per (projector,
+// column) in a fixed order), then Q += Z Y.  In the CG the correction's
+// share of p.q is ||Z^T p||^2, added by the alpha finaliser.
+// ------------------------------------------------------------------------
+
+// Z[row][j] = sum_s M[row][row + off_s] zeta[row + off_s][j].
+__global__ void __launch_bounds__(kBlock)
+nl_mass_kernel(Desc d, const double* __restrict__ zeta,
+               double* __restrict__ Z, int k) {
+  const long long total = d.n * k;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total;
+       e += (long long)gridDim.x * kBlock) {
+    const long long row = e / k;
+    const int j = (int)(e - row * k);
+    const unsigned ur = (unsigned)row;
+    const unsigned uq = ur / (unsigned)d.mx;
+    const int i = (int)(ur - uq * (unsigned)d.mx);
+    const unsigned uk = uq / (unsigned)d.my;
+    const int jj = (int)(uq - uk * (unsigned)d.my);
+    const int kk = (int)uk;
+    double acc = 0.0;
+#pragma unroll
+    for (int st = 0; st < kStencil; ++st) {
+      const int ox = st_off(st, 0), oy = st_off(st, 1), oz = st_off(st, 2);
+      const bool ok = (unsigned)(i + ox) < (unsigned)d.mx &&
+                      (unsigned)(jj + oy) < (unsigned)d.my &&
+                      (unsigned)(kk + oz) < (unsigned)d.mz;
+      const long long nb = ok ? row + ox + (long long)d.mx * (oy + (long long)d.my * oz) : row;
+      acc = fma(ldg(d.diagM + (size_t)st * d.n + row), zeta[nb * k + j], acc);
+    }
+    Z[e] = acc;
+  }
+}
+
+// Sources of Z^T X: the FP64 CG direction P (chunk-major), the start
+// orbitals U0 or the basis X (row-major).
+enum { kZtP = 0, kZtU0 = 1, kZtX = 2 };
+
+__device__ __forceinline__ double zt_src(const Desc& d, int src, long long row,
+                                         int c) {
+  if (src == kZtP) return d.P[cm_index(d.n, row, c, d.v64)];
+  const double* X = src == kZtU0 ? d.U0 : d.X;
+  return X[(size_t)row * d.ncols + c];
+}
+
+// Partials of Y = Z^T X over the tiles of kCmRows rows: staged 64 rows at
+// a time in LDS, one (projector, column) pair per thread.
+__global__ void __launch_bounds__(kBlock)
+zt_partial_kernel(const Desc* __restrict__ D, int nprob, int src) {
+  __shared__ double zs[64][kNtMax + 1], xs[64][kNtMax + 1];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (d.kz == 0) return;
+  const int lb = blockIdx.x - d.b0;
+  const int k = d.kz, nc = d.ncols, npair = k * nc;
+  for (TileWalk w = tile_walk(d.ntc, lb, d.nb); w.t < w.end; w.t += w.step) {
+    const long long r0 = w.t * kCmRows;
+    const int rows = (int)min((long long)kCmRows, d.n - r0);
+    double acc[(kNtMax * kNtMax + kBlock - 1) / kBlock];
+    constexpr int kMaxPer = (kNtMax * kNtMax + kBlock - 1) / kBlock;
+#pragma unroll
+    for (int a = 0; a < kMaxPer; ++a) acc[a] = 0.0;
+    for (int s0 = 0; s0 < rows; s0 += 64) {
+      const int sr = min(64, rows - s0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < sr * k; e += kBlock)
+        zs[e / k][e % k] = ldg(d.Zp + (size_t)(r0 + s0 + e / k) * k + e % k);
+      for (int e = threadIdx.x; e < sr * nc; e += kBlock)
+        xs[e / nc][e % nc] = zt_src(d, src, r0 + s0 + e / nc, e % nc);
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < kMaxPer; ++a) {
+        const int q = threadIdx.x + a * kBlock;
+        if (q >= npair) break;
+        const int j = q / nc, c = q % nc;
+        double v = acc[a];
+        for (int r = 0; r < sr; ++r) v = fma(zs[r][j], xs[r][c], v);
+        acc[a] = v;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kMaxPer; ++a) {
+      const int q = threadIdx.x + a * kBlock;
+      if (q < npair) stg(d.zpart + (size_t)q * d.ntc + w.t, acc[a]);
+    }
+  }
+}
+
+// Y[j][c] = sum over tiles (one wavefront per pair; grid: pair x problem).
+__global__ void __launch_bounds__(kFinal)
+zt_final_kernel(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.y];
+  const int q = blockIdx.x;
+  if (d.kz == 0 || q >= d.kz * d.ncols) return;
+  double tot[1];
+  column_sums<1>(d.zpart, 0, q, d.ntc, tot);
+  if ((threadIdx.x & (kFinal - 1)) == 0) d.zy[q] = tot[0];
+}
+
+// FP64 CG: Q += Z Y on the active chunks (after the stencil SpMM).
+__global__ void __launch_bounds__(kBlock)
+lowrank_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (d.kz == 0 || ldg(&d.cs->n_active[par]) == 0) return;
+  const int lb = blockIdx.x - d.b0;
+  const int V = d.v64, cpr = d.ncols / V, k = d.kz;
+  for (TileWalk w = tile_walk((long long)d.ntc * cpr, lb, d.nb); w.t < w.end;
+       w.t += w.step) {
+    const CmUnit un = cm_unit(w.t, cpr);
+    if (!chunk_active(d.cs->act[par], un.ch, V, d.ncols)) continue;
+    for (int rr = 0; rr < kCmRpt; ++rr) {
+      const long long row = un.t * kCmRows + threadIdx.x + rr * kBlock;
+      if (row >= d.n) break;
+      for (int u = 0; u < V; ++u) {
+        const int c = un.ch * V + u;
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j)
+          acc = fma(ldg(d.Zp + (size_t)row * k + j), ldg(d.zy + j * d.ncols + c),
+                    acc);
+        double* q = d.Q + cm_index(d.n, row, c, V);
+        *q += acc;
+      }
+    }
+  }
+}
+
+// Rayleigh-Ritz: HW (row-major, in R) += Z Y.
+__global__ void __launch_bounds__(kBlock)
+lowrank_rm_kernel(const Desc* __restrict__ D, int nprob) {
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (d.kz == 0) return;
+  const int lb = blockIdx.x - d.b0;
+  const long long total = d.n * d.ncols;
+  const int k = d.kz;
+  for (long long e = (long long)lb * kBlock + threadIdx.x; e < total;
+       e += (long long)d.nb * kBlock) {
+    const long long row = e / d.ncols;
+    const int c = (int)(e - row * d.ncols);
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j)
+      acc = fma(ldg(d.Zp + (size_t)row * k + j), ldg(d.zy + j * d.ncols + c),
+                acc);
+    d.R[e] += acc;
+  }
+}
+
+// ------------------------------------------------------------------------
 // Persistent CG: every iteration of every problem of the table in one
 // cooperative launch.  The phases of an iteration -- SpMM, alpha, r-update,
 // beta, p-update -- are the same device functions as the per-kernel path
@@ -952,6 +1106,13 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
     stencil_product<double, double, V, true, 8, true>(
         wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
         g.ch * V, au, mu, u);
+    for (int j = 0; j < d.kz; ++j) {  // nonlocal term: A u += Z (Z^T u)
+      const double z = ldg(d.Zp + (size_t)row * d.kz + j);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (g.ch * V + v < ncols)
+          au[v] = fma(z, ldg(d.zy + j * ncols + g.ch * V + v), au[v]);
+    }
     const size_t o = (size_t)row * ncols + g.ch * V;
     double b[V], r[V], p[V];
     if (d.Bin) {
@@ -1924,7 +2085,26 @@ hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t) {
   return hipGetLastError();
 }
 
+// Y = Z^T (source) for every problem with a nonlocal term.
+static void zt_launch(Launch& L, int src, hipStream_t s, Timing* t, int st) {
+  klaunch(t, st, zt_partial_kernel, dim3(L.blocks), dim3(kBlock), 0, s,
+          (const Desc*)L.d, L.nprob, src);
+  klaunch(t, st, zt_final_kernel, dim3(L.maxkz * L.maxcols, L.nprob),
+          dim3(kFinal), 0, s, (const Desc*)L.d);
+}
+
+hipError_t launch_nl_mass(const Desc& d, const double* zeta, double* Z,
+                          int k, hipStream_t s) {
+  const long long total = d.n * k;
+  const int grid = (int)std::min<long long>((total + kBlock - 1) / kBlock,
+                                            4096);
+  hipLaunchKernelGGL(nl_mass_kernel, dim3(grid), dim3(kBlock), 0, s, d, zeta,
+                     Z, k);
+  return hipGetLastError();
+}
+
 hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
+  if (L.maxkz) zt_launch(L, kZtU0, s, t, PARO_ST_START);
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_START, pcg_start_kernel, dim3(L.blocks),
                   dim3(kBlock), weights_bytes(L.tr64, sizeof(double), 2), s,
                   L.d, L.nprob);
@@ -1937,8 +2117,14 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
 template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
   const Desc* D = L.d;
+  if constexpr (sizeof(T) == 8)
+    if (L.maxkz) zt_launch(L, kZtP, s, t, PARO_ST_CG_SPMM);
   klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
+  if constexpr (sizeof(T) == 8)
+    if (L.maxkz)
+      klaunch(t, PARO_ST_CG_SPMM, lowrank_cm_kernel, dim3(L.blocks),
+              dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
           dim3(kFinal), 0, s, D, par);
   klaunch(t, PARO_ST_CG_RUPD, rupd_cm_kernel<T, W>, dim3(L.blocks),
@@ -2165,6 +2351,11 @@ hipError_t launch_small_geneig(const double* A, const double* B, int n,
 hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   hipError_t e;
   if ((e = launch_spmm(L, true, s, t)) != hipSuccess) return e;
+  if (L.maxkz) {  // HW += Z (Z^T W)
+    zt_launch(L, kZtX, s, t, PARO_ST_RR_SPMM);
+    klaunch(t, PARO_ST_RR_SPMM, lowrank_rm_kernel, dim3(L.blocks),
+            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob);
+  }
   if ((e = gram(L, true, s, t)) != hipSuccess) return e;
   klaunch(t, PARO_ST_SMALL, geneig_batch_kernel, dim3(L.nprob), dim3(kBlock),
           0, s, (const Desc*)L.d);
