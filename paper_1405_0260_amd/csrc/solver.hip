@@ -2180,19 +2180,17 @@ hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s) {
 template <typename T, int W>
 static hipError_t cg_persistent_w(Launch& L, int iters, hipStream_t s,
                                   Timing* t, bool* fits) {
-  static int per_cu = -1, cus = 0;
-  if (per_cu < 0) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(cg_persistent_kernel<T, W>),
-          kBlock, 0);
-    if (e != hipSuccess) return e;
-  }
+  // Co-resident capacity of this kernel on the current device.
+  int per_cu = 0, cus = 0, dev = 0;
+  hipError_t e0 = hipGetDevice(&dev);
+  if (e0 == hipSuccess)
+    e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                               dev);
+  if (e0 == hipSuccess)
+    e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(cg_persistent_kernel<T, W>),
+        kBlock, 0);
+  if (e0 != hipSuccess) return e0;
   *fits = (long long)per_cu * cus >= L.blocks;
   if (!*fits) return hipSuccess;
   const Desc* D = L.d;
