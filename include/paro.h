@@ -433,7 +433,7 @@ int paro_set_clusters(paro_problem* p, const int32_t* sizes, int32_t count,
  * the term is set); the Hamiltonian of every later source solve and
  * projection is H + Z Z^T (the Jacobi preconditioner keeps the local
  * diagonal; the shift stays valid since Z Z^T is positive semidefinite).
- * FP64 precision only (EINVAL otherwise); 1 <= k <= 64; k = 0 removes the
+ * FP64 precision only (EINVAL otherwise); 1 <= k <= 32; k = 0 removes the
  * term.  Asynchronous on `stream`.  The component calls (paro_spmm,
  * paro_pcg) and the persistent CG apply the local operator only; with the
  * term set, CG runs kernel by kernel. */

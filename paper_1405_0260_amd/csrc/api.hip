@@ -1272,8 +1272,8 @@ size_t up256n(size_t x) { return (x + 255) & ~size_t(255); }
 int paro_nonlocal_query(const paro_problem* h, int32_t k, size_t* bytes) {
   if (!h || !bytes) return fail(PARO_EINVAL, "NULL argument");
   const Problem& p = h->p;
-  if (k < 0 || k > kNtMax)
-    return fail(PARO_EINVAL, "projector count must be 0..%d", kNtMax);
+  if (k < 0 || k > 32)
+    return fail(PARO_EINVAL, "projector count must be 0..32");
   *bytes = up256n(sizeof(double) * (size_t)p.n * k) +
            up256n(sizeof(double) * (size_t)k * kNtMax) +
            up256n(sizeof(double) * (size_t)k * kNtMax * cm_tiles(p.n));

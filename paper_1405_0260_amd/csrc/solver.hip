@@ -372,11 +372,7 @@ __device__ __forceinline__ void alpha_pair(const Desc& d, int c, int par) {
   double tot[1];
   column_sums<1>(d.pqp, 0, c, d.pqn, tot);
   if (lane == 0) {
-    double pq = tot[0];
-    for (int j = 0; j < d.kz; ++j) {  // nonlocal share: ||Z^T p||^2
-      const double y = d.zy[j * d.ncols + c];
-      pq = fma(y, y, pq);
-    }
+    const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
       atomicOr(&cs->status, isfinite(pq) ? (int)kStNotSpd : (int)kStNonFinite);
       cs->alpha[c] = 0.0;
@@ -448,6 +444,18 @@ cg_beta_kernel(const Desc* __restrict__ D, int par) {
 __device__ __forceinline__ size_t cm_index(long long n, long long row, int c,
                                            int V) {
   return ((size_t)(c / V) * n + row) * V + (c % V);
+}
+
+// The nonlocal share of row `row`, columns c0 .. c0 + V: Z[row] Y[:, c].
+template <int V>
+__device__ __forceinline__ void nl_add(const Desc& d, long long row, int c0,
+                                       double (&y)[V]) {
+  for (int j = 0; j < d.kz; ++j) {
+    const double z = ldg(d.Zp + (size_t)row * d.kz + j);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      y[v] = fma(z, ldg(d.zy + j * d.ncols + c0 + v), y[v]);
+  }
 }
 
 // Sum K values per lane over the wavefront (K a power of two, K <= 64).
@@ -594,6 +602,8 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
         for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
 #pragma unroll
       for (int u = 0; u < V; ++u) self[u] = x[kSelf][u];
+      if constexpr (sizeof(T) == 8)
+        if (d.kz) nl_add<V>(d, row, ch * V, q);  // + Z (Z^T p)
       stv<T, V>(vs.Q + ((size_t)ch * n + row) * V, q);
     }
     double pq[V];
@@ -814,10 +824,10 @@ redirect_cm_kernel(const Desc* __restrict__ D, int nprob) {
 // Nonlocal pseudopotential term (Sec. 2): V_nl u = sum_j (u, zeta_j) zeta_j
 // has the Galerkin matrix Z Z^T with Z = M zeta (n x k), so the operator of
 // the source problems and of the projection becomes A + Z Z^T.  It is
-// applied as a low-rank correction around the stencil kernels: Y = Z^T X
-// (per-tile partials over kCmRows rows, then one wavefront per (projector,
-// column) in a fixed order), then Q += Z Y.  In the CG the correction's
-// share of p.q is ||Z^T p||^2, added by the alpha finaliser.
+// applied as a low-rank correction inside the stencil kernels: Y = Z^T X
+// first (per-(tile, chunk) partials, then one wavefront per (projector,
+// column) in a fixed order), then the kernel that forms A X adds Z Y row
+// by row (the CG SpMM, so p.q includes the term; the start residual; HW).
 // ------------------------------------------------------------------------
 
 // Z[row][j] = sum_s M[row][row + off_s] zeta[row + off_s][j].
@@ -853,52 +863,70 @@ nl_mass_kernel(Desc d, const double* __restrict__ zeta,
 // orbitals U0 or the basis X (row-major).
 enum { kZtP = 0, kZtU0 = 1, kZtX = 2 };
 
-__device__ __forceinline__ double zt_src(const Desc& d, int src, long long row,
-                                         int c) {
-  if (src == kZtP) return d.P[cm_index(d.n, row, c, d.v64)];
+// Partials of Y = Z^T X for unit (tile t of kCmRows rows, FP64 chunk ch):
+// a thread accumulates its rows' products for KP (>= k, a power of two)
+// projectors and the chunk's V columns, then one wavefront reduction and
+// a fixed-order sum over the four wavefronts; partial slot
+// zpart[(j ncols + c) ntc + t].
+template <int KP, int V>
+__device__ __forceinline__ void zt_unit(const Desc& d, int src, long long t,
+                                        int ch, double* __restrict__ ws) {
+  constexpr int K = KP * V;
+  const int k = d.kz, nc = d.ncols;
+  double acc[K];
+#pragma unroll
+  for (int e = 0; e < K; ++e) acc[e] = 0.0;
   const double* X = src == kZtU0 ? d.U0 : d.X;
-  return X[(size_t)row * d.ncols + c];
+#pragma unroll
+  for (int rr = 0; rr < kCmRpt; ++rr) {
+    const long long row = t * kCmRows + threadIdx.x + rr * kBlock;
+    if (row >= d.n) break;
+    double x[V];
+    if (src == kZtP)
+      ldv<double, V>(d.P + ((size_t)ch * d.n + row) * V, x);
+    else
+      ldv<double, V>(X + (size_t)row * nc + ch * V, x);
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const double z = j < k ? ldg(d.Zp + (size_t)row * k + j) : 0.0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[j * V + v] = fma(z, x[v], acc[j * V + v]);
+    }
+  }
+  constexpr int kGroup = 64 / K;
+  const double tot = wave_reduce_scatter<K>(acc);
+  const int lane = threadIdx.x & 63;
+  if ((lane & (kGroup - 1)) == 0) ws[(threadIdx.x >> 6) * K + lane / kGroup] = tot;
+  __syncthreads();
+  const int e = threadIdx.x;
+  if (e < K && e / V < k) {
+    const double sum = ((ws[e] + ws[K + e]) + ws[2 * K + e]) + ws[3 * K + e];
+    const int j = e / V, c = ch * V + e % V;
+    stg(d.zpart + ((size_t)j * nc + c) * d.ntc + t, sum);
+  }
+  __syncthreads();
 }
 
-// Partials of Y = Z^T X over the tiles of kCmRows rows: staged 64 rows at
-// a time in LDS, one (projector, column) pair per thread.
+// par: the CG parity (source P: chunks without an active column and
+// launches queued after convergence are skipped; their Y is not read).
+template <int KP>
 __global__ void __launch_bounds__(kBlock)
-zt_partial_kernel(const Desc* __restrict__ D, int nprob, int src) {
-  __shared__ double zs[64][kNtMax + 1], xs[64][kNtMax + 1];
+zt_partial_kernel(const Desc* __restrict__ D, int nprob, int src, int par) {
+  __shared__ double ws[4 * 64];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
   if (d.kz == 0) return;
+  if (src == kZtP && ldg(&d.cs->n_active[par]) == 0) return;
   const int lb = blockIdx.x - d.b0;
-  const int k = d.kz, nc = d.ncols, npair = k * nc;
-  for (TileWalk w = tile_walk(d.ntc, lb, d.nb); w.t < w.end; w.t += w.step) {
-    const long long r0 = w.t * kCmRows;
-    const int rows = (int)min((long long)kCmRows, d.n - r0);
-    double acc[(kNtMax * kNtMax + kBlock - 1) / kBlock];
-    constexpr int kMaxPer = (kNtMax * kNtMax + kBlock - 1) / kBlock;
-#pragma unroll
-    for (int a = 0; a < kMaxPer; ++a) acc[a] = 0.0;
-    for (int s0 = 0; s0 < rows; s0 += 64) {
-      const int sr = min(64, rows - s0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < sr * k; e += kBlock)
-        zs[e / k][e % k] = ldg(d.Zp + (size_t)(r0 + s0 + e / k) * k + e % k);
-      for (int e = threadIdx.x; e < sr * nc; e += kBlock)
-        xs[e / nc][e % nc] = zt_src(d, src, r0 + s0 + e / nc, e % nc);
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < kMaxPer; ++a) {
-        const int q = threadIdx.x + a * kBlock;
-        if (q >= npair) break;
-        const int j = q / nc, c = q % nc;
-        double v = acc[a];
-        for (int r = 0; r < sr; ++r) v = fma(zs[r][j], xs[r][c], v);
-        acc[a] = v;
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < kMaxPer; ++a) {
-      const int q = threadIdx.x + a * kBlock;
-      if (q < npair) stg(d.zpart + (size_t)q * d.ntc + w.t, acc[a]);
-    }
+  const int V = d.v64, cpr = d.ncols / V;
+  for (TileWalk w = tile_walk((long long)d.ntc * cpr, lb, d.nb); w.t < w.end;
+       w.t += w.step) {
+    const CmUnit un = cm_unit(w.t, cpr);
+    if (src == kZtP && !chunk_active(d.cs->act[par], un.ch, V, d.ncols))
+      continue;
+    if (V == 2)
+      zt_unit<KP, 2>(d, src, un.t, un.ch, ws);
+    else
+      zt_unit<KP, 1>(d, src, un.t, un.ch, ws);
   }
 }
 
@@ -913,52 +941,6 @@ zt_final_kernel(const Desc* __restrict__ D) {
   if ((threadIdx.x & (kFinal - 1)) == 0) d.zy[q] = tot[0];
 }
 
-// FP64 CG: Q += Z Y on the active chunks (after the stencil SpMM).
-__global__ void __launch_bounds__(kBlock)
-lowrank_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
-  if (d.kz == 0 || ldg(&d.cs->n_active[par]) == 0) return;
-  const int lb = blockIdx.x - d.b0;
-  const int V = d.v64, cpr = d.ncols / V, k = d.kz;
-  for (TileWalk w = tile_walk((long long)d.ntc * cpr, lb, d.nb); w.t < w.end;
-       w.t += w.step) {
-    const CmUnit un = cm_unit(w.t, cpr);
-    if (!chunk_active(d.cs->act[par], un.ch, V, d.ncols)) continue;
-    for (int rr = 0; rr < kCmRpt; ++rr) {
-      const long long row = un.t * kCmRows + threadIdx.x + rr * kBlock;
-      if (row >= d.n) break;
-      for (int u = 0; u < V; ++u) {
-        const int c = un.ch * V + u;
-        double acc = 0.0;
-        for (int j = 0; j < k; ++j)
-          acc = fma(ldg(d.Zp + (size_t)row * k + j), ldg(d.zy + j * d.ncols + c),
-                    acc);
-        double* q = d.Q + cm_index(d.n, row, c, V);
-        *q += acc;
-      }
-    }
-  }
-}
-
-// Rayleigh-Ritz: HW (row-major, in R) += Z Y.
-__global__ void __launch_bounds__(kBlock)
-lowrank_rm_kernel(const Desc* __restrict__ D, int nprob) {
-  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
-  if (d.kz == 0) return;
-  const int lb = blockIdx.x - d.b0;
-  const long long total = d.n * d.ncols;
-  const int k = d.kz;
-  for (long long e = (long long)lb * kBlock + threadIdx.x; e < total;
-       e += (long long)d.nb * kBlock) {
-    const long long row = e / d.ncols;
-    const int c = (int)(e - row * d.ncols);
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j)
-      acc = fma(ldg(d.Zp + (size_t)row * k + j), ldg(d.zy + j * d.ncols + c),
-                acc);
-    d.R[e] += acc;
-  }
-}
 
 // ------------------------------------------------------------------------
 // Persistent CG: every iteration of every problem of the table in one
@@ -1106,13 +1088,7 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
     stencil_product<double, double, V, true, 8, true>(
         wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
         g.ch * V, au, mu, u);
-    for (int j = 0; j < d.kz; ++j) {  // nonlocal term: A u += Z (Z^T u)
-      const double z = ldg(d.Zp + (size_t)row * d.kz + j);
-#pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (g.ch * V + v < ncols)
-          au[v] = fma(z, ldg(d.zy + j * ncols + g.ch * V + v), au[v]);
-    }
+    if (d.kz) nl_add<V>(d, row, g.ch * V, au);  // A u += Z (Z^T u)
     const size_t o = (size_t)row * ncols + g.ch * V;
     double b[V], r[V], p[V];
     if (d.Bin) {
@@ -1404,7 +1380,7 @@ gather_reports_kernel(const Desc* __restrict__ D, int nprob,
 // X -> R = H X (s1 = sigma), Q = M X.  Component form: Y1, Y2, s1 of the
 // descriptor (either output may be null).
 // ------------------------------------------------------------------------
-template <int V>
+template <int V, bool NL>
 __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
     double* __restrict__ red) {
   const Geo g = geo_of<V>(d, vb);
@@ -1451,18 +1427,21 @@ __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = fma(s1, mx[v], ax[v]);
+      if (NL && rr && d.kz) nl_add<V>(d, row, g.ch * V, y);  // + Z Z^T W
       stv<double, V>(Y1 + o, y);
     }
     if (Y2) stv<double, V>(Y2 + o, mx);
   }
 }
 
-template <int VFIX>
+// NL: some problem of the table has a nonlocal term.
+template <int VFIX, bool NL>
 __global__ void PARO_STREAM_BOUNDS
 spmm_dual_kernel(const Desc* __restrict__ D, int nprob, int rr) {
   __shared__ double red[1 * kBlock * (VFIX ? VFIX : 2)];
-  PARO_VB_LOOP64(D, nprob, VFIX, (spmm_dual_body<VV>(d, vb, rr, red)))
+  PARO_VB_LOOP64(D, nprob, VFIX, (spmm_dual_body<VV, NL>(d, vb, rr, red)))
 }
+
 
 // ------------------------------------------------------------------------
 // Gram contractions G1 = W^T Y1, G2 = W^T Y2 on FP64 matrix cores
@@ -2077,18 +2056,38 @@ static void klaunch(Timing* t, int stage, F kernel, dim3 grid, dim3 block,
       klaunch(T, ST, KERNEL<0>, __VA_ARGS__);                          \
   }
 
+template <int W>
+static void spmm_dual_w(Launch& L, bool rr, hipStream_t s, Timing* t) {
+  const size_t smem = weights_bytes(L.tr64, sizeof(double), 2);
+  if (L.maxkz)
+    klaunch(t, PARO_ST_RR_SPMM, spmm_dual_kernel<W, true>, dim3(L.blocks),
+            dim3(kBlock), smem, s, (const Desc*)L.d, L.nprob, rr ? 1 : 0);
+  else
+    klaunch(t, PARO_ST_RR_SPMM, spmm_dual_kernel<W, false>, dim3(L.blocks),
+            dim3(kBlock), smem, s, (const Desc*)L.d, L.nprob, rr ? 1 : 0);
+}
+
 hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t) {
-  PARO_LAUNCH_W64(L.v64u, t, PARO_ST_RR_SPMM, spmm_dual_kernel,
-                  dim3(L.blocks), dim3(kBlock),
-                  weights_bytes(L.tr64, sizeof(double), 2), s, L.d, L.nprob,
-                  rr ? 1 : 0);
+  switch (L.v64u) {
+    case 2: spmm_dual_w<2>(L, rr, s, t); break;
+    case 1: spmm_dual_w<1>(L, rr, s, t); break;
+    default: spmm_dual_w<0>(L, rr, s, t);
+  }
   return hipGetLastError();
 }
 
 // Y = Z^T (source) for every problem with a nonlocal term.
-static void zt_launch(Launch& L, int src, hipStream_t s, Timing* t, int st) {
-  klaunch(t, st, zt_partial_kernel, dim3(L.blocks), dim3(kBlock), 0, s,
-          (const Desc*)L.d, L.nprob, src);
+static void zt_launch(Launch& L, int src, hipStream_t s, Timing* t, int st,
+                      int par = 0) {
+  const Desc* D = L.d;
+  const dim3 g(L.blocks), b(kBlock);
+  const int n = L.nprob;
+  if (L.maxkz <= 1) klaunch(t, st, zt_partial_kernel<1>, g, b, 0, s, D, n, src, par);
+  else if (L.maxkz <= 2) klaunch(t, st, zt_partial_kernel<2>, g, b, 0, s, D, n, src, par);
+  else if (L.maxkz <= 4) klaunch(t, st, zt_partial_kernel<4>, g, b, 0, s, D, n, src, par);
+  else if (L.maxkz <= 8) klaunch(t, st, zt_partial_kernel<8>, g, b, 0, s, D, n, src, par);
+  else if (L.maxkz <= 16) klaunch(t, st, zt_partial_kernel<16>, g, b, 0, s, D, n, src, par);
+  else klaunch(t, st, zt_partial_kernel<32>, g, b, 0, s, D, n, src, par);
   klaunch(t, st, zt_final_kernel, dim3(L.maxkz * L.maxcols, L.nprob),
           dim3(kFinal), 0, s, (const Desc*)L.d);
 }
@@ -2118,13 +2117,9 @@ template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
   const Desc* D = L.d;
   if constexpr (sizeof(T) == 8)
-    if (L.maxkz) zt_launch(L, kZtP, s, t, PARO_ST_CG_SPMM);
+    if (L.maxkz) zt_launch(L, kZtP, s, t, PARO_ST_CG_SPMM, par);
   klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
-  if constexpr (sizeof(T) == 8)
-    if (L.maxkz)
-      klaunch(t, PARO_ST_CG_SPMM, lowrank_cm_kernel, dim3(L.blocks),
-              dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
           dim3(kFinal), 0, s, D, par);
   klaunch(t, PARO_ST_CG_RUPD, rupd_cm_kernel<T, W>, dim3(L.blocks),
@@ -2348,12 +2343,8 @@ hipError_t launch_small_geneig(const double* A, const double* B, int n,
 
 hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   hipError_t e;
+  if (L.maxkz) zt_launch(L, kZtX, s, t, PARO_ST_RR_SPMM);  // Z^T W
   if ((e = launch_spmm(L, true, s, t)) != hipSuccess) return e;
-  if (L.maxkz) {  // HW += Z (Z^T W)
-    zt_launch(L, kZtX, s, t, PARO_ST_RR_SPMM);
-    klaunch(t, PARO_ST_RR_SPMM, lowrank_rm_kernel, dim3(L.blocks),
-            dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob);
-  }
   if ((e = gram(L, true, s, t)) != hipSuccess) return e;
   klaunch(t, PARO_ST_SMALL, geneig_batch_kernel, dim3(L.nprob), dim3(kBlock),
           0, s, (const Desc*)L.d);
