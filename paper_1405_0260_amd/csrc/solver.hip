@@ -322,9 +322,8 @@ __device__ __forceinline__ Geo geo_of(const Desc& d, int vb) {
 
 // The virtual blocks of the real block that runs this code: its problem
 // `d` (owner of blockIdx.x) and the segments vb = lb, lb + nb, ... < ns.
-// BODY runs once per segment with VV (constexpr) the problem's vector
-// width; a barrier separates consecutive segments.  Widths 2 / 1 (FP64)
-// or 4 / 2 / 1 (FP32).
+// BODY runs once per segment with VV (constexpr) the problem's FP64
+// vector width (2 or 1); a barrier separates consecutive segments.
 #define PARO_VB_CASE(W, BODY) \
   {                           \
     constexpr int VV = W;     \
@@ -346,14 +345,10 @@ __device__ __forceinline__ Geo geo_of(const Desc& d, int vb) {
   PARO_VB_LOOP_(D, nprob, d.v64,                                       \
                 if constexpr (VFIX != 0) PARO_VB_CASE(VFIX, BODY) else if \
                     (vw_ == 2) PARO_VB_CASE(2, BODY) else PARO_VB_CASE(1, BODY))
-#define PARO_VB_LOOP32(D, nprob, VFIX, BODY)                                 \
-  PARO_VB_LOOP_(D, nprob, d.v32,                                             \
-                if constexpr (VFIX != 0) PARO_VB_CASE(VFIX, BODY) else if      \
-                    (vw_ == 4) PARO_VB_CASE(4, BODY) else if (vw_ == 2)        \
-                        PARO_VB_CASE(2, BODY) else PARO_VB_CASE(1, BODY))
 
-// alpha_c = (r.z)_c / (p.q)_c for the active columns (grid: column x
-// problem).  Also clears the next parity's active count for cg_beta.
+// alpha_c = (r.z)_c / (p.q)_c for one column of a problem (one
+// wavefront; the persistent CG's alpha phase).  Also clears the next
+// parity's active count for the beta phase.
 __device__ __forceinline__ void alpha_pair(const Desc& d, int c, int par) {
   const int lane = threadIdx.x & (kFinal - 1);
   ColState* cs = d.cs;
@@ -382,10 +377,6 @@ __device__ __forceinline__ void alpha_pair(const Desc& d, int c, int par) {
   }
 }
 
-__global__ void __launch_bounds__(kFinal)
-cg_alpha_kernel(const Desc* __restrict__ D, int par) {
-  alpha_pair(D[blockIdx.y], blockIdx.x, par);
-}
 
 // beta_c, iteration count and the stopping test of every active column
 // (grid: column x problem); counts the columns active next iteration.
@@ -774,6 +765,63 @@ __global__ void PARO_STREAM_BOUNDS
 rupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double ws[4 * 8];
   PARO_CM_LOOP(T, D, nprob, par, VFIX, (rupd_cm_chunk<T, VV>(d, un, par, ws)))
+}
+
+// The r-update with alpha computed in place (the alpha finaliser folded
+// into the kernel): wavefront w < V of a unit forms alpha of column
+// ch V + w from the p.q partials in the finaliser's order (same bits), the
+// unit of tile 0 stores it for the p-update and sets the status bits, and
+// block 0 does the finaliser's per-iteration bookkeeping.
+template <typename T, int V>
+__device__ __forceinline__ void rupd_alpha_chunk(const Desc& d, CmUnit un,
+                                                 int par, double* ws,
+                                                 double* al_s) {
+  ColState* cs = d.cs;
+  const int* act = cs->act[par];
+  if (!chunk_active(act, un.ch, V, d.ncols)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < V) {
+    const int c = un.ch * V + wave;
+    double a = 0.0;
+    if (ldg(act + c)) {
+      double tot[1];
+      column_sums<1>(d.pqp, 0, c, d.pqn, tot);
+      const double pq = tot[0];
+      const bool bad = !(pq > 0.0) || !isfinite(pq);
+      a = bad ? 0.0 : cs->rz[c] / pq;
+      if (lane == 0 && un.t == 0) {
+        if (bad)
+          atomicOr(&cs->status,
+                   isfinite(pq) ? (int)kStNotSpd : (int)kStNonFinite);
+        cs->alpha[c] = a;
+      }
+    }
+    if (lane == 0) al_s[wave] = a;
+  }
+  __syncthreads();
+  T al[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) al[u] = (T)al_s[u];
+  rupd_cm_unit<T, V>(d, un.t, un.ch, al, ws);  // ends with a barrier
+}
+
+template <typename T, int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+rupd_alpha_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * 8];
+  __shared__ double al_s[4];
+  {
+    const Desc& d0 = D[owner(D, nprob, blockIdx.x, false)];
+    if (blockIdx.x == d0.b0 && threadIdx.x == 0) {
+      // As the finaliser: the next parity starts idle; one more iteration
+      // when this one runs.
+      ColState* cs = d0.cs;
+      if (ldg(&cs->n_active[par]) != 0) cs->cg_iters += 1;
+      cs->n_active[par ^ 1] = 0;
+    }
+  }
+  PARO_CM_LOOP(T, D, nprob, par, VFIX,
+               (rupd_alpha_chunk<T, VV>(d, un, par, ws, al_s)))
 }
 
 template <typename T, int VFIX>
@@ -2120,9 +2168,7 @@ static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
     if (L.maxkz) zt_launch(L, kZtP, s, t, PARO_ST_CG_SPMM, par);
   klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
-  klaunch(t, PARO_ST_CG_FINAL, cg_alpha_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kFinal), 0, s, D, par);
-  klaunch(t, PARO_ST_CG_RUPD, rupd_cm_kernel<T, W>, dim3(L.blocks),
+  klaunch(t, PARO_ST_CG_RUPD, rupd_alpha_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_FINAL, cg_beta_kernel, dim3(L.maxcols, L.nprob),
           dim3(kFinal), 0, s, D, par);
