@@ -251,8 +251,8 @@ def main():
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
         kernel_names = {"cg_spmm": "spmm_cm_kernel",
-                        "cg_rupd": "rupd_cm_kernel",
-                        "cg_pupd": "pupd_cm_kernel"}
+                        "cg_rupd": "rupd_alpha_kernel",
+                        "cg_pupd": "pupd_beta_kernel"}
         traffic = (measured_traffic(kernel_names[dom]) if prec == "mixed"
                    else None)
         all_ms = sum(v["ms"] for v in td["stages"].values())

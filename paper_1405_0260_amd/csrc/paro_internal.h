@@ -44,15 +44,17 @@ enum : int {
 // problem owns one ColState; all reductions end in it.
 struct ColState {
   double bb[kNtMax];      // ||b||^2 of the current (outer) system
-  double rz[kNtMax];      // r . z of the current iterate
+  double rz[kNtMax];      // r . z of the current iterate (the latest)
   double alpha[kNtMax];
   double beta[kNtMax];
   double rr[kNtMax];      // ||r||^2 of the current iterate
   double tol2[kNtMax];    // stop when rr <= tol2 (inner/outer threshold)
   double rr64[kNtMax];    // FP64 residual^2 of the outer (refinement) loop
+  double rzp[2][kNtMax];  // r . z entering the CG iteration of parity s
+  int itp[2][kNtMax];     // iterations taken before that iteration
   int act[2][kNtMax];     // CG column active in iteration of parity s
   int oact[kNtMax];       // outer refinement still running for this column
-  int iters[kNtMax];      // CG iterations taken in this step
+  int iters[kNtMax];      // CG iterations taken in this step (latest)
   int n_active[2];        // number of active columns, per parity
   int n_outer;            // columns still refining
   int status;             // kSt* bits

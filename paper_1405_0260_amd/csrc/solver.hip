@@ -372,14 +372,55 @@ __device__ __forceinline__ void alpha_pair(const Desc& d, int c, int par) {
       atomicOr(&cs->status, isfinite(pq) ? (int)kStNotSpd : (int)kStNonFinite);
       cs->alpha[c] = 0.0;
     } else {
-      cs->alpha[c] = cs->rz[c] / pq;
+      cs->alpha[c] = cs->rzp[par][c] / pq;
     }
   }
 }
 
 
+// The end of a CG iteration for one active column from its new r.z and
+// r.r: beta, the iteration count and whether the column goes on.  Reads
+// only state of parity `par`, so every unit of a kernel may evaluate it
+// while one of them commits (beta_commit writes parity par ^ 1 and the
+// latest copies).
+struct BetaStep {
+  double beta;
+  int it, next, bad;
+};
+__device__ __forceinline__ BetaStep beta_step(const ColState* cs, int c,
+                                              int par, double rz, double rr) {
+  BetaStep b;
+  b.bad = !isfinite(rz) || !isfinite(rr);
+  b.beta = b.bad ? 0.0 : rz / cs->rzp[par][c];
+  b.it = cs->itp[par][c] + 1;
+  const bool more = rr > cs->tol2[c];
+  b.next = (!b.bad && more && b.it < cs->maxit &&
+            !(ldg(&cs->status) & kStNotSpd)) ? 1 : 0;
+  return b;
+}
+__device__ __forceinline__ void beta_commit(ColState* cs, int c, int par,
+                                            const BetaStep& b, double rz,
+                                            double rr) {
+  if (b.bad) {
+    atomicOr(&cs->status, (int)kStNonFinite);
+  } else {
+    cs->beta[c] = b.beta;
+    cs->rz[c] = rz;
+    cs->rzp[par ^ 1][c] = rz;
+    cs->rr[c] = rr;
+    cs->iters[c] = b.it;
+    cs->itp[par ^ 1][c] = b.it;
+    if (rr > cs->tol2[c] && b.it >= cs->maxit)
+      atomicOr(&cs->status, (int)kStNoConv);
+  }
+  cs->act[par ^ 1][c] = b.next;
+  if (b.next) atomicAdd(&cs->n_active[par ^ 1], 1);
+  atomicAdd(&cs->cg_col_iters, 1ULL);
+}
+
 // beta_c, iteration count and the stopping test of every active column
-// (grid: column x problem); counts the columns active next iteration.
+// (one wavefront; the persistent CG's beta phase); counts the columns
+// active next iteration.
 __device__ __forceinline__ void beta_pair(const Desc& d, int c, int par) {
   const int lane = threadIdx.x & (kFinal - 1);
   ColState* cs = d.cs;
@@ -391,29 +432,10 @@ __device__ __forceinline__ void beta_pair(const Desc& d, int c, int par) {
   double tot[2];
   column_sums<2>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
   if (lane != 0) return;
-  int next = 0;
-  const double rz = tot[0], rr = tot[1];
-  if (!isfinite(rz) || !isfinite(rr)) {
-    atomicOr(&cs->status, (int)kStNonFinite);
-  } else {
-    cs->beta[c] = rz / cs->rz[c];
-    cs->rz[c] = rz;
-    cs->rr[c] = rr;
-    const int it = cs->iters[c] + 1;
-    cs->iters[c] = it;
-    const bool more = rr > cs->tol2[c];
-    if (more && it >= cs->maxit) atomicOr(&cs->status, (int)kStNoConv);
-    next = (more && it < cs->maxit && !(cs->status & kStNotSpd)) ? 1 : 0;
-  }
-  cs->act[par ^ 1][c] = next;
-  if (next) atomicAdd(&cs->n_active[par ^ 1], 1);
-  atomicAdd(&cs->cg_col_iters, 1ULL);
+  const BetaStep b = beta_step(cs, c, par, tot[0], tot[1]);
+  beta_commit(cs, c, par, b, tot[0], tot[1]);
 }
 
-__global__ void __launch_bounds__(kFinal)
-cg_beta_kernel(const Desc* __restrict__ D, int par) {
-  beta_pair(D[blockIdx.y], blockIdx.x, par);
-}
 
 // ------------------------------------------------------------------------
 // The CG of the source solves, in chunk-major layout.
@@ -760,12 +782,6 @@ spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   }
 }
 
-template <typename T, int VFIX>
-__global__ void PARO_STREAM_BOUNDS
-rupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double ws[4 * 8];
-  PARO_CM_LOOP(T, D, nprob, par, VFIX, (rupd_cm_chunk<T, VV>(d, un, par, ws)))
-}
 
 // The r-update with alpha computed in place (the alpha finaliser folded
 // into the kernel): wavefront w < V of a unit forms alpha of column
@@ -788,7 +804,7 @@ __device__ __forceinline__ void rupd_alpha_chunk(const Desc& d, CmUnit un,
       column_sums<1>(d.pqp, 0, c, d.pqn, tot);
       const double pq = tot[0];
       const bool bad = !(pq > 0.0) || !isfinite(pq);
-      a = bad ? 0.0 : cs->rz[c] / pq;
+      a = bad ? 0.0 : cs->rzp[par][c] / pq;
       if (lane == 0 && un.t == 0) {
         if (bad)
           atomicOr(&cs->status,
@@ -824,10 +840,61 @@ rupd_alpha_kernel(const Desc* __restrict__ D, int nprob, int par) {
                (rupd_alpha_chunk<T, VV>(d, un, par, ws, al_s)))
 }
 
+
+// The p-update with beta computed in place (the beta finaliser folded
+// into the kernel): wavefront w < V of a unit forms r.z and r.r of column
+// ch V + w from the r-update's partials in the finaliser's order, every
+// unit evaluates beta_step from the parity-par state (same bits), and the
+// unit of tile 0 commits it.  Block 0 marks the inactive columns idle in
+// the next parity.
+template <typename T, int V>
+__device__ __forceinline__ void pupd_beta_chunk(const Desc& d, CmUnit un,
+                                                int par, double* b_s) {
+  ColState* cs = d.cs;
+  T al[V];
+  if (!cm_alpha<T, V>(cs, par, un.ch, al)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < V) {
+    const int c = un.ch * V + wave;
+    double beta = 0.0;
+    int next = 0;
+    if (ldg(&cs->act[par][c])) {
+      double tot[2];
+      column_sums<2>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
+      const BetaStep b = beta_step(cs, c, par, tot[0], tot[1]);
+      beta = b.beta;
+      next = b.next;
+      if (lane == 0 && un.t == 0) beta_commit(cs, c, par, b, tot[0], tot[1]);
+    }
+    if (lane == 0) {
+      b_s[wave] = beta;
+      b_s[4 + wave] = next ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  T be[V];
+  bool nx[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    nx[u] = b_s[4 + u] != 0.0;
+    be[u] = nx[u] ? (T)b_s[u] : T(0);
+  }
+  pupd_cm_unit<T, V>(d, un.t, un.ch, al, be, nx);
+  __syncthreads();  // b_s is rewritten by the next unit
+}
+
 template <typename T, int VFIX>
 __global__ void PARO_STREAM_BOUNDS
-pupd_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  PARO_CM_LOOP(T, D, nprob, par, VFIX, (pupd_cm_chunk<T, VV>(d, un, par)))
+pupd_beta_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double b_s[8];
+  {
+    const Desc& d0 = D[owner(D, nprob, blockIdx.x, false)];
+    if (blockIdx.x == d0.b0 && ldg(&d0.cs->n_active[par]) != 0)
+      for (int c = threadIdx.x; c < d0.ncols; c += kBlock)
+        if (!ldg(&d0.cs->act[par][c])) d0.cs->act[par ^ 1][c] = 0;
+  }
+  PARO_CM_LOOP(T, D, nprob, par, VFIX,
+               (pupd_beta_chunk<T, VV>(d, un, par, b_s)))
 }
 
 // Continuing FP32 pass after residual replacement: p = D^-1 r + beta p on
@@ -1188,10 +1255,12 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
   const double rtol = d.rtol;
   cs->bb[c] = bb;
   cs->rz[c] = rz;
+  cs->rzp[0][c] = rz;
   cs->rr[c] = rr;
   cs->rr64[c] = rr;
   cs->tol2[c] = rtol * rtol * bb;
   cs->iters[c] = 0;
+  cs->itp[0][c] = 0;
   int a = 0;
   if (!isfinite(bb) || !isfinite(rr)) {
     atomicOr(&cs->status, (int)kStNonFinite);
@@ -1316,6 +1385,8 @@ refine_final_kernel(const Desc* __restrict__ D, int restart) {
     // residual: beta = (r.z)_new / (r.z) of the step before.
     if (!restart && a) cs->beta[c] = cs->beta[c] * (tot[1] / cs->rz[c]);
     cs->rz[c] = tot[1];
+    cs->rzp[0][c] = tot[1];  // the next pass starts at parity 0
+    cs->itp[0][c] = cs->iters[c];
   }
   cs->oact[c] = a;
   cs->act[0][c] = a;
@@ -2170,9 +2241,7 @@ static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
           dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_RUPD, rupd_alpha_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
-  klaunch(t, PARO_ST_CG_FINAL, cg_beta_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kFinal), 0, s, D, par);
-  klaunch(t, PARO_ST_CG_PUPD, pupd_cm_kernel<T, W>, dim3(L.blocks),
+  klaunch(t, PARO_ST_CG_PUPD, pupd_beta_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
 }
 
