@@ -191,7 +191,6 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.part = (double*)at(L.part);
   p.cpart = (double*)at(L.cpart);
   p.gpart = (double*)at(L.gpart);
-  p.gsum = (double*)at(L.gsum);
   p.Ah = (double*)at(L.Ah);
   p.Bh = (double*)at(L.Bh);
   p.C = (double*)at(L.C);
@@ -270,7 +269,6 @@ void desc_init(Problem& p) {
   d.pqn = (int)((p.n + kBlock - 1) / kBlock);
   d.part = p.part;
   d.gpart = p.gpart;
-  d.gsum = p.gsum;
   d.Ah = p.Ah;
   d.Bh = p.Bh;
   d.C = p.C;
@@ -847,7 +845,6 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.cpart = take(sizeof(double) * (size_t)Nt *
                  (2 * cm_tiles(n) + (n + kBlock - 1) / kBlock));
   L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
-  L.gsum = take(sizeof(double) * (size_t)kGramY * gram_tiles(Nt));
   L.Ah = take(sizeof(double) * kNtMax * kNtMax);
   L.Bh = take(sizeof(double) * kNtMax * kNtMax);
   L.C = take(sizeof(double) * kNtMax * kNtMax);

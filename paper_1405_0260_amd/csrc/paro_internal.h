@@ -25,7 +25,6 @@ constexpr int kGramGrid = 512;       // first-stage blocks of the Gram
 // at most its own single-problem grid).
 constexpr int kBatchGrid = 4 * PARO_GRID;
 constexpr int kBatchGramGrid = 4 * kGramGrid;
-constexpr int kGramY = 16;           // second-stage split of those blocks
 // Tile entries per Gram block for nt16 = ceil(ncols / 16): two symmetric
 // results, tile pairs I <= J, 16 x 16 each.
 constexpr int gram_tiles(int ncols) {
@@ -142,7 +141,6 @@ struct Desc {
   double* Y2;
   double* part;
   double* gpart;
-  double* gsum;
   double* Ah;
   double* Bh;
   double* C;
@@ -246,7 +244,6 @@ struct Problem {
   double* cpart;          // FP32 CG partials: 2 Nt cm_tiles(n) (r.z, r.r),
                           // then Nt ceil(n / kBlock) (p.q)
   double* gpart;          // Gram partials: kGramGrid * gram_tiles(Nt)
-  double* gsum;           // kGramY * gram_tiles(Nt)
   double* Ah;             // Nt x Nt
   double* Bh;
   double* C;              // Ritz coefficients, Nt x Nt
@@ -275,7 +272,7 @@ struct Layout {
   size_t rowptr, col, valA, valM, valA32, dinv, dinv32, diagA, diagM,
       diagA32;
   size_t X, R, P, Q, B, Xc, R32, P32, Q32, X32;
-  size_t part, cpart, gpart, gsum, Ah, Bh, C, theta, vmin, cs, si, cnt,
+  size_t part, cpart, gpart, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
   size_t desc, clus;
   size_t total;

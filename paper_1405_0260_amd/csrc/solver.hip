@@ -1679,53 +1679,52 @@ __device__ __forceinline__ int gram_per_blk(int ncols, bool sym) {
   return (sym ? 2 : 1) * gram_ntiles((ncols + 15) / 16, sym) * 256;
 }
 
-// Second stage: entry e of problem z's tiles is the fixed-order sum over
-// its gns first-stage segments, split into kGramY chunks (grid: entries x
-// chunk x problem).
-__global__ void __launch_bounds__(kBlock)
-gram_reduce_kernel(const Desc* __restrict__ D, int sym) {
-  const Desc& d = D[blockIdx.z];
-  const int per_blk = gram_per_blk(d.ncols, sym != 0);
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= per_blk) return;
-  const int nb = d.gns;
-  const int y = blockIdx.y, chunk = (nb + kGramY - 1) / kGramY;
-  const int b0 = y * chunk, b1 = min(nb, b0 + chunk);
-  double s = 0.0;
-  for (int b = b0; b < b1; ++b) s += ldg(d.gpart + (size_t)b * per_blk + e);
-  stg(d.gsum + (size_t)y * per_blk + e, s);
+// Second stage, one wavefront per result entry (grid: entries / 4 x
+// problem): the entry's first-stage partials over the problem's gns
+// segments are summed in a fixed order (lane l adds segments l, l + 64,
+// ..., then a butterfly) and written to Ah = W^T H W, Bh = W^T M W
+// (sym: entries i <= j, mirrored, diagonal tiles symmetrised) or to
+// Y2 = W^T Y1 (component form).
+__device__ __forceinline__ double gram_entry_sum(const Desc& d, int per_blk,
+                                                 int e) {
+  const int lane = threadIdx.x & 63;
+  double v = 0.0;
+  for (int b = lane; b < d.gns; b += 64)
+    v += ldg(d.gpart + (size_t)b * per_blk + e);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
-// Scatter of the summed tiles into the ncols x ncols results (one block
-// per problem): Ah = W^T H W, Bh = W^T M W symmetrised (sym), or Y2 =
-// W^T Y1 (component form).
 __global__ void __launch_bounds__(kBlock)
-gram_scatter_kernel(const Desc* __restrict__ D, int sym) {
-  const Desc& d = D[blockIdx.x];
+gram_final_kernel(const Desc* __restrict__ D, int sym) {
+  const Desc& d = D[blockIdx.y];
   const int ncols = d.ncols;
+  const int o = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (o >= ncols * ncols) return;
+  const int i = o / ncols, j = o % ncols;
   const int nt16 = (ncols + 15) / 16;
   const int per_blk = gram_per_blk(ncols, sym != 0);
-  const int np = gram_ntiles(nt16, sym != 0);
-  auto tile = [&](int idx) {
-    double v = 0.0;
-    for (int y = 0; y < kGramY; ++y) v += d.gsum[(size_t)y * per_blk + idx];
-    return v;
-  };
-  for (int t = threadIdx.x; t < ncols * ncols; t += kBlock) {
-    const int i = t / ncols, j = t % ncols;
-    if (!sym) {
-      d.Y2[t] = tile(((i / 16) * nt16 + j / 16) * 256 + (i % 16) * 16 + j % 16);
-      continue;
-    }
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    const int I = lo / 16, J = hi / 16;
-    const int q = I * nt16 - I * (I - 1) / 2 + (J - I);
-    const int a = (lo % 16) * 16 + hi % 16, b = (hi % 16) * 16 + lo % 16;
-    for (int g = 0; g < 2; ++g) {
+  const bool lead = (threadIdx.x & 63) == 0;
+  if (!sym) {
+    const double v = gram_entry_sum(
+        d, per_blk, ((i / 16) * nt16 + j / 16) * 256 + (i % 16) * 16 + j % 16);
+    if (lead) d.Y2[o] = v;
+    return;
+  }
+  if (i > j) return;
+  const int I = i / 16, J = j / 16;
+  const int q = I * nt16 - I * (I - 1) / 2 + (J - I);
+  const int np = gram_ntiles(nt16, true);
+  const int ea = (i % 16) * 16 + j % 16, eb = (j % 16) * 16 + i % 16;
+  for (int g = 0; g < 2; ++g) {
+    const int base = (g * np + q) * 256;
+    double v = gram_entry_sum(d, per_blk, base + ea);
+    if (I == J) v = 0.5 * (v + gram_entry_sum(d, per_blk, base + eb));
+    if (lead) {
       double* G = g == 0 ? d.Ah : d.Bh;
-      const int base = (g * np + q) * 256;
-      G[t] = (I == J) ? 0.5 * (tile(base + a) + tile(base + b))
-                      : tile(base + a);
+      G[i * ncols + j] = v;
+      G[j * ncols + i] = v;
     }
   }
 }
@@ -2430,17 +2429,13 @@ static void gram_first(Launch& L, hipStream_t s, Timing* t) {
 }
 
 static hipError_t gram(Launch& L, bool sym, hipStream_t s, Timing* t) {
-  const int nt16 = L.nt16;
-  const int per_blk = (sym ? 2 : 1) * gram_ntiles(nt16, sym) * 256;
   if (sym)
     gram_first<true>(L, s, t);
   else
     gram_first<false>(L, s, t);
-  klaunch(t, PARO_ST_GRAM, gram_reduce_kernel,
-          dim3((per_blk + kBlock - 1) / kBlock, kGramY, L.nprob), dim3(kBlock),
-          0, s, (const Desc*)L.d, sym ? 1 : 0);
-  klaunch(t, PARO_ST_GRAM, gram_scatter_kernel, dim3(L.nprob), dim3(kBlock),
-          0, s, (const Desc*)L.d, sym ? 1 : 0);
+  klaunch(t, PARO_ST_GRAM, gram_final_kernel,
+          dim3((L.maxcols * L.maxcols + 3) / 4, L.nprob), dim3(kBlock), 0, s,
+          (const Desc*)L.d, sym ? 1 : 0);
   return hipGetLastError();
 }
 
