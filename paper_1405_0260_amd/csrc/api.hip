@@ -598,8 +598,11 @@ int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
     HIP_OR_FAIL(launch_cm_unpack(c.L, s, c.timing));
     return PARO_OK;
   }
+  // Pass 0's residual, FP32 start state and inner target come from the
+  // start kernel (x0 = u0).
   for (int pass = 0;; ++pass) {
-    HIP_OR_FAIL(launch_refine_residual(c.L, pass == 0, s, c.timing));
+    if (pass > 0)
+      HIP_OR_FAIL(launch_refine_residual(c.L, s, c.timing));
     int pw[2];
     int rc = poll(c, 2, pw, s);
     if (rc) return rc;

@@ -300,11 +300,10 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
                            Timing* t);
 // FP32 inner solves inside FP64 refinement.
-// FP64 residual of the refinement and the next FP32 pass: `restart`
-// starts CG (p = D^-1 r), else the search direction is kept and
+// FP64 residual of the refinement and the next FP32 pass (the first pass
+// starts from launch_pcg_start's state): the search direction is kept and
 // launch_redirect (after the poll) turns it with the replaced residual.
-hipError_t launch_refine_residual(Launch& L, bool restart, hipStream_t s,
-                                  Timing* t);
+hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_redirect(Launch& L, hipStream_t s, Timing* t);
 // Autotuner: the CG SpMM alone (parity 0), and a set-up making every
 // column active.

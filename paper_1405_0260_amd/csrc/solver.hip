@@ -1218,8 +1218,28 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
       r[v] = b[v] - au[v];
       p[v] = di * r[v];
       acc[0][v] += b[v] * b[v];
-      acc[1][v] += r[v] * p[v];
       acc[2][v] += r[v] * r[v];
+    }
+    if (d.R32) {
+      // Mixed precision: this residual is also the first refinement
+      // pass's (x0 = u0), so the FP32 inner CG starts from it directly:
+      // r, p = D^-1 r rounded to FP32, correction 0, r.z of the rounded
+      // values.
+      float r32[V], p32[V], z32[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        r32[v] = (float)r[v];
+        p32[v] = (float)p[v];
+        z32[v] = 0.0f;
+        acc[1][v] += (double)r32[v] * (double)p32[v];
+      }
+      const size_t o32 = cm_index(d.n, row, g.ch * V, d.v32);
+      stv<float, V>(d.R32 + o32, r32);
+      stv<float, V>(d.P32 + o32, p32);
+      stv<float, V>(d.X32 + o32, z32);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[1][v] += r[v] * p[v];
     }
     if (d.X != U) stv<double, V>(d.X + o, u);
     if (d.Xc) {  // FP64 CG: its chunk-major start state
@@ -1258,7 +1278,11 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
   cs->rzp[0][c] = rz;
   cs->rr[c] = rr;
   cs->rr64[c] = rr;
-  cs->tol2[c] = rtol * rtol * bb;
+  // Mixed precision: the first inner FP32 pass's target (as in every
+  // refinement pass); FP64: the solve's own.
+  cs->tol2[c] = d.R32 ? fmax(d.inner_rtol * d.inner_rtol * rr,
+                             0.09 * rtol * rtol * bb)
+                      : rtol * rtol * bb;
   cs->iters[c] = 0;
   cs->itp[0][c] = 0;
   int a = 0;
@@ -1282,13 +1306,14 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
 //   r64 = B - A_s X;  converged columns (||r64|| <= rtol ||b||) retire;
 //   the others solve A d = r64 in FP32 from d = 0, to
 //   ||r|| <= inner_rtol ||r64||.  The first pass of a solve starts CG
-//   (p = D^-1 r); later passes keep the search direction p and only
-//   replace the recursively updated residual by the FP64 one (residual
-//   replacement), so CG continues instead of restarting.
+//   (p = D^-1 r) from the start kernel's residual; the passes here keep
+//   the search direction p and only replace the recursively updated
+//   residual by the FP64 one (residual replacement), so CG continues
+//   instead of restarting.
 // ------------------------------------------------------------------------
 template <int V>
 __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
-    int restart, double* __restrict__ red) {
+    double* __restrict__ red) {
   const Geo g = geo_of<V>(d, vb);
   ColState* cs = d.cs;
   const int ncols = d.ncols;
@@ -1322,21 +1347,19 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
     double b[V];
     ldv<double, V>(d.B + o, b);
     const double di = ldg(d.dinv + row);
-    float r32[V], p32[V], z32[V];
+    float r32[V], z32[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const double r = b[v] - ax[v];
       acc[0][v] += r * r;
       r32[v] = (float)r;
-      p32[v] = (float)(di * r);
       z32[v] = 0.0f;
-      acc[1][v] += (double)r32[v] * (double)p32[v];
+      acc[1][v] += (double)r32[v] * (double)(float)(di * r);
     }
     // FP32 vectors are chunk-major; the V FP64 columns of this thread lie
     // in one FP32 chunk (the FP32 width is a multiple of the FP64 one).
     const size_t o32 = cm_index(d.n, row, g.ch * V, d.v32);
     stv<float, V>(d.R32 + o32, r32);
-    if (restart) stv<float, V>(d.P32 + o32, p32);
     stv<float, V>(d.X32 + o32, z32);
   }
   block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
@@ -1344,16 +1367,16 @@ __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
 
 template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
-refine_residual_kernel(const Desc* __restrict__ D, int nprob, int restart) {
+refine_residual_kernel(const Desc* __restrict__ D, int nprob) {
   __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX,
-                 (refine_residual_body<VV>(d, vb, restart, red)))
+                 (refine_residual_body<VV>(d, vb, red)))
 }
 
 // Outer (refinement) test per column and the inner threshold of the next
 // FP32 solve (grid: column x problem).
 __global__ void __launch_bounds__(kFinal)
-refine_final_kernel(const Desc* __restrict__ D, int restart) {
+refine_final_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= d.ncols) return;
@@ -1381,9 +1404,9 @@ refine_final_kernel(const Desc* __restrict__ D, int restart) {
     // test needs (0.3 rtol ||b||: the margin covers the drift between the
     // FP32 recursive residual and the FP64 one).
     cs->tol2[c] = fmax(irt * irt * rr, 0.09 * rtol * rtol * cs->bb[c]);
-    // A continuing pass takes the last step's beta with the replaced
+    // The continuing pass takes the last step's beta with the replaced
     // residual: beta = (r.z)_new / (r.z) of the step before.
-    if (!restart && a) cs->beta[c] = cs->beta[c] * (tot[1] / cs->rz[c]);
+    if (a) cs->beta[c] = cs->beta[c] * (tot[1] / cs->rz[c]);
     cs->rz[c] = tot[1];
     cs->rzp[0][c] = tot[1];  // the next pass starts at parity 0
     cs->itp[0][c] = cs->iters[c];
@@ -2356,14 +2379,12 @@ hipError_t launch_all_active(Launch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine_residual(Launch& L, bool restart, hipStream_t s,
-                                  Timing* t) {
+hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_kernel,
                   dim3(L.blocks), dim3(kBlock),
-                  weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob,
-                  restart ? 1 : 0);
+                  weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
   klaunch(t, PARO_ST_REFINE, refine_final_kernel, dim3(L.maxcols, L.nprob),
-          dim3(kFinal), 0, s, L.d, restart ? 1 : 0);
+          dim3(kFinal), 0, s, L.d);
   return hipGetLastError();
 }
 
