@@ -150,12 +150,12 @@ constexpr int kFinal = 64;
 // the wavefront, whose lanes all end with the same bits).  The loads of 16
 // segments per lane are issued together (clamped addresses, masked adds):
 // the partials come from every XCD, so each round trip costs the full
-// fabric latency.  Every lane receives the sums.
-template <int NA>
+// fabric latency.  Every lane receives the sums.  KU (loads per lane in
+// flight) changes the register use, not the order of the additions.
+template <int NA, int kU = 16>
 __device__ __forceinline__ void column_sums(const double* __restrict__ part,
                                             size_t stride, int c, int nb,
                                             double (&out)[NA]) {
-  constexpr int kU = 16;
   const int t = threadIdx.x & (kFinal - 1);  // lane of the wavefront
   double v[NA];
 #pragma unroll
@@ -201,6 +201,19 @@ __device__ __forceinline__ bool chunk_active(const int* act, int ch, int V,
     a |= c < ncols ? x : 0;
   }
   return a != 0;
+}
+
+// Active columns as a mask (lane c of each wavefront reads column c's
+// flag; at most 64 columns): one load for every chunk of a block.
+__device__ __forceinline__ unsigned long long active_mask(const int* act,
+                                                         int ncols) {
+  const int lane = threadIdx.x & 63;
+  const int x = ldg(act + min(lane, ncols - 1));  // unconditional load
+  return __ballot(lane < ncols && x != 0);
+}
+template <int V>
+__device__ __forceinline__ bool chunk_in_mask(unsigned long long m, int ch) {
+  return ((m >> (ch * V)) & ((1ull << V) - 1)) != 0;
 }
 
 // The 15-point Kuhn stencil: neighbour offsets (x, y, z) in ascending
@@ -387,15 +400,30 @@ struct BetaStep {
   double beta;
   int it, next, bad;
 };
-__device__ __forceinline__ BetaStep beta_step(const ColState* cs, int c,
-                                              int par, double rz, double rr) {
+// The parity-par state beta_step reads, loaded ahead of the partials.
+struct BetaIn {
+  double rzp, tol2;
+  int itp, maxit, status;
+};
+__device__ __forceinline__ BetaIn beta_in(const ColState* cs, int c,
+                                          int par) {
+  BetaIn q;
+  q.rzp = ldg(&cs->rzp[par][c]);
+  q.tol2 = ldg(&cs->tol2[c]);
+  q.itp = ldg(&cs->itp[par][c]);
+  q.maxit = ldg(&cs->maxit);
+  q.status = ldg(&cs->status);
+  return q;
+}
+__device__ __forceinline__ BetaStep beta_step(const BetaIn& q, double rz,
+                                              double rr) {
   BetaStep b;
   b.bad = !isfinite(rz) || !isfinite(rr);
-  b.beta = b.bad ? 0.0 : rz / cs->rzp[par][c];
-  b.it = cs->itp[par][c] + 1;
-  const bool more = rr > cs->tol2[c];
-  b.next = (!b.bad && more && b.it < cs->maxit &&
-            !(ldg(&cs->status) & kStNotSpd)) ? 1 : 0;
+  b.beta = b.bad ? 0.0 : rz / q.rzp;
+  b.it = q.itp + 1;
+  const bool more = rr > q.tol2;
+  b.next = (!b.bad && more && b.it < q.maxit && !(q.status & kStNotSpd))
+               ? 1 : 0;
   return b;
 }
 __device__ __forceinline__ void beta_commit(ColState* cs, int c, int par,
@@ -429,10 +457,11 @@ __device__ __forceinline__ void beta_pair(const Desc& d, int c, int par) {
     if (lane == 0) cs->act[par ^ 1][c] = 0;
     return;
   }
+  const BetaIn q = beta_in(cs, c, par);
   double tot[2];
   column_sums<2>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
   if (lane != 0) return;
-  const BetaStep b = beta_step(cs, c, par, tot[0], tot[1]);
+  const BetaStep b = beta_step(q, tot[0], tot[1]);
   beta_commit(cs, c, par, b, tot[0], tot[1]);
 }
 
@@ -571,7 +600,7 @@ __device__ __forceinline__ CmUnit cm_unit(long long u, int cpr) {
 // reduction of the thread's V products.
 template <typename T, int V>
 __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
-                                             int par,
+                                             unsigned long long amask,
                                              double* __restrict__ ws) {
   const CmVecs<T> vs(d);
   const int tid = threadIdx.x;
@@ -581,7 +610,7 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
   const long long row = t * kBlock + tid;
   const bool valid = row < n;
   const long long rr = valid ? row : n - 1;
-  const int* act = d.cs->act[par];
+  const int lane = tid & 63;
   const unsigned ur = (unsigned)rr;
   const unsigned uq = ur / (unsigned)mx;
   const int i = (int)(ur - uq * (unsigned)mx);
@@ -600,7 +629,7 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
     a[s] = ldg(vs.diag + (size_t)s * n + rr);
   }
   for (int ch = 0; ch < cpr; ++ch) {
-    if (!chunk_active(act, ch, V, ncols)) continue;
+    if (!chunk_in_mask<V>(amask, ch)) continue;
     const T* Pr = vs.P + ((size_t)ch * n + rr) * V;
     T q[V], self[V];
 #pragma unroll
@@ -624,13 +653,12 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
     for (int u = 0; u < V; ++u) pq[u] = (double)self[u] * (double)q[u];
     const double tot = wave_reduce_scatter<V>(pq);
     constexpr int kGroup = 64 / V;
-    const int lane = tid & 63;
     if ((lane & (kGroup - 1)) == 0)
       ws[(tid >> 6) * ncols + ch * V + lane / kGroup] = tot;
   }
   __syncthreads();
   for (int c = tid; c < ncols; c += kBlock) {
-    if (!ldg(act + c)) continue;
+    if (((amask >> c) & 1) == 0) continue;
     const double s = ((ws[c] + ws[ncols + c]) + ws[2 * ncols + c]) +
                      ws[3 * ncols + c];
     stg(d.pqp + (size_t)c * d.pqn + t, s);
@@ -638,62 +666,118 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
   __syncthreads();  // ws is reused by the next tile
 }
 
-// r -= alpha q, z = D^-1 r for chunk ch of tile t; r . z and r . r.
+// The CG updates of chunk ch of tile t (kCmRpt rows per thread) in two
+// halves: the loads, issued as soon as the unit is known to be active
+// (before its alpha / beta are formed, so the two latencies overlap; all
+// rows of a thread are loaded before any is stored, or the compiler,
+// unable to rule out aliasing, serialises the rows), then the arithmetic
+// and the stores.  Rows past the end load row n - 1 (unconditional loads
+// stay in flight together) and contribute nothing.
 template <typename T, int V>
-__device__ __forceinline__ void rupd_cm_unit(const Desc& d, long long t,
-                                             int ch, const T (&al)[V],
-                                             double* __restrict__ ws) {
+struct RupdRegs {
+  T r[kCmRpt][V], q[kCmRpt][V], di[kCmRpt];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void rupd_cm_load(const Desc& d, long long t,
+                                             int ch, RupdRegs<T, V>& g) {
   const long long n = d.n;
   const CmVecs<T> vs(d);
+  const long long row0 = t * kCmRows + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const long long row = min(row0 + k * kBlock, n - 1);
+    const size_t o = ((size_t)ch * n + row) * V;
+    ldv<T, V>(vs.R + o, g.r[k]);
+    ldv<T, V>(vs.Q + o, g.q[k]);
+    g.di[k] = ldg(vs.dinv + row);
+  }
+}
+
+// r -= alpha q, z = D^-1 r; r . z and r . r partials of the unit.
+template <typename T, int V>
+__device__ __forceinline__ void rupd_cm_finish(const Desc& d, long long t,
+                                               int ch, const T (&al)[V],
+                                               RupdRegs<T, V>& g,
+                                               double* __restrict__ ws) {
+  const long long n = d.n;
+  const CmVecs<T> vs(d);
+  const long long row0 = t * kCmRows + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const bool ok = row0 + k * kBlock < n;
+    g.di[k] = ok ? g.di[k] : T(0);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      g.r[k][u] = ok ? g.r[k][u] : T(0);
+      g.q[k][u] = ok ? g.q[k][u] : T(0);
+    }
+  }
   double x[2 * V];
 #pragma unroll
   for (int u = 0; u < 2 * V; ++u) x[u] = 0.0;
 #pragma unroll
-  for (int k = 0; k < kCmRpt; ++k) {
-    const long long row = t * kCmRows + threadIdx.x + k * kBlock;
-    if (row >= n) break;
-    const size_t o = ((size_t)ch * n + row) * V;
-    T r[V], q[V];
-    ldv<T, V>(vs.R + o, r);
-    ldv<T, V>(vs.Q + o, q);
-    const T di = ldg(vs.dinv + row);
+  for (int k = 0; k < kCmRpt; ++k)
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-      r[u] = fma(-al[u], q[u], r[u]);
-      x[u] += (double)r[u] * (double)(di * r[u]);
-      x[V + u] += (double)r[u] * (double)r[u];
+      g.r[k][u] = fma(-al[u], g.q[k][u], g.r[k][u]);
+      x[u] += (double)g.r[k][u] * (double)(g.di[k] * g.r[k][u]);
+      x[V + u] += (double)g.r[k][u] * (double)g.r[k][u];
     }
-    stv<T, V>(vs.R + o, r);
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const long long row = row0 + k * kBlock;
+    if (row < n) stv<T, V>(vs.R + ((size_t)ch * n + row) * V, g.r[k]);
   }
   cm_unit_partials<2, V>(x, d, ch, t, ws);
 }
 
-// x += alpha p (columns active this iteration); p = D^-1 r + beta p
-// (columns active next iteration), chunk ch of tile t.
 template <typename T, int V>
-__device__ __forceinline__ void pupd_cm_unit(const Desc& d, long long t,
-                                             int ch, const T (&al)[V],
-                                             const T (&be)[V],
-                                             const bool (&nx)[V]) {
+struct PupdRegs {
+  T x[kCmRpt][V], p[kCmRpt][V], r[kCmRpt][V], di[kCmRpt];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void pupd_cm_load(const Desc& d, long long t,
+                                             int ch, PupdRegs<T, V>& g) {
   const long long n = d.n;
   const CmVecs<T> vs(d);
+  const long long row0 = t * kCmRows + threadIdx.x;
 #pragma unroll
   for (int k = 0; k < kCmRpt; ++k) {
-    const long long row = t * kCmRows + threadIdx.x + k * kBlock;
-    if (row >= n) break;
+    const long long row = min(row0 + k * kBlock, n - 1);
     const size_t o = ((size_t)ch * n + row) * V;
-    T x[V], p[V], r[V];
-    ldv<T, V>(vs.X + o, x);
-    ldv<T, V>(vs.P + o, p);
-    ldv<T, V>(vs.R + o, r);
-    const T di = ldg(vs.dinv + row);
+    ldv<T, V>(vs.X + o, g.x[k]);
+    ldv<T, V>(vs.P + o, g.p[k]);
+    ldv<T, V>(vs.R + o, g.r[k]);
+    g.di[k] = ldg(vs.dinv + row);
+  }
+}
+
+// x += alpha p (columns active this iteration); p = D^-1 r + beta p
+// (columns active next iteration).
+template <typename T, int V>
+__device__ __forceinline__ void pupd_cm_finish(const Desc& d, long long t,
+                                               int ch, const T (&al)[V],
+                                               const T (&be)[V],
+                                               const bool (&nx)[V],
+                                               PupdRegs<T, V>& g) {
+  const long long n = d.n;
+  const CmVecs<T> vs(d);
+  const long long row0 = t * kCmRows + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kCmRpt; ++k) {
+    const long long row = row0 + k * kBlock;
+    if (row >= n) continue;
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-      x[u] = fma(al[u], p[u], x[u]);
-      p[u] = nx[u] ? fma(be[u], p[u], di * r[u]) : p[u];
+      g.x[k][u] = fma(al[u], g.p[k][u], g.x[k][u]);
+      g.p[k][u] =
+          nx[u] ? fma(be[u], g.p[k][u], g.di[k] * g.r[k][u]) : g.p[k][u];
     }
-    stv<T, V>(vs.X + o, x);
-    stv<T, V>(vs.P + o, p);
+    const size_t o = ((size_t)ch * n + row) * V;
+    stv<T, V>(vs.X + o, g.x[k]);
+    stv<T, V>(vs.P + o, g.p[k]);
   }
 }
 
@@ -714,10 +798,14 @@ __device__ __forceinline__ void pupd_cm_unit(const Desc& d, long long t,
 // (owner of blockIdx.x), with VV (constexpr) the problem's FP32 width.
 // Launches queued after convergence (no active column) do nothing: the
 // column flags may be stale then.
+// `amask` (bit c: column c active at parity par) is loaded once, with the
+// active count.
 #define PARO_CM_LOOP(T, D, nprob, par, VFIX, BODY)                         \
   {                                                                        \
     const Desc& d = D[owner(D, nprob, blockIdx.x, false)];                 \
-    if (ldg(&d.cs->n_active[par]) == 0) return;                            \
+    const int nact_ = ldg(&d.cs->n_active[par]);                           \
+    const unsigned long long amask = active_mask(d.cs->act[par], d.ncols); \
+    if (nact_ == 0) return;                                                \
     const int lb_ = blockIdx.x - d.b0;                                     \
     const int vw_ = VFIX ? VFIX : cm_width<T>(d);                          \
     const int cpr_ = d.ncols / vw_;                                        \
@@ -756,15 +844,20 @@ __device__ __forceinline__ void pupd_cm_chunk(const Desc& d, CmUnit un,
     nx[u] = ldg(&cs->act[par ^ 1][c]) != 0;
     be[u] = nx[u] ? (T)ldg(&cs->beta[c]) : T(0);
   }
-  pupd_cm_unit<T, V>(d, un.t, un.ch, al, be, nx);
+  PupdRegs<T, V> g;
+  pupd_cm_load<T, V>(d, un.t, un.ch, g);
+  pupd_cm_finish<T, V>(d, un.t, un.ch, al, be, nx, g);
 }
 
 template <typename T, int V>
 __device__ __forceinline__ void rupd_cm_chunk(const Desc& d, CmUnit un,
                                               int par, double* ws) {
   T al[V];
-  if (cm_alpha<T, V>(d.cs, par, un.ch, al))
-    rupd_cm_unit<T, V>(d, un.t, un.ch, al, ws);
+  if (cm_alpha<T, V>(d.cs, par, un.ch, al)) {
+    RupdRegs<T, V> g;
+    rupd_cm_load<T, V>(d, un.t, un.ch, g);
+    rupd_cm_finish<T, V>(d, un.t, un.ch, al, g, ws);
+  }
 }
 
 // VFIX: the common vector width of the launch's problems, or 0 (each
@@ -774,11 +867,13 @@ __global__ void PARO_STREAM_BOUNDS
 spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double ws[4 * kNtMax];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
-  if (ldg(&d.cs->n_active[par]) == 0) return;  // queued after convergence
+  const int nact = ldg(&d.cs->n_active[par]);
+  const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
+  if (nact == 0) return;  // queued after convergence
   const int lb = blockIdx.x - d.b0;
   const int vw = cm_width<T>(d);
   for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end; w.t += w.step) {
-    PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, par, ws)))
+    PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, amask, ws)))
   }
 }
 
@@ -790,21 +885,24 @@ spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
 // block 0 does the finaliser's per-iteration bookkeeping.
 template <typename T, int V>
 __device__ __forceinline__ void rupd_alpha_chunk(const Desc& d, CmUnit un,
-                                                 int par, double* ws,
-                                                 double* al_s) {
+                                                 int par,
+                                                 unsigned long long amask,
+                                                 double* ws, double* al_s) {
   ColState* cs = d.cs;
-  const int* act = cs->act[par];
-  if (!chunk_active(act, un.ch, V, d.ncols)) return;
+  if (!chunk_in_mask<V>(amask, un.ch)) return;
+  RupdRegs<T, V> g;
+  rupd_cm_load<T, V>(d, un.t, un.ch, g);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (wave < V) {
     const int c = un.ch * V + wave;
     double a = 0.0;
-    if (ldg(act + c)) {
+    if ((amask >> c) & 1) {
+      const double rz = ldg(&cs->rzp[par][c]);
       double tot[1];
       column_sums<1>(d.pqp, 0, c, d.pqn, tot);
       const double pq = tot[0];
       const bool bad = !(pq > 0.0) || !isfinite(pq);
-      a = bad ? 0.0 : cs->rzp[par][c] / pq;
+      a = bad ? 0.0 : rz / pq;
       if (lane == 0 && un.t == 0) {
         if (bad)
           atomicOr(&cs->status,
@@ -818,7 +916,7 @@ __device__ __forceinline__ void rupd_alpha_chunk(const Desc& d, CmUnit un,
   T al[V];
 #pragma unroll
   for (int u = 0; u < V; ++u) al[u] = (T)al_s[u];
-  rupd_cm_unit<T, V>(d, un.t, un.ch, al, ws);  // ends with a barrier
+  rupd_cm_finish<T, V>(d, un.t, un.ch, al, g, ws);  // ends with a barrier
 }
 
 template <typename T, int VFIX>
@@ -837,7 +935,7 @@ rupd_alpha_kernel(const Desc* __restrict__ D, int nprob, int par) {
     }
   }
   PARO_CM_LOOP(T, D, nprob, par, VFIX,
-               (rupd_alpha_chunk<T, VV>(d, un, par, ws, al_s)))
+               (rupd_alpha_chunk<T, VV>(d, un, par, amask, ws, al_s)))
 }
 
 
@@ -849,19 +947,31 @@ rupd_alpha_kernel(const Desc* __restrict__ D, int nprob, int par) {
 // the next parity.
 template <typename T, int V>
 __device__ __forceinline__ void pupd_beta_chunk(const Desc& d, CmUnit un,
-                                                int par, double* b_s) {
+                                                int par,
+                                                unsigned long long amask,
+                                                double* b_s) {
   ColState* cs = d.cs;
+  if (!chunk_in_mask<V>(amask, un.ch)) return;
   T al[V];
-  if (!cm_alpha<T, V>(cs, par, un.ch, al)) return;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int c = un.ch * V + u;  // < ncols (ncols is a multiple of V)
+    const T a = (T)ldg(&cs->alpha[c]);  // unconditional: loads together
+    al[u] = ((amask >> c) & 1) ? a : T(0);
+  }
+  PupdRegs<T, V> g;
+  pupd_cm_load<T, V>(d, un.t, un.ch, g);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (wave < V) {
     const int c = un.ch * V + wave;
     double beta = 0.0;
     int next = 0;
-    if (ldg(&cs->act[par][c])) {
+    if ((amask >> c) & 1) {
+      const BetaIn q = beta_in(cs, c, par);
       double tot[2];
-      column_sums<2>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
-      const BetaStep b = beta_step(cs, c, par, tot[0], tot[1]);
+      // 4 loads per lane: the unit's data are in registers meanwhile.
+      column_sums<2, 4>(d.cgp, (size_t)d.cgstride, c, d.cgn, tot);
+      const BetaStep b = beta_step(q, tot[0], tot[1]);
       beta = b.beta;
       next = b.next;
       if (lane == 0 && un.t == 0) beta_commit(cs, c, par, b, tot[0], tot[1]);
@@ -879,7 +989,7 @@ __device__ __forceinline__ void pupd_beta_chunk(const Desc& d, CmUnit un,
     nx[u] = b_s[4 + u] != 0.0;
     be[u] = nx[u] ? (T)b_s[u] : T(0);
   }
-  pupd_cm_unit<T, V>(d, un.t, un.ch, al, be, nx);
+  pupd_cm_finish<T, V>(d, un.t, un.ch, al, be, nx, g);
   __syncthreads();  // b_s is rewritten by the next unit
 }
 
@@ -894,7 +1004,7 @@ pupd_beta_kernel(const Desc* __restrict__ D, int nprob, int par) {
         if (!ldg(&d0.cs->act[par][c])) d0.cs->act[par ^ 1][c] = 0;
   }
   PARO_CM_LOOP(T, D, nprob, par, VFIX,
-               (pupd_beta_chunk<T, VV>(d, un, par, b_s)))
+               (pupd_beta_chunk<T, VV>(d, un, par, amask, b_s)))
 }
 
 // Continuing FP32 pass after residual replacement: p = D^-1 r + beta p on
@@ -1087,10 +1197,11 @@ cg_persistent_kernel(const Desc* __restrict__ D, int nprob, int iters) {
   bool done = false;
   for (int it = 0; it < iters; ++it) {
     const bool on = ldg(&d.cs->n_active[par]) != 0;
+    const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
     if (on)
       for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end;
            w.t += w.step) {
-        PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, par, ws)))
+        PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, amask, ws)))
       }
     grid.sync();
     for (int q = blockIdx.x * (kBlock / 64) + wave; q < npairs; q += nwaves)
