@@ -1865,19 +1865,55 @@ gram_final_kernel(const Desc* __restrict__ D, int sym) {
 
 // ------------------------------------------------------------------------
 // Small generalised eigenproblem A c = theta B c (Step 4's N_t x N_t
-// problem), one workgroup, FP64, everything in LDS.
-//   1. B = L L^T (Cholesky);  2. S = L^{-1} A L^{-T};  3. cyclic Jacobi on
-//   S with round-robin ordering (N_t/2 disjoint rotations per round,
-//   applied as independent 2 x 2 blocks: two barriers per round);
-//   4. theta ascending (ties by index);  5. C = L^{-T} Y;  6. signs.
+// problem), one workgroup of kGeThreads, FP64, everything in LDS.
+//   1. B = L L^T (Cholesky, right-looking, one barrier per column);
+//   2. Li = L^{-1} (column j by thread j: a forward substitution each,
+//      no barriers), S = Li A Li^T as two small products;
+//   3. cyclic Jacobi on S with round-robin ordering: N_t/2 disjoint
+//      rotations per round, each thread forming the (c, s) it needs from
+//      the round's input matrix and writing the output matrix (two LDS
+//      copies alternate), so a round costs one barrier;
+//   4. theta ascending (ties by index);  5. C = Li^T Y;  6. signs.
 // ------------------------------------------------------------------------
 constexpr int kLd = kNtMax + 1;
+constexpr int kGeThreads = 512;
 
 // Maximum over a wavefront (every lane receives it).
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+// Round-robin pair `slot` of round `round` over nn (even) indices: slot 0
+// pairs index 0 with the rotating ring's head; the ring 1 .. nn-1
+// advances by one per round.  Every index is in exactly one pair.
+__device__ __forceinline__ void rr_pair(int slot, int round, int nn, int& p,
+                                        int& q) {
+  int a0 = slot == 0 ? 0 : slot + round;
+  a0 = a0 > nn - 1 ? a0 - (nn - 1) : a0;
+  int b0 = nn - 1 - slot + round;
+  b0 = b0 > nn - 1 ? b0 - (nn - 1) : b0;
+  p = a0 < b0 ? a0 : b0;
+  q = a0 < b0 ? b0 : a0;
+}
+
+// The Jacobi rotation (c, s) annihilating S[p][q] (identity when q is the
+// dummy index of an odd n or |S[p][q]| <= skip).
+__device__ __forceinline__ bool jacobi_cs(const double (*S)[kLd], int p,
+                                          int q, int n, double skip,
+                                          double& c, double& sn) {
+  c = 1.0;
+  sn = 0.0;
+  if (q >= n) return false;
+  const double apq = S[p][q];
+  if (!(fabs(apq) > skip)) return false;
+  const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
+  const double t =
+      (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  sn = t * c;
+  return true;
 }
 
 __device__ void geneig_body(const double* __restrict__ Ain,
@@ -1887,62 +1923,67 @@ __device__ void geneig_body(const double* __restrict__ Ain,
                             int* __restrict__ info_out,
                             int* __restrict__ status,
                             const int* __restrict__ clus) {
-  __shared__ double A[kNtMax][kLd];
-  __shared__ double L[kNtMax][kLd];
-  __shared__ double Y[kNtMax][kLd];
-  __shared__ double rc[kNtMax / 2], rs[kNtMax / 2];
-  __shared__ int rp[kNtMax / 2], rq[kNtMax / 2], rr[kNtMax / 2];
-  __shared__ double red[kBlock];
-  __shared__ int s_info;
+  __shared__ double Sa[kNtMax][kLd];  // A, then S and Jacobi ping
+  __shared__ double Sb[kNtMax][kLd];  // Li A, then Jacobi pong, then C
+  __shared__ double L[kNtMax][kLd];   // B; L^T (strict upper); Li (lower)
+  __shared__ double Y[kNtMax][kLd];   // eigenvectors of S
+  __shared__ double red[kGeThreads / 64];
+  __shared__ int s_info, s_rot;
   __shared__ int perm[kNtMax];
   __shared__ double th[kNtMax];
-  __shared__ double dl[kNtMax];
+  __shared__ double ld[kNtMax];  // diagonal of L
   const int tid = threadIdx.x;
   const int nn = n + (n & 1);
   // Zero the padded LDS matrices (odd n uses row/column n as a dummy),
-  // then load the n x n inputs with independent, unrolled global loads.
-  for (int e = tid; e < kNtMax * kNtMax; e += kBlock) {
+  // then load the n x n inputs.
+  for (int e = tid; e < kNtMax * kNtMax; e += kGeThreads) {
     const int i = e / kNtMax, j = e % kNtMax;
-    A[i][j] = 0.0;
+    Sa[i][j] = 0.0;
+    Sb[i][j] = 0.0;
     L[i][j] = 0.0;
-    Y[i][j] = 0.0;
+    Y[i][j] = (i == j && i < n) ? 1.0 : 0.0;
   }
   if (tid == 0) s_info = 0;
   __syncthreads();
   // Cluster-wise projection: entries coupling different clusters are
-  // dropped, so every step below works block by block (rotations and
-  // substitutions never mix blocks of a block-diagonal pencil).
+  // dropped, so every step below works block by block (the factor, its
+  // inverse, the products and the rotations of a block-diagonal pencil
+  // never mix blocks).
 #pragma unroll 4
-  for (int e = tid; e < n * n; e += kBlock) {
+  for (int e = tid; e < n * n; e += kGeThreads) {
     const int i = e / n, j = e % n;
     const bool keep = !clus || clus[i] == clus[j];
-    A[i][j] = keep ? Ain[e] : 0.0;
+    Sa[i][j] = keep ? Ain[e] : 0.0;
     L[i][j] = keep ? Bin[e] : 0.0;
   }
+  if (tid < n) th[tid] = Bin[tid * n + tid];  // diagonal of B (pivot test)
   __syncthreads();
 
-  // 1. Cholesky B = L L^T, right-looking: at step k every thread reads the
-  // pivot, column k is scaled, then the trailing lower triangle is
-  // updated (entries see their updates in ascending k, as a left-looking
-  // dot product would).
-  if (tid < n) th[tid] = L[tid][tid];  // diagonal of B (pivot test)
-  __syncthreads();
+  // 1. Cholesky, right-looking: at step k the pivot d = B_k[k][k] of the
+  // running Schur complement is read, column k scaled by 1/sqrt(d) is
+  // stored transposed in the strict upper triangle (row k, which no later
+  // step touches), and the trailing lower triangle is updated with the
+  // unscaled column (b_ik b_jk / d), all in one phase.
   for (int k = 0; k < n; ++k) {
     const double piv = L[k][k];
     // A pivot at rounding level of the diagonal means the columns are
     // linearly dependent in the M inner product.
     const bool bad = !(piv > 1e-14 * th[k]) || !isfinite(piv);
-    const double lkk = sqrt(bad ? 1.0 : piv);
-    for (int i = k + 1 + tid; i < n; i += kBlock) L[i][k] = L[i][k] / lkk;
-    __syncthreads();
-    if (tid == 0) {
-      L[k][k] = lkk;
-      if (bad && s_info == 0) s_info = k + 1;
-    }
+    const double d = bad ? 1.0 : piv;
+    const double lkk = sqrt(d), rd = 1.0 / d, rl = 1.0 / lkk;
     const int m = n - k - 1;
-    for (int e = tid; e < m * m; e += kBlock) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) L[i][j] -= L[i][k] * L[j][k];
+    for (int e = tid; e < m * (m + 1); e += kGeThreads) {
+      if (e < m * m) {
+        const int i = k + 1 + e / m, j = k + 1 + e % m;
+        if (j <= i) L[i][j] -= (L[i][k] * rd) * L[j][k];
+      } else {
+        const int i = k + 1 + (e - m * m);
+        L[k][i] = L[i][k] * rl;
+      }
+    }
+    if (tid == 0) {
+      ld[k] = lkk;
+      if (bad && s_info == 0) s_info = k + 1;
     }
     __syncthreads();
   }
@@ -1951,149 +1992,133 @@ __device__ void geneig_body(const double* __restrict__ Ain,
       *info_out = s_info;
       if (status) atomicOr(status, (int)kStSingular);
     }
-    for (int e = tid; e < n * n; e += kBlock)
+    for (int e = tid; e < n * n; e += kGeThreads)
       C_out[e] = (e / n == e % n) ? 1.0 : 0.0;
-    for (int e = tid; e < n; e += kBlock) theta_out[e] = Ain[e * n + e];
+    for (int e = tid; e < n; e += kGeThreads) theta_out[e] = Ain[e * n + e];
     return;
   }
-  if (tid < n) dl[tid] = 1.0 / L[tid][tid];
 
-  // 2. S = L^{-1} A L^{-T}: two forward substitutions, each row-parallel
-  // with one barrier per step (step i finalises row i into the output and
-  // removes it from the rows below).  First Y := A, A := L^{-1} Y; then
-  // Y := A^T, A := L^{-1} Y.
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int e = tid; e < n * n; e += kBlock) {
-      const int i = e / n, j = e % n;
-      Y[i][j] = pass == 0 ? A[i][j] : A[j][i];
-    }
-    __syncthreads();
-    for (int i = 0; i < n; ++i) {
-      const double di = dl[i];
-      for (int e = tid; e < (n - i) * n; e += kBlock) {
-        const int r = i + e / n, j = e % n;
-        const double x = Y[i][j] * di;
-        if (r == i)
-          A[i][j] = x;
-        else
-          Y[r][j] -= L[r][i] * x;
-      }
-      __syncthreads();
+  // 2. Li = L^{-1}: thread j solves L x = e_j by forward substitution
+  // (x_i = -(sum_{j <= k < i} L[i][k] x_k) / L[i][i]) and keeps x in
+  // column j of the lower triangle (L[i][k] is read from its transposed
+  // copy L^T[k][i]; the lower triangle's old contents are dead).
+  if (tid < n) {
+    const int j = tid;
+    L[j][j] = 1.0 / ld[j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[k][i] * L[k][j];
+      L[i][j] = -s / ld[i];
     }
   }
-  for (int e = tid; e < n * n; e += kBlock) {
+  __syncthreads();
+  // Sb = Li A (Li lower triangular: k <= i).
+  for (int e = tid; e < n * n; e += kGeThreads) {
     const int i = e / n, j = e % n;
-    if (i < j) {
-      const double s = 0.5 * (A[i][j] + A[j][i]);
-      A[i][j] = s;
-      A[j][i] = s;
-    }
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) s += L[i][k] * Sa[k][j];
+    Sb[i][j] = s;
   }
-  // Y := identity (eigenvector accumulator).
-  for (int e = tid; e < kNtMax * kNtMax; e += kBlock) {
-    const int i = e / kNtMax, j = e % kNtMax;
-    Y[i][j] = (i == j && i < n) ? 1.0 : 0.0;
+  __syncthreads();
+  // S = (Li A) Li^T, symmetrised: S[i][j] = S[j][i] = the mean of the two
+  // computed triangles.
+  for (int e = tid; e < n * n; e += kGeThreads) {
+    const int i = e / n, j = e % n;
+    if (i > j) continue;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k <= j; ++k) s1 += Sb[i][k] * L[j][k];
+    for (int k = 0; k <= i; ++k) s2 += Sb[j][k] * L[i][k];
+    const double s = i == j ? s1 : 0.5 * (s1 + s2);
+    Sa[i][j] = s;
+    Sa[j][i] = s;
   }
   __syncthreads();
 
-  // 3. Cyclic Jacobi, round-robin pairs (N_t / 2 disjoint rotations per
-  // round).  A rotation is skipped when |a_pq| <= 1e-17 ||S||_F (already
-  // zero at working precision); the iteration stops after a sweep that
-  // rotates nothing.
+  // 3. Cyclic Jacobi, round-robin pairs.  A rotation is skipped when
+  // |s_pq| <= 1e-17 ||S||_F (already zero at working precision); the
+  // iteration stops before a sweep that would rotate nothing.
   const int half = nn / 2;
   const int nblk = half * half;
-  __shared__ int s_rot;
+  const int nwave = kGeThreads / 64;
   double fro2 = 0.0;
-  for (int e = tid; e < n * n; e += kBlock) {
-    const double v = A[e / n][e % n];
+  for (int e = tid; e < n * n; e += kGeThreads) {
+    const double v = Sa[e / n][e % n];
     fro2 += v * v;
   }
-  red[tid] = fro2;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) fro2 += __shfl_xor(fro2, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = fro2;
   __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  const double skip = 1e-17 * sqrt(red[0]);
-  __syncthreads();  // red is reused below
+  double tot = 0.0;
+  for (int w = 0; w < nwave; ++w) tot += red[w];
+  const double skip = 1e-17 * sqrt(tot);
+  double (*Sc)[kLd] = Sa;  // the current S
+  double (*Sn)[kLd] = Sb;  // the next S
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
-    // Stop before a sweep that would rotate nothing: every |a_pq| <= skip.
     double off = 0.0;
-    for (int e = tid; e < n * n; e += kBlock) {
+    for (int e = tid; e < n * n; e += kGeThreads) {
       const int i = e / n, j = e % n;
-      if (i < j) off = fmax(off, fabs(A[i][j]));
+      if (i < j) off = fmax(off, fabs(Sc[i][j]));
     }
     off = wave_max(off);
+    __syncthreads();  // red is rewritten
     if ((tid & 63) == 0) red[tid >> 6] = off;
     if (tid == 0) s_rot = 0;
     __syncthreads();
-    if (fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) <= skip) break;
+    double mx = 0.0;
+    for (int w = 0; w < nwave; ++w) mx = fmax(mx, red[w]);
+    if (mx <= skip) break;
     for (int round = 0; round < nn - 1; ++round) {
-      if (tid < half) {
-        // Round-robin pairing: slot 0 pairs index 0 with the rotating
-        // ring's head; the ring 1 .. nn-1 advances by one per round.
-        int a0 = tid == 0 ? 0 : tid + round;
-        a0 = a0 > nn - 1 ? a0 - (nn - 1) : a0;
-        int b0 = nn - 1 - tid + round;
-        b0 = b0 > nn - 1 ? b0 - (nn - 1) : b0;
-        const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
-        double c = 1.0, sn = 0.0;
-        int rot = 0;
-        if (q < n) {
-          const double apq = A[p][q];
-          if (fabs(apq) > skip) {
-            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) /
-                             (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-            rot = 1;
-            s_rot = 1;
-          }
-        }
-        rc[tid] = c;
-        rs[tid] = sn;
-        rp[tid] = p;
-        rq[tid] = q;
-        rr[tid] = rot;
-      }
-      __syncthreads();
-      // A <- J^T A J as independent 2 x 2 blocks (row pair k, column pair
+      // S' = J^T S J as independent 2 x 2 blocks (row pair k, column pair
       // l): the row rotation, then the column rotation; Y <- Y J.  A pair
       // that does not rotate has c = 1, s = 0 (exact identity).
-      for (int e = tid; e < nblk + n * half; e += kBlock) {
+      for (int e = tid; e < nblk + n * half; e += kGeThreads) {
         if (e < nblk) {
           const int k = e / half, l = e - k * half;
-          const int p = rp[k], q = rq[k], r = rp[l], t = rq[l];
-          const double c1 = rc[k], s1 = rs[k], c2 = rc[l], s2 = rs[l];
-          const double apr = A[p][r], apt = A[p][t];
-          const double aqr = A[q][r], aqt = A[q][t];
+          int p, q, r, t;
+          rr_pair(k, round, nn, p, q);
+          rr_pair(l, round, nn, r, t);
+          double c1, s1, c2, s2;
+          const bool rot = jacobi_cs(Sc, p, q, n, skip, c1, s1);
+          if (k == l) {
+            c2 = c1;
+            s2 = s1;
+            if (rot) s_rot = 1;
+          } else {
+            jacobi_cs(Sc, r, t, n, skip, c2, s2);
+          }
+          const double apr = Sc[p][r], apt = Sc[p][t];
+          const double aqr = Sc[q][r], aqt = Sc[q][t];
           const double bpr = c1 * apr - s1 * aqr, bpt = c1 * apt - s1 * aqt;
           const double bqr = s1 * apr + c1 * aqr, bqt = s1 * apt + c1 * aqt;
           double cpt = s2 * bpr + c2 * bpt, cqr = c2 * bqr - s2 * bqt;
-          if (k == l && rr[k]) cpt = cqr = 0.0;  // the annihilated pair
-          A[p][r] = c2 * bpr - s2 * bpt;
-          A[p][t] = cpt;
-          A[q][r] = cqr;
-          A[q][t] = s2 * bqr + c2 * bqt;
+          if (k == l && rot) cpt = cqr = 0.0;  // the annihilated pair
+          Sn[p][r] = c2 * bpr - s2 * bpt;
+          Sn[p][t] = cpt;
+          Sn[q][r] = cqr;
+          Sn[q][t] = s2 * bqr + c2 * bqt;
         } else {
           const int e2 = e - nblk, l = e2 / n, i = e2 - l * n;
-          const int p = rp[l], q = rq[l];
-          const double c = rc[l], sn = rs[l];
+          int p, q;
+          rr_pair(l, round, nn, p, q);
+          double c, sn;
+          jacobi_cs(Sc, p, q, n, skip, c, sn);
           const double yp = Y[i][p], yq = Y[i][q];
           Y[i][p] = c * yp - sn * yq;
           Y[i][q] = sn * yp + c * yq;
         }
       }
       __syncthreads();
+      double (*sw)[kLd] = Sc;
+      Sc = Sn;
+      Sn = sw;
     }
     if (s_rot == 0) break;
-    __syncthreads();
   }
 
   // 4. Ascending order, ties broken by index (with clusters: within each
   // cluster, which keeps its columns).
-  if (tid < n) th[tid] = A[tid][tid];
+  if (tid < n) th[tid] = Sc[tid][tid];
   __syncthreads();
   if (tid < n) {
     int rank = 0;
@@ -2109,21 +2134,16 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     perm[rank] = tid;
   }
   __syncthreads();
-  // 5. C[:, r] = L^{-T} Y[:, perm[r]] (back substitution, row-parallel,
-  // one barrier per step), stored in A (its diagonal was saved in th).
-  double (*Cs)[kLd] = A;
-  for (int i = n - 1; i >= 0; --i) {
-    const double di = dl[i];
-    for (int e = tid; e < (i + 1) * n; e += kBlock) {
-      const int r = e / n, c = e % n, src = perm[c];
-      const double x = Y[i][src] * di;
-      if (r == i)
-        Cs[i][c] = x;
-      else
-        Y[r][src] -= L[i][r] * x;
-    }
-    __syncthreads();
+  // 5. C[:, r] = Li^T Y[:, perm[r]] (Li lower triangular: k >= i), into
+  // the free copy of S.
+  double (*Cs)[kLd] = Sn;
+  for (int e = tid; e < n * n; e += kGeThreads) {
+    const int i = e / n, r = e % n, src = perm[r];
+    double s = 0.0;
+    for (int k = i; k < n; ++k) s += L[k][i] * Y[k][src];
+    Cs[i][r] = s;
   }
+  __syncthreads();
   // 6. Sign: largest-magnitude entry of each column positive.
   if (tid < n) {
     const int r = tid;
@@ -2144,7 +2164,7 @@ __device__ void geneig_body(const double* __restrict__ Ain,
 }
 
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kGeThreads)
 small_geneig_kernel(const double* __restrict__ A, const double* __restrict__ B,
                     int n, double* __restrict__ theta, double* __restrict__ C,
                     int* __restrict__ info) {
@@ -2153,7 +2173,7 @@ small_geneig_kernel(const double* __restrict__ A, const double* __restrict__ B,
 
 // Step 4's small eigenproblem of every problem of the table (one block
 // per problem).
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kGeThreads)
 geneig_batch_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.x];
   geneig_body(d.Ah, d.Bh, d.ncols, d.theta, d.C, d.geneig_info,
@@ -2578,7 +2598,7 @@ hipError_t launch_gram_full(Launch& L, hipStream_t s, Timing* t) {
 hipError_t launch_small_geneig(const double* A, const double* B, int n,
                                double* theta, double* C, int* info,
                                hipStream_t s) {
-  hipLaunchKernelGGL(small_geneig_kernel, dim3(1), dim3(kBlock), 0, s, A, B, n,
+  hipLaunchKernelGGL(small_geneig_kernel, dim3(1), dim3(kGeThreads), 0, s, A, B, n,
                      theta, C, info);
   return hipGetLastError();
 }
@@ -2588,7 +2608,7 @@ hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   if (L.maxkz) zt_launch(L, kZtX, s, t, PARO_ST_RR_SPMM);  // Z^T W
   if ((e = launch_spmm(L, true, s, t)) != hipSuccess) return e;
   if ((e = gram(L, true, s, t)) != hipSuccess) return e;
-  klaunch(t, PARO_ST_SMALL, geneig_batch_kernel, dim3(L.nprob), dim3(kBlock),
+  klaunch(t, PARO_ST_SMALL, geneig_batch_kernel, dim3(L.nprob), dim3(kGeThreads),
           0, s, (const Desc*)L.d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // Rotation: C (ncols^2) plus three row tiles of tr * ncols = kBlock * V
