@@ -259,7 +259,8 @@ def main():
         cg_ms = sum(td["stages"][k]["ms"] for k in
                     ("cg_spmm", "cg_rupd", "cg_pupd", "cg_final"))
         g = td["stages"]["gram"]
-        gram_flop = 4.0 * n * Nt * Nt * g["launches"] / 3  # 3 kernels/Gram
+        # Two launches per Gram (MFMA tiles, then the fixed-order final).
+        gram_flop = 4.0 * n * Nt * Nt * g["launches"] / 2
         return {
             "bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -372,15 +372,17 @@ int paro_pcg(paro_problem* p, const double* d_B, double* d_X, int ncols,
  * --------------------------------------------------------------------- */
 enum {
   PARO_ST_CG_SPMM = 0,   /* CG: Q = A P with p.q partials              */
-  PARO_ST_CG_RUPD = 1,   /* CG: r -= alpha q, z, r.z, r.r              */
-  PARO_ST_CG_PUPD = 2,   /* CG: x += alpha p, p = z + beta p           */
+  PARO_ST_CG_RUPD = 1,   /* CG: alpha; r -= alpha q, z, r.z, r.r       */
+  PARO_ST_CG_PUPD = 2,   /* CG: beta, stop test; x += alpha p,
+                            p = z + beta p                             */
   PARO_ST_START = 3,     /* source-problem start (b, r0, p0)           */
   PARO_ST_REFINE = 4,    /* FP64 residual + correction update          */
   PARO_ST_RR_SPMM = 5,   /* Rayleigh-Ritz: H W and M W                 */
   PARO_ST_GRAM = 6,      /* W^T H W, W^T M W on matrix cores           */
   PARO_ST_SMALL = 7,     /* small generalised eigensolve (one block)   */
   PARO_ST_ROTATE = 8,    /* U = W C with residual norms                */
-  PARO_ST_CG_FINAL = 9,  /* CG: per-column alpha, beta and stop test   */
+  PARO_ST_CG_FINAL = 9,  /* unused: alpha and beta are formed inside
+                            the update kernels                         */
   PARO_ST_NUM = 10
 };
 
