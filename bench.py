@@ -96,6 +96,10 @@ def parse():
                     help="cells per axis of the Kohn-Sham run")
     ap.add_argument("--ks-iters", type=int, default=300,
                     help="outer iterations at most")
+    ap.add_argument("--no-hbm", action="store_true",
+                    help="skip the CG rates of the 96^3 linear problem")
+    ap.add_argument("--hbm-steps", type=int, default=12,
+                    help="ParO steps of that run")
     ap.add_argument("--ks-poisson-cg", action="store_true",
                     help="Hartree by Jacobi-PCG instead of the direct solve")
     ap.add_argument("--serve-requests", type=int, default=64,
@@ -123,6 +127,29 @@ def algorithmic_bytes(stage, n, nnz, vec_bytes, mat_bytes, diag_bytes):
     if stage == "cg_pupd":   # read X, P, R, D^-1; write X, P
         return n * diag_bytes, 5 * n * vec_bytes
     raise KeyError(stage)
+
+
+def cg_stage_rates(td, n, nnz, vec_b):
+    """Per CG kernel of one event-timed solve (timing dict td): launches,
+    time and achieved GB/s on the CSR figure and on the stencil format;
+    also the algorithmic bytes of the whole CG iteration."""
+    stages = {}
+    it_bytes = 0.0
+    for st in ("cg_spmm", "cg_rupd", "cg_pupd"):
+        s = td["stages"][st]
+        if s["launches"] == 0:
+            continue
+        fixed, per_col = algorithmic_bytes(st, n, nnz, vec_b, vec_b, vec_b)
+        total = fixed * td["cg_iters"] + per_col * td["cg_col_iters"]
+        fo, po = own_format_bytes(st, n, vec_b, vec_b, vec_b)
+        own = fo * td["cg_iters"] + po * td["cg_col_iters"]
+        it_bytes += total
+        stages[st] = {"total_ms": s["ms"], "launches": s["launches"],
+                      "us_per_launch": 1e3 * s["ms"] / s["launches"],
+                      "bytes_per_launch": total / s["launches"],
+                      "gbs": total / (s["ms"] * 1e-3) / 1e9,
+                      "own_gbs": own / (s["ms"] * 1e-3) / 1e9}
+    return stages, it_bytes
 
 
 def own_format_bytes(stage, n, vec_bytes, mat_bytes, diag_bytes):
@@ -231,23 +258,7 @@ def main():
         _, rep_t, prob_t, tim = solve(prec, timing=True)
         td = tim.as_dict()
         vec_b = 4 if prec == "mixed" else 8
-        stages = {}
-        it_bytes = 0.0
-        for st in ("cg_spmm", "cg_rupd", "cg_pupd"):
-            s = td["stages"][st]
-            if s["launches"] == 0:
-                continue
-            fixed, per_col = algorithmic_bytes(st, n, prob_t.nnz, vec_b,
-                                               vec_b, vec_b)
-            total = fixed * td["cg_iters"] + per_col * td["cg_col_iters"]
-            fo, po = own_format_bytes(st, n, vec_b, vec_b, vec_b)
-            own = fo * td["cg_iters"] + po * td["cg_col_iters"]
-            it_bytes += total
-            stages[st] = {"total_ms": s["ms"], "launches": s["launches"],
-                          "us_per_launch": 1e3 * s["ms"] / s["launches"],
-                          "bytes_per_launch": total / s["launches"],
-                          "gbs": total / (s["ms"] * 1e-3) / 1e9,
-                          "own_gbs": own / (s["ms"] * 1e-3) / 1e9}
+        stages, it_bytes = cg_stage_rates(td, n, prob_t.nnz, vec_b)
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
         kernel_names = {"cg_spmm": "spmm_cm_kernel",
@@ -309,6 +320,10 @@ def main():
     if not args.no_serve:
         serve = serve_bench(args, prec)
 
+    hbm = None
+    if not args.no_hbm:
+        hbm = hbm_bound_rates(args)
+
     ks = None
     if not args.no_ks:
         ks = ks_bench(args, prec)
@@ -350,6 +365,7 @@ def main():
         "batch64": batch,
         "serve": serve,
         "kohn_sham": ks,
+        "cg_rates_96": hbm,
         "nonlocal": nonlocal_term,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -559,6 +575,57 @@ def nonlocal_bench(args):
     out.update({"workload": f"softcoulomb_64c_N{w.N}_m{w.m}_nonlocal8",
                 "projectors": int(zeta.shape[1]), "unit": "orbital-updates/s",
                 "precision": "fp64"})
+    return out
+
+
+def hbm_bound_rates(args):
+    """CG kernel rates where the vectors exceed the 256 MB Infinity Cache:
+    the linear problem of the 96^3 Kohn-Sham workload (its external
+    potential, N = 32, m = 8, N_t = 40), a fixed number of ParO steps from
+    the seeded start, event-timed, mixed precision and plain FP64."""
+    import torch
+    from paper_1405_0260_amd import binding as pb
+    from paper_1405_0260_amd import inputs
+
+    dev = torch.device("cuda:0")
+    w = inputs.kohn_sham_96(nc=args.ks_nc)
+    box = pb.Box.cube(w.nc, w.lo, w.hi)
+    V = torch.from_numpy(w.V).to(dev)
+    U0 = torch.from_numpy(w.U0()).to(dev)
+    out = {"workload": f"linear_{w.nc}c_N{w.N}_m{w.m}", "n_dof": w.n_dof,
+           "paro_steps": args.hbm_steps}
+    for prec in ("mixed", "fp64"):
+        o = pb.default_opts(N=w.N, m=w.m, max_steps=args.hbm_steps,
+                            lambda_tol=1e-14, resid_tol=1e-14,
+                            pcg_rtol=1e-10, inner_rtol=args.inner_rtol,
+                            precision=pb.PARO_FP32_INNER if prec == "mixed"
+                            else pb.PARO_FP64)
+        lam = torch.zeros(w.Nt, dtype=torch.float64, device=dev)
+        U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=dev)
+        p = pb.paro_assemble(box, V, o)
+        pb.paro_set_timing(p, True)
+        pb.paro_solve(p, U0, lam, U)
+        torch.cuda.synchronize()
+        td = pb.paro_get_timing(p).as_dict()
+        vec_b = 4 if prec == "mixed" else 8
+        stages, it_bytes = cg_stage_rates(td, w.n_dof, p.nnz, vec_b)
+        cg_ms = sum(v["total_ms"] for v in stages.values())
+        sp = stages["cg_spmm"]
+        out[prec] = {
+            "spmm_gbs": round(sp["gbs"], 1),
+            "spmm_frac": round(sp["gbs"] / HBM_PEAK_GBS, 4),
+            "spmm_own_format_gbs": round(sp["own_gbs"], 1),
+            "spmm_us_per_launch": round(sp["us_per_launch"], 2),
+            "cg_stage_gbs": {k: round(v["gbs"], 1) for k, v in stages.items()},
+            "cg_iteration_gbs": round(it_bytes / (cg_ms * 1e-3) / 1e9, 1),
+            "cg_iteration_frac": round(it_bytes / (cg_ms * 1e-3) / 1e9 /
+                                       HBM_PEAK_GBS, 4),
+            "active_cols_avg": round(td["cg_col_iters"] /
+                                     max(1, td["cg_iters"]), 2)}
+        log(f"[hbm-bound {prec}] SpMM {sp['gbs']:.0f} GB/s, CG iteration "
+            f"{out[prec]['cg_iteration_gbs']:.0f} GB/s")
+        del p, U, lam
+        torch.cuda.empty_cache()
     return out
 
 

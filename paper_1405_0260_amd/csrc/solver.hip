@@ -594,6 +594,71 @@ __device__ __forceinline__ CmUnit cm_unit(long long u, int cpr) {
   return r;
 }
 
+// The value of the adjacent lane of a wavefront: lane - 1 (NEXT false,
+// DPP wave_shr:1) or lane + 1 (NEXT true, wave_shl:1); the lane without a
+// source (0, resp. 63) keeps `old`.
+template <bool NEXT>
+__device__ __forceinline__ int lane_shift(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, NEXT ? 0x130 : 0x138, 0xf, 0xf,
+                                     false);
+}
+template <bool NEXT>
+__device__ __forceinline__ float lane_shift(float old, float v) {
+  return __int_as_float(
+      lane_shift<NEXT>(__float_as_int(old), __float_as_int(v)));
+}
+template <bool NEXT>
+__device__ __forceinline__ double lane_shift(double old, double v) {
+  const long long o = __double_as_longlong(old);
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = (unsigned)lane_shift<NEXT>((int)o, (int)x);
+  const unsigned hi =
+      (unsigned)lane_shift<NEXT>((int)(o >> 32), (int)(x >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The 15 neighbour values of a thread's row (Pr: the row's V values; off:
+// per-offset element steps, 0 where the neighbour lies outside the box).
+// The lanes of a wavefront hold consecutive rows, so the x - 1 and x + 1
+// neighbours of a row are the x-centred neighbours of the adjacent lanes'
+// rows: only the 7 x-centred ones are loaded, the other 8 arrive by a
+// wavefront shift, and lanes 0 and 63 load their own x - 1, resp. x + 1,
+// neighbours.  Where the shifted value belongs to another grid line (x = 0
+// or x = mx - 1), the coefficient is 0.
+template <typename T, int V>
+__device__ __forceinline__ void stencil_gather(const T* Pr,
+                                               const int (&off)[kStencil],
+                                               int lane,
+                                               T (&x)[kStencil][V]) {
+  // Offsets with x = 0 (loaded), x = -1 and x = +1 (shifted), pairwise:
+  // the x = -1 one of plane k is kM[k], centred kM[k] + 1; the x = +1 one
+  // is kP[k], centred kP[k] - 1 (the stencil's ascending order).
+  constexpr int kC[7] = {1, 3, 5, 7, 9, 11, 13};
+  constexpr int kM[4] = {0, 2, 4, 6};
+  constexpr int kP[4] = {8, 10, 12, 14};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) ldv<T, V>(Pr + off[kC[k]], x[kC[k]]);
+  // Edge values: lane 0 holds its x - 1 neighbours, lane 63 its x + 1
+  // ones (plane k in e[k]); the shift leaves them in place on those lanes.
+  T e[4][V];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int u = 0; u < V; ++u) e[k][u] = T(0);
+  if (lane == 0 || lane == 63) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      ldv<T, V>(Pr + (lane == 0 ? off[kM[k]] : off[kP[k]]), e[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      x[kM[k]][u] = lane_shift<false>(e[k][u], x[kM[k] + 1][u]);
+      x[kP[k]][u] = lane_shift<true>(e[k][u], x[kP[k] - 1][u]);
+    }
+}
+
 // Q = A P on the active chunks of SpMM tile t (kBlock rows, one per
 // thread); per (column, tile) p . q.  The row's 15 coefficients stay in
 // registers across the chunks; each chunk ends with one wavefront
@@ -631,19 +696,21 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
   for (int ch = 0; ch < cpr; ++ch) {
     if (!chunk_in_mask<V>(amask, ch)) continue;
     const T* Pr = vs.P + ((size_t)ch * n + rr) * V;
+    T x[kStencil][V];
+    stencil_gather<T, V>(Pr, off, lane, x);
     T q[V], self[V];
 #pragma unroll
-    for (int u = 0; u < V; ++u) q[u] = self[u] = T(0);
+    for (int u = 0; u < V; ++u) q[u] = T(0);
+#pragma unroll
+    for (int s = 0; s < kStencil; ++s)
+#pragma unroll
+      for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      self[u] = valid ? x[kSelf][u] : T(0);
+      q[u] = valid ? q[u] : T(0);
+    }
     if (valid) {
-      T x[kStencil][V];
-#pragma unroll
-      for (int s = 0; s < kStencil; ++s) ldv<T, V>(Pr + off[s], x[s]);
-#pragma unroll
-      for (int s = 0; s < kStencil; ++s)
-#pragma unroll
-        for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
-#pragma unroll
-      for (int u = 0; u < V; ++u) self[u] = x[kSelf][u];
       if constexpr (sizeof(T) == 8)
         if (d.kz) nl_add<V>(d, row, ch * V, q);  // + Z (Z^T p)
       stv<T, V>(vs.Q + ((size_t)ch * n + row) * V, q);
