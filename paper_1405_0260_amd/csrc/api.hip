@@ -266,7 +266,7 @@ void desc_init(Problem& p) {
   d.cgn = d.ntc;
   d.cgstride = (long long)p.Nt * d.ntc;
   d.pqp = p.cpart + 2 * d.cgstride;
-  d.pqn = (int)((p.n + kBlock - 1) / kBlock);
+  d.pqn = (int)((p.n + kSpmmRows - 1) / kSpmmRows);
   d.part = p.part;
   d.gpart = p.gpart;
   d.Ah = p.Ah;
@@ -846,7 +846,7 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.X32 = f32 ? take(sizeof(float) * blk) : 0;
   L.part = take(sizeof(double) * 3 * (size_t)kGridMax * kNtMax);
   L.cpart = take(sizeof(double) * (size_t)Nt *
-                 (2 * cm_tiles(n) + (n + kBlock - 1) / kBlock));
+                 (2 * cm_tiles(n) + (n + kSpmmRows - 1) / kSpmmRows));
   L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
   L.Ah = take(sizeof(double) * kNtMax * kNtMax);
   L.Bh = take(sizeof(double) * kNtMax * kNtMax);

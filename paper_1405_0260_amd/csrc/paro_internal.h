@@ -166,6 +166,11 @@ constexpr int vec32_of(int ncols) {
 // Rows per streaming tile.
 constexpr int tile_rows(int ncols, int V) { return kBlock / (ncols / V); }
 
+// Tiles of the CG SpMM: each wavefront computes kSpmmWaveRows rows (its
+// first and last lanes hold the neighbouring rows), kSpmmRows per block.
+constexpr int kSpmmWaveRows = 62;
+constexpr int kSpmmRows = (kBlock / 64) * kSpmmWaveRows;
+
 // Tiles of the chunk-major FP32 CG kernels: kCmRpt rows per thread.
 // Element (row, c) of an FP32 CG vector with vector width V sits at
 // ((c / V) n + row) V + c % V: V-column chunks, each an n x V array.

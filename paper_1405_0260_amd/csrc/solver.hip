@@ -621,48 +621,34 @@ __device__ __forceinline__ double lane_shift(double old, double v) {
 // per-offset element steps, 0 where the neighbour lies outside the box).
 // The lanes of a wavefront hold consecutive rows, so the x - 1 and x + 1
 // neighbours of a row are the x-centred neighbours of the adjacent lanes'
-// rows: only the 7 x-centred ones are loaded, the other 8 arrive by a
-// wavefront shift, and lanes 0 and 63 load their own x - 1, resp. x + 1,
-// neighbours.  Where the shifted value belongs to another grid line (x = 0
-// or x = mx - 1), the coefficient is 0.
+// rows: only the 7 x-centred values are loaded and the other 8 arrive by
+// a wavefront shift (lanes 0 and 63, the wavefront's halo rows, receive
+// no valid shifted values).  Where a shifted value belongs to another
+// grid line (x = 0 or x = mx - 1) its coefficient is 0.
 template <typename T, int V>
 __device__ __forceinline__ void stencil_gather(const T* Pr,
                                                const int (&off)[kStencil],
-                                               int lane,
                                                T (&x)[kStencil][V]) {
-  // Offsets with x = 0 (loaded), x = -1 and x = +1 (shifted), pairwise:
-  // the x = -1 one of plane k is kM[k], centred kM[k] + 1; the x = +1 one
-  // is kP[k], centred kP[k] - 1 (the stencil's ascending order).
-  constexpr int kC[7] = {1, 3, 5, 7, 9, 11, 13};
-  constexpr int kM[4] = {0, 2, 4, 6};
-  constexpr int kP[4] = {8, 10, 12, 14};
+  // Stencil order: the x-centred offset of plane k is 2k + 1; planes
+  // k < 4 have their x - 1 offset at 2k, planes k >= 3 their x + 1 one at
+  // 2k + 2.
 #pragma unroll
-  for (int k = 0; k < 7; ++k) ldv<T, V>(Pr + off[kC[k]], x[kC[k]]);
-  // Edge values: lane 0 holds its x - 1 neighbours, lane 63 its x + 1
-  // ones (plane k in e[k]); the shift leaves them in place on those lanes.
-  T e[4][V];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int u = 0; u < V; ++u) e[k][u] = T(0);
-  if (lane == 0 || lane == 63) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      ldv<T, V>(Pr + (lane == 0 ? off[kM[k]] : off[kP[k]]), e[k]);
-  }
+  for (int k = 0; k < 7; ++k) ldv<T, V>(Pr + off[2 * k + 1], x[2 * k + 1]);
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-      x[kM[k]][u] = lane_shift<false>(e[k][u], x[kM[k] + 1][u]);
-      x[kP[k]][u] = lane_shift<true>(e[k][u], x[kP[k] - 1][u]);
+      x[2 * k][u] = lane_shift<false>(T(0), x[2 * k + 1][u]);
+      x[2 * k + 8][u] = lane_shift<true>(T(0), x[2 * k + 7][u]);
     }
 }
 
-// Q = A P on the active chunks of SpMM tile t (kBlock rows, one per
-// thread); per (column, tile) p . q.  The row's 15 coefficients stay in
-// registers across the chunks; each chunk ends with one wavefront
-// reduction of the thread's V products.
+// Q = A P on the active chunks of SpMM tile t (kSpmmRows rows: each
+// wavefront computes 62 consecutive rows on lanes 1..62, its lanes 0 and
+// 63 holding the rows just before and after, whose x-centred neighbours
+// the computing lanes need); per (column, tile) p . q.  The row's 15
+// coefficients stay in registers across the chunks; each chunk ends with
+// one wavefront reduction of the thread's V products.
 template <typename T, int V>
 __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
                                              unsigned long long amask,
@@ -672,10 +658,11 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
   const long long n = d.n;
   const int mx = d.mx, my = d.my, mz = d.mz, ncols = d.ncols;
   const int cpr = ncols / V;
-  const long long row = t * kBlock + tid;
-  const bool valid = row < n;
-  const long long rr = valid ? row : n - 1;
   const int lane = tid & 63;
+  const long long row =
+      t * kSpmmRows + (long long)(tid >> 6) * kSpmmWaveRows + lane - 1;
+  const bool valid = lane >= 1 && lane <= kSpmmWaveRows && row < n;
+  const long long rr = row < 0 ? 0 : (row < n ? row : n - 1);
   const unsigned ur = (unsigned)rr;
   const unsigned uq = ur / (unsigned)mx;
   const int i = (int)(ur - uq * (unsigned)mx);
@@ -697,7 +684,7 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
     if (!chunk_in_mask<V>(amask, ch)) continue;
     const T* Pr = vs.P + ((size_t)ch * n + rr) * V;
     T x[kStencil][V];
-    stencil_gather<T, V>(Pr, off, lane, x);
+    stencil_gather<T, V>(Pr, off, x);
     T q[V], self[V];
 #pragma unroll
     for (int u = 0; u < V; ++u) q[u] = T(0);
