@@ -266,7 +266,9 @@ void desc_init(Problem& p) {
   d.cgn = d.ntc;
   d.cgstride = (long long)p.Nt * d.ntc;
   d.pqp = p.cpart + 2 * d.cgstride;
-  d.pqn = (int)((p.n + kSpmmRows - 1) / kSpmmRows);
+  d.spt = (int)spmm_tiles(p.n);
+  d.spg = spmm_seg_tiles(p.n);
+  d.pqn = (d.spt + d.spg - 1) / d.spg;
   d.part = p.part;
   d.gpart = p.gpart;
   d.Ah = p.Ah;
@@ -310,6 +312,7 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
   }
   L.nt16 = (L.maxcols + 15) / 16;
   for (int i = 0; i < n; ++i) L.maxkz = std::max(L.maxkz, tab[i].kz);
+  for (int i = 0; i < n; ++i) L.seg |= tab[i].spg > 1 ? 1 : 0;
   L.v64u = n > 0 ? tab[0].v64 : 0;
   L.v32u = n > 0 ? tab[0].v32 : 0;
   for (int i = 1; i < n; ++i) {
@@ -846,7 +849,7 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.X32 = f32 ? take(sizeof(float) * blk) : 0;
   L.part = take(sizeof(double) * 3 * (size_t)kGridMax * kNtMax);
   L.cpart = take(sizeof(double) * (size_t)Nt *
-                 (2 * cm_tiles(n) + (n + kSpmmRows - 1) / kSpmmRows));
+                 (2 * cm_tiles(n) + spmm_tiles(n)));
   L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
   L.Ah = take(sizeof(double) * kNtMax * kNtMax);
   L.Bh = take(sizeof(double) * kNtMax * kNtMax);

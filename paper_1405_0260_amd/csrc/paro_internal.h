@@ -135,7 +135,8 @@ struct Desc {
   int cgn;                // partials per column of r.z and r.r (CG)
   long long cgstride;     // ... the stride between the two quantities
   double* cgp;            // ... and where they are (part, or cpart)
-  int pqn;                // partials per column of p.q (CG SpMM)
+  int pqn;                // partials per column of p.q (CG SpMM segments)
+  int spt, spg;           // SpMM tiles, and tiles per p.q segment
   double* pqp;            // ... and where they are
   double* Y1;             // component SpMM / Gram operands
   double* Y2;
@@ -170,6 +171,17 @@ constexpr int tile_rows(int ncols, int V) { return kBlock / (ncols / V); }
 // first and last lanes hold the neighbouring rows), kSpmmRows per block.
 constexpr int kSpmmWaveRows = 62;
 constexpr int kSpmmRows = (kBlock / 64) * kSpmmWaveRows;
+// The SpMM's p.q partials: one per segment of spg tiles (tiles g, g +
+// pqn, ...), with spg (a function of n alone) making at most kSpmmSegMax
+// segments, so the per-column reductions that read them stay one round of
+// loads.
+constexpr int kSpmmSegMax = 2048;
+__host__ __device__ constexpr long long spmm_tiles(long long n) {
+  return (n + kSpmmRows - 1) / kSpmmRows;
+}
+__host__ __device__ constexpr int spmm_seg_tiles(long long n) {
+  return (int)((spmm_tiles(n) + kSpmmSegMax - 1) / kSpmmSegMax);
+}
 
 // Tiles of the chunk-major FP32 CG kernels: kCmRpt rows per thread.
 // Element (row, c) of an FP32 CG vector with vector width V sits at
@@ -194,6 +206,7 @@ struct Launch {
   int v64u, v32u;         // common vector width of all problems, or 0
   int nt16_mixed;         // problems differ in ceil(ncols / 16)
   int maxkz;              // most nonlocal projectors of a problem (0: none)
+  int seg;                // some problem has SpMM segments of > 1 tile
 };
 
 // Per-problem step summary for the host (one PollReport per problem).

@@ -649,7 +649,7 @@ __device__ __forceinline__ void stencil_gather(const T* Pr,
 // the computing lanes need); per (column, tile) p . q.  The row's 15
 // coefficients stay in registers across the chunks; each chunk ends with
 // one wavefront reduction of the thread's V products.
-template <typename T, int V>
+template <typename T, int V, bool SEG>
 __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
                                              unsigned long long amask,
                                              double* __restrict__ ws) {
@@ -711,13 +711,41 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
       ws[(tid >> 6) * ncols + ch * V + lane / kGroup] = tot;
   }
   __syncthreads();
-  for (int c = tid; c < ncols; c += kBlock) {
-    if (((amask >> c) & 1) == 0) continue;
-    const double s = ((ws[c] + ws[ncols + c]) + ws[2 * ncols + c]) +
-                     ws[3 * ncols + c];
-    stg(d.pqp + (size_t)c * d.pqn + t, s);
+  // Thread c < ncols: column c's tile sum is the partial (one tile per
+  // segment), or is added to its segment's (kept in ws[4 ncols + c], which
+  // only that thread touches).
+  if (tid < ncols) {
+    const double sum = ((ws[tid] + ws[ncols + tid]) + ws[2 * ncols + tid]) +
+                       ws[3 * ncols + tid];
+    if constexpr (SEG)
+      ws[4 * ncols + tid] += sum;
+    else if ((amask >> tid) & 1)
+      stg(d.pqp + (size_t)tid * d.pqn + t, sum);
   }
   __syncthreads();  // ws is reused by the next tile
+}
+
+// The SpMM over segment g of a problem: tiles g, g + pqn, g + 2 pqn, ...
+// (at most spg of them, in that order; strided, so the blocks' k-th tiles
+// are neighbours and share their stencil halos in L2); one p.q partial per
+// (active column, segment).
+// SEG false: every problem of the launch has one tile per segment (a
+// separate instantiation: the segment loop costs the single-tile kernel
+// registers).  ws: 5 kNtMax doubles.
+template <typename T, int V, bool SEG>
+__device__ __forceinline__ void spmm_cm_segment(const Desc& d, long long g,
+                                                unsigned long long amask,
+                                                double* __restrict__ ws) {
+  if constexpr (!SEG) {
+    spmm_cm_tile<T, V, false>(d, g, amask, ws);
+  } else {
+    const int c = threadIdx.x, ncols = d.ncols;
+    if (c < ncols) ws[4 * ncols + c] = 0.0;
+    for (long long t = g; t < d.spt; t += d.pqn)
+      spmm_cm_tile<T, V, true>(d, t, amask, ws);
+    if (c < ncols && ((amask >> c) & 1))
+      stg(d.pqp + (size_t)c * d.pqn + g, ws[4 * ncols + c]);
+  }
 }
 
 // The CG updates of chunk ch of tile t (kCmRpt rows per thread) in two
@@ -916,10 +944,10 @@ __device__ __forceinline__ void rupd_cm_chunk(const Desc& d, CmUnit un,
 
 // VFIX: the common vector width of the launch's problems, or 0 (each
 // block branches on its problem's width: 4, 2, 1 FP32 or 2, 1 FP64).
-template <typename T, int VFIX>
+template <typename T, int VFIX, bool SEG>
 __global__ void PARO_STREAM_BOUNDS
 spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double ws[4 * kNtMax];
+  __shared__ double ws[5 * kNtMax];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
   const int nact = ldg(&d.cs->n_active[par]);
   const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
@@ -927,7 +955,8 @@ spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   const int lb = blockIdx.x - d.b0;
   const int vw = cm_width<T>(d);
   for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end; w.t += w.step) {
-    PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, amask, ws)))
+    PARO_CM_WIDTH(T, VFIX, vw,
+                  (spmm_cm_segment<T, VV, SEG>(d, w.t, amask, ws)))
   }
 }
 
@@ -1239,7 +1268,7 @@ __global__ void __launch_bounds__(kBlock, 3)
 cg_persistent_kernel(const Desc* __restrict__ D, int nprob, int iters) {
   namespace cgr = cooperative_groups;
   cgr::grid_group grid = cgr::this_grid();
-  __shared__ double ws[4 * kNtMax];
+  __shared__ double ws[5 * kNtMax];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
   const int lb = blockIdx.x - d.b0;
   const int vw = cm_width<T>(d);
@@ -1255,7 +1284,8 @@ cg_persistent_kernel(const Desc* __restrict__ D, int nprob, int iters) {
     if (on)
       for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end;
            w.t += w.step) {
-        PARO_CM_WIDTH(T, VFIX, vw, (spmm_cm_tile<T, VV>(d, w.t, amask, ws)))
+        PARO_CM_WIDTH(T, VFIX, vw,
+                      (spmm_cm_segment<T, VV, true>(d, w.t, amask, ws)))
       }
     grid.sync();
     for (int q = blockIdx.x * (kBlock / 64) + wave; q < npairs; q += nwaves)
@@ -2444,8 +2474,12 @@ static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
   const Desc* D = L.d;
   if constexpr (sizeof(T) == 8)
     if (L.maxkz) zt_launch(L, kZtP, s, t, PARO_ST_CG_SPMM, par);
-  klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W>, dim3(L.blocks),
-          dim3(kBlock), 0, s, D, L.nprob, par);
+  if (L.seg)
+    klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, true>, dim3(L.blocks),
+            dim3(kBlock), 0, s, D, L.nprob, par);
+  else
+    klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, false>, dim3(L.blocks),
+            dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_RUPD, rupd_alpha_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_PUPD, pupd_beta_kernel<T, W>, dim3(L.blocks),
@@ -2472,23 +2506,30 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
 }
 
 // The CG SpMM alone (autotuner timing).
-hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s) {
+template <typename T, bool SEG>
+static void cg_spmm_w(Launch& L, hipStream_t s) {
   const Desc* D = L.d;
   const dim3 g(L.blocks), b(kBlock);
-  if (fp32) {
-    switch (L.v32u) {
-      case 4: hipLaunchKernelGGL((spmm_cm_kernel<float, 4>), g, b, 0, s, D, L.nprob, 0); break;
-      case 2: hipLaunchKernelGGL((spmm_cm_kernel<float, 2>), g, b, 0, s, D, L.nprob, 0); break;
-      case 1: hipLaunchKernelGGL((spmm_cm_kernel<float, 1>), g, b, 0, s, D, L.nprob, 0); break;
-      default: hipLaunchKernelGGL((spmm_cm_kernel<float, 0>), g, b, 0, s, D, L.nprob, 0);
+  const int w = sizeof(T) == 4 ? L.v32u : L.v64u;
+  if constexpr (sizeof(T) == 4)
+    if (w == 4) {
+      hipLaunchKernelGGL((spmm_cm_kernel<T, 4, SEG>), g, b, 0, s, D, L.nprob,
+                         0);
+      return;
     }
-  } else {
-    switch (L.v64u) {
-      case 2: hipLaunchKernelGGL((spmm_cm_kernel<double, 2>), g, b, 0, s, D, L.nprob, 0); break;
-      case 1: hipLaunchKernelGGL((spmm_cm_kernel<double, 1>), g, b, 0, s, D, L.nprob, 0); break;
-      default: hipLaunchKernelGGL((spmm_cm_kernel<double, 0>), g, b, 0, s, D, L.nprob, 0);
-    }
-  }
+  if (w == 2)
+    hipLaunchKernelGGL((spmm_cm_kernel<T, 2, SEG>), g, b, 0, s, D, L.nprob, 0);
+  else if (w == 1)
+    hipLaunchKernelGGL((spmm_cm_kernel<T, 1, SEG>), g, b, 0, s, D, L.nprob, 0);
+  else
+    hipLaunchKernelGGL((spmm_cm_kernel<T, 0, SEG>), g, b, 0, s, D, L.nprob, 0);
+}
+
+hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s) {
+  if (fp32)
+    L.seg ? cg_spmm_w<float, true>(L, s) : cg_spmm_w<float, false>(L, s);
+  else
+    L.seg ? cg_spmm_w<double, true>(L, s) : cg_spmm_w<double, false>(L, s);
   return hipGetLastError();
 }
 
