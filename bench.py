@@ -42,24 +42,23 @@ def solver_code_sha():
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def measured_traffic(kernel_substr):
-    """HBM bytes per launch of the dominant kernel from the committed PMC
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known
-    size), or None when the summary is missing, covers another kernel, or
-    was taken on a different solver source than the one built now."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of a CG kernel from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size), or
+    None when the summary is missing, lacks that kernel, or was taken on a
+    different solver source than the one built now."""
     try:
         text = open(TRAFFIC).read()
         sha = solver_code_sha()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("solver_sha256: ", "traffic_kernel: ",
-                                      "traffic_bytes_per_launch: ")))
+                  if line.startswith(("solver_sha256: ",
+                                      "traffic_bytes_per_launch[")))
     if fields.get("solver_sha256") != sha:
         return None
-    if kernel_substr not in fields.get("traffic_kernel", ""):
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    value = fields.get(f"traffic_bytes_per_launch[{kernel}]")
+    return None if value is None else float(value)
 
 
 def parse():
