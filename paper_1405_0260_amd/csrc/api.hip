@@ -183,6 +183,8 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.P = (double*)at(L.P);
   p.Q = (double*)at(L.Q);
   p.B = L.B ? (double*)at(L.B) : nullptr;
+  p.HU = (double*)at(L.HU);
+  p.MU = (double*)at(L.MU);
   p.Xc = L.Xc ? (double*)at(L.Xc) : nullptr;
   p.R32 = L.R32 ? (float*)at(L.R32) : nullptr;
   p.P32 = L.P32 ? (float*)at(L.P32) : nullptr;
@@ -255,6 +257,9 @@ void desc_init(Problem& p) {
   d.P = p.P;
   d.Q = p.Q;
   d.B = p.B;
+  d.HU = p.HU;
+  d.MU = p.MU;
+  d.use_hu = 0;
   d.Xc = p.Xc;
   d.R32 = p.R32;
   d.P32 = p.P32;
@@ -640,8 +645,14 @@ int read_reports(Ctx& c, std::vector<PollReport>& out, hipStream_t s) {
 // descriptors' U0 = X = Uout (the orbitals, in place) and lam are set.
 // Per-problem status goes into `reps` (if given).  `single`: a CG
 // breakdown stops before the projection and is returned.
-int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single) {
+// trust: U (and lambda) of every problem are the outputs of its last
+// rotation, with the operator unchanged since (the library's own step
+// loops), so the start takes A_s U = HU - s MU and M U from that rotation
+// instead of applying the operators again.
+int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
+                bool trust) {
   const double t0 = now_s();
+  for (Desc& d : c.tab) d.use_hu = trust ? 1 : 0;
   int rc = upload(c, s);
   if (rc) return rc;
   HIP_OR_FAIL(launch_pcg_start(c.L, s, c.timing));
@@ -842,6 +853,8 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   L.P = take(sizeof(double) * blk);
   L.Q = take(sizeof(double) * blk);
   L.B = f32 ? take(sizeof(double) * blk) : 0;
+  L.HU = take(sizeof(double) * blk);
+  L.MU = take(sizeof(double) * blk);
   L.Xc = f32 ? 0 : take(sizeof(double) * blk);
   L.R32 = f32 ? take(sizeof(float) * blk) : 0;
   L.P32 = f32 ? take(sizeof(float) * blk) : 0;
@@ -1016,8 +1029,8 @@ int paro_init(paro_problem* h, const double* d_U0, double* d_lambda,
   return init_tables(c, s);
 }
 
-int paro_step(paro_problem* h, double* d_lambda, double* d_U, void* stream,
-              paro_report_t* report) {
+static int step_impl(paro_problem* h, double* d_lambda, double* d_U,
+                     void* stream, paro_report_t* report, bool trust) {
   try {
     if (!h || !d_lambda || !d_U)
       return fail(PARO_EINVAL, "NULL argument to paro_step");
@@ -1031,10 +1044,15 @@ int paro_step(paro_problem* h, double* d_lambda, double* d_U, void* stream,
     d.U0 = d.X = d.Uout = d_U;
     d.lam = d_lambda;
     d.have_old = 1;
-    return step_tables(c, s, report, true);
+    return step_tables(c, s, report, true, trust);
   } catch (...) {
     return fail(PARO_EDEVICE, "unexpected exception in paro_step");
   }
+}
+
+int paro_step(paro_problem* h, double* d_lambda, double* d_U, void* stream,
+              paro_report_t* report) {
+  return step_impl(h, d_lambda, d_U, stream, report, false);
 }
 
 int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
@@ -1057,7 +1075,7 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
   int code = PARO_ENOCONV;
   for (int k = 0; k < p.opts.max_steps; ++k) {
     paro_report_t r{};
-    rc = paro_step(h, d_lambda, d_U, s, &r);
+    rc = step_impl(h, d_lambda, d_U, s, &r, true);  // U from the last step
     acc.steps += 1;
     acc.pcg_iters += r.pcg_iters;
     acc.refinements += r.refinements;
@@ -1158,9 +1176,13 @@ int paro_batch_init(paro_problem* const* probs, int32_t count,
 // Batch steps keep their CG prediction between calls of one thread.
 static thread_local int g_batch_predict[5] = {0, 0, 0, 0, 0};
 
-int paro_batch_step(paro_problem* const* probs, int32_t count,
+}  // extern "C"
+
+namespace paro {
+int batch_step_impl(paro_problem* const* probs, int32_t count,
                     double* const* d_lambda, double* const* d_U, void* d_ws,
-                    size_t bytes, void* stream, paro_report_t* reports) {
+                    size_t bytes, void* stream, paro_report_t* reports,
+                    bool trust) {
   try {
     if (!d_lambda || !d_U) return fail(PARO_EINVAL, "NULL arrays");
     Ctx c;
@@ -1176,10 +1198,20 @@ int paro_batch_step(paro_problem* const* probs, int32_t count,
       d.lam = d_lambda[i];
       d.have_old = 1;
     }
-    return step_tables(c, s, reports, false);
+    return step_tables(c, s, reports, false, trust);
   } catch (...) {
     return fail(PARO_EDEVICE, "unexpected exception in paro_batch_step");
   }
+}
+}  // namespace paro
+
+extern "C" {
+
+int paro_batch_step(paro_problem* const* probs, int32_t count,
+                    double* const* d_lambda, double* const* d_U, void* d_ws,
+                    size_t bytes, void* stream, paro_report_t* reports) {
+  return paro::batch_step_impl(probs, count, d_lambda, d_U, d_ws, bytes,
+                               stream, reports, false);
 }
 
 int paro_batch_solve(paro_problem* const* probs, int32_t count,
@@ -1222,8 +1254,8 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
       us.push_back(d_U[i]);
     }
     rs.assign(active.size(), paro_report_t{});
-    rc = paro_batch_step(ps.data(), (int)ps.size(), ls.data(), us.data(),
-                         d_ws, bytes, stream, rs.data());
+    rc = batch_step_impl(ps.data(), (int)ps.size(), ls.data(), us.data(),
+                         d_ws, bytes, stream, rs.data(), true);
     if (rc) return rc;
     std::vector<int> still;
     for (size_t k = 0; k < active.size(); ++k) {

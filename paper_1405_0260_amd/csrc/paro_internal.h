@@ -126,6 +126,9 @@ struct Desc {
   double* P;
   double* Q;
   double* B;              // stored right-hand sides (refinement), or null
+  double* HU;             // H U and M U of the last rotation (row-major),
+  double* MU;             // written by every rotation
+  int use_hu;             // the start forms A_s U from them (U, H unchanged)
   double* Xc;             // FP64 CG iterate, chunk-major (FP64 mode only)
   float* R32;             // FP32 CG vectors, chunk-major (see cm_index)
   float* P32;
@@ -247,6 +250,7 @@ struct Problem {
   double* P;
   double* Q;
   double* B;              // right-hand sides (refinement mode)
+  double *HU, *MU;        // H U, M U of the last rotation
   double* Xc;             // chunk-major FP64 CG iterate (FP64 mode)
   float* R32;             // n x Nt blocks (FP32 inner solves, chunk-major)
   float* P32;
@@ -289,7 +293,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 struct Layout {
   size_t rowptr, col, valA, valM, valA32, dinv, dinv32, diagA, diagM,
       diagA32;
-  size_t X, R, P, Q, B, Xc, R32, P32, Q32, X32;
+  size_t X, R, P, Q, B, HU, MU, Xc, R32, P32, Q32, X32;
   size_t part, cpart, gpart, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
   size_t desc, clus;
@@ -297,6 +301,13 @@ struct Layout {
 };
 
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision);
+// paro_batch_step; trust: U and lambda of every problem come unchanged
+// from its last rotation under the same operator (the library's own
+// loops), so the start reuses that rotation's H U and M U.
+int batch_step_impl(paro_problem* const* probs, int32_t count,
+                    double* const* d_lambda, double* const* d_U, void* d_ws,
+                    size_t bytes, void* stream, paro_report_t* reports,
+                    bool trust);
 // Record `msg` as this thread's last error (paro_last_error); returns code.
 int set_error(int code, const char* msg);
 int64_t kuhn_nnz(int mx, int my, int mz);

@@ -284,9 +284,10 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
         us.push_back(r->d_U);
       }
       std::vector<paro_report_t> reps(ps.size());
-      const int rc = paro_batch_step(ps.data(), (int)ps.size(), ls.data(),
-                                     us.data(), s->batch_ws, s->batch_bytes,
-                                     s->stream, reps.data());
+      // The served problems' U and lambda come from their last rotation.
+      const int rc = paro::batch_step_impl(
+          ps.data(), (int)ps.size(), ls.data(), us.data(), s->batch_ws,
+          s->batch_bytes, s->stream, reps.data(), true);
       if (rc != PARO_OK) return rc;
       std::vector<Request*> still;
       for (size_t k = 0; k < s->active.size(); ++k) {

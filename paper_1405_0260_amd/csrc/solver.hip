@@ -1355,7 +1355,9 @@ cm_unpack_kernel(const Desc* __restrict__ D, int nprob) {
 //   b = (lam - s) M u0  (or the given Bin),  x0 = u0,
 //   r = b - A_s x0,  p = D^-1 r;  partials ||b||^2, r.z, ||r||^2.
 // ------------------------------------------------------------------------
-template <int V>
+// HU: A_s u and M u come from the last rotation (d.HU, d.MU: U, lambda
+// and the operator unchanged since), no operator application.
+template <int V, bool HU>
 __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
     double* __restrict__ red) {
   const Geo g = geo_of<V>(d, vb);
@@ -1388,18 +1390,28 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
        w.t += w.step) {
     const long long r0 = w.t * g.tr;
     const int rows = (int)min((long long)g.tr, d.n - r0);
-    stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
-                                wb);
+    if constexpr (!HU)
+      stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
+                                  wb);
     if (g.lr >= rows) continue;
     const long long row = r0 + g.lr;
-    double au[V], mu[V], u[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
-    stencil_product<double, double, V, true, 8, true>(
-        wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
-        g.ch * V, au, mu, u);
-    if (d.kz) nl_add<V>(d, row, g.ch * V, au);  // A u += Z (Z^T u)
     const size_t o = (size_t)row * ncols + g.ch * V;
+    double au[V], mu[V], u[V];
+    if constexpr (HU) {
+      double hu[V];
+      ldv<double, V>(U + o, u);
+      ldv<double, V>(d.HU + o, hu);
+      ldv<double, V>(d.MU + o, mu);
+#pragma unroll
+      for (int v = 0; v < V; ++v) au[v] = fma(-d.sigma, mu[v], hu[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
+      stencil_product<double, double, V, true, 8, true>(
+          wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
+          g.ch * V, au, mu, u);
+      if (d.kz) nl_add<V>(d, row, g.ch * V, au);  // A u += Z (Z^T u)
+    }
     double b[V], r[V], p[V];
     if (d.Bin) {
       ldv<double, V>(d.Bin + o, b);
@@ -1452,7 +1464,9 @@ template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
 pcg_start_kernel(const Desc* __restrict__ D, int nprob) {
   __shared__ double red[3 * kBlock * (VFIX ? VFIX : 2)];
-  PARO_VB_LOOP64(D, nprob, VFIX, (pcg_start_body<VV>(d, vb, red)))
+  PARO_VB_LOOP64(D, nprob, VFIX,
+                 (d.use_hu ? pcg_start_body<VV, true>(d, vb, red)
+                           : pcg_start_body<VV, false>(d, vb, red)))
 }
 
 // Per-column start state: ||b||^2, r.z, ||r||^2, the stopping threshold
@@ -2265,9 +2279,10 @@ geneig_batch_kernel(const Desc* __restrict__ D) {
 }
 
 // ------------------------------------------------------------------------
-// Rotation U = W C with HU = (HW) C, MU = (MW) C formed on the fly for the
-// residual norms ||HU_i - theta_i MU_i||, ||MU_i|| (Step 4 output and the
-// stopping test).  Rows of W, HW, MW are staged through LDS; W may be the
+// Rotation U = W C with HU = (HW) C, MU = (MW) C, for the residual norms
+// ||HU_i - theta_i MU_i||, ||MU_i|| (Step 4 output and the stopping test)
+// and stored for the next step's start (its right-hand side and residual
+// need M U and A_s U = HU - s MU).  Rows of W, HW, MW are staged through LDS; W may be the
 // output itself (each tile is read before it is written).
 // ------------------------------------------------------------------------
 template <int V>
@@ -2325,7 +2340,10 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
           mu[v] = fma(mk, c, mu[v]);
         }
       }
-      stv<double, V>(U + base + (size_t)g.lr * ncols + g.ch * V, u);
+      const size_t o = base + (size_t)g.lr * ncols + g.ch * V;
+      stv<double, V>(U + o, u);
+      stv<double, V>(d.HU + o, hu);  // for the next start
+      stv<double, V>(d.MU + o, mu);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double r = hu[v] - th[v] * mu[v];
