@@ -887,6 +887,7 @@ __device__ __forceinline__ void pupd_cm_finish(const Desc& d, long long t,
     const Desc& d = D[owner(D, nprob, blockIdx.x, false)];                 \
     const int nact_ = ldg(&d.cs->n_active[par]);                           \
     const unsigned long long amask = active_mask(d.cs->act[par], d.ncols); \
+    (void)amask;                                                           \
     if (nact_ == 0) return;                                                \
     const int lb_ = blockIdx.x - d.b0;                                     \
     const int vw_ = VFIX ? VFIX : cm_width<T>(d);                          \
@@ -1834,29 +1835,46 @@ __device__ __forceinline__ void gram_body(const Desc& d, int vb,
   const long long nw = (long long)nb * 4;
   const long long per = (nsteps + nw - 1) / nw;
   const long long s0 = gw * per, s1 = min(nsteps, s0 + per);
-  for (long long st = s0; st < s1; ++st) {
-    const long long row = st * 4 + lk;
-    double a[NT16], y1[NT16], y2[NT16];
+  // GU steps per group: their loads (unconditional, clamped addresses;
+  // masked values are 0) are in flight together before the MFMAs, which
+  // run step by step in the same order as one step at a time.
+  constexpr int GU = NT16 <= 1 ? 8 : (NT16 == 2 ? 4 : 2);
+  for (long long st0 = s0; st0 < s1; st0 += GU) {
+    double a[GU][NT16], y1[GU][NT16], y2[GU][NT16];
 #pragma unroll
-    for (int I = 0; I < NT16; ++I) {
-      const int c = I * 16 + li;
-      const bool ok = row < n && c < ncols;
-      const size_t o = (size_t)row * ncols + c;
-      a[I] = ok ? ldg(W + o) : 0.0;
-      y1[I] = ok ? ldg(Y1 + o) : 0.0;
-      y2[I] = (ok && SYM) ? ldg(Y2 + o) : 0.0;
-    }
-    int q = 0;
+    for (int u = 0; u < GU; ++u) {
+      const long long row = (st0 + u) * 4 + lk;
+      const bool rok = st0 + u < s1 && row < n;
 #pragma unroll
-    for (int I = 0; I < NT16; ++I)
-#pragma unroll
-      for (int J = SYM ? I : 0; J < NT16; ++J, ++q) {
-        acc[0][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], y1[J],
-                                                         acc[0][q], 0, 0, 0);
-        if (SYM)
-          acc[NG - 1][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-              a[I], y2[J], acc[NG - 1][q], 0, 0, 0);
+      for (int I = 0; I < NT16; ++I) {
+        const int c = I * 16 + li;
+        const bool ok = rok && c < ncols;
+        const size_t o = ok ? (size_t)row * ncols + c : 0;
+        const double va = ldg(W + o), vy1 = ldg(Y1 + o);
+        a[u][I] = ok ? va : 0.0;
+        y1[u][I] = ok ? vy1 : 0.0;
+        if (SYM) {
+          const double vy2 = ldg(Y2 + o);
+          y2[u][I] = ok ? vy2 : 0.0;
+        } else {
+          y2[u][I] = 0.0;
+        }
       }
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      int q = 0;
+#pragma unroll
+      for (int I = 0; I < NT16; ++I)
+#pragma unroll
+        for (int J = SYM ? I : 0; J < NT16; ++J, ++q) {
+          acc[0][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              a[u][I], y1[u][J], acc[0][q], 0, 0, 0);
+          if (SYM)
+            acc[NG - 1][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                a[u][I], y2[u][J], acc[NG - 1][q], 0, 0, 0);
+        }
+    }
   }
   // D layout (measured): lane l, element r holds row l/16 + 4r, column
   // l%16.  The four wavefronts' tiles are added in wave order.
