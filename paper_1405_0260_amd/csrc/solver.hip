@@ -2329,18 +2329,43 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
   double acc[2][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
-  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-       w.t += w.step) {
+  // A tile's rows of W, HW, MW are loaded into registers (KR values of
+  // each per thread) one tile ahead: the loads of the next tile are in
+  // flight while this one is computed (they precede this tile's stores,
+  // which they never overlap, also when U is W).
+  constexpr int KR = V;  // tr * ncols = kBlock * V
+  double rw[KR], rh[KR], rm[KR];
+  auto fetch = [&](long long t) {
+    const long long r0 = t * g.tr;
+    const int cnt = (int)min((long long)g.tr, d.n - r0) * ncols;
+    const size_t base = (size_t)r0 * ncols;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int e = tid + k * kBlock;
+      const size_t o = base + (e < cnt ? e : 0);
+      rw[k] = ldg(W + o);
+      rh[k] = ldg(HW + o);
+      rm[k] = ldg(MW + o);
+    }
+  };
+  TileWalk w = tile_walk(g.ntiles, g.lb, g.nb);
+  if (w.t < w.end) fetch(w.t);
+  for (; w.t < w.end; w.t += w.step) {
     const long long r0 = w.t * g.tr;
     const int rows = (int)min((long long)g.tr, d.n - r0);
     __syncthreads();
     const size_t base = (size_t)r0 * ncols;
-    for (int e = tid; e < rows * ncols; e += kBlock) {
-      sW[e] = ldg(W + base + e);
-      sH[e] = ldg(HW + base + e);
-      sM[e] = ldg(MW + base + e);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int e = tid + k * kBlock;
+      if (e < rows * ncols) {
+        sW[e] = rw[k];
+        sH[e] = rh[k];
+        sM[e] = rm[k];
+      }
     }
     __syncthreads();
+    if (w.t + w.step < w.end) fetch(w.t + w.step);
     if (g.lr < g.tr && g.lr < rows) {
       double u[V], hu[V], mu[V];
 #pragma unroll
