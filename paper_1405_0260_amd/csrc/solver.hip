@@ -876,8 +876,31 @@ __device__ __forceinline__ void pupd_cm_finish(const Desc& d, long long t,
     else PARO_VB_CASE(1, BODY)                                             \
   }
 
+// Chunks (of vw columns) with an active column, as a mask over chunks.
+__device__ __forceinline__ unsigned long long chunk_mask(
+    unsigned long long amask, int cpr, int vw) {
+  const unsigned long long low = (1ull << vw) - 1;
+  unsigned long long m = 0;
+  for (int ch = 0; ch < cpr; ++ch)
+    if ((amask >> (ch * vw)) & low) m |= 1ull << ch;
+  return m;
+}
+// Unit u of the active units: tile u / nac and the (u % nac)-th chunk set
+// in cm (nac of them).
+__device__ __forceinline__ CmUnit cm_unit_active(long long u, int nac,
+                                                 unsigned long long cm) {
+  CmUnit r;
+  r.t = u / nac;
+  int k = (int)(u - r.t * nac);
+  for (; k > 0; --k) cm &= cm - 1;  // drop the k lowest chunks
+  r.ch = __builtin_ctzll(cm);
+  return r;
+}
+
 // The units of the real block that runs this code, in its problem `d`
-// (owner of blockIdx.x), with VV (constexpr) the problem's FP32 width.
+// (owner of blockIdx.x), with VV (constexpr) the problem's FP32 width:
+// (tile, chunk) pairs over the chunks with an active column only, so the
+// blocks share the live work evenly.
 // Launches queued after convergence (no active column) do nothing: the
 // column flags may be stale then.
 // `amask` (bit c: column c active at parity par) is loaded once, with the
@@ -892,9 +915,11 @@ __device__ __forceinline__ void pupd_cm_finish(const Desc& d, long long t,
     const int lb_ = blockIdx.x - d.b0;                                     \
     const int vw_ = VFIX ? VFIX : cm_width<T>(d);                          \
     const int cpr_ = d.ncols / vw_;                                        \
-    for (TileWalk w_ = tile_walk((long long)d.ntc * cpr_, lb_, d.nb);      \
+    const unsigned long long cm_ = chunk_mask(amask, cpr_, vw_);           \
+    const int nac_ = __popcll(cm_);                                        \
+    for (TileWalk w_ = tile_walk((long long)d.ntc * nac_, lb_, d.nb);      \
          w_.t < w_.end; w_.t += w_.step) {                                 \
-      const CmUnit un = cm_unit(w_.t, cpr_);                               \
+      const CmUnit un = cm_unit_active(w_.t, nac_, cm_);                   \
       PARO_CM_WIDTH(T, VFIX, vw_, BODY)                                    \
     }                                                                      \
   }
