@@ -1,0 +1,91 @@
+"""Host logic of bench.py (no GPU): the algorithmic byte model of the CG
+kernels, the rates derived from a timing record, the guard that ties a
+committed traffic summary to the solver source it was measured on, and the
+one-GPU contract of the command line."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_algorithmic_bytes_per_kernel():
+    n, nnz = 1000, 14000
+    # SpMM: the CSR pass (values + column indices + row pointers), then
+    # read P and write Q per active column.
+    assert bench.algorithmic_bytes("cg_spmm", n, nnz, 4, 4, 4) == (
+        nnz * 8 + 4 * (n + 1), 2 * n * 4)
+    assert bench.algorithmic_bytes("cg_spmm", n, nnz, 8, 8, 8) == (
+        nnz * 12 + 4 * (n + 1), 2 * n * 8)
+    # r-update: D^-1 once; R, Q read and R written per column.
+    assert bench.algorithmic_bytes("cg_rupd", n, nnz, 4, 4, 4) == (
+        n * 4, 3 * n * 4)
+    # p-update: D^-1 once; X, P, R read and X, P written per column.
+    assert bench.algorithmic_bytes("cg_pupd", n, nnz, 8, 8, 8) == (
+        n * 8, 5 * n * 8)
+    # The stencil format: 15 coefficients per row, no indices.
+    assert bench.own_format_bytes("cg_spmm", n, 4, 4, 4) == (
+        15 * n * 4, 2 * n * 4)
+    with pytest.raises(KeyError):
+        bench.algorithmic_bytes("gram", n, nnz, 8, 8, 8)
+
+
+def test_stage_rates_from_a_timing_record():
+    n, nnz = 2000, 28000
+    td = {"cg_iters": 10, "cg_col_iters": 30,
+          "stages": {"cg_spmm": {"ms": 0.5, "launches": 10},
+                     "cg_rupd": {"ms": 0.25, "launches": 10},
+                     "cg_pupd": {"ms": 0.0, "launches": 0}}}
+    stages, it_bytes = bench.cg_stage_rates(td, n, nnz, 4)
+    assert set(stages) == {"cg_spmm", "cg_rupd"}
+    spmm = (nnz * 8 + 4 * (n + 1)) * 10 + 2 * n * 4 * 30
+    rupd = n * 4 * 10 + 3 * n * 4 * 30
+    assert it_bytes == spmm + rupd
+    assert stages["cg_spmm"]["bytes_per_launch"] == spmm / 10
+    assert abs(stages["cg_spmm"]["gbs"] - spmm / 0.5e-3 / 1e9) < 1e-9
+    assert abs(stages["cg_rupd"]["us_per_launch"] - 25.0) < 1e-12
+
+
+def _summary(sha, lines):
+    return "\n".join([f"solver_sha256: {sha}", ""] + lines) + "\n"
+
+
+def test_traffic_summary_is_tied_to_the_source(tmp_path, monkeypatch):
+    src = tmp_path / "solver.hip"
+    src.write_text("int a;  // one\n\n/* block\ncomment */ int b;\n")
+    monkeypatch.setattr(bench, "SOLVER_SRC", str(src))
+    sha = bench.solver_code_sha()
+    # Comments and blank lines do not change the fingerprint ...
+    src.write_text("int a;  // two\n/* other */ int b;\n")
+    assert bench.solver_code_sha() == sha
+    # ... code does.
+    src.write_text("int a; int b;\n")
+    assert bench.solver_code_sha() != sha
+    src.write_text("int a;  // one\n\n/* block\ncomment */ int b;\n")
+
+    traffic = tmp_path / "traffic.md"
+    monkeypatch.setattr(bench, "TRAFFIC", str(traffic))
+    traffic.write_text(_summary(sha, [
+        "traffic_bytes_per_launch[spmm_cm_kernel]: 1234",
+        "traffic_bytes_per_launch[pupd_beta_kernel]: 5678"]))
+    assert bench.measured_traffic("spmm_cm_kernel") == 1234.0
+    assert bench.measured_traffic("pupd_beta_kernel") == 5678.0
+    assert bench.measured_traffic("rupd_alpha_kernel") is None
+    traffic.write_text(_summary("0" * 64, [
+        "traffic_bytes_per_launch[spmm_cm_kernel]: 1234"]))
+    assert bench.measured_traffic("spmm_cm_kernel") is None
+    os.remove(traffic)
+    assert bench.measured_traffic("spmm_cm_kernel") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
