@@ -75,7 +75,8 @@ typedef struct paro_opts {
   double resid_tol;       /* and max_{i<N} ||H u - l M u|| / (scale ||M u||) */
   double pcg_rtol;        /* source solves: ||b - A w|| <= rtol ||b||        */
   double inner_rtol;      /* FP32 inner solves: residual reduction per pass
-                             (never below what pcg_rtol needs)             */
+                             (a pass stops at 0.8 pcg_rtol ||b|| at the
+                             lowest; the FP64 residual decides)          */
 } paro_opts_t;
 
 typedef struct paro_report {
