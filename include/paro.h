@@ -147,11 +147,16 @@ int paro_init(paro_problem* p, const double* d_U0, double* d_lambda,
 int paro_step(paro_problem* p, double* d_lambda, double* d_U, void* stream,
               paro_report_t* report);
 
-/* Whole solve: paro_init from d_U0, then paro_step until both tolerances
+/* Whole solve: paro_init from d_U0, then ParO steps until both tolerances
  * hold for the N requested pairs or opts.max_steps steps were taken.
  * d_lambda (Nt) and d_U (n_dof x Nt) receive the final Ritz pairs (the
  * first N are the answer).  Returns PARO_OK, or PARO_ENOCONV if max_steps
- * was reached first (outputs and report are still filled).  Synchronous. */
+ * was reached first (outputs and report are still filled).  Synchronous.
+ * Its steps are paro_step's, except that each takes M u and H u from the
+ * previous step's rotation (which stores them in the workspace) instead
+ * of applying the operators again, which a public paro_step cannot do
+ * since the caller may change U between calls; the results agree up to
+ * rounding.  paro_batch_solve and the server do the same. */
 int paro_solve(paro_problem* p, const double* d_U0, double* d_lambda,
                double* d_U, void* stream, paro_report_t* report);
 
