@@ -231,3 +231,25 @@ def test_errors_are_reported():
     pb.paro_init(prob, gu.to_dev(w.U0()), lam, U)
     rep = pb.paro_step(prob, lam, U)
     assert rep.status == pb.PARO_ENOCONV
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_solve_loop_matches_public_steps(precision):
+    """paro_solve's steps take M u and H u from the previous rotation
+    instead of applying the operators; public paro_step calls apply them.
+    Both must give the same iterates up to rounding, step for step."""
+    w = inputs.molecule(nc=14, N=6, m=2, lo=-6.0, hi=6.0)
+    steps = 12
+    # lambda_tol = 0: paro_solve runs exactly max_steps steps.
+    prob_a = gu.workload_problem(w, precision=precision, max_steps=steps,
+                                 lambda_tol=0.0, pcg_rtol=1e-11)
+    lam_a, U_a, rep_a = gu.solve(prob_a, w.U0())
+    assert rep_a.steps == steps
+    prob_b = gu.workload_problem(w, precision=precision, pcg_rtol=1e-11)
+    hist, U_b, reps = run_steps(prob_b, w.U0(), steps)
+    lam_b = hist[-1]
+    # The two starts differ by rounding; the source solves (to 1e-11)
+    # carry that into W at the solve tolerance, which bounds the change.
+    scale = np.max(np.abs(lam_b))
+    assert np.max(np.abs(lam_a - lam_b)) <= 1e-9 * scale
+    assert np.max(np.abs(U_a - U_b)) <= 1e-6 * np.max(np.abs(U_b))
