@@ -1417,35 +1417,10 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
-  extern __shared__ unsigned char smem[];
-  double* wa = reinterpret_cast<double*>(smem);
-  double* wb = wa + kStencil * g.tr;
-  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-       w.t += w.step) {
-    const long long r0 = w.t * g.tr;
-    const int rows = (int)min((long long)g.tr, d.n - r0);
-    if constexpr (!HU)
-      stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
-                                  wb);
-    if (g.lr >= rows) continue;
-    const long long row = r0 + g.lr;
+  // The start state of one row from A_s u (au), M u (mu) and u.
+  auto emit = [&](long long row, const double (&u)[V], const double (&au)[V],
+                  const double (&mu)[V], double di) {
     const size_t o = (size_t)row * ncols + g.ch * V;
-    double au[V], mu[V], u[V];
-    if constexpr (HU) {
-      double hu[V];
-      ldv<double, V>(U + o, u);
-      ldv<double, V>(d.HU + o, hu);
-      ldv<double, V>(d.MU + o, mu);
-#pragma unroll
-      for (int v = 0; v < V; ++v) au[v] = fma(-d.sigma, mu[v], hu[v]);
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
-      stencil_product<double, double, V, true, 8, true>(
-          wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
-          g.ch * V, au, mu, u);
-      if (d.kz) nl_add<V>(d, row, g.ch * V, au);  // A u += Z (Z^T u)
-    }
     double b[V], r[V], p[V];
     if (d.Bin) {
       ldv<double, V>(d.Bin + o, b);
@@ -1453,7 +1428,6 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
 #pragma unroll
       for (int v = 0; v < V; ++v) b[v] = sh[v] * mu[v];
     }
-    const double di = ldg(d.dinv + row);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       r[v] = b[v] - au[v];
@@ -1490,6 +1464,60 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
       stv<double, V>(d.P + oc, p);
     }
     if (d.B) stv<double, V>(d.B + o, b);
+  };
+  if constexpr (HU) {
+    // kTU tiles per group, all their loads before any store (which the
+    // compiler cannot move the next tile's loads past); rows past the
+    // end load row n - 1.  Rows are emitted in the same order as one
+    // tile at a time.
+    constexpr int kTU = 4;
+    for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+         w.t += kTU * w.step) {
+      double u[kTU][V], hu[kTU][V], mu[kTU][V], di[kTU];
+      bool ok[kTU];
+      long long rowk[kTU];
+#pragma unroll
+      for (int k = 0; k < kTU; ++k) {
+        const long long t = w.t + k * w.step;
+        const long long r0 = t * g.tr;
+        ok[k] = t < w.end && g.lr < min((long long)g.tr, d.n - r0);
+        rowk[k] = ok[k] ? r0 + g.lr : d.n - 1;
+        const size_t o = (size_t)rowk[k] * ncols + g.ch * V;
+        ldv<double, V>(U + o, u[k]);
+        ldv<double, V>(d.HU + o, hu[k]);
+        ldv<double, V>(d.MU + o, mu[k]);
+        di[k] = ldg(d.dinv + rowk[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kTU; ++k) {
+        if (!ok[k]) continue;
+        double au[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) au[v] = fma(-d.sigma, mu[k][v], hu[k][v]);
+        emit(rowk[k], u[k], au, mu[k], di[k]);
+      }
+    }
+  } else {
+    extern __shared__ unsigned char smem[];
+    double* wa = reinterpret_cast<double*>(smem);
+    double* wb = wa + kStencil * g.tr;
+    for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
+         w.t += w.step) {
+      const long long r0 = w.t * g.tr;
+      const int rows = (int)min((long long)g.tr, d.n - r0);
+      stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
+                                  wb);
+      if (g.lr >= rows) continue;
+      const long long row = r0 + g.lr;
+      double au[V], mu[V], u[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) au[v] = mu[v] = 0.0;
+      stencil_product<double, double, V, true, 8, true>(
+          wa + g.lr, wb + g.lr, g.tr, d.mx, d.my, d.mz, row, U, ncols,
+          g.ch * V, au, mu, u);
+      if (d.kz) nl_add<V>(d, row, g.ch * V, au);  // A u += Z (Z^T u)
+      emit(row, u, au, mu, ldg(d.dinv + row));
+    }
   }
   block_partials<V, 3>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
 }
@@ -1676,18 +1704,31 @@ __device__ __forceinline__ void refine_update_body(const Desc& d, int vb,
     const int c = g.ch * V + v;
     a[v] = c < ncols && cs->oact[c];
   }
+  // kTU tiles per group: all their loads before any store (the stores
+  // could alias the next loads for the compiler, which would otherwise
+  // wait a round trip per tile); rows past the end load row n - 1.
+  constexpr int kTU = 4;
   for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-       w.t += w.step) {
-    const long long row = w.t * g.tr + g.lr;
-    if (row >= d.n) continue;
-    const size_t o = (size_t)row * ncols + g.ch * V;
-    double x[V];
-    float dx[V];
-    ldv<double, V>(d.X + o, x);
-    ldv<float, V>(d.X32 + cm_index(d.n, row, g.ch * V, d.v32), dx);
+       w.t += kTU * w.step) {
+    double x[kTU][V];
+    float dx[kTU][V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) x[v] += a[v] ? (double)dx[v] : 0.0;
-    stv<double, V>(d.X + o, x);
+    for (int k = 0; k < kTU; ++k) {
+      const long long t = w.t + k * w.step;
+      const long long row =
+          t < w.end ? min(t * g.tr + g.lr, d.n - 1) : d.n - 1;
+      ldv<double, V>(d.X + (size_t)row * ncols + g.ch * V, x[k]);
+      ldv<float, V>(d.X32 + cm_index(d.n, row, g.ch * V, d.v32), dx[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kTU; ++k) {
+      const long long t = w.t + k * w.step;
+      const long long row = t * g.tr + g.lr;
+      if (t >= w.end || row >= d.n) continue;
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[k][v] += a[v] ? (double)dx[k][v] : 0.0;
+      stv<double, V>(d.X + (size_t)row * ncols + g.ch * V, x[k]);
+    }
   }
 }
 
