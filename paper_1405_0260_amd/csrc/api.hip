@@ -273,7 +273,7 @@ void desc_init(Problem& p) {
   d.pqp = p.cpart + 2 * d.cgstride;
   d.spt = (int)spmm_tiles(p.n);
   d.spg = spmm_seg_tiles(p.n);
-  d.pqn = (d.spt + d.spg - 1) / d.spg;
+  d.pqn = spmm_segments(p.n);
   d.part = p.part;
   d.gpart = p.gpart;
   d.Ah = p.Ah;

@@ -174,17 +174,36 @@ constexpr int tile_rows(int ncols, int V) { return kBlock / (ncols / V); }
 // first and last lanes hold the neighbouring rows), kSpmmRows per block.
 constexpr int kSpmmWaveRows = 62;
 constexpr int kSpmmRows = (kBlock / 64) * kSpmmWaveRows;
-// The SpMM's p.q partials: one per segment of spg tiles (tiles g, g +
-// pqn, ...), with spg (a function of n alone) making at most kSpmmSegMax
-// segments, so the per-column reductions that read them stay one round of
-// loads.
+// The SpMM's p.q partials, one per (column, segment); the segments are a
+// function of n alone, so a problem's sums do not depend on the launch.
+// Up to kSpmmSegMax tiles a segment is one tile (pqn = spt).  Beyond, the
+// tiles are cut into kSpmmSlabs contiguous slabs of C = ceil(spt /
+// kSpmmSlabs) tiles (the slabs of the XCD-aware tile walk), and segment
+// g = x kSpmmSlabSegs + l holds tiles x C + l, x C + l + kSpmmSlabSegs, ...
+// of slab x: with one segment per block, an XCD's blocks then sweep their
+// slab in one contiguous pass (their k-th tiles are neighbours), so a
+// plane's stencil neighbours are still in that XCD's L2 when the next
+// planes need them.  pqn <= kSpmmSegMax keeps the per-column reductions
+// that read the partials at one round of loads.
 constexpr int kSpmmSegMax = 2048;
+constexpr int kSpmmSlabs = 8;
+constexpr int kSpmmSlabSegs = 128;
 __host__ __device__ constexpr long long spmm_tiles(long long n) {
   return (n + kSpmmRows - 1) / kSpmmRows;
 }
-__host__ __device__ constexpr int spmm_seg_tiles(long long n) {
-  return (int)((spmm_tiles(n) + kSpmmSegMax - 1) / kSpmmSegMax);
+__host__ __device__ constexpr int spmm_segments(long long n) {
+  return spmm_tiles(n) <= kSpmmSegMax ? (int)spmm_tiles(n)
+                                      : kSpmmSlabs * kSpmmSlabSegs;
 }
+// Most tiles in one segment.
+__host__ __device__ constexpr int spmm_seg_tiles(long long n) {
+  return spmm_tiles(n) <= kSpmmSegMax
+             ? 1
+             : (int)(((spmm_tiles(n) + kSpmmSlabs - 1) / kSpmmSlabs +
+                      kSpmmSlabSegs - 1) /
+                     kSpmmSlabSegs);
+}
+static_assert(kSpmmSlabs * kSpmmSlabSegs <= kSpmmSegMax, "segment count");
 
 // Tiles of the chunk-major FP32 CG kernels: kCmRpt rows per thread.
 // Element (row, c) of an FP32 CG vector with vector width V sits at

@@ -725,13 +725,13 @@ __device__ __forceinline__ void spmm_cm_tile(const Desc& d, long long t,
   __syncthreads();  // ws is reused by the next tile
 }
 
-// The SpMM over segment g of a problem: tiles g, g + pqn, g + 2 pqn, ...
-// (at most spg of them, in that order; strided, so the blocks' k-th tiles
-// are neighbours and share their stencil halos in L2); one p.q partial per
-// (active column, segment).
+// The SpMM over segment g of a problem (its tiles in ascending order; one
+// tile, or every kSpmmSlabSegs-th tile of a slab, as spmm_segments
+// defines them); one p.q partial per (active column, segment).
 // SEG false: every problem of the launch has one tile per segment (a
 // separate instantiation: the segment loop costs the single-tile kernel
 // registers).  ws: 5 kNtMax doubles.
+static_assert(kSpmmSlabs == kXcd, "SpMM slabs follow the XCD tile walk");
 template <typename T, int V, bool SEG>
 __device__ __forceinline__ void spmm_cm_segment(const Desc& d, long long g,
                                                 unsigned long long amask,
@@ -741,8 +741,15 @@ __device__ __forceinline__ void spmm_cm_segment(const Desc& d, long long g,
   } else {
     const int c = threadIdx.x, ncols = d.ncols;
     if (c < ncols) ws[4 * ncols + c] = 0.0;
-    for (long long t = g; t < d.spt; t += d.pqn)
-      spmm_cm_tile<T, V, true>(d, t, amask, ws);
+    long long t = g, end = g + 1, step = 1;
+    if (d.pqn < d.spt) {  // slab segments
+      const long long slab = (d.spt + kSpmmSlabs - 1) / kSpmmSlabs;
+      const long long x = g / kSpmmSlabSegs;
+      t = x * slab + (g - x * kSpmmSlabSegs);
+      end = min((long long)d.spt, (x + 1) * slab);
+      step = kSpmmSlabSegs;
+    }
+    for (; t < end; t += step) spmm_cm_tile<T, V, true>(d, t, amask, ws);
     if (c < ncols && ((amask >> c) & 1))
       stg(d.pqp + (size_t)c * d.pqn + g, ws[4 * ncols + c]);
   }

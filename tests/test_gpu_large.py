@@ -1,7 +1,8 @@
 """Source solves on a mesh large enough that the CG SpMM groups its tiles
 into segments: 81^3 = 531,441 rows is more than 2048 tiles of 248 rows, so
-each p.q partial covers two strided tiles (the path the 96^3 workload
-takes).  Checked against the oracle's matrix: the FP64 residual of the
+the tiles form 8 slabs of 268 (the last one 267) and each of the 1024
+p.q partials covers every 128th tile of a slab, two or three tiles (the
+path the 96^3 workload takes).  Checked against the oracle's matrix: the FP64 residual of the
 result, and for FP64 the iteration count of the oracle's own Jacobi-PCG
 on each column (any error in an iterate changes it)."""
 import numpy as np
