@@ -47,3 +47,42 @@ def test_pcg_with_segmented_spmm_partials(large_case, precision):
         for c in range(NCOLS):
             _, k = oparo.jacobi_pcg(A, B[:, c], X0[:, c], dinv, 1e-12, 10000)
             assert abs(its[c] - k) <= 1, (c, its[c], k)
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_batch_with_segmented_member_matches_alone(precision):
+    """A batch of the 81^3 problem (slab segments) and a 12^3 one (one tile
+    per segment): the launch takes the segmented SpMM for both, the small
+    problem alone takes the single-tile instantiation.  Two ParO steps,
+    bitwise equal to the members stepped alone."""
+    import torch
+    ws = [inputs.harmonic(nc=NC, N=2, m=2, seed=31, max_steps=50),
+          inputs.harmonic(nc=12, N=2, m=2, seed=32, max_steps=50)]
+    gu.note(f"large batch: n = {[w.n_dof for w in ws]}, "
+            f"precision = {precision}")
+    probs = [gu.workload_problem(w, precision=precision, pcg_rtol=1e-10)
+             for w in ws]
+    U0s = [gu.to_dev(w.U0()) for w in ws]
+
+    def outs():
+        return ([torch.zeros(p.Nt, dtype=torch.float64, device=gu.device())
+                 for p in probs],
+                [torch.zeros(p.n, p.Nt, dtype=torch.float64,
+                             device=gu.device()) for p in probs])
+
+    batch = pb.Batch(len(probs))
+    lams, Us = outs()
+    pb.paro_batch_init(batch, probs, U0s, lams, Us)
+    lams1, Us1 = outs()
+    for p, U0, l1, U1 in zip(probs, U0s, lams1, Us1):
+        pb.paro_init(p, U0, l1, U1)
+    for step in range(2):
+        reps = pb.paro_batch_step(batch, probs, lams, Us)
+        for k, p in enumerate(probs):
+            r1 = pb.paro_step(p, lams1[k], Us1[k])
+            assert reps[k].status == r1.status == pb.PARO_OK, (step, k)
+            assert reps[k].pcg_iters == r1.pcg_iters, (step, k)
+        torch.cuda.synchronize()
+        for k in range(len(probs)):
+            assert torch.equal(lams[k], lams1[k]), (step, k)
+            assert torch.equal(Us[k], Us1[k]), (step, k)
