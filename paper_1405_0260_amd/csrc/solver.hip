@@ -2095,7 +2095,11 @@ __device__ __forceinline__ void rr_pair(int slot, int round, int nn, int& p,
 }
 
 // The Jacobi rotation (c, s) annihilating S[p][q] (identity when q is the
-// dummy index of an odd n or |S[p][q]| <= skip).
+// dummy index of an odd n or |S[p][q]| <= skip): the smaller angle, tan t =
+// sgn(d) h / (|d| + r) with d = S[q][q] - S[p][p], h = 2 S[p][q] and
+// r = sqrt(d^2 + h^2).  With w = |d| + r, 1 + tan^2 t = 2 r w / w^2, so
+// c = w / sqrt(2 r w) and s = sgn(d) h / sqrt(2 r w): two square roots and
+// one division on the round's critical path, no cancellation.
 __device__ __forceinline__ bool jacobi_cs(const double (*S)[kLd], int p,
                                           int q, int n, double skip,
                                           double& c, double& sn) {
@@ -2104,11 +2108,12 @@ __device__ __forceinline__ bool jacobi_cs(const double (*S)[kLd], int p,
   if (q >= n) return false;
   const double apq = S[p][q];
   if (!(fabs(apq) > skip)) return false;
-  const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
-  const double t =
-      (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
-  sn = t * c;
+  const double d = S[q][q] - S[p][p], h = 2.0 * apq;
+  const double r = sqrt(fma(d, d, h * h));
+  const double w = fabs(d) + r;
+  const double k = 1.0 / sqrt(2.0 * r * w);
+  c = w * k;
+  sn = (d >= 0.0 ? h : -h) * k;
   return true;
 }
 
