@@ -375,6 +375,7 @@ struct Ctx {
   int precision;
   GraphCache* graphs;     // null: launch kernel by kernel
   int last_status = 0;    // status bits seen by the last poll
+  int last_outer = -1;    // refining columns seen by the last poll
   std::vector<Desc> ptab; // table laid out for the persistent CG grid
 };
 
@@ -458,7 +459,7 @@ struct Mailbox {
   char* d = nullptr;  // device address of the same memory
   int seq = 0;
 };
-constexpr size_t kMbPoll = 0;       // poll words: seq, count, iters, status
+constexpr size_t kMbPoll = 0;  // poll words: seq, count, iters, status, refining
 constexpr size_t kMbRepSeq = 64;    // report sequence word
 constexpr size_t kMbReports = 128;  // PollReport[PARO_BATCH_MAX]
 constexpr size_t kMailboxBytes = kMbReports + 32 * PARO_BATCH_MAX;
@@ -516,6 +517,7 @@ int poll(Ctx& c, int which, int out[2], hipStream_t s) {
   out[0] = hw[1];
   out[1] = hw[2];
   c.last_status = hw[3];
+  c.last_outer = hw[4];
   if (c.timing) c.timing->resolve();
   return PARO_OK;
 }
@@ -607,19 +609,33 @@ int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
     return PARO_OK;
   }
   // Pass 0's residual, FP32 start state and inner target come from the
-  // start kernel (x0 = u0).
+  // start kernel (x0 = u0).  Pass 0 needs no poll of its own: the start
+  // kernel makes a column CG-active exactly where it refines, so with no
+  // refining column the CG launches are no-ops, and the CG loop's last
+  // poll also returns the refining count.
   for (int pass = 0;; ++pass) {
-    if (pass > 0)
+    int rc;
+    if (pass > 0) {
       HIP_OR_FAIL(launch_refine_residual(c.L, s, c.timing));
-    int pw[2];
-    int rc = poll(c, 2, pw, s);
-    if (rc) return rc;
-    if (pw[0] == 0) break;
-    if (pass > 200)
-      return fail(PARO_EDEVICE, "refinement loop did not terminate");
-    if (pass > 0) HIP_OR_FAIL(launch_redirect(c.L, s, c.timing));
+      int pw[2];
+      rc = poll(c, 2, pw, s);
+      if (rc) return rc;
+      if (pw[0] == 0) break;
+      if (pass > 200)
+        return fail(PARO_EDEVICE, "refinement loop did not terminate");
+      HIP_OR_FAIL(launch_redirect(c.L, s, c.timing));
+    }
+    c.last_outer = -1;
     rc = run_cg(c, true, s, 1 + (pass < 3 ? pass : 3));
     if (rc) return rc;
+    if (pass == 0) {
+      if (c.last_outer < 0) {  // a CG path that did not poll
+        int pw[2];
+        rc = poll(c, 2, pw, s);
+        if (rc) return rc;
+      }
+      if (c.last_outer == 0) break;
+    }
     HIP_OR_FAIL(launch_refine_update(c.L, s, c.timing));
     if (refinements) ++*refinements;
   }

@@ -1746,28 +1746,32 @@ refine_update_kernel(const Desc* __restrict__ D, int nprob) {
   PARO_VB_LOOP64(D, nprob, VFIX, (refine_update_body<VV>(d, vb, red)))
 }
 
-// Sum over the table of the active CG columns (which = 0, parity 0) or of
-// the refining columns (which = 1), for the host's poll (one block).
+// Sum over the table of the active CG columns (which = 0 or 1: that
+// parity) or of the refining columns (which = 2), for the host's poll (one
+// block); out[4] is always the refining count.
 __global__ void __launch_bounds__(kBlock)
 count_active_kernel(const Desc* __restrict__ D, int nprob, int which,
                     int* __restrict__ out, int seq) {
-  __shared__ int red[kBlock], mx[kBlock], st[kBlock];
-  int s = 0, m = 0, f = 0;
+  __shared__ int red[kBlock], mx[kBlock], st[kBlock], ot[kBlock];
+  int s = 0, m = 0, f = 0, o = 0;
   for (int p = threadIdx.x; p < nprob; p += kBlock) {
     const ColState* cs = D[p].cs;
     s += which == 2 ? cs->n_outer : cs->n_active[which];
+    o += cs->n_outer;
     m = max(m, (int)(cs->cg_iters - cs->cg_mark));
     f |= cs->status;
   }
   red[threadIdx.x] = s;
   mx[threadIdx.x] = m;
   st[threadIdx.x] = f;
+  ot[threadIdx.x] = o;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       red[threadIdx.x] += red[threadIdx.x + w];
       mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + w]);
       st[threadIdx.x] |= st[threadIdx.x + w];
+      ot[threadIdx.x] += ot[threadIdx.x + w];
     }
     __syncthreads();
   }
@@ -1775,6 +1779,7 @@ count_active_kernel(const Desc* __restrict__ D, int nprob, int which,
     out[1] = red[0];
     out[2] = mx[0];
     out[3] = st[0];
+    out[4] = ot[0];
     // out is host memory the caller spins on: the values, then the
     // sequence number with system-scope release.
     __hip_atomic_store(&out[0], seq, __ATOMIC_RELEASE,
