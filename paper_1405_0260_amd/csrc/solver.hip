@@ -2071,9 +2071,10 @@ gram_final_kernel(const Desc* __restrict__ D, int sym) {
 //   2. Li = L^{-1} (column j by thread j: a forward substitution each,
 //      no barriers), S = Li A Li^T as two small products;
 //   3. cyclic Jacobi on S with round-robin ordering: N_t/2 disjoint
-//      rotations per round, each thread forming the (c, s) it needs from
-//      the round's input matrix and writing the output matrix (two LDS
-//      copies alternate), so a round costs one barrier;
+//      rotations per round, formed once (one thread per pair) into LDS,
+//      then applied as independent 2 x 2 blocks from one LDS copy of S
+//      into the other (two copies alternate) and to Y: two barriers per
+//      round;
 //   4. theta ascending (ties by index);  5. C = Li^T Y;  6. signs.
 // ------------------------------------------------------------------------
 constexpr int kLd = kNtMax + 1;
@@ -2138,6 +2139,8 @@ __device__ void geneig_body(const double* __restrict__ Ain,
   __shared__ int perm[kNtMax];
   __shared__ double th[kNtMax];
   __shared__ double ld[kNtMax];  // diagonal of L
+  __shared__ double rc_c[kNtMax / 2], rc_s[kNtMax / 2];
+  __shared__ int rc_r[kNtMax / 2];
   const int tid = threadIdx.x;
   const int nn = n + (n & 1);
   // Zero the padded LDS matrices (odd n uses row/column n as a dummy),
@@ -2275,24 +2278,28 @@ __device__ void geneig_body(const double* __restrict__ Ain,
     for (int w = 0; w < nwave; ++w) mx = fmax(mx, red[w]);
     if (mx <= skip) break;
     for (int round = 0; round < nn - 1; ++round) {
-      // S' = J^T S J as independent 2 x 2 blocks (row pair k, column pair
-      // l): the row rotation, then the column rotation; Y <- Y J.  A pair
-      // that does not rotate has c = 1, s = 0 (exact identity).
+      // The round's rotations, formed once (thread k: pair k), then
+      // applied as independent 2 x 2 blocks and to Y.
+      if (tid < half) {
+        int p, q;
+        rr_pair(tid, round, nn, p, q);
+        double c, sn;
+        const bool rot = jacobi_cs(Sc, p, q, n, skip, c, sn);
+        rc_c[tid] = c;
+        rc_s[tid] = sn;
+        rc_r[tid] = rot ? 1 : 0;
+        if (rot) s_rot = 1;
+      }
+      __syncthreads();
       for (int e = tid; e < nblk + n * half; e += kGeThreads) {
         if (e < nblk) {
           const int k = e / half, l = e - k * half;
           int p, q, r, t;
           rr_pair(k, round, nn, p, q);
           rr_pair(l, round, nn, r, t);
-          double c1, s1, c2, s2;
-          const bool rot = jacobi_cs(Sc, p, q, n, skip, c1, s1);
-          if (k == l) {
-            c2 = c1;
-            s2 = s1;
-            if (rot) s_rot = 1;
-          } else {
-            jacobi_cs(Sc, r, t, n, skip, c2, s2);
-          }
+          const double c1 = rc_c[k], s1 = rc_s[k];
+          const double c2 = rc_c[l], s2 = rc_s[l];
+          const bool rot = rc_r[k] != 0;
           const double apr = Sc[p][r], apt = Sc[p][t];
           const double aqr = Sc[q][r], aqt = Sc[q][t];
           const double bpr = c1 * apr - s1 * aqr, bpt = c1 * apt - s1 * aqt;
@@ -2307,8 +2314,7 @@ __device__ void geneig_body(const double* __restrict__ Ain,
           const int e2 = e - nblk, l = e2 / n, i = e2 - l * n;
           int p, q;
           rr_pair(l, round, nn, p, q);
-          double c, sn;
-          jacobi_cs(Sc, p, q, n, skip, c, sn);
+          const double c = rc_c[l], sn = rc_s[l];
           const double yp = Y[i][p], yq = Y[i][q];
           Y[i][p] = c * yp - sn * yq;
           Y[i][q] = sn * yp + c * yq;
