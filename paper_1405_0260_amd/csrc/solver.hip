@@ -2022,10 +2022,22 @@ __device__ __forceinline__ int gram_per_blk(int ncols, bool sym) {
 // Y2 = W^T Y1 (component form).
 __device__ __forceinline__ double gram_entry_sum(const Desc& d, int per_blk,
                                                  int e) {
+  // Lane l adds partials l, l + 64, ... in ascending order; the loads of
+  // kU of them are issued together (clamped addresses, masked adds), so
+  // the kGramGrid partials cost one round trip.
+  constexpr int kU = kGramGrid / 64;
   const int lane = threadIdx.x & 63;
   double v = 0.0;
-  for (int b = lane; b < d.gns; b += 64)
-    v += ldg(d.gpart + (size_t)b * per_blk + e);
+  for (int b0 = 0; b0 < d.gns; b0 += kU * 64) {
+    double x[kU];
+#pragma unroll
+    for (int i = 0; i < kU; ++i)
+      x[i] = ldg(d.gpart +
+                 (size_t)min(b0 + lane + i * 64, d.gns - 1) * per_blk + e);
+#pragma unroll
+    for (int i = 0; i < kU; ++i)
+      v = (b0 + lane + i * 64 < d.gns) ? v + x[i] : v;
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
