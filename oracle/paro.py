@@ -33,6 +33,7 @@ design notes):
 from __future__ import annotations
 
 import dataclasses
+import multiprocessing
 from typing import List, Optional
 
 import numpy as np
@@ -151,17 +152,43 @@ class ParOResult:
     pcg_iters: List[List[int]]
 
 
-def paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit, clusters=None):
+# Operator of the source problems seen by the worker processes of
+# paro_solve(workers=k); set before the pool forks, read-only afterwards.
+_POOL_OPERATOR = {}
+
+
+def _pool_start():
+    # One BLAS thread per worker: the workers already fill the cores, and a
+    # BLAS thread pool inherited across fork() can stall.
+    from threadpoolctl import threadpool_limits
+    _POOL_OPERATOR["limits"] = threadpool_limits(limits=1)
+
+
+def _pool_solve(job):
+    b, x0 = job
+    op = _POOL_OPERATOR
+    return jacobi_pcg(op["A"], b, x0, op["dinv"], op["rtol"], op["maxit"])
+
+
+def paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit, clusters=None,
+              pool=None):
     """One ParO iteration (Steps 3 and 4) from (lam, U); returns the new
     pairs and the PCG iteration count of each source problem.  With
     `clusters` (sizes of consecutive column groups) Step 4 projects each
-    cluster separately (rayleigh_ritz_clustered)."""
+    cluster separately (rayleigh_ritz_clustered).  With `pool` (from
+    paro_solve(workers=k)) the independent source problems of Step 3 are
+    spread over worker processes, which the paper names as the method's
+    parallelism; each is the same jacobi_pcg call as in the serial loop."""
     MU = M @ U
     W = np.empty_like(U)
+    jobs = [((lam[i] - sigma) * MU[:, i], U[:, i]) for i in range(U.shape[1])]
+    if pool is None:                         # Step 3: independent problems
+        out = [jacobi_pcg(A, b, x0, dinv, rtol, maxit) for b, x0 in jobs]
+    else:
+        out = pool.map(_pool_solve, jobs, chunksize=1)
     its = []
-    for i in range(U.shape[1]):              # Step 3: independent problems
-        b = (lam[i] - sigma) * MU[:, i]
-        W[:, i], k = jacobi_pcg(A, b, U[:, i], dinv, rtol, maxit)
+    for i, (w, k) in enumerate(out):
+        W[:, i] = w
         its.append(k)
     if clusters:                             # Step 4
         lam_new, U_new = rayleigh_ritz_clustered(H, M, W, clusters)
@@ -172,12 +199,14 @@ def paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit, clusters=None):
 
 def paro_solve(H, M, U0, N, sigma: Optional[float] = None, V_nodal=None,
                max_steps=100, lambda_tol=0.0, resid_tol=0.0, rtol=1e-10,
-               maxit=None, callback=None) -> ParOResult:
+               maxit=None, callback=None, workers=None) -> ParOResult:
     """Run ParO from the orbitals U0 (n x (N + m)).
 
     sigma: the shift (None -> shift_from_potential(V_nodal)).
     Stops after max_steps, or earlier when lambda_tol > 0 and every
-    requested pair satisfies both tolerances."""
+    requested pair satisfies both tolerances.  workers: number of processes
+    for the source problems of Step 3 (None: solved one after another);
+    the iterates are the same either way."""
     if sigma is None:
         sigma = shift_from_potential(V_nodal)
     n = H.shape[0]
@@ -189,10 +218,34 @@ def paro_solve(H, M, U0, N, sigma: Optional[float] = None, V_nodal=None,
     lam_hist = [lam.copy()]
     res_hist = [residuals(H, M, lam, U)[:N]]
     pcg_hist = []
+    pool = None
+    if workers:
+        _POOL_OPERATOR.update(A=A, dinv=dinv, rtol=rtol, maxit=maxit)
+        pool = multiprocessing.get_context("fork").Pool(workers,
+                                                        _pool_start)
+    try:
+        lam, U, steps, converged = _iterate(
+            H, M, A, dinv, lam, U, sigma, rtol, maxit, N, max_steps,
+            lambda_tol, resid_tol, callback, pool, lam_hist, res_hist,
+            pcg_hist)
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
+            _POOL_OPERATOR.clear()
+    return ParOResult(lam[:N].copy(), U[:, :N].copy(), lam, U, sigma, steps,
+                      converged, lam_hist, res_hist, pcg_hist)
+
+
+def _iterate(H, M, A, dinv, lam, U, sigma, rtol, maxit, N, max_steps,
+             lambda_tol, resid_tol, callback, pool, lam_hist, res_hist,
+             pcg_hist):
+    """The ParO loop of paro_solve (Steps 3-4 repeated, stopping test)."""
     converged = False
     steps = 0
     for step in range(max_steps):
-        lam_new, U, its = paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit)
+        lam_new, U, its = paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit,
+                                    pool=pool)
         dl = np.abs(lam_new - lam) / scale_floor(lam_new)
         lam = lam_new
         rho = residuals(H, M, lam, U)
@@ -206,5 +259,4 @@ def paro_solve(H, M, U0, N, sigma: Optional[float] = None, V_nodal=None,
                 and np.max(rho[:N]) <= resid_tol:
             converged = True
             break
-    return ParOResult(lam[:N].copy(), U[:, :N].copy(), lam, U, sigma, steps,
-                      converged, lam_hist, res_hist, pcg_hist)
+    return lam, U, steps, converged

@@ -253,3 +253,31 @@ def test_solve_loop_matches_public_steps(precision):
     scale = np.max(np.abs(lam_b))
     assert np.max(np.abs(lam_a - lam_b)) <= 1e-9 * scale
     assert np.max(np.abs(U_a - U_b)) <= 1e-6 * np.max(np.abs(U_b))
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_step_reports_match_oracle_stopping_measures(precision):
+    """The per-step stopping measures (Algorithm A.1 stopping reading) that
+    paro_solve, the batch solve and the server act on: for the 24^3
+    harmonic run, every step's reported max_i dlambda_i and max_i rho_i
+    (i <= N) against the oracle's, computed from its lambda and residual
+    histories of the same 30 steps from the same start."""
+    w = inputs.harmonic_24()
+    prob = gu.workload_problem(w, pcg_rtol=1e-12, precision=precision)
+    hist, _, reps = run_steps(prob, w.U0(), 30)
+    H, M, s = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+    r = oparo.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=30,
+                         rtol=1e-12)
+    L = np.array(r.lam_history)
+    dl = np.max(np.abs(L[1:, :w.N] - L[:-1, :w.N])
+                / np.stack([oparo.scale_floor(x) for x in L[1:]])[:, :w.N],
+                axis=1)
+    rho = np.array([x[:w.N].max() for x in r.resid_history[1:]])
+    g_dl = np.array([x.max_dlambda for x in reps])
+    g_rho = np.array([x.max_resid for x in reps])
+    e_dl = np.max(np.abs(g_dl - dl) / dl)
+    e_rho = np.max(np.abs(g_rho - rho) / rho)
+    gu.note(f"step reports vs oracle: dlambda rel {e_dl:.2e} "
+            f"(last {g_dl[-1]:.3e}), rho rel {e_rho:.2e} "
+            f"(last {g_rho[-1]:.3e})")
+    assert e_dl < 1e-6 and e_rho < 1e-6

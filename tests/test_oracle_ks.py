@@ -88,3 +88,74 @@ def test_converged_scf_is_self_consistent():
     rho_out = ks.density(r.U, w.N)
     assert np.linalg.norm(rho_out - r.rho_in) / np.linalg.norm(r.rho_in) \
         < 1e-7
+
+
+def _box_mesh():
+    """A non-cubic box and grid, so a dof <-> vertex numbering slip (x
+    fastest, (nx-1)(ny-1) per z layer) moves values to other points."""
+    nc, lo, hi = (12, 10, 14), np.zeros(3), np.array([2.0, 1.6, 2.4])
+    return fem.kuhn_mesh(nc, lo, hi), lo, hi
+
+
+def _at_dofs(mesh, f):
+    """Values of f(x) at the interior vertices, in dof order, computed from
+    the vertex coordinates (not from the dof numbering formula)."""
+    inner = np.nonzero(mesh.dof >= 0)[0]
+    out = np.empty(inner.size)
+    out[mesh.dof[inner]] = f(mesh.X[inner])
+    return out
+
+
+def test_effective_potential_without_density_is_the_external_potential():
+    mesh, lo, hi = _box_mesh()
+    V = np.random.default_rng(5).standard_normal(mesh.X.shape[0])
+    n = mesh.n_dof
+    out = ks.effective_potential(mesh, V, np.zeros(n), np.zeros(n))
+    assert np.array_equal(out, V)
+
+
+def test_effective_potential_keeps_boundary_values_and_maps_by_coordinates():
+    """Sec. 2 effective potential V_ext + V_H + v_x: on boundary vertices
+    rho = V_H = 0 (homogeneous Dirichlet data), so V_ext is kept bit for
+    bit; at an interior vertex x the added terms are V_H(x) and
+    -(3 rho(x) / pi)^(1/3), with rho and V_H looked up by the vertex."""
+    mesh, lo, hi = _box_mesh()
+    V = np.random.default_rng(6).standard_normal(mesh.X.shape[0])
+    rho = _at_dofs(mesh, lambda X: 1.0 + X[:, 0] + 3.0 * X[:, 1] ** 2
+                   + 5.0 * X[:, 2] ** 3)
+    vh = _at_dofs(mesh, lambda X: np.sin(X[:, 0]) + 7.0 * X[:, 2])
+    out = ks.effective_potential(mesh, V, rho, vh)
+    bnd = mesh.dof < 0
+    assert np.array_equal(out[bnd], V[bnd])
+    X = mesh.X[~bnd]
+    r = 1.0 + X[:, 0] + 3.0 * X[:, 1] ** 2 + 5.0 * X[:, 2] ** 3
+    expect = V[~bnd] + np.sin(X[:, 0]) + 7.0 * X[:, 2] \
+        - (3.0 * r / np.pi) ** (1.0 / 3.0)
+    assert np.allclose(out[~bnd], expect, rtol=0, atol=1e-13)
+
+
+def test_effective_potential_of_a_sine_density_matches_the_closed_form():
+    """Manufactured Hartree term: on [0,a]x[0,b]x[0,c] the product
+    V*(x) = prod sin(pi x_k / L_k) solves -Lap V* = 4 pi rho for
+    rho = pi (1/a^2 + 1/b^2 + 1/c^2) V* / 4 and vanishes on the boundary,
+    so V_eff - V_ext = V* - (3 rho / pi)^(1/3) at interior vertices up to
+    the O(h^2) error of the P1 Poisson solve (halving h quarters it)."""
+    errs = []
+    for scale in (1, 2):
+        nc = tuple(scale * k for k in (8, 6, 10))
+        L = np.array([2.0, 1.6, 2.4])
+        mesh = fem.kuhn_mesh(nc, np.zeros(3), L)
+        K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+        coef = np.pi * np.sum(1.0 / L ** 2) / 4.0
+        vstar = lambda X: np.prod(np.sin(np.pi * X / L), axis=1)
+        rho = _at_dofs(mesh, lambda X: coef * vstar(X))
+        Vext = np.cos(mesh.X[:, 0]) * mesh.X[:, 1]
+        out = ks.effective_potential(mesh, Vext, rho,
+                                     ks.hartree(K, M, rho))
+        inner = mesh.dof >= 0
+        X = mesh.X[inner]
+        expect = vstar(X) - np.cbrt(3.0 * coef * vstar(X) / np.pi)
+        errs.append(np.max(np.abs(out[inner] - Vext[inner] - expect)))
+        assert np.array_equal(out[~inner], Vext[~inner])
+    assert errs[1] < 0.025
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs

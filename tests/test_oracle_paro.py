@@ -186,3 +186,53 @@ def test_harmonic_p_shell_splits_into_singlet_and_exact_doublet():
         d = np.diff(p)
         assert min(d) < 1e-10 * p[0]
         assert max(d) > 1e-3 * p[0]
+
+
+def test_residuals_of_a_two_pair_mixture_match_the_closed_form():
+    """Stopping measure (Algorithm A.1 stopping reading): for exact pairs
+    (l1, u1), (l2, u2) with u^T M u = I, the normalised mixture
+    u = (u1 + e u2) / sqrt(1 + e^2) has Rayleigh quotient
+    l = (l1 + e^2 l2) / (1 + e^2) and residual
+    H u - l M u = e (l2 - l1) / (1 + e^2)^(3/2) * M (u2 - e u1).
+    Two mixtures with different e and different pairs sit in one call so a
+    residual scaled by the wrong column's eigenvalue or norm fails."""
+    w, H, M = problem("sc", 8)
+    lam, U = reference.dense_lowest(H, M, 6)
+    cols, lams, expect = [], [], []
+    for (a, b, e) in ((0, 1, 0.03), (2, 5, 0.4)):
+        u = (U[:, a] + e * U[:, b]) / np.sqrt(1.0 + e * e)
+        lq = (lam[a] + e * e * lam[b]) / (1.0 + e * e)
+        num = abs(e * (lam[b] - lam[a])) / (1.0 + e * e) ** 1.5 \
+            * np.linalg.norm(M @ (U[:, b] - e * U[:, a]))
+        cols.append(u)
+        lams.append(lq)
+        expect.append(num)
+    Uc = np.stack(cols, axis=1)
+    lams = np.array(lams)
+    scale = np.maximum(np.abs(lams), 1e-3 * np.abs(lams).max())
+    mu_norm = np.linalg.norm(M @ Uc, axis=0)
+    rho = paro.residuals(H, M, lams, Uc)
+    assert np.allclose(rho, np.array(expect) / (scale * mu_norm),
+                       rtol=1e-9, atol=0)
+    # Exact pairs have residual at rounding level.
+    assert np.max(paro.residuals(H, M, lam, U)) < 1e-12
+
+
+def test_scale_floor_guards_eigenvalues_near_zero():
+    """The relative measures divide by max(|l_i|, 1e-3 max_j |l_j|): an
+    eigenvalue of exactly zero is measured against one thousandth of the
+    largest magnitude, the others against themselves."""
+    s = paro.scale_floor(np.array([0.0, -2.0, 5e-4, 1.0]))
+    assert np.array_equal(s, [2e-3, 2.0, 2e-3, 1.0])
+
+
+def test_worker_pool_gives_the_serial_iterates():
+    """Step 3's source problems are independent: solving them in worker
+    processes returns bit-identical iterates."""
+    w, H, M = problem("sc", 8)
+    a = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=5)
+    b = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=5,
+                        workers=2)
+    assert np.array_equal(a.U_all, b.U_all)
+    assert np.array_equal(np.array(a.lam_history), np.array(b.lam_history))
+    assert a.pcg_iters == b.pcg_iters
