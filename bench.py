@@ -1,13 +1,17 @@
 #!/usr/bin/env python
-"""ParO throughput on one MI355X: orbital-updates/s on the 64^3 soft-Coulomb
-workload (8 centres, N = 16 requested orbitals + 8 buffer orbitals).
+"""ParO throughput on one MI355X: orbital-updates/s on the largest
+single-GPU workload, the linear eigenproblem of the 96^3 Kohn-Sham
+workload's external potential (20 soft-Coulomb centres on [-14,14]^3,
+857,375 dofs, N = 32 requested orbitals + 8 buffer orbitals), in FP64.
 
 One benchmark step is one whole solve from inputs resident in HBM:
 assembly of the operator, the Rayleigh-Ritz start, and ParO steps until the
 requested pairs meet lambda_tol / resid_tol.  Throughput counts
-n_dof * N per ParO step (requested orbitals, not the buffer).
+n_dof * N per ParO step (requested orbitals, not the buffer).  The
+eigenvalues are checked against the oracle's converged run
+(tests/golden/linear_96c_lowest.txt).
 
-    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
+    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]
 
 Prints one JSON line (see the keys at the bottom).
 """
@@ -25,9 +29,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-GOLDEN = os.path.join(ROOT, "tests", "golden", "softcoulomb_64c_lowest.txt")
-TRAFFIC = os.path.join(ROOT, "profiles", "softcoulomb64_mixed_traffic.md")
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+GOLDEN = os.path.join(GOLDEN_DIR, "linear_96c_lowest.txt")
+GOLDEN64 = os.path.join(GOLDEN_DIR, "softcoulomb_64c_lowest.txt")
+GOLDEN_BATCH = os.path.join(GOLDEN_DIR, "batch64_sample_lowest.txt")
+GOLDEN_SERVE = os.path.join(GOLDEN_DIR, "serve_sample_lowest.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC = {"fp64": os.path.join(PROFILES, "linear96_fp64_traffic.md"),
+           "mixed": os.path.join(PROFILES, "linear96_mixed_traffic.md")}
 SOLVER_SRC = os.path.join(ROOT, "paper_1405_0260_amd", "csrc", "solver.hip")
+KERNEL_NAMES = {"cg_spmm": "spmm_cm_kernel", "cg_rupd": "rupd_alpha_kernel",
+                "cg_pupd": "pupd_beta_kernel"}
 
 
 def solver_code_sha():
@@ -42,13 +54,13 @@ def solver_code_sha():
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of a CG kernel from the committed PMC summary
+def measured_traffic(kernel, path):
+    """HBM bytes per launch of a CG kernel from a committed PMC summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size), or
     None when the summary is missing, lacks that kernel, or was taken on a
     different solver source than the one built now."""
     try:
-        text = open(TRAFFIC).read()
+        text = open(path).read()
         sha = solver_code_sha()
     except OSError:
         return None
@@ -61,30 +73,41 @@ def measured_traffic(kernel):
     return None if value is None else float(value)
 
 
+def lambda_error(lam, ref):
+    """max_i |l_i - r_i| / max(|r_i|, 1e-3 max|r|) over the given pairs."""
+    ref = np.asarray(ref, dtype=np.float64)
+    floor = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+    return float(np.max(np.abs(np.asarray(lam) - ref) / floor))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="arithmetic of the headline solves (the other "
+                         "precision is reported beside them)")
+    ap.add_argument("--nc", type=int, default=96,
+                    help="cells per axis of the headline workload")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true",
-                    help="skip the plain FP64 comparison solves")
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="skip the solves in the other precision")
+    ap.add_argument("--no-64", action="store_true",
+                    help="skip the 64^3 soft-Coulomb context runs")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed solves only (for rocprofv3)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="FP32 inner CG residual reduction per refinement")
-    ap.add_argument("--m", type=int, default=None,
-                    help="buffer orbitals (default: the workload's)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="with --profile-only: first copy a 256 MiB buffer "
                          "(a plain copy kernel of known size, the reference "
                          "for the HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-problem uneven batch")
-    ap.add_argument("--batch-sequential", action="store_true",
-                    help="also solve the batch members one by one")
+    ap.add_argument("--no-batch-sequential", action="store_true",
+                    help="do not also solve the batch members one by one")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served request stream")
     ap.add_argument("--no-ks", action="store_true",
@@ -95,10 +118,6 @@ def parse():
                     help="cells per axis of the Kohn-Sham run")
     ap.add_argument("--ks-iters", type=int, default=300,
                     help="outer iterations at most")
-    ap.add_argument("--no-hbm", action="store_true",
-                    help="skip the CG rates of the 96^3 linear problem")
-    ap.add_argument("--hbm-steps", type=int, default=12,
-                    help="ParO steps of that run")
     ap.add_argument("--ks-poisson-cg", action="store_true",
                     help="Hartree by Jacobi-PCG instead of the direct solve")
     ap.add_argument("--serve-requests", type=int, default=64,
@@ -107,6 +126,9 @@ def parse():
                     help="device arena of the server (admission budget)")
     ap.add_argument("--serve-slots", type=int, default=64,
                     help="most requests resident at once")
+    ap.add_argument("--cpu-workers", type=int, default=None,
+                    help="worker processes of the all-core oracle sample "
+                         "(default: the usable cores, at most 16)")
     return ap.parse_args()
 
 
@@ -146,6 +168,7 @@ def cg_stage_rates(td, n, nnz, vec_b):
         stages[st] = {"total_ms": s["ms"], "launches": s["launches"],
                       "us_per_launch": 1e3 * s["ms"] / s["launches"],
                       "bytes_per_launch": total / s["launches"],
+                      "own_bytes_per_launch": own / s["launches"],
                       "gbs": total / (s["ms"] * 1e-3) / 1e9,
                       "own_gbs": own / (s["ms"] * 1e-3) / 1e9}
     return stages, it_bytes
@@ -160,111 +183,92 @@ def own_format_bytes(stage, n, vec_bytes, mat_bytes, diag_bytes):
     return algorithmic_bytes(stage, n, 0, vec_bytes, mat_bytes, diag_bytes)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} "
-              "is not supported (the multi-GPU sharding is a design note, "
-              "not built)", file=sys.stderr)
-        sys.exit(2)
+class Solver:
+    """Whole solves of one workload (assembly + paro_solve) in one
+    precision, with the caller-owned workspace kept across solves."""
 
-    import torch
-    from paper_1405_0260_amd import binding as pb
-    from paper_1405_0260_amd import inputs
-
-    dev = torch.device("cuda:0")
-    w = inputs.molecule_64()
-    if args.m is not None:
-        w = inputs.molecule(m=args.m)
-    box = pb.Box.cube(w.nc, w.lo, w.hi)
-    V = torch.from_numpy(w.V).to(dev)
-    U0 = torch.from_numpy(w.U0()).to(dev)
-    n, Nt, N = w.n_dof, w.Nt, w.N
-    lam = torch.zeros(Nt, dtype=torch.float64, device=dev)
-    U = torch.zeros(n, Nt, dtype=torch.float64, device=dev)
-    golden = np.loadtxt(GOLDEN) if os.path.exists(GOLDEN) else None
-
-    def opts_for(prec):
-        return pb.default_opts(
-            N=N, m=w.m, max_steps=2000, lambda_tol=1e-11, resid_tol=1e-7,
-            pcg_rtol=1e-10, inner_rtol=args.inner_rtol,
+    def __init__(self, w, prec, golden, inner_rtol):
+        import torch
+        from paper_1405_0260_amd import binding as pb
+        self.pb, self.torch, self.w, self.prec = pb, torch, w, prec
+        dev = torch.device("cuda:0")
+        self.golden = golden
+        self.box = pb.Box.cube(w.nc, w.lo, w.hi)
+        self.V = torch.from_numpy(w.V).to(dev)
+        self.U0 = torch.from_numpy(w.U0()).to(dev)
+        self.lam = torch.zeros(w.Nt, dtype=torch.float64, device=dev)
+        self.U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=dev)
+        self.opts = pb.default_opts(
+            N=w.N, m=w.m, max_steps=4000, lambda_tol=1e-11, resid_tol=1e-7,
+            pcg_rtol=1e-10, inner_rtol=inner_rtol,
             precision=pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64)
+        _, self.nnz, nbytes = pb.paro_query(self.box, self.opts)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
 
-    workspaces = {}
-
-    def solve(prec, timing=False):
-        o = opts_for(prec)
-        if prec not in workspaces:
-            _, _, nbytes = pb.paro_query(box, o)
-            workspaces[prec] = torch.empty(nbytes + 256, dtype=torch.uint8,
-                                           device=dev)
+    def solve(self, timing=False):
+        pb, torch = self.pb, self.torch
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        prob = pb.paro_assemble(box, V, o, workspace=workspaces[prec])
+        prob = pb.paro_assemble(self.box, self.V, self.opts,
+                                workspace=self.ws)
         if timing:
             pb.paro_set_timing(prob, True)
-        rep = pb.paro_solve(prob, U0, lam, U)
+        rep = pb.paro_solve(prob, self.U0, self.lam, self.U)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         tim = pb.paro_get_timing(prob) if timing else None
         return t1 - t0, rep, prob, tim
 
-    def run(prec, steps, warmup):
+    def run(self, steps, warmup, tag):
+        w = self.w
         for k in range(warmup):
-            dt, rep, _, _ = solve(prec)
-            log(f"[{prec}] warmup {k}: {dt:.3f} s, {rep.steps} ParO steps, "
+            dt, rep, _, _ = self.solve()
+            log(f"[{tag}] warmup {k}: {dt:.3f} s, {rep.steps} ParO steps, "
                 f"{rep.pcg_iters} CG iterations")
-        torch.cuda.synchronize()
+        self.torch.cuda.synchronize()
         times, reps = [], []
         t0 = time.perf_counter()
         for k in range(steps):
-            dt, rep, prob, _ = solve(prec)
+            dt, rep, _, _ = self.solve()
             times.append(dt)
             reps.append(rep)
-            log(f"[{prec}] step {k}: {dt:.3f} s, {rep.steps} ParO steps, "
+            log(f"[{tag}] step {k}: {dt:.3f} s, {rep.steps} ParO steps, "
                 f"{rep.pcg_iters} CG iterations, status {rep.status}")
-        torch.cuda.synchronize()
+        self.torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        lam_host = lam.cpu().numpy()
+        lam_host = self.lam.cpu().numpy()
         err = None
-        if golden is not None:
-            ref = golden[:N]
-            floor = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
-            err = float(np.max(np.abs(lam_host[:N] - ref) / floor))
-        updates = sum(r.steps for r in reps) * n * N
+        if self.golden is not None:
+            err = lambda_error(lam_host[:w.N], self.golden[:w.N])
+        updates = sum(r.steps for r in reps) * w.n_dof * w.N
+        last = reps[-1]
         return {
             "value": updates / wall, "wall": wall, "times": times,
-            "reps": reps, "lambda_err": err, "lambda": lam_host[:N].tolist(),
-            "ok": all(r.status == 0 for r in reps),
+            "reps": reps, "lambda_err": err, "ok": all(r.status == 0
+                                                       for r in reps),
+            "summary": {
+                "value": updates / wall, "unit": "orbital-updates/s",
+                "ms_per_solve": 1e3 * float(np.mean(times)),
+                "paro_steps": last.steps, "cg_iters": last.pcg_iters,
+                "refinements": last.refinements,
+                "lambda_rel_err_vs_oracle_ref": err,
+                "converged": all(r.status == 0 for r in reps)},
         }
 
-    prec = args.precision
-    if args.copy_probe:
-        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    main_res = run(prec, args.steps, args.warmup)
-    if args.profile_only:
-        log(json.dumps({"value": main_res["value"]}))
-        return
-
-    def kernel_roofline(prec):
+    def roofline(self):
         """Roofline of the dominant CG kernel from one event-timed solve
-        of the same workload, plus the whole CG iteration and the Gram's
+        (dispatch-stamped HIP events on the launch stream), plus the whole
+        CG iteration, every stage's share of kernel time and the Gram's
         FP64 MFMA rate."""
-        _, rep_t, prob_t, tim = solve(prec, timing=True)
+        w, prec = self.w, self.prec
+        n, Nt = w.n_dof, w.Nt
+        _, rep_t, prob_t, tim = self.solve(timing=True)
         td = tim.as_dict()
         vec_b = 4 if prec == "mixed" else 8
         stages, it_bytes = cg_stage_rates(td, n, prob_t.nnz, vec_b)
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
-        kernel_names = {"cg_spmm": "spmm_cm_kernel",
-                        "cg_rupd": "rupd_alpha_kernel",
-                        "cg_pupd": "pupd_beta_kernel"}
-        traffic = (measured_traffic(kernel_names[dom]) if prec == "mixed"
-                   else None)
+        traffic = measured_traffic(KERNEL_NAMES[dom], TRAFFIC[prec])
         all_ms = sum(v["ms"] for v in td["stages"].values())
         cg_ms = sum(td["stages"][k]["ms"] for k in
                     ("cg_spmm", "cg_rupd", "cg_pupd", "cg_final"))
@@ -272,11 +276,10 @@ def main():
         # Two launches per Gram (MFMA tiles, then the fixed-order final).
         gram_flop = 4.0 * n * Nt * Nt * g["launches"] / 2
         return {
-            "bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1),
+            "bound": "hbm", "kernel": KERNEL_NAMES[dom],
+            "achieved": round(d["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
-            "achieved_own_format": round(d["own_gbs"], 1),
-            "frac_own_format": round(d["own_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else int(traffic),
             "traffic_over_algorithmic": None if traffic is None else
             round(traffic / d["bytes_per_launch"], 3),
@@ -286,6 +289,10 @@ def main():
             "active_cols_avg": round(td["cg_col_iters"] /
                                      max(1, td["cg_iters"]), 2),
             "cg_stage_gbs": {k: round(v["gbs"], 1) for k, v in stages.items()},
+            "cg_stage_own_format_gbs": {k: round(v["own_gbs"], 1)
+                                        for k, v in stages.items()},
+            "cg_stage_us_per_launch": {k: round(v["us_per_launch"], 2)
+                                       for k, v in stages.items()},
             "cg_iteration_gbs": round(it_bytes / (cg_ms * 1e-3) / 1e9, 1),
             "cg_iteration_frac": round(it_bytes / (cg_ms * 1e-3) / 1e9 /
                                        HBM_PEAK_GBS, 4),
@@ -299,33 +306,77 @@ def main():
                                if v["ms"] > 0},
         }
 
-    roofline = kernel_roofline(prec)
-    nnz = pb.paro_query(box, opts_for(prec))[1]
 
-    fp64 = None
-    if not args.no_fp64 and prec != "fp64":
-        r64 = run("fp64", max(1, args.steps - 1), 0)
-        fp64 = {"value": r64["value"], "ms_per_solve":
-                1e3 * float(np.mean(r64["times"])),
-                "paro_steps": r64["reps"][-1].steps,
-                "lambda_err": r64["lambda_err"], "ok": r64["ok"],
-                "roofline": kernel_roofline("fp64")}
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} "
+              "is not supported (the multi-GPU sharding is a design note, "
+              "not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1405_0260_amd import inputs
+
+    dev = torch.device("cuda:0")
+    w = inputs.kohn_sham_96(nc=args.nc)
+    golden = np.loadtxt(GOLDEN) if (args.nc == 96 and
+                                    os.path.exists(GOLDEN)) else None
+    prec = args.precision
+    other = "mixed" if prec == "fp64" else "fp64"
+
+    if args.copy_probe:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    head = Solver(w, prec, golden, args.inner_rtol)
+    main_res = head.run(args.steps, args.warmup, prec)
+    if args.profile_only:
+        log(json.dumps({"value": main_res["value"]}))
+        return
+    roofline = head.roofline()
+    nnz = head.nnz
+    del head
+    torch.cuda.empty_cache()
+
+    other_res = None
+    if not args.no_other_precision:
+        s2 = Solver(w, other, golden, args.inner_rtol)
+        r2 = s2.run(max(1, args.steps - 1), 0, other)
+        other_res = dict(r2["summary"], precision=other,
+                         roofline=s2.roofline())
+        del s2
+        torch.cuda.empty_cache()
+
+    ctx64 = None
+    if not args.no_64:
+        g64 = np.loadtxt(GOLDEN64) if os.path.exists(GOLDEN64) else None
+        w64 = inputs.molecule_64()
+        ctx64 = {"workload": f"softcoulomb_64c_N{w64.N}_m{w64.m}",
+                 "n_dof": w64.n_dof,
+                 "note": "working set fits the 256 MB Infinity Cache: "
+                         "its CG kernel rates are cache-assisted"}
+        for p in ("fp64", "mixed"):
+            s3 = Solver(w64, p, g64, args.inner_rtol)
+            r3 = s3.run(2, 1, f"64c {p}")
+            ctx64[p] = dict(r3["summary"], roofline=s3.roofline())
+            del s3
+        torch.cuda.empty_cache()
 
     batch = None
     if not args.no_batch:
-        batch = batch_bench(args, prec)
+        batch = batch_bench(args, "mixed")
 
     serve = None
     if not args.no_serve:
-        serve = serve_bench(args, prec)
-
-    hbm = None
-    if not args.no_hbm:
-        hbm = hbm_bound_rates(args)
+        serve = serve_bench(args, "mixed")
 
     ks = None
     if not args.no_ks:
-        ks = ks_bench(args, prec)
+        ks = ks_bench(args, "mixed")
 
     nonlocal_term = None
     if not args.no_nonlocal:
@@ -333,7 +384,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(w, args.cpu_workers)
 
     times = np.array(main_res["times"])
     last = main_res["reps"][-1]
@@ -347,10 +398,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-inner/f64" if prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"softcoulomb_64c_N{N}_m{w.m}", "n_dof": n,
-                   "nnz": nnz, "N": N, "m": w.m,
-                   "precision": prec, "inner_rtol": args.inner_rtol,
-                   "lambda_tol": 1e-11,
+        "config": {"workload": f"linear_{w.nc}c_N{w.N}_m{w.m}",
+                   "potential": "20 soft-Coulomb centres, Z in 1..8, R in "
+                                "[-5,5]^3 (seed 3), box [-14,14]^3",
+                   "n_dof": w.n_dof, "nnz": nnz,
+                   "N": w.N, "m": w.m, "precision": prec,
+                   "inner_rtol": args.inner_rtol, "lambda_tol": 1e-11,
                    "resid_tol": 1e-7, "pcg_rtol": 1e-10,
                    "parallelism": "single-gpu"},
         "latency_ms": {"p50": 1e3 * float(np.percentile(times, 50)),
@@ -360,11 +413,11 @@ def main():
         "ms_per_paro_step": 1e3 * float(np.mean(times)) / last.steps,
         "lambda_rel_err_vs_oracle_ref": main_res["lambda_err"],
         "converged": main_res["ok"],
-        "fp64_plain": fp64,
+        "other_precision": other_res,
+        "softcoulomb_64c": ctx64,
         "batch64": batch,
         "serve": serve,
         "kohn_sham": ks,
-        "cg_rates_96": hbm,
         "nonlocal": nonlocal_term,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -423,7 +476,11 @@ def batch_bench(args, prec):
                                             (work.sum() * steps.max())),
            "n_dof_range": [int(min(x.n_dof for x in ws)),
                            int(max(x.n_dof for x in ws))]}
-    if args.batch_sequential:
+    errs = member_errors(GOLDEN_BATCH, {j: lams[j] for j in
+                                        range(len(ws))}, ws)
+    if errs:
+        out["lambda_rel_err_vs_oracle_ref"] = errs
+    if not args.no_batch_sequential:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         upd = 0.0
@@ -432,7 +489,38 @@ def batch_bench(args, prec):
             r = pb.paro_solve(p, U0s[k], lams[k], Us[k])
             upd += r.steps * ws[k].n_dof * ws[k].N
         torch.cuda.synchronize()
-        out["sequential_value"] = upd / (time.perf_counter() - t0)
+        seq = time.perf_counter() - t0
+        out["sequential"] = {"value": upd / seq, "seconds": seq,
+                             "batch_speedup": seq / dt}
+        log(f"[batch64] one by one: {seq:.3f} s ({seq / dt:.2f}x the "
+            f"batch)")
+    return out
+
+
+def read_member_golden(path):
+    """{member index: requested eigenvalues} from a golden file whose data
+    lines read 'j lam_1 ... lam_N'."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = line.split()
+        out[int(v[0])] = np.array([float(x) for x in v[1:]])
+    return out
+
+
+def member_errors(path, lams, ws):
+    """Relative lambda error of the sampled members (those with a stored
+    oracle reference) of a batch or served stream."""
+    ref = read_member_golden(path)
+    out = {}
+    for j, r in ref.items():
+        if j in lams:
+            lam = lams[j]
+            lam = lam.cpu().numpy() if hasattr(lam, "cpu") else lam
+            out[ws[j].name] = lambda_error(lam[:ws[j].N], r[:ws[j].N])
     return out
 
 
@@ -502,6 +590,9 @@ def serve_bench(args, prec):
                            "p50_s": float(np.percentile(lat, 50)),
                            "p99_s": float(np.percentile(lat, 99))},
            "converged": int(sum(r.status == 0 for r in reps.values()))}
+    errs = member_errors(GOLDEN_SERVE, res, reqs)
+    if errs:
+        out["lambda_rel_err_vs_oracle_ref"] = errs
     for frac in (0.5, 0.9):
         rate = frac * sat
         arrive = inputs.arrivals(len(reqs), rate, seed=5)
@@ -577,57 +668,6 @@ def nonlocal_bench(args):
     return out
 
 
-def hbm_bound_rates(args):
-    """CG kernel rates where the vectors exceed the 256 MB Infinity Cache:
-    the linear problem of the 96^3 Kohn-Sham workload (its external
-    potential, N = 32, m = 8, N_t = 40), a fixed number of ParO steps from
-    the seeded start, event-timed, mixed precision and plain FP64."""
-    import torch
-    from paper_1405_0260_amd import binding as pb
-    from paper_1405_0260_amd import inputs
-
-    dev = torch.device("cuda:0")
-    w = inputs.kohn_sham_96(nc=args.ks_nc)
-    box = pb.Box.cube(w.nc, w.lo, w.hi)
-    V = torch.from_numpy(w.V).to(dev)
-    U0 = torch.from_numpy(w.U0()).to(dev)
-    out = {"workload": f"linear_{w.nc}c_N{w.N}_m{w.m}", "n_dof": w.n_dof,
-           "paro_steps": args.hbm_steps}
-    for prec in ("mixed", "fp64"):
-        o = pb.default_opts(N=w.N, m=w.m, max_steps=args.hbm_steps,
-                            lambda_tol=1e-14, resid_tol=1e-14,
-                            pcg_rtol=1e-10, inner_rtol=args.inner_rtol,
-                            precision=pb.PARO_FP32_INNER if prec == "mixed"
-                            else pb.PARO_FP64)
-        lam = torch.zeros(w.Nt, dtype=torch.float64, device=dev)
-        U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=dev)
-        p = pb.paro_assemble(box, V, o)
-        pb.paro_set_timing(p, True)
-        pb.paro_solve(p, U0, lam, U)
-        torch.cuda.synchronize()
-        td = pb.paro_get_timing(p).as_dict()
-        vec_b = 4 if prec == "mixed" else 8
-        stages, it_bytes = cg_stage_rates(td, w.n_dof, p.nnz, vec_b)
-        cg_ms = sum(v["total_ms"] for v in stages.values())
-        sp = stages["cg_spmm"]
-        out[prec] = {
-            "spmm_gbs": round(sp["gbs"], 1),
-            "spmm_frac": round(sp["gbs"] / HBM_PEAK_GBS, 4),
-            "spmm_own_format_gbs": round(sp["own_gbs"], 1),
-            "spmm_us_per_launch": round(sp["us_per_launch"], 2),
-            "cg_stage_gbs": {k: round(v["gbs"], 1) for k, v in stages.items()},
-            "cg_iteration_gbs": round(it_bytes / (cg_ms * 1e-3) / 1e9, 1),
-            "cg_iteration_frac": round(it_bytes / (cg_ms * 1e-3) / 1e9 /
-                                       HBM_PEAK_GBS, 4),
-            "active_cols_avg": round(td["cg_col_iters"] /
-                                     max(1, td["cg_iters"]), 2)}
-        log(f"[hbm-bound {prec}] SpMM {sp['gbs']:.0f} GB/s, CG iteration "
-            f"{out[prec]['cg_iteration_gbs']:.0f} GB/s")
-        del p, U, lam
-        torch.cuda.empty_cache()
-    return out
-
-
 def ks_bench(args, prec):
     """Self-consistent Kohn-Sham around ParO on the 96^3 workload (20
     soft-Coulomb centres, N = 32 occupied orbitals, 8 buffer orbitals,
@@ -676,46 +716,88 @@ def ks_bench(args, prec):
             "min_residual": float(hist[1:rep.iterations].min())}
 
 
-def cpu_baseline(w):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    the Step-3 source solves of the first few orbitals and the Step-4
-    projection of the first ParO step from the seeded start, scaled to one
-    whole ParO step (N + m source solves + one projection)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, workers=None):
+    """The oracle, as it stands, on a bounded sample of the headline
+    workload: its first ParO step from the seeded start.
+      * all cores: the whole step (N + m source solves and the Rayleigh-
+        Ritz projection) with the oracle's worker pool for the independent
+        source problems of Step 3 (one process per usable core, at most
+        16) and the host BLAS threads for the projection;
+      * one thread: the first source solves until ~15 s have passed and the
+        projection, scaled to the whole step.
+    Throughput = n_dof * N per step time.  The first step starts from
+    random orbitals, so its CG solves take far more iterations than the
+    average step of a solve (the CG counts are reported)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import fem, paro as oparo
 
+    workers = workers or min(16, usable_cores())
+    mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+    H, M = fem.hamiltonian(mesh, w.V)
+    s = oparo.shift_from_potential(w.V)
+    maxit = 10 * w.n_dof
+    # All cores.  Step 1 (the start's Rayleigh-Ritz) is timed on its own
+    # and taken out of the one-step solve.
+    t0 = time.perf_counter()
+    oparo.rayleigh_ritz(H, M, w.U0())
+    t_start = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = oparo.paro_solve(H, M, w.U0(), w.N, sigma=s, max_steps=1,
+                         rtol=1e-10, maxit=maxit, workers=workers)
+    step_all = time.perf_counter() - t0 - t_start
+    its_all = r.pcg_iters[0]
+    # One thread.
     with threadpool_limits(limits=1):
-        mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
-        H, M = fem.hamiltonian(mesh, w.V)
-        s = oparo.shift_from_potential(w.V)
         A = (H - s * M).tocsr()
         dinv = 1.0 / A.diagonal()
         lam, U = oparo.rayleigh_ritz(H, M, w.U0())
         MU = M @ U
         k = 0
         t0 = time.perf_counter()
-        its = []
         W = U.copy()
-        while k < w.Nt and (time.perf_counter() - t0 < 15.0 or k < 2):
+        while k < w.Nt and (time.perf_counter() - t0 < 15.0 or k < 1):
             b = (lam[k] - s) * MU[:, k]
-            W[:, k], it = oparo.jacobi_pcg(A, b, U[:, k], dinv, 1e-10,
-                                           10 * A.shape[0])
-            its.append(it)
+            W[:, k], _ = oparo.jacobi_pcg(A, b, U[:, k], dinv, 1e-10, maxit)
             k += 1
         t_solve = (time.perf_counter() - t0) / k
         t1 = time.perf_counter()
         oparo.rayleigh_ritz(H, M, W)
         t_rr = time.perf_counter() - t1
-    step = t_solve * w.Nt + t_rr
-    return {"value": w.n_dof * w.N / step, "unit": "orbital-updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"first ParO step of the same workload from the "
-                      f"seeded start: {k} of {w.Nt} source solves "
-                      f"(Jacobi-PCG, {int(np.mean(its))} iterations each on "
-                      f"average) and the Rayleigh-Ritz projection, scaled "
-                      f"to one step; numpy/scipy, 1 thread",
-            "seconds_per_paro_step": step}
+    step_one = t_solve * w.Nt + t_rr
+    return {"value": w.n_dof * w.N / step_all, "unit": "orbital-updates/s",
+            "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cores": usable_cores(),
+            "sample": f"first ParO step of the headline workload from the "
+                      f"seeded start: {w.Nt} Jacobi-PCG source solves "
+                      f"({int(np.mean(its_all))} CG iterations each on "
+                      f"average, {int(np.max(its_all))} at most) over "
+                      f"{workers} worker processes, then the Rayleigh-Ritz "
+                      f"projection; numpy/scipy",
+            "seconds_per_paro_step": step_all,
+            "one_thread": {
+                "value": w.n_dof * w.N / step_one,
+                "unit": "orbital-updates/s", "cores": 1,
+                "sample": f"{k} of the same {w.Nt} source solves and the "
+                          f"projection, scaled to the whole step",
+                "seconds_per_paro_step": step_one}}
 
 
 if __name__ == "__main__":

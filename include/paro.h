@@ -99,19 +99,28 @@ typedef struct paro_problem paro_problem;   /* opaque, host memory only */
 void paro_default_opts(paro_opts_t* opts);
 
 /* Sizes for a box and options, host only.  n_dof = (nx-1)(ny-1)(nz-1);
- * nnz = number of stored entries of the 15-point Kuhn P1 pattern;
+ * nnz = number of nonzeros of the 15-point Kuhn P1 pattern (the size of
+ * the CSR copy paro_export_csr writes);
  * workspace_bytes = device memory paro_assemble needs (the whole resident
- * footprint of the problem: matrices, solver blocks, reductions).
+ * footprint of the problem: stencil-order matrices, solver blocks,
+ * reductions; no CSR copy).
  * Any output pointer may be NULL. */
 int paro_query(const paro_box_t* box, const paro_opts_t* opts,
                int64_t* n_dof, int64_t* nnz, size_t* workspace_bytes);
 
 /* Assemble the source-problem operator on the device (Sec. 2 finite
  * elements; eq. (eq-operator-A) with the potential fixed):
- *   A_s = K/2 + M_V - s M (CSR, FP64 and an FP32 copy), M (CSR, FP64),
- *   the Jacobi diagonal of A_s,
+ *   A_s = K/2 + M_V - s M (FP64, and an FP32 copy in PARO_FP32_INNER
+ *   mode), M (FP64), the inverse of the diagonal of A_s,
  * with K the P1 stiffness, M the consistent mass and M_V the mass weighted
- * by the nodal interpolant of V, integrated exactly.
+ * by the nodal interpolant of V, integrated exactly.  Storage is stencil
+ * order, not CSR: on the uniform Kuhn mesh every interior row couples to
+ * the same 15 neighbour offsets (the row itself, the 6 axis neighbours,
+ * the 6 face diagonals +-(1,1,0), +-(1,0,1), +-(0,1,1) and the 2 body
+ * diagonals +-(1,1,1)), so a matrix is 15 arrays of n_dof coefficients
+ * (coefficient s of row r at [s][r], 0 where the neighbour lies outside
+ * the box) and needs no column indices or row pointers.  A CSR copy is
+ * made only on request (paro_export_csr).
  *   d_V: (nx+1)(ny+1)(nz+1) nodal potential values, x fastest, all vertices
  *        including the boundary (device pointer, FP64).
  *   d_workspace/bytes: caller-owned device memory of at least
@@ -138,9 +147,10 @@ int paro_init(paro_problem* p, const double* d_U0, double* d_lambda,
  * reads (lambda^n, U^n) from d_lambda / d_U and overwrites them with
  * (lambda^{n+1}, U^{n+1}).  The Nt source problems
  *   (H - s M) w_i = (lambda_i - s) M u_i,   w_i^0 = u_i
- * are solved by Jacobi-preconditioned CG (one CSR pass per CG iteration
- * serves all Nt columns) to ||r_i|| <= pcg_rtol ||b_i||, then Rayleigh-Ritz
- * on span W.  A pure function of (lambda, U) and the problem.
+ * are solved by Jacobi-preconditioned CG (one pass over the stencil
+ * coefficients per CG iteration serves all Nt columns; each column keeps
+ * its own alpha, beta and stopping test) to ||r_i|| <= pcg_rtol ||b_i||,
+ * then Rayleigh-Ritz on span W.  A pure function of (lambda, U) and the problem.
  * If `report` is NULL the call is asynchronous on `stream` except for the
  * CG loop's convergence polling (one 4-byte read every few iterations);
  * otherwise it synchronises and fills `report` for this step. */
@@ -337,8 +347,11 @@ const char* paro_strerror(int status);
  * used for kernel-level checking and measurement).  All asynchronous.
  * --------------------------------------------------------------------- */
 
-/* Copy the assembled CSR (rowptr int32[n+1], col int32[nnz], A_s and M
- * values FP64[nnz]) into caller device buffers; also the shift. */
+/* Write the assembled A_s and M in CSR form (rowptr int32[n+1],
+ * col int32[nnz] ascending within a row, values FP64[nnz]) into caller
+ * device buffers, built from the stencil-order arrays by one kernel (the
+ * workspace holds no CSR copy); any of the four may be NULL.  Also the
+ * shift (h_sigma, nullable).  Asynchronous on `stream`. */
 int paro_export_csr(paro_problem* p, int32_t* d_rowptr, int32_t* d_col,
                     double* d_valA, double* d_valM, double* h_sigma,
                     void* stream);

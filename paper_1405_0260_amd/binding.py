@@ -366,7 +366,8 @@ def paro_pcg(p: Problem, B, X, stream=None):
 
 
 def paro_set_graphs(on: bool = True):
-    """Run CG chunks as captured HIP graphs (default) or kernel by kernel."""
+    """Run CG chunks as captured HIP graphs (on) or kernel by kernel (off,
+    the default); process-wide."""
     lib().paro_set_graphs(1 if on else 0)
 
 

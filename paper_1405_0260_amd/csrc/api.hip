@@ -85,9 +85,11 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b) {
 // shape, the precision, the starting parity and the chunk length.  The
 // kernels read their descriptors from device memory at run time, so a
 // graph stays valid while the launch shape (table address, grid, vector
-// widths, problem count) is unchanged.
+// widths, problem count, nonlocal projector count, SpMM segmentation) is
+// unchanged.
+typedef std::array<int64_t, 18> GraphKey;
 struct GraphCache {
-  std::map<std::array<int64_t, 12>, hipGraphExec_t> m;
+  std::map<GraphKey, hipGraphExec_t> m;
   ~GraphCache() {
     for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
   }
@@ -168,11 +170,6 @@ int check_opts(const paro_opts_t* o, int64_t n) {
 
 void carve(Problem& p, char* base, const Layout& L) {
   auto at = [&](size_t off) { return (void*)(base + off); };
-  p.rowptr = (int32_t*)at(L.rowptr);
-  p.col = (int32_t*)at(L.col);
-  p.valA = (double*)at(L.valA);
-  p.valM = (double*)at(L.valM);
-  p.valA32 = L.valA32 ? (float*)at(L.valA32) : nullptr;
   p.dinv = (double*)at(L.dinv);
   p.dinv32 = L.dinv32 ? (float*)at(L.dinv32) : nullptr;
   p.diagA = (double*)at(L.diagA);
@@ -238,11 +235,6 @@ void desc_init(Problem& p) {
   d.sigma = p.sigma;
   d.rtol = p.opts.pcg_rtol;
   d.inner_rtol = p.opts.inner_rtol;
-  d.rowptr = p.rowptr;
-  d.col = p.col;
-  d.valA = p.valA;
-  d.valM = p.valM;
-  d.valA32 = p.valA32;
   d.dinv = p.dinv;
   d.dinv32 = p.dinv32;
   d.diagA = p.diagA;
@@ -391,9 +383,14 @@ hipStream_t capture_stream() {
 // Launch `k` CG iterations from parity `par` as one cached graph.
 int cg_graph(Ctx& c, bool fp32, int par, int k, hipStream_t s) {
   const Launch& L = c.L;
-  const std::array<int64_t, 12> key = {
+  // Every Launch field that selects a kernel, an instantiation or a grid
+  // of launch_pcg_iter is part of the key (the nonlocal term's projector
+  // count and the segmented SpMM included), so a change of any of them
+  // captures a new graph instead of replaying a stale one.
+  const GraphKey key = {
       (int64_t)(uintptr_t)L.d, L.nprob, L.blocks, L.gblocks, L.maxcols,
-      L.v64u, L.v32u, L.tr64, L.tr32, fp32 ? 1 : 0, par, k};
+      L.mincols, L.nt16, L.tr64, L.tr32, L.vmax64, L.v64u, L.v32u,
+      L.nt16_mixed, L.maxkz, L.seg, fp32 ? 1 : 0, par, k};
   auto it = c.graphs->m.find(key);
   if (it == c.graphs->m.end()) {
     hipStream_t cs = capture_stream();
@@ -845,6 +842,7 @@ int autotune(Problem& p, hipStream_t s) {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
+  (void)nnz;  // the stencil arrays do not depend on the pattern's size
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -854,11 +852,6 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   };
   const bool f32 = precision == PARO_FP32_INNER;
   const size_t blk = (size_t)n * Nt;
-  L.rowptr = take(sizeof(int32_t) * (n + 1));
-  L.col = take(sizeof(int32_t) * nnz);
-  L.valA = take(sizeof(double) * nnz);
-  L.valM = take(sizeof(double) * nnz);
-  L.valA32 = f32 ? take(sizeof(float) * nnz) : 0;
   L.dinv = take(sizeof(double) * n);
   L.dinv32 = f32 ? take(sizeof(float) * n) : 0;
   L.diagA = take(sizeof(double) * kStencil * n);
@@ -1472,18 +1465,8 @@ int paro_export_csr(paro_problem* h, int32_t* d_rowptr, int32_t* d_col,
   if (!h) return fail(PARO_EINVAL, "NULL problem");
   Problem& p = h->p;
   hipStream_t s = (hipStream_t)stream;
-  if (d_rowptr)
-    HIP_OR_FAIL(hipMemcpyAsync(d_rowptr, p.rowptr, 4 * (p.n + 1),
-                               hipMemcpyDeviceToDevice, s));
-  if (d_col)
-    HIP_OR_FAIL(hipMemcpyAsync(d_col, p.col, 4 * p.nnz,
-                               hipMemcpyDeviceToDevice, s));
-  if (d_valA)
-    HIP_OR_FAIL(hipMemcpyAsync(d_valA, p.valA, 8 * p.nnz,
-                               hipMemcpyDeviceToDevice, s));
-  if (d_valM)
-    HIP_OR_FAIL(hipMemcpyAsync(d_valM, p.valM, 8 * p.nnz,
-                               hipMemcpyDeviceToDevice, s));
+  if (d_rowptr || d_col || d_valA || d_valM)
+    HIP_OR_FAIL(launch_csr_export(p, d_rowptr, d_col, d_valA, d_valM, s));
   if (h_sigma) *h_sigma = p.sigma;
   return PARO_OK;
 }

@@ -106,47 +106,21 @@ __device__ __forceinline__ bool valid(int i, int o, int m) {
 __global__ void __launch_bounds__(kBlock)
 assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
                 int mz, double hx, double hy, double hz, double sigma,
-                int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                double* __restrict__ valA, double* __restrict__ valM,
-                float* __restrict__ valA32, double* __restrict__ dinv,
-                float* __restrict__ dinv32, double* __restrict__ diagA,
-                double* __restrict__ diagM, float* __restrict__ diagA32) {
+                double* __restrict__ dinv, float* __restrict__ dinv32,
+                double* __restrict__ diagA, double* __restrict__ diagM,
+                float* __restrict__ diagA32) {
   const long long n = (long long)mx * my * mz;
   const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d > n) return;
+  if (d >= n) return;
   const int nvx = mx + 2, nvy = my + 2;
-
-  if (d == n) {  // closing row pointer
-    long long tot = 0;
-    for (int s = 0; s < kStencil; ++s)
-      tot += prefix_valid(mx, kOff[s][0], mx) *
-             prefix_valid(my, kOff[s][1], my) *
-             prefix_valid(mz, kOff[s][2], mz);
-    rowptr[n] = (int32_t)tot;
-    return;
-  }
   const int i = (int)(d % mx);
   const int j = (int)((d / mx) % my);
   const int k = (int)(d / ((long long)mx * my));
-
-  // Closed-form prefix: rows before (i, j, k) in x-fastest order.
-  long long start = 0;
-  for (int s = 0; s < kStencil; ++s) {
-    const int ox = kOff[s][0], oy = kOff[s][1], oz = kOff[s][2];
-    const long long tx = prefix_valid(mx, ox, mx);
-    const long long ty = prefix_valid(my, oy, my);
-    const long long fz = valid(k, oz, mz), fy = valid(j, oy, my);
-    start += prefix_valid(k, oz, mz) * ty * tx +
-             fz * prefix_valid(j, oy, my) * tx +
-             fz * fy * prefix_valid(i, ox, mx);
-  }
-  rowptr[d] = (int32_t)start;
 
   const double vol = hx * hy * hz / 6.0;
   const double hv[3] = {hx, hy, hz};
   const int I = i + 1, J = j + 1, K = k + 1;  // vertex indices
 
-  int slot = (int)start;
   for (int s = 0; s < kStencil; ++s) {
     const int ox = kOff[s][0], oy = kOff[s][1], oz = kOff[s][2];
     if (!valid(i, ox, mx) || !valid(j, oy, my) || !valid(k, oz, mz)) {
@@ -214,10 +188,6 @@ assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
       a_sum += 0.5 * kab + mvab - sigma * mab;
       m_sum += mab;
     }
-    col[slot] = (int32_t)(d + ox + (long long)mx * (oy + (long long)my * oz));
-    valA[slot] = a_sum;
-    valM[slot] = m_sum;
-    if (valA32) valA32[slot] = (float)a_sum;
     diagA[(size_t)s * n + d] = a_sum;
     diagM[(size_t)s * n + d] = m_sum;
     if (diagA32) diagA32[(size_t)s * n + d] = (float)a_sum;
@@ -225,6 +195,56 @@ assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
       dinv[d] = 1.0 / a_sum;
       if (dinv32) dinv32[d] = (float)(1.0 / a_sum);
     }
+  }
+}
+
+// CSR copy of the stencil-order matrices (row d = thread d, plus the
+// closing row pointer): the entries of a row are its in-box neighbours in
+// stencil order, which is ascending column order; the row's first slot
+// comes from a closed-form count of the entries of the rows before it.
+// Any output may be null.
+__global__ void __launch_bounds__(kBlock)
+csr_export_kernel(int mx, int my, int mz, const double* __restrict__ diagA,
+                  const double* __restrict__ diagM,
+                  int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                  double* __restrict__ valA, double* __restrict__ valM) {
+  const long long n = (long long)mx * my * mz;
+  const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d > n) return;
+  if (d == n) {  // closing row pointer
+    long long tot = 0;
+    for (int s = 0; s < kStencil; ++s)
+      tot += prefix_valid(mx, kOff[s][0], mx) *
+             prefix_valid(my, kOff[s][1], my) *
+             prefix_valid(mz, kOff[s][2], mz);
+    if (rowptr) rowptr[n] = (int32_t)tot;
+    return;
+  }
+  const int i = (int)(d % mx);
+  const int j = (int)((d / mx) % my);
+  const int k = (int)(d / ((long long)mx * my));
+  // Rows before (i, j, k) in x-fastest order, offset by offset.
+  long long start = 0;
+  for (int s = 0; s < kStencil; ++s) {
+    const int ox = kOff[s][0], oy = kOff[s][1], oz = kOff[s][2];
+    const long long tx = prefix_valid(mx, ox, mx);
+    const long long ty = prefix_valid(my, oy, my);
+    const long long fz = valid(k, oz, mz), fy = valid(j, oy, my);
+    start += prefix_valid(k, oz, mz) * ty * tx +
+             fz * prefix_valid(j, oy, my) * tx +
+             fz * fy * prefix_valid(i, ox, mx);
+  }
+  if (rowptr) rowptr[d] = (int32_t)start;
+  long long slot = start;
+  for (int s = 0; s < kStencil; ++s) {
+    const int ox = kOff[s][0], oy = kOff[s][1], oz = kOff[s][2];
+    if (!valid(i, ox, mx) || !valid(j, oy, my) || !valid(k, oz, mz))
+      continue;
+    if (col)
+      col[slot] =
+          (int32_t)(d + ox + (long long)mx * (oy + (long long)my * oz));
+    if (valA) valA[slot] = diagA[(size_t)s * n + d];
+    if (valM) valM[slot] = diagM[(size_t)s * n + d];
     ++slot;
   }
 }
@@ -297,12 +317,20 @@ hipError_t launch_potential_range(const double* V, int64_t nv, double* out,
 
 hipError_t launch_assemble(Problem& p, const double* V, hipStream_t s) {
   static const Incidence inc = build_incidence();
-  const long long rows = p.n + 1;
-  const int grid = (int)((rows + kBlock - 1) / kBlock);
+  const int grid = (int)((p.n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(assemble_kernel, dim3(grid), dim3(kBlock), 0, s, inc, V,
                      p.mx, p.my, p.mz, p.h[0], p.h[1], p.h[2], p.sigma,
-                     p.rowptr, p.col, p.valA, p.valM, p.valA32, p.dinv,
-                     p.dinv32, p.diagA, p.diagM, p.diagA32);
+                     p.dinv, p.dinv32, p.diagA, p.diagM, p.diagA32);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_export(const Problem& p, int32_t* rowptr, int32_t* col,
+                             double* valA, double* valM, hipStream_t s) {
+  const long long rows = p.n + 1;
+  const int grid = (int)((rows + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(csr_export_kernel, dim3(grid), dim3(kBlock), 0, s, p.mx,
+                     p.my, p.mz, (const double*)p.diagA,
+                     (const double*)p.diagM, rowptr, col, valA, valM);
   return hipGetLastError();
 }
 

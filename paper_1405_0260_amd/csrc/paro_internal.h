@@ -105,11 +105,6 @@ struct Desc {
   int v64, v32;           // columns per thread
   double sigma, rtol, inner_rtol;
   double s1;              // component SpMM: Y1 = A X + s1 M X
-  const int32_t* rowptr;
-  const int32_t* col;
-  const double* valA;     // A_s
-  const double* valM;
-  const float* valA32;
   const double* dinv;
   const float* dinv32;
   const double* diagA;    // stencil order: [kStencil][n], 0 outside the box
@@ -254,11 +249,6 @@ struct Problem {
   double h[3];
   int grid;               // persistent grid (workgroups) of the solvers
   // device memory, carved from the caller's workspace
-  int32_t* rowptr;
-  int32_t* col;
-  double* valA;           // A_s = K/2 + M_V - s M
-  double* valM;           // M
-  float* valA32;          // FP32 copy of A_s
   double* dinv;           // 1 / diag(A_s)
   float* dinv32;
   double* diagA;          // A_s, M (and FP32 A_s) in stencil order
@@ -310,8 +300,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 
 // Workspace layout: byte offsets of every region for a problem shape.
 struct Layout {
-  size_t rowptr, col, valA, valM, valA32, dinv, dinv32, diagA, diagM,
-      diagA32;
+  size_t dinv, dinv32, diagA, diagM, diagA32;
   size_t X, R, P, Q, B, HU, MU, Xc, R32, P32, Q32, X32;
   size_t part, cpart, gpart, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
@@ -335,6 +324,10 @@ int64_t kuhn_nnz(int mx, int my, int mz);
 hipError_t launch_potential_range(const double* V, int64_t nv, double* out,
                                   unsigned* cnt, double* part, hipStream_t s);
 hipError_t launch_assemble(Problem& p, const double* V, hipStream_t s);
+// CSR copy of the problem's A_s and M into caller buffers (any may be
+// null): rowptr int32[n + 1], col int32[nnz], valA, valM FP64[nnz].
+hipError_t launch_csr_export(const Problem& p, int32_t* rowptr, int32_t* col,
+                             double* valA, double* valM, hipStream_t s);
 
 // ---- launchers (solver.hip) ----------------------------------------------
 // All take a Launch over a descriptor table; a single problem is a table of

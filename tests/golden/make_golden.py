@@ -101,8 +101,53 @@ def linear_96c(nc=96, workers=None):
          f"({time.time() - t:.0f} s, {workers} worker processes)")
 
 
+def _member_lowest(name, ws, members, title):
+    """Lowest N eigenvalues of the chosen members of a problem list
+    (shift-invert Lanczos about the oracle's shift), one line per member:
+    'j lam_1 ... lam_N'."""
+    lines = []
+    for j in members:
+        w = ws[j]
+        mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+        H, M = fem.hamiltonian(mesh, w.V)
+        s = paro.shift_from_potential(w.V) - 0.5
+        # Lanczos can miss a copy of a degenerate eigenvalue near the end
+        # of the wanted range: ask for the whole buffered range plus more,
+        # twice with different counts, and keep the N lowest only if the
+        # two agree.
+        lam, _ = reference.sparse_lowest(H, M, w.Nt + 2, s)
+        lam2, _ = reference.sparse_lowest(H, M, w.Nt + 6, s)
+        assert np.allclose(lam[:w.N], lam2[:w.N], rtol=1e-12, atol=0), \
+            (w.name, lam[:w.N], lam2[:w.N])
+        lines.append(f"{j} " + " ".join(f"{x:.17g}" for x in lam[:w.N]))
+        print(f"  {w.name}: {lam[:min(3, w.N)]}", flush=True)
+    path = os.path.join(HERE, name)
+    with open(path, "w") as f:
+        f.write(f"# {title}\n# oracle.reference.sparse_lowest (shift-invert "
+                "Lanczos about the oracle's shift - 0.5), lowest N per member"
+                "\n# line: member index, then its N requested eigenvalues\n"
+                "# written by: python tests/golden/make_golden.py\n")
+        f.write("\n".join(lines) + "\n")
+    print("wrote", path)
+
+
+def batch_sample():
+    _member_lowest("batch64_sample_lowest.txt", inputs.batch_64(),
+                   [3, 7, 15, 22, 26, 44, 47],
+                   "Sampled members of the 64-problem uneven batch "
+                   "(paper_1405_0260_amd.inputs.batch_64)")
+
+
+def serve_sample():
+    _member_lowest("serve_sample_lowest.txt", inputs.serve_requests(64),
+                   [1, 2, 10, 14, 18],
+                   "Sampled requests of the served stream "
+                   "(paper_1405_0260_amd.inputs.serve_requests(64))")
+
+
 JOBS = {"harmonic_48c": harmonic_48c, "harmonic_24c": harmonic_24c,
-        "molecule_64c": molecule_64c, "linear_96c": linear_96c}
+        "molecule_64c": molecule_64c, "linear_96c": linear_96c,
+        "batch_sample": batch_sample, "serve_sample": serve_sample}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(JOBS)):

@@ -6,6 +6,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -68,18 +69,40 @@ def test_traffic_summary_is_tied_to_the_source(tmp_path, monkeypatch):
     src.write_text("int a;  // one\n\n/* block\ncomment */ int b;\n")
 
     traffic = tmp_path / "traffic.md"
-    monkeypatch.setattr(bench, "TRAFFIC", str(traffic))
     traffic.write_text(_summary(sha, [
         "traffic_bytes_per_launch[spmm_cm_kernel]: 1234",
         "traffic_bytes_per_launch[pupd_beta_kernel]: 5678"]))
-    assert bench.measured_traffic("spmm_cm_kernel") == 1234.0
-    assert bench.measured_traffic("pupd_beta_kernel") == 5678.0
-    assert bench.measured_traffic("rupd_alpha_kernel") is None
+    path = str(traffic)
+    assert bench.measured_traffic("spmm_cm_kernel", path) == 1234.0
+    assert bench.measured_traffic("pupd_beta_kernel", path) == 5678.0
+    assert bench.measured_traffic("rupd_alpha_kernel", path) is None
     traffic.write_text(_summary("0" * 64, [
         "traffic_bytes_per_launch[spmm_cm_kernel]: 1234"]))
-    assert bench.measured_traffic("spmm_cm_kernel") is None
+    assert bench.measured_traffic("spmm_cm_kernel", path) is None
     os.remove(traffic)
-    assert bench.measured_traffic("spmm_cm_kernel") is None
+    assert bench.measured_traffic("spmm_cm_kernel", path) is None
+
+
+def test_lambda_error_uses_the_floor():
+    ref = [-2.0, 0.0, 1.0]
+    assert bench.lambda_error([-2.0, 1e-6, 1.0], ref) == 1e-6 / 2e-3
+    assert bench.lambda_error(ref, ref) == 0.0
+
+
+def test_member_golden_format(tmp_path):
+    g = tmp_path / "members.txt"
+    g.write_text("# header\n3 -1.5 -1.25\n7 2.5\n")
+    ref = bench.read_member_golden(str(g))
+    assert set(ref) == {3, 7} and np.array_equal(ref[3], [-1.5, -1.25])
+
+    class W:
+        def __init__(self, name, N):
+            self.name, self.N = name, N
+    ws = {3: W("a", 2), 7: W("b", 1)}
+    errs = bench.member_errors(str(g), {3: np.array([-1.5, -1.25, 9.0]),
+                                        7: np.array([2.5 * (1 + 1e-9)])},
+                               ws)
+    assert errs["a"] == 0.0 and abs(errs["b"] - 1e-9) < 1e-15
 
 
 def test_more_than_one_gpu_is_refused():
