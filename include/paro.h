@@ -462,17 +462,28 @@ int paro_nonlocal_query(const paro_problem* p, int32_t k, size_t* bytes);
 int paro_set_nonlocal(paro_problem* p, const double* d_zeta, int32_t k,
                       void* d_ws, size_t bytes, void* stream);
 
-/* Autotuner (on by default): at assembly, the CG SpMM of each new problem
- * shape (grid, N + m, precision) is timed with the full and the halved
- * real block count, and the faster is kept for the shape for the rest of
+/* CG SpMM forms.  Meshes up to 2048 tiles of 248 rows sweep the rows in
+ * tile order.  Larger meshes whose planes span at most 256 tiles march
+ * along z instead: a unit owns a tile of one plane, a range of planes and
+ * a group of column chunks, keeps the neighbour lines of the previous
+ * plane in registers and loads only the new ones, so each value of the
+ * search direction is read from memory about once per iteration instead
+ * of three times; p.q partials are kept per (plane range, tile).
+ *
+ * Autotuner (on by default): at assembly, the CG SpMM of each new problem
+ * shape (grid, N + m, precision) is timed for every variant -- the
+ * z-marching SpMM with 1, 2 or 4 chunks per unit (variants 0, 1, 2), the
+ * row sweep with one (variant 0) -- each with the full and the halved
+ * real block count, and the fastest is kept for the shape for the rest of
  * the process.  The choice never changes the arithmetic or the results
- * (reductions run over per-tile partial sums fixed by the problem).
+ * (the reductions run over partial sums fixed by the mesh).
  * paro_set_autotune(0) keeps the defaults; paro_tuned reports a problem's
- * real block count (and a reserved variant field: -1 untuned, else 0). */
+ * variant (-1 untuned) and real block count. */
 void paro_set_autotune(int on);
 int paro_tuned(const paro_problem* p, int32_t* variant, int32_t* blocks);
-/* Pin a problem's real block count (a multiple of 8, at most its
- * reduction segment count); variant is reserved and must be -1 or 0. */
+/* Pin a problem's SpMM variant (-1 default, 0, or for a z-marching
+ * problem also 1 or 2) and real block count (a multiple of 8, at most its
+ * reduction segment count).  PARO_EINVAL otherwise. */
 int paro_set_tuning(paro_problem* p, int32_t variant, int32_t blocks);
 
 /* Turn per-launch event timing on (1) or off (0); clears the sums. */

@@ -412,14 +412,17 @@ def paro_set_autotune(on: bool = True):
 
 
 def paro_tuned(p: Problem):
-    """(reserved variant field, real block count) chosen for the problem."""
+    """(SpMM variant, real block count) chosen for the problem: variant -1
+    untuned, 0 for the row-sweep SpMM, 0/1/2 (1, 2 or 4 chunks per unit)
+    for the z-marching one."""
     v, b = c_i32(), c_i32()
     _check(lib().paro_tuned(p.handle, ctypes.byref(v), ctypes.byref(b)))
     return v.value, b.value
 
 
 def paro_set_tuning(p: Problem, variant: int, blocks: int):
-    """Pin the real block count of a problem (variant: -1 or 0)."""
+    """Pin the SpMM variant and real block count of a problem (variant -1 or
+    0; up to 2 for a z-marching problem)."""
     _check(lib().paro_set_tuning(p.handle, variant, blocks))
 
 

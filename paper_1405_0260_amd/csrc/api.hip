@@ -87,7 +87,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b) {
 // graph stays valid while the launch shape (table address, grid, vector
 // widths, problem count, nonlocal projector count, SpMM segmentation) is
 // unchanged.
-typedef std::array<int64_t, 18> GraphKey;
+typedef std::array<int64_t, 21> GraphKey;
 struct GraphCache {
   std::map<GraphKey, hipGraphExec_t> m;
   ~GraphCache() {
@@ -266,6 +266,12 @@ void desc_init(Problem& p) {
   d.spt = (int)spmm_tiles(p.n);
   d.spg = spmm_seg_tiles(p.n);
   d.pqn = spmm_segments(p.n);
+  d.zm = zm_ranges(p.mx, p.my, p.mz);
+  d.zxy = (int)(((long long)p.mx * p.my + kSpmmRows - 1) / kSpmmRows);
+  if (d.zm) {
+    d.pqn = d.zm * d.zxy;
+    d.spg = 1;
+  }
   d.part = p.part;
   d.gpart = p.gpart;
   d.Ah = p.Ah;
@@ -309,7 +315,20 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
   }
   L.nt16 = (L.maxcols + 15) / 16;
   for (int i = 0; i < n; ++i) L.maxkz = std::max(L.maxkz, tab[i].kz);
-  for (int i = 0; i < n; ++i) L.seg |= tab[i].spg > 1 ? 1 : 0;
+  L.zmg = 0;
+  for (int i = 0; i < n; ++i) {
+    const Desc& d = tab[i];
+    if (d.zm) {
+      L.zm = 1;
+      // Chunks per unit: the first z-marching problem's tuned variant
+      // (any choice gives the same results).
+      if (L.zmg == 0) L.zmg = d.cg_var >= 0 ? 1 << d.cg_var : 2;
+    } else {
+      L.ntile = 1;
+      L.seg |= d.spg > 1 ? 1 : 0;
+    }
+  }
+  if (L.zmg == 0) L.zmg = 2;
   L.v64u = n > 0 ? tab[0].v64 : 0;
   L.v32u = n > 0 ? tab[0].v32 : 0;
   for (int i = 1; i < n; ++i) {
@@ -390,7 +409,8 @@ int cg_graph(Ctx& c, bool fp32, int par, int k, hipStream_t s) {
   const GraphKey key = {
       (int64_t)(uintptr_t)L.d, L.nprob, L.blocks, L.gblocks, L.maxcols,
       L.mincols, L.nt16, L.tr64, L.tr32, L.vmax64, L.v64u, L.v32u,
-      L.nt16_mixed, L.maxkz, L.seg, fp32 ? 1 : 0, par, k};
+      L.nt16_mixed, L.maxkz, L.seg, L.ntile, L.zm, L.zmg, fp32 ? 1 : 0,
+      par, k};
   auto it = c.graphs->m.find(key);
   if (it == c.graphs->m.end()) {
     hipStream_t cs = capture_stream();
@@ -570,7 +590,7 @@ int run_cg_persistent(Ctx& c, bool fp32, hipStream_t s, int slot) {
 }
 
 int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
-  if (g_persistent_on.load() && c.L.maxkz == 0) {
+  if (g_persistent_on.load() && c.L.maxkz == 0 && c.L.zm == 0) {
     const int rc = run_cg_persistent(c, fp32, s, slot);
     if (rc != 1) return rc;  // 1: does not fit, run kernel by kernel
   }
@@ -764,11 +784,13 @@ int batch_ctx(Ctx& c, paro_problem* const* probs, int count, void* ws,
 }
 
 // Autotuner of the CG SpMM: for a problem shape (grid, columns,
-// precision) time every kernel variant with the full and the halved real
-// block count on the problem's own operator (all columns active, scratch
-// vectors), keep the fastest, and cache it for the process.  Neither
-// choice changes the arithmetic: variants differ only in staging and
-// gather depth, and the reduction segments stay the problem's own.
+// precision) time every kernel variant (the z-marching SpMM with 1, 2 or
+// 4 chunks per unit; the row sweep has one) with the full and the halved
+// real block count on the problem's own operator (all columns active,
+// scratch vectors), keep the fastest, and cache it for the process.  No
+// choice changes the arithmetic: a variant only decides which columns a
+// unit serves, the block count which block serves a unit, and the
+// reduction segments stay the problem's own.
 std::atomic<int> g_autotune_on{1};
 std::mutex g_tune_mu;
 std::map<std::array<int, 5>, std::pair<int, int>> g_tune;
@@ -804,27 +826,33 @@ int autotune(Problem& p, hipStream_t s) {
   }
   const int ns = p.hd.ns;
   const int half = std::max(8, ns / 2 / 8 * 8);
+  // Variants: the row-sweep SpMM has one (0); the z-marching one serves
+  // 1, 2 or 4 chunks per unit (variant log2 of that).
+  const int nvar = p.hd.zm ? 3 : 1;
   float best = 1e30f;
   int best_var = 0, best_nb = ns;
   hipError_t err = hipSuccess;
-  for (int nb : {ns, half}) {
-    if (nb == half && half == ns) continue;
-    c.tab[0].nb = nb;
-    if ((rc = upload(c, s)) != PARO_OK) break;
-    if ((err = launch_cg_spmm(c.L, fp32, s)) != hipSuccess) break;
-    if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
-    for (int k = 0; k < 5 && err == hipSuccess; ++k)
-      err = launch_cg_spmm(c.L, fp32, s);
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (err != hipSuccess) break;
-    if (ms < best) {
-      best = ms;
-      best_nb = nb;
+  for (int var = 0; var < nvar && err == hipSuccess && rc == PARO_OK; ++var)
+    for (int nb : {ns, half}) {
+      if (nb == half && half == ns) continue;
+      c.tab[0].nb = nb;
+      c.tab[0].cg_var = var;
+      if ((rc = upload(c, s)) != PARO_OK) break;
+      if ((err = launch_cg_spmm(c.L, fp32, s)) != hipSuccess) break;
+      if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+      for (int k = 0; k < 5 && err == hipSuccess; ++k)
+        err = launch_cg_spmm(c.L, fp32, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (ms < best) {
+        best = ms;
+        best_nb = nb;
+        best_var = var;
+      }
     }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
@@ -1398,8 +1426,10 @@ void paro_set_autotune(int on) { g_autotune_on.store(on ? 1 : 0); }
 int paro_set_tuning(paro_problem* h, int32_t variant, int32_t blocks) {
   if (!h) return fail(PARO_EINVAL, "NULL problem");
   Problem& p = h->p;
-  if (variant < -1 || variant > 0)
-    return fail(PARO_EINVAL, "variant must be -1 or 0");
+  const int vmax = p.hd.zm ? 2 : 0;
+  if (variant < -1 || variant > vmax)
+    return fail(PARO_EINVAL, "variant must be in [-1, %d] for this problem",
+                vmax);
   if (blocks < 8 || blocks > p.hd.ns || blocks % 8)
     return fail(PARO_EINVAL, "blocks must be a multiple of 8 in [8, %d]",
                 p.hd.ns);

@@ -135,6 +135,9 @@ struct Desc {
   double* cgp;            // ... and where they are (part, or cpart)
   int pqn;                // partials per column of p.q (CG SpMM segments)
   int spt, spg;           // SpMM tiles, and tiles per p.q segment
+  int zm;                 // z-marching CG SpMM: plane ranges (a multiple
+                          // of 8), or 0 (row sweep)
+  int zxy;                // ... and xy tiles of kSpmmRows rows per plane
   double* pqp;            // ... and where they are
   double* Y1;             // component SpMM / Gram operands
   double* Y2;
@@ -186,6 +189,22 @@ constexpr int kSpmmSlabSegs = 128;
 __host__ __device__ constexpr long long spmm_tiles(long long n) {
   return (n + kSpmmRows - 1) / kSpmmRows;
 }
+// Plane ranges of the z-marching CG SpMM for an mx x my x mz grid: used
+// where the row sweep would need slab segments (more than kSpmmSegMax
+// tiles), with at least 384 segments (plane range, xy tile) so that one
+// active chunk group still spreads over the GPU, at most kSpmmSegMax, and
+// at least 3 planes per range; 0 where that is not possible (the row
+// sweep serves the problem).
+inline int zm_ranges(int mx, int my, int mz) {
+  const long long plane = (long long)mx * my;
+  const long long nxy = (plane + kSpmmRows - 1) / kSpmmRows;
+  const long long tiles = (plane * mz + kSpmmRows - 1) / kSpmmRows;
+  if (tiles <= kSpmmSegMax || nxy * 8 > kSpmmSegMax) return 0;
+  long long nzr = 8 * ((384 + 8 * nxy - 1) / (8 * nxy));
+  while (nzr * nxy > kSpmmSegMax) nzr -= 8;
+  if (nzr > mz / 3) nzr = (mz / 3) / 8 * 8;
+  return nzr < 8 ? 0 : (int)nzr;
+}
 __host__ __device__ constexpr int spmm_segments(long long n) {
   return spmm_tiles(n) <= kSpmmSegMax ? (int)spmm_tiles(n)
                                       : kSpmmSlabs * kSpmmSlabSegs;
@@ -223,7 +242,11 @@ struct Launch {
   int v64u, v32u;         // common vector width of all problems, or 0
   int nt16_mixed;         // problems differ in ceil(ncols / 16)
   int maxkz;              // most nonlocal projectors of a problem (0: none)
-  int seg;                // some problem has SpMM segments of > 1 tile
+  int seg;                // some row-sweep problem has SpMM segments of
+                          // > 1 tile
+  int ntile;              // some problem uses the row-sweep CG SpMM
+  int zm;                 // some problem uses the z-marching CG SpMM
+  int zmg;                // chunks per z-marching unit (1, 2 or 4)
 };
 
 // Per-problem step summary for the host (one PollReport per problem).

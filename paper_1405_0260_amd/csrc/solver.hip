@@ -982,6 +982,7 @@ __global__ void PARO_STREAM_BOUNDS
 spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double ws[5 * kNtMax];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (d.zm != 0) return;  // served by spmm_zm_kernel
   const int nact = ldg(&d.cs->n_active[par]);
   const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
   if (nact == 0) return;  // queued after convergence
@@ -990,6 +991,207 @@ spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   for (TileWalk w = tile_walk(d.pqn, lb, d.nb); w.t < w.end; w.t += w.step) {
     PARO_CM_WIDTH(T, VFIX, vw,
                   (spmm_cm_segment<T, VV, SEG>(d, w.t, amask, ws)))
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// z-marching CG SpMM (problems with zm > 0).  The sweep over rows above
+// reads every P value of a plane three times, as the z + 1 neighbour, the
+// centre and the z - 1 neighbour of rows one plane apart; on large meshes
+// the rows in flight on an XCD span several planes of every active chunk,
+// more than its 4 MB L2 holds, so the three reads reach the fabric.  Here
+// a unit owns an xy tile of kSpmmRows consecutive rows of a plane (the
+// same lane layout: lanes 0 and 63 of a wavefront hold the neighbouring
+// rows for the x-shifts), a range of planes and a group of G chunks, and
+// walks the planes upward.  Per chunk a thread keeps four of the seven
+// x-centred lines it gathers (plane z - 1 at y and y - 1, plane z at y and
+// y + 1) in registers from one plane to the next and loads three: plane z
+// at y - 1 and plane z + 1 at y and y + 1.  The 15 coefficients of a row
+// are loaded once per plane for the whole group; the other groups of the
+// same tile and planes run on the same XCD at the same time and find them
+// in its L2.
+//
+// q is formed exactly as in spmm_cm_tile (same products, same order), so
+// Q is bitwise the same.  p.q is summed per (column, segment), segment =
+// (plane range, xy tile): each thread adds its rows' products over the
+// planes in ascending order, then one wavefront reduction and the four
+// wavefronts in a fixed order.  The segments depend on the mesh alone and
+// G only chooses which columns a unit serves, so every choice of G and of
+// the block count gives the same bits.
+//
+// Unit walk: XCD x (= local block mod 8) owns the plane ranges
+// [x zm / 8, (x + 1) zm / 8); its units are ordered (range, tile, group)
+// with the group fastest, so the blocks of an XCD work on the groups of a
+// few neighbouring tiles of one range at a time.
+// ---------------------------------------------------------------------------
+
+// The x-centred line of the thread's row at plane z and y offset oy
+// (element offset oyo, 0 where j + oy leaves the box), plane clamped to
+// the box (a plane outside it has coefficient 0 and reads a valid row).
+template <typename T, int V>
+__device__ __forceinline__ void zm_line(const T* __restrict__ Pc, int z,
+                                        int mz, long long plane, int pc,
+                                        int oyo, T (&o)[V]) {
+  const int zq = z < 0 ? 0 : (z >= mz ? mz - 1 : z);
+  ldv<T, V>(Pc + ((size_t)zq * plane + pc + oyo) * V, o);
+}
+
+template <typename T, int V, int G>
+__device__ __forceinline__ void spmm_zm_unit(const Desc& d, int tau, int zeta,
+                                             int ch0, unsigned long long amask,
+                                             double* __restrict__ ws) {
+  const CmVecs<T> vs(d);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long n = d.n;
+  const int mx = d.mx, my = d.my, mz = d.mz, ncols = d.ncols;
+  const int cpr = ncols / V;
+  const long long plane = (long long)mx * my;
+  const long long p = (long long)tau * kSpmmRows +
+                      (long long)wave * kSpmmWaveRows + lane - 1;
+  const bool valid = lane >= 1 && lane <= kSpmmWaveRows && p < plane;
+  const int pc = (int)(p < 0 ? 0 : (p < plane ? p : plane - 1));
+  const int j = pc / mx;
+  const int oym = j > 0 ? -mx : 0, oyp = j < my - 1 ? mx : 0;
+  const int za = (int)((long long)zeta * mz / d.zm);
+  const int zb = (int)((long long)(zeta + 1) * mz / d.zm);
+  bool on[G];
+  const T* Pc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int ch = ch0 + g;
+    on[g] = ch < cpr && chunk_in_mask<V>(amask, ch);
+    Pc[g] = vs.P + (size_t)(ch < cpr ? ch : 0) * n * V;
+  }
+  // Carried lines: plane z - 1 at y and y - 1, plane z at y and y + 1.
+  T cm0[G][V], cmm[G][V], c00[G][V], c0p[G][V];
+  double acc[G][V];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) acc[g][u] = 0.0;
+    if (on[g]) {
+      zm_line<T, V>(Pc[g], za - 1, mz, plane, pc, 0, cm0[g]);
+      zm_line<T, V>(Pc[g], za - 1, mz, plane, pc, oym, cmm[g]);
+      zm_line<T, V>(Pc[g], za, mz, plane, pc, 0, c00[g]);
+      zm_line<T, V>(Pc[g], za, mz, plane, pc, oyp, c0p[g]);
+    }
+  }
+  for (int z = za; z < zb; ++z) {
+    const size_t row = (size_t)z * plane + pc;
+    T a[kStencil];
+#pragma unroll
+    for (int s = 0; s < kStencil; ++s) a[s] = ldg(vs.diag + (size_t)s * n + row);
+    T c0m[G][V], c10[G][V], c1p[G][V];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (on[g]) {
+        zm_line<T, V>(Pc[g], z, mz, plane, pc, oym, c0m[g]);
+        zm_line<T, V>(Pc[g], z + 1, mz, plane, pc, 0, c10[g]);
+        zm_line<T, V>(Pc[g], z + 1, mz, plane, pc, oyp, c1p[g]);
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (!on[g]) continue;
+      T x[kStencil][V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        x[1][u] = cmm[g][u];
+        x[3][u] = cm0[g][u];
+        x[5][u] = c0m[g][u];
+        x[7][u] = c00[g][u];
+        x[9][u] = c0p[g][u];
+        x[11][u] = c10[g][u];
+        x[13][u] = c1p[g][u];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          x[2 * k][u] = lane_shift<false>(T(0), x[2 * k + 1][u]);
+          x[2 * k + 8][u] = lane_shift<true>(T(0), x[2 * k + 7][u]);
+        }
+      T q[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) q[u] = T(0);
+#pragma unroll
+      for (int s = 0; s < kStencil; ++s)
+#pragma unroll
+        for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
+      if (valid) {
+        if constexpr (sizeof(T) == 8)
+          if (d.kz) nl_add<V>(d, (long long)row, (ch0 + g) * V, q);
+        stv<T, V>(vs.Q + ((size_t)(ch0 + g) * n + row) * V, q);
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+          acc[g][u] += (double)x[kSelf][u] * (double)q[u];
+      }
+      // Next plane: z becomes z - 1, z + 1 becomes z.
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        cm0[g][u] = c00[g][u];
+        cmm[g][u] = c0m[g][u];
+        c00[g][u] = c10[g][u];
+        c0p[g][u] = c1p[g][u];
+      }
+    }
+  }
+  // Per (column, segment) p.q: wavefront, then the four wavefronts.
+  constexpr int kGroup = 64 / V;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (!on[g]) continue;  // uniform over the block
+    const double tot = wave_reduce_scatter<V>(acc[g]);
+    if ((lane & (kGroup - 1)) == 0)
+      ws[wave * ncols + (ch0 + g) * V + lane / kGroup] = tot;
+  }
+  __syncthreads();
+  // Thread tid < ncols stores column tid's partial if the column is
+  // active (so its chunk is one of this unit's G).
+  const int c = tid - ch0 * V;
+  if (c >= 0 && c < G * V && tid < ncols && ((amask >> tid) & 1)) {
+    const double sum = ((ws[tid] + ws[ncols + tid]) + ws[2 * ncols + tid]) +
+                       ws[3 * ncols + tid];
+    stg(d.pqp + (size_t)tid * d.pqn + ((size_t)zeta * d.zxy + tau), sum);
+  }
+  __syncthreads();  // ws is reused by the next unit
+}
+
+// The g-th set bit of m (g < popcount(m)).
+__device__ __forceinline__ int nth_bit(unsigned long long m, int g) {
+  for (; g > 0; --g) m &= m - 1;
+  return __builtin_ctzll(m);
+}
+
+template <typename T, int VFIX, int G>
+__global__ void PARO_STREAM_BOUNDS
+spmm_zm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * kNtMax];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (d.zm == 0) return;  // served by spmm_cm_kernel
+  const int nact = ldg(&d.cs->n_active[par]);
+  const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
+  if (nact == 0) return;  // queued after convergence
+  const int lb = blockIdx.x - d.b0;
+  const int vw = cm_width<T>(d);
+  const int cpr = d.ncols / vw;
+  // Groups of G chunks with an active column.
+  const unsigned long long cm = chunk_mask(amask, cpr, vw);
+  unsigned long long gm = 0;
+  for (int g = 0; g * G < cpr; ++g)
+    if ((cm >> (g * G)) & ((1ull << G) - 1)) gm |= 1ull << g;
+  const int nag = __popcll(gm);
+  const int x = lb % kXcd, l = lb / kXcd, gx = d.nb / kXcd;
+  const int zr = d.zm / kXcd;
+  const long long units = (long long)zr * d.zxy * nag;
+  for (long long k = l; k < units; k += gx) {
+    const long long rest = k / nag;
+    const int gi = (int)(k - rest * nag);
+    const int tau = (int)(rest % d.zxy);
+    const int zeta = x * zr + (int)(rest / d.zxy);
+    const int ch0 = nth_bit(gm, gi) * G;
+    PARO_CM_WIDTH(T, VFIX, vw,
+                  (spmm_zm_unit<T, VV, G>(d, tau, zeta, ch0, amask, ws)))
   }
 }
 
@@ -2639,16 +2841,39 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
 
 // One CG iteration of every problem of the table (chunk-major kernels).
 template <typename T, int W>
+static void cg_spmm_launch(Launch& L, int par, hipStream_t s, Timing* t) {
+  const Desc* D = L.d;
+  if (L.ntile) {
+    if (L.seg)
+      klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, true>, dim3(L.blocks),
+              dim3(kBlock), 0, s, D, L.nprob, par);
+    else
+      klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, false>,
+              dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob, par);
+  }
+  if (L.zm) {
+    switch (L.zmg) {
+      case 1:
+        klaunch(t, PARO_ST_CG_SPMM, spmm_zm_kernel<T, W, 1>, dim3(L.blocks),
+                dim3(kBlock), 0, s, D, L.nprob, par);
+        break;
+      case 4:
+        klaunch(t, PARO_ST_CG_SPMM, spmm_zm_kernel<T, W, 4>, dim3(L.blocks),
+                dim3(kBlock), 0, s, D, L.nprob, par);
+        break;
+      default:
+        klaunch(t, PARO_ST_CG_SPMM, spmm_zm_kernel<T, W, 2>, dim3(L.blocks),
+                dim3(kBlock), 0, s, D, L.nprob, par);
+    }
+  }
+}
+
+template <typename T, int W>
 static void cg_iter_w(Launch& L, int par, hipStream_t s, Timing* t) {
   const Desc* D = L.d;
   if constexpr (sizeof(T) == 8)
     if (L.maxkz) zt_launch(L, kZtP, s, t, PARO_ST_CG_SPMM, par);
-  if (L.seg)
-    klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, true>, dim3(L.blocks),
-            dim3(kBlock), 0, s, D, L.nprob, par);
-  else
-    klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, false>, dim3(L.blocks),
-            dim3(kBlock), 0, s, D, L.nprob, par);
+  cg_spmm_launch<T, W>(L, par, s, t);
   klaunch(t, PARO_ST_CG_RUPD, rupd_alpha_kernel<T, W>, dim3(L.blocks),
           dim3(kBlock), 0, s, D, L.nprob, par);
   klaunch(t, PARO_ST_CG_PUPD, pupd_beta_kernel<T, W>, dim3(L.blocks),
@@ -2675,30 +2900,21 @@ hipError_t launch_pcg_iter(Launch& L, bool fp32, int par, hipStream_t s,
 }
 
 // The CG SpMM alone (autotuner timing).
-template <typename T, bool SEG>
-static void cg_spmm_w(Launch& L, hipStream_t s) {
-  const Desc* D = L.d;
-  const dim3 g(L.blocks), b(kBlock);
-  const int w = sizeof(T) == 4 ? L.v32u : L.v64u;
-  if constexpr (sizeof(T) == 4)
-    if (w == 4) {
-      hipLaunchKernelGGL((spmm_cm_kernel<T, 4, SEG>), g, b, 0, s, D, L.nprob,
-                         0);
-      return;
-    }
-  if (w == 2)
-    hipLaunchKernelGGL((spmm_cm_kernel<T, 2, SEG>), g, b, 0, s, D, L.nprob, 0);
-  else if (w == 1)
-    hipLaunchKernelGGL((spmm_cm_kernel<T, 1, SEG>), g, b, 0, s, D, L.nprob, 0);
-  else
-    hipLaunchKernelGGL((spmm_cm_kernel<T, 0, SEG>), g, b, 0, s, D, L.nprob, 0);
-}
-
 hipError_t launch_cg_spmm(Launch& L, bool fp32, hipStream_t s) {
-  if (fp32)
-    L.seg ? cg_spmm_w<float, true>(L, s) : cg_spmm_w<float, false>(L, s);
-  else
-    L.seg ? cg_spmm_w<double, true>(L, s) : cg_spmm_w<double, false>(L, s);
+  if (fp32) {
+    switch (L.v32u) {
+      case 4: cg_spmm_launch<float, 4>(L, 0, s, nullptr); break;
+      case 2: cg_spmm_launch<float, 2>(L, 0, s, nullptr); break;
+      case 1: cg_spmm_launch<float, 1>(L, 0, s, nullptr); break;
+      default: cg_spmm_launch<float, 0>(L, 0, s, nullptr);
+    }
+  } else {
+    switch (L.v64u) {
+      case 2: cg_spmm_launch<double, 2>(L, 0, s, nullptr); break;
+      case 1: cg_spmm_launch<double, 1>(L, 0, s, nullptr); break;
+      default: cg_spmm_launch<double, 0>(L, 0, s, nullptr);
+    }
+  }
   return hipGetLastError();
 }
 

@@ -1,10 +1,16 @@
-"""Source solves on a mesh large enough that the CG SpMM groups its tiles
-into segments: 81^3 = 531,441 rows is more than 2048 tiles of 248 rows, so
-the tiles form 8 slabs of 268 (the last one 267) and each of the 1024
-p.q partials covers every 128th tile of a slab, two or three tiles (the
-path the 96^3 workload takes).  Checked against the oracle's matrix: the FP64 residual of the
-result, and for FP64 the iteration count of the oracle's own Jacobi-PCG
-on each column (any error in an iterate changes it)."""
+"""Source solves on meshes large enough that the CG SpMM leaves its plain
+one-tile-per-segment form:
+
+* 81^3 = 531,441 rows (more than 2048 tiles of 248 rows) takes the
+  z-marching SpMM: 26 xy tiles per 80 x 80 plane, 16 ranges of 5 planes,
+  one p.q partial per (range, tile);
+* a flat 289 x 289 x 8 box (83,521-row planes, too many xy tiles for the
+  z-march) keeps the row sweep with slab segments: 8 slabs of tiles, each
+  of the 1024 p.q partials covering every 128th tile of a slab.
+
+Checked against the oracle's matrix: the FP64 residual of the result, and
+for FP64 the iteration count of the oracle's own Jacobi-PCG on each column
+(any error in an iterate changes it)."""
 import numpy as np
 import pytest
 
@@ -19,24 +25,39 @@ NC = 82  # 81^3 interior dofs
 NCOLS = 4
 
 
-@pytest.fixture(scope="module")
-def large_case():
-    w = inputs.harmonic(nc=NC, N=NCOLS)
-    assert w.n_dof > 2048 * 248
-    H, M, s = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+FLAT = (290, 290, 9)   # 289 x 289 x 8 interior vertices
+
+
+def _case(shape):
+    if shape == "cube":
+        w = inputs.harmonic(nc=NC, N=NCOLS)
+        ncs, lo, hi, V = w.nc, w.lo, w.hi, w.V
+    else:
+        ncs, lo, hi = FLAT, (-6.0, -6.0, -1.5), (6.0, 6.0, 1.5)
+        X = inputs.vertex_coords(ncs, lo, hi)
+        V = 0.5 * np.sum(X * X, axis=1)
+    H, M, s = gu.oracle_matrices(ncs, lo, hi, V)
     A = (H - s * M).tocsr()
+    n = A.shape[0]
+    assert n > 2048 * 248
     rng = np.random.default_rng(11)
-    B = rng.standard_normal((w.n_dof, NCOLS))
-    X0 = rng.standard_normal((w.n_dof, NCOLS)) * 0.01
-    return w, A, B, X0
+    B = rng.standard_normal((n, NCOLS))
+    X0 = rng.standard_normal((n, NCOLS)) * 0.01
+    return (ncs, lo, hi, V), A, B, X0
+
+
+@pytest.fixture(scope="module", params=["cube", "flat"])
+def large_case(request):
+    return request.param, _case(request.param)
 
 
 @pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
 def test_pcg_with_segmented_spmm_partials(large_case, precision):
-    w, A, B, X0 = large_case
-    gu.note(f"large pcg: n = {w.n_dof}, ncols = {NCOLS}, "
+    shape, ((ncs, lo, hi, V), A, B, X0) = large_case
+    gu.note(f"large pcg: {shape} {ncs}, n = {A.shape[0]}, ncols = {NCOLS}, "
             f"precision = {precision}")
-    prob = gu.workload_problem(w, precision=precision, pcg_rtol=1e-12)
+    prob = gu.assemble(ncs, lo, hi, V, N=NCOLS, precision=precision,
+                       pcg_rtol=1e-12)
     Xd = gu.to_dev(X0)
     its = pb.paro_pcg(prob, gu.to_dev(B), Xd)
     X = Xd.cpu().numpy()
@@ -45,16 +66,16 @@ def test_pcg_with_segmented_spmm_partials(large_case, precision):
     if precision == pb.PARO_FP64:
         dinv = 1.0 / A.diagonal()
         for c in range(NCOLS):
-            _, k = oparo.jacobi_pcg(A, B[:, c], X0[:, c], dinv, 1e-12, 10000)
+            _, k = oparo.jacobi_pcg(A, B[:, c], X0[:, c], dinv, 1e-12, 20000)
             assert abs(its[c] - k) <= 1, (c, its[c], k)
 
 
 @pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
 def test_batch_with_segmented_member_matches_alone(precision):
-    """A batch of the 81^3 problem (slab segments) and a 12^3 one (one tile
-    per segment): the launch takes the segmented SpMM for both, the small
-    problem alone takes the single-tile instantiation.  Two ParO steps,
-    bitwise equal to the members stepped alone."""
+    """A batch of the 81^3 problem (z-marching SpMM) and a 12^3 one (row
+    sweep, one tile per segment): the batch launches both SpMM kernels,
+    each serving its own problems.  Two ParO steps, bitwise equal to the
+    members stepped alone."""
     import torch
     ws = [inputs.harmonic(nc=NC, N=2, m=2, seed=31, max_steps=50),
           inputs.harmonic(nc=12, N=2, m=2, seed=32, max_steps=50)]
@@ -86,3 +107,38 @@ def test_batch_with_segmented_member_matches_alone(precision):
         for k in range(len(probs)):
             assert torch.equal(lams[k], lams1[k]), (step, k)
             assert torch.equal(Us[k], Us1[k]), (step, k)
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_z_march_variants_give_the_same_steps(precision):
+    """The z-marching SpMM's tuning choices (1, 2 or 4 chunks per unit,
+    full or halved block count) only decide which unit or block serves a
+    column: three ParO steps agree bit for bit under every choice."""
+    import torch
+    w = inputs.harmonic(nc=NC, N=6, m=4, seed=33)
+    gu.note(f"z-march variants, precision {precision}")
+    pb.paro_set_autotune(False)
+    try:
+        p = gu.workload_problem(w, precision=precision, pcg_rtol=1e-10)
+        _, ns = pb.paro_tuned(p)
+        ref = None
+        for var in (-1, 0, 1, 2):
+            for nb in (ns, max(8, ns // 2 // 8 * 8)):
+                pb.paro_set_tuning(p, var, nb)
+                lam = torch.zeros(p.Nt, dtype=torch.float64,
+                                  device=gu.device())
+                U = torch.zeros(p.n, p.Nt, dtype=torch.float64,
+                                device=gu.device())
+                pb.paro_init(p, gu.to_dev(w.U0()), lam, U)
+                its = [pb.paro_step(p, lam, U).pcg_iters for _ in range(3)]
+                got = (lam.cpu().numpy(), U.cpu().numpy(), its)
+                if ref is None:
+                    ref = got
+                    continue
+                assert got[2] == ref[2], (var, nb)
+                assert np.array_equal(got[0], ref[0]), (var, nb)
+                assert np.array_equal(got[1], ref[1]), (var, nb)
+        with pytest.raises(pb.ParoError):
+            pb.paro_set_tuning(p, 3, ns)
+    finally:
+        pb.paro_set_autotune(True)
