@@ -366,6 +366,26 @@ int paro_spmm(paro_problem* p, int which, const double* d_X, double* d_Y,
 int paro_gram(paro_problem* p, const double* d_W, const double* d_Y,
               double* d_G, int ncols, void* stream);
 
+/* Allocation-free Gram, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): G = W^T Y (ncols x ncols, row-major, device d_G) for
+ * n x ncols row-major FP64 device blocks W and Y, on FP64 matrix cores,
+ * with the same kernels, segments and summation order as paro_gram on a
+ * problem of n dofs and N + m = ncols (so the same bits).  Needs no
+ * problem and no workspace: its scratch (a launch descriptor and the
+ * first-stage tile partials, 16 MiB + 1 KiB) is a static device array
+ * that every device holds for the life of the process.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library call)
+ * and is asynchronous on `stream`.  Every call on a device shares that
+ * device's scratch: calls that overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.  The scratch
+ * keeps the last call's contents; each call overwrites all of it that it
+ * reads, so nothing needs clearing.
+ * Errors: PARO_EINVAL (NULL pointer, ncols outside 1..64, n outside
+ * 1..2^31-1: the scratch is sized for 64 columns), PARO_EDEVICE. */
+int paro_gram_noalloc(const double* d_W, const double* d_Y, double* d_G,
+                      int64_t n, int ncols, void* stream);
+
 /* Dense generalised symmetric eigenproblem A c = theta B c, B positive
  * definite, n <= 64, on one workgroup: Cholesky B = L L^T, cyclic Jacobi
  * on L^{-1} A L^{-T}, theta ascending, C = L^{-T} Y (C^T B C = I), each

@@ -136,6 +136,7 @@ def lib():
         "paro_export_csr": (c_i32, [P, P, P, P, P, ctypes.POINTER(c_dbl), P]),
         "paro_spmm": (c_i32, [P, c_i32, P, P, c_i32, P]),
         "paro_gram": (c_i32, [P, P, P, P, c_i32, P]),
+        "paro_gram_noalloc": (c_i32, [P, P, P, c_i64, c_i32, P]),
         "paro_small_geneig": (c_i32, [P, P, c_i32, P, P, P, P]),
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
@@ -341,6 +342,17 @@ def paro_gram(p: Problem, W, Y, G, stream=None):
     _f64(G, (ncols, ncols), "G")
     _check(lib().paro_gram(p.handle, _ptr(W), _ptr(Y), _ptr(G), ncols,
                            _stream(stream)))
+
+
+def paro_gram_noalloc(W, Y, G, stream=None):
+    """G = W^T Y without a problem or workspace (the library's static
+    device scratch; allocates nothing)."""
+    n, ncols = W.shape
+    _f64(W, (n, ncols), "W")
+    _f64(Y, (n, ncols), "Y")
+    _f64(G, (ncols, ncols), "G")
+    _check(lib().paro_gram_noalloc(_ptr(W), _ptr(Y), _ptr(G), n, ncols,
+                                   _stream(stream)))
 
 
 def paro_small_geneig(A, B, theta, C, info, stream=None):

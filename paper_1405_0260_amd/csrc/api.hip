@@ -916,6 +916,55 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   return L;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free Gram (paro_gram_noalloc): its scratch -- one launch
+// descriptor and the first-stage tile partials -- is this file-scope
+// device array, of which every device holds its own copy for the life of
+// the process.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocDescBytes = 1024;
+constexpr size_t kNoAllocPartBytes =
+    sizeof(double) * (size_t)kGramGrid * 16 * 256;  // 64 columns, 512 segments
+constexpr size_t kNoAllocBytes = kNoAllocDescBytes + kNoAllocPartBytes;
+static_assert(sizeof(Desc) <= kNoAllocDescBytes, "descriptor slot");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the
+// first call per device).
+int scratch_address(void** out) {
+  int dev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(PARO_EDEVICE, "device %d beyond the supported %d", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PARO_EDEVICE, "hipGetSymbolAddress(scratch): %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PARO_OK;
+}
+
+// Writes a descriptor passed by value into device memory (no copy from
+// host memory, nothing to allocate or pin).
+__global__ void store_desc_kernel(Desc d, Desc* dst) {
+  if (threadIdx.x == 0) *dst = d;
+}
+
+}  // namespace
+
 }  // namespace paro
 
 using namespace paro;
@@ -1538,6 +1587,38 @@ int paro_gram(paro_problem* h, const double* d_W, const double* d_Y,
   int rc = upload(c, s);
   if (rc) return rc;
   HIP_OR_FAIL(launch_gram_full(c.L, s, c.timing));
+  return PARO_OK;
+}
+
+int paro_gram_noalloc(const double* d_W, const double* d_Y, double* d_G,
+                      int64_t n, int ncols, void* stream) {
+  if (!d_W || !d_Y || !d_G) return fail(PARO_EINVAL, "NULL argument");
+  if (ncols < 1 || ncols > kNtMax)
+    return fail(PARO_EINVAL, "ncols must be 1..%d (the scratch holds %zu "
+                "bytes: the partials of %d columns)", kNtMax, kNoAllocBytes,
+                kNtMax);
+  if (n < 1 || n > (int64_t)INT32_MAX)
+    return fail(PARO_EINVAL, "n must be 1..%d", INT32_MAX);
+  void* base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Desc d;
+  std::memset(&d, 0, sizeof d);
+  d.n = n;
+  set_cols(d, ncols);
+  d.g0 = 0;
+  // The segments of paro_gram on a problem of n rows and ncols orbitals.
+  d.gnb = d.gns = std::min(pick_grid(n, ncols), kGramGrid);
+  d.X = const_cast<double*>(d_W);
+  d.Y1 = const_cast<double*>(d_Y);
+  d.Y2 = d_G;
+  d.gpart = (double*)((unsigned char*)base + kNoAllocDescBytes);
+  Desc* dd = (Desc*)base;
+  hipLaunchKernelGGL(store_desc_kernel, dim3(1), dim3(64), 0, s, d, dd);
+  HIP_OR_FAIL(hipGetLastError());
+  Launch L = make_launch(dd, &d, 1);
+  HIP_OR_FAIL(launch_gram_full(L, s, nullptr));
   return PARO_OK;
 }
 
