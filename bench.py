@@ -268,7 +268,13 @@ class Solver:
         stages, it_bytes = cg_stage_rates(td, n, prob_t.nnz, vec_b)
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
-        traffic = measured_traffic(KERNEL_NAMES[dom], TRAFFIC[prec])
+        kname = KERNEL_NAMES[dom]
+        traffic = measured_traffic(kname, TRAFFIC[prec])
+        if dom == "cg_spmm" and traffic is None:
+            # Meshes beyond 2048 row tiles run the z-marching SpMM.
+            t2 = measured_traffic("spmm_zm_kernel", TRAFFIC[prec])
+            if t2 is not None:
+                kname, traffic = "spmm_zm_kernel", t2
         all_ms = sum(v["ms"] for v in td["stages"].values())
         cg_ms = sum(td["stages"][k]["ms"] for k in
                     ("cg_spmm", "cg_rupd", "cg_pupd", "cg_final"))
@@ -276,7 +282,7 @@ class Solver:
         # Two launches per Gram (MFMA tiles, then the fixed-order final).
         gram_flop = 4.0 * n * Nt * Nt * g["launches"] / 2
         return {
-            "bound": "hbm", "kernel": KERNEL_NAMES[dom],
+            "bound": "hbm", "kernel": kname,
             "achieved": round(d["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
