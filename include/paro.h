@@ -225,7 +225,8 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
  * by the library's Jacobi-PCG when poisson_maxit > 0), v_x the Slater
  * exchange -(3 rho/pi)^(1/3).
  * Outer iteration n: density of U^(n); rho_in = that density at n = 0,
- * else (1 - mixing) rho_in + mixing * density; V_eff; values-only
+ * else (1 - mixing) rho_in + mixing * density (or, with kerker_q0 > 0,
+ * rho_in + mixing * the Kerker-filtered residual); V_eff; values-only
  * re-assembly (shift recomputed unless sigma_mode = 1); one ParO step.
  * --------------------------------------------------------------------- */
 typedef struct paro_ks_opts {
@@ -238,6 +239,12 @@ typedef struct paro_ks_opts {
                              <= scf_tol and the problem's lambda_tol and
                              resid_tol hold for the step                  */
   double poisson_rtol;    /* relative CG tolerance (CG Hartree only)     */
+  double kerker_q0;       /* 0: linear mixing rho_in += mixing (rho_out -
+                             rho_in); > 0: the residual is first filtered
+                             by (K + q0^2 vol I)^-1 K (K the P1 stiffness,
+                             vol the cell volume), Kerker's q^2 / (q^2 +
+                             q0^2) on the grid, which damps long-wavelength
+                             charge sloshing; applied in the sine basis     */
 } paro_ks_opts_t;
 
 typedef struct paro_ks_report {

@@ -19,7 +19,12 @@ current density), with these readings:
     density -(3/4)(3/pi)^(1/3) rho^(4/3) of the homogeneous electron gas.
   * The Hamiltonian of a step is built from the mixed input density
     rho_in and used for both Step 3 and Step 4; linear mixing
-    rho_in <- (1 - beta) rho_in + beta rho_out, beta = 0.3.
+    rho_in <- (1 - beta) rho_in + beta rho_out, beta = 0.3, or (the paper
+    names no mixing scheme) Kerker-preconditioned mixing
+    rho_in <- rho_in + beta (K + q0^2 vol I)^{-1} K (rho_out - rho_in),
+    with K the P1 stiffness matrix and vol the cell volume: the grid form
+    of Kerker's factor q^2 / (q^2 + q0^2), which damps the long-wavelength
+    part of the residual.
   * Outer iteration n: rho_out = density of U^(n); rho_in = rho_out at
     n = 0, else the mixture; V_eff = V_ext + V_H(rho_in) + v_x(rho_in) at
     the vertices; one ParO step with H(V_eff) and its shift.  The density
@@ -54,6 +59,15 @@ def slater_exchange(rho: np.ndarray) -> np.ndarray:
     return -np.cbrt(3.0 * np.maximum(rho, 0.0) / np.pi)
 
 
+def kerker_filter(K, e: np.ndarray, q0: float, vol: float) -> np.ndarray:
+    """(K + q0^2 vol I)^{-1} K e (q0 = 0: e itself), solved directly."""
+    if q0 == 0.0:
+        return np.array(e, dtype=np.float64, copy=True)
+    import scipy.sparse as sp
+    A = (K + (q0 * q0 * vol) * sp.identity(K.shape[0], format="csr")).tocsc()
+    return spla.spsolve(A, K @ e)
+
+
 def effective_potential(mesh: fem.Mesh, V_ext: np.ndarray, rho: np.ndarray,
                         vh: np.ndarray) -> np.ndarray:
     """V_ext + V_H + v_x at every vertex (rho = V_H = 0 on the boundary)."""
@@ -77,10 +91,12 @@ class SCFResult:
 
 def scf(mesh: fem.Mesh, V_ext: np.ndarray, U0: np.ndarray, N: int,
         iterations: int, mixing: float = 0.3, rtol: float = 1e-10,
-        maxit=None) -> SCFResult:
+        maxit=None, kerker_q0: float = 0.0) -> SCFResult:
     """`iterations` outer iterations of ParO with Kohn-Sham updates.
 
-    Step 1: Rayleigh-Ritz of U0 with the bare Hamiltonian H(V_ext)."""
+    Step 1: Rayleigh-Ritz of U0 with the bare Hamiltonian H(V_ext).
+    kerker_q0 > 0 filters the density residual before mixing
+    (kerker_filter); 0 is plain linear mixing."""
     K, M, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
     H0, _ = fem.hamiltonian(mesh, V_ext)
     lam, U = oparo.rayleigh_ritz(H0, M, np.asarray(U0, dtype=np.float64))
@@ -97,7 +113,12 @@ def scf(mesh: fem.Mesh, V_ext: np.ndarray, U0: np.ndarray, N: int,
         else:
             res_hist.append(float(np.linalg.norm(rho_out - rho_in) /
                                   np.linalg.norm(rho_in)))
-            rho_in = (1.0 - mixing) * rho_in + mixing * rho_out
+            if kerker_q0 > 0.0:
+                vol = float(np.prod(mesh.h))
+                rho_in = rho_in + mixing * kerker_filter(
+                    K, rho_out - rho_in, kerker_q0, vol)
+            else:
+                rho_in = (1.0 - mixing) * rho_in + mixing * rho_out
         vh = hartree(K, M, rho_in)
         V = effective_potential(mesh, V_ext, rho_in, vh)
         H, _ = fem.hamiltonian(mesh, V)

@@ -80,7 +80,7 @@ class ServerStats(ctypes.Structure):
 class KsOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_i32), ("poisson_maxit", c_i32),
                 ("mixing", c_dbl), ("occupancy", c_dbl), ("scf_tol", c_dbl),
-                ("poisson_rtol", c_dbl)]
+                ("poisson_rtol", c_dbl), ("kerker_q0", c_dbl)]
 
 
 class KsReport(ctypes.Structure):

@@ -1,6 +1,8 @@
 // Kohn-Sham outer iteration around ParO (Sec. 2, eqs. (eq-ks), (weak-ks),
 // (eq-operator-A); Algorithm 3.1): each outer iteration forms the density
-// of the current orbitals, mixes it into the input density, solves the
+// of the current orbitals, mixes it into the input density (linearly, or
+// with the residual filtered by Kerker's (K + q0^2 vol I)^-1 K, which
+// damps its long-wavelength part), solves the
 // Poisson equation -Lap V_H = 4 pi rho for the Hartree potential (P1, zero
 // on the box boundary: K V_H = 4 pi M rho, solved directly with the 3-D
 // discrete sine transform that diagonalises K on the uniform box grid, or
@@ -72,6 +74,46 @@ ks_mix_kernel(const double* __restrict__ rho_out, double* __restrict__ rho_in,
     part[blockIdx.x] = r0[0];
     part[kKsGrid + blockIdx.x] = r1[0];
   }
+}
+
+// Kerker-preconditioned mixing, first half: the density residual
+// e = rho_out - rho_in into `e` and its norm partials (as ks_mix_kernel).
+__global__ void __launch_bounds__(kBlock)
+ks_resid_vec_kernel(const double* __restrict__ rho_out,
+                    const double* __restrict__ rho_in, long long n,
+                    double* __restrict__ e_out, double* __restrict__ part) {
+  __shared__ double r0[kBlock], r1[kBlock];
+  double a = 0.0, b = 0.0;
+  for (long long d = (long long)blockIdx.x * kBlock + threadIdx.x; d < n;
+       d += (long long)gridDim.x * kBlock) {
+    const double i = rho_in[d], e = rho_out[d] - i;
+    e_out[d] = e;
+    a = fma(e, e, a);
+    b = fma(i, i, b);
+  }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      r0[threadIdx.x] += r0[threadIdx.x + w];
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = r0[0];
+    part[kKsGrid + blockIdx.x] = r1[0];
+  }
+}
+
+// Second half: rho_in += beta * (filtered residual).
+__global__ void __launch_bounds__(kBlock)
+ks_axpy_kernel(double* __restrict__ rho_in, const double* __restrict__ e,
+               long long n, double beta) {
+  for (long long d = (long long)blockIdx.x * kBlock + threadIdx.x; d < n;
+       d += (long long)gridDim.x * kBlock)
+    rho_in[d] = fma(beta, e[d], rho_in[d]);
 }
 
 // Fixed-order sum of the partials: out[0] = ||rho_out - rho_in||^2,
@@ -226,6 +268,23 @@ dst_divide_kernel(double* __restrict__ g, int mx, int my, int mz,
   }
 }
 
+// Kerker filter in the sine basis: g[x, y, z] *= lambda / (lambda + c),
+// lambda_xyz the eigenvalue of the stiffness matrix K, c = q0^2 times the
+// cell volume (the lumped mass), i.e. (K + c I)^-1 K.
+__global__ void __launch_bounds__(kBlock)
+dst_kerker_kernel(double* __restrict__ g, int mx, int my, int mz,
+                  const double* __restrict__ ev, double c) {
+  const long long n = (long long)mx * my * mz;
+  for (long long d = (long long)blockIdx.x * kBlock + threadIdx.x; d < n;
+       d += (long long)gridDim.x * kBlock) {
+    const int x = (int)(d % mx);
+    const int y = (int)((d / mx) % my);
+    const int z = (int)(d / ((long long)mx * my));
+    const double lam = ev[x] + ev[mx + y] + ev[mx + my + z];
+    g[d] *= lam / (lam + c);
+  }
+}
+
 hipError_t dgemm(hipStream_t s, int M, int N, int K, const double* A,
                  long long lda, long long sA, const double* B, long long ldb,
                  long long sB, double* C, long long ldc, long long sC,
@@ -333,6 +392,7 @@ void paro_ks_default_opts(paro_ks_opts_t* o) {
   o->scf_tol = 1e-8;
   o->poisson_rtol = 1e-12;
   o->poisson_maxit = 0;  // direct sine-transform solve
+  o->kerker_q0 = 0.0;    // plain linear mixing
 }
 
 int paro_ks_query(const paro_box_t* box, size_t* workspace_bytes) {
@@ -359,7 +419,8 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
     if (((uintptr_t)d_ws & 255) != 0)
       return set_error(PARO_EINVAL, "workspace must be 256-byte aligned");
     if (!(kopt->mixing > 0.0) || kopt->mixing > 1.0 || kopt->max_iter < 1 ||
-        !(kopt->occupancy > 0.0))
+        !(kopt->occupancy > 0.0) || !(kopt->kerker_q0 >= 0.0) ||
+        !std::isfinite(kopt->kerker_q0))
       return set_error(PARO_EINVAL, "bad Kohn-Sham options");
     const paro_box_t box = p->p.box;
     const paro_opts_t eig = p->p.opts;
@@ -391,10 +452,13 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
     double* ev = (double*)(base + L.ev);
     const int mx = box.nx - 1, my = box.ny - 1, mz = box.nz - 1;
     const bool direct = kopt->poisson_maxit <= 0;
-    if (direct) {
-      const double hx = (box.hi[0] - box.lo[0]) / box.nx;
-      const double hy = (box.hi[1] - box.lo[1]) / box.ny;
-      const double hz = (box.hi[2] - box.lo[2]) / box.nz;
+    const bool kerker = kopt->kerker_q0 > 0.0;
+    const double hx = (box.hi[0] - box.lo[0]) / box.nx;
+    const double hy = (box.hi[1] - box.lo[1]) / box.ny;
+    const double hz = (box.hi[2] - box.lo[2]) / box.nz;
+    const double kerker_c = kopt->kerker_q0 * kopt->kerker_q0 * hx * hy * hz;
+    const double dst_inv = 8.0 / ((double)(mx + 1) * (my + 1) * (mz + 1));
+    if (direct || kerker) {
       hipLaunchKernelGGL(dst_tables_kernel, dim3(64), dim3(kBlock), 0, s, mx,
                          my, mz, hy * hz / hx, hz * hx / hy, hx * hy / hz, Sx,
                          Sy, Sz, ev);
@@ -426,9 +490,27 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
       hipLaunchKernelGGL(ks_density_kernel, dim3(gd), dim3(kBlock), 0, s,
                          (const double*)d_U, (long long)n, Nt, N,
                          kopt->occupancy, rho_out);
-      hipLaunchKernelGGL(ks_mix_kernel, dim3(kKsGrid), dim3(kBlock), 0, s,
-                         (const double*)rho_out, rho_in, (long long)n,
-                         kopt->mixing, it == 0 ? 1 : 0, part);
+      if (kerker && it > 0) {
+        // rho_in += mixing * (K + c I)^-1 K (rho_out - rho_in): the
+        // residual to the sine basis (rho_out is free once e is formed),
+        // the filter, and back.
+        hipLaunchKernelGGL(ks_resid_vec_kernel, dim3(kKsGrid), dim3(kBlock),
+                           0, s, (const double*)rho_out,
+                           (const double*)rho_in, (long long)n, b, part);
+        KS_HIP(hipGetLastError());
+        KS_HIP(dst3(s, mx, my, mz, Sx, Sy, Sz, b, t1, rho_out, 1.0));
+        hipLaunchKernelGGL(dst_kerker_kernel, dim3(gd), dim3(kBlock), 0, s,
+                           rho_out, mx, my, mz, (const double*)ev, kerker_c);
+        KS_HIP(hipGetLastError());
+        KS_HIP(dst3(s, mx, my, mz, Sx, Sy, Sz, rho_out, t1, b, dst_inv));
+        hipLaunchKernelGGL(ks_axpy_kernel, dim3(gd), dim3(kBlock), 0, s,
+                           rho_in, (const double*)b, (long long)n,
+                           kopt->mixing);
+      } else {
+        hipLaunchKernelGGL(ks_mix_kernel, dim3(kKsGrid), dim3(kBlock), 0, s,
+                           (const double*)rho_out, rho_in, (long long)n,
+                           kopt->mixing, it == 0 ? 1 : 0, part);
+      }
       hipLaunchKernelGGL(ks_residual_kernel, dim3(1), dim3(kBlock), 0, s,
                          (const double*)part, res);
       KS_HIP(hipGetLastError());
@@ -442,8 +524,7 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
         hipLaunchKernelGGL(dst_divide_kernel, dim3(gd), dim3(kBlock), 0, s,
                            vh, mx, my, mz, (const double*)ev);
         KS_HIP(hipGetLastError());
-        const double inv = 8.0 / ((double)(mx + 1) * (my + 1) * (mz + 1));
-        KS_HIP(dst3(s, mx, my, mz, Sx, Sy, Sz, vh, t1, b, inv));
+        KS_HIP(dst3(s, mx, my, mz, Sx, Sy, Sz, vh, t1, b, dst_inv));
         KS_HIP(hipMemcpyAsync(vh, b, 8 * n, hipMemcpyDeviceToDevice, s));
       } else {
         // (1/2) K V_H = 2 pi M rho_in by PCG, warm-started from the last V_H.

@@ -20,7 +20,7 @@ def small_molecule(nc=10, N=2, m=4):
 
 
 def run_gpu(w, iterations, precision=pb.PARO_FP64, scf_tol=0.0,
-            lambda_tol=1e-12, resid_tol=1e-9):
+            lambda_tol=1e-12, resid_tol=1e-9, kerker_q0=0.0):
     import torch
     p = gu.workload_problem(w, precision=precision, pcg_rtol=1e-12,
                             lambda_tol=lambda_tol, resid_tol=resid_tol)
@@ -28,20 +28,22 @@ def run_gpu(w, iterations, precision=pb.PARO_FP64, scf_tol=0.0,
     U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=gu.device())
     rho = torch.zeros(w.n_dof, dtype=torch.float64, device=gu.device())
     o = pb.ks_default_opts(max_iter=iterations, scf_tol=scf_tol,
-                           poisson_rtol=1e-13)
+                           poisson_rtol=1e-13, kerker_q0=kerker_q0)
     rep = pb.paro_ks_solve(p, gu.to_dev(w.V), gu.to_dev(w.U0()), lam, U, o,
                            rho=rho)
     torch.cuda.synchronize()
     return lam.cpu().numpy(), U.cpu().numpy(), rho.cpu().numpy(), rep
 
 
-def test_ks_iterates_match_oracle():
+@pytest.mark.parametrize("kerker_q0", [0.0, 0.8])
+def test_ks_iterates_match_oracle(kerker_q0):
     w = small_molecule()
-    gu.note("KS 30 iterations, FP64")
-    lam, U, rho, rep = run_gpu(w, 30)
+    gu.note(f"KS 30 iterations, FP64, Kerker q0 {kerker_q0}")
+    lam, U, rho, rep = run_gpu(w, 30, kerker_q0=kerker_q0)
     assert rep.iterations == 30 and rep.status == pb.PARO_ENOCONV
     mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
-    r = oks.scf(mesh, w.V, w.U0(), w.N, iterations=30, rtol=1e-12)
+    r = oks.scf(mesh, w.V, w.U0(), w.N, iterations=30, rtol=1e-12,
+                kerker_q0=kerker_q0)
     floor = np.maximum(np.abs(r.lam), 1e-3 * np.abs(r.lam).max())
     assert np.max(np.abs(lam - r.lam) / floor) < 1e-9
     assert np.linalg.norm(rho - r.rho_in) / np.linalg.norm(r.rho_in) < 1e-9

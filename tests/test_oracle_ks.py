@@ -159,3 +159,45 @@ def test_effective_potential_of_a_sine_density_matches_the_closed_form():
         assert np.array_equal(out[~inner], Vext[~inner])
     assert errs[1] < 0.025
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_kerker_filter_without_screening_is_the_identity():
+    mesh = fem.kuhn_mesh((5, 6, 7), 0.0, (1.0, 1.2, 1.4))
+    K, _, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    e = np.random.default_rng(3).standard_normal(mesh.n_dof)
+    assert np.array_equal(ks.kerker_filter(K, e, 0.0, 0.01), e)
+
+
+def test_kerker_filter_scales_a_sine_mode_by_the_closed_form_factor():
+    """On a uniform box grid the P1 stiffness is the 7-point operator
+    sum_a c_a T_a (c_x = h_y h_z / h_x, cyclically), whose eigenvectors
+    are products of discrete sines with eigenvalues
+    lambda = sum_a c_a 2 (1 - cos(pi p_a / (m_a + 1))); the filter must
+    multiply such a mode by lambda / (lambda + q0^2 h_x h_y h_z)."""
+    nc, L = (8, 6, 10), np.array([2.0, 1.5, 3.0])
+    mesh = fem.kuhn_mesh(nc, np.zeros(3), L)
+    K, _, _ = fem.assemble(mesh, np.zeros(mesh.X.shape[0]))
+    h = L / np.array(nc)
+    c = np.array([h[1] * h[2] / h[0], h[2] * h[0] / h[1],
+                  h[0] * h[1] / h[2]])
+    q0 = 1.3
+    for p in ((1, 1, 1), (3, 2, 7), (7, 5, 9)):
+        mode = lambda X: np.prod(np.sin(np.pi * np.array(p) * X / L), axis=1)
+        e = _at_dofs(mesh, mode)
+        lam = sum(c[a] * 2.0 * (1.0 - np.cos(np.pi * p[a] / nc[a]))
+                  for a in range(3))
+        f = lam / (lam + q0 * q0 * np.prod(h))
+        got = ks.kerker_filter(K, e, q0, float(np.prod(h)))
+        assert np.allclose(got, f * e, rtol=0, atol=1e-12 * np.abs(e).max())
+
+
+def test_kerker_mixing_reaches_the_same_fixed_point():
+    """The filter only changes the path: a converged Kerker-mixed run is
+    self-consistent with the same lowest eigenvalues as linear mixing."""
+    w = small_molecule()
+    mesh = fem.kuhn_mesh(w.nc, w.lo, w.hi)
+    a = ks.scf(mesh, w.V, w.U0(), w.N, iterations=220, rtol=1e-12)
+    b = ks.scf(mesh, w.V, w.U0(), w.N, iterations=220, rtol=1e-12,
+               kerker_q0=0.8)
+    assert b.residual_history[-1] < 1e-8, b.residual_history[-5:]
+    assert np.allclose(a.lam[:w.N], b.lam[:w.N], rtol=1e-9)
