@@ -21,4 +21,9 @@ calculations", arXiv:1405.0260, that it follows):
              self-consistent ParO (Sec. 2 Kohn-Sham equation; Algorithm 3.1).
   nonlocal_  The nonlocal pseudopotential term V_nl u = sum_j (u, zeta_j)
              zeta_j as the rank-k Galerkin operator Z Z^T (Sec. 2).
+  adapt      Step 2 of Algorithm 3.1: residual estimator, Doerfler and
+             maximum marking (Sec. 2 adaptive finite element approximation,
+             eqs. (dorfler-strategy), (maximum-strategy)), conforming
+             bisection, P1 transfer of the orbitals, and the ParO loop with
+             an adaptive Step 2.
 """
