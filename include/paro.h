@@ -345,6 +345,55 @@ void paro_server_destroy(paro_server* s);
  * buffer per calling thread (64 KB, hipHostMalloc'd on first use and kept
  * until the process ends) that the device writes directly. */
 
+/* ---------------------------------------------------------------------
+ * Step 2 on the uniform Kuhn mesh (Sec. 2, adaptive finite element
+ * approximation: Solve -> Estimate -> Mark -> Refine; Algorithm 3.1
+ * Step 2).  Elements: cell c (x fastest over nx * ny * nz cells) holds six
+ * Kuhn elements q = 0..5, one per permutation p of the axes in
+ * lexicographic order, vertices c, c + e_p0, c + e_p0 + e_p1, c + (1,1,1);
+ * element index q * (nx ny nz) + c.
+ * --------------------------------------------------------------------- */
+enum { PARO_MARK_DORFLER = 0, PARO_MARK_MAXIMUM = 1 };
+
+/* Number of elements of the box's Kuhn mesh, 6 nx ny nz (0 if invalid). */
+int64_t paro_elements(const paro_box_t* box);
+
+/* Estimate: the residual a posteriori indicator of the first nreq columns
+ * of d_U (n_dof x ncols row-major, FP64, device) with eigenvalues
+ * d_lambda, for -1/2 Lap u + V u = lambda u (d_V: nodal potential at all
+ * vertices):
+ *   eta_T^2 = sum_i h_T^2 ||lambda_i u_i - V_h u_i||^2_T
+ *           + 1/2 sum_{F interior face of T} h_F ||[1/2 grad u_i . n_F]||^2_F
+ * (h_T, h_F longest edges; the element term integrated exactly), one
+ * value per element into d_eta (paro_elements doubles).  The paper names
+ * the loop but not the estimator; this is the usual residual indicator.
+ * Asynchronous.  PARO_EINVAL on bad shapes (1 <= nreq <= ncols <= 64). */
+int paro_estimate(const paro_box_t* box, const double* d_V,
+                  const double* d_lambda, const double* d_U, int32_t ncols,
+                  int32_t nreq, double* d_eta, void* stream);
+
+/* Mark: d_marked[k] (uint8, count) = 1 for the marked elements.
+ * PARO_MARK_DORFLER, eq. (dorfler-strategy): a smallest set whose sum of
+ * eta^2 reaches theta times the total -- every element above a threshold
+ * and, lowest indices first, as many equal to it as needed.
+ * PARO_MARK_MAXIMUM, eq. (maximum-strategy): eta >= theta max eta.
+ * 0 < theta <= 1.  d_ws: device scratch of paro_mark_workspace_bytes(),
+ * 256-byte aligned.  Synchronous (the threshold search reads sums back);
+ * *h_nmarked (nullable) receives the count. */
+size_t paro_mark_workspace_bytes(void);
+int paro_mark(const double* d_eta, int64_t count, double theta,
+              int32_t strategy, uint8_t* d_marked, int64_t* h_nmarked,
+              void* d_ws, size_t bytes, void* stream);
+
+/* Refine every element and carry the orbitals over: d_Uc (n_dof x ncols
+ * of the box's mesh) -> d_Uf (n_dof x ncols of the same box with 2 nx,
+ * 2 ny, 2 nz cells, whose Kuhn elements refine the coarse ones) by P1
+ * interpolation: every fine vertex is a coarse vertex or the midpoint of
+ * a coarse edge (axis, face diagonal or main diagonal) and takes the mean
+ * of its ends.  Asynchronous; 1 <= ncols <= 64. */
+int paro_prolong(const paro_box_t* coarse, const double* d_Uc, double* d_Uf,
+                 int32_t ncols, void* stream);
+
 /* Message for the last failing call on this thread (never NULL). */
 const char* paro_last_error(void);
 const char* paro_strerror(int status);

@@ -137,6 +137,13 @@ def lib():
         "paro_spmm": (c_i32, [P, c_i32, P, P, c_i32, P]),
         "paro_gram": (c_i32, [P, P, P, P, c_i32, P]),
         "paro_gram_noalloc": (c_i32, [P, P, P, c_i64, c_i32, P]),
+        "paro_elements": (c_i64, [ctypes.POINTER(Box)]),
+        "paro_estimate": (c_i32, [ctypes.POINTER(Box), P, P, P, c_i32, c_i32,
+                                  P, P]),
+        "paro_mark_workspace_bytes": (ctypes.c_size_t, []),
+        "paro_mark": (c_i32, [P, c_i64, c_dbl, c_i32, P,
+                              ctypes.POINTER(c_i64), P, ctypes.c_size_t, P]),
+        "paro_prolong": (c_i32, [ctypes.POINTER(Box), P, P, c_i32, P]),
         "paro_small_geneig": (c_i32, [P, P, c_i32, P, P, P, P]),
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
@@ -353,6 +360,48 @@ def paro_gram_noalloc(W, Y, G, stream=None):
     _f64(G, (ncols, ncols), "G")
     _check(lib().paro_gram_noalloc(_ptr(W), _ptr(Y), _ptr(G), n, ncols,
                                    _stream(stream)))
+
+
+PARO_MARK_DORFLER = 0
+PARO_MARK_MAXIMUM = 1
+
+
+def paro_elements(box: Box) -> int:
+    return lib().paro_elements(ctypes.byref(box))
+
+
+def paro_estimate(box: Box, V, lam, U, nreq, eta, stream=None):
+    """Residual estimator per element of the first nreq columns of U (see
+    include/paro.h) into eta (paro_elements(box) doubles)."""
+    n, ncols = U.shape
+    _f64(V, ((box.nx + 1) * (box.ny + 1) * (box.nz + 1),), "V")
+    _f64(lam, (ncols,), "lambda")
+    _f64(eta, (paro_elements(box),), "eta")
+    _check(lib().paro_estimate(ctypes.byref(box), _ptr(V), _ptr(lam),
+                               _ptr(U), ncols, nreq, _ptr(eta),
+                               _stream(stream)))
+
+
+def paro_mark(eta, theta, strategy=PARO_MARK_DORFLER, stream=None):
+    """Marked elements (uint8 device tensor) and their count."""
+    import torch
+    nbytes = lib().paro_mark_workspace_bytes()
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=eta.device)
+    off = (-ws.data_ptr()) % 256
+    marked = torch.empty(eta.shape[0], dtype=torch.uint8, device=eta.device)
+    cnt = c_i64()
+    _check(lib().paro_mark(_ptr(eta), eta.shape[0], theta, strategy,
+                           _ptr(marked), ctypes.byref(cnt),
+                           ctypes.c_void_p(ws.data_ptr() + off), nbytes,
+                           _stream(stream)))
+    return marked, cnt.value
+
+
+def paro_prolong(box: Box, Uc, Uf, stream=None):
+    """Orbitals of the box's mesh -> the mesh with twice the cells."""
+    ncols = Uc.shape[1]
+    _check(lib().paro_prolong(ctypes.byref(box), _ptr(Uc), _ptr(Uf), ncols,
+                              _stream(stream)))
 
 
 def paro_small_geneig(A, B, theta, C, info, stream=None):

@@ -26,7 +26,8 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
          f"-I{INCLUDE}", f"-I{CSRC}"]
-SOURCES = ["assemble.hip", "solver.hip", "api.hip", "serve.hip", "ks.hip"]
+SOURCES = ["assemble.hip", "solver.hip", "api.hip", "serve.hip", "ks.hip",
+           "adapt.hip"]
 
 
 def _compile(src: str) -> str:
