@@ -281,3 +281,47 @@ def test_step_reports_match_oracle_stopping_measures(precision):
             f"(last {g_dl[-1]:.3e}), rho rel {e_rho:.2e} "
             f"(last {g_rho[-1]:.3e})")
     assert e_dl < 1e-6 and e_rho < 1e-6
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_softcoulomb_64_matches_golden_and_spans_the_eigenspace(precision):
+    """The 64^3 soft-Coulomb workload (N = 16, m = 8) solved to tight
+    tolerances: lambda against the stored shift-invert eigenvalues, and the
+    subspace angle to the exact 16-dimensional eigenspace bounded with the
+    oracle's matrices: sin theta <= ||R||_{M^-1} / (lambda_17 - lambda_16)
+    (Davis-Kahan), R = H U - M U Lambda over the requested pairs."""
+    w = inputs.molecule_64()
+    prob = gu.workload_problem(w, precision=precision, max_steps=3000,
+                               lambda_tol=1e-13, resid_tol=1e-10)
+    lam, U, rep = gu.solve(prob, w.U0())
+    assert rep.status == 0, rep.as_dict()
+    golden = np.loadtxt(os.path.join(GOLDEN, "softcoulomb_64c_lowest.txt"))
+    N = w.N
+    assert rel_lambda_err(lam[:N], golden[:N]) < 1e-10
+    H, M, s = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+    assert m_orthonormality_error(M, U) < 1e-11
+    R = H @ U[:, :N] - (M @ U[:, :N]) * lam[None, :N]
+    dinv = 1.0 / M.diagonal()
+    norm2 = 0.0
+    for c in range(N):
+        y, _ = oparo.jacobi_pcg(M, R[:, c], np.zeros(R.shape[0]), dinv,
+                                1e-12, 2000)
+        norm2 += float(R[:, c] @ y)
+    sin_bound = np.sqrt(norm2) / (golden[N] - lam[N - 1])
+    gu.note(f"64^3 subspace: sin theta <= {sin_bound:.2e}, gap "
+            f"{golden[N] - golden[N - 1]:.3e}")
+    assert sin_bound < 1e-6
+
+
+def test_linear_96_fp64_matches_the_oracle_run():
+    """The headline workload: the 96^3 linear problem of the 20-centre
+    potential, solved in FP64, against the oracle's converged ParO run."""
+    w = inputs.kohn_sham_96()
+    prob = gu.workload_problem(w, precision=pb.PARO_FP64, max_steps=4000,
+                               lambda_tol=1e-11, resid_tol=1e-7)
+    lam, _, rep = gu.solve(prob, w.U0())
+    assert rep.status == 0, rep.as_dict()
+    golden = np.loadtxt(os.path.join(GOLDEN, "linear_96c_lowest.txt"))
+    err = rel_lambda_err(lam[:w.N], golden[:w.N])
+    gu.note(f"96^3 lambda error vs oracle {err:.2e} after {rep.steps} steps")
+    assert err < 1e-10
