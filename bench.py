@@ -104,6 +104,10 @@ def parse():
                     help="with --profile-only: first copy a 256 MiB buffer "
                          "(a plain copy kernel of known size, the reference "
                          "for the HBM byte counters)")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the estimate / mark / refine-everything run")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the 24^3 harmonic latency run")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-problem uneven batch")
     ap.add_argument("--no-batch-sequential", action="store_true",
@@ -375,6 +379,14 @@ def main():
             del s3
         torch.cuda.empty_cache()
 
+    adaptive = None
+    if not args.no_adaptive:
+        adaptive = adaptive_bench(args, golden)
+
+    latency = None
+    if not args.no_latency:
+        latency = latency_bench(args)
+
     batch = None
     if not args.no_batch:
         batch = batch_bench(args, "mixed")
@@ -424,6 +436,8 @@ def main():
         "converged": main_res["ok"],
         "other_precision": other_res,
         "softcoulomb_64c": ctx64,
+        "adaptive_refine_all": adaptive,
+        "harmonic_24c_latency": latency,
         "batch64": batch,
         "serve": serve,
         "kohn_sham": ks,
@@ -729,6 +743,102 @@ def ks_bench(args, prec):
             "homo_lumo_gap": float(lam_h[w.N] - lam_h[w.N - 1]),
             "residual_every_100": [float(x) for x in
                                    hist[1:rep.iterations:100]]}
+
+
+def adaptive_bench(args, golden):
+    """Step 2 with every element refined, measured: the 96^3 workload's
+    potential on 48^3 cells, solved (FP64); the residual estimator and
+    Doerfler marking (theta 0.5) of its pairs; the orbitals carried to the
+    96^3 mesh; the 96^3 solve from them, beside the headline's solve from
+    the seeded random start."""
+    import torch
+    from paper_1405_0260_amd import binding as pb
+    from paper_1405_0260_amd import inputs
+
+    dev = torch.device("cuda:0")
+    wc, wf = inputs.kohn_sham_96(nc=48), inputs.kohn_sham_96(nc=96)
+    out = {"coarse": f"linear_{wc.nc}c_N{wc.N}_m{wc.m}",
+           "fine": f"linear_{wf.nc}c_N{wf.N}_m{wf.m}"}
+
+    def solver(w):
+        return Solver(w, "fp64", None, args.inner_rtol)
+
+    sc = solver(wc)
+    dt_c, rep_c, _, _ = sc.solve()
+    out["coarse_seconds"] = dt_c
+    out["coarse_paro_steps"] = rep_c.steps
+    # Estimate and mark (timed apart, after a warm-up call).
+    box = sc.box
+    nel = pb.paro_elements(box)
+    eta = torch.zeros(nel, dtype=torch.float64, device=dev)
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.paro_estimate(box, sc.V, sc.lam, sc.U, wc.N, eta)
+        torch.cuda.synchronize()
+        t_est = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        marked, nmark = pb.paro_mark(eta, 0.5, pb.PARO_MARK_DORFLER)
+        torch.cuda.synchronize()
+        t_mark = time.perf_counter() - t0
+    out.update({"elements": nel, "estimate_ms": 1e3 * t_est,
+                "estimate_elements_per_s": nel / t_est,
+                "mark_ms": 1e3 * t_mark, "marked_theta_0.5": nmark})
+    sf = solver(wf)
+    Uf = torch.zeros(wf.n_dof, wf.Nt, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.paro_prolong(box, sc.U, Uf)
+    torch.cuda.synchronize()
+    out["prolong_ms"] = 1e3 * (time.perf_counter() - t0)
+    sf.U0 = Uf
+    dt_f, rep_f, _, _ = sf.solve()
+    lam = sf.lam.cpu().numpy()
+    out.update({"fine_seconds_from_transfer": dt_f,
+                "fine_paro_steps_from_transfer": rep_f.steps,
+                "fine_converged": rep_f.status == 0,
+                "lambda_rel_err_vs_oracle_ref":
+                    lambda_error(lam[:wf.N], golden[:wf.N])
+                    if golden is not None else None})
+    log(f"[adaptive] 48^3 solve {dt_c:.2f} s, estimate {1e3 * t_est:.1f} ms, "
+        f"mark {1e3 * t_mark:.1f} ms, 96^3 from the transfer {dt_f:.2f} s "
+        f"({rep_f.steps} steps)")
+    return out
+
+
+def latency_bench(args):
+    """The harmonic-oscillator workload (24^3 cells, N = 4, FP64), whose
+    working set sits in the caches: microseconds per ParO step over its 30
+    steps, and its eigenvalue error after them and at convergence."""
+    import torch
+    from paper_1405_0260_amd import binding as pb
+    from paper_1405_0260_amd import inputs
+
+    w = inputs.harmonic_24()
+    conv = np.loadtxt(os.path.join(GOLDEN_DIR, "harmonic_24c_lowest10.txt"))
+    s = Solver(w, "fp64", conv, args.inner_rtol)
+    s.opts.max_steps = 30
+    s.opts.lambda_tol = 0.0
+    s.opts.resid_tol = 0.0
+    times = []
+    for k in range(6):
+        dt, rep, _, _ = s.solve()
+        times.append(dt)
+    lam30 = s.lam.cpu().numpy()
+    s.opts.max_steps = 1000
+    s.opts.lambda_tol = 1e-13
+    s.opts.resid_tol = 1e-9
+    dtc, repc, _, _ = s.solve()
+    lamc = s.lam.cpu().numpy()
+    t = float(np.median(times[1:]))
+    return {"workload": "harmonic_24c_N4", "n_dof": w.n_dof,
+            "paro_steps": 30, "seconds_per_solve": t,
+            "us_per_paro_step": 1e6 * t / 30,
+            "note": "whole solve (assembly, start, 30 steps) / 30",
+            "lambda_rel_err_after_30_steps": lambda_error(lam30[:4],
+                                                          conv[:4]),
+            "steps_to_converge": repc.steps,
+            "lambda_rel_err_converged": lambda_error(lamc[:4], conv[:4])}
 
 
 def cpu_model():

@@ -292,7 +292,8 @@ def test_softcoulomb_64_matches_golden_and_spans_the_eigenspace(precision):
     (Davis-Kahan), R = H U - M U Lambda over the requested pairs."""
     w = inputs.molecule_64()
     prob = gu.workload_problem(w, precision=precision, max_steps=3000,
-                               lambda_tol=1e-13, resid_tol=1e-10)
+                               lambda_tol=1e-13, resid_tol=1e-9,
+                               pcg_rtol=1e-12)
     lam, U, rep = gu.solve(prob, w.U0())
     assert rep.status == 0, rep.as_dict()
     golden = np.loadtxt(os.path.join(GOLDEN, "softcoulomb_64c_lowest.txt"))
