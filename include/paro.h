@@ -89,6 +89,8 @@ typedef struct paro_report {
   double max_resid;
   double sigma;
   double seconds;         /* wall time of the call                          */
+  int64_t reorth;         /* projections redone after re-orthonormalising a
+                             nearly dependent basis (see paro_init)         */
 } paro_report_t;
 
 typedef struct paro_problem paro_problem;   /* opaque, host memory only */
@@ -137,9 +139,16 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
 /* Step 1 of Algorithm A.1: from arbitrary linearly independent orbitals
  * d_U0 (n_dof x Nt) form the Rayleigh-Ritz pairs of their span, which are
  * M-orthonormal, into d_lambda (Nt) and d_U (n_dof x Nt).  d_U0 may equal
- * d_U.  Asynchronous on `stream`.
- * Errors: PARO_EINVAL; PARO_ESINGULAR is reported through paro_step /
- * paro_solve status (device-side flag) when U0^T M U0 is singular. */
+ * d_U.  Asynchronous on `stream`, so it neither reads nor repairs a failed
+ * projection: when the Cholesky factorisation of U0^T M U0 fails, d_U
+ * holds U0 and the problem's device status flag is set.  paro_solve,
+ * paro_batch_solve and the server run Step 1 synchronously instead: a
+ * start block whose Gram matrix fails its factorisation is first
+ * re-orthonormalised by one shifted Cholesky-QR pass (W <- W L^{-T},
+ * L L^T = W^T M W + s I, s a rounding-level shift, Fukaya et al., SIAM
+ * J. Sci. Comput. 2020) and projected again; PARO_ESINGULAR only if that
+ * fails too (columns dependent to rounding level).
+ * Errors: PARO_EINVAL. */
 int paro_init(paro_problem* p, const double* d_U0, double* d_lambda,
               double* d_U, void* stream);
 
@@ -153,7 +162,11 @@ int paro_init(paro_problem* p, const double* d_U0, double* d_lambda,
  * then Rayleigh-Ritz on span W.  A pure function of (lambda, U) and the problem.
  * If `report` is NULL the call is asynchronous on `stream` except for the
  * CG loop's convergence polling (one 4-byte read every few iterations);
- * otherwise it synchronises and fills `report` for this step. */
+ * otherwise it synchronises and fills `report` for this step, and a
+ * projection whose Gram matrix W^T M W fails its Cholesky factorisation
+ * is retried once after the shifted Cholesky-QR re-orthonormalisation of
+ * W described at paro_init (report->status PARO_ESINGULAR if the retry
+ * fails as well). */
 int paro_step(paro_problem* p, double* d_lambda, double* d_U, void* stream,
               paro_report_t* report);
 
@@ -301,7 +314,8 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
 typedef struct paro_server paro_server;     /* opaque, host memory only */
 
 typedef struct paro_server_stats {
-  int32_t queued;           /* submitted, not yet admitted                */
+  int32_t queued;           /* submitted, not yet stepping (waiting, or
+                               being uploaded and assembled)            */
   int32_t active;           /* resident on the device                     */
   int64_t done;             /* retired so far                             */
   size_t arena_used;        /* bytes of the arena held by requests        */
@@ -311,8 +325,12 @@ typedef struct paro_server_stats {
 
 /* d_arena: device memory the server sub-allocates (256-byte aligned; the
  * caller keeps it alive until paro_server_destroy).  max_active: most
- * problems resident at once (1..PARO_BATCH_MAX).  stream: all work of the
- * server runs on it. */
+ * problems resident at once (1..PARO_BATCH_MAX).  stream: the steps run
+ * on it.  Admitted requests are uploaded and assembled by a worker thread
+ * of the server on a stream of its own (default priority), while ticks
+ * step the resident problems; a request's first step waits for its
+ * admission through an event, so no tick waits for an assembly unless
+ * nothing else is resident. */
 int paro_server_create(void* d_arena, size_t arena_bytes, int32_t max_active,
                        void* stream, paro_server** out);
 
@@ -326,11 +344,17 @@ int paro_server_submit(paro_server* s, const paro_box_t* box,
                        const double* h_U0, double* h_lambda, double* h_U,
                        int64_t* id);
 
-/* One scheduling round (admit, one batched ParO step, retire).  Writes up
- * to max_done ids of retired, not yet returned requests to done_ids and
- * their number to *n_done (the rest are returned by later ticks).
- * Synchronous.  Per-request failures (including a request that cannot be
- * assembled) do not fail the tick; they are in the request's report. */
+/* One scheduling round: hand queued requests (arrival order, while a
+ * slot is free and their block fits) to the admission worker, take Step 1
+ * of the requests it has assembled, one batched ParO step of every
+ * resident problem, retire.  Writes up to max_done ids of retired, not yet
+ * returned requests to done_ids and their number to *n_done (the rest are
+ * returned by later ticks).  Synchronous.  Per-request failures
+ * (including a request that cannot be assembled, or a start block that
+ * stays dependent) do not fail the tick; they are in the request's report.
+ * A device error of a batched call fails every resident request with that
+ * code (they retire, release their arena space and are returned as done)
+ * and is returned. */
 int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
                      int32_t* n_done, paro_server_stats_t* stats);
 

@@ -48,7 +48,7 @@ class Report(ctypes.Structure):
     _fields_ = [("status", c_i32), ("steps", c_i32), ("pcg_iters", c_i64),
                 ("refinements", c_i64), ("n_dof", c_i64), ("nnz", c_i64),
                 ("max_dlambda", c_dbl), ("max_resid", c_dbl),
-                ("sigma", c_dbl), ("seconds", c_dbl)]
+                ("sigma", c_dbl), ("seconds", c_dbl), ("reorth", c_i64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

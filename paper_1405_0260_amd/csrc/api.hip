@@ -674,6 +674,45 @@ int read_reports(Ctx& c, std::vector<PollReport>& out, hipStream_t s) {
   return PARO_OK;
 }
 
+// Problems whose Rayleigh-Ritz factorisation of W^T M W failed (status
+// bit kStSingular in the reports just read) get one shifted Cholesky-QR
+// re-orthonormalisation of W and the projection again, on a table of
+// those problems alone (their own block counts, so their arithmetic is
+// what it is in any launch).  `pr` is updated with the new reports, their
+// status marked kStReorth; a problem whose basis is dependent to rounding
+// level keeps the singular status.
+int retry_singular(Ctx& c, std::vector<PollReport>& pr, hipStream_t s) {
+  std::vector<int> idx;
+  for (size_t i = 0; i < pr.size(); ++i)
+    if (pr[i].status & kStSingular) idx.push_back((int)i);
+  if (idx.empty()) return PARO_OK;
+  Ctx r = c;
+  r.tab.clear();
+  int b = 0, g = 0;
+  for (int i : idx) {
+    Desc d = c.tab[i];
+    d.X = d.Uout;  // the failed projection left U = W
+    d.b0 = b;
+    d.g0 = g;
+    b += d.nb;
+    g += d.gnb;
+    r.tab.push_back(d);
+  }
+  int rc = upload(r, s);
+  if (rc) return rc;
+  HIP_OR_FAIL(launch_reorth(r.L, s));
+  HIP_OR_FAIL(launch_rayleigh_ritz(r.L, s, r.timing));
+  HIP_OR_FAIL(launch_reorth_check(r.L, s));
+  std::vector<PollReport> again;
+  rc = read_reports(r, again, s);
+  if (rc) return rc;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    pr[idx[k]] = again[k];
+    pr[idx[k]].status |= kStReorth;
+  }
+  return idx.size() == c.tab.size() ? PARO_OK : upload(c, s);
+}
+
 // One ParO step (Steps 3 and 4) for every problem of the table; the
 // descriptors' U0 = X = Uout (the orbitals, in place) and lam are set.
 // Per-problem status goes into `reps` (if given).  `single`: a CG
@@ -700,6 +739,8 @@ int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
   if (!reps) return PARO_OK;
   rc = read_reports(c, pr, s);
   if (rc) return rc;
+  rc = retry_singular(c, pr, s);
+  if (rc) return rc;
   const double dt = now_s() - t0;
   int first = PARO_OK;
   for (size_t i = 0; i < c.tab.size(); ++i) {
@@ -713,17 +754,29 @@ int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
     r.max_resid = pr[i].max_resid;
     r.sigma = c.tab[i].sigma;
     r.seconds = dt;
-    r.status = status_to_code(pr[i].status);
+    r.status = status_to_code(pr[i].status & ~kStReorth);
+    r.reorth = (pr[i].status & kStReorth) ? 1 : 0;
     if (first == PARO_OK) first = r.status;
   }
   return single ? first : PARO_OK;
 }
 
 // Step 1 (Rayleigh-Ritz of the start block) for every problem.
-int init_tables(Ctx& c, hipStream_t s) {
+// status: null (asynchronous), or it receives every problem's status
+// bits after the projection, with the re-orthonormalisation retry done
+// (kStReorth marks a retried problem).
+int init_tables(Ctx& c, hipStream_t s, std::vector<int>* status) {
   int rc = upload(c, s);
   if (rc) return rc;
   HIP_OR_FAIL(launch_rayleigh_ritz(c.L, s, c.timing));
+  if (!status) return PARO_OK;
+  std::vector<PollReport> pr;
+  rc = read_reports(c, pr, s);
+  if (rc) return rc;
+  rc = retry_singular(c, pr, s);
+  if (rc) return rc;
+  status->resize(pr.size());
+  for (size_t i = 0; i < pr.size(); ++i) (*status)[i] = pr[i].status;
   return PARO_OK;
 }
 
@@ -868,6 +921,8 @@ int autotune(Problem& p, hipStream_t s) {
 }  // namespace
 
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int status_code(int st) { return status_to_code(st); }
 
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   (void)nnz;  // the stencil arrays do not depend on the pattern's size
@@ -1098,8 +1153,13 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
   }
 }
 
-int paro_init(paro_problem* h, const double* d_U0, double* d_lambda,
-              double* d_U, void* stream) {
+}  // extern "C"
+
+namespace paro {
+// Step 1 of one problem; with `status`, synchronous: it receives the
+// status bits after the projection (and its re-orthonormalisation retry).
+int init_impl(paro_problem* h, const double* d_U0, double* d_lambda,
+                     double* d_U, void* stream, int* status) {
   if (!h || !d_U0 || !d_lambda || !d_U)
     return fail(PARO_EINVAL, "NULL argument to paro_init");
   Problem& p = h->p;
@@ -1112,7 +1172,20 @@ int paro_init(paro_problem* h, const double* d_U0, double* d_lambda,
   d.Uout = d_U;
   d.lam = d_lambda;
   d.have_old = 0;
-  return init_tables(c, s);
+  if (!status) return init_tables(c, s, nullptr);
+  std::vector<int> st;
+  const int rc = init_tables(c, s, &st);
+  if (rc) return rc;
+  *status = st[0];
+  return PARO_OK;
+}
+}  // namespace paro
+
+extern "C" {
+
+int paro_init(paro_problem* h, const double* d_U0, double* d_lambda,
+              double* d_U, void* stream) {
+  return init_impl(h, d_U0, d_lambda, d_U, stream, nullptr);
 }
 
 static int step_impl(paro_problem* h, double* d_lambda, double* d_U,
@@ -1147,14 +1220,12 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
   Problem& p = h->p;
   hipStream_t s = (hipStream_t)stream;
   const double t0 = now_s();
-  int rc = paro_init(h, d_U0, d_lambda, d_U, s);
-  if (rc) return rc;
   int st = 0;
-  HIP_OR_FAIL(hipMemcpyAsync(&st, &p.cs->status, sizeof st,
-                             hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipStreamSynchronize(s));
-  if (st) return status_to_code(st);
+  int rc = init_impl(h, d_U0, d_lambda, d_U, s, &st);
+  if (rc) return rc;
+  if (st & ~kStReorth) return status_to_code(st & ~kStReorth);
   paro_report_t acc{};
+  acc.reorth = (st & kStReorth) ? 1 : 0;
   acc.n_dof = p.n;
   acc.nnz = p.nnz;
   acc.sigma = p.sigma;
@@ -1165,6 +1236,7 @@ int paro_solve(paro_problem* h, const double* d_U0, double* d_lambda,
     acc.steps += 1;
     acc.pcg_iters += r.pcg_iters;
     acc.refinements += r.refinements;
+    acc.reorth += r.reorth;
     acc.max_dlambda = r.max_dlambda;
     acc.max_resid = r.max_resid;
     if (rc != PARO_OK && rc != PARO_ENOCONV) {
@@ -1231,10 +1303,13 @@ size_t paro_batch_workspace_bytes(int32_t count) {
   return batch_layout(count).total;
 }
 
-int paro_batch_init(paro_problem* const* probs, int32_t count,
+}  // extern "C"
+
+namespace paro {
+int batch_init_impl(paro_problem* const* probs, int32_t count,
                     const double* const* d_U0, double* const* d_lambda,
                     double* const* d_U, void* d_ws, size_t bytes,
-                    void* stream) {
+                    void* stream, std::vector<int>* status) {
   try {
     if (!d_U0 || !d_lambda || !d_U) return fail(PARO_EINVAL, "NULL arrays");
     Ctx c;
@@ -1253,10 +1328,21 @@ int paro_batch_init(paro_problem* const* probs, int32_t count,
       d.lam = d_lambda[i];
       d.have_old = 0;
     }
-    return init_tables(c, s);
+    return init_tables(c, s, status);
   } catch (...) {
     return fail(PARO_EDEVICE, "unexpected exception in paro_batch_init");
   }
+}
+}  // namespace paro
+
+extern "C" {
+
+int paro_batch_init(paro_problem* const* probs, int32_t count,
+                    const double* const* d_U0, double* const* d_lambda,
+                    double* const* d_U, void* d_ws, size_t bytes,
+                    void* stream) {
+  return paro::batch_init_impl(probs, count, d_U0, d_lambda, d_U, d_ws, bytes,
+                               stream, nullptr);
 }
 
 // Batch steps keep their CG prediction between calls of one thread.
@@ -1306,10 +1392,10 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
                      void* stream, paro_report_t* reports) {
   if (!reports) return fail(PARO_EINVAL, "reports are required");
   const double t0 = now_s();
-  int rc = paro_batch_init(probs, count, d_U0, d_lambda, d_U, d_ws, bytes,
-                           stream);
+  std::vector<int> st;
+  int rc = paro::batch_init_impl(probs, count, d_U0, d_lambda, d_U, d_ws,
+                                 bytes, stream, &st);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
   std::vector<int> active;
   for (int i = 0; i < count; ++i) {
     reports[i] = paro_report_t{};
@@ -1317,13 +1403,10 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
     reports[i].nnz = probs[i]->p.nnz;
     reports[i].sigma = probs[i]->p.sigma;
     reports[i].status = PARO_ENOCONV;
-    // Start-block failures (dependent start columns).
-    int st = 0;
-    HIP_OR_FAIL(hipMemcpyAsync(&st, &probs[i]->p.cs->status, sizeof st,
-                               hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(hipStreamSynchronize(s));
-    if (st)
-      reports[i].status = status_to_code(st);
+    // Start blocks that stay dependent after the re-orthonormalisation.
+    reports[i].reorth = (st[i] & kStReorth) ? 1 : 0;
+    if (st[i] & ~kStReorth)
+      reports[i].status = status_to_code(st[i] & ~kStReorth);
     else
       active.push_back(i);
   }
@@ -1352,6 +1435,7 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
       a.steps += 1;
       a.pcg_iters += r.pcg_iters;
       a.refinements += r.refinements;
+      a.reorth += r.reorth;
       a.max_dlambda = r.max_dlambda;
       a.max_resid = r.max_resid;
       bool done = false;

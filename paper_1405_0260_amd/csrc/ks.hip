@@ -477,8 +477,11 @@ int paro_ks_solve(paro_problem* p, const double* d_Vext,
     // The caller's problem holds H(V_ext): Step 1 with the bare Hamiltonian.
     rc = paro_update_potential(p, d_Vext, s);
     if (rc) return rc;
-    rc = paro_init(p, d_U0, d_lambda, d_U, s);
+    int st0 = 0;
+    rc = paro::init_impl(p, d_U0, d_lambda, d_U, s, &st0);
     if (rc) return rc;
+    if (st0 & ~paro::kStReorth)
+      return paro::status_code(st0 & ~paro::kStReorth);
     paro_ks_report_t rep{};
     rep.status = PARO_ENOCONV;
     const auto t0 = std::chrono::steady_clock::now();

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "paro.h"
 
@@ -37,6 +38,9 @@ enum : int {
   kStNoConv = 2,      // CG iteration cap reached
   kStSingular = 4,    // Cholesky of W^T M W failed
   kStNonFinite = 8,   // NaN / Inf met in a reduction
+  // Set by the host only, in reports it has read: the problem's basis was
+  // re-orthonormalised and projected again this step.
+  kStReorth = 16,
 };
 
 // Per-column scalars of the block CG, resident in device memory.  One
@@ -339,6 +343,20 @@ int batch_step_impl(paro_problem* const* probs, int32_t count,
                     double* const* d_lambda, double* const* d_U, void* d_ws,
                     size_t bytes, void* stream, paro_report_t* reports,
                     bool trust);
+// paro_init; with `status`, synchronous: it receives the status bits
+// after Step 1's projection, with the re-orthonormalisation retry done.
+int init_impl(paro_problem* h, const double* d_U0, double* d_lambda,
+              double* d_U, void* stream, int* status);
+// paro_batch_init; with `status`, synchronous: it receives every
+// problem's status bits after Step 1's projection, with the
+// re-orthonormalisation retry of nearly dependent start blocks done.
+int batch_init_impl(paro_problem* const* probs, int32_t count,
+                    const double* const* d_U0, double* const* d_lambda,
+                    double* const* d_U, void* d_ws, size_t bytes,
+                    void* stream, std::vector<int>* status);
+// Status bits of a problem (ColState::status) as a PARO_* code (the
+// error message recorded as with any failure).
+int status_code(int st);
 // Record `msg` as this thread's last error (paro_last_error); returns code.
 int set_error(int code, const char* msg);
 int64_t kuhn_nnz(int mx, int my, int mz);
@@ -397,6 +415,12 @@ hipError_t launch_gather_reports(Launch& L, PollReport* out, int* seqp,
 // Rayleigh-Ritz on W = X: H W, M W, the two Grams, the small eigensolve,
 // U = W C with residual norms and the step's convergence measures.
 hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t);
+// Shifted Cholesky-QR pass over U = W of every problem of the table (the
+// state a failed Rayleigh-Ritz leaves), before the projection is redone.
+hipError_t launch_reorth(Launch& L, hipStream_t s);
+// ... and after the projection that follows it: flags a problem singular
+// when its new basis still has a column of rounding-level independence.
+hipError_t launch_reorth_check(Launch& L, hipStream_t s);
 // Component Gram G = X^T Y1 into Y2 (non-symmetric, all tiles).
 hipError_t launch_gram_full(Launch& L, hipStream_t s, Timing* t);
 hipError_t launch_small_geneig(const double* A, const double* B, int n,

@@ -5,15 +5,25 @@
 // and eigenvalues), handed out by a first-fit allocator with coalescing
 // free lists.  Requests are admitted in arrival order while a slot is free
 // and their block fits; each tick then advances all resident problems by
-// one ParO step through paro_batch_step, so new arrivals join the running
+// one ParO step through the batched step, so new arrivals join the running
 // batch at the next step boundary instead of waiting for it to drain.
+//
+// Uploading and assembling admitted requests (host copies, the stencil
+// assembly, the shift read-back) runs on a worker thread of the server,
+// on a stream of its own with the default priority, while the tick's
+// thread drives the resident problems' step on the caller's stream; the
+// first step of an admitted request waits for its admission round through
+// an event.
 #include <algorithm>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -86,6 +96,7 @@ struct Request {
   double* d_lam = nullptr;
   void* d_ws = nullptr;
   paro_report_t rep{};
+  int admit_rc = PARO_OK;  // the admission worker's result
   bool done = false;
 };
 
@@ -97,12 +108,22 @@ struct paro_server {
   void* batch_ws = nullptr;
   size_t batch_bytes = 0;
   int max_active = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // steps (the caller's stream)
+  hipStream_t astream = nullptr;  // admission copies and assembly
+  hipEvent_t admitted = nullptr;  // end of the last admission round
   int64_t next_id = 1, ticks = 0, retired = 0;
   std::deque<Request*> queue;
   std::vector<Request*> active;
+  std::vector<Request*> ready;     // assembled, waiting for Step 1
   std::deque<int64_t> unreported;  // retired, id not yet returned
   std::unordered_map<int64_t, Request*> all;
+  // Admission worker: `job` (arena blocks already taken) is handed over
+  // with pending = true and handed back with pending = false, done = true.
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<Request*> job;
+  bool pending = false, done = false, stop = false;
 };
 
 namespace {
@@ -123,7 +144,8 @@ void release(paro_server* s, Request* r) {
   r->block = 0;
 }
 
-// Copy the inputs of r into its arena block and assemble it.
+// Copy the inputs of r into its arena block and assemble it (admission
+// worker, admission stream).
 int admit_one(paro_server* s, Request* r) {
   char* blk = s->base + r->off;
   size_t o = 0;
@@ -135,17 +157,95 @@ int admit_one(paro_server* s, Request* r) {
   o += up256(sizeof(double) * r->U0.size());
   r->d_lam = reinterpret_cast<double*>(blk + o);
   SRV_HIP(hipMemcpyAsync(r->d_V, r->V.data(), sizeof(double) * r->V.size(),
-                         hipMemcpyHostToDevice, s->stream));
+                         hipMemcpyHostToDevice, s->astream));
   SRV_HIP(hipMemcpyAsync(r->d_U, r->U0.data(),
                          sizeof(double) * r->U0.size(),
-                         hipMemcpyHostToDevice, s->stream));
+                         hipMemcpyHostToDevice, s->astream));
   const int rc = paro_assemble(&r->box, r->d_V, &r->opts, r->d_ws,
-                               r->ws_bytes, s->stream, &r->prob);
+                               r->ws_bytes, s->astream, &r->prob);
   // Host copies are no longer needed once on the device.
-  SRV_HIP(hipStreamSynchronize(s->stream));
+  SRV_HIP(hipStreamSynchronize(s->astream));
   std::vector<double>().swap(r->V);
   std::vector<double>().swap(r->U0);
   return rc;
+}
+
+void worker_main(paro_server* s, int device) {
+  const bool on_device = hipSetDevice(device) == hipSuccess;
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    s->cv.wait(lk, [s] { return s->stop || s->pending; });
+    if (s->stop) return;
+    const std::vector<Request*> job = s->job;
+    lk.unlock();
+    for (Request* r : job) {
+      try {
+        r->admit_rc = on_device ? admit_one(s, r) : PARO_EDEVICE;
+      } catch (...) {
+        r->admit_rc = PARO_EDEVICE;
+      }
+    }
+    const hipError_t e = hipEventRecord(s->admitted, s->astream);
+    if (e != hipSuccess)
+      for (Request* r : job)
+        if (r->admit_rc == PARO_OK) r->admit_rc = PARO_EDEVICE;
+    lk.lock();
+    s->pending = false;
+    s->done = true;
+    s->cv.notify_all();
+  }
+}
+
+// The admission stream, event and worker, made on the first admission
+// (creating a server touches no device).
+int start_admission(paro_server* s) {
+  if (s->worker.joinable()) return PARO_OK;
+  int device = 0;
+  SRV_HIP(hipGetDevice(&device));  // the worker uses the caller's device
+  if (!s->astream)
+    SRV_HIP(hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking));
+  if (!s->admitted)
+    SRV_HIP(hipEventCreateWithFlags(&s->admitted, hipEventDisableTiming));
+  try {
+    s->worker = std::thread(worker_main, s, device);
+  } catch (...) {
+    return paro::set_error(PARO_EDEVICE, "admission thread");
+  }
+  return PARO_OK;
+}
+
+// Hand the finished admission round back: assembled requests wait for
+// Step 1, the others retire with their error.  wait: block until the
+// round in flight (if any) is over.
+void collect(paro_server* s, bool wait, std::vector<Request*>& finished) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (wait) s->cv.wait(lk, [s] { return !s->pending; });
+  if (!s->done) return;
+  for (Request* r : s->job) {
+    if (r->admit_rc == PARO_OK) {
+      s->ready.push_back(r);
+    } else {
+      r->rep.status = r->admit_rc;
+      finished.push_back(r);
+    }
+  }
+  s->job.clear();
+  s->done = false;
+}
+
+// Fail every request of `rs` with `code` (a device error of a batched
+// call): they leave the device and are reported like any retired request
+// (one that had already failed on its own keeps its status).
+void fail_all(paro_server* s, std::vector<Request*>& rs, int code) {
+  for (Request* r : rs) {
+    if (r->rep.status == PARO_OK || r->rep.status == PARO_ENOCONV)
+      r->rep.status = code;
+    release(s, r);
+    r->done = true;
+    s->retired += 1;
+    s->unreported.push_back(r->id);
+  }
+  rs.clear();
 }
 
 int retire(paro_server* s, Request* r) {
@@ -233,46 +333,73 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
   try {
     if (!s) return paro::set_error(PARO_EINVAL, "NULL server");
     if (n_done) *n_done = 0;
-    std::vector<Request*> fresh, finished;
-    // 1. Admission in arrival order: a free slot and room in the arena.
-    while (!s->queue.empty() &&
-           (int)(s->active.size() + fresh.size()) < s->max_active) {
-      Request* r = s->queue.front();
-      size_t off = 0;
-      if (!s->arena.alloc(r->need, &off)) break;
-      s->queue.pop_front();
-      r->off = off;
-      r->block = r->need;
-      const int rc = admit_one(s, r);
-      if (rc != PARO_OK) {
-        r->rep.status = rc;
-        release(s, r);
-        r->done = true;
-        s->retired += 1;
-        finished.push_back(r);
-        continue;
-      }
-      fresh.push_back(r);
+    std::vector<Request*> finished;
+    // 1. Hand back a finished admission round; start the next one (in
+    // arrival order, while a slot is free and the block fits).  With no
+    // problem to step meanwhile, wait for the round.
+    if (!s->queue.empty()) {
+      const int rc = start_admission(s);
+      if (rc != PARO_OK) return rc;
     }
-    // 2. Step 1 for the new arrivals (one batched call), in place on d_U.
-    if (!fresh.empty()) {
+    collect(s, false, finished);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (!s->pending && !s->done) {
+        while (!s->queue.empty() &&
+               (int)(s->active.size() + s->ready.size() + s->job.size()) <
+                   s->max_active) {
+          Request* r = s->queue.front();
+          size_t off = 0;
+          if (!s->arena.alloc(r->need, &off)) break;
+          s->queue.pop_front();
+          r->off = off;
+          r->block = r->need;
+          s->job.push_back(r);
+        }
+        if (!s->job.empty()) {
+          s->pending = true;
+          s->cv.notify_all();
+        }
+      }
+    }
+    if (s->active.empty() && s->ready.empty()) collect(s, true, finished);
+    // 2. Step 1 for the assembled arrivals (one batched call), in place on
+    // d_U, after their admission round.
+    if (!s->ready.empty()) {
       std::vector<paro_problem*> ps;
       std::vector<const double*> u0;
       std::vector<double*> ls, us;
-      for (Request* r : fresh) {
+      for (Request* r : s->ready) {
         ps.push_back(r->prob);
         u0.push_back(r->d_U);
         ls.push_back(r->d_lam);
         us.push_back(r->d_U);
       }
-      const int rc = paro_batch_init(ps.data(), (int)ps.size(), u0.data(),
-                                     ls.data(), us.data(), s->batch_ws,
-                                     s->batch_bytes, s->stream);
-      if (rc != PARO_OK) return rc;
-      for (Request* r : fresh) {
-        r->rep.n_dof = r->n;
-        s->active.push_back(r);
+      int rc = hipStreamWaitEvent(s->stream, s->admitted, 0) == hipSuccess
+                   ? PARO_OK
+                   : paro::set_error(PARO_EDEVICE, "admission event wait");
+      std::vector<int> st;
+      if (rc == PARO_OK)
+        rc = paro::batch_init_impl(ps.data(), (int)ps.size(), u0.data(),
+                                   ls.data(), us.data(), s->batch_ws,
+                                   s->batch_bytes, s->stream, &st);
+      if (rc != PARO_OK) {
+        fail_all(s, s->ready, rc);
+        fail_all(s, s->active, rc);
+        return rc;
       }
+      for (size_t k = 0; k < s->ready.size(); ++k) {
+        Request* r = s->ready[k];
+        r->rep.n_dof = r->n;
+        r->rep.reorth = (st[k] & paro::kStReorth) ? 1 : 0;
+        if (st[k] & ~paro::kStReorth) {  // dependent even after the retry
+          r->rep.status = paro::status_code(st[k] & ~paro::kStReorth);
+          finished.push_back(r);
+        } else {
+          s->active.push_back(r);
+        }
+      }
+      s->ready.clear();
     }
     // 3. One ParO step for every resident problem.
     if (!s->active.empty()) {
@@ -288,7 +415,11 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
       const int rc = paro::batch_step_impl(
           ps.data(), (int)ps.size(), ls.data(), us.data(), s->batch_ws,
           s->batch_bytes, s->stream, reps.data(), true);
-      if (rc != PARO_OK) return rc;
+      if (rc != PARO_OK) {
+        fail_all(s, s->active, rc);
+        fail_all(s, finished, rc);
+        return rc;
+      }
       std::vector<Request*> still;
       for (size_t k = 0; k < s->active.size(); ++k) {
         Request* r = s->active[k];
@@ -297,6 +428,7 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
         a.steps += 1;
         a.pcg_iters += x.pcg_iters;
         a.refinements += x.refinements;
+        a.reorth += x.reorth;
         a.n_dof = x.n_dof;
         a.nnz = x.nnz;
         a.sigma = x.sigma;
@@ -324,10 +456,14 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
       s->active.swap(still);
     }
     // 4. Retire: results to the host, arena space back.
-    for (Request* r : finished) {
-      if (!r->done) {
-        const int rc = retire(s, r);
-        if (rc != PARO_OK) return rc;
+    for (size_t k = 0; k < finished.size(); ++k) {
+      Request* r = finished[k];
+      const int rc = retire(s, r);
+      if (rc != PARO_OK) {
+        std::vector<Request*> rest(finished.begin() + k, finished.end());
+        fail_all(s, rest, rc);
+        fail_all(s, s->active, rc);
+        return rc;
       }
       s->unreported.push_back(r->id);
     }
@@ -339,7 +475,9 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
     if (n_done) *n_done = nd;
     s->ticks += 1;
     if (stats) {
-      stats->queued = (int32_t)s->queue.size();
+      std::lock_guard<std::mutex> lk(s->mu);
+      stats->queued = (int32_t)(s->queue.size() + s->job.size() +
+                                s->ready.size());
       stats->active = (int32_t)s->active.size();
       stats->done = s->retired;
       stats->arena_used = s->arena.used();
@@ -364,10 +502,20 @@ int paro_server_report(paro_server* s, int64_t id, paro_report_t* report) {
 
 void paro_server_destroy(paro_server* s) {
   if (!s) return;
+  if (s->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv.notify_all();
+    s->worker.join();  // after the round in flight, if any
+  }
   for (auto& kv : s->all) {
     if (kv.second->prob) paro_destroy(kv.second->prob);
     delete kv.second;
   }
+  if (s->admitted) (void)hipEventDestroy(s->admitted);
+  if (s->astream) (void)hipStreamDestroy(s->astream);
   delete s;
 }
 
