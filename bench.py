@@ -54,20 +54,23 @@ def solver_code_sha():
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def measured_traffic(kernel, path):
+def measured_traffic(kernel, path, workload=None):
     """HBM bytes per launch of a CG kernel from a committed PMC summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size), or
-    None when the summary is missing, lacks that kernel, or was taken on a
-    different solver source than the one built now."""
+    None when the summary is missing, lacks that kernel, covers another
+    workload than `workload` (if given), or was taken on a different
+    solver source than the one built now."""
     try:
         text = open(path).read()
         sha = solver_code_sha()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("solver_sha256: ",
+                  if line.startswith(("solver_sha256: ", "workload: ",
                                       "traffic_bytes_per_launch[")))
     if fields.get("solver_sha256") != sha:
+        return None
+    if workload is not None and fields.get("workload") != workload:
         return None
     value = fields.get(f"traffic_bytes_per_launch[{kernel}]")
     return None if value is None else float(value)
@@ -194,10 +197,11 @@ class Solver:
     """Whole solves of one workload (assembly + paro_solve) in one
     precision, with the caller-owned workspace kept across solves."""
 
-    def __init__(self, w, prec, golden, inner_rtol):
+    def __init__(self, w, prec, golden, inner_rtol, key):
         import torch
         from paper_1405_0260_amd import binding as pb
         self.pb, self.torch, self.w, self.prec = pb, torch, w, prec
+        self.key = key  # the workload's label (keys its traffic summary)
         dev = torch.device("cuda:0")
         self.golden = golden
         self.box = pb.Box.cube(w.nc, w.lo, w.hi)
@@ -276,10 +280,10 @@ class Solver:
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
         kname = KERNEL_NAMES[dom]
-        traffic = measured_traffic(kname, TRAFFIC[prec])
+        traffic = measured_traffic(kname, TRAFFIC[prec], self.key)
         if dom == "cg_spmm" and traffic is None:
             # Meshes beyond 2048 row tiles run the z-marching SpMM.
-            t2 = measured_traffic("spmm_zm_kernel", TRAFFIC[prec])
+            t2 = measured_traffic("spmm_zm_kernel", TRAFFIC[prec], self.key)
             if t2 is not None:
                 kname, traffic = "spmm_zm_kernel", t2
         all_ms = sum(v["ms"] for v in td["stages"].values())
@@ -345,7 +349,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    head = Solver(w, prec, golden, args.inner_rtol)
+    key = f"linear_{w.nc}c_N{w.N}_m{w.m}"
+    head = Solver(w, prec, golden, args.inner_rtol, key)
     main_res = head.run(args.steps, args.warmup, prec)
     if args.profile_only:
         log(json.dumps({"value": main_res["value"]}))
@@ -357,7 +362,7 @@ def main():
 
     other_res = None
     if not args.no_other_precision:
-        s2 = Solver(w, other, golden, args.inner_rtol)
+        s2 = Solver(w, other, golden, args.inner_rtol, key)
         r2 = s2.run(max(1, args.steps - 1), 0, other)
         other_res = dict(r2["summary"], precision=other,
                          roofline=s2.roofline())
@@ -373,7 +378,7 @@ def main():
                  "note": "working set fits the 256 MB Infinity Cache: "
                          "its CG kernel rates are cache-assisted"}
         for p in ("fp64", "mixed"):
-            s3 = Solver(w64, p, g64, args.inner_rtol)
+            s3 = Solver(w64, p, g64, args.inner_rtol, ctx64["workload"])
             r3 = s3.run(2, 1, f"64c {p}")
             ctx64[p] = dict(r3["summary"], roofline=s3.roofline())
             del s3
@@ -419,7 +424,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-inner/f64" if prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"linear_{w.nc}c_N{w.N}_m{w.m}",
+        "config": {"workload": key,
                    "potential": "20 soft-Coulomb centres, Z in 1..8, R in "
                                 "[-5,5]^3 (seed 3), box [-14,14]^3",
                    "n_dof": w.n_dof, "nnz": nnz,
@@ -595,6 +600,9 @@ def serve_bench(args, prec):
                 done_at[j] = t
                 reps[j] = rep
                 res[j] = lam
+                if len(done_at) % 200 == 0:
+                    log(f"[serve] {len(done_at)} of {len(reqs)} requests "
+                        f"done at {t:.1f} s")
         makespan = time.perf_counter() - t0
         lat = np.array([done_at[j] - arrive[j] for j in range(len(reqs))])
         upd = float(sum(reps[j].steps * work[j] for j in range(len(reqs))))
@@ -761,7 +769,8 @@ def adaptive_bench(args, golden):
            "fine": f"linear_{wf.nc}c_N{wf.N}_m{wf.m}"}
 
     def solver(w):
-        return Solver(w, "fp64", None, args.inner_rtol)
+        return Solver(w, "fp64", None, args.inner_rtol,
+                      f"linear_{w.nc}c_N{w.N}_m{w.m}")
 
     sc = solver(wc)
     dt_c, rep_c, _, _ = sc.solve()
@@ -816,7 +825,7 @@ def latency_bench(args):
 
     w = inputs.harmonic_24()
     conv = np.loadtxt(os.path.join(GOLDEN_DIR, "harmonic_24c_lowest10.txt"))
-    s = Solver(w, "fp64", conv, args.inner_rtol)
+    s = Solver(w, "fp64", conv, args.inner_rtol, f"harmonic_24c_N{w.N}")
     s.opts.max_steps = 30
     s.opts.lambda_tol = 0.0
     s.opts.resid_tol = 0.0

@@ -76,6 +76,15 @@ def test_traffic_summary_is_tied_to_the_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("spmm_cm_kernel", path) == 1234.0
     assert bench.measured_traffic("pupd_beta_kernel", path) == 5678.0
     assert bench.measured_traffic("rupd_alpha_kernel", path) is None
+    # A summary names the workload it was measured on; another workload's
+    # roofline gets no traffic from it.
+    traffic.write_text(_summary(sha, [
+        "workload: linear_96c_N32_m8",
+        "traffic_bytes_per_launch[pupd_beta_kernel]: 5678"]))
+    assert bench.measured_traffic("pupd_beta_kernel", path,
+                                  "linear_96c_N32_m8") == 5678.0
+    assert bench.measured_traffic("pupd_beta_kernel", path,
+                                  "softcoulomb_64c_N16_m8") is None
     traffic.write_text(_summary("0" * 64, [
         "traffic_bytes_per_launch[spmm_cm_kernel]: 1234"]))
     assert bench.measured_traffic("spmm_cm_kernel", path) is None
