@@ -526,8 +526,8 @@ def batch_bench(args, prec):
 
 
 def read_member_golden(path):
-    """{member index: requested eigenvalues} from a golden file whose data
-    lines read 'j lam_1 ... lam_N'."""
+    """{member index: (member name, requested eigenvalues)} from a golden
+    file whose data lines read 'j name lam_1 ... lam_N'."""
     out = {}
     if not os.path.exists(path):
         return out
@@ -535,20 +535,21 @@ def read_member_golden(path):
         if line.startswith("#") or not line.strip():
             continue
         v = line.split()
-        out[int(v[0])] = np.array([float(x) for x in v[1:]])
+        out[int(v[0])] = (v[1], np.array([float(x) for x in v[2:]]))
     return out
 
 
 def member_errors(path, lams, ws):
     """Relative lambda error of the sampled members (those with a stored
-    oracle reference) of a batch or served stream."""
+    oracle reference for the same member recipe, by name) of a batch or
+    served stream."""
     ref = read_member_golden(path)
     out = {}
-    for j, r in ref.items():
-        if j in lams:
+    for j, (name, r) in ref.items():
+        if j in lams and j < len(ws) and ws[j].name == name:
             lam = lams[j]
             lam = lam.cpu().numpy() if hasattr(lam, "cpu") else lam
-            out[ws[j].name] = lambda_error(lam[:ws[j].N], r[:ws[j].N])
+            out[name] = lambda_error(lam[:ws[j].N], r[:ws[j].N])
     return out
 
 

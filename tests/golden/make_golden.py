@@ -104,7 +104,8 @@ def linear_96c(nc=96, workers=None):
 def _member_lowest(name, ws, members, title):
     """Lowest N eigenvalues of the chosen members of a problem list
     (shift-invert Lanczos about the oracle's shift), one line per member:
-    'j lam_1 ... lam_N'."""
+    'j name lam_1 ... lam_N' (the name identifies the member's recipe, so a
+    reader can tell a different list apart)."""
     lines = []
     for j in members:
         w = ws[j]
@@ -119,13 +120,15 @@ def _member_lowest(name, ws, members, title):
         lam2, _ = reference.sparse_lowest(H, M, w.Nt + 6, s)
         assert np.allclose(lam[:w.N], lam2[:w.N], rtol=1e-12, atol=0), \
             (w.name, lam[:w.N], lam2[:w.N])
-        lines.append(f"{j} " + " ".join(f"{x:.17g}" for x in lam[:w.N]))
+        lines.append(f"{j} {w.name} " +
+                     " ".join(f"{x:.17g}" for x in lam[:w.N]))
         print(f"  {w.name}: {lam[:min(3, w.N)]}", flush=True)
     path = os.path.join(HERE, name)
     with open(path, "w") as f:
         f.write(f"# {title}\n# oracle.reference.sparse_lowest (shift-invert "
                 "Lanczos about the oracle's shift - 0.5), lowest N per member"
-                "\n# line: member index, then its N requested eigenvalues\n"
+                "\n# line: member index, member name, then its N requested "
+                "eigenvalues\n"
                 "# written by: python tests/golden/make_golden.py\n")
         f.write("\n".join(lines) + "\n")
     print("wrote", path)

@@ -100,18 +100,21 @@ def test_lambda_error_uses_the_floor():
 
 def test_member_golden_format(tmp_path):
     g = tmp_path / "members.txt"
-    g.write_text("# header\n3 -1.5 -1.25\n7 2.5\n")
+    g.write_text("# header\n3 a -1.5 -1.25\n7 b 2.5\n")
     ref = bench.read_member_golden(str(g))
-    assert set(ref) == {3, 7} and np.array_equal(ref[3], [-1.5, -1.25])
+    assert set(ref) == {3, 7} and ref[3][0] == "a"
+    assert np.array_equal(ref[3][1], [-1.5, -1.25])
 
     class W:
         def __init__(self, name, N):
             self.name, self.N = name, N
-    ws = {3: W("a", 2), 7: W("b", 1)}
-    errs = bench.member_errors(str(g), {3: np.array([-1.5, -1.25, 9.0]),
-                                        7: np.array([2.5 * (1 + 1e-9)])},
-                               ws)
+    ws = [W("x", 1)] * 3 + [W("a", 2)] + [W("x", 1)] * 3 + [W("b", 1)]
+    lams = {3: np.array([-1.5, -1.25, 9.0]), 7: np.array([2.5 * (1 + 1e-9)])}
+    errs = bench.member_errors(str(g), lams, ws)
     assert errs["a"] == 0.0 and abs(errs["b"] - 1e-9) < 1e-15
+    # A list whose member 7 is another recipe is not compared there.
+    ws[7] = W("c", 1)
+    assert set(bench.member_errors(str(g), lams, ws)) == {"a"}
 
 
 def test_more_than_one_gpu_is_refused():
