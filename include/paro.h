@@ -7,7 +7,9 @@
  * iteration of Dai, Gong, Zhou and Zhu (arXiv:1405.0260):
  *   Algorithm A.1 (appendix; linear eigenproblem, a(u,v) = int A grad u .
  *   grad v + c u v with A = I/2 and c = V), with the N + m buffer orbitals of
- *   Algorithm 3.2, and Step 2 (mesh adaptation) taken as the identity:
+ *   Algorithm 3.2; Step 2 (mesh adaptation) is the identity inside
+ *   paro_step, and is offered separately (estimate, mark, refine,
+ *   transfer) on the uniform mesh and on general bisection meshes:
  *     Step 3: for every orbital i independently solve the source problem
  *             a(u_i^{n+1/2}, v) = lambda_i^n (u_i^n, v) for all v,
  *     Step 4: Rayleigh-Ritz on span{u_i^{n+1/2}} giving (lambda_i^{n+1},
@@ -417,6 +419,105 @@ int paro_mark(const double* d_eta, int64_t count, double theta,
  * of its ends.  Asynchronous; 1 <= ncols <= 64. */
 int paro_prolong(const paro_box_t* coarse, const double* d_Uc, double* d_Uf,
                  int32_t ncols, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Step 2 with local refinement: general bisection meshes of a box (Sec. 2
+ * adaptive loop; Algorithm 3.1 Step 2 builds T_{n+1} from T_n).  The
+ * paper leaves the refinement to the literature; the library uses
+ * Maubach's tagged bisection: an element is an ordered vertex list
+ * (x0, x1, x2, x3) with a tag k in {1, 2, 3}; it is cut at the midpoint z
+ * of its refinement edge (x0, xk) into (x0, .., x_{k-1}, z, x_{k+1}, ..,
+ * x3) and (x1, .., xk, z, x_{k+1}, .., x3), both tagged k - 1 (3 after
+ * 1).  Before an element is cut at an edge, every element around the edge
+ * with another refinement edge is bisected first (recursively), and then
+ * all elements around it are cut together, so the mesh stays conforming.
+ * The uniform Kuhn mesh (elements c, c + e_p0, c + e_p0 + e_p1,
+ * c + (1,1,1), tag 3, numbered as for paro_elements) is the usual start.
+ * Vertices on the box boundary carry the Dirichlet data; the interior
+ * vertices in vertex order are the dofs.  A mesh is a host object;
+ * problems assembled on it are solved by paro_init / paro_step /
+ * paro_solve and the batch and cluster calls like box problems, in
+ * PARO_FP64 (the operator is stored in CSR: no stencil, no FP32 copy).
+ * --------------------------------------------------------------------- */
+typedef struct paro_mesh paro_mesh;  /* opaque, host memory only */
+
+/* The uniform Kuhn mesh of the box as a bisection mesh.  PARO_EINVAL for
+ * a bad box or one beyond 32-bit element indices. */
+int paro_mesh_create(const paro_box_t* box, paro_mesh** out);
+
+/* A mesh from host arrays: X (nv x 3 coordinates), tets (ne x 4 ordered
+ * vertex lists), tags (ne, in 1..3), parents (nv x 2: the ends of the
+ * edge a vertex halves, each older than the vertex, or -1, -1; NULL: all
+ * -1).  box: lo and hi of the domain (its cell counts are not used).
+ * The arrays are copied.  PARO_EINVAL for indices out of range, repeated
+ * corners, tags outside 1..3 or non-finite coordinates. */
+int paro_mesh_from_arrays(const paro_box_t* box, int64_t nv, const double* X,
+                          int64_t ne, const int32_t* tets,
+                          const int32_t* tags, const int32_t* parents,
+                          paro_mesh** out);
+
+/* Sizes (any pointer may be NULL). */
+int paro_mesh_info(const paro_mesh* m, int64_t* nv, int64_t* ne,
+                   int64_t* n_dof);
+
+/* Copies of the mesh into host buffers of the sizes paro_mesh_info gives
+ * (any pointer may be NULL): X (nv x 3), tets (ne x 4), tags (ne),
+ * parents (nv x 2), dof (nv: the dof of a vertex, -1 on the boundary). */
+int paro_mesh_arrays(const paro_mesh* m, double* X, int32_t* tets,
+                     int32_t* tags, int32_t* parents, int32_t* dof);
+
+/* Refine: bisect every element with marked[e] != 0 (host array of ne
+ * bytes, e.g. paro_mark's output copied to the host) at least once, with
+ * the conforming closure, into a new mesh *out (m is unchanged).  Old
+ * vertices keep their indices; new vertices follow in creation order with
+ * their parents; surviving elements keep their order, new ones follow.
+ * Host only. */
+int paro_mesh_refine(const paro_mesh* m, const uint8_t* marked,
+                     paro_mesh** out);
+
+void paro_mesh_destroy(paro_mesh* m);
+
+/* Sizes of a problem on the mesh (as paro_query): n_dof, nnz of the CSR
+ * operator, and the workspace of paro_mesh_assemble.  Host only; builds
+ * the pattern, so it costs about as much as the host part of assembly.
+ * PARO_EINVAL also for a precision other than PARO_FP64. */
+int paro_mesh_query(const paro_mesh* m, const paro_opts_t* opts,
+                    int64_t* n_dof, int64_t* nnz, size_t* workspace_bytes);
+
+/* Assemble on the mesh (as paro_assemble): d_V is the nodal potential at
+ * every vertex (nv doubles, device; copied), the operator A_s = K/2 + M_V
+ * - s M and M go to CSR in the workspace (values gathered row by row over
+ * the incident elements in a fixed order: no atomics), together with the
+ * mesh tables that paro_mesh_estimate reads.  Synchronises `stream` once.
+ * The problem serves paro_init / paro_step / paro_solve, the batch calls,
+ * paro_set_clusters, paro_spmm, paro_gram, paro_pcg and paro_export_csr;
+ * paro_update_potential and paro_set_nonlocal return PARO_EINVAL. */
+int paro_mesh_assemble(const paro_mesh* m, const double* d_V,
+                       const paro_opts_t* opts, void* d_workspace,
+                       size_t bytes, void* stream, paro_problem** out);
+
+/* Estimate on a mesh problem: the indicator of paro_estimate for every
+ * element of the mesh it was assembled on (d_eta: ne doubles), from the
+ * first nreq columns of d_U (n_dof x ncols) with eigenvalues d_lambda and
+ * the problem's nodal potential.  Asynchronous.  Mark with paro_mark. */
+int paro_mesh_estimate(const paro_problem* p, const double* d_lambda,
+                       const double* d_U, int32_t ncols, int32_t nreq,
+                       double* d_eta, void* stream);
+
+/* Carry orbitals to a refined mesh by P1 interpolation (exact: the coarse
+ * space lies in the fine one): fine must come from coarse by
+ * paro_mesh_refine (one call or several: old vertices keep their indices)
+ * -- checked on the coordinates.  d_Uc (coarse n_dof x ncols) -> d_Uf
+ * (fine n_dof x ncols): old dofs keep their values, a new vertex takes the
+ * mean of the two ends of the edge it halves (0 on the boundary),
+ * generation by generation.  d_ws: device scratch of
+ * paro_mesh_prolong_workspace_bytes(coarse, fine), 256-byte aligned.
+ * Synchronises `stream` once (the host tables it uploads). */
+size_t paro_mesh_prolong_workspace_bytes(const paro_mesh* coarse,
+                                         const paro_mesh* fine);
+int paro_mesh_prolong(const paro_mesh* coarse, const paro_mesh* fine,
+                      const double* d_Uc, double* d_Uf, int32_t ncols,
+                      void* d_ws, size_t bytes, void* stream);
 
 /* Message for the last failing call on this thread (never NULL). */
 const char* paro_last_error(void);

@@ -144,6 +144,27 @@ def lib():
         "paro_mark": (c_i32, [P, c_i64, c_dbl, c_i32, P,
                               ctypes.POINTER(c_i64), P, ctypes.c_size_t, P]),
         "paro_prolong": (c_i32, [ctypes.POINTER(Box), P, P, c_i32, P]),
+        "paro_mesh_create": (c_i32, [ctypes.POINTER(Box), ctypes.POINTER(P)]),
+        "paro_mesh_from_arrays": (c_i32, [ctypes.POINTER(Box), c_i64, P,
+                                          c_i64, P, P, P,
+                                          ctypes.POINTER(P)]),
+        "paro_mesh_info": (c_i32, [P, ctypes.POINTER(c_i64),
+                                   ctypes.POINTER(c_i64),
+                                   ctypes.POINTER(c_i64)]),
+        "paro_mesh_arrays": (c_i32, [P, P, P, P, P, P]),
+        "paro_mesh_refine": (c_i32, [P, P, ctypes.POINTER(P)]),
+        "paro_mesh_destroy": (None, [P]),
+        "paro_mesh_query": (c_i32, [P, ctypes.POINTER(Opts),
+                                    ctypes.POINTER(c_i64),
+                                    ctypes.POINTER(c_i64),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
+        "paro_mesh_assemble": (c_i32, [P, P, ctypes.POINTER(Opts), P,
+                                       ctypes.c_size_t, P,
+                                       ctypes.POINTER(P)]),
+        "paro_mesh_estimate": (c_i32, [P, P, P, c_i32, c_i32, P, P]),
+        "paro_mesh_prolong_workspace_bytes": (ctypes.c_size_t, [P, P]),
+        "paro_mesh_prolong": (c_i32, [P, P, P, P, c_i32, P, ctypes.c_size_t,
+                                      P]),
         "paro_small_geneig": (c_i32, [P, P, c_i32, P, P, P, P]),
         "paro_pcg": (c_i32, [P, P, P, c_i32, P, P]),
         "paro_set_timing": (c_i32, [P, c_i32]),
@@ -402,6 +423,140 @@ def paro_prolong(box: Box, Uc, Uf, stream=None):
     ncols = Uc.shape[1]
     _check(lib().paro_prolong(ctypes.byref(box), _ptr(Uc), _ptr(Uf), ncols,
                               _stream(stream)))
+
+
+# ------------------------------------------------- general bisection meshes
+
+class Mesh:
+    """A bisection mesh of a box (host object of the library).  Arrays
+    come back as numpy copies."""
+
+    def __init__(self, handle, box):
+        self.handle = handle
+        self.box = box
+
+    @classmethod
+    def kuhn(cls, box: Box) -> "Mesh":
+        h = c_vp()
+        _check(lib().paro_mesh_create(ctypes.byref(box), ctypes.byref(h)))
+        return cls(h, box)
+
+    @classmethod
+    def from_arrays(cls, box: Box, X, tets, tags, parents=None) -> "Mesh":
+        import numpy as np
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        tags = np.ascontiguousarray(tags, dtype=np.int32)
+        if parents is not None:
+            parents = np.ascontiguousarray(parents, dtype=np.int32)
+        h = c_vp()
+        _check(lib().paro_mesh_from_arrays(
+            ctypes.byref(box), X.shape[0], X.ctypes.data, tets.shape[0],
+            tets.ctypes.data, tags.ctypes.data,
+            None if parents is None else parents.ctypes.data,
+            ctypes.byref(h)))
+        return cls(h, box)
+
+    def info(self):
+        """(vertices, elements, dofs)."""
+        nv, ne, n = c_i64(), c_i64(), c_i64()
+        _check(lib().paro_mesh_info(self.handle, ctypes.byref(nv),
+                                    ctypes.byref(ne), ctypes.byref(n)))
+        return nv.value, ne.value, n.value
+
+    def arrays(self):
+        """dict of X, tets, tags, parents, dof (numpy)."""
+        import numpy as np
+        nv, ne, _ = self.info()
+        out = {"X": np.empty((nv, 3)), "tets": np.empty((ne, 4), np.int32),
+               "tags": np.empty(ne, np.int32),
+               "parents": np.empty((nv, 2), np.int32),
+               "dof": np.empty(nv, np.int32)}
+        _check(lib().paro_mesh_arrays(
+            self.handle, out["X"].ctypes.data, out["tets"].ctypes.data,
+            out["tags"].ctypes.data, out["parents"].ctypes.data,
+            out["dof"].ctypes.data))
+        return out
+
+    def refine(self, marked) -> "Mesh":
+        """Bisect the marked elements (host bool/uint8 array or a device
+        uint8 tensor) with the conforming closure."""
+        import numpy as np
+        if hasattr(marked, "cpu"):
+            marked = marked.cpu().numpy()
+        m = np.ascontiguousarray(marked, dtype=np.uint8)
+        _, ne, _ = self.info()
+        if m.shape != (ne,):
+            raise ValueError(f"marked must have {ne} entries")
+        h = c_vp()
+        _check(lib().paro_mesh_refine(self.handle, m.ctypes.data,
+                                      ctypes.byref(h)))
+        return Mesh(h, self.box)
+
+    def close(self):
+        if self.handle:
+            lib().paro_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def paro_mesh_query(mesh: Mesh, opts: Opts):
+    n, z, b = c_i64(), c_i64(), ctypes.c_size_t()
+    _check(lib().paro_mesh_query(mesh.handle, ctypes.byref(opts),
+                                 ctypes.byref(n), ctypes.byref(z),
+                                 ctypes.byref(b)))
+    return n.value, z.value, b.value
+
+
+def paro_mesh_assemble(mesh: Mesh, V, opts: Opts, stream=None,
+                       workspace=None) -> Problem:
+    """Assemble on a mesh; V: float64 device tensor of all vertices."""
+    import torch
+    n, z, nbytes = paro_mesh_query(mesh, opts)
+    nv, _, _ = mesh.info()
+    _f64(V, (nv,), "V")
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                device=V.device)
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    h = c_vp()
+    _check(lib().paro_mesh_assemble(mesh.handle, _ptr(V), ctypes.byref(opts),
+                                    base + off, workspace.numel() - off,
+                                    _stream(stream), ctypes.byref(h)))
+    p = Problem(h, mesh.box, opts, workspace, n, z)
+    p.mesh = mesh  # keeps the host mesh alive with the problem
+    return p
+
+
+def paro_mesh_estimate(p: Problem, lam, U, nreq, eta, stream=None):
+    """Indicator per element of the mesh p was assembled on."""
+    n, ncols = U.shape
+    _f64(U, (p.n, ncols), "U")
+    _f64(lam, (ncols,), "lambda")
+    _, ne, _ = p.mesh.info()
+    _f64(eta, (ne,), "eta")
+    _check(lib().paro_mesh_estimate(p.handle, _ptr(lam), _ptr(U), ncols,
+                                    nreq, _ptr(eta), _stream(stream)))
+
+
+def paro_mesh_prolong(coarse: Mesh, fine: Mesh, Uc, Uf, stream=None):
+    """Orbitals of `coarse` -> the refined mesh `fine` (P1 transfer)."""
+    import torch
+    ncols = Uc.shape[1]
+    nbytes = lib().paro_mesh_prolong_workspace_bytes(coarse.handle,
+                                                     fine.handle)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=Uc.device)
+    off = (-ws.data_ptr()) % 256
+    _check(lib().paro_mesh_prolong(coarse.handle, fine.handle, _ptr(Uc),
+                                   _ptr(Uf), ncols,
+                                   ctypes.c_void_p(ws.data_ptr() + off),
+                                   nbytes, _stream(stream)))
 
 
 def paro_small_geneig(A, B, theta, C, info, stream=None):

@@ -27,7 +27,7 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
          f"-I{INCLUDE}", f"-I{CSRC}"]
 SOURCES = ["assemble.hip", "solver.hip", "api.hip", "serve.hip", "ks.hip",
-           "adapt.hip", "reorth.hip"]
+           "adapt.hip", "reorth.hip", "mesh.hip"]
 
 
 def _compile(src: str) -> str:

@@ -417,12 +417,178 @@ bool box_ok(const paro_box_t* box) {
     }                                                                   \
   } while (0)
 
+// ---- general (bisection) meshes --------------------------------------
+// The same indicator on an element of a general mesh: corners from the
+// element list, values through the dof map (0 on the boundary), the
+// gradient from the element's edge vectors, the element across each face
+// from the face-neighbour table.
+
+// Coordinates and values of orbital column i at the corners of element e.
+__device__ __forceinline__ void mesh_corners(
+    const int32_t* __restrict__ tets, const double* __restrict__ Xv,
+    const int32_t* __restrict__ dofmap, const double* __restrict__ U,
+    int ncols, int i, long long e, double (&X)[4][3], double (&u)[4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int32_t v = tets[4 * e + a];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) X[a][x] = Xv[3 * (size_t)v + x];
+    const int32_t d = dofmap[v];
+    u[a] = d >= 0 ? U[(size_t)d * ncols + i] : 0.0;
+  }
+}
+
+// Gradient of the P1 interpolant of u on the element with corners X (the
+// edge vectors' inverse by cofactors); returns |det| = 6 |T|.
+__device__ __forceinline__ double mesh_grad(const double (&X)[4][3],
+                                            const double (&u)[4],
+                                            double (&g)[3]) {
+  double E[3][3], du[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    du[a] = u[a + 1] - u[0];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) E[a][x] = X[a + 1][x] - X[0][x];
+  }
+  double cof[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+      const int x1 = (x + 1) % 3, x2 = (x + 2) % 3;
+      cof[a][x] = E[a1][x1] * E[a2][x2] - E[a1][x2] * E[a2][x1];
+    }
+  const double det = E[0][0] * cof[0][0] + E[0][1] * cof[0][1] +
+                     E[0][2] * cof[0][2];
+  // E g = du  =>  g = E^{-1} du, (E^{-1})[x][a] = cof[a][x] / det.
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+    g[x] = (cof[0][x] * du[0] + cof[1][x] * du[1] + cof[2][x] * du[2]) / det;
+  return fabs(det);
+}
+
+__global__ void __launch_bounds__(kBlock)
+mesh_estimate_kernel(const int32_t* __restrict__ tets,
+                     const int32_t* __restrict__ nbr,
+                     const double* __restrict__ Xv,
+                     const int32_t* __restrict__ dofmap,
+                     const double* __restrict__ Vv,
+                     const double* __restrict__ lam,
+                     const double* __restrict__ U, int ncols, int nreq,
+                     int NP, long long nelem, double* __restrict__ eta) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long e = t / NP;
+  const int i = (int)(t % NP);
+  double s = 0.0;
+  if (e < nelem && i < nreq) {
+    double X[4][3], u[4], vv[4];
+    mesh_corners(tets, Xv, dofmap, U, ncols, i, e, X, u);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) vv[a] = Vv[tets[4 * e + a]];
+    double hT2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a + 1; b < 4; ++b) {
+        double l2 = 0.0;
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+          l2 += (X[a][x] - X[b][x]) * (X[a][x] - X[b][x]);
+        hT2 = fmax(hT2, l2);
+      }
+    double gT[3];
+    const double vol = mesh_grad(X, u, gT) / 6.0;
+    const double l = lam[i];
+    double R[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        R[a][b] = 0.5 * l * (u[a] + u[b]) - 0.5 * (vv[a] * u[b] + vv[b] * u[a]);
+    double r2 = 0.0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            r2 += R[a][b] * R[cc][d] * quartic(a, b, cc, d);
+    s = hT2 * vol * r2;
+    for (int k = 0; k < 4; ++k) {
+      const int32_t f = nbr[4 * e + k];
+      if (f < 0) continue;  // boundary face
+      double Xn[4][3], un[4], gN[3];
+      mesh_corners(tets, Xv, dofmap, U, ncols, i, f, Xn, un);
+      (void)mesh_grad(Xn, un, gN);
+      double F[3][3];
+      int m = 0;
+      for (int a = 0; a < 4; ++a) {
+        if (a == k) continue;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) F[m][x] = X[a][x];
+        ++m;
+      }
+      const double e1[3] = {F[1][0] - F[0][0], F[1][1] - F[0][1],
+                            F[1][2] - F[0][2]};
+      const double e2[3] = {F[2][0] - F[0][0], F[2][1] - F[0][1],
+                            F[2][2] - F[0][2]};
+      const double nrm[3] = {e1[1] * e2[2] - e1[2] * e2[1],
+                             e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+      const double nn = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] +
+                             nrm[2] * nrm[2]);
+      double hF2 = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b) {
+          double l2 = 0.0;
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+            l2 += (F[a][x] - F[b][x]) * (F[a][x] - F[b][x]);
+          hF2 = fmax(hF2, l2);
+        }
+      double j = 0.0;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) j += (gT[x] - gN[x]) * nrm[x];
+      j = 0.5 * j / nn;
+      s += 0.5 * sqrt(hF2) * (0.5 * nn) * j * j;
+    }
+  }
+  for (int o = NP / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, NP);
+  if (e < nelem && i == 0) eta[e] = sqrt(s);
+}
+
 }  // namespace
 }  // namespace paro
 
 using namespace paro;
 
 extern "C" {
+
+int paro_mesh_estimate(const paro_problem* h, const double* d_lambda,
+                       const double* d_U, int32_t ncols, int32_t nreq,
+                       double* d_eta, void* stream) {
+  if (!h || !d_lambda || !d_U || !d_eta)
+    return set_error(PARO_EINVAL, "bad argument to paro_mesh_estimate");
+  const Problem& p = h->p;
+  if (!p.csr)
+    return set_error(PARO_EINVAL,
+                     "paro_mesh_estimate needs a problem assembled on a "
+                     "mesh (paro_estimate serves box problems)");
+  if (ncols < 1 || ncols > kNtMax || nreq < 1 || nreq > ncols)
+    return set_error(PARO_EINVAL, "need 1 <= nreq <= ncols <= 64");
+  int NP = 1;
+  while (NP < nreq) NP <<= 1;
+  const long long threads = (long long)p.ne * NP;
+  const long long blocks = (threads + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL)
+    return set_error(PARO_EINVAL, "mesh too large for paro_mesh_estimate");
+  hipLaunchKernelGGL(mesh_estimate_kernel, dim3((unsigned)blocks),
+                     dim3(kBlock), 0, (hipStream_t)stream, p.tets, p.nbr,
+                     p.Xv, p.dofmap, p.Vv, d_lambda, d_U, ncols, nreq, NP,
+                     (long long)p.ne, d_eta);
+  AD_HIP(hipGetLastError());
+  return PARO_OK;
+}
 
 int64_t paro_elements(const paro_box_t* box) {
   if (!box_ok(box)) return 0;

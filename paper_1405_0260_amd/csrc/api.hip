@@ -87,7 +87,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b) {
 // graph stays valid while the launch shape (table address, grid, vector
 // widths, problem count, nonlocal projector count, SpMM segmentation) is
 // unchanged.
-typedef std::array<int64_t, 21> GraphKey;
+typedef std::array<int64_t, 22> GraphKey;
 struct GraphCache {
   std::map<GraphKey, hipGraphExec_t> m;
   ~GraphCache() {
@@ -172,8 +172,8 @@ void carve(Problem& p, char* base, const Layout& L) {
   auto at = [&](size_t off) { return (void*)(base + off); };
   p.dinv = (double*)at(L.dinv);
   p.dinv32 = L.dinv32 ? (float*)at(L.dinv32) : nullptr;
-  p.diagA = (double*)at(L.diagA);
-  p.diagM = (double*)at(L.diagM);
+  p.diagA = L.diagA ? (double*)at(L.diagA) : nullptr;
+  p.diagM = L.diagM ? (double*)at(L.diagM) : nullptr;
   p.diagA32 = L.diagA32 ? (float*)at(L.diagA32) : nullptr;
   p.X = (double*)at(L.X);
   p.R = (double*)at(L.R);
@@ -205,6 +205,20 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.Zp = nullptr;
   p.kz = 0;
   p.zy = p.zpart = nullptr;
+  p.csr = L.rowptr != 0;
+  if (p.csr) {
+    p.rowptr = (int32_t*)at(L.rowptr);
+    p.colidx = (int32_t*)at(L.colidx);
+    p.valA = (double*)at(L.valA);
+    p.valM = (double*)at(L.valM);
+    p.inc_ptr = (int32_t*)at(L.inc_ptr);
+    p.inc = (int32_t*)at(L.inc);
+    p.tets = (int32_t*)at(L.tets);
+    p.Xv = (double*)at(L.Xv);
+    p.Vv = (double*)at(L.Vv);
+    p.dofmap = (int32_t*)at(L.dofmap);
+    p.nbr = (int32_t*)at(L.nbr);
+  }
 }
 
 int pick_grid(int64_t n, int Nt) {
@@ -286,6 +300,22 @@ void desc_init(Problem& p) {
   d.kz = p.kz;
   d.zy = p.zy;
   d.zpart = p.zpart;
+  d.csr = p.csr ? 1 : 0;
+  if (p.csr) {
+    d.rowptr = p.rowptr;
+    d.colidx = p.colidx;
+    d.valA = p.valA;
+    d.valM = p.valM;
+    d.mx = d.my = d.mz = 0;
+    d.zm = 0;
+    // p.q segments of the CSR CG SpMM: kBlock rows each, or a multiple
+    // when that would exceed kSpmmSegMax segments.
+    const long long per = (p.n + kSpmmSegMax * (long long)kBlock - 1) /
+                          (kSpmmSegMax * (long long)kBlock);
+    d.csr_rows = (int)(kBlock * (per < 1 ? 1 : per));
+    d.pqn = (int)((p.n + d.csr_rows - 1) / d.csr_rows);
+    d.spg = 1;
+  }
 }
 
 // Column count of a descriptor (component calls use fewer than N + m).
@@ -318,7 +348,9 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
   L.zmg = 0;
   for (int i = 0; i < n; ++i) {
     const Desc& d = tab[i];
-    if (d.zm) {
+    if (d.csr) {
+      L.csr = 1;
+    } else if (d.zm) {
       L.zm = 1;
       // Chunks per unit: the first z-marching problem's tuned variant
       // (any choice gives the same results).
@@ -409,8 +441,8 @@ int cg_graph(Ctx& c, bool fp32, int par, int k, hipStream_t s) {
   const GraphKey key = {
       (int64_t)(uintptr_t)L.d, L.nprob, L.blocks, L.gblocks, L.maxcols,
       L.mincols, L.nt16, L.tr64, L.tr32, L.vmax64, L.v64u, L.v32u,
-      L.nt16_mixed, L.maxkz, L.seg, L.ntile, L.zm, L.zmg, fp32 ? 1 : 0,
-      par, k};
+      L.nt16_mixed, L.maxkz, L.seg, L.ntile, L.zm, L.zmg, L.csr,
+      fp32 ? 1 : 0, par, k};
   auto it = c.graphs->m.find(key);
   if (it == c.graphs->m.end()) {
     hipStream_t cs = capture_stream();
@@ -590,7 +622,8 @@ int run_cg_persistent(Ctx& c, bool fp32, hipStream_t s, int slot) {
 }
 
 int run_cg(Ctx& c, bool fp32, hipStream_t s, int slot) {
-  if (g_persistent_on.load() && c.L.maxkz == 0 && c.L.zm == 0) {
+  if (g_persistent_on.load() && c.L.maxkz == 0 && c.L.zm == 0 &&
+      c.L.csr == 0) {
     const int rc = run_cg_persistent(c, fp32, s, slot);
     if (rc != 1) return rc;  // 1: does not fit, run kernel by kernel
   }
@@ -674,6 +707,19 @@ int read_reports(Ctx& c, std::vector<PollReport>& out, hipStream_t s) {
   return PARO_OK;
 }
 
+// General meshes have no operator path in the start kernel: a start that
+// cannot reuse a rotation's H U and M U (use_hu = 0) forms them from U0
+// first (use_hu = 2, launch_csr_dual mode 2).  True if any problem does.
+bool mark_csr_starts(Ctx& c) {
+  bool any = false;
+  for (Desc& d : c.tab)
+    if (d.csr && d.use_hu == 0) {
+      d.use_hu = 2;
+      any = true;
+    }
+  return any;
+}
+
 // Problems whose Rayleigh-Ritz factorisation of W^T M W failed (status
 // bit kStSingular in the reports just read) get one shifted Cholesky-QR
 // re-orthonormalisation of W and the projection again, on a table of
@@ -725,8 +771,10 @@ int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
                 bool trust) {
   const double t0 = now_s();
   for (Desc& d : c.tab) d.use_hu = trust ? 1 : 0;
+  const bool csr_hu = mark_csr_starts(c);
   int rc = upload(c, s);
   if (rc) return rc;
+  if (csr_hu) HIP_OR_FAIL(launch_csr_dual(c.L, 2, s, c.timing));
   HIP_OR_FAIL(launch_pcg_start(c.L, s, c.timing));
   int64_t refinements = 0;
   rc = solve_sources(c, s, &refinements);
@@ -924,8 +972,8 @@ int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
 int status_code(int st) { return status_to_code(st); }
 
-Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
-  (void)nnz;  // the stencil arrays do not depend on the pattern's size
+Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
+                   const MeshSizes* ms) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -935,11 +983,26 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision) {
   };
   const bool f32 = precision == PARO_FP32_INNER;
   const size_t blk = (size_t)n * Nt;
+  if (ms) {
+    // General mesh: the CSR operator and the mesh tables come first (the
+    // first region sits at offset 0, so a nonzero offset marks a mesh).
+    L.Xv = take(sizeof(double) * 3 * ms->nv);
+    L.rowptr = take(sizeof(int32_t) * (n + 1));
+    L.colidx = take(sizeof(int32_t) * nnz);
+    L.valA = take(sizeof(double) * nnz);
+    L.valM = take(sizeof(double) * nnz);
+    L.inc_ptr = take(sizeof(int32_t) * (n + 1));
+    L.inc = take(sizeof(int32_t) * 2 * ms->ninc);
+    L.tets = take(sizeof(int32_t) * 4 * ms->ne);
+    L.Vv = take(sizeof(double) * ms->nv);
+    L.dofmap = take(sizeof(int32_t) * ms->nv);
+    L.nbr = take(sizeof(int32_t) * 4 * ms->ne);
+  }
   L.dinv = take(sizeof(double) * n);
   L.dinv32 = f32 ? take(sizeof(float) * n) : 0;
-  L.diagA = take(sizeof(double) * kStencil * n);
-  L.diagM = take(sizeof(double) * kStencil * n);
-  L.diagA32 = f32 ? take(sizeof(float) * kStencil * n) : 0;
+  L.diagA = ms ? 0 : take(sizeof(double) * kStencil * n);
+  L.diagM = ms ? 0 : take(sizeof(double) * kStencil * n);
+  L.diagA32 = f32 && !ms ? take(sizeof(float) * kStencil * n) : 0;
   L.X = take(sizeof(double) * blk);
   L.R = take(sizeof(double) * blk);
   L.P = take(sizeof(double) * blk);
@@ -1155,6 +1218,140 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Problems on general (bisection) meshes: the operator in CSR.
+// ---------------------------------------------------------------------------
+namespace {
+int mesh_shape(const paro_mesh* m, const paro_opts_t* opts, MeshOps* ops,
+               Layout* L) {
+  if (!m) return fail(PARO_EINVAL, "NULL mesh");
+  int rc = mesh_ops(m->m, ops);
+  if (rc) return rc;
+  rc = check_opts(opts, ops->n);
+  if (rc) return rc;
+  if (opts->precision != PARO_FP64)
+    return fail(PARO_EINVAL, "mesh problems are solved in PARO_FP64");
+  MeshSizes ms{m->m.nv(), m->m.ne(), (int64_t)ops->inc_ptr[ops->n]};
+  *L = make_layout(ops->n, (int64_t)ops->colidx.size(), opts->N + opts->m,
+                   PARO_FP64, &ms);
+  return PARO_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int paro_mesh_query(const paro_mesh* m, const paro_opts_t* opts,
+                    int64_t* n_dof, int64_t* nnz, size_t* workspace_bytes) {
+  try {
+    MeshOps ops;
+    Layout L;
+    const int rc = mesh_shape(m, opts, &ops, &L);
+    if (rc) return rc;
+    if (n_dof) *n_dof = ops.n;
+    if (nnz) *nnz = (int64_t)ops.colidx.size();
+    if (workspace_bytes) *workspace_bytes = L.total;
+    return PARO_OK;
+  } catch (...) {
+    return fail(PARO_EDEVICE, "host allocation failed");
+  }
+}
+
+int paro_mesh_assemble(const paro_mesh* m, const double* d_V,
+                       const paro_opts_t* opts, void* d_ws, size_t bytes,
+                       void* stream, paro_problem** out) {
+  try {
+    if (!out) return fail(PARO_EINVAL, "out is NULL");
+    *out = nullptr;
+    MeshOps ops;
+    Layout L;
+    int rc = mesh_shape(m, opts, &ops, &L);
+    if (rc) return rc;
+    if (!d_V || !d_ws) return fail(PARO_EINVAL, "NULL device pointer");
+    if (((uintptr_t)d_ws & 255) != 0)
+      return fail(PARO_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < L.total)
+      return fail(PARO_ENOMEM, "workspace %zu bytes < %zu required", bytes,
+                  L.total);
+    const MeshData& md = m->m;
+    hipStream_t s = (hipStream_t)stream;
+    paro_problem* h = new (std::nothrow) paro_problem();
+    if (!h) return fail(PARO_EDEVICE, "host allocation failed");
+    Problem& p = h->p;
+    std::memset(&p.box, 0, sizeof p.box);
+    for (int a = 0; a < 3; ++a) {
+      p.box.lo[a] = md.lo[a];
+      p.box.hi[a] = md.hi[a];
+    }
+    p.opts = *opts;
+    p.mx = p.my = p.mz = 0;
+    p.n = ops.n;
+    p.nnz = (int64_t)ops.colidx.size();
+    p.N = opts->N;
+    p.Nt = opts->N + opts->m;
+    p.h[0] = p.h[1] = p.h[2] = 0.0;
+    p.grid = pick_grid(p.n, p.Nt);
+    p.ws_bytes = bytes;
+    p.last_stream = s;
+    p.nv = md.nv();
+    p.ne = md.ne();
+    carve(p, (char*)d_ws, L);
+    auto bail = [&](int code) {
+      delete h;
+      return code;
+    };
+    auto put = [&](void* dst, const void* src, size_t n) {
+      return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+    };
+    hipError_t he =
+        hipMemsetAsync((char*)d_ws + L.vmin, 0, L.total - L.vmin, s);
+    if (he == hipSuccess)
+      he = put(p.Xv, md.X.data(), sizeof(double) * md.X.size());
+    if (he == hipSuccess)
+      he = put(p.rowptr, ops.rowptr.data(), sizeof(int32_t) * (p.n + 1));
+    if (he == hipSuccess)
+      he = put(p.colidx, ops.colidx.data(), sizeof(int32_t) * p.nnz);
+    if (he == hipSuccess)
+      he = put(p.inc_ptr, ops.inc_ptr.data(), sizeof(int32_t) * (p.n + 1));
+    if (he == hipSuccess)
+      he = put(p.inc, ops.inc.data(), sizeof(int32_t) * ops.inc.size());
+    if (he == hipSuccess)
+      he = put(p.tets, md.tets.data(), sizeof(int32_t) * md.tets.size());
+    if (he == hipSuccess)
+      he = put(p.dofmap, ops.dof.data(), sizeof(int32_t) * ops.dof.size());
+    if (he == hipSuccess)
+      he = put(p.nbr, ops.nbr.data(), sizeof(int32_t) * ops.nbr.size());
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(p.Vv, d_V, sizeof(double) * p.nv,
+                          hipMemcpyDeviceToDevice, s);
+    if (he != hipSuccess)
+      return bail(fail(PARO_EDEVICE, "mesh upload: %s",
+                       hipGetErrorString(he)));
+    if (launch_potential_range(p.Vv, p.nv, p.vmin, p.cnt + kCntMin, p.part,
+                               s) != hipSuccess)
+      return bail(fail(PARO_EDEVICE, "potential range launch failed"));
+    double rng[3];
+    he = hipMemcpyAsync(rng, p.vmin, sizeof rng, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess)
+      return bail(fail(PARO_EDEVICE, "reading the potential range: %s",
+                       hipGetErrorString(he)));
+    if (rng[2] != 0.0)
+      return bail(fail(PARO_EINVAL, "potential has %.0f non-finite values",
+                       rng[2]));
+    p.sigma = opts->sigma_mode == 1 ? opts->sigma
+                                    : (rng[0] >= 0.0 ? 0.0 : rng[0] - 1.0);
+    if (launch_mesh_assemble(p, s) != hipSuccess)
+      return bail(fail(PARO_EDEVICE, "mesh assembly launch failed"));
+    desc_init(p);
+    *out = h;
+    return PARO_OK;
+  } catch (...) {
+    return fail(PARO_EDEVICE, "unexpected exception in paro_mesh_assemble");
+  }
+}
+
+}  // extern "C"
+
 namespace paro {
 // Step 1 of one problem; with `status`, synchronous: it receives the
 // status bits after the projection (and its re-orthonormalisation retry).
@@ -1267,6 +1464,10 @@ int paro_update_potential(paro_problem* h, const double* d_V, void* stream) {
   try {
     if (!h || !d_V) return fail(PARO_EINVAL, "NULL argument");
     Problem& p = h->p;
+    if (p.csr)
+      return fail(PARO_EINVAL,
+                  "paro_update_potential serves box problems; assemble a "
+                  "mesh problem again for a new potential");
     hipStream_t s = (hipStream_t)stream;
     p.last_stream = s;
     const int64_t nv =
@@ -1489,6 +1690,8 @@ int paro_set_nonlocal(paro_problem* h, const double* d_zeta, int32_t k,
                       void* d_ws, size_t bytes, void* stream) {
   if (!h) return fail(PARO_EINVAL, "NULL problem");
   Problem& p = h->p;
+  if (p.csr && k != 0)
+    return fail(PARO_EINVAL, "the nonlocal term serves box problems only");
   if (k == 0) {
     p.Zp = nullptr;
     p.kz = 0;
@@ -1628,8 +1831,18 @@ int paro_export_csr(paro_problem* h, int32_t* d_rowptr, int32_t* d_col,
   if (!h) return fail(PARO_EINVAL, "NULL problem");
   Problem& p = h->p;
   hipStream_t s = (hipStream_t)stream;
-  if (d_rowptr || d_col || d_valA || d_valM)
+  if (p.csr) {  // the operator is stored in CSR already
+    const auto cp = [&](void* dst, const void* src, size_t n) {
+      return dst ? hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, s)
+                 : hipSuccess;
+    };
+    HIP_OR_FAIL(cp(d_rowptr, p.rowptr, sizeof(int32_t) * (p.n + 1)));
+    HIP_OR_FAIL(cp(d_col, p.colidx, sizeof(int32_t) * p.nnz));
+    HIP_OR_FAIL(cp(d_valA, p.valA, sizeof(double) * p.nnz));
+    HIP_OR_FAIL(cp(d_valM, p.valM, sizeof(double) * p.nnz));
+  } else if (d_rowptr || d_col || d_valA || d_valM) {
     HIP_OR_FAIL(launch_csr_export(p, d_rowptr, d_col, d_valA, d_valM, s));
+  }
   if (h_sigma) *h_sigma = p.sigma;
   return PARO_OK;
 }
@@ -1734,8 +1947,10 @@ int paro_pcg(paro_problem* h, const double* d_B, double* d_X, int ncols,
     d.U0 = d.X = p.X;
     d.Bin = d_B;
     d.lam = nullptr;
+    const bool csr_hu = mark_csr_starts(c);
     int rc = upload(c, s);
     if (rc) return rc;
+    if (csr_hu) HIP_OR_FAIL(launch_csr_dual(c.L, 2, s, c.timing));
     HIP_OR_FAIL(launch_pcg_start(c.L, s, c.timing));
     rc = solve_sources(c, s, nullptr);
     if (rc) return rc;

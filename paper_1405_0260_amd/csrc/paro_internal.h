@@ -161,6 +161,14 @@ struct Desc {
   int kz;                 // number of projectors (0: none)
   double* zy;             // kz x ncols: Z^T X of the current phase
   double* zpart;          // kz ncols x ntc partial sums of Z^T X
+  // General (bisection) meshes: the operator as CSR over the dofs
+  // (csr = 1; then diagA / diagM are unused and mx, my, mz are 0).
+  int csr;
+  const int32_t* rowptr;  // n + 1
+  const int32_t* colidx;  // nnz, ascending within a row
+  const double* valA;     // A_s = H - s M
+  const double* valM;     // M
+  int csr_rows;           // rows per p.q segment of the CSR CG SpMM
 };
 
 // Columns per thread of a problem with `ncols` columns: the widest vector
@@ -251,6 +259,7 @@ struct Launch {
   int ntile;              // some problem uses the row-sweep CG SpMM
   int zm;                 // some problem uses the z-marching CG SpMM
   int zmg;                // chunks per z-marching unit (1, 2 or 4)
+  int csr;                // some problem is on a general (CSR) mesh
 };
 
 // Per-problem step summary for the host (one PollReport per problem).
@@ -318,6 +327,21 @@ struct Problem {
   int cg_predict[5];      // CG iterations of the last solve per pass slot
   Desc hd;                // host copy of the problem's descriptor
   Desc* dd;               // its device slot (workspace)
+  // General meshes (csr): the operator and the mesh on the device.
+  bool csr = false;
+  int32_t* rowptr = nullptr;
+  int32_t* colidx = nullptr;
+  double* valA = nullptr;
+  double* valM = nullptr;
+  int32_t* inc_ptr = nullptr;  // n + 1: incident (element, corner) pairs
+  int32_t* inc = nullptr;      // of each dof row, 2 ints each
+  int32_t* tets = nullptr;     // ne x 4
+  double* Xv = nullptr;        // nv x 3 vertex coordinates
+  double* Vv = nullptr;        // nv nodal potential
+  int32_t* dofmap = nullptr;   // nv: dof of a vertex, -1 on the boundary
+  int32_t* nbr = nullptr;      // ne x 4: element across the face opposite
+                               // corner a, -1 on the boundary
+  int64_t nv = 0, ne = 0;
 };
 
 // Kernel timing (api.hip): a pair of events for one launch when timing is
@@ -327,6 +351,8 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 
 // Workspace layout: byte offsets of every region for a problem shape.
 struct Layout {
+  size_t rowptr, colidx, valA, valM, inc_ptr, inc, tets, Xv, Vv, dofmap,
+      nbr;  // general meshes only (0 otherwise)
   size_t dinv, dinv32, diagA, diagM, diagA32;
   size_t X, R, P, Q, B, HU, MU, Xc, R32, P32, Q32, X32;
   size_t part, cpart, gpart, Ah, Bh, C, theta, vmin, cs, si, cnt,
@@ -335,7 +361,50 @@ struct Layout {
   size_t total;
 };
 
-Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision);
+// Sizes of a general mesh's device arrays (make_layout's mesh regions).
+struct MeshSizes {
+  int64_t nv, ne, ninc;  // vertices, elements, incident (element, corner)
+                         // pairs of the dof rows
+};
+// ms: null for the uniform stencil format, else the CSR operator and mesh
+// arrays replace the stencil coefficients.
+Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
+                   const MeshSizes* ms = nullptr);
+
+// A bisection mesh of a box (host): ordered elements (x0, x1, x2, x3)
+// with Maubach tags, and for every vertex made by bisection the two ends
+// of the edge it halves (-1, -1 for the others).  Vertices on the box
+// boundary carry the Dirichlet data; the others, in vertex order, are the
+// dofs.
+struct MeshData {
+  double lo[3], hi[3];
+  std::vector<double> X;         // nv x 3
+  std::vector<int32_t> tets;     // ne x 4
+  std::vector<int32_t> tags;     // ne, in {1, 2, 3}
+  std::vector<int32_t> parents;  // nv x 2
+  int64_t nv() const { return (int64_t)X.size() / 3; }
+  int64_t ne() const { return (int64_t)tags.size(); }
+};
+// Host-built tables of a mesh's operator: the dof of every vertex, the
+// CSR pattern over the dofs, the (element, corner) pairs incident to each
+// dof row (ascending element), and the face neighbours of every element.
+struct MeshOps {
+  std::vector<int32_t> dof;
+  int64_t n = 0;
+  std::vector<int32_t> rowptr, colidx, inc_ptr, inc, nbr;
+};
+int mesh_ops(const MeshData& m, MeshOps* out);
+// Values of the CSR operator (A_s, M), 1 / diag(A_s) and the mesh tables
+// already in the problem's workspace, from the nodal potential p.Vv.
+hipError_t launch_mesh_assemble(Problem& p, hipStream_t s);
+// CSR operator kernels of general meshes (csr.hip).
+// CG SpMM of the CSR problems of the table (FP64, chunk-major P -> Q and
+// the p.q partials).
+hipError_t launch_csr_cg_spmm(Launch& L, int par, hipStream_t s, Timing* t);
+// Row-major products of the CSR problems: mode 0 Y1 = A X + s1 M X and
+// Y2 = M X (component form), mode 1 R = H X, Q = M X (Rayleigh-Ritz),
+// mode 2 HU = H U0, MU = M U0 (a start that cannot reuse a rotation's).
+hipError_t launch_csr_dual(Launch& L, int mode, hipStream_t s, Timing* t);
 // paro_batch_step; trust: U and lambda of every problem come unchanged
 // from its last rotation under the same operator (the library's own
 // loops), so the start reuses that rotation's H U and M U.
@@ -428,6 +497,11 @@ hipError_t launch_small_geneig(const double* A, const double* B, int n,
                                hipStream_t s);
 
 }  // namespace paro
+
+struct paro_mesh {
+  paro::MeshData m;
+};
+
 
 // The opaque handle of the C ABI: host metadata of one assembled problem.
 struct paro_problem {

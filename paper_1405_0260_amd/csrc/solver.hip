@@ -982,7 +982,7 @@ __global__ void PARO_STREAM_BOUNDS
 spmm_cm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double ws[5 * kNtMax];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
-  if (d.zm != 0) return;  // served by spmm_zm_kernel
+  if (d.zm != 0 || d.csr) return;  // served by spmm_zm_kernel or CSR
   const int nact = ldg(&d.cs->n_active[par]);
   const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
   if (nact == 0) return;  // queued after convergence
@@ -2022,6 +2022,7 @@ gather_reports_kernel(const Desc* __restrict__ D, int nprob,
 template <int V, bool NL>
 __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
     double* __restrict__ red) {
+  if (d.csr) return;  // csr_dual_kernel
   const Geo g = geo_of<V>(d, vb);
   const int ncols = d.ncols;
   double* Y1 = rr ? d.R : d.Y1;
@@ -2747,6 +2748,144 @@ rotate_final_kernel(const Desc* __restrict__ D) {
   }
 }
 
+// ------------------------------------------------------------------------
+// General (bisection) meshes: the operator in CSR over the dofs, FP64.
+// The vector kernels of the CG (r- and p-update) and of Rayleigh-Ritz are
+// layout-free and serve these problems unchanged; only the products with
+// A_s and M differ.
+//
+// CG SpMM: a unit is (segment of csr_rows consecutive rows, chunk with an
+// active column); thread tid takes rows r0 + tid, r0 + tid + kBlock, ...
+// of the segment, forms q = A_s p over its row's entries in column order,
+// stores q (chunk-major) and adds p_row q to its p.q partial; then one
+// wavefront reduction and the four wavefronts in a fixed order give the
+// (column, segment) partial, so the sums depend on the problem alone.
+// ------------------------------------------------------------------------
+template <int V>
+__device__ __forceinline__ void csr_cg_unit(const Desc& d, long long seg,
+                                            int ch, unsigned long long amask,
+                                            double* __restrict__ ws) {
+  const long long n = d.n;
+  const long long r0 = seg * d.csr_rows;
+  const long long r1 = min(n, r0 + d.csr_rows);
+  const double* P = d.P;
+  double acc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0.0;
+  for (long long r = r0 + threadIdx.x; r < r1; r += kBlock) {
+    double q[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) q[v] = 0.0;
+    const int j1 = ldg(d.rowptr + r + 1);
+    for (int j = ldg(d.rowptr + r); j < j1; ++j) {
+      const int c = ldg(d.colidx + j);
+      const double a = ldg(d.valA + j);
+      double x[V];
+      ldv<double, V>(P + cm_index(n, c, ch * V, V), x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) q[v] = fma(a, x[v], q[v]);
+    }
+    double self[V];
+    ldv<double, V>(P + cm_index(n, r, ch * V, V), self);
+    stv<double, V>(d.Q + cm_index(n, r, ch * V, V), q);
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] += self[v] * q[v];
+  }
+  constexpr int kGroup = 64 / V;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double tot = wave_reduce_scatter<V>(acc);
+  if ((lane & (kGroup - 1)) == 0) ws[wave * V + lane / kGroup] = tot;
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < V && ((amask >> (ch * V + k)) & 1)) {
+    const double sum = ((ws[k] + ws[V + k]) + ws[2 * V + k]) + ws[3 * V + k];
+    stg(d.pqp + (size_t)(ch * V + k) * d.pqn + seg, sum);
+  }
+  __syncthreads();  // ws is reused by the next unit
+}
+
+__global__ void PARO_STREAM_BOUNDS
+csr_cg_spmm_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * 2];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (!d.csr) return;
+  const int nact = ldg(&d.cs->n_active[par]);
+  const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
+  if (nact == 0) return;  // queued after convergence
+  const int lb = blockIdx.x - d.b0;
+  const int V = d.v64;
+  const int cpr = d.ncols / V;
+  const unsigned long long cm = chunk_mask(amask, cpr, V);
+  const int nac = __popcll(cm);
+  for (TileWalk w = tile_walk((long long)d.pqn * nac, lb, d.nb); w.t < w.end;
+       w.t += w.step) {
+    const CmUnit un = cm_unit_active(w.t, nac, cm);
+    if (V == 2)
+      csr_cg_unit<2>(d, un.t, un.ch, amask, ws);
+    else
+      csr_cg_unit<1>(d, un.t, un.ch, amask, ws);
+  }
+}
+
+// Row-major products of the CSR problems, one thread per (row, chunk of V
+// columns): mode 0 Y1 = A X + s1 M X, Y2 = M X (component form; either
+// output may be absent); mode 1 R = H X, Q = M X (Rayleigh-Ritz: H =
+// A_s + s M); mode 2 HU = H U0, MU = M U0 for the problems whose start
+// cannot take them from a rotation (use_hu = 2: formed here, then read by
+// the start like a rotation's).
+template <int V>
+__device__ __forceinline__ void csr_dual_rows(const Desc& d, int mode,
+                                              int lb) {
+  const double* X = mode == 2 ? d.U0 : d.X;
+  double* Y1 = mode == 0 ? d.Y1 : (mode == 1 ? d.R : d.HU);
+  double* Y2 = mode == 0 ? d.Y2 : (mode == 1 ? d.Q : d.MU);
+  const double s1 = mode == 0 ? d.s1 : d.sigma;
+  const bool needA = Y1 != nullptr;
+  const int ncols = d.ncols, cpr = ncols / V;
+  const long long total = d.n * cpr;
+  for (long long t = (long long)lb * kBlock + threadIdx.x; t < total;
+       t += (long long)d.nb * kBlock) {
+    const long long r = t / cpr;
+    const int ch = (int)(t - r * cpr);
+    double ax[V], mx[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ax[v] = mx[v] = 0.0;
+    const int j1 = ldg(d.rowptr + r + 1);
+    for (int j = ldg(d.rowptr + r); j < j1; ++j) {
+      const int c = ldg(d.colidx + j);
+      const double a = needA ? ldg(d.valA + j) : 0.0;
+      const double m = ldg(d.valM + j);
+      double x[V];
+      ldv<double, V>(X + (size_t)c * ncols + ch * V, x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        ax[v] = fma(a, x[v], ax[v]);
+        mx[v] = fma(m, x[v], mx[v]);
+      }
+    }
+    const size_t o = (size_t)r * ncols + ch * V;
+    if (Y1) {
+      double y[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) y[v] = fma(s1, mx[v], ax[v]);
+      stv<double, V>(Y1 + o, y);
+    }
+    if (Y2) stv<double, V>(Y2 + o, mx);
+  }
+}
+
+__global__ void PARO_STREAM_BOUNDS
+csr_dual_kernel(const Desc* __restrict__ D, int nprob, int mode) {
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (!d.csr) return;
+  if (mode == 2 && d.use_hu != 2) return;  // its start needs no H U0, M U0
+  const int lb = blockIdx.x - d.b0;
+  if (d.v64 == 2)
+    csr_dual_rows<2>(d, mode, lb);
+  else
+    csr_dual_rows<1>(d, mode, lb);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2800,6 +2939,20 @@ hipError_t launch_spmm(Launch& L, bool rr, hipStream_t s, Timing* t) {
     case 1: spmm_dual_w<1>(L, rr, s, t); break;
     default: spmm_dual_w<0>(L, rr, s, t);
   }
+  if (L.csr) return launch_csr_dual(L, rr ? 1 : 0, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_dual(Launch& L, int mode, hipStream_t s, Timing* t) {
+  klaunch(t, mode == 2 ? PARO_ST_START : PARO_ST_RR_SPMM, csr_dual_kernel,
+          dim3(L.blocks), dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob,
+          mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_cg_spmm(Launch& L, int par, hipStream_t s, Timing* t) {
+  klaunch(t, PARO_ST_CG_SPMM, csr_cg_spmm_kernel, dim3(L.blocks),
+          dim3(kBlock), 0, s, (const Desc*)L.d, L.nprob, par);
   return hipGetLastError();
 }
 
@@ -2843,6 +2996,8 @@ hipError_t launch_pcg_start(Launch& L, hipStream_t s, Timing* t) {
 template <typename T, int W>
 static void cg_spmm_launch(Launch& L, int par, hipStream_t s, Timing* t) {
   const Desc* D = L.d;
+  if constexpr (sizeof(T) == 8)
+    if (L.csr) (void)launch_csr_cg_spmm(L, par, s, t);
   if (L.ntile) {
     if (L.seg)
       klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, true>, dim3(L.blocks),

@@ -81,13 +81,18 @@ def soft_coulomb_centres(seed: int, count: int, zmax: int, r: float):
     return Z, R
 
 
-def soft_coulomb_potential(nc, lo, hi, Z, R) -> np.ndarray:
-    X = vertex_coords(nc, lo, hi)
+def soft_coulomb_at(X: np.ndarray, Z, R) -> np.ndarray:
+    """The soft-Coulomb potential of centres (Z, R) at the points X (the
+    vertices of any mesh)."""
     V = np.zeros(X.shape[0])
     for zk, rk in zip(Z, R):
         d2 = np.sum((X - rk) ** 2, axis=1)
         V -= zk / np.sqrt(d2 + SOFT_EPS)
     return V
+
+
+def soft_coulomb_potential(nc, lo, hi, Z, R) -> np.ndarray:
+    return soft_coulomb_at(vertex_coords(nc, lo, hi), Z, R)
 
 
 def initial_orbitals(n_dof: int, Nt: int, seed: int) -> np.ndarray:
