@@ -1222,12 +1222,22 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
 // Problems on general (bisection) meshes: the operator in CSR.
 // ---------------------------------------------------------------------------
 namespace {
-int mesh_shape(const paro_mesh* m, const paro_opts_t* opts, MeshOps* ops,
-               Layout* L) {
+int mesh_shape(const paro_mesh* m, const paro_opts_t* opts,
+               std::shared_ptr<const MeshOps>* out, Layout* L) {
   if (!m) return fail(PARO_EINVAL, "NULL mesh");
-  int rc = mesh_ops(m->m, ops);
-  if (rc) return rc;
-  rc = check_opts(opts, ops->n);
+  std::shared_ptr<const MeshOps> ops;
+  {
+    std::lock_guard<std::mutex> g(m->ops_mu);
+    if (!m->ops) {
+      auto built = std::make_shared<MeshOps>();
+      const int rc0 = mesh_ops(m->m, built.get());
+      if (rc0) return rc0;
+      m->ops = built;
+    }
+    ops = m->ops;
+  }
+  *out = ops;
+  int rc = check_opts(opts, ops->n);
   if (rc) return rc;
   if (opts->precision != PARO_FP64)
     return fail(PARO_EINVAL, "mesh problems are solved in PARO_FP64");
@@ -1243,12 +1253,12 @@ extern "C" {
 int paro_mesh_query(const paro_mesh* m, const paro_opts_t* opts,
                     int64_t* n_dof, int64_t* nnz, size_t* workspace_bytes) {
   try {
-    MeshOps ops;
+    std::shared_ptr<const MeshOps> ops;
     Layout L;
     const int rc = mesh_shape(m, opts, &ops, &L);
     if (rc) return rc;
-    if (n_dof) *n_dof = ops.n;
-    if (nnz) *nnz = (int64_t)ops.colidx.size();
+    if (n_dof) *n_dof = ops->n;
+    if (nnz) *nnz = (int64_t)ops->colidx.size();
     if (workspace_bytes) *workspace_bytes = L.total;
     return PARO_OK;
   } catch (...) {
@@ -1262,10 +1272,11 @@ int paro_mesh_assemble(const paro_mesh* m, const double* d_V,
   try {
     if (!out) return fail(PARO_EINVAL, "out is NULL");
     *out = nullptr;
-    MeshOps ops;
+    std::shared_ptr<const MeshOps> opsp;
     Layout L;
-    int rc = mesh_shape(m, opts, &ops, &L);
+    int rc = mesh_shape(m, opts, &opsp, &L);
     if (rc) return rc;
+    const MeshOps& ops = *opsp;
     if (!d_V || !d_ws) return fail(PARO_EINVAL, "NULL device pointer");
     if (((uintptr_t)d_ws & 255) != 0)
       return fail(PARO_EINVAL, "workspace must be 256-byte aligned");

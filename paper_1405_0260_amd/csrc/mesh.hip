@@ -88,25 +88,35 @@ MeshData kuhn(const paro_box_t& b) {
 }
 
 // Maubach bisection with the conforming closure (see the file notes).
+// The elements around an edge (a, b) are found from the elements at
+// vertex a (a per-vertex list kept up to date as elements are cut), by
+// testing each for vertex b.
 class Refiner {
  public:
   explicit Refiner(const MeshData& in) : m_(in) {
-    const int64_t ne = in.ne();
+    const int64_t ne = in.ne(), nv = in.nv();
     el_.resize(ne);
+    std::vector<int32_t> deg(nv, 0);
     for (int64_t e = 0; e < ne; ++e) {
-      for (int a = 0; a < 4; ++a) el_[e].v[a] = in.tets[4 * e + a];
+      for (int a = 0; a < 4; ++a) {
+        el_[e].v[a] = in.tets[4 * e + a];
+        ++deg[el_[e].v[a]];
+      }
       el_[e].tag = in.tags[e];
       el_[e].alive = true;
     }
-    by_edge_.reserve((size_t)(1.3 * ne) + 16);
+    at_.resize(nv);
+    for (int64_t v = 0; v < nv; ++v) at_[v].reserve(deg[v] + 4);
     for (int64_t e = 0; e < ne; ++e) link((int32_t)e);
   }
 
   void bisect(int32_t i) {
-    const uint64_t e = ref_edge(i);
+    const int32_t a = el_[i].v[0], b = el_[i].v[el_[i].tag];
+    const uint64_t e = edge_key(a, b);
     for (;;) {
+      around(a, b, &tmp_);
       int32_t bad = -1;
-      for (int32_t j : by_edge_[e])
+      for (int32_t j : tmp_)
         if (ref_edge(j) != e) {
           bad = j;
           break;
@@ -114,8 +124,9 @@ class Refiner {
       if (bad < 0) break;
       bisect(bad);
     }
-    const std::vector<int32_t> around = by_edge_[e];
-    for (int32_t j : around) cut(j);
+    around(a, b, &tmp_);
+    const std::vector<int32_t> all = tmp_;
+    for (int32_t j : all) cut(j);
   }
 
   bool alive(int64_t i) const { return el_[i].alive; }
@@ -145,20 +156,28 @@ class Refiner {
     return edge_key(el_[i].v[0], el_[i].v[el_[i].tag]);
   }
 
+  // Live elements with both a and b among their corners.
+  void around(int32_t a, int32_t b, std::vector<int32_t>* out) const {
+    out->clear();
+    for (int32_t j : at_[a]) {
+      const int32_t* v = el_[j].v;
+      if (v[0] == b || v[1] == b || v[2] == b || v[3] == b) out->push_back(j);
+    }
+  }
+
   void link(int32_t i) {
-    const int32_t* v = el_[i].v;
-    for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b) by_edge_[edge_key(v[a], v[b])].push_back(i);
+    for (int a = 0; a < 4; ++a) at_[el_[i].v[a]].push_back(i);
   }
 
   void unlink(int32_t i) {
-    const int32_t* v = el_[i].v;
-    for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b) {
-        std::vector<int32_t>& l = by_edge_[edge_key(v[a], v[b])];
-        auto it = std::find(l.begin(), l.end(), i);
-        if (it != l.end()) l.erase(it);
+    for (int a = 0; a < 4; ++a) {
+      std::vector<int32_t>& l = at_[el_[i].v[a]];
+      auto it = std::find(l.begin(), l.end(), i);
+      if (it != l.end()) {
+        *it = l.back();
+        l.pop_back();
       }
+    }
   }
 
   int32_t midpoint(int32_t a, int32_t b) {
@@ -170,6 +189,7 @@ class Refiner {
       m_.X.push_back(0.5 * (m_.X[3 * (size_t)a + c] + m_.X[3 * (size_t)b + c]));
     m_.parents.push_back(std::min(a, b));
     m_.parents.push_back(std::max(a, b));
+    at_.emplace_back();
     mid_[k] = z;
     return z;
   }
@@ -199,8 +219,9 @@ class Refiner {
 
   MeshData m_;
   std::vector<Elem> el_;
-  std::unordered_map<uint64_t, std::vector<int32_t>> by_edge_;
+  std::vector<std::vector<int32_t>> at_;  // live elements at each vertex
   std::unordered_map<uint64_t, int32_t> mid_;
+  std::vector<int32_t> tmp_;
 };
 
 bool inside_box(const MeshData& m, const double* x) {

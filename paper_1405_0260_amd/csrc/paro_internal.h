@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "paro.h"
@@ -500,6 +502,10 @@ hipError_t launch_small_geneig(const double* A, const double* B, int n,
 
 struct paro_mesh {
   paro::MeshData m;
+  // The operator tables of the mesh, built by the first query or assembly
+  // and kept (a mesh never changes after it is made).
+  mutable std::shared_ptr<const paro::MeshOps> ops;
+  mutable std::mutex ops_mu;
 };
 
 
