@@ -2754,59 +2754,91 @@ rotate_final_kernel(const Desc* __restrict__ D) {
 // layout-free and serve these problems unchanged; only the products with
 // A_s and M differ.
 //
-// CG SpMM: a unit is (segment of csr_rows consecutive rows, chunk with an
-// active column); thread tid takes rows r0 + tid, r0 + tid + kBlock, ...
-// of the segment, forms q = A_s p over its row's entries in column order,
-// stores q (chunk-major) and adds p_row q to its p.q partial; then one
-// wavefront reduction and the four wavefronts in a fixed order give the
-// (column, segment) partial, so the sums depend on the problem alone.
+// CG SpMM: a unit is (segment of csr_rows consecutive rows, group of
+// kCsrG consecutive chunks with an active column); thread tid takes rows
+// r0 + tid, r0 + tid + kBlock, ... of the segment, reads each entry of its
+// row once for the whole group, forms q = A_s p in column order for every
+// live chunk of the group, stores q (chunk-major) and adds p_row q to its
+// p.q partials; then one wavefront reduction and the four wavefronts in a
+// fixed order give the (column, segment) partials, so the sums depend on
+// the problem alone (not on the grouping, which only decides which
+// columns a unit serves).
 // ------------------------------------------------------------------------
+constexpr int kCsrG = 4;
+
 template <int V>
 __device__ __forceinline__ void csr_cg_unit(const Desc& d, long long seg,
-                                            int ch, unsigned long long amask,
+                                            int ch0, unsigned long long amask,
                                             double* __restrict__ ws) {
   const long long n = d.n;
   const long long r0 = seg * d.csr_rows;
   const long long r1 = min(n, r0 + d.csr_rows);
+  const int cpr = d.ncols / V;
   const double* P = d.P;
-  double acc[V];
+  bool on[kCsrG];
+  double acc[kCsrG][V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) acc[v] = 0.0;
+  for (int g = 0; g < kCsrG; ++g) {
+    on[g] = ch0 + g < cpr && chunk_in_mask<V>(amask, ch0 + g);
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[g][v] = 0.0;
+  }
   for (long long r = r0 + threadIdx.x; r < r1; r += kBlock) {
-    double q[V];
+    double q[kCsrG][V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) q[v] = 0.0;
+    for (int g = 0; g < kCsrG; ++g)
+#pragma unroll
+      for (int v = 0; v < V; ++v) q[g][v] = 0.0;
     const int j1 = ldg(d.rowptr + r + 1);
     for (int j = ldg(d.rowptr + r); j < j1; ++j) {
       const int c = ldg(d.colidx + j);
       const double a = ldg(d.valA + j);
-      double x[V];
-      ldv<double, V>(P + cm_index(n, c, ch * V, V), x);
 #pragma unroll
-      for (int v = 0; v < V; ++v) q[v] = fma(a, x[v], q[v]);
+      for (int g = 0; g < kCsrG; ++g) {
+        if (!on[g]) continue;
+        double x[V];
+        ldv<double, V>(P + cm_index(n, c, (ch0 + g) * V, V), x);
+#pragma unroll
+        for (int v = 0; v < V; ++v) q[g][v] = fma(a, x[v], q[g][v]);
+      }
     }
-    double self[V];
-    ldv<double, V>(P + cm_index(n, r, ch * V, V), self);
-    stv<double, V>(d.Q + cm_index(n, r, ch * V, V), q);
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] += self[v] * q[v];
+    for (int g = 0; g < kCsrG; ++g) {
+      if (!on[g]) continue;
+      const size_t o = cm_index(n, r, (ch0 + g) * V, V);
+      double self[V];
+      ldv<double, V>(P + o, self);
+      stv<double, V>(d.Q + o, q[g]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[g][v] += self[v] * q[g][v];
+    }
   }
   constexpr int kGroup = 64 / V;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double tot = wave_reduce_scatter<V>(acc);
-  if ((lane & (kGroup - 1)) == 0) ws[wave * V + lane / kGroup] = tot;
+#pragma unroll
+  for (int g = 0; g < kCsrG; ++g) {
+    if (!on[g]) continue;  // uniform over the block
+    const double tot = wave_reduce_scatter<V>(acc[g]);
+    if ((lane & (kGroup - 1)) == 0)
+      ws[wave * kCsrG * V + g * V + lane / kGroup] = tot;
+  }
   __syncthreads();
   const int k = threadIdx.x;
-  if (k < V && ((amask >> (ch * V + k)) & 1)) {
-    const double sum = ((ws[k] + ws[V + k]) + ws[2 * V + k]) + ws[3 * V + k];
-    stg(d.pqp + (size_t)(ch * V + k) * d.pqn + seg, sum);
+  if (k < kCsrG * V) {
+    const int g = k / V, c = (ch0 + g) * V + k % V;
+    if (on[g] && ((amask >> c) & 1)) {
+      const int w = kCsrG * V;
+      const double sum =
+          ((ws[k] + ws[w + k]) + ws[2 * w + k]) + ws[3 * w + k];
+      stg(d.pqp + (size_t)c * d.pqn + seg, sum);
+    }
   }
   __syncthreads();  // ws is reused by the next unit
 }
 
 __global__ void PARO_STREAM_BOUNDS
 csr_cg_spmm_kernel(const Desc* __restrict__ D, int nprob, int par) {
-  __shared__ double ws[4 * 2];
+  __shared__ double ws[4 * kCsrG * 2];
   const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
   if (!d.csr) return;
   const int nact = ldg(&d.cs->n_active[par]);
@@ -2815,15 +2847,23 @@ csr_cg_spmm_kernel(const Desc* __restrict__ D, int nprob, int par) {
   const int lb = blockIdx.x - d.b0;
   const int V = d.v64;
   const int cpr = d.ncols / V;
+  // Groups of kCsrG chunks with an active column.
   const unsigned long long cm = chunk_mask(amask, cpr, V);
-  const int nac = __popcll(cm);
-  for (TileWalk w = tile_walk((long long)d.pqn * nac, lb, d.nb); w.t < w.end;
+  unsigned long long gm = 0;
+  for (int g = 0; g * kCsrG < cpr; ++g)
+    if ((cm >> (g * kCsrG)) & ((1ull << kCsrG) - 1)) gm |= 1ull << g;
+  const int nag = __popcll(gm);
+  for (TileWalk w = tile_walk((long long)d.pqn * nag, lb, d.nb); w.t < w.end;
        w.t += w.step) {
-    const CmUnit un = cm_unit_active(w.t, nac, cm);
+    const long long seg = w.t / nag;
+    const int gi = (int)(w.t - seg * nag);
+    unsigned long long m = gm;
+    for (int k = 0; k < gi; ++k) m &= m - 1;
+    const int ch0 = __builtin_ctzll(m) * kCsrG;
     if (V == 2)
-      csr_cg_unit<2>(d, un.t, un.ch, amask, ws);
+      csr_cg_unit<2>(d, seg, ch0, amask, ws);
     else
-      csr_cg_unit<1>(d, un.t, un.ch, amask, ws);
+      csr_cg_unit<1>(d, seg, ch0, amask, ws);
   }
 }
 
