@@ -420,7 +420,21 @@ struct Ctx {
   int last_status = 0;    // status bits seen by the last poll
   int last_outer = -1;    // refining columns seen by the last poll
   std::vector<Desc> ptab; // table laid out for the persistent CG grid
+  std::vector<Problem*> owners;  // the problem of each table entry
 };
+
+// After a Rayleigh-Ritz of the table: what the next start can reuse.
+void note_rotation(Ctx& c) {
+  for (size_t i = 0; i < c.tab.size() && i < c.owners.size(); ++i) {
+    Desc& h = c.owners[i]->hd;
+    h.start_ready = c.tab[i].emit;
+    h.hu_valid = c.tab[i].emit ? 0 : 1;
+  }
+}
+// Before anything that overwrites the CG state or H U, M U.
+void forget_rotation(Ctx& c) {
+  for (Problem* p : c.owners) p->hd.start_ready = p->hd.hu_valid = 0;
+}
 
 // The stream CG chunks are captured on (capture only records; the graphs
 // run on the caller's stream, which may be the null stream).
@@ -770,7 +784,16 @@ int retry_singular(Ctx& c, std::vector<PollReport>& pr, hipStream_t s) {
 int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
                 bool trust) {
   const double t0 = now_s();
-  for (Desc& d : c.tab) d.use_hu = trust ? 1 : 0;
+  // The start: from the state the last rotation emitted (trusted loops),
+  // else from its H U, M U (trusted loops after a rotation that kept
+  // them), else by applying the operators.  The rotation of this step
+  // emits the next start's state when the caller is a library loop.
+  for (Desc& d : c.tab) {
+    d.use_hu = !trust ? 0 : (d.start_ready ? 3 : (d.hu_valid ? 1 : 0));
+    d.start_part = d.use_hu == 3 ? 2 : 0;
+    d.emit = trust ? 1 : 0;
+  }
+  forget_rotation(c);
   const bool csr_hu = mark_csr_starts(c);
   int rc = upload(c, s);
   if (rc) return rc;
@@ -784,6 +807,7 @@ int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
   if (single && (c.last_status & (kStNonFinite | kStNotSpd)))
     return status_to_code(c.last_status);
   HIP_OR_FAIL(launch_rayleigh_ritz(c.L, s, c.timing));
+  note_rotation(c);
   if (!reps) return PARO_OK;
   rc = read_reports(c, pr, s);
   if (rc) return rc;
@@ -814,9 +838,17 @@ int step_tables(Ctx& c, hipStream_t s, paro_report_t* reps, bool single,
 // bits after the projection, with the re-orthonormalisation retry done
 // (kStReorth marks a retried problem).
 int init_tables(Ctx& c, hipStream_t s, std::vector<int>* status) {
+  // A synchronous Step 1 belongs to a library loop, whose first step
+  // starts from the state this rotation emits.
+  for (Desc& d : c.tab) {
+    d.emit = status ? 1 : 0;
+    d.use_hu = 0;
+  }
+  forget_rotation(c);
   int rc = upload(c, s);
   if (rc) return rc;
   HIP_OR_FAIL(launch_rayleigh_ritz(c.L, s, c.timing));
+  note_rotation(c);
   if (!status) return PARO_OK;
   std::vector<PollReport> pr;
   rc = read_reports(c, pr, s);
@@ -831,6 +863,7 @@ int init_tables(Ctx& c, hipStream_t s, std::vector<int>* status) {
 Ctx single_ctx(Problem& p) {
   Ctx c;
   c.tab.assign(1, p.hd);
+  c.owners.assign(1, &p);
   c.L = make_launch(p.dd, c.tab.data(), 1);
   c.timing = p.timing;
   c.predict = p.cg_predict;
@@ -872,6 +905,7 @@ int batch_ctx(Ctx& c, paro_problem* const* probs, int count, void* ws,
     prec = p.opts.precision;
     maxit = std::max(maxit, p.opts.pcg_maxit);
     c.tab.push_back(p.hd);
+    c.owners.push_back(&probs[i]->p);
   }
   layout_batch(c.tab);
   char* base = (char*)ws;
@@ -1015,7 +1049,9 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
   L.P32 = f32 ? take(sizeof(float) * blk) : 0;
   L.Q32 = f32 ? take(sizeof(float) * blk) : 0;
   L.X32 = f32 ? take(sizeof(float) * blk) : 0;
-  L.part = take(sizeof(double) * 3 * (size_t)kGridMax * kNtMax);
+  // Partials of 5 quantities: a rotation's 2 and the start state it may
+  // emit (3), or a start's 3.
+  L.part = take(sizeof(double) * 5 * (size_t)kGridMax * kNtMax);
   L.cpart = take(sizeof(double) * (size_t)Nt *
                  (2 * cm_tiles(n) + spmm_tiles(n)));
   L.gpart = take(sizeof(double) * (size_t)kGramGrid * gram_tiles(Nt));
@@ -1495,6 +1531,7 @@ int paro_update_potential(paro_problem* h, const double* d_V, void* stream) {
     if (p.opts.sigma_mode != 1) p.sigma = rng[0] >= 0.0 ? 0.0 : rng[0] - 1.0;
     HIP_OR_FAIL(launch_assemble(p, d_V, s));
     p.hd.sigma = p.sigma;
+    p.hd.start_ready = p.hd.hu_valid = 0;  // the operator changed
     return PARO_OK;
   } catch (...) {
     return fail(PARO_EDEVICE, "unexpected exception in paro_update_potential");
@@ -1709,6 +1746,7 @@ int paro_set_nonlocal(paro_problem* h, const double* d_zeta, int32_t k,
     p.zy = p.zpart = nullptr;
     p.hd.Zp = nullptr;
     p.hd.kz = 0;
+    p.hd.start_ready = p.hd.hu_valid = 0;  // the operator changed
     return PARO_OK;
   }
   if (p.opts.precision != PARO_FP64)
@@ -1735,6 +1773,7 @@ int paro_set_nonlocal(paro_problem* h, const double* d_zeta, int32_t k,
   p.hd.kz = k;
   p.hd.zy = p.zy;
   p.hd.zpart = p.zpart;
+  p.hd.start_ready = p.hd.hu_valid = 0;  // the operator changed
   return PARO_OK;
 }
 
@@ -1953,6 +1992,7 @@ int paro_pcg(paro_problem* h, const double* d_B, double* d_X, int ncols,
     const size_t bytes = sizeof(double) * (size_t)p.n * ncols;
     HIP_OR_FAIL(hipMemcpyAsync(p.X, d_X, bytes, hipMemcpyDeviceToDevice, s));
     Ctx c = single_ctx(p);
+    forget_rotation(c);  // the CG state and H U, M U are overwritten
     Desc& d = c.tab[0];
     set_cols(d, ncols);
     d.U0 = d.X = p.X;

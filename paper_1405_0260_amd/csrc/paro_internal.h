@@ -129,7 +129,19 @@ struct Desc {
   double* B;              // stored right-hand sides (refinement), or null
   double* HU;             // H U and M U of the last rotation (row-major),
   double* MU;             // written by every rotation
-  int use_hu;             // the start forms A_s U from them (U, H unchanged)
+  int use_hu;             // the start forms A_s U from them (U, H unchanged);
+                          // 2: from them after launch_csr_dual mode 2;
+                          // 3: the last rotation emitted the start state
+                          // (the start kernel only resets the column state)
+  int emit;               // the rotation also writes the next step's start
+                          // state (x0, r0, p0 and its partials) instead of
+                          // H U and M U
+  int start_part;         // first partial quantity the start finaliser
+                          // reads (0, or 2 after an emitting rotation)
+  int start_ready;        // host only: the last rotation emitted the start
+                          // state and nothing has overwritten it since
+  int hu_valid;           // host only: HU, MU hold H U, M U of the last
+                          // rotation
   double* Xc;             // FP64 CG iterate, chunk-major (FP64 mode only)
   float* R32;             // FP32 CG vectors, chunk-major (see cm_index)
   float* P32;
@@ -303,7 +315,7 @@ struct Problem {
   float* P32;
   float* Q32;
   float* X32;
-  double* part;           // kGridMax * kNtMax * 3 reduction partials
+  double* part;           // kGridMax * kNtMax * 5 reduction partials
   int* clus;              // kNtMax cluster ids (paro_set_clusters)
   bool clustered;
   const double* Zp;       // nonlocal projectors (caller's workspace)
@@ -404,7 +416,7 @@ hipError_t launch_mesh_assemble(Problem& p, hipStream_t s);
 // the p.q partials).
 hipError_t launch_csr_cg_spmm(Launch& L, int par, hipStream_t s, Timing* t);
 // Row-major products of the CSR problems: mode 0 Y1 = A X + s1 M X and
-// Y2 = M X (component form), mode 1 R = H X, Q = M X (Rayleigh-Ritz),
+// Y2 = M X (component form), mode 1 HU = H X, MU = M X (Rayleigh-Ritz),
 // mode 2 HU = H U0, MU = M U0 (a start that cannot reuse a rotation's).
 hipError_t launch_csr_dual(Launch& L, int mode, hipStream_t s, Timing* t);
 // paro_batch_step; trust: U and lambda of every problem come unchanged

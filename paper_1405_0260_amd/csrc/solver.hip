@@ -1614,6 +1614,7 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
     cs->maxit = d.maxit;
     cs->cg_mark = cs->cg_iters;
   }
+  if (d.use_hu == 3) return;  // the last rotation emitted the start state
   const double* U = d.U0;
   double sh[V];
 #pragma unroll
@@ -1749,7 +1750,8 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
   if (c >= d.ncols) return;
   ColState* cs = d.cs;
   double tot[3];
-  column_sums<3>(d.part, kPartStride, c, d.ns, tot);
+  column_sums<3>(d.part + (size_t)d.start_part * kPartStride, kPartStride, c,
+                 d.ns, tot);
   if (threadIdx.x != 0) return;
   const double bb = tot[0], rz = tot[1], rr = tot[2];
   const double rtol = d.rtol;
@@ -2025,8 +2027,8 @@ __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
   if (d.csr) return;  // csr_dual_kernel
   const Geo g = geo_of<V>(d, vb);
   const int ncols = d.ncols;
-  double* Y1 = rr ? d.R : d.Y1;
-  double* Y2 = rr ? d.Q : d.Y2;
+  double* Y1 = rr ? d.HU : d.Y1;  // Rayleigh-Ritz: H W, M W over H U, M U
+  double* Y2 = rr ? d.MU : d.Y2;
   const double s1 = rr ? d.sigma : d.s1;
   const double* X = d.X;
   const bool needA = Y1 != nullptr;
@@ -2107,8 +2109,8 @@ __device__ __forceinline__ void gram_body(const Desc& d, int vb,
   constexpr int NG = SYM ? 2 : 1;
   const int nb = d.gns;
   const double* W = d.X;
-  const double* Y1 = SYM ? d.R : d.Y1;
-  const double* Y2 = SYM ? d.Q : nullptr;
+  const double* Y1 = SYM ? d.HU : d.Y1;
+  const double* Y2 = SYM ? d.MU : nullptr;
   const long long n = d.n;
   const int ncols = d.ncols;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -2609,37 +2611,101 @@ geneig_batch_kernel(const Desc* __restrict__ D) {
 
 // ------------------------------------------------------------------------
 // Rotation U = W C with HU = (HW) C, MU = (MW) C, for the residual norms
-// ||HU_i - theta_i MU_i||, ||MU_i|| (Step 4 output and the stopping test)
-// and stored for the next step's start (its right-hand side and residual
-// need M U and A_s U = HU - s MU).  Rows of W, HW, MW are staged through LDS; W may be the
-// output itself (each tile is read before it is written).
+// ||HU_i - theta_i MU_i||, ||MU_i|| (Step 4 output and the stopping test).
+// H W and M W are read from the HU and MU buffers.  Rows of W, HW, MW are
+// staged through LDS, so W may be the output itself and HU, MU are
+// rewritten in place (each tile is read before it is written).
+//
+// Without emit, HU and MU are stored for the next step's start (its
+// right-hand side and residual need M U and A_s U = HU - s MU).  With emit
+// (the library's own step loops, where U, lambda and the operator reach
+// the next step unchanged) the rotation writes that start state itself,
+// from the same registers and with the same arithmetic and order as the
+// start kernel: b = (theta - s) MU, r = b - (HU - s MU), p = D^-1 r, the
+// CG iterate x0 = U (FP64: chunk-major Xc, R, P; mixed: the FP32 r, p, 0
+// and the FP64 b), and the start's partials ||b||^2, r.z, ||r||^2 as
+// quantities 2..4 (after the rotation's 0..1).  The next start then only
+// resets the column state; HU and MU keep H W and M W.
 // ------------------------------------------------------------------------
+template <int V>
+__device__ __forceinline__ void start_emit(const Desc& d, long long row,
+                                           int ch, const double (&u)[V],
+                                           const double (&hu)[V],
+                                           const double (&mu)[V],
+                                           const double (&sh)[V], double di,
+                                           double (&acc)[5][V]) {
+  const size_t o = (size_t)row * d.ncols + ch * V;
+  double b[V], r[V], p[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const double au = fma(-d.sigma, mu[v], hu[v]);
+    b[v] = sh[v] * mu[v];
+    r[v] = b[v] - au;
+    p[v] = di * r[v];
+    acc[2][v] += b[v] * b[v];
+    acc[4][v] += r[v] * r[v];
+  }
+  if (d.R32) {
+    float r32[V], p32[V], z32[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r32[v] = (float)r[v];
+      p32[v] = (float)p[v];
+      z32[v] = 0.0f;
+      acc[3][v] += (double)r32[v] * (double)p32[v];
+    }
+    const size_t o32 = cm_index(d.n, row, ch * V, d.v32);
+    stv<float, V>(d.R32 + o32, r32);
+    stv<float, V>(d.P32 + o32, p32);
+    stv<float, V>(d.X32 + o32, z32);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[3][v] += r[v] * p[v];
+  }
+  if (d.Xc) {
+    const size_t oc = cm_index(d.n, row, ch * V, V);
+    stv<double, V>(d.Xc + oc, u);
+    stv<double, V>(d.R + oc, r);
+    stv<double, V>(d.P + oc, p);
+  }
+  if (d.B) stv<double, V>(d.B + o, b);
+}
+
 template <int V>
 __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
     double* __restrict__ red) {
   const Geo g = geo_of<V>(d, vb);
   const int ncols = d.ncols;
+  const bool emit = d.emit != 0;
   const double* W = d.X;
-  const double* HW = d.R;
-  const double* MW = d.Q;
+  const double* HW = d.HU;
+  const double* MW = d.MU;
   double* U = d.Uout;
   extern __shared__ unsigned char smem[];
+  // Row stride ld = ncols | 1 (odd): the rows a wavefront reads at once
+  // fall in different LDS banks.
+  const int ld = ncols | 1;
   double* sC = reinterpret_cast<double*>(smem);        // ncols^2
-  double* sW = sC + ncols * ncols;                     // tr * ncols each
-  double* sH = sW + g.tr * ncols;
-  double* sM = sH + g.tr * ncols;
+  double* sW = sC + ncols * ncols;                     // tr * ld each
+  double* sH = sW + g.tr * ld;
+  double* sM = sH + g.tr * ld;
   const int tid = threadIdx.x;
   if (g.lb == 0 && tid == 0) {
     d.si->max_dlambda = 0.0;
     d.si->max_resid = 0.0;
   }
   for (int e = tid; e < ncols * ncols; e += kBlock) sC[e] = ldg(d.C + e);
-  double th[V];
+  double th[V], sh[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) th[v] = d.theta[min(g.ch * V + v, ncols - 1)];
-  double acc[2][V];
+  for (int v = 0; v < V; ++v) {
+    th[v] = d.theta[min(g.ch * V + v, ncols - 1)];
+    sh[v] = th[v] - d.sigma;
+  }
+  double acc[5][V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
   // A tile's rows of W, HW, MW are loaded into registers (KR values of
   // each per thread) one tile ahead: the loads of the next tile are in
   // flight while this one is computed (they precede this tile's stores,
@@ -2670,9 +2736,10 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
     for (int k = 0; k < KR; ++k) {
       const int e = tid + k * kBlock;
       if (e < rows * ncols) {
-        sW[e] = rw[k];
-        sH[e] = rh[k];
-        sM[e] = rm[k];
+        const int o = e + (e / ncols) * (ld - ncols);
+        sW[o] = rw[k];
+        sH[o] = rh[k];
+        sM[o] = rm[k];
       }
     }
     __syncthreads();
@@ -2681,9 +2748,9 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
       double u[V], hu[V], mu[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) u[v] = hu[v] = mu[v] = 0.0;
-      const double* wr = sW + g.lr * ncols;
-      const double* hr = sH + g.lr * ncols;
-      const double* mr = sM + g.lr * ncols;
+      const double* wr = sW + g.lr * ld;
+      const double* hr = sH + g.lr * ld;
+      const double* mr = sM + g.lr * ld;
       for (int k = 0; k < ncols; ++k) {
         const double wk = wr[k], hk = hr[k], mk = mr[k];
 #pragma unroll
@@ -2694,10 +2761,15 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
           mu[v] = fma(mk, c, mu[v]);
         }
       }
+      const long long row = r0 + g.lr;
       const size_t o = base + (size_t)g.lr * ncols + g.ch * V;
       stv<double, V>(U + o, u);
-      stv<double, V>(d.HU + o, hu);  // for the next start
-      stv<double, V>(d.MU + o, mu);
+      if (emit) {
+        start_emit<V>(d, row, g.ch, u, hu, mu, sh, ldg(d.dinv + row), acc);
+      } else {
+        stv<double, V>(d.HU + o, hu);  // for the next start
+        stv<double, V>(d.MU + o, mu);
+      }
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double r = hu[v] - th[v] * mu[v];
@@ -2707,13 +2779,25 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
     }
   }
   __syncthreads();
-  block_partials<V, 2>(acc, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+  double rot[2][V], st[3][V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    rot[0][v] = acc[0][v];
+    rot[1][v] = acc[1][v];
+    st[0][v] = acc[2][v];
+    st[1][v] = acc[3][v];
+    st[2][v] = acc[4][v];
+  }
+  block_partials<V, 2>(rot, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+  if (emit)
+    block_partials<V, 3>(st, ncols, g.cpr, g.tr, g.lb, g.nb,
+                         d.part + 2 * kPartStride, red);
 }
 
 template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
 rotate_kernel(const Desc* __restrict__ D, int nprob) {
-  __shared__ double red[2 * kBlock * (VFIX ? VFIX : 2)];
+  __shared__ double red[3 * kBlock * (VFIX ? VFIX : 2)];
   PARO_VB_LOOP64(D, nprob, VFIX, (rotate_body<VV>(d, vb, red)))
 }
 
@@ -2869,16 +2953,17 @@ csr_cg_spmm_kernel(const Desc* __restrict__ D, int nprob, int par) {
 
 // Row-major products of the CSR problems, one thread per (row, chunk of V
 // columns): mode 0 Y1 = A X + s1 M X, Y2 = M X (component form; either
-// output may be absent); mode 1 R = H X, Q = M X (Rayleigh-Ritz: H =
-// A_s + s M); mode 2 HU = H U0, MU = M U0 for the problems whose start
+// output may be absent); mode 1 HU = H X, MU = M X (Rayleigh-Ritz: H =
+// A_s + s M; over the last rotation's H U, M U); mode 2 HU = H U0,
+// MU = M U0 for the problems whose start
 // cannot take them from a rotation (use_hu = 2: formed here, then read by
 // the start like a rotation's).
 template <int V>
 __device__ __forceinline__ void csr_dual_rows(const Desc& d, int mode,
                                               int lb) {
   const double* X = mode == 2 ? d.U0 : d.X;
-  double* Y1 = mode == 0 ? d.Y1 : (mode == 1 ? d.R : d.HU);
-  double* Y2 = mode == 0 ? d.Y2 : (mode == 1 ? d.Q : d.MU);
+  double* Y1 = mode == 0 ? d.Y1 : d.HU;
+  double* Y2 = mode == 0 ? d.Y2 : d.MU;
   const double s1 = mode == 0 ? d.s1 : d.sigma;
   const bool needA = Y1 != nullptr;
   const int ncols = d.ncols, cpr = ncols / V;
@@ -3286,10 +3371,11 @@ hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
   klaunch(t, PARO_ST_SMALL, geneig_batch_kernel, dim3(L.nprob), dim3(kGeThreads),
           0, s, (const Desc*)L.d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // Rotation: C (ncols^2) plus three row tiles of tr * ncols = kBlock * V
-  // values each.
+  // Rotation: C (ncols^2) plus three row tiles of tr rows at stride
+  // ncols | 1, tr * ncols = kBlock * V values each.
   const size_t smem = sizeof(double) * ((size_t)L.maxcols * L.maxcols +
-                                        3 * (size_t)kBlock * L.vmax64);
+                                        3 * ((size_t)kBlock * L.vmax64 +
+                                             (size_t)L.tr64));
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_ROTATE, rotate_kernel, dim3(L.blocks),
                   dim3(kBlock), smem, s, L.d, L.nprob);
   klaunch(t, PARO_ST_ROTATE, rotate_final_kernel, dim3(L.maxcols, L.nprob),
