@@ -2627,17 +2627,20 @@ geneig_batch_kernel(const Desc* __restrict__ D) {
 // quantities 2..4 (after the rotation's 0..1).  The next start then only
 // resets the column state; HU and MU keep H W and M W.
 // ------------------------------------------------------------------------
-template <int V>
+// The start state of one row (VR consecutive columns from col0) from the
+// rotation's registers; acc[2..4] take ||b||^2, r.z, ||r||^2.  The CG
+// vectors are chunk-major with the problem's widths (FP64 v64, FP32 v32).
+template <int VR>
 __device__ __forceinline__ void start_emit(const Desc& d, long long row,
-                                           int ch, const double (&u)[V],
-                                           const double (&hu)[V],
-                                           const double (&mu)[V],
-                                           const double (&sh)[V], double di,
-                                           double (&acc)[5][V]) {
-  const size_t o = (size_t)row * d.ncols + ch * V;
-  double b[V], r[V], p[V];
+                                           int col0, const double (&u)[VR],
+                                           const double (&hu)[VR],
+                                           const double (&mu)[VR],
+                                           const double (&sh)[VR], double di,
+                                           double (&acc)[5][VR]) {
+  const size_t o = (size_t)row * d.ncols + col0;
+  double b[VR], r[VR], p[VR];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
+  for (int v = 0; v < VR; ++v) {
     const double au = fma(-d.sigma, mu[v], hu[v]);
     b[v] = sh[v] * mu[v];
     r[v] = b[v] - au;
@@ -2645,36 +2648,58 @@ __device__ __forceinline__ void start_emit(const Desc& d, long long row,
     acc[2][v] += b[v] * b[v];
     acc[4][v] += r[v] * r[v];
   }
+  constexpr int VS = VR < 2 ? VR : 2;  // store width (VR > 1: ncols even)
   if (d.R32) {
-    float r32[V], p32[V], z32[V];
+    float r32[VR], p32[VR];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
+    for (int v = 0; v < VR; ++v) {
       r32[v] = (float)r[v];
       p32[v] = (float)p[v];
-      z32[v] = 0.0f;
       acc[3][v] += (double)r32[v] * (double)p32[v];
     }
-    const size_t o32 = cm_index(d.n, row, ch * V, d.v32);
-    stv<float, V>(d.R32 + o32, r32);
-    stv<float, V>(d.P32 + o32, p32);
-    stv<float, V>(d.X32 + o32, z32);
+#pragma unroll
+    for (int j = 0; j < VR; j += VS) {
+      const size_t o32 = cm_index(d.n, row, col0 + j, d.v32);
+      float a[VS], c[VS], z[VS];
+#pragma unroll
+      for (int v = 0; v < VS; ++v) {
+        a[v] = r32[j + v];
+        c[v] = p32[j + v];
+        z[v] = 0.0f;
+      }
+      stv<float, VS>(d.R32 + o32, a);
+      stv<float, VS>(d.P32 + o32, c);
+      stv<float, VS>(d.X32 + o32, z);
+    }
   } else {
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[3][v] += r[v] * p[v];
+    for (int v = 0; v < VR; ++v) acc[3][v] += r[v] * p[v];
   }
   if (d.Xc) {
-    const size_t oc = cm_index(d.n, row, ch * V, V);
-    stv<double, V>(d.Xc + oc, u);
-    stv<double, V>(d.R + oc, r);
-    stv<double, V>(d.P + oc, p);
+#pragma unroll
+    for (int j = 0; j < VR; j += VS) {
+      const size_t oc = cm_index(d.n, row, col0 + j, VS);
+      double a[VS], c[VS], e[VS];
+#pragma unroll
+      for (int v = 0; v < VS; ++v) {
+        a[v] = u[j + v];
+        c[v] = r[j + v];
+        e[v] = p[j + v];
+      }
+      stv<double, VS>(d.Xc + oc, a);
+      stv<double, VS>(d.R + oc, c);
+      stv<double, VS>(d.P + oc, e);
+    }
   }
-  if (d.B) stv<double, V>(d.B + o, b);
+  if (d.B) stv<double, VR>(d.B + o, b);
 }
 
-template <int V>
-__device__ __forceinline__ void rotate_body(const Desc& d, int vb,
-    double* __restrict__ red) {
-  const Geo g = geo_of<V>(d, vb);
+// One virtual block of the rotation with VR columns per thread (4 where
+// N_t allows: each LDS read of a row's W, HW, MW value then serves four
+// columns).  red: LDS scratch for the partials (3 kBlock VR doubles).
+template <int VR>
+__device__ __forceinline__ void rotate_rows(const Desc& d, int vb) {
+  const Geo g = geo_of<VR>(d, vb);
   const int ncols = d.ncols;
   const bool emit = d.emit != 0;
   const double* W = d.X;
@@ -2689,28 +2714,29 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
   double* sW = sC + ncols * ncols;                     // tr * ld each
   double* sH = sW + g.tr * ld;
   double* sM = sH + g.tr * ld;
+  double* red = sW;  // after the last tile
   const int tid = threadIdx.x;
   if (g.lb == 0 && tid == 0) {
     d.si->max_dlambda = 0.0;
     d.si->max_resid = 0.0;
   }
   for (int e = tid; e < ncols * ncols; e += kBlock) sC[e] = ldg(d.C + e);
-  double th[V], sh[V];
+  double th[VR], sh[VR];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    th[v] = d.theta[min(g.ch * V + v, ncols - 1)];
+  for (int v = 0; v < VR; ++v) {
+    th[v] = d.theta[min(g.ch * VR + v, ncols - 1)];
     sh[v] = th[v] - d.sigma;
   }
-  double acc[5][V];
+  double acc[5][VR];
 #pragma unroll
   for (int a = 0; a < 5; ++a)
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[a][v] = 0.0;
+    for (int v = 0; v < VR; ++v) acc[a][v] = 0.0;
   // A tile's rows of W, HW, MW are loaded into registers (KR values of
   // each per thread) one tile ahead: the loads of the next tile are in
   // flight while this one is computed (they precede this tile's stores,
   // which they never overlap, also when U is W).
-  constexpr int KR = V;  // tr * ncols = kBlock * V
+  constexpr int KR = VR;  // tr * ncols <= kBlock * VR
   double rw[KR], rh[KR], rm[KR];
   auto fetch = [&](long long t) {
     const long long r0 = t * g.tr;
@@ -2745,60 +2771,72 @@ __device__ __forceinline__ void rotate_body(const Desc& d, int vb,
     __syncthreads();
     if (w.t + w.step < w.end) fetch(w.t + w.step);
     if (g.lr < g.tr && g.lr < rows) {
-      double u[V], hu[V], mu[V];
+      double u[VR], hu[VR], mu[VR];
 #pragma unroll
-      for (int v = 0; v < V; ++v) u[v] = hu[v] = mu[v] = 0.0;
+      for (int v = 0; v < VR; ++v) u[v] = hu[v] = mu[v] = 0.0;
       const double* wr = sW + g.lr * ld;
       const double* hr = sH + g.lr * ld;
       const double* mr = sM + g.lr * ld;
       for (int k = 0; k < ncols; ++k) {
         const double wk = wr[k], hk = hr[k], mk = mr[k];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const double c = sC[k * ncols + g.ch * V + v];
+        for (int v = 0; v < VR; ++v) {
+          const double c = sC[k * ncols + g.ch * VR + v];
           u[v] = fma(wk, c, u[v]);
           hu[v] = fma(hk, c, hu[v]);
           mu[v] = fma(mk, c, mu[v]);
         }
       }
       const long long row = r0 + g.lr;
-      const size_t o = base + (size_t)g.lr * ncols + g.ch * V;
-      stv<double, V>(U + o, u);
+      const size_t o = base + (size_t)g.lr * ncols + g.ch * VR;
+      stv<double, VR>(U + o, u);
       if (emit) {
-        start_emit<V>(d, row, g.ch, u, hu, mu, sh, ldg(d.dinv + row), acc);
+        start_emit<VR>(d, row, g.ch * VR, u, hu, mu, sh, ldg(d.dinv + row),
+                       acc);
       } else {
-        stv<double, V>(d.HU + o, hu);  // for the next start
-        stv<double, V>(d.MU + o, mu);
+        stv<double, VR>(d.HU + o, hu);  // for the next start
+        stv<double, VR>(d.MU + o, mu);
       }
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
+      for (int v = 0; v < VR; ++v) {
         const double r = hu[v] - th[v] * mu[v];
         acc[0][v] += r * r;
         acc[1][v] += mu[v] * mu[v];
       }
     }
   }
-  __syncthreads();
-  double rot[2][V], st[3][V];
+  __syncthreads();  // the tiles are consumed: red may reuse them
+  double rot[2][VR], st[3][VR];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
+  for (int v = 0; v < VR; ++v) {
     rot[0][v] = acc[0][v];
     rot[1][v] = acc[1][v];
     st[0][v] = acc[2][v];
     st[1][v] = acc[3][v];
     st[2][v] = acc[4][v];
   }
-  block_partials<V, 2>(rot, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+  block_partials<VR, 2>(rot, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
   if (emit)
-    block_partials<V, 3>(st, ncols, g.cpr, g.tr, g.lb, g.nb,
-                         d.part + 2 * kPartStride, red);
+    block_partials<VR, 3>(st, ncols, g.cpr, g.tr, g.lb, g.nb,
+                          d.part + 2 * kPartStride, red);
+}
+
+template <int V>
+__device__ __forceinline__ void rotate_body(const Desc& d, int vb) {
+  if constexpr (V == 2) {
+    if (d.ncols % 4 == 0)
+      rotate_rows<4>(d, vb);
+    else
+      rotate_rows<2>(d, vb);
+  } else {
+    rotate_rows<1>(d, vb);
+  }
 }
 
 template <int VFIX>
 __global__ void PARO_STREAM_BOUNDS
 rotate_kernel(const Desc* __restrict__ D, int nprob) {
-  __shared__ double red[3 * kBlock * (VFIX ? VFIX : 2)];
-  PARO_VB_LOOP64(D, nprob, VFIX, (rotate_body<VV>(d, vb, red)))
+  PARO_VB_LOOP64(D, nprob, VFIX, (rotate_body<VV>(d, vb)))
 }
 
 // Per column: lambda = theta, relative change and residual; maxima over
@@ -3372,10 +3410,10 @@ hipError_t launch_rayleigh_ritz(Launch& L, hipStream_t s, Timing* t) {
           0, s, (const Desc*)L.d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // Rotation: C (ncols^2) plus three row tiles of tr rows at stride
-  // ncols | 1, tr * ncols = kBlock * V values each.
+  // ncols | 1, tr * ncols <= kBlock * 4 values and tr <= kBlock each (the
+  // tiles also hold the partials' scratch of 3 kBlock 4 doubles).
   const size_t smem = sizeof(double) * ((size_t)L.maxcols * L.maxcols +
-                                        3 * ((size_t)kBlock * L.vmax64 +
-                                             (size_t)L.tr64));
+                                        3 * (size_t)kBlock * 5);
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_ROTATE, rotate_kernel, dim3(L.blocks),
                   dim3(kBlock), smem, s, L.d, L.nprob);
   klaunch(t, PARO_ST_ROTATE, rotate_final_kernel, dim3(L.maxcols, L.nprob),
