@@ -386,6 +386,7 @@ int paro_server_tick(paro_server* s, int64_t* done_ids, int32_t max_done,
       if (rc != PARO_OK) {
         fail_all(s, s->ready, rc);
         fail_all(s, s->active, rc);
+        fail_all(s, finished, rc);
         return rc;
       }
       for (size_t k = 0; k < s->ready.size(); ++k) {
