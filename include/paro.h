@@ -106,8 +106,9 @@ void paro_default_opts(paro_opts_t* opts);
  * nnz = number of nonzeros of the 15-point Kuhn P1 pattern (the size of
  * the CSR copy paro_export_csr writes);
  * workspace_bytes = device memory paro_assemble needs (the whole resident
- * footprint of the problem: stencil-order matrices, solver blocks,
- * reductions; no CSR copy).
+ * footprint of the problem: stencil-order matrices, a copy of the nodal
+ * potential for the matrix-free SpMM, solver blocks, reductions; no CSR
+ * copy).
  * Any output pointer may be NULL. */
 int paro_query(const paro_box_t* box, const paro_opts_t* opts,
                int64_t* n_dof, int64_t* nnz, size_t* workspace_bytes);
@@ -124,9 +125,14 @@ int paro_query(const paro_box_t* box, const paro_opts_t* opts,
  * diagonals +-(1,1,1)), so a matrix is 15 arrays of n_dof coefficients
  * (coefficient s of row r at [s][r], 0 where the neighbour lies outside
  * the box) and needs no column indices or row pointers.  A CSR copy is
- * made only on request (paro_export_csr).
+ * made only on request (paro_export_csr).  On the uniform mesh K and M
+ * are the same in every row; a row of M_V is a fixed linear function of the
+ * potential at the row's 15 stencil vertices (weights in units of vol/60,
+ * derived from the exact integrals of products of three barycentric
+ * coordinates), which is how the coefficients are evaluated.
  *   d_V: (nx+1)(ny+1)(nz+1) nodal potential values, x fastest, all vertices
- *        including the boundary (device pointer, FP64).
+ *        including the boundary (device pointer, FP64; read during the
+ *        call and copied into the workspace).
  *   d_workspace/bytes: caller-owned device memory of at least
  *        paro_query's workspace_bytes, 256-byte aligned; it must outlive the
  *        problem.  The problem keeps pointers into it.
@@ -630,6 +636,18 @@ void paro_set_graphs(int on);
  * kernel-by-kernel launches.  Process-wide. */
 void paro_set_persistent(int on);
 
+/* Matrix-free FP64 CG SpMM on uniform box problems (on by default): the
+ * z-marching SpMM forms each row's 15 stencil coefficients from the nodal
+ * potential at its stencil vertices (Sec. 2: the potential part of the P1
+ * operator on a uniform Kuhn mesh is linear in those values, the rest is
+ * the same for every row) instead of reading the 15 stored ones, with the
+ * function the assembly stores them with: results are bitwise those of the
+ * stored-coefficient form, which off (0) selects.  Box problems keep a
+ * copy of the potential in their workspace for it (paro_query's size
+ * includes it).  FP32 inner solves read the stored FP32 coefficients.
+ * Process-wide. */
+void paro_set_matrix_free(int on);
+
 /* Cluster-wise projection, the eigenvalue-separation variant of Sec. 3
  * (remarks after Algorithm 3.1): the N + m columns form `count`
  * consecutive clusters of sizes[0..count) (each >= 1, summing to N + m),
@@ -673,7 +691,8 @@ int paro_set_nonlocal(paro_problem* p, const double* d_zeta, int32_t k,
  *
  * Autotuner (on by default): at assembly, the CG SpMM of each new problem
  * shape (grid, N + m, precision) is timed for every variant -- the
- * z-marching SpMM with 1, 2 or 4 chunks per unit (variants 0, 1, 2), the
+ * z-marching SpMM with 1, 2 or 4 chunks per unit (variants 0, 1, 2; the
+ * matrix-free FP64 form groups its chunks itself and has one), the
  * row sweep with one (variant 0) -- each with the full and the halved
  * real block count, and the fastest is kept for the shape for the rest of
  * the process.  The choice never changes the arithmetic or the results

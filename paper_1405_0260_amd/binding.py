@@ -170,6 +170,7 @@ def lib():
         "paro_set_timing": (c_i32, [P, c_i32]),
         "paro_set_graphs": (None, [c_i32]),
         "paro_set_persistent": (None, [c_i32]),
+        "paro_set_matrix_free": (None, [c_i32]),
         "paro_set_clusters": (c_i32, [P, P, c_i32, P]),
         "paro_nonlocal_query": (c_i32, [P, c_i32, ctypes.POINTER(ctypes.c_size_t)]),
         "paro_set_nonlocal": (c_i32, [P, P, c_i32, P, ctypes.c_size_t, P]),
@@ -620,6 +621,13 @@ def paro_set_nonlocal(p: Problem, zeta=None, stream=None):
 def paro_set_persistent(on: bool = True):
     """Run every CG iteration of a call in one cooperative launch."""
     lib().paro_set_persistent(1 if on else 0)
+
+
+def paro_set_matrix_free(on: bool = True):
+    """FP64 z-marching CG SpMM forms the stencil coefficients from the
+    potential (on, the default) or reads the stored ones (off); the same
+    bits either way.  Process-wide."""
+    lib().paro_set_matrix_free(1 if on else 0)
 
 
 def paro_set_autotune(on: bool = True):

@@ -87,7 +87,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b) {
 // graph stays valid while the launch shape (table address, grid, vector
 // widths, problem count, nonlocal projector count, SpMM segmentation) is
 // unchanged.
-typedef std::array<int64_t, 22> GraphKey;
+typedef std::array<int64_t, 23> GraphKey;
 struct GraphCache {
   std::map<GraphKey, hipGraphExec_t> m;
   ~GraphCache() {
@@ -103,6 +103,7 @@ thread_local std::string g_err = "no error";
 // dependent kernels is what remains, and graphs do not shorten it).
 std::atomic<int> g_graphs_on{0};
 std::atomic<int> g_persistent_on{0};
+std::atomic<int> g_matfree_on{1};
 // Co-resident workgroups of the persistent CG kernel (three per CU on 256
 // CUs); the launcher checks the device's actual capacity.
 constexpr int kPersistGrid = 768;
@@ -145,6 +146,11 @@ int check_box(const paro_box_t* box) {
   return PARO_OK;
 }
 
+// All vertices of a box's Kuhn mesh (where its potential is given).
+int64_t box_vertices(const paro_box_t& b) {
+  return (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
+}
+
 int check_opts(const paro_opts_t* o, int64_t n) {
   if (!o) return fail(PARO_EINVAL, "opts is NULL");
   if (o->N < 1 || o->m < 0)
@@ -175,6 +181,8 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.diagA = L.diagA ? (double*)at(L.diagA) : nullptr;
   p.diagM = L.diagM ? (double*)at(L.diagM) : nullptr;
   p.diagA32 = L.diagA32 ? (float*)at(L.diagA32) : nullptr;
+  p.Vb = L.vbox ? (double*)at(L.vbox) : nullptr;
+  p.kconst = L.kconst ? (double*)at(L.kconst) : nullptr;
   p.X = (double*)at(L.X);
   p.R = (double*)at(L.R);
   p.P = (double*)at(L.P);
@@ -254,6 +262,8 @@ void desc_init(Problem& p) {
   d.diagA = p.diagA;
   d.diagM = p.diagM;
   d.diagA32 = p.diagA32;
+  d.Vb = p.Vb;
+  d.kconst = p.kconst;
   d.mx = p.mx;
   d.my = p.my;
   d.mz = p.mz;
@@ -361,6 +371,11 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
     }
   }
   if (L.zmg == 0) L.zmg = 2;
+  // The matrix-free FP64 z-marching SpMM needs every z-marching problem's
+  // potential (box problems keep it in their workspace).
+  L.zmf = L.zm && g_matfree_on.load();
+  for (int i = 0; i < n; ++i)
+    if (tab[i].zm && !tab[i].csr && !(tab[i].Vb && tab[i].kconst)) L.zmf = 0;
   L.v64u = n > 0 ? tab[0].v64 : 0;
   L.v32u = n > 0 ? tab[0].v32 : 0;
   for (int i = 1; i < n; ++i) {
@@ -455,7 +470,7 @@ int cg_graph(Ctx& c, bool fp32, int par, int k, hipStream_t s) {
   const GraphKey key = {
       (int64_t)(uintptr_t)L.d, L.nprob, L.blocks, L.gblocks, L.maxcols,
       L.mincols, L.nt16, L.tr64, L.tr32, L.vmax64, L.v64u, L.v32u,
-      L.nt16_mixed, L.maxkz, L.seg, L.ntile, L.zm, L.zmg, L.csr,
+      L.nt16_mixed, L.maxkz, L.seg, L.ntile, L.zm, L.zmg, L.zmf, L.csr,
       fp32 ? 1 : 0, par, k};
   auto it = c.graphs->m.find(key);
   if (it == c.graphs->m.end()) {
@@ -962,8 +977,9 @@ int autotune(Problem& p, hipStream_t s) {
   const int ns = p.hd.ns;
   const int half = std::max(8, ns / 2 / 8 * 8);
   // Variants: the row-sweep SpMM has one (0); the z-marching one serves
-  // 1, 2 or 4 chunks per unit (variant log2 of that).
-  const int nvar = p.hd.zm ? 3 : 1;
+  // 1, 2 or 4 chunks per unit (variant log2 of that), except in its
+  // matrix-free FP64 form, which balances its own chunk groups.
+  const int nvar = p.hd.zm && !(c.L.zmf && !fp32) ? 3 : 1;
   float best = 1e30f;
   int best_var = 0, best_nb = ns;
   hipError_t err = hipSuccess;
@@ -1007,7 +1023,7 @@ int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 int status_code(int st) { return status_to_code(st); }
 
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
-                   const MeshSizes* ms) {
+                   const MeshSizes* ms, int64_t nvbox) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -1037,6 +1053,8 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
   L.diagA = ms ? 0 : take(sizeof(double) * kStencil * n);
   L.diagM = ms ? 0 : take(sizeof(double) * kStencil * n);
   L.diagA32 = f32 && !ms ? take(sizeof(float) * kStencil * n) : 0;
+  L.vbox = !ms && nvbox > 0 ? take(sizeof(double) * nvbox) : 0;
+  L.kconst = L.vbox ? take(sizeof(double) * (kStencil + 1)) : 0;
   L.X = take(sizeof(double) * blk);
   L.R = take(sizeof(double) * blk);
   L.P = take(sizeof(double) * blk);
@@ -1170,7 +1188,9 @@ int paro_query(const paro_box_t* box, const paro_opts_t* opts,
   if (nnz) *nnz = z;
   if (workspace_bytes)
     *workspace_bytes =
-        make_layout(n, z, opts->N + opts->m, opts->precision).total;
+        make_layout(n, z, opts->N + opts->m, opts->precision, nullptr,
+                    box_vertices(*box))
+            .total;
   return PARO_OK;
 }
 
@@ -1209,7 +1229,8 @@ int paro_assemble(const paro_box_t* box, const double* d_V,
     p.grid = pick_grid(n, p.Nt);
     p.ws_bytes = bytes;
     p.last_stream = s;
-    const Layout L = make_layout(n, z, p.Nt, opts->precision);
+    const Layout L =
+        make_layout(n, z, p.Nt, opts->precision, nullptr, box_vertices(*box));
     carve(p, (char*)d_ws, L);
     auto bail = [&](int code) {
       delete h;
@@ -1718,6 +1739,8 @@ int paro_batch_solve(paro_problem* const* probs, int32_t count,
 void paro_set_graphs(int on) { g_graphs_on.store(on ? 1 : 0); }
 
 void paro_set_persistent(int on) { g_persistent_on.store(on ? 1 : 0); }
+
+void paro_set_matrix_free(int on) { g_matfree_on.store(on ? 1 : 0); }
 
 namespace {
 size_t up256n(size_t x) { return (x + 255) & ~size_t(255); }

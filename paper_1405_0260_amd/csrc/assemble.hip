@@ -3,14 +3,19 @@
 // Finite elements as in Sec. 2 of the paper (continuous piecewise-linear
 // functions on a conforming tetrahedral mesh, zero on the boundary) and the
 // form of eq. (eq-operator-A) with a fixed potential:
-//   a(w, v) = 1/2 (grad w, grad v) + (V_h w, v),
-// V_h the nodal interpolant of V, integrated exactly.  One thread owns one
-// matrix row (one interior vertex) and sums the contributions of the 24
-// tetrahedra around it in a fixed order: no atomics, bitwise reproducible.
+//   a(w, v) = 1/2 (grad w, grad v) + (V_h w, v) - s (w, v),
+// V_h the nodal interpolant of V, integrated exactly.  The stiffness and
+// mass parts of a row are the same at every interior vertex of a uniform
+// mesh: they are summed once on the host over the tetrahedra around each
+// vertex pair.  The potential part is the closed form of kuhn.h, which one
+// thread per row evaluates from the potential at its 15 stencil vertices:
+// no atomics, bitwise reproducible, and bitwise the coefficients the
+// matrix-free CG SpMM forms on the fly.
 //
-// Besides CSR, every value is also written in stencil order: diag[s][d] is
-// the coefficient of row d and neighbour offset s (0 when the neighbour is
-// outside the box), the layout the solver kernels stream.
+// The values are written in stencil order: diag[s][d] is the coefficient of
+// row d and neighbour offset s (0 when the neighbour is outside the box),
+// the layout the solver kernels stream.  CSR copies come from the stencil
+// arrays.
 //
 // Pattern: every edge of a Kuhn tetrahedron is a multiple-free difference
 // of e_x, e_y, e_z, e_i + e_j or (1,1,1), so a row couples its vertex to at
@@ -20,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 
+#include "kuhn.h"
 #include "paro_internal.h"
 
 namespace paro {
@@ -32,64 +38,75 @@ __constant__ int kOff[kStencil][3] = {
     {0, -1, 0},   {-1, 0, 0},  {0, 0, 0},   {1, 0, 0},  {0, 1, 0},
     {1, 1, 0},    {0, 0, 1},   {1, 0, 1},   {0, 1, 1},  {1, 1, 1}};
 
-// Local vertices of the Kuhn tetrahedron of permutation q of the axes:
-// (0,0,0), e_q0, e_q0 + e_q1, (1,1,1).
-__constant__ int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
-                                {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-
-struct Incidence {
-  // For stencil offset s: entries [first[s], first[s+1]) of the lists.
-  int first[kStencil + 1];
-  unsigned char corner[96];  // cube corner occupied by the row vertex (bits)
-  unsigned char perm[96];
-  unsigned char la[96];      // local index of the row vertex
-  unsigned char lb[96];      // local index of the column vertex
+// The row-independent part of the operator: for each offset s the
+// stiffness sum K_s = sum_e vol grad lambda_a . grad lambda_b and the mass
+// sum M_s = sum_e (phi_a, phi_b)_e over the tetrahedra e around the pair
+// (row vertex = local vertex a, neighbour = local vertex b).
+struct KuhnConst {
+  double c0[kStencil];  // 1/2 K_s - s M_s
+  double m[kStencil];   // M_s
+  double vol60;         // tetrahedron volume / 60
 };
 
-void local_vertex(int q, int a, int out[3]) {
-  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
-                                 {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-  out[0] = out[1] = out[2] = 0;
-  if (a >= 1) out[perm[q][0]] = 1;
-  if (a >= 2) out[perm[q][1]] = 1;
-  if (a == 3) out[0] = out[1] = out[2] = 1;
-}
-
-// Enumerate, for each offset, every (cube, tetrahedron, local pair) whose
-// two local vertices are the row vertex and the row vertex + offset.
-Incidence build_incidence() {
-  static const int off[kStencil][3] = {
-      {-1, -1, -1}, {0, -1, -1}, {-1, 0, -1}, {0, 0, -1}, {-1, -1, 0},
-      {0, -1, 0},   {-1, 0, 0},  {0, 0, 0},   {1, 0, 0},  {0, 1, 0},
-      {1, 1, 0},    {0, 0, 1},   {1, 0, 1},   {0, 1, 1},  {1, 1, 1}};
-  Incidence t{};
-  int k = 0;
+KuhnConst kuhn_constants(const double h[3], double sigma) {
+  KuhnConst kc{};
+  const double vol = h[0] * h[1] * h[2] / 6.0;
   for (int s = 0; s < kStencil; ++s) {
-    t.first[s] = k;
+    double ksum = 0.0, msum = 0.0;
     for (int c = 0; c < 8; ++c) {
-      int cv[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+      const int cv[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
       for (int q = 0; q < 6; ++q) {
+        int L[4][3] = {};
         int la = -1, lb = -1;
         for (int a = 0; a < 4; ++a) {
-          int L[3];
-          local_vertex(q, a, L);
-          if (L[0] == cv[0] && L[1] == cv[1] && L[2] == cv[2]) la = a;
-          if (L[0] == cv[0] + off[s][0] && L[1] == cv[1] + off[s][1] &&
-              L[2] == cv[2] + off[s][2])
+          kuhn_local(q, a, L[a]);
+          if (L[a][0] == cv[0] && L[a][1] == cv[1] && L[a][2] == cv[2]) la = a;
+          if (L[a][0] == cv[0] + kKuhnOff[s][0] &&
+              L[a][1] == cv[1] + kKuhnOff[s][1] &&
+              L[a][2] == cv[2] + kKuhnOff[s][2])
             lb = a;
         }
-        if (la >= 0 && lb >= 0) {
-          t.corner[k] = (unsigned char)c;
-          t.perm[k] = (unsigned char)q;
-          t.la[k] = (unsigned char)la;
-          t.lb[k] = (unsigned char)lb;
-          ++k;
+        if (la < 0 || lb < 0) continue;
+        // Edge matrix E (rows x_a - x_0, a = 1..3) and its inverse; the
+        // barycentric gradients are the columns of E^{-1}.
+        double E[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int x = 0; x < 3; ++x) E[a][x] = h[x] * L[a + 1][x];
+        const double det =
+            E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+            E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+            E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+        double Ei[3][3];
+        Ei[0][0] = (E[1][1] * E[2][2] - E[1][2] * E[2][1]) / det;
+        Ei[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) / det;
+        Ei[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) / det;
+        Ei[1][0] = (E[1][2] * E[2][0] - E[1][0] * E[2][2]) / det;
+        Ei[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) / det;
+        Ei[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) / det;
+        Ei[2][0] = (E[1][0] * E[2][1] - E[1][1] * E[2][0]) / det;
+        Ei[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) / det;
+        Ei[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) / det;
+        double ga[3], gb[3];
+        for (int x = 0; x < 3; ++x) {
+          // grad lambda_a (a >= 1) = column a-1 of E^{-1}: Ei[x][a-1].
+          const double g1 = Ei[x][0], g2 = Ei[x][1], g3 = Ei[x][2];
+          const double gl[4] = {-(g1 + g2 + g3), g1, g2, g3};
+          ga[x] = gl[la];
+          gb[x] = gl[lb];
         }
+        ksum += vol * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
+        msum += la == lb ? vol / 10.0 : vol / 20.0;
       }
     }
+    kc.c0[s] = 0.5 * ksum - sigma * msum;
+    kc.m[s] = msum;
   }
-  t.first[kStencil] = k;
-  return t;
+  kc.vol60 = vol / 60.0;
+  return kc;
+}
+
+__device__ __forceinline__ bool valid(int i, int o, int m) {
+  return i + o >= 0 && i + o < m;
 }
 
 // Number of i in [0, i0) with 0 <= i + o < m, for o in {-1, 0, 1}.
@@ -99,103 +116,44 @@ __device__ __forceinline__ long long prefix_valid(int i0, int o, int m) {
   return i0 > 1 ? i0 - 1 : 0;
 }
 
-__device__ __forceinline__ bool valid(int i, int o, int m) {
-  return i + o >= 0 && i + o < m;
-}
-
+// One thread per row.  V holds all (mx + 2)(my + 2)(mz + 2) vertices, x
+// fastest; the row of dof (i, j, k) is vertex (i + 1, j + 1, k + 1).
+// Thread d < 16 also publishes c0 and vol / 60 to `kconst` (the matrix-free
+// CG SpMM reads them there).
 __global__ void __launch_bounds__(kBlock)
-assemble_kernel(Incidence inc, const double* __restrict__ V, int mx, int my,
-                int mz, double hx, double hy, double hz, double sigma,
-                double* __restrict__ dinv, float* __restrict__ dinv32,
+assemble_kernel(KuhnConst kc, const double* __restrict__ V, int mx, int my,
+                int mz, double* __restrict__ dinv, float* __restrict__ dinv32,
                 double* __restrict__ diagA, double* __restrict__ diagM,
-                float* __restrict__ diagA32) {
+                float* __restrict__ diagA32, double* __restrict__ kconst) {
   const long long n = (long long)mx * my * mz;
   const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kconst && d < kStencil + 1)
+    kconst[d] = d < kStencil ? kc.c0[d] : kc.vol60;
   if (d >= n) return;
-  const int nvx = mx + 2, nvy = my + 2;
   const int i = (int)(d % mx);
   const int j = (int)((d / mx) % my);
   const int k = (int)(d / ((long long)mx * my));
-
-  const double vol = hx * hy * hz / 6.0;
-  const double hv[3] = {hx, hy, hz};
-  const int I = i + 1, J = j + 1, K = k + 1;  // vertex indices
-
+  const long long sy = mx + 2, sz = (long long)(mx + 2) * (my + 2);
+  const double* Vr = V + (i + 1) + sy * (j + 1) + sz * (k + 1);
+  double v[kStencil];
+  unsigned mask = 0;
+#pragma unroll
   for (int s = 0; s < kStencil; ++s) {
-    const int ox = kOff[s][0], oy = kOff[s][1], oz = kOff[s][2];
-    if (!valid(i, ox, mx) || !valid(j, oy, my) || !valid(k, oz, mz)) {
-      // Stencil order: a neighbour outside the box has coefficient 0.
-      diagA[(size_t)s * n + d] = 0.0;
-      diagM[(size_t)s * n + d] = 0.0;
-      if (diagA32) diagA32[(size_t)s * n + d] = 0.0f;
-      continue;
-    }
-    double a_sum = 0.0, m_sum = 0.0;
-    for (int e = inc.first[s]; e < inc.first[s + 1]; ++e) {
-      const int c = inc.corner[e], q = inc.perm[e];
-      const int la = inc.la[e], lb = inc.lb[e];
-      const int bx = I - (c & 1), by = J - ((c >> 1) & 1),
-                bz = K - ((c >> 2) & 1);
-      // Local vertex offsets and their potential values.
-      int L[4][3];
-      double Vl[4];
-      for (int a = 0; a < 4; ++a) {
-        L[a][0] = L[a][1] = L[a][2] = 0;
-        if (a >= 1) L[a][kPerm[q][0]] = 1;
-        if (a >= 2) L[a][kPerm[q][1]] = 1;
-        if (a == 3) L[a][0] = L[a][1] = L[a][2] = 1;
-        const long long vid = (long long)(bx + L[a][0]) +
-                              (long long)nvx * ((by + L[a][1]) +
-                                                (long long)nvy * (bz + L[a][2]));
-        Vl[a] = V[vid];
-      }
-      // Edge matrix E (rows x_a - x_0, a = 1..3) and its inverse; the
-      // barycentric gradients are the columns of E^{-1}.
-      double E[3][3];
-      for (int a = 0; a < 3; ++a)
-        for (int x = 0; x < 3; ++x) E[a][x] = hv[x] * L[a + 1][x];
-      const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
-                         E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
-                         E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
-      double Ei[3][3];
-      Ei[0][0] = (E[1][1] * E[2][2] - E[1][2] * E[2][1]) / det;
-      Ei[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) / det;
-      Ei[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) / det;
-      Ei[1][0] = (E[1][2] * E[2][0] - E[1][0] * E[2][2]) / det;
-      Ei[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) / det;
-      Ei[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) / det;
-      Ei[2][0] = (E[1][0] * E[2][1] - E[1][1] * E[2][0]) / det;
-      Ei[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) / det;
-      Ei[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) / det;
-      double ga[3], gb[3];
-      for (int x = 0; x < 3; ++x) {
-        // grad lambda_a (a >= 1) = column a-1 of E^{-1}: Ei[x][a-1].
-        const double g1 = Ei[x][0], g2 = Ei[x][1], g3 = Ei[x][2];
-        const double gl[4] = {-(g1 + g2 + g3), g1, g2, g3};
-        ga[x] = gl[la];
-        gb[x] = gl[lb];
-      }
-      const double kab = vol * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
-      const double vsum = Vl[0] + Vl[1] + Vl[2] + Vl[3];
-      double mab, mvab;
-      if (la == lb) {
-        mab = vol / 10.0;
-        mvab = vol / 60.0 * (vsum + 2.0 * Vl[la]);
-      } else {
-        mab = vol / 20.0;
-        mvab = vol / 120.0 * (vsum + Vl[la] + Vl[lb]);
-      }
-      a_sum += 0.5 * kab + mvab - sigma * mab;
-      m_sum += mab;
-    }
-    diagA[(size_t)s * n + d] = a_sum;
-    diagM[(size_t)s * n + d] = m_sum;
-    if (diagA32) diagA32[(size_t)s * n + d] = (float)a_sum;
-    if (ox == 0 && oy == 0 && oz == 0) {
-      dinv[d] = 1.0 / a_sum;
-      if (dinv32) dinv32[d] = (float)(1.0 / a_sum);
-    }
+    const int ox = kKuhnOff[s][0], oy = kKuhnOff[s][1], oz = kKuhnOff[s][2];
+    v[s] = Vr[ox + sy * oy + sz * oz];
+    if (valid(i, ox, mx) && valid(j, oy, my) && valid(k, oz, mz))
+      mask |= 1u << s;
   }
+  double a[kStencil];
+  kuhn_row(v, kc.c0, kc.vol60, mask, a);
+#pragma unroll
+  for (int s = 0; s < kStencil; ++s) {
+    diagA[(size_t)s * n + d] = a[s];
+    diagM[(size_t)s * n + d] = (mask >> s) & 1u ? kc.m[s] : 0.0;
+    if (diagA32) diagA32[(size_t)s * n + d] = (float)a[s];
+  }
+  dinv[d] = 1.0 / a[7];
+  if (dinv32) dinv32[d] = (float)(1.0 / a[7]);
 }
 
 // CSR copy of the stencil-order matrices (row d = thread d, plus the
@@ -316,11 +274,18 @@ hipError_t launch_potential_range(const double* V, int64_t nv, double* out,
 }
 
 hipError_t launch_assemble(Problem& p, const double* V, hipStream_t s) {
-  static const Incidence inc = build_incidence();
+  const KuhnConst kc = kuhn_constants(p.h, p.sigma);
+  if (p.Vb) {
+    // The matrix-free CG SpMM reads the potential during every solve.
+    const size_t nv = (size_t)(p.mx + 2) * (p.my + 2) * (p.mz + 2);
+    const hipError_t e = hipMemcpyAsync(p.Vb, V, sizeof(double) * nv,
+                                        hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   const int grid = (int)((p.n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(assemble_kernel, dim3(grid), dim3(kBlock), 0, s, inc, V,
-                     p.mx, p.my, p.mz, p.h[0], p.h[1], p.h[2], p.sigma,
-                     p.dinv, p.dinv32, p.diagA, p.diagM, p.diagA32);
+  hipLaunchKernelGGL(assemble_kernel, dim3(grid), dim3(kBlock), 0, s, kc, V,
+                     p.mx, p.my, p.mz, p.dinv, p.dinv32, p.diagA, p.diagM,
+                     p.diagA32, p.kconst);
   return hipGetLastError();
 }
 

@@ -116,6 +116,8 @@ struct Desc {
   const double* diagA;    // stencil order: [kStencil][n], 0 outside the box
   const double* diagM;
   const float* diagA32;
+  const double* Vb;       // uniform box: nodal potential (all vertices) and
+  const double* kconst;   // stencil constants (c0[15], vol / 60), or null
   int mx, my, mz;         // interior vertices per axis (rows = mx my mz)
   int cg_var;             // reserved (one CG SpMM kernel): -1 or 0
   const double* U0;       // start of the source solves (x0), gathered
@@ -273,6 +275,8 @@ struct Launch {
   int ntile;              // some problem uses the row-sweep CG SpMM
   int zm;                 // some problem uses the z-marching CG SpMM
   int zmg;                // chunks per z-marching unit (1, 2 or 4)
+  int zmf;                // FP64 z-marching SpMM forms the coefficients
+                          // from the potential (matrix-free)
   int csr;                // some problem is on a general (CSR) mesh
 };
 
@@ -304,6 +308,10 @@ struct Problem {
   double* diagA;          // A_s, M (and FP32 A_s) in stencil order
   double* diagM;
   float* diagA32;
+  double* Vb = nullptr;     // uniform box: the nodal potential at all
+                            // (mx + 2)(my + 2)(mz + 2) vertices, x fastest
+  double* kconst = nullptr; // ... and c0[15], vol / 60 of its stencil
+                            // (kuhn.h): what the matrix-free SpMM reads
   double* X;              // n x Nt blocks (FP64)
   double* R;
   double* P;
@@ -367,7 +375,7 @@ void timing_add(Timing* t, int stage, hipEvent_t a, hipEvent_t b);
 struct Layout {
   size_t rowptr, colidx, valA, valM, inc_ptr, inc, tets, Xv, Vv, dofmap,
       nbr;  // general meshes only (0 otherwise)
-  size_t dinv, dinv32, diagA, diagM, diagA32;
+  size_t dinv, dinv32, diagA, diagM, diagA32, vbox, kconst;
   size_t X, R, P, Q, B, HU, MU, Xc, R32, P32, Q32, X32;
   size_t part, cpart, gpart, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
@@ -382,8 +390,10 @@ struct MeshSizes {
 };
 // ms: null for the uniform stencil format, else the CSR operator and mesh
 // arrays replace the stencil coefficients.
+// nvbox: vertices of a uniform box problem (its potential is kept for the
+// matrix-free CG SpMM), 0 for none.
 Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
-                   const MeshSizes* ms = nullptr);
+                   const MeshSizes* ms = nullptr, int64_t nvbox = 0);
 
 // A bisection mesh of a box (host): ordered elements (x0, x1, x2, x3)
 // with Maubach tags, and for every vertex made by bisection the two ends

@@ -24,6 +24,7 @@
 
 #include <cmath>
 
+#include "kuhn.h"
 #include "paro_internal.h"
 
 namespace paro {
@@ -592,6 +593,14 @@ __device__ __forceinline__ CmUnit cm_unit(long long u, int cpr) {
   r.t = u / cpr;
   r.ch = (int)(u - r.t * cpr);
   return r;
+}
+
+// A wavefront-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // The value of the adjacent lane of a wavefront: lane - 1 (NEXT false,
@@ -1192,6 +1201,234 @@ spmm_zm_kernel(const Desc* __restrict__ D, int nprob, int par) {
     const int ch0 = nth_bit(gm, gi) * G;
     PARO_CM_WIDTH(T, VFIX, vw,
                   (spmm_zm_unit<T, VV, G>(d, tau, zeta, ch0, amask, ws)))
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Matrix-free z-marching CG SpMM (FP64, uniform box problems).  The stored
+// stencil holds 15 coefficients per row, 120 bytes against the 16 of a
+// chunk's P value: with a few active chunks the coefficients are most of
+// the traffic, and every chunk group reads them again.  On a uniform Kuhn
+// mesh a row's coefficients are c0 + vol/60 W v with v the potential at
+// its 15 stencil vertices (kuhn.h), so this form reads the potential (8
+// bytes per vertex) instead and forms the coefficients with kuhn_row, the
+// function the assembly stored them with: the operator, Q and the p.q
+// partials are bitwise those of spmm_zm_kernel.
+//
+// The potential lines march along z like the P lines: per plane a thread
+// loads 7 values (plane z at y - 1, x - 1 and x; plane z at y, x - 1;
+// plane z + 1 at y and y + 1, x and x + 1) and carries 8.  Units are
+// (plane range, xy tile, chunk group) as in spmm_zm_kernel, with the
+// active chunks compacted and cut into ceil(nac / 4) groups of as equal
+// sizes as possible, so every chunk of a unit is active and the
+// coefficients of a row are formed once per group.
+// ---------------------------------------------------------------------------
+template <int V, int G>
+__device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
+                                              int zeta, const int (&cl)[4],
+                                              unsigned long long amask,
+                                              double* __restrict__ ws) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long n = d.n;
+  const int mx = d.mx, my = d.my, mz = d.mz, ncols = d.ncols;
+  const long long plane = (long long)mx * my;
+  const long long p = (long long)tau * kSpmmRows +
+                      (long long)wave * kSpmmWaveRows + lane - 1;
+  const bool valid = lane >= 1 && lane <= kSpmmWaveRows && p < plane;
+  const int pc = (int)(p < 0 ? 0 : (p < plane ? p : plane - 1));
+  const int j = pc / mx, i = pc - j * mx;
+  const int oym = j > 0 ? -mx : 0, oyp = j < my - 1 ? mx : 0;
+  const int za = (int)((long long)zeta * mz / d.zm);
+  const int zb = (int)((long long)(zeta + 1) * mz / d.zm);
+  // Offsets whose neighbour lies in the box, x and y (z per plane).
+  unsigned mxy = 0;
+#pragma unroll
+  for (int s = 0; s < kStencil; ++s) {
+    const int ox = kKuhnOff[s][0], oy = kKuhnOff[s][1];
+    const bool vx = ox < 0 ? i > 0 : (ox > 0 ? i < mx - 1 : true);
+    const bool vy = oy < 0 ? j > 0 : (oy > 0 ? j < my - 1 : true);
+    mxy |= (vx && vy ? 1u : 0u) << s;
+  }
+  // The stencil constants are uniform: held in scalar registers.
+  double c0[kStencil];
+#pragma unroll
+  for (int s = 0; s < kStencil; ++s) c0[s] = uniform(ldg(d.kconst + s));
+  const double vol60 = uniform(ldg(d.kconst + kStencil));
+  // Potential of vertex (i + 1 + dx, j + 1 + dy, K + dz): Vr[K sz + ...].
+  const long long sy = mx + 2, sz = (long long)(mx + 2) * (my + 2);
+  const double* Vr = d.Vb + (i + 1) + sy * (j + 1);
+  const double* Pc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) Pc[g] = d.P + (size_t)cl[g] * n * V;
+  double cm0[G][V], cmm[G][V], c00[G][V], c0p[G][V];
+  double acc[G][V];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) acc[g][u] = 0.0;
+    zm_line<double, V>(Pc[g], za - 1, mz, plane, pc, 0, cm0[g]);
+    zm_line<double, V>(Pc[g], za - 1, mz, plane, pc, oym, cmm[g]);
+    zm_line<double, V>(Pc[g], za, mz, plane, pc, 0, c00[g]);
+    zm_line<double, V>(Pc[g], za, mz, plane, pc, oyp, c0p[g]);
+  }
+  // Carried potential (stencil slots 0-3, 7-10 of plane za; vertex plane
+  // K = z + 1 holds dof plane z).
+  double w0, w1, w2, w3, w7, w8, w9, w10;
+  {
+    const double* b = Vr + sz * za;  // vertex plane K - 1
+    w0 = ldg(b - 1 - sy);
+    w1 = ldg(b - sy);
+    w2 = ldg(b - 1);
+    w3 = ldg(b);
+    w7 = ldg(b + sz);
+    w8 = ldg(b + sz + 1);
+    w9 = ldg(b + sz + sy);
+    w10 = ldg(b + sz + sy + 1);
+  }
+  for (int z = za; z < zb; ++z) {
+    const size_t row = (size_t)z * plane + pc;
+    const double* b = Vr + sz * (z + 1);
+    double v[kStencil];
+    v[0] = w0; v[1] = w1; v[2] = w2; v[3] = w3;
+    v[4] = ldg(b - 1 - sy);
+    v[5] = ldg(b - sy);
+    v[6] = ldg(b - 1);
+    v[7] = w7; v[8] = w8; v[9] = w9; v[10] = w10;
+    v[11] = ldg(b + sz);
+    v[12] = ldg(b + sz + 1);
+    v[13] = ldg(b + sz + sy);
+    v[14] = ldg(b + sz + sy + 1);
+    double c0m[G][V], c10[G][V], c1p[G][V];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      zm_line<double, V>(Pc[g], z, mz, plane, pc, oym, c0m[g]);
+      zm_line<double, V>(Pc[g], z + 1, mz, plane, pc, 0, c10[g]);
+      zm_line<double, V>(Pc[g], z + 1, mz, plane, pc, oyp, c1p[g]);
+    }
+    unsigned mask = mxy;
+    if (z == 0) mask &= ~0xfu;                // dz = -1: slots 0-3
+    if (z == mz - 1) mask &= ~(0xfu << 11);   // dz = +1: slots 11-14
+    double a[kStencil];
+    kuhn_row(v, c0, vol60, mask, a);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      double x[kStencil][V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        x[1][u] = cmm[g][u];
+        x[3][u] = cm0[g][u];
+        x[5][u] = c0m[g][u];
+        x[7][u] = c00[g][u];
+        x[9][u] = c0p[g][u];
+        x[11][u] = c10[g][u];
+        x[13][u] = c1p[g][u];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          x[2 * k][u] = lane_shift<false>(0.0, x[2 * k + 1][u]);
+          x[2 * k + 8][u] = lane_shift<true>(0.0, x[2 * k + 7][u]);
+        }
+      double q[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) q[u] = 0.0;
+#pragma unroll
+      for (int s = 0; s < kStencil; ++s)
+#pragma unroll
+        for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
+      if (valid) {
+        if (d.kz) nl_add<V>(d, (long long)row, cl[g] * V, q);
+        stv<double, V>(d.Q + ((size_t)cl[g] * n + row) * V, q);
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+          acc[g][u] += (double)x[kSelf][u] * (double)q[u];
+      }
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        cm0[g][u] = c00[g][u];
+        cmm[g][u] = c0m[g][u];
+        c00[g][u] = c10[g][u];
+        c0p[g][u] = c1p[g][u];
+      }
+    }
+    w0 = v[4]; w1 = v[5]; w2 = v[6]; w3 = v[7];
+    w7 = v[11]; w8 = v[12]; w9 = v[13]; w10 = v[14];
+  }
+  // Per (column, segment) p.q, reduced as in spmm_zm_unit.
+  constexpr int kGroup = 64 / V;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const double tot = wave_reduce_scatter<V>(acc[g]);
+    if ((lane & (kGroup - 1)) == 0)
+      ws[wave * ncols + cl[g] * V + lane / kGroup] = tot;
+  }
+  __syncthreads();
+  // Thread tid < ncols stores column tid's partial if the column is active
+  // and its chunk is one of this unit's.
+  bool mine = false;
+#pragma unroll
+  for (int g = 0; g < G; ++g) mine = mine || tid / V == cl[g];
+  if (mine && tid < ncols && ((amask >> tid) & 1)) {
+    const double sum = ((ws[tid] + ws[ncols + tid]) + ws[2 * ncols + tid]) +
+                       ws[3 * ncols + tid];
+    stg(d.pqp + (size_t)tid * d.pqn + ((size_t)zeta * d.zxy + tau), sum);
+  }
+  __syncthreads();  // ws is reused by the next unit
+}
+
+template <int V>
+__device__ __forceinline__ void spmm_zmf_group(const Desc& d, int tau,
+                                               int zeta, int gs,
+                                               const int (&cl)[4],
+                                               unsigned long long amask,
+                                               double* ws) {
+  switch (gs) {
+    case 4: spmm_zmf_unit<V, 4>(d, tau, zeta, cl, amask, ws); break;
+    case 3: spmm_zmf_unit<V, 3>(d, tau, zeta, cl, amask, ws); break;
+    case 2: spmm_zmf_unit<V, 2>(d, tau, zeta, cl, amask, ws); break;
+    default: spmm_zmf_unit<V, 1>(d, tau, zeta, cl, amask, ws); break;
+  }
+}
+
+// VFIX: the common FP64 width of the launch's problems, or 0.
+template <int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+spmm_zmf_kernel(const Desc* __restrict__ D, int nprob, int par) {
+  __shared__ double ws[4 * kNtMax];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (d.zm == 0) return;  // served by spmm_cm_kernel or CSR
+  const int nact = ldg(&d.cs->n_active[par]);
+  const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
+  if (nact == 0) return;  // queued after convergence
+  const int lb = blockIdx.x - d.b0;
+  const int vw = VFIX ? VFIX : d.v64;
+  const unsigned long long cm = chunk_mask(amask, d.ncols / vw, vw);
+  const int nac = __popcll(cm);
+  const int nag = (nac + 3) / 4;
+  const int x = lb % kXcd, l = lb / kXcd, gx = d.nb / kXcd;
+  const int zr = d.zm / kXcd;
+  const long long units = (long long)zr * d.zxy * nag;
+  for (long long k = l; k < units; k += gx) {
+    const long long rest = k / nag;
+    const int gi = (int)(k - rest * nag);
+    const int tau = (int)(rest % d.zxy);
+    const int zeta = x * zr + (int)(rest / d.zxy);
+    // Group gi: active chunks [gi nac / nag, (gi + 1) nac / nag).
+    const int r0 = gi * nac / nag, r1 = (gi + 1) * nac / nag;
+    int cl[4];
+    unsigned long long rem = cm;
+    for (int r = 0; r < r0; ++r) rem &= rem - 1;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      cl[g] = rem ? __builtin_ctzll(rem) : 0;
+      if (g < r1 - r0) rem &= rem - 1;
+    }
+    if (vw == 2)
+      spmm_zmf_group<2>(d, tau, zeta, r1 - r0, cl, amask, ws);
+    else
+      spmm_zmf_group<1>(d, tau, zeta, r1 - r0, cl, amask, ws);
   }
 }
 
@@ -3169,6 +3406,12 @@ static void cg_spmm_launch(Launch& L, int par, hipStream_t s, Timing* t) {
       klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, false>,
               dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob, par);
   }
+  if constexpr (sizeof(T) == 8)
+    if (L.zm && L.zmf) {
+      klaunch(t, PARO_ST_CG_SPMM, spmm_zmf_kernel<W>, dim3(L.blocks),
+              dim3(kBlock), 0, s, D, L.nprob, par);
+      return;
+    }
   if (L.zm) {
     switch (L.zmg) {
       case 1:

@@ -142,3 +142,40 @@ def test_z_march_variants_give_the_same_steps(precision):
             pb.paro_set_tuning(p, 3, ns)
     finally:
         pb.paro_set_autotune(True)
+
+
+@pytest.mark.parametrize("ncols", [7, 10])
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_matrix_free_spmm_is_bitwise_the_stored_one(ncols, precision):
+    """The matrix-free z-marching SpMM (each row's coefficients formed from
+    the potential at its stencil vertices) against the stored-coefficient
+    one on an 81^3 box with a rough random potential: the same CG iterates
+    bit for bit and the same iteration counts.  7 columns run one column
+    per chunk (groups of 4 and 3 chunks), 10 columns two per chunk (groups
+    of 3 and 2); columns leave the groups as they converge.  In FP32-inner
+    mode only the FP64 refinement SpMM changes form."""
+    ncs, lo, hi = NC, -8.0, 8.0
+    X = inputs.vertex_coords(ncs, lo, hi)
+    V = 0.5 * np.sum(X * X, axis=1) + np.random.default_rng(3).uniform(
+        -2.0, 2.0, X.shape[0])
+    n = (NC - 1) ** 3
+    rng = np.random.default_rng(12)
+    B = rng.standard_normal((n, ncols))
+    X0 = rng.standard_normal((n, ncols)) * 0.01
+    out = []
+    try:
+        for mf in (True, False):
+            pb.paro_set_matrix_free(mf)
+            gu.note(f"matrix-free {mf}: {ncs}^3 box, ncols {ncols}, "
+                    f"precision {precision}")
+            prob = gu.assemble(ncs, lo, hi, V, N=ncols, precision=precision,
+                               pcg_rtol=1e-11)
+            Xd = gu.to_dev(X0)
+            its = pb.paro_pcg(prob, gu.to_dev(B), Xd)
+            out.append((its, Xd.cpu().numpy()))
+    finally:
+        pb.paro_set_matrix_free(True)
+    (its_mf, X_mf), (its_st, X_st) = out
+    assert its_mf == its_st
+    assert np.array_equal(X_mf, X_st)
+    assert max(its_mf) > 20
