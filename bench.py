@@ -167,36 +167,60 @@ def algorithmic_bytes(stage, n, nnz, vec_bytes, mat_bytes, diag_bytes):
     raise KeyError(stage)
 
 
-def cg_stage_rates(td, n, nnz, vec_b):
+def z_march(nc):
+    """Whether the library's CG SpMM marches along z on an nc^3-cell box:
+    more than 2048 row tiles of 248 rows, planes of at most 256 tiles and
+    at least 3 planes per range (the plane-range rule of the library)."""
+    m = nc - 1
+    plane = m * m
+    nxy = -(-plane // 248)
+    tiles = -(-plane * m // 248)
+    if tiles <= 2048 or nxy * 8 > 2048:
+        return False
+    nzr = 8 * (-(-384 // (8 * nxy)))
+    while nzr * nxy > 2048:
+        nzr -= 8
+    if nzr > m // 3:
+        nzr = (m // 3) // 8 * 8
+    return nzr >= 8
+
+
+def cg_stage_rates(td, n, nnz, vec_b, nv=None):
     """Per CG kernel of one event-timed solve (timing dict td): launches,
-    time and achieved GB/s on the CSR figure and on the stencil format;
-    also the algorithmic bytes of the whole CG iteration."""
+    time and achieved GB/s on the CSR figure and on the library's own
+    format (nv: vertices of the potential the matrix-free SpMM reads, or
+    None for the stored stencil); also the algorithmic bytes of the whole
+    CG iteration on both."""
     stages = {}
     it_bytes = 0.0
+    it_own = 0.0
     for st in ("cg_spmm", "cg_rupd", "cg_pupd"):
         s = td["stages"][st]
         if s["launches"] == 0:
             continue
         fixed, per_col = algorithmic_bytes(st, n, nnz, vec_b, vec_b, vec_b)
         total = fixed * td["cg_iters"] + per_col * td["cg_col_iters"]
-        fo, po = own_format_bytes(st, n, vec_b, vec_b, vec_b)
+        fo, po = own_format_bytes(st, n, vec_b, vec_b, vec_b, nv)
         own = fo * td["cg_iters"] + po * td["cg_col_iters"]
         it_bytes += total
+        it_own += own
         stages[st] = {"total_ms": s["ms"], "launches": s["launches"],
                       "us_per_launch": 1e3 * s["ms"] / s["launches"],
                       "bytes_per_launch": total / s["launches"],
                       "own_bytes_per_launch": own / s["launches"],
                       "gbs": total / (s["ms"] * 1e-3) / 1e9,
                       "own_gbs": own / (s["ms"] * 1e-3) / 1e9}
-    return stages, it_bytes
+    return stages, it_bytes, it_own
 
 
-def own_format_bytes(stage, n, vec_bytes, mat_bytes, diag_bytes):
-    """(fixed, per_column) bytes of the same kernels with the matrix in the
-    stencil order the library stores it in: 15 coefficients per row and no
-    column indices or row pointers."""
+def own_format_bytes(stage, n, vec_bytes, mat_bytes, diag_bytes, nv=None):
+    """(fixed, per_column) bytes of the same kernels in the library's own
+    format: the SpMM reads 15 stored coefficients per row (no column
+    indices or row pointers), or, matrix-free (nv given), the potential at
+    the nv vertices and forms the coefficients itself."""
     if stage == "cg_spmm":
-        return 15 * n * mat_bytes, 2 * n * vec_bytes
+        fixed = 8 * nv if nv else 15 * n * mat_bytes
+        return fixed, 2 * n * vec_bytes
     return algorithmic_bytes(stage, n, 0, vec_bytes, mat_bytes, diag_bytes)
 
 
@@ -283,16 +307,18 @@ class Solver:
         _, rep_t, prob_t, tim = self.solve(timing=True)
         td = tim.as_dict()
         vec_b = 4 if prec == "mixed" else 8
-        stages, it_bytes = cg_stage_rates(td, n, prob_t.nnz, vec_b)
+        # FP64 z-marching SpMMs are matrix-free (the FP32 inner one of the
+        # mixed precision reads its stored FP32 stencil).
+        zm = z_march(w.nc)
+        nv = (w.nc + 1) ** 3 if zm and prec == "fp64" else None
+        stages, it_bytes, it_own = cg_stage_rates(td, n, prob_t.nnz, vec_b,
+                                                  nv)
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
         kname = KERNEL_NAMES[dom]
+        if dom == "cg_spmm" and zm:
+            kname = "spmm_zmf_kernel" if prec == "fp64" else "spmm_zm_kernel"
         traffic = measured_traffic(kname, TRAFFIC[prec], self.key)
-        if dom == "cg_spmm" and traffic is None:
-            # Meshes beyond 2048 row tiles run the z-marching SpMM.
-            t2 = measured_traffic("spmm_zm_kernel", TRAFFIC[prec], self.key)
-            if t2 is not None:
-                kname, traffic = "spmm_zm_kernel", t2
         all_ms = sum(v["ms"] for v in td["stages"].values())
         cg_ms = sum(td["stages"][k]["ms"] for k in
                     ("cg_spmm", "cg_rupd", "cg_pupd", "cg_final"))
@@ -320,6 +346,10 @@ class Solver:
             "cg_iteration_gbs": round(it_bytes / (cg_ms * 1e-3) / 1e9, 1),
             "cg_iteration_frac": round(it_bytes / (cg_ms * 1e-3) / 1e9 /
                                        HBM_PEAK_GBS, 4),
+            # The same on the bytes the library's own format must move
+            # (matrix-free SpMM: the potential instead of a matrix).
+            "cg_iteration_own_format_frac": round(
+                it_own / (cg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "gram_mfma_tflops": round(gram_flop / (g["ms"] * 1e-3) / 1e12, 2)
             if g["ms"] > 0 else None,
             "gram_mfma_frac_of_fp64_peak": round(

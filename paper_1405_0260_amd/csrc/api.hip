@@ -1054,7 +1054,7 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
   L.diagM = ms ? 0 : take(sizeof(double) * kStencil * n);
   L.diagA32 = f32 && !ms ? take(sizeof(float) * kStencil * n) : 0;
   L.vbox = !ms && nvbox > 0 ? take(sizeof(double) * nvbox) : 0;
-  L.kconst = L.vbox ? take(sizeof(double) * (kStencil + 1)) : 0;
+  L.kconst = L.vbox ? take(sizeof(double) * 32) : 0;
   L.X = take(sizeof(double) * blk);
   L.R = take(sizeof(double) * blk);
   L.P = take(sizeof(double) * blk);

@@ -43,9 +43,9 @@ __constant__ int kOff[kStencil][3] = {
 // sum M_s = sum_e (phi_a, phi_b)_e over the tetrahedra e around the pair
 // (row vertex = local vertex a, neighbour = local vertex b).
 struct KuhnConst {
-  double c0[kStencil];  // 1/2 K_s - s M_s
+  double k[kKcCount];   // c0_s = 1/2 K_s - s M_s, vol / 60, M by pair class
+                        // (the layout of kuhn.h)
   double m[kStencil];   // M_s
-  double vol60;         // tetrahedron volume / 60
 };
 
 KuhnConst kuhn_constants(const double h[3], double sigma) {
@@ -98,10 +98,14 @@ KuhnConst kuhn_constants(const double h[3], double sigma) {
         msum += la == lb ? vol / 10.0 : vol / 20.0;
       }
     }
-    kc.c0[s] = 0.5 * ksum - sigma * msum;
+    kc.k[s] = 0.5 * ksum - sigma * msum;
     kc.m[s] = msum;
   }
-  kc.vol60 = vol / 60.0;
+  kc.k[kKcVol60] = vol / 60.0;
+  // The sums of a pair class are the same additions in the same order.
+  kc.k[kKcM4] = kc.m[1];
+  kc.k[kKcM6] = kc.m[0];
+  kc.k[kKcMDiag] = kc.m[7];
   return kc;
 }
 
@@ -116,10 +120,18 @@ __device__ __forceinline__ long long prefix_valid(int i0, int o, int m) {
   return i0 > 1 ? i0 - 1 : 0;
 }
 
+// Mass coefficient of offset S (its pair class).
+template <int S>
+__device__ __forceinline__ void mass_row_from(const double* k, unsigned mask,
+                                              double (&m)[kStencil]) {
+  m[S] = (mask >> S) & 1u ? k[kuhn_mass_slot(S)] : 0.0;
+  if constexpr (S + 1 < kStencil) mass_row_from<S + 1>(k, mask, m);
+}
+
 // One thread per row.  V holds all (mx + 2)(my + 2)(mz + 2) vertices, x
 // fastest; the row of dof (i, j, k) is vertex (i + 1, j + 1, k + 1).
-// Thread d < 16 also publishes c0 and vol / 60 to `kconst` (the matrix-free
-// CG SpMM reads them there).
+// Threads d < kKcCount also publish the stencil constants to `kconst`
+// (the matrix-free SpMMs read them there).
 __global__ void __launch_bounds__(kBlock)
 assemble_kernel(KuhnConst kc, const double* __restrict__ V, int mx, int my,
                 int mz, double* __restrict__ dinv, float* __restrict__ dinv32,
@@ -127,8 +139,7 @@ assemble_kernel(KuhnConst kc, const double* __restrict__ V, int mx, int my,
                 float* __restrict__ diagA32, double* __restrict__ kconst) {
   const long long n = (long long)mx * my * mz;
   const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (kconst && d < kStencil + 1)
-    kconst[d] = d < kStencil ? kc.c0[d] : kc.vol60;
+  if (kconst && d < kKcCount) kconst[d] = kc.k[d];
   if (d >= n) return;
   const int i = (int)(d % mx);
   const int j = (int)((d / mx) % my);
@@ -144,12 +155,13 @@ assemble_kernel(KuhnConst kc, const double* __restrict__ V, int mx, int my,
     if (valid(i, ox, mx) && valid(j, oy, my) && valid(k, oz, mz))
       mask |= 1u << s;
   }
-  double a[kStencil];
-  kuhn_row(v, kc.c0, kc.vol60, mask, a);
+  double a[kStencil], m[kStencil];
+  kuhn_row(v, kc.k, kc.k[kKcVol60], mask, a);
+  mass_row_from<0>(kc.k, mask, m);
 #pragma unroll
   for (int s = 0; s < kStencil; ++s) {
     diagA[(size_t)s * n + d] = a[s];
-    diagM[(size_t)s * n + d] = (mask >> s) & 1u ? kc.m[s] : 0.0;
+    diagM[(size_t)s * n + d] = m[s];
     if (diagA32) diagA32[(size_t)s * n + d] = (float)a[s];
   }
   dinv[d] = 1.0 / a[7];

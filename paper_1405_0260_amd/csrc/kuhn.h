@@ -114,6 +114,21 @@ static_assert(kuhn_table_even(), "Kuhn potential weights");
 
 inline constexpr KuhnTable kKuhn = make_kuhn_table();
 
+// The constants of a problem's stencil as the device reads them (the
+// workspace copy written by the assembly): c0[15], vol / 60, then the mass
+// coefficients, which depend on the offset only through the number of
+// tetrahedra around the pair (vol / 20 each, vol / 10 each on the
+// diagonal): M of a 4-tetrahedron pair, of a 6-tetrahedron pair, of the
+// diagonal.
+constexpr int kKcVol60 = 15;
+constexpr int kKcM4 = 16, kKcM6 = 17, kKcMDiag = 18;
+constexpr int kKcCount = 19;
+// Slot of the mass coefficient of offset s in that array.
+constexpr int kuhn_mass_slot(int s) {
+  return s == 7 ? kKcMDiag : (kKuhn.nel[s] == 4 ? kKcM4 : kKcM6);
+}
+static_assert(kKuhn.nel[0] == 6 && kKuhn.nel[1] == 4, "Kuhn pair classes");
+
 // Coefficient S of a row from the potential v[k] at its stencil vertices:
 // c0[S] + vol60 sum_k W[S][k] v[k] (ascending k), or 0 where bit S of
 // `mask` (neighbour inside the box) is clear.

@@ -117,7 +117,7 @@ struct Desc {
   const double* diagM;
   const float* diagA32;
   const double* Vb;       // uniform box: nodal potential (all vertices) and
-  const double* kconst;   // stencil constants (c0[15], vol / 60), or null
+  const double* kconst;   // stencil constants (kuhn.h layout), or null
   int mx, my, mz;         // interior vertices per axis (rows = mx my mz)
   int cg_var;             // reserved (one CG SpMM kernel): -1 or 0
   const double* U0;       // start of the source solves (x0), gathered
@@ -310,8 +310,8 @@ struct Problem {
   float* diagA32;
   double* Vb = nullptr;     // uniform box: the nodal potential at all
                             // (mx + 2)(my + 2)(mz + 2) vertices, x fastest
-  double* kconst = nullptr; // ... and c0[15], vol / 60 of its stencil
-                            // (kuhn.h): what the matrix-free SpMM reads
+  double* kconst = nullptr; // ... and its stencil constants (kuhn.h):
+                            // what the matrix-free SpMMs read
   double* X;              // n x Nt blocks (FP64)
   double* R;
   double* P;

@@ -1224,14 +1224,21 @@ spmm_zm_kernel(const Desc* __restrict__ D, int nprob, int par) {
 // sizes as possible, so every chunk of a unit is active and the
 // coefficients of a row are formed once per group.
 // ---------------------------------------------------------------------------
-template <int V, int G>
-__device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
-                                              int zeta, const int (&cl)[4],
-                                              unsigned long long amask,
-                                              double* __restrict__ ws) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// The z-march of one unit over the chunk-major block `src` (chunks cl[0..G)
+// of V columns): per plane z of [za, zb) and chunk g it calls
+//   f(g, row, valid, mask, a, x)
+// with row the thread's row of plane z, valid false on the wavefront's halo
+// lanes and past the plane, mask the offsets whose neighbour lies in the
+// box, a the row's 15 coefficients of A_s (kuhn_row) and x[s][u] the value
+// of column u at neighbour s (0-weighted where the neighbour is outside).
+template <int V, int G, class F>
+__device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
+                                          const int (&cl)[4],
+                                          const double* __restrict__ src,
+                                          F&& f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long n = d.n;
-  const int mx = d.mx, my = d.my, mz = d.mz, ncols = d.ncols;
+  const int mx = d.mx, my = d.my, mz = d.mz;
   const long long plane = (long long)mx * my;
   const long long p = (long long)tau * kSpmmRows +
                       (long long)wave * kSpmmWaveRows + lane - 1;
@@ -1254,19 +1261,16 @@ __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
   double c0[kStencil];
 #pragma unroll
   for (int s = 0; s < kStencil; ++s) c0[s] = uniform(ldg(d.kconst + s));
-  const double vol60 = uniform(ldg(d.kconst + kStencil));
+  const double vol60 = uniform(ldg(d.kconst + kKcVol60));
   // Potential of vertex (i + 1 + dx, j + 1 + dy, K + dz): Vr[K sz + ...].
   const long long sy = mx + 2, sz = (long long)(mx + 2) * (my + 2);
   const double* Vr = d.Vb + (i + 1) + sy * (j + 1);
   const double* Pc[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) Pc[g] = d.P + (size_t)cl[g] * n * V;
+  for (int g = 0; g < G; ++g) Pc[g] = src + (size_t)cl[g] * n * V;
   double cm0[G][V], cmm[G][V], c00[G][V], c0p[G][V];
-  double acc[G][V];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int u = 0; u < V; ++u) acc[g][u] = 0.0;
     zm_line<double, V>(Pc[g], za - 1, mz, plane, pc, 0, cm0[g]);
     zm_line<double, V>(Pc[g], za - 1, mz, plane, pc, oym, cmm[g]);
     zm_line<double, V>(Pc[g], za, mz, plane, pc, 0, c00[g]);
@@ -1287,7 +1291,7 @@ __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
     w10 = ldg(b + sz + sy + 1);
   }
   for (int z = za; z < zb; ++z) {
-    const size_t row = (size_t)z * plane + pc;
+    const long long row = (long long)z * plane + pc;
     const double* b = Vr + sz * (z + 1);
     double v[kStencil];
     v[0] = w0; v[1] = w1; v[2] = w2; v[3] = w3;
@@ -1331,20 +1335,7 @@ __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
           x[2 * k][u] = lane_shift<false>(0.0, x[2 * k + 1][u]);
           x[2 * k + 8][u] = lane_shift<true>(0.0, x[2 * k + 7][u]);
         }
-      double q[V];
-#pragma unroll
-      for (int u = 0; u < V; ++u) q[u] = 0.0;
-#pragma unroll
-      for (int s = 0; s < kStencil; ++s)
-#pragma unroll
-        for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
-      if (valid) {
-        if (d.kz) nl_add<V>(d, (long long)row, cl[g] * V, q);
-        stv<double, V>(d.Q + ((size_t)cl[g] * n + row) * V, q);
-#pragma unroll
-        for (int u = 0; u < V; ++u)
-          acc[g][u] += (double)x[kSelf][u] * (double)q[u];
-      }
+      f(g, row, valid, mask, a, x);
 #pragma unroll
       for (int u = 0; u < V; ++u) {
         cm0[g][u] = c00[g][u];
@@ -1356,6 +1347,41 @@ __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
     w0 = v[4]; w1 = v[5]; w2 = v[6]; w3 = v[7];
     w7 = v[11]; w8 = v[12]; w9 = v[13]; w10 = v[14];
   }
+}
+
+template <int V, int G>
+__device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
+                                              int zeta, const int (&cl)[4],
+                                              unsigned long long amask,
+                                              double* __restrict__ ws) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long n = d.n;
+  const int ncols = d.ncols;
+  double acc[G][V];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int u = 0; u < V; ++u) acc[g][u] = 0.0;
+  zmf_march<V, G>(
+      d, tau, zeta, cl, d.P,
+      [&](int g, long long row, bool valid, unsigned,
+          const double (&a)[kStencil], const double (&x)[kStencil][V]) {
+        // q = sum_s a_s x_s, s ascending, as spmm_zm_unit.
+        double q[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) q[u] = 0.0;
+#pragma unroll
+        for (int s = 0; s < kStencil; ++s)
+#pragma unroll
+          for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
+        if (valid) {
+          if (d.kz) nl_add<V>(d, row, cl[g] * V, q);
+          stv<double, V>(d.Q + ((size_t)cl[g] * n + row) * V, q);
+#pragma unroll
+          for (int u = 0; u < V; ++u)
+            acc[g][u] += (double)x[kSelf][u] * (double)q[u];
+        }
+      });
   // Per (column, segment) p.q, reduced as in spmm_zm_unit.
   constexpr int kGroup = 64 / V;
 #pragma unroll
@@ -1431,7 +1457,6 @@ spmm_zmf_kernel(const Desc* __restrict__ D, int nprob, int par) {
       spmm_zmf_group<1>(d, tau, zeta, r1 - r0, cl, amask, ws);
   }
 }
-
 
 // The r-update with alpha computed in place (the alpha finaliser folded
 // into the kernel): wavefront w < V of a unit forms alpha of column

@@ -31,6 +31,9 @@ def test_algorithmic_bytes_per_kernel():
     # The stencil format: 15 coefficients per row, no indices.
     assert bench.own_format_bytes("cg_spmm", n, 4, 4, 4) == (
         15 * n * 4, 2 * n * 4)
+    # Matrix-free: the potential at the nv vertices instead.
+    assert bench.own_format_bytes("cg_spmm", n, 8, 8, 8, nv=3000) == (
+        3000 * 8, 2 * n * 8)
     with pytest.raises(KeyError):
         bench.algorithmic_bytes("gram", n, nnz, 8, 8, 8)
 
@@ -41,14 +44,24 @@ def test_stage_rates_from_a_timing_record():
           "stages": {"cg_spmm": {"ms": 0.5, "launches": 10},
                      "cg_rupd": {"ms": 0.25, "launches": 10},
                      "cg_pupd": {"ms": 0.0, "launches": 0}}}
-    stages, it_bytes = bench.cg_stage_rates(td, n, nnz, 4)
+    stages, it_bytes, it_own = bench.cg_stage_rates(td, n, nnz, 4)
     assert set(stages) == {"cg_spmm", "cg_rupd"}
     spmm = (nnz * 8 + 4 * (n + 1)) * 10 + 2 * n * 4 * 30
     rupd = n * 4 * 10 + 3 * n * 4 * 30
     assert it_bytes == spmm + rupd
+    assert it_own == 15 * n * 4 * 10 + 2 * n * 4 * 30 + rupd
+    _, _, it_mf = bench.cg_stage_rates(td, n, nnz, 4, nv=3000)
+    assert it_mf == 3000 * 8 * 10 + 2 * n * 4 * 30 + rupd
     assert stages["cg_spmm"]["bytes_per_launch"] == spmm / 10
     assert abs(stages["cg_spmm"]["gbs"] - spmm / 0.5e-3 / 1e9) < 1e-9
     assert abs(stages["cg_rupd"]["us_per_launch"] - 25.0) < 1e-12
+
+
+def test_z_march_rule_matches_the_library_meshes():
+    # 95^3 and 81^3 rows march along z (more than 2048 tiles of 248 rows);
+    # 63^3 and smaller sweep the rows.
+    assert bench.z_march(96) and bench.z_march(82)
+    assert not bench.z_march(64) and not bench.z_march(24)
 
 
 def _summary(sha, lines):

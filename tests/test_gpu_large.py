@@ -179,3 +179,41 @@ def test_matrix_free_spmm_is_bitwise_the_stored_one(ncols, precision):
     assert its_mf == its_st
     assert np.array_equal(X_mf, X_st)
     assert max(its_mf) > 20
+
+
+@pytest.mark.parametrize("N,m", [(4, 2), (5, 2)])
+def test_matrix_free_steps_are_bitwise_the_stored_ones(N, m):
+    """ParO steps on an 81^3 box with a rough potential, CG SpMM in the
+    matrix-free form (coefficients from the potential) against the
+    stored-coefficient form: the same Ritz values and orbitals bit for bit
+    after Step 1 and three steps, through starts, source solves whose
+    columns converge at different iterations, and rotations.  6 columns
+    make 3 chunks of 2, 7 columns 7 single-column chunks (groups of 4 and
+    3)."""
+    import torch
+    ncs, lo, hi = NC, -8.0, 8.0
+    X = inputs.vertex_coords(ncs, lo, hi)
+    V = 0.5 * np.sum(X * X, axis=1) + np.random.default_rng(4).uniform(
+        -1.0, 1.0, X.shape[0])
+    n = (NC - 1) ** 3
+    U0 = gu.to_dev(np.random.default_rng(5).standard_normal((n, N + m)))
+    out = []
+    try:
+        for mf in (True, False):
+            pb.paro_set_matrix_free(mf)
+            gu.note(f"matrix-free {mf}: steps on {ncs}^3, N {N}, m {m}")
+            prob = gu.assemble(ncs, lo, hi, V, N=N, m=m, pcg_rtol=1e-9)
+            lam = torch.zeros(N + m, dtype=torch.float64, device=gu.device())
+            U = torch.zeros(n, N + m, dtype=torch.float64, device=gu.device())
+            pb.paro_init(prob, U0, lam, U)
+            lams = [lam.cpu().numpy().copy()]
+            for _ in range(3):
+                pb.paro_step(prob, lam, U)
+                lams.append(lam.cpu().numpy().copy())
+            out.append((np.array(lams), U.cpu().numpy()))
+    finally:
+        pb.paro_set_matrix_free(True)
+    (l_mf, U_mf), (l_st, U_st) = out
+    assert np.array_equal(l_mf, l_st)
+    assert np.array_equal(U_mf, U_st)
+    assert np.all(np.isfinite(l_mf)) and l_mf[-1, 0] < l_mf[0, 0]
