@@ -307,17 +307,16 @@ class Solver:
         _, rep_t, prob_t, tim = self.solve(timing=True)
         td = tim.as_dict()
         vec_b = 4 if prec == "mixed" else 8
-        # FP64 z-marching SpMMs are matrix-free (the FP32 inner one of the
-        # mixed precision reads its stored FP32 stencil).
+        # The z-marching SpMMs are matrix-free: they read the potential.
         zm = z_march(w.nc)
-        nv = (w.nc + 1) ** 3 if zm and prec == "fp64" else None
+        nv = (w.nc + 1) ** 3 if zm else None
         stages, it_bytes, it_own = cg_stage_rates(td, n, prob_t.nnz, vec_b,
                                                   nv)
         dom = max(stages, key=lambda k: stages[k]["total_ms"])
         d = stages[dom]
         kname = KERNEL_NAMES[dom]
         if dom == "cg_spmm" and zm:
-            kname = "spmm_zmf_kernel" if prec == "fp64" else "spmm_zm_kernel"
+            kname = "spmm_zmf_kernel"
         traffic = measured_traffic(kname, TRAFFIC[prec], self.key)
         all_ms = sum(v["ms"] for v in td["stages"].values())
         cg_ms = sum(td["stages"][k]["ms"] for k in

@@ -636,16 +636,16 @@ void paro_set_graphs(int on);
  * kernel-by-kernel launches.  Process-wide. */
 void paro_set_persistent(int on);
 
-/* Matrix-free FP64 CG SpMM on uniform box problems (on by default): the
+/* Matrix-free CG SpMM on uniform box problems (on by default): the
  * z-marching SpMM forms each row's 15 stencil coefficients from the nodal
  * potential at its stencil vertices (Sec. 2: the potential part of the P1
  * operator on a uniform Kuhn mesh is linear in those values, the rest is
  * the same for every row) instead of reading the 15 stored ones, with the
- * function the assembly stores them with: results are bitwise those of the
+ * function the assembly stores them with (FP32 inner solves: rounded from
+ * FP64, as the stored FP32 stencil is): results are bitwise those of the
  * stored-coefficient form, which off (0) selects.  Box problems keep a
  * copy of the potential in their workspace for it (paro_query's size
- * includes it).  FP32 inner solves read the stored FP32 coefficients.
- * Process-wide. */
+ * includes it).  Process-wide. */
 void paro_set_matrix_free(int on);
 
 /* Cluster-wise projection, the eigenvalue-separation variant of Sec. 3

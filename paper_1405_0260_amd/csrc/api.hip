@@ -371,7 +371,7 @@ Launch make_launch(Desc* dtab, const Desc* tab, int n) {
     }
   }
   if (L.zmg == 0) L.zmg = 2;
-  // The matrix-free FP64 z-marching SpMM needs every z-marching problem's
+  // The matrix-free z-marching SpMM needs every z-marching problem's
   // potential (box problems keep it in their workspace).
   L.zmf = L.zm && g_matfree_on.load();
   for (int i = 0; i < n; ++i)
@@ -978,8 +978,8 @@ int autotune(Problem& p, hipStream_t s) {
   const int half = std::max(8, ns / 2 / 8 * 8);
   // Variants: the row-sweep SpMM has one (0); the z-marching one serves
   // 1, 2 or 4 chunks per unit (variant log2 of that), except in its
-  // matrix-free FP64 form, which balances its own chunk groups.
-  const int nvar = p.hd.zm && !(c.L.zmf && !fp32) ? 3 : 1;
+  // matrix-free form, which balances its own chunk groups.
+  const int nvar = p.hd.zm && !c.L.zmf ? 3 : 1;
   float best = 1e30f;
   int best_var = 0, best_nb = ns;
   hipError_t err = hipSuccess;

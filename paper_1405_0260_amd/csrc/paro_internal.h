@@ -275,7 +275,7 @@ struct Launch {
   int ntile;              // some problem uses the row-sweep CG SpMM
   int zm;                 // some problem uses the z-marching CG SpMM
   int zmg;                // chunks per z-marching unit (1, 2 or 4)
-  int zmf;                // FP64 z-marching SpMM forms the coefficients
+  int zmf;                // the z-marching SpMM forms the coefficients
                           // from the potential (matrix-free)
   int csr;                // some problem is on a general (CSR) mesh
 };

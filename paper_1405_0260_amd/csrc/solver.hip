@@ -1206,36 +1206,38 @@ spmm_zm_kernel(const Desc* __restrict__ D, int nprob, int par) {
 
 
 // ---------------------------------------------------------------------------
-// Matrix-free z-marching CG SpMM (FP64, uniform box problems).  The stored
-// stencil holds 15 coefficients per row, 120 bytes against the 16 of a
-// chunk's P value: with a few active chunks the coefficients are most of
-// the traffic, and every chunk group reads them again.  On a uniform Kuhn
-// mesh a row's coefficients are c0 + vol/60 W v with v the potential at
-// its 15 stencil vertices (kuhn.h), so this form reads the potential (8
-// bytes per vertex) instead and forms the coefficients with kuhn_row, the
-// function the assembly stored them with: the operator, Q and the p.q
-// partials are bitwise those of spmm_zm_kernel.
+// Matrix-free z-marching CG SpMM (uniform box problems).  The stored
+// stencil holds 15 coefficients per row, 120 bytes in FP64 (60 in FP32)
+// against the 16 of a chunk's P value: with a few active chunks the
+// coefficients are most of the traffic, and every chunk group reads them
+// again.  On a uniform Kuhn mesh a row's coefficients are c0 + vol/60 W v
+// with v the potential at its 15 stencil vertices (kuhn.h), so this form
+// reads the potential (8 bytes per vertex) instead and forms the
+// coefficients with kuhn_row, the function the assembly stored them with
+// (FP32: rounded from FP64, as the stored FP32 stencil is): the operator,
+// Q and the p.q partials are bitwise those of spmm_zm_kernel.
 //
 // The potential lines march along z like the P lines: per plane a thread
 // loads 7 values (plane z at y - 1, x - 1 and x; plane z at y, x - 1;
 // plane z + 1 at y and y + 1, x and x + 1) and carries 8.  Units are
 // (plane range, xy tile, chunk group) as in spmm_zm_kernel, with the
-// active chunks compacted and cut into ceil(nac / 4) groups of as equal
-// sizes as possible, so every chunk of a unit is active and the
-// coefficients of a row are formed once per group.
+// active chunks compacted and cut into the fewest groups of at most 4
+// chunks (3 for FP32 chunks of 4 columns), of as equal sizes as possible,
+// so every chunk of a unit is active and the coefficients of a row are
+// formed once per group.
 // ---------------------------------------------------------------------------
 // The z-march of one unit over the chunk-major block `src` (chunks cl[0..G)
-// of V columns): per plane z of [za, zb) and chunk g it calls
+// of V columns of type T): per plane z of [za, zb) and chunk g it calls
 //   f(g, row, valid, mask, a, x)
 // with row the thread's row of plane z, valid false on the wavefront's halo
 // lanes and past the plane, mask the offsets whose neighbour lies in the
-// box, a the row's 15 coefficients of A_s (kuhn_row) and x[s][u] the value
-// of column u at neighbour s (0-weighted where the neighbour is outside).
-template <int V, int G, class F>
+// box, a the row's 15 FP64 coefficients of A_s (kuhn_row) and x[s][u] the
+// value of column u at neighbour s (0-weighted where the neighbour is
+// outside).
+template <typename T, int V, int G, class F>
 __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
                                           const int (&cl)[4],
-                                          const double* __restrict__ src,
-                                          F&& f) {
+                                          const T* __restrict__ src, F&& f) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long n = d.n;
   const int mx = d.mx, my = d.my, mz = d.mz;
@@ -1265,16 +1267,16 @@ __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
   // Potential of vertex (i + 1 + dx, j + 1 + dy, K + dz): Vr[K sz + ...].
   const long long sy = mx + 2, sz = (long long)(mx + 2) * (my + 2);
   const double* Vr = d.Vb + (i + 1) + sy * (j + 1);
-  const double* Pc[G];
+  const T* Pc[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) Pc[g] = src + (size_t)cl[g] * n * V;
-  double cm0[G][V], cmm[G][V], c00[G][V], c0p[G][V];
+  T cm0[G][V], cmm[G][V], c00[G][V], c0p[G][V];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    zm_line<double, V>(Pc[g], za - 1, mz, plane, pc, 0, cm0[g]);
-    zm_line<double, V>(Pc[g], za - 1, mz, plane, pc, oym, cmm[g]);
-    zm_line<double, V>(Pc[g], za, mz, plane, pc, 0, c00[g]);
-    zm_line<double, V>(Pc[g], za, mz, plane, pc, oyp, c0p[g]);
+    zm_line<T, V>(Pc[g], za - 1, mz, plane, pc, 0, cm0[g]);
+    zm_line<T, V>(Pc[g], za - 1, mz, plane, pc, oym, cmm[g]);
+    zm_line<T, V>(Pc[g], za, mz, plane, pc, 0, c00[g]);
+    zm_line<T, V>(Pc[g], za, mz, plane, pc, oyp, c0p[g]);
   }
   // Carried potential (stencil slots 0-3, 7-10 of plane za; vertex plane
   // K = z + 1 holds dof plane z).
@@ -1303,12 +1305,12 @@ __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
     v[12] = ldg(b + sz + 1);
     v[13] = ldg(b + sz + sy);
     v[14] = ldg(b + sz + sy + 1);
-    double c0m[G][V], c10[G][V], c1p[G][V];
+    T c0m[G][V], c10[G][V], c1p[G][V];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      zm_line<double, V>(Pc[g], z, mz, plane, pc, oym, c0m[g]);
-      zm_line<double, V>(Pc[g], z + 1, mz, plane, pc, 0, c10[g]);
-      zm_line<double, V>(Pc[g], z + 1, mz, plane, pc, oyp, c1p[g]);
+      zm_line<T, V>(Pc[g], z, mz, plane, pc, oym, c0m[g]);
+      zm_line<T, V>(Pc[g], z + 1, mz, plane, pc, 0, c10[g]);
+      zm_line<T, V>(Pc[g], z + 1, mz, plane, pc, oyp, c1p[g]);
     }
     unsigned mask = mxy;
     if (z == 0) mask &= ~0xfu;                // dz = -1: slots 0-3
@@ -1317,7 +1319,7 @@ __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
     kuhn_row(v, c0, vol60, mask, a);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      double x[kStencil][V];
+      T x[kStencil][V];
 #pragma unroll
       for (int u = 0; u < V; ++u) {
         x[1][u] = cmm[g][u];
@@ -1332,8 +1334,8 @@ __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int u = 0; u < V; ++u) {
-          x[2 * k][u] = lane_shift<false>(0.0, x[2 * k + 1][u]);
-          x[2 * k + 8][u] = lane_shift<true>(0.0, x[2 * k + 7][u]);
+          x[2 * k][u] = lane_shift<false>(T(0), x[2 * k + 1][u]);
+          x[2 * k + 8][u] = lane_shift<true>(T(0), x[2 * k + 7][u]);
         }
       f(g, row, valid, mask, a, x);
 #pragma unroll
@@ -1349,7 +1351,7 @@ __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
   }
 }
 
-template <int V, int G>
+template <typename T, int V, int G>
 __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
                                               int zeta, const int (&cl)[4],
                                               unsigned long long amask,
@@ -1357,26 +1359,31 @@ __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long n = d.n;
   const int ncols = d.ncols;
+  const CmVecs<T> vs(d);
   double acc[G][V];
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int u = 0; u < V; ++u) acc[g][u] = 0.0;
-  zmf_march<V, G>(
-      d, tau, zeta, cl, d.P,
+  zmf_march<T, V, G>(
+      d, tau, zeta, cl, vs.P,
       [&](int g, long long row, bool valid, unsigned,
-          const double (&a)[kStencil], const double (&x)[kStencil][V]) {
-        // q = sum_s a_s x_s, s ascending, as spmm_zm_unit.
-        double q[V];
+          const double (&a)[kStencil], const T (&x)[kStencil][V]) {
+        // q = sum_s a_s x_s, s ascending, as spmm_zm_unit (FP32: the
+        // coefficients rounded as in the stored FP32 stencil).
+        T q[V];
 #pragma unroll
-        for (int u = 0; u < V; ++u) q[u] = 0.0;
+        for (int u = 0; u < V; ++u) q[u] = T(0);
 #pragma unroll
-        for (int s = 0; s < kStencil; ++s)
+        for (int s = 0; s < kStencil; ++s) {
+          const T as = (T)a[s];
 #pragma unroll
-          for (int u = 0; u < V; ++u) q[u] = fma(a[s], x[s][u], q[u]);
+          for (int u = 0; u < V; ++u) q[u] = fma(as, x[s][u], q[u]);
+        }
         if (valid) {
-          if (d.kz) nl_add<V>(d, row, cl[g] * V, q);
-          stv<double, V>(d.Q + ((size_t)cl[g] * n + row) * V, q);
+          if constexpr (sizeof(T) == 8)
+            if (d.kz) nl_add<V>(d, row, cl[g] * V, q);
+          stv<T, V>(vs.Q + ((size_t)cl[g] * n + row) * V, q);
 #pragma unroll
           for (int u = 0; u < V; ++u)
             acc[g][u] += (double)x[kSelf][u] * (double)q[u];
@@ -1404,22 +1411,31 @@ __device__ __forceinline__ void spmm_zmf_unit(const Desc& d, int tau,
   __syncthreads();  // ws is reused by the next unit
 }
 
-template <int V>
+// Most chunks per unit: 4, or 3 for FP32 chunks of 4 columns (16 columns
+// per unit would need more registers than two wavefronts per SIMD have).
+__host__ __device__ constexpr int zmf_group_max(int bytes, int V) {
+  return bytes == 4 && V == 4 ? 3 : 4;
+}
+
+template <typename T, int V>
 __device__ __forceinline__ void spmm_zmf_group(const Desc& d, int tau,
                                                int zeta, int gs,
                                                const int (&cl)[4],
                                                unsigned long long amask,
                                                double* ws) {
   switch (gs) {
-    case 4: spmm_zmf_unit<V, 4>(d, tau, zeta, cl, amask, ws); break;
-    case 3: spmm_zmf_unit<V, 3>(d, tau, zeta, cl, amask, ws); break;
-    case 2: spmm_zmf_unit<V, 2>(d, tau, zeta, cl, amask, ws); break;
-    default: spmm_zmf_unit<V, 1>(d, tau, zeta, cl, amask, ws); break;
+    case 4:
+      if constexpr (zmf_group_max(sizeof(T), V) == 4)
+        spmm_zmf_unit<T, V, 4>(d, tau, zeta, cl, amask, ws);
+      break;
+    case 3: spmm_zmf_unit<T, V, 3>(d, tau, zeta, cl, amask, ws); break;
+    case 2: spmm_zmf_unit<T, V, 2>(d, tau, zeta, cl, amask, ws); break;
+    default: spmm_zmf_unit<T, V, 1>(d, tau, zeta, cl, amask, ws); break;
   }
 }
 
-// VFIX: the common FP64 width of the launch's problems, or 0.
-template <int VFIX>
+// VFIX: the common width of the launch's problems in T, or 0.
+template <typename T, int VFIX>
 __global__ void PARO_STREAM_BOUNDS
 spmm_zmf_kernel(const Desc* __restrict__ D, int nprob, int par) {
   __shared__ double ws[4 * kNtMax];
@@ -1429,10 +1445,11 @@ spmm_zmf_kernel(const Desc* __restrict__ D, int nprob, int par) {
   const unsigned long long amask = active_mask(d.cs->act[par], d.ncols);
   if (nact == 0) return;  // queued after convergence
   const int lb = blockIdx.x - d.b0;
-  const int vw = VFIX ? VFIX : d.v64;
+  const int vw = VFIX ? VFIX : cm_width<T>(d);
   const unsigned long long cm = chunk_mask(amask, d.ncols / vw, vw);
   const int nac = __popcll(cm);
-  const int nag = (nac + 3) / 4;
+  const int gmax = zmf_group_max(sizeof(T), vw);
+  const int nag = (nac + gmax - 1) / gmax;
   const int x = lb % kXcd, l = lb / kXcd, gx = d.nb / kXcd;
   const int zr = d.zm / kXcd;
   const long long units = (long long)zr * d.zxy * nag;
@@ -1451,10 +1468,12 @@ spmm_zmf_kernel(const Desc* __restrict__ D, int nprob, int par) {
       cl[g] = rem ? __builtin_ctzll(rem) : 0;
       if (g < r1 - r0) rem &= rem - 1;
     }
-    if (vw == 2)
-      spmm_zmf_group<2>(d, tau, zeta, r1 - r0, cl, amask, ws);
+    if (sizeof(T) == 4 && vw == 4)
+      spmm_zmf_group<T, 4>(d, tau, zeta, r1 - r0, cl, amask, ws);
+    else if (vw == 2)
+      spmm_zmf_group<T, 2>(d, tau, zeta, r1 - r0, cl, amask, ws);
     else
-      spmm_zmf_group<1>(d, tau, zeta, r1 - r0, cl, amask, ws);
+      spmm_zmf_group<T, 1>(d, tau, zeta, r1 - r0, cl, amask, ws);
   }
 }
 
@@ -3431,12 +3450,11 @@ static void cg_spmm_launch(Launch& L, int par, hipStream_t s, Timing* t) {
       klaunch(t, PARO_ST_CG_SPMM, spmm_cm_kernel<T, W, false>,
               dim3(L.blocks), dim3(kBlock), 0, s, D, L.nprob, par);
   }
-  if constexpr (sizeof(T) == 8)
-    if (L.zm && L.zmf) {
-      klaunch(t, PARO_ST_CG_SPMM, spmm_zmf_kernel<W>, dim3(L.blocks),
-              dim3(kBlock), 0, s, D, L.nprob, par);
-      return;
-    }
+  if (L.zm && L.zmf) {
+    klaunch(t, PARO_ST_CG_SPMM, spmm_zmf_kernel<T, W>, dim3(L.blocks),
+            dim3(kBlock), 0, s, D, L.nprob, par);
+    return;
+  }
   if (L.zm) {
     switch (L.zmg) {
       case 1:

@@ -153,7 +153,8 @@ def test_matrix_free_spmm_is_bitwise_the_stored_one(ncols, precision):
     bit for bit and the same iteration counts.  7 columns run one column
     per chunk (groups of 4 and 3 chunks), 10 columns two per chunk (groups
     of 3 and 2); columns leave the groups as they converge.  In FP32-inner
-    mode only the FP64 refinement SpMM changes form."""
+    mode both the FP32 inner SpMM (coefficients rounded from FP64) and the
+    FP64 refinement SpMM change form."""
     ncs, lo, hi = NC, -8.0, 8.0
     X = inputs.vertex_coords(ncs, lo, hi)
     V = 0.5 * np.sum(X * X, axis=1) + np.random.default_rng(3).uniform(
