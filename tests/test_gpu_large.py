@@ -218,3 +218,43 @@ def test_matrix_free_steps_are_bitwise_the_stored_ones(N, m):
     assert np.array_equal(l_mf, l_st)
     assert np.array_equal(U_mf, U_st)
     assert np.all(np.isfinite(l_mf)) and l_mf[-1, 0] < l_mf[0, 0]
+
+
+def test_matrix_free_spmm_on_an_anisotropic_box():
+    """A 97 x 81 x 71-cell box of unequal spacings (96 x 80 x 70 interior
+    vertices, 2168 tiles: the z-marching SpMM) with a rough potential: the
+    matrix-free source solves against the oracle's own matrix (FP64
+    residual; CG iteration counts within one of the oracle's Jacobi-PCG)
+    and bitwise against the stored-coefficient form."""
+    ncs, lo, hi = (97, 81, 71), (-7.0, -5.0, -4.5), (6.0, 5.5, 4.0)
+    X = inputs.vertex_coords(ncs, lo, hi)
+    V = 0.5 * np.sum(X * X, axis=1) + np.random.default_rng(8).uniform(
+        -1.0, 1.0, X.shape[0])
+    H, M, s = gu.oracle_matrices(ncs, lo, hi, V)
+    A = (H - s * M).tocsr()
+    n = A.shape[0]
+    assert n == 96 * 80 * 70 and n > 2048 * 248
+    ncols = 3
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((n, ncols))
+    X0 = rng.standard_normal((n, ncols)) * 0.01
+    out = []
+    try:
+        for mf in (True, False):
+            pb.paro_set_matrix_free(mf)
+            gu.note(f"matrix-free {mf}: anisotropic box {ncs}")
+            prob = gu.assemble(ncs, lo, hi, V, N=ncols, pcg_rtol=1e-12)
+            Xd = gu.to_dev(X0)
+            its = pb.paro_pcg(prob, gu.to_dev(B), Xd)
+            out.append((its, Xd.cpu().numpy()))
+            del prob
+    finally:
+        pb.paro_set_matrix_free(True)
+    (its, Xm), (its_st, Xs) = out
+    assert its == its_st and np.array_equal(Xm, Xs)
+    res = np.linalg.norm(B - A @ Xm, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.max(res) <= 1.01e-12, res
+    dinv = 1.0 / A.diagonal()
+    for c in range(ncols):
+        _, k = oparo.jacobi_pcg(A, B[:, c], X0[:, c], dinv, 1e-12, 20000)
+        assert abs(its[c] - k) <= 1, (c, its[c], k)
