@@ -191,6 +191,7 @@ void carve(Problem& p, char* base, const Layout& L) {
   p.HU = (double*)at(L.HU);
   p.MU = (double*)at(L.MU);
   p.Xc = L.Xc ? (double*)at(L.Xc) : nullptr;
+  p.Xm = L.Xm ? (double*)at(L.Xm) : nullptr;
   p.R32 = L.R32 ? (float*)at(L.R32) : nullptr;
   p.P32 = L.P32 ? (float*)at(L.P32) : nullptr;
   p.Q32 = L.Q32 ? (float*)at(L.Q32) : nullptr;
@@ -296,6 +297,11 @@ void desc_init(Problem& p) {
     d.pqn = d.zm * d.zxy;
     d.spg = 1;
   }
+  // Mixed precision on a z-marching mesh: the FP64 refinement iterate and
+  // right-hand sides chunk-major, its residual by a z-march whose two
+  // partials per (column, segment) fit the p.q partial region.
+  d.Xm = p.Xm;
+  d.rcm = p.Xm && d.zm && 2 * (long long)d.pqn <= d.spt ? 1 : 0;
   d.part = p.part;
   d.gpart = p.gpart;
   d.Ah = p.Ah;
@@ -718,6 +724,8 @@ int solve_sources(Ctx& c, hipStream_t s, int64_t* refinements) {
     HIP_OR_FAIL(launch_refine_update(c.L, s, c.timing));
     if (refinements) ++*refinements;
   }
+  // Problems whose refinement iterate is chunk-major hand it to X.
+  if (c.L.zm) HIP_OR_FAIL(launch_cm_unpack(c.L, s, c.timing));
   return PARO_OK;
 }
 
@@ -1063,6 +1071,9 @@ Layout make_layout(int64_t n, int64_t nnz, int Nt, int precision,
   L.HU = take(sizeof(double) * blk);
   L.MU = take(sizeof(double) * blk);
   L.Xc = f32 ? 0 : take(sizeof(double) * blk);
+  // Mixed precision on a box: the chunk-major refinement iterate (used on
+  // meshes with the z-marching SpMM).
+  L.Xm = f32 && !ms && nvbox > 0 ? take(sizeof(double) * blk) : 0;
   L.R32 = f32 ? take(sizeof(float) * blk) : 0;
   L.P32 = f32 ? take(sizeof(float) * blk) : 0;
   L.Q32 = f32 ? take(sizeof(float) * blk) : 0;

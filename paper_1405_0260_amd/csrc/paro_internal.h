@@ -145,6 +145,10 @@ struct Desc {
   int hu_valid;           // host only: HU, MU hold H U, M U of the last
                           // rotation
   double* Xc;             // FP64 CG iterate, chunk-major (FP64 mode only)
+  double* Xm;             // mixed precision, z-marching meshes: the FP64
+  int rcm;                // refinement iterate chunk-major (rcm = 1; B is
+                          // then chunk-major too and X is written from Xm
+                          // after the solves), or null / 0
   float* R32;             // FP32 CG vectors, chunk-major (see cm_index)
   float* P32;
   float* Q32;
@@ -319,6 +323,7 @@ struct Problem {
   double* B;              // right-hand sides (refinement mode)
   double *HU, *MU;        // H U, M U of the last rotation
   double* Xc;             // chunk-major FP64 CG iterate (FP64 mode)
+  double* Xm = nullptr;   // chunk-major FP64 refinement iterate (mixed)
   float* R32;             // n x Nt blocks (FP32 inner solves, chunk-major)
   float* P32;
   float* Q32;
@@ -376,7 +381,7 @@ struct Layout {
   size_t rowptr, colidx, valA, valM, inc_ptr, inc, tets, Xv, Vv, dofmap,
       nbr;  // general meshes only (0 otherwise)
   size_t dinv, dinv32, diagA, diagM, diagA32, vbox, kconst;
-  size_t X, R, P, Q, B, HU, MU, Xc, R32, P32, Q32, X32;
+  size_t X, R, P, Q, B, HU, MU, Xc, Xm, R32, P32, Q32, X32;
   size_t part, cpart, gpart, Ah, Bh, C, theta, vmin, cs, si, cnt,
       flag;
   size_t desc, clus;

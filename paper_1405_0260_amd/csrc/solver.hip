@@ -1231,10 +1231,10 @@ spmm_zm_kernel(const Desc* __restrict__ D, int nprob, int par) {
 //   f(g, row, valid, mask, a, x)
 // with row the thread's row of plane z, valid false on the wavefront's halo
 // lanes and past the plane, mask the offsets whose neighbour lies in the
-// box, a the row's 15 FP64 coefficients of A_s (kuhn_row) and x[s][u] the
-// value of column u at neighbour s (0-weighted where the neighbour is
-// outside).
-template <typename T, int V, int G, class F>
+// box, a the row's 15 FP64 coefficients of A_s (kuhn_row; MF false: read
+// from the stored stencil, the same values) and x[s][u] the value of
+// column u at neighbour s (0-weighted where the neighbour is outside).
+template <typename T, int V, int G, bool MF = true, class F>
 __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
                                           const int (&cl)[4],
                                           const T* __restrict__ src, F&& f) {
@@ -1316,7 +1316,13 @@ __device__ __forceinline__ void zmf_march(const Desc& d, int tau, int zeta,
     if (z == 0) mask &= ~0xfu;                // dz = -1: slots 0-3
     if (z == mz - 1) mask &= ~(0xfu << 11);   // dz = +1: slots 11-14
     double a[kStencil];
-    kuhn_row(v, c0, vol60, mask, a);
+    if constexpr (MF) {
+      kuhn_row(v, c0, vol60, mask, a);
+    } else {
+#pragma unroll
+      for (int s = 0; s < kStencil; ++s)
+        a[s] = ldg(d.diagA + (size_t)s * n + row);
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       T x[kStencil][V];
@@ -1847,6 +1853,9 @@ cg_persistent_kernel(const Desc* __restrict__ D, int nprob, int iters) {
 template <int V>
 __device__ __forceinline__ void cm_unpack_body(const Desc& d, int vb,
                                                double* __restrict__ red) {
+  // FP64: the CG iterate; mixed (rcm): the refinement iterate.
+  const double* src = d.Xc ? d.Xc : (d.rcm ? d.Xm : nullptr);
+  if (!src) return;
   const Geo g = geo_of<V>(d, vb);
   if (g.lr >= g.tr) return;
   for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
@@ -1854,7 +1863,7 @@ __device__ __forceinline__ void cm_unpack_body(const Desc& d, int vb,
     const long long row = w.t * g.tr + g.lr;
     if (row >= d.n) continue;
     double x[V];
-    ldv<double, V>(d.Xc + cm_index(d.n, row, g.ch * V, V), x);
+    ldv<double, V>(src + cm_index(d.n, row, g.ch * V, V), x);
     stv<double, V>(d.X + (size_t)row * d.ncols + g.ch * V, x);
   }
 }
@@ -1946,6 +1955,12 @@ __device__ __forceinline__ void pcg_start_body(const Desc& d, int vb,
     } else {
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[1][v] += r[v] * p[v];
+    }
+    if (d.rcm) {  // mixed, chunk-major refinement: x0 and b
+      const size_t oc = cm_index(d.n, row, g.ch * V, V);
+      stv<double, V>(d.Xm + oc, u);
+      stv<double, V>(d.B + oc, b);
+      return;
     }
     if (d.X != U) stv<double, V>(d.X + o, u);
     if (d.Xc) {  // FP64 CG: its chunk-major start state
@@ -2077,6 +2092,7 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
 template <int V>
 __device__ __forceinline__ void refine_residual_body(const Desc& d, int vb,
     double* __restrict__ red) {
+  if (d.rcm) return;  // refine_residual_zm_kernel
   const Geo g = geo_of<V>(d, vb);
   ColState* cs = d.cs;
   const int ncols = d.ncols;
@@ -2136,6 +2152,151 @@ refine_residual_kernel(const Desc* __restrict__ D, int nprob) {
                  (refine_residual_body<VV>(d, vb, red)))
 }
 
+// The same residual on a z-marching mesh whose refinement iterate Xm and
+// right-hand sides B are chunk-major (rcm): a z-march over the chunks
+// with an outer-active column (compacted into balanced groups), the
+// coefficients formed from the potential (mf) or read from the stored
+// stencil (the same values), the products in spmm_dual_kernel's order, so
+// r64 is bitwise that of the row sweep.  Groups hold at most 3 chunks
+// (two sums per column: 4 would leave one wavefront per SIMD).  The
+// partials ||r64||^2 and the
+// FP32 r.z go per (column, plane range x tile) to the p.q partial region
+// (dead between CG passes): quantity a of column c, segment g at
+// pqp[a ncols pqn + c pqn + g].
+template <int V, int G, bool MF>
+__device__ __forceinline__ void refine_zm_unit(const Desc& d, int tau,
+                                               int zeta, const int (&cl)[4],
+                                               unsigned long long amask,
+                                               double* __restrict__ ws) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long n = d.n;
+  const int ncols = d.ncols;
+  double acc[G][2][V];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int u = 0; u < V; ++u) acc[g][a][u] = 0.0;
+  zmf_march<double, V, G, MF>(
+      d, tau, zeta, cl, d.Xm,
+      [&](int g, long long row, bool valid, unsigned,
+          const double (&a)[kStencil], const double (&x)[kStencil][V]) {
+        double ax[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) ax[u] = 0.0;
+#pragma unroll
+        for (int s = 0; s < kStencil; ++s)
+#pragma unroll
+          for (int u = 0; u < V; ++u) ax[u] = fma(a[s], x[s][u], ax[u]);
+        if (!valid) return;
+        double b[V];
+        ldv<double, V>(d.B + ((size_t)cl[g] * n + row) * V, b);
+        const double di = ldg(d.dinv + row);
+        float r32[V], z32[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const double r = b[u] - ax[u];
+          acc[g][0][u] += r * r;
+          r32[u] = (float)r;
+          z32[u] = 0.0f;
+          acc[g][1][u] += (double)r32[u] * (double)(float)(di * r);
+        }
+        const size_t o32 = cm_index(n, row, cl[g] * V, d.v32);
+        stv<float, V>(d.R32 + o32, r32);
+        stv<float, V>(d.X32 + o32, z32);
+      });
+  // Per (column, segment): wavefront, then the four wavefronts in order.
+  constexpr int kGroup = 64 / V;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double tot = wave_reduce_scatter<V>(acc[g][a]);
+      if ((lane & (kGroup - 1)) == 0)
+        ws[(a * 4 + wave) * ncols + cl[g] * V + lane / kGroup] = tot;
+    }
+  __syncthreads();
+  bool mine = false;
+#pragma unroll
+  for (int g = 0; g < G; ++g) mine = mine || tid / V == cl[g];
+  if (mine && tid < ncols && ((amask >> tid) & 1)) {
+    const size_t seg = (size_t)zeta * d.zxy + tau;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double* w = ws + a * 4 * ncols;
+      const double sum = ((w[tid] + w[ncols + tid]) + w[2 * ncols + tid]) +
+                         w[3 * ncols + tid];
+      stg(d.pqp + ((size_t)a * ncols + tid) * d.pqn + seg, sum);
+    }
+  }
+  __syncthreads();  // ws is reused by the next unit
+}
+
+template <int V, bool MF>
+__device__ __forceinline__ void refine_zm_group(const Desc& d, int tau,
+                                                int zeta, int gs,
+                                                const int (&cl)[4],
+                                                unsigned long long amask,
+                                                double* ws) {
+  switch (gs) {
+    case 3: refine_zm_unit<V, 3, MF>(d, tau, zeta, cl, amask, ws); break;
+    case 2: refine_zm_unit<V, 2, MF>(d, tau, zeta, cl, amask, ws); break;
+    default: refine_zm_unit<V, 1, MF>(d, tau, zeta, cl, amask, ws); break;
+  }
+}
+
+template <int VFIX>
+__global__ void PARO_STREAM_BOUNDS
+refine_residual_zm_kernel(const Desc* __restrict__ D, int nprob, int mf) {
+  __shared__ double ws[2 * 4 * kNtMax];
+  const Desc& d = D[owner(D, nprob, blockIdx.x, false)];
+  if (!d.rcm) return;  // refine_residual_kernel
+  ColState* cs = d.cs;
+  const int lb = blockIdx.x - d.b0;
+  if (lb == 0 && threadIdx.x == 0) {  // read only by the finalize kernel
+    cs->n_active[0] = 0;
+    cs->n_active[1] = 0;
+    cs->n_outer = 0;
+    cs->cg_mark = cs->cg_iters;
+  }
+  const unsigned long long amask = active_mask(cs->oact, d.ncols);
+  const int vw = VFIX ? VFIX : d.v64;
+  const unsigned long long cm = chunk_mask(amask, d.ncols / vw, vw);
+  const int nac = __popcll(cm);
+  if (nac == 0) return;
+  const int nag = (nac + 2) / 3;
+  const int x = lb % kXcd, l = lb / kXcd, gx = d.nb / kXcd;
+  const int zr = d.zm / kXcd;
+  const long long units = (long long)zr * d.zxy * nag;
+  for (long long k = l; k < units; k += gx) {
+    const long long rest = k / nag;
+    const int gi = (int)(k - rest * nag);
+    const int tau = (int)(rest % d.zxy);
+    const int zeta = x * zr + (int)(rest / d.zxy);
+    const int r0 = gi * nac / nag, r1 = (gi + 1) * nac / nag;
+    int cl[4];
+    unsigned long long rem = cm;
+    for (int r = 0; r < r0; ++r) rem &= rem - 1;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      cl[g] = rem ? __builtin_ctzll(rem) : 0;
+      if (g < r1 - r0) rem &= rem - 1;
+    }
+    if (vw == 2) {
+      if (mf)
+        refine_zm_group<2, true>(d, tau, zeta, r1 - r0, cl, amask, ws);
+      else
+        refine_zm_group<2, false>(d, tau, zeta, r1 - r0, cl, amask, ws);
+    } else {
+      if (mf)
+        refine_zm_group<1, true>(d, tau, zeta, r1 - r0, cl, amask, ws);
+      else
+        refine_zm_group<1, false>(d, tau, zeta, r1 - r0, cl, amask, ws);
+    }
+  }
+}
+
 // Outer (refinement) test per column and the inner threshold of the next
 // FP32 solve (grid: column x problem).
 __global__ void __launch_bounds__(kFinal)
@@ -2152,7 +2313,10 @@ refine_final_kernel(const Desc* __restrict__ D) {
     return;
   }
   double tot[2];
-  column_sums<2>(d.part, kPartStride, c, d.ns, tot);
+  if (d.rcm)
+    column_sums<2>(d.pqp, (size_t)d.ncols * d.pqn, c, d.pqn, tot);
+  else
+    column_sums<2>(d.part, kPartStride, c, d.ns, tot);
   if (threadIdx.x != 0) return;
   int a = 0;
   const double rr = tot[0], rtol = d.rtol, irt = d.inner_rtol;
@@ -2182,10 +2346,55 @@ refine_final_kernel(const Desc* __restrict__ D) {
   }
 }
 
+// Xm += d for a chunk-major refinement iterate (rcm): chunk by chunk
+// (those with a refining column; uniform), the problem's threads over the
+// chunk's rows, four rows per thread loaded before any is stored.
+template <int V>
+__device__ __forceinline__ void refine_update_cm(const Desc& d, int vb) {
+  const ColState* cs = d.cs;
+  const int cpr = d.ncols / V;
+  const long long n = d.n;
+  const long long stride = (long long)d.ns * kBlock;
+  constexpr int kTU = 4;
+  for (int ch = 0; ch < cpr; ++ch) {
+    bool a[V], any = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      a[v] = ldg(&cs->oact[ch * V + v]) != 0;
+      any = any || a[v];
+    }
+    if (!any) continue;
+    double* xm = d.Xm + (size_t)ch * n * V;
+    for (long long r0 = (long long)vb * kBlock + threadIdx.x; r0 < n;
+         r0 += kTU * stride) {
+      double x[kTU][V];
+      float dx[kTU][V];
+#pragma unroll
+      for (int k = 0; k < kTU; ++k) {
+        const long long row = min(r0 + k * stride, n - 1);
+        ldv<double, V>(xm + (size_t)row * V, x[k]);
+        ldv<float, V>(d.X32 + cm_index(n, row, ch * V, d.v32), dx[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kTU; ++k) {
+        const long long row = r0 + k * stride;
+        if (row >= n) continue;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[k][v] += a[v] ? (double)dx[k][v] : 0.0;
+        stv<double, V>(xm + (size_t)row * V, x[k]);
+      }
+    }
+  }
+}
+
 // X += d (FP32 correction) for columns that refined in this pass.
 template <int V>
 __device__ __forceinline__ void refine_update_body(const Desc& d, int vb,
     double* __restrict__ red) {
+  if (d.rcm) {
+    refine_update_cm<V>(d, vb);
+    return;
+  }
   const Geo g = geo_of<V>(d, vb);
   const ColState* cs = d.cs;
   const int ncols = d.ncols;
@@ -2972,7 +3181,22 @@ __device__ __forceinline__ void start_emit(const Desc& d, long long row,
       stv<double, VS>(d.P + oc, e);
     }
   }
-  if (d.B) stv<double, VR>(d.B + o, b);
+  if (d.rcm) {  // mixed, chunk-major refinement: x0 = U and b
+#pragma unroll
+    for (int j = 0; j < VR; j += VS) {
+      const size_t oc = cm_index(d.n, row, col0 + j, VS);
+      double a[VS], c[VS];
+#pragma unroll
+      for (int v = 0; v < VS; ++v) {
+        a[v] = u[j + v];
+        c[v] = b[j + v];
+      }
+      stv<double, VS>(d.Xm + oc, a);
+      stv<double, VS>(d.B + oc, c);
+    }
+  } else if (d.B) {
+    stv<double, VR>(d.B + o, b);
+  }
 }
 
 // One virtual block of the rotation with VR columns per thread (4 where
@@ -3598,6 +3822,9 @@ hipError_t launch_refine_residual(Launch& L, hipStream_t s, Timing* t) {
   PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_kernel,
                   dim3(L.blocks), dim3(kBlock),
                   weights_bytes(L.tr64, sizeof(double), 1), s, L.d, L.nprob);
+  if (L.zm)  // problems with a chunk-major refinement iterate
+    PARO_LAUNCH_W64(L.v64u, t, PARO_ST_REFINE, refine_residual_zm_kernel,
+                    dim3(L.blocks), dim3(kBlock), 0, s, L.d, L.nprob, L.zmf);
   klaunch(t, PARO_ST_REFINE, refine_final_kernel, dim3(L.maxcols, L.nprob),
           dim3(kFinal), 0, s, L.d);
   return hipGetLastError();
