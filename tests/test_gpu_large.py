@@ -258,3 +258,27 @@ def test_matrix_free_spmm_on_an_anisotropic_box():
     for c in range(ncols):
         _, k = oparo.jacobi_pcg(A, B[:, c], X0[:, c], dinv, 1e-12, 20000)
         assert abs(its[c] - k) <= 1, (c, its[c], k)
+
+
+def test_mixed_solve_with_chunk_major_refinement_matches_fp64():
+    """A whole mixed-precision solve on the 81^3 harmonic box, where the
+    FP64 refinement iterate is chunk-major (the emitting rotation writes
+    x0 and b that way, the residual is a z-march, X is unpacked after the
+    solves): the same Ritz values as the plain FP64 solve."""
+    w = inputs.harmonic(nc=NC, N=4, m=inputs.harmonic_buffer(4),
+                        max_steps=400)
+    U0 = w.U0()
+    out = {}
+    for prec in (pb.PARO_FP64, pb.PARO_FP32_INNER):
+        gu.note(f"81^3 harmonic solve, precision {prec}")
+        prob = gu.workload_problem(w, precision=prec)
+        lam, U, rep = gu.solve(prob, U0)
+        assert rep.status == 0, rep.as_dict()
+        assert np.all(np.isfinite(U))
+        out[prec] = lam[:w.N]
+    rel = np.abs(out[pb.PARO_FP32_INNER] - out[pb.PARO_FP64]) / np.abs(
+        out[pb.PARO_FP64])
+    assert np.max(rel) <= 1e-10, rel
+    # The continuum values 3/2 and 5/2 within the mesh's O(h^2) error.
+    assert abs(out[pb.PARO_FP64][0] - 1.5) < 0.05
+    assert np.all(np.abs(out[pb.PARO_FP64][1:] - 2.5) < 0.1)
