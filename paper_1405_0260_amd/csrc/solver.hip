@@ -143,6 +143,35 @@ __device__ void block_partials(const double (&acc)[NA][V], int ncols, int cpr,
   __syncthreads();
 }
 
+// block_partials for a thread that holds the values of tile row lr and
+// chunk ch (slot lr cpr + ch, whatever its thread index; slot < 0: none):
+// the same sums in the same order.
+template <int NA, int V>
+__device__ void block_partials_slot(const double (&acc)[NA][V], int slot,
+                                    int ncols, int cpr, int tr, int vb,
+                                    int ns, double* __restrict__ part,
+                                    double* __restrict__ red) {
+  const int tid = threadIdx.x;
+  if (slot >= 0)
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        red[(a * kBlock + slot) * V + v] = acc[a][v];
+  __syncthreads();
+  if (tid < ncols) {
+    const int ch = tid / V, v = tid % V;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const double* ra = red + a * kBlock * V;
+      double s = 0.0;
+      for (int lr = 0; lr < tr; ++lr) s += ra[(lr * cpr + ch) * V + v];
+      stg(part + a * kPartStride + (size_t)tid * ns + vb, s);
+    }
+  }
+  __syncthreads();
+}
+
 // Finalisers run one wavefront per (column, problem).
 constexpr int kFinal = 64;
 
@@ -3206,6 +3235,12 @@ template <int VR>
 __device__ __forceinline__ void rotate_rows(const Desc& d, int vb) {
   const Geo g = geo_of<VR>(d, vb);
   const int ncols = d.ncols;
+  // Thread (tile row lr, chunk ch) with the row fastest: a wavefront's
+  // chunk-major stores of the emitted start run along contiguous rows
+  // (the row-major U store is the one that scatters).
+  const int lr = threadIdx.x % g.tr;
+  const int ch = threadIdx.x / g.tr < g.cpr ? threadIdx.x / g.tr : g.cpr;
+  const bool own = ch < g.cpr;
   const bool emit = d.emit != 0;
   const double* W = d.X;
   const double* HW = d.HU;
@@ -3229,7 +3264,7 @@ __device__ __forceinline__ void rotate_rows(const Desc& d, int vb) {
   double th[VR], sh[VR];
 #pragma unroll
   for (int v = 0; v < VR; ++v) {
-    th[v] = d.theta[min(g.ch * VR + v, ncols - 1)];
+    th[v] = d.theta[min(min(ch, g.cpr - 1) * VR + v, ncols - 1)];
     sh[v] = th[v] - d.sigma;
   }
   double acc[5][VR];
@@ -3275,28 +3310,28 @@ __device__ __forceinline__ void rotate_rows(const Desc& d, int vb) {
     }
     __syncthreads();
     if (w.t + w.step < w.end) fetch(w.t + w.step);
-    if (g.lr < g.tr && g.lr < rows) {
+    if (own && lr < rows) {
       double u[VR], hu[VR], mu[VR];
 #pragma unroll
       for (int v = 0; v < VR; ++v) u[v] = hu[v] = mu[v] = 0.0;
-      const double* wr = sW + g.lr * ld;
-      const double* hr = sH + g.lr * ld;
-      const double* mr = sM + g.lr * ld;
+      const double* wr = sW + lr * ld;
+      const double* hr = sH + lr * ld;
+      const double* mr = sM + lr * ld;
       for (int k = 0; k < ncols; ++k) {
         const double wk = wr[k], hk = hr[k], mk = mr[k];
 #pragma unroll
         for (int v = 0; v < VR; ++v) {
-          const double c = sC[k * ncols + g.ch * VR + v];
+          const double c = sC[k * ncols + ch * VR + v];
           u[v] = fma(wk, c, u[v]);
           hu[v] = fma(hk, c, hu[v]);
           mu[v] = fma(mk, c, mu[v]);
         }
       }
-      const long long row = r0 + g.lr;
-      const size_t o = base + (size_t)g.lr * ncols + g.ch * VR;
+      const long long row = r0 + lr;
+      const size_t o = base + (size_t)lr * ncols + ch * VR;
       stv<double, VR>(U + o, u);
       if (emit) {
-        start_emit<VR>(d, row, g.ch * VR, u, hu, mu, sh, ldg(d.dinv + row),
+        start_emit<VR>(d, row, ch * VR, u, hu, mu, sh, ldg(d.dinv + row),
                        acc);
       } else {
         stv<double, VR>(d.HU + o, hu);  // for the next start
@@ -3320,10 +3355,12 @@ __device__ __forceinline__ void rotate_rows(const Desc& d, int vb) {
     st[1][v] = acc[3][v];
     st[2][v] = acc[4][v];
   }
-  block_partials<VR, 2>(rot, ncols, g.cpr, g.tr, g.lb, g.nb, d.part, red);
+  const int slot = own ? lr * g.cpr + ch : -1;
+  block_partials_slot<2, VR>(rot, slot, ncols, g.cpr, g.tr, g.lb, g.nb,
+                             d.part, red);
   if (emit)
-    block_partials<VR, 3>(st, ncols, g.cpr, g.tr, g.lb, g.nb,
-                          d.part + 2 * kPartStride, red);
+    block_partials_slot<3, VR>(st, slot, ncols, g.cpr, g.tr, g.lb, g.nb,
+                               d.part + 2 * kPartStride, red);
 }
 
 template <int V>
