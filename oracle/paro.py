@@ -25,7 +25,10 @@ design notes):
     lambda^(0), which the paper leaves to the user.
   * Source solver.  The paper does not name one: each source problem is
     solved by Jacobi-preconditioned conjugate gradients, started from
-    x0 = u_i^(n), until ||r||_2 <= rtol ||b||_2.
+    x0 = u_i^(n), until ||r||_2 <= rtol ||b||_2, or, with reduce > 0, until
+    ||r||_2 <= max(rtol ||b||_2, reduce ||r_0||_2) (an inexact Step 3: the
+    start's residual b - A u_i is minus the pair's eigen-residual
+    H u_i - lambda_i M u_i, and the solve shrinks it by the factor reduce).
   * Stopping.  The paper runs a fixed number of iterations.  Here the loop
     stops after max_steps, or once every requested pair has a relative
     eigenvalue change <= lambda_tol and relative residual <= resid_tol.
@@ -58,20 +61,22 @@ def shift_from_potential(V_nodal: np.ndarray) -> float:
     return 0.0 if vmin >= 0.0 else vmin - 1.0
 
 
-def jacobi_pcg(A, b, x0, dinv, rtol, maxit):
+def jacobi_pcg(A, b, x0, dinv, rtol, maxit, reduce=0.0):
     """Jacobi-preconditioned CG for A x = b (one source problem, Step 3).
 
-    Stops when ||r||_2 <= rtol ||b||_2, checked before every iteration (so
-    zero iterations are taken if x0 already satisfies it).  Returns the
-    solution and the number of iterations."""
+    Stops when ||r||_2 <= max(rtol ||b||_2, reduce ||r_0||_2), r_0 = b - A x0,
+    checked before every iteration (so zero iterations are taken if x0
+    already satisfies it).  Returns the solution and the number of
+    iterations."""
     x = np.array(x0, dtype=np.float64, copy=True)
     r = b - A @ x
     z = dinv * r
     p = z.copy()
     rz = float(r @ z)
     bnorm = float(np.linalg.norm(b))
+    stop = max(rtol * bnorm, reduce * float(np.linalg.norm(r)))
     it = 0
-    while float(np.linalg.norm(r)) > rtol * bnorm:
+    while float(np.linalg.norm(r)) > stop:
         if it >= maxit:
             raise NoConvergence(f"PCG: {it} iterations, "
                                 f"|r|/|b| = {np.linalg.norm(r) / bnorm:.3e}")
@@ -167,23 +172,26 @@ def _pool_start():
 def _pool_solve(job):
     b, x0 = job
     op = _POOL_OPERATOR
-    return jacobi_pcg(op["A"], b, x0, op["dinv"], op["rtol"], op["maxit"])
+    return jacobi_pcg(op["A"], b, x0, op["dinv"], op["rtol"], op["maxit"],
+                      op["reduce"])
 
 
 def paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit, clusters=None,
-              pool=None):
+              pool=None, reduce=0.0):
     """One ParO iteration (Steps 3 and 4) from (lam, U); returns the new
     pairs and the PCG iteration count of each source problem.  With
     `clusters` (sizes of consecutive column groups) Step 4 projects each
     cluster separately (rayleigh_ritz_clustered).  With `pool` (from
     paro_solve(workers=k)) the independent source problems of Step 3 are
     spread over worker processes, which the paper names as the method's
-    parallelism; each is the same jacobi_pcg call as in the serial loop."""
+    parallelism; each is the same jacobi_pcg call as in the serial loop.
+    `reduce`: the inexact stopping test of jacobi_pcg."""
     MU = M @ U
     W = np.empty_like(U)
     jobs = [((lam[i] - sigma) * MU[:, i], U[:, i]) for i in range(U.shape[1])]
     if pool is None:                         # Step 3: independent problems
-        out = [jacobi_pcg(A, b, x0, dinv, rtol, maxit) for b, x0 in jobs]
+        out = [jacobi_pcg(A, b, x0, dinv, rtol, maxit, reduce)
+               for b, x0 in jobs]
     else:
         out = pool.map(_pool_solve, jobs, chunksize=1)
     its = []
@@ -199,14 +207,16 @@ def paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit, clusters=None,
 
 def paro_solve(H, M, U0, N, sigma: Optional[float] = None, V_nodal=None,
                max_steps=100, lambda_tol=0.0, resid_tol=0.0, rtol=1e-10,
-               maxit=None, callback=None, workers=None) -> ParOResult:
+               maxit=None, callback=None, workers=None,
+               reduce=0.0) -> ParOResult:
     """Run ParO from the orbitals U0 (n x (N + m)).
 
     sigma: the shift (None -> shift_from_potential(V_nodal)).
     Stops after max_steps, or earlier when lambda_tol > 0 and every
     requested pair satisfies both tolerances.  workers: number of processes
     for the source problems of Step 3 (None: solved one after another);
-    the iterates are the same either way."""
+    the iterates are the same either way.  reduce: the source solves'
+    inexact stopping test (jacobi_pcg)."""
     if sigma is None:
         sigma = shift_from_potential(V_nodal)
     n = H.shape[0]
@@ -220,14 +230,15 @@ def paro_solve(H, M, U0, N, sigma: Optional[float] = None, V_nodal=None,
     pcg_hist = []
     pool = None
     if workers:
-        _POOL_OPERATOR.update(A=A, dinv=dinv, rtol=rtol, maxit=maxit)
+        _POOL_OPERATOR.update(A=A, dinv=dinv, rtol=rtol, maxit=maxit,
+                              reduce=reduce)
         pool = multiprocessing.get_context("fork").Pool(workers,
                                                         _pool_start)
     try:
         lam, U, steps, converged = _iterate(
             H, M, A, dinv, lam, U, sigma, rtol, maxit, N, max_steps,
             lambda_tol, resid_tol, callback, pool, lam_hist, res_hist,
-            pcg_hist)
+            pcg_hist, reduce)
     finally:
         if pool is not None:
             pool.close()
@@ -239,13 +250,13 @@ def paro_solve(H, M, U0, N, sigma: Optional[float] = None, V_nodal=None,
 
 def _iterate(H, M, A, dinv, lam, U, sigma, rtol, maxit, N, max_steps,
              lambda_tol, resid_tol, callback, pool, lam_hist, res_hist,
-             pcg_hist):
+             pcg_hist, reduce=0.0):
     """The ParO loop of paro_solve (Steps 3-4 repeated, stopping test)."""
     converged = False
     steps = 0
     for step in range(max_steps):
         lam_new, U, its = paro_step(H, M, A, dinv, lam, U, sigma, rtol, maxit,
-                                    pool=pool)
+                                    pool=pool, reduce=reduce)
         dl = np.abs(lam_new - lam) / scale_floor(lam_new)
         lam = lam_new
         rho = residuals(H, M, lam, U)

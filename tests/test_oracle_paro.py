@@ -51,6 +51,54 @@ def test_pcg_zero_iterations_when_start_is_exact():
     assert it == 0 and np.array_equal(x, x0)
 
 
+@pytest.mark.parametrize("eta", [1e-1, 1e-3])
+def test_pcg_reduce_stops_at_the_first_iterate_below_max_threshold(eta):
+    """The inexact stopping test: ||r|| <= max(rtol ||b||, eta ||r0||).
+    The returned iterate meets it, one iteration fewer does not (the cap
+    one below the count raises), and the same threshold given as rtol
+    alone (eta ||r0|| / ||b||) takes the same iterations to the same x."""
+    w, H, M = problem("sc", 9)
+    s = paro.shift_from_potential(w.V)
+    A = (H - s * M).tocsr()
+    dinv = 1.0 / A.diagonal()
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(A.shape[0])
+    x0 = rng.standard_normal(A.shape[0])
+    r0 = np.linalg.norm(b - A @ x0)
+    x, it = paro.jacobi_pcg(A, b, x0, dinv, 1e-14, 10000, reduce=eta)
+    assert it >= 2
+    assert np.linalg.norm(b - A @ x) <= eta * r0 * (1 + 1e-9)
+    with pytest.raises(paro.NoConvergence):
+        paro.jacobi_pcg(A, b, x0, dinv, 1e-14, it - 1, reduce=eta)
+    x2, it2 = paro.jacobi_pcg(A, b, x0, dinv,
+                              eta * r0 / np.linalg.norm(b), 10000)
+    assert it2 == it and np.allclose(x2, x, rtol=0, atol=1e-12)
+    # rtol above eta ||r0|| / ||b|| governs instead.
+    loose = 10 * eta * r0 / np.linalg.norm(b)
+    x3, it3 = paro.jacobi_pcg(A, b, x0, dinv, loose, 10000, reduce=eta)
+    assert it3 <= it
+    assert np.linalg.norm(b - A @ x3) <= loose * np.linalg.norm(b) * (1 + 1e-9)
+
+
+def test_paro_with_inexact_source_solves_converges_to_dense_pairs():
+    """Algorithm A.1 with Step 3 solved inexactly (each source solve
+    shrinks its start's residual, the pair's eigen-residual, by 1e-2):
+    the fixed point is unchanged, so the loop still reaches the lowest
+    eigenpairs of H u = lambda M u from a library eigensolver."""
+    w, H, M = problem("sc", 8)
+    ref, Uref = reference.dense_lowest(H, M, w.Nt + 1)
+    r = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=3000,
+                        lambda_tol=1e-13, resid_tol=1e-10, rtol=1e-12,
+                        reduce=1e-2)
+    assert r.converged
+    assert rel_lambda_err(r.lam, ref[:w.N]) < 1e-10
+    assert subspace_sine(M, r.U, Uref[:, :w.N]) < 1e-7
+    # Fewer CG iterations than exact-enough solves over the same steps.
+    exact = paro.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V,
+                            max_steps=r.steps, rtol=1e-12)
+    assert sum(map(sum, r.pcg_iters)) < sum(map(sum, exact.pcg_iters))
+
+
 def test_pcg_reports_breakdown_on_indefinite_matrix():
     A = sp.diags([-1.0, -2.0, -3.0]).tocsr()
     with pytest.raises(paro.NotSPD):
