@@ -37,9 +37,14 @@ GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 # residual its source solve left behind (an inner tolerance equal to
 # RESID_TOL stalls the outer test), and a tighter one only adds CG
 # iterations (1e-10 takes the 96^3 solve the same 492 ParO steps to the
-# same eigenvalues, with 44 % more CG iterations).
+# same eigenvalues, with 44 % more CG iterations).  Each source solve also
+# stops once it has shrunk its warm start's residual (the pair's
+# eigen-residual) by PCG_REDUCE: a ParO step reduces that residual by a
+# few per cent at this workload's rate, so solving far beyond it is
+# wasted; at 1e-2 the outer iteration takes 495 steps instead of 492.
 LAMBDA_TOL, RESID_TOL = 1e-11, 1e-7
 PCG_RTOL = 1e-8  # RESID_TOL / 10
+PCG_REDUCE = 1e-2
 GOLDEN = os.path.join(GOLDEN_DIR, "linear_96c_lowest.txt")
 GOLDEN64 = os.path.join(GOLDEN_DIR, "softcoulomb_64c_lowest.txt")
 GOLDEN_BATCH = os.path.join(GOLDEN_DIR, "batch64_sample_lowest.txt")
@@ -252,7 +257,8 @@ class Solver:
         self.U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=dev)
         self.opts = pb.default_opts(
             N=w.N, m=w.m, max_steps=4000, lambda_tol=LAMBDA_TOL,
-            resid_tol=RESID_TOL, pcg_rtol=PCG_RTOL, inner_rtol=inner_rtol,
+            resid_tol=RESID_TOL, pcg_rtol=PCG_RTOL, pcg_reduce=PCG_REDUCE,
+            inner_rtol=inner_rtol,
             precision=pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64)
         _, self.nnz, nbytes = pb.paro_query(self.box, self.opts)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -483,6 +489,7 @@ def main():
                    "N": w.N, "m": w.m, "precision": prec,
                    "inner_rtol": args.inner_rtol, "lambda_tol": LAMBDA_TOL,
                    "resid_tol": RESID_TOL, "pcg_rtol": PCG_RTOL,
+                   "pcg_reduce": PCG_REDUCE,
                    "parallelism": "single-gpu"},
         "latency_ms": {"p50": 1e3 * float(np.percentile(times, 50)),
                        "p99": 1e3 * float(np.percentile(times, 99))},
@@ -520,7 +527,8 @@ def batch_bench(args, prec):
     precision = pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64
     opts = [pb.default_opts(N=x.N, m=x.m, max_steps=x.max_steps,
                             lambda_tol=LAMBDA_TOL, resid_tol=RESID_TOL,
-                            pcg_rtol=PCG_RTOL, inner_rtol=args.inner_rtol,
+                            pcg_rtol=PCG_RTOL, pcg_reduce=PCG_REDUCE,
+                            inner_rtol=args.inner_rtol,
                             precision=precision)
             for x in ws]
     boxes = [pb.Box.cube(x.nc, x.lo, x.hi) for x in ws]
@@ -622,7 +630,8 @@ def serve_bench(args, prec):
     precision = pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64
     opts = [pb.default_opts(N=x.N, m=x.m, max_steps=x.max_steps,
                             lambda_tol=LAMBDA_TOL, resid_tol=RESID_TOL,
-                            pcg_rtol=PCG_RTOL, inner_rtol=args.inner_rtol,
+                            pcg_rtol=PCG_RTOL, pcg_reduce=PCG_REDUCE,
+                            inner_rtol=args.inner_rtol,
                             precision=precision)
             for x in reqs]
     boxes = [pb.Box.cube(x.nc, x.lo, x.hi) for x in reqs]
@@ -729,7 +738,7 @@ def nonlocal_bench(args):
     U = torch.zeros(w.n_dof, w.Nt, dtype=torch.float64, device=dev)
     o = pb.default_opts(N=w.N, m=w.m, max_steps=2000, lambda_tol=LAMBDA_TOL,
                         resid_tol=RESID_TOL, pcg_rtol=PCG_RTOL,
-                        precision=pb.PARO_FP64)
+                        pcg_reduce=PCG_REDUCE, precision=pb.PARO_FP64)
     out = {}
     for name, nl in (("local", False), ("nonlocal", True)):
         times = []
@@ -773,6 +782,7 @@ def ks_bench(args, prec):
     precision = pb.PARO_FP32_INNER if prec == "mixed" else pb.PARO_FP64
     o = pb.default_opts(N=w.N, m=w.m, max_steps=args.ks_iters,
                         lambda_tol=1e-10, resid_tol=1e-6, pcg_rtol=1e-7,
+                        pcg_reduce=PCG_REDUCE,
                         inner_rtol=args.inner_rtol, precision=precision)
     box = pb.Box.cube(w.nc, w.lo, w.hi)
     V = torch.from_numpy(w.V).to(dev)
@@ -891,7 +901,8 @@ def local_adaptive_bench(args, golden):
     w = inputs.kohn_sham_96(nc=args.local_nc)
     box = pb.Box.cube(w.nc, w.lo, w.hi)
     opts = pb.default_opts(N=w.N, m=w.m, max_steps=4000, lambda_tol=LAMBDA_TOL,
-                           resid_tol=RESID_TOL, pcg_rtol=PCG_RTOL)
+                           resid_tol=RESID_TOL, pcg_rtol=PCG_RTOL,
+                           pcg_reduce=PCG_REDUCE)
 
     def clock():
         torch.cuda.synchronize()
@@ -1044,7 +1055,8 @@ def cpu_baseline(w, workers=None):
     t_start = time.perf_counter() - t0
     t0 = time.perf_counter()
     r = oparo.paro_solve(H, M, w.U0(), w.N, sigma=s, max_steps=1,
-                         rtol=PCG_RTOL, maxit=maxit, workers=workers)
+                         rtol=PCG_RTOL, maxit=maxit, workers=workers,
+                         reduce=PCG_REDUCE)
     step_all = time.perf_counter() - t0 - t_start
     its_all = r.pcg_iters[0]
     # One thread.
@@ -1059,7 +1071,7 @@ def cpu_baseline(w, workers=None):
         while k < w.Nt and (time.perf_counter() - t0 < 15.0 or k < 1):
             b = (lam[k] - s) * MU[:, k]
             W[:, k], _ = oparo.jacobi_pcg(A, b, U[:, k], dinv, PCG_RTOL,
-                                                maxit)
+                                                maxit, reduce=PCG_REDUCE)
             k += 1
         t_solve = (time.perf_counter() - t0) / k
         t1 = time.perf_counter()

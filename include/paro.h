@@ -79,6 +79,13 @@ typedef struct paro_opts {
   double inner_rtol;      /* FP32 inner solves: residual reduction per pass
                              (a pass stops at 0.8 pcg_rtol ||b|| at the
                              lowest; the FP64 residual decides)          */
+  double pcg_reduce;      /* source solves also stop once ||b - A w|| <=
+                             pcg_reduce ||b - A x0||, x0 = u_i the warm
+                             start (Algorithm A.1 Step 3 solved inexactly:
+                             x0's residual is the pair's eigen-residual
+                             H u_i - lambda_i M u_i, so the solve shrinks
+                             it by a fixed factor); in [0, 1), 0 (the
+                             default) leaves only pcg_rtol               */
 } paro_opts_t;
 
 typedef struct paro_report {

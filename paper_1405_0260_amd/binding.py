@@ -41,7 +41,8 @@ class Opts(ctypes.Structure):
                 ("pcg_maxit", c_i32), ("precision", c_i32),
                 ("sigma_mode", c_i32), ("sigma", c_dbl),
                 ("lambda_tol", c_dbl), ("resid_tol", c_dbl),
-                ("pcg_rtol", c_dbl), ("inner_rtol", c_dbl)]
+                ("pcg_rtol", c_dbl), ("inner_rtol", c_dbl),
+                ("pcg_reduce", c_dbl)]
 
 
 class Report(ctypes.Structure):

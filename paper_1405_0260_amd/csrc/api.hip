@@ -166,6 +166,8 @@ int check_opts(const paro_opts_t* o, int64_t n) {
   if (o->pcg_maxit < 1) return fail(PARO_EINVAL, "pcg_maxit must be >= 1");
   if (!(o->pcg_rtol > 0.0) || !(o->pcg_rtol < 1.0))
     return fail(PARO_EINVAL, "pcg_rtol must lie in (0, 1)");
+  if (!(o->pcg_reduce >= 0.0) || !(o->pcg_reduce < 1.0))
+    return fail(PARO_EINVAL, "pcg_reduce must lie in [0, 1)");
   if (o->precision == PARO_FP32_INNER &&
       (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)))
     return fail(PARO_EINVAL, "inner_rtol must lie in (0, 1)");
@@ -258,6 +260,10 @@ void desc_init(Problem& p) {
   d.sigma = p.sigma;
   d.rtol = p.opts.pcg_rtol;
   d.inner_rtol = p.opts.inner_rtol;
+  {
+    const double q = p.opts.pcg_reduce / p.opts.pcg_rtol;
+    d.reduce2 = q * q;
+  }
   d.dinv = p.dinv;
   d.dinv32 = p.dinv32;
   d.diagA = p.diagA;

@@ -110,6 +110,7 @@ struct Desc {
   int ns, gns;            // reduction segments (virtual blocks)
   int v64, v32;           // columns per thread
   double sigma, rtol, inner_rtol;
+  double reduce2;         // (pcg_reduce / rtol)^2: 0, or the floor of ||b||^2
   double s1;              // component SpMM: Y1 = A X + s1 M X
   const double* dinv;
   const float* dinv32;

@@ -2067,7 +2067,11 @@ pcg_start_kernel(const Desc* __restrict__ D, int nprob) {
 }
 
 // Per-column start state: ||b||^2, r.z, ||r||^2, the stopping threshold
-// and the first active set (grid: column x problem).
+// and the first active set (grid: column x problem).  Every stopping test
+// of the solve (the CG's, and the refinement's in mixed precision) is
+// rtol^2 bb; with pcg_reduce the stored bb is raised to at least
+// (pcg_reduce / rtol)^2 ||r0||^2, so the threshold becomes
+// max(rtol ||b||, pcg_reduce ||r0||) in all of them.
 __global__ void __launch_bounds__(kFinal)
 pcg_start_final_kernel(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.y];
@@ -2078,7 +2082,11 @@ pcg_start_final_kernel(const Desc* __restrict__ D) {
   column_sums<3>(d.part + (size_t)d.start_part * kPartStride, kPartStride, c,
                  d.ns, tot);
   if (threadIdx.x != 0) return;
-  const double bb = tot[0], rz = tot[1], rr = tot[2];
+  const double rz = tot[1], rr = tot[2];
+  // (A comparison, not fmax: a NaN ||b||^2 must stay NaN for the check
+  // below.)
+  const double bfl = d.reduce2 * rr;
+  const double bb = tot[0] < bfl ? bfl : tot[0];
   const double rtol = d.rtol;
   cs->bb[c] = bb;
   cs->rz[c] = rz;

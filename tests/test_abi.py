@@ -58,6 +58,7 @@ def test_default_options(lib):
     o = pb.paro_default_opts()
     assert (o.N, o.m, o.precision, o.sigma_mode) == (1, 0, pb.PARO_FP64, 0)
     assert o.pcg_rtol == 1e-10 and o.lambda_tol == 1e-12
+    assert o.pcg_reduce == 0.0
     assert o.max_steps == 200 and o.pcg_maxit == 10000
 
 
@@ -77,6 +78,8 @@ def test_workspace_grows_with_columns_and_precision(lib):
     (pb.Box.cube(8, 0, 1), dict(N=0), pb.PARO_EINVAL),
     (pb.Box.cube(8, 1, 0), dict(N=1), pb.PARO_EINVAL),
     (pb.Box.cube(8, 0, 1), dict(N=1, pcg_rtol=0.0), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 0, 1), dict(N=1, pcg_reduce=1.0), pb.PARO_EINVAL),
+    (pb.Box.cube(8, 0, 1), dict(N=1, pcg_reduce=-0.1), pb.PARO_EINVAL),
 ])
 def test_query_rejects_bad_arguments(lib, box, opts, code):
     with pytest.raises(pb.ParoError) as e:

@@ -76,6 +76,56 @@ def test_harmonic_24_converges_to_1e8():
     gu.note(f"steps {rep.steps} lambda {lam[:4]}")
 
 
+def test_inexact_source_solves_match_oracle_iterates():
+    """pcg_reduce (Step 3 solved inexactly: each source solve stops once it
+    has shrunk its warm start's residual, the pair's eigen-residual, by
+    1e-2): the 24^3 harmonic run's 30 FP64 steps against the oracle's with
+    the same stopping test, step by step (Ritz values, and the largest CG
+    count of each step within one of the oracle's)."""
+    w = inputs.harmonic_24()
+    eta = 1e-2
+    prob = gu.workload_problem(w, pcg_rtol=1e-12, pcg_reduce=eta)
+    hist, U, reps = run_steps(prob, w.U0(), 30)
+    H, M, s = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+    r = oparo.paro_solve(H, M, w.U0(), w.N, V_nodal=w.V, max_steps=30,
+                         rtol=1e-12, reduce=eta)
+    L = np.array(r.lam_history)
+    errs = [rel_lambda_err(hist[k], L[k]) for k in range(31)]
+    its = [max(x) for x in r.pcg_iters]
+    gu.note(f"inexact steps vs oracle: lambda rel {max(errs):.2e}; CG per "
+            f"step gpu {[x.pcg_iters for x in reps][:6]} oracle {its[:6]}")
+    assert max(errs) < 1e-9
+    for k, rep in enumerate(reps):
+        assert abs(rep.pcg_iters - its[k]) <= 1, (k, rep.pcg_iters, its[k])
+    assert m_orthonormality_error(M, U) < 1e-12
+    assert subspace_sine(M, U, r.U_all) < 1e-7
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_inexact_source_solves_converge_to_dense_pairs(precision):
+    """With pcg_reduce the fixed point is unchanged: a solve of the 12^3
+    soft-Coulomb case (N = 6, m = 4) still reaches the lowest eigenpairs
+    of the dense pencil, in both precisions (mixed: the FP64 refinement
+    stops at the same max(rtol ||b||, pcg_reduce ||r0||))."""
+    w = make_case(kind="sc", nc=12, N=6, m=4)
+    H, M, s = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+    prob = gu.workload_problem(w, precision=precision, max_steps=3000,
+                               lambda_tol=1e-13, resid_tol=1e-9,
+                               pcg_rtol=1e-10, pcg_reduce=1e-2)
+    lam, U, rep = gu.solve(prob, w.U0())
+    assert rep.status == 0, rep.as_dict()
+    ref, Uref = reference.dense_lowest(H, M, w.Nt + 1)
+    assert rel_lambda_err(lam[:w.N], ref[:w.N]) < 1e-8
+    assert subspace_sine(M, U[:, :w.N], Uref[:, :w.N]) < 1e-6
+    exact = gu.workload_problem(w, precision=precision, max_steps=3000,
+                                lambda_tol=1e-13, resid_tol=1e-9,
+                                pcg_rtol=1e-10)
+    _, _, rep_e = gu.solve(exact, w.U0())
+    gu.note(f"pcg_reduce 1e-2: {rep.steps} steps, {rep.pcg_iters} CG; "
+            f"without: {rep_e.steps} steps, {rep_e.pcg_iters} CG")
+    assert rep.pcg_iters < rep_e.pcg_iters
+
+
 CONVERGED_CASES = [
     ("ho_10", dict(kind="ho", nc=10, N=4, m=0)),
     ("sc_12_m4", dict(kind="sc", nc=12, N=6, m=4)),
