@@ -54,7 +54,8 @@ TRAFFIC = {"fp64": os.path.join(PROFILES, "linear96_fp64_traffic.md"),
            "mixed": os.path.join(PROFILES, "linear96_mixed_traffic.md")}
 SOLVER_SRC = os.path.join(ROOT, "paper_1405_0260_amd", "csrc", "solver.hip")
 KERNEL_NAMES = {"cg_spmm": "spmm_cm_kernel", "cg_rupd": "rupd_alpha_kernel",
-                "cg_pupd": "pupd_beta_kernel"}
+                "cg_pupd": "pupd_beta_kernel", "rr_spmm": "spmm_dual_kernel",
+                "gram": "gram_kernel", "rotate": "rotate_kernel"}
 
 
 def solver_code_sha():
@@ -180,6 +181,31 @@ def algorithmic_bytes(stage, n, nnz, vec_bytes, mat_bytes, diag_bytes):
     if stage == "cg_pupd":   # read X, P, R, D^-1; write X, P
         return n * diag_bytes, 5 * n * vec_bytes
     raise KeyError(stage)
+
+
+def rr_stage_rates(td, n, nnz, nt, emitting=True):
+    """Rates of the once-per-step Rayleigh-Ritz kernels from a timed solve,
+    on the algorithmic bytes of each launch (FP64): the dual SpMM reads
+    the matrix pair and W and writes H W and M W, z (8 + 8 + 4) + 4 (n + 1)
+    + 3 n N_t 8; the Gram reads W, H W and M W, 3 n N_t 8; the rotation
+    reads them and writes U and, in the library's loops, the next step's
+    start state x0, r0, p0, 7 n N_t 8 (6 when it stores H U, M U).  A
+    stage's time includes its finaliser (gram_final about 9 %, rotate_final
+    about 2 % of the stage), and its launch count counts both kernels."""
+    per = {"rr_spmm": (nnz * 20 + 4 * (n + 1) + 3 * n * nt * 8, 1),
+           "gram": (3 * n * nt * 8, 2),
+           "rotate": ((7 if emitting else 6) * n * nt * 8, 2)}
+    out = {}
+    for st, (b, kpl) in per.items():
+        s_ = td["stages"].get(st)
+        if not s_ or s_["ms"] <= 0 or s_["launches"] == 0:
+            continue
+        calls = s_["launches"] // kpl
+        out[st] = {"total_ms": s_["ms"], "launches": calls,
+                   "us_per_launch": 1e3 * s_["ms"] / calls,
+                   "bytes_per_launch": float(b),
+                   "gbs": b * calls / (s_["ms"] * 1e-3) / 1e9}
+    return out
 
 
 def z_march(nc):
@@ -314,10 +340,12 @@ class Solver:
         }
 
     def roofline(self):
-        """Roofline of the dominant CG kernel from one event-timed solve
-        (dispatch-stamped HIP events on the launch stream), plus the whole
-        CG iteration, every stage's share of kernel time and the Gram's
-        FP64 MFMA rate."""
+        """Roofline of the dominant kernel (the CG kernels and the
+        once-per-step Rayleigh-Ritz kernels, whichever takes the most time)
+        from one event-timed solve (dispatch-stamped HIP events on the
+        launch stream), every such kernel's rate beside it, the whole CG
+        iteration, every stage's share of kernel time and the Gram's FP64
+        MFMA rate."""
         w, prec = self.w, self.prec
         n, Nt = w.n_dof, w.Nt
         _, rep_t, prob_t, tim = self.solve(timing=True)
@@ -328,8 +356,10 @@ class Solver:
         nv = (w.nc + 1) ** 3 if zm else None
         stages, it_bytes, it_own = cg_stage_rates(td, n, prob_t.nnz, vec_b,
                                                   nv)
-        dom = max(stages, key=lambda k: stages[k]["total_ms"])
-        d = stages[dom]
+        rr = rr_stage_rates(td, n, prob_t.nnz, Nt)
+        both = dict(stages, **rr)
+        dom = max(both, key=lambda k: both[k]["total_ms"])
+        d = both[dom]
         kname = KERNEL_NAMES[dom]
         if dom == "cg_spmm" and zm:
             kname = "spmm_zmf_kernel"
@@ -353,6 +383,10 @@ class Solver:
             "launches": d["launches"],
             "active_cols_avg": round(td["cg_col_iters"] /
                                      max(1, td["cg_iters"]), 2),
+            "kernels_frac": {KERNEL_NAMES[k] if k != "cg_spmm" or not zm
+                             else "spmm_zmf_kernel":
+                             round(v["gbs"] / HBM_PEAK_GBS, 4)
+                             for k, v in both.items()},
             "cg_stage_gbs": {k: round(v["gbs"], 1) for k, v in stages.items()},
             "cg_stage_own_format_gbs": {k: round(v["own_gbs"], 1)
                                         for k, v in stages.items()},

@@ -2564,16 +2564,45 @@ __device__ __forceinline__ void spmm_dual_body(const Desc& d, int vb, int rr,
   double* wa = reinterpret_cast<double*>(smem);
   double* wb = wa + kStencil * g.tr;
   const bool two = needA && needM;
-  for (TileWalk w = tile_walk(g.ntiles, g.lb, g.nb); w.t < w.end;
-       w.t += w.step) {
+  const double* da = needA ? d.diagA : d.diagM;
+  const double* db = two ? d.diagM : nullptr;
+  // A tile's coefficients fit one per thread (15 tr <= 256: 15 or more
+  // chunks per row): the next tile's are loaded into registers before this
+  // tile's products, so their latency overlaps the products' loads, and
+  // stored to LDS at the top of the next iteration.
+  const bool pf = kStencil * g.tr <= kBlock;
+  double na = 0.0, nm = 0.0;
+  auto prefetch = [&](long long t) {
+    const long long r0 = t * g.tr;
+    const int rows = (int)min((long long)g.tr, d.n - r0);
+    const int e = threadIdx.x;
+    if (e < kStencil * rows) {
+      const int s = e / rows, lr = e - s * rows;
+      na = ldg(da + (size_t)s * d.n + r0 + lr);
+      if (two) nm = ldg(db + (size_t)s * d.n + r0 + lr);
+    }
+  };
+  TileWalk w = tile_walk(g.ntiles, g.lb, g.nb);
+  if (pf && w.t < w.end) prefetch(w.t);
+  for (; w.t < w.end; w.t += w.step) {
     const long long r0 = w.t * g.tr;
     const int rows = (int)min((long long)g.tr, d.n - r0);
-    if (two)
-      stage_weights<double, true>(d.diagA, d.diagM, d.n, r0, rows, g.tr, wa,
-                                  wb);
-    else
-      stage_weights<double, false>(needA ? d.diagA : d.diagM, nullptr, d.n,
-                                   r0, rows, g.tr, wa, nullptr);
+    if (pf) {
+      __syncthreads();  // the previous tile's products are done with LDS
+      const int e = threadIdx.x;
+      if (e < kStencil * rows) {
+        const int s = e / rows, lr = e - s * rows;
+        wa[s * g.tr + lr] = na;
+        if (two) wb[s * g.tr + lr] = nm;
+      }
+      __syncthreads();
+      if (w.t + w.step < w.end) prefetch(w.t + w.step);
+    } else if (two) {
+      stage_weights<double, true>(da, db, d.n, r0, rows, g.tr, wa, wb);
+    } else {
+      stage_weights<double, false>(da, nullptr, d.n, r0, rows, g.tr, wa,
+                                   nullptr);
+    }
     if (g.lr >= rows) continue;
     const long long row = r0 + g.lr;
     double ax[V], mx[V], self[V];
