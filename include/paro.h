@@ -106,7 +106,8 @@ typedef struct paro_problem paro_problem;   /* opaque, host memory only */
 
 /* Fill `opts` with defaults: m = 0, max_steps = 200, pcg_maxit = 10000,
  * FP64, automatic shift, lambda_tol = 1e-12, resid_tol = 1e-8,
- * pcg_rtol = 1e-10, inner_rtol = 1e-5.  N must still be set. */
+ * pcg_rtol = 1e-10, inner_rtol = 1e-5, pcg_reduce = 0 (source solves to
+ * pcg_rtol).  N must still be set. */
 void paro_default_opts(paro_opts_t* opts);
 
 /* Sizes for a box and options, host only.  n_dof = (nx-1)(ny-1)(nz-1);
