@@ -2684,7 +2684,7 @@ __device__ __forceinline__ void gram_body(const Desc& d, int vb,
   // GU steps per group: their loads (unconditional, clamped addresses;
   // masked values are 0) are in flight together before the MFMAs, which
   // run step by step in the same order as one step at a time.
-  constexpr int GU = NT16 <= 1 ? 8 : (NT16 == 2 ? 4 : 2);
+  constexpr int GU = NT16 <= 1 ? 8 : (NT16 <= 3 ? 4 : 2);
   for (long long st0 = s0; st0 < s1; st0 += GU) {
     double a[GU][NT16], y1[GU][NT16], y2[GU][NT16];
 #pragma unroll
