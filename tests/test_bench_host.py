@@ -1,5 +1,5 @@
 """Host logic of bench.py (no GPU): the algorithmic byte model of the CG
-kernels, the rates derived from a timing record, the guard that ties a
+and Rayleigh-Ritz kernels, the rates derived from a timing record, the guard that ties a
 committed traffic summary to the solver source it was measured on, and the
 one-GPU contract of the command line."""
 import os
@@ -55,6 +55,31 @@ def test_stage_rates_from_a_timing_record():
     assert stages["cg_spmm"]["bytes_per_launch"] == spmm / 10
     assert abs(stages["cg_spmm"]["gbs"] - spmm / 0.5e-3 / 1e9) < 1e-9
     assert abs(stages["cg_rupd"]["us_per_launch"] - 25.0) < 1e-12
+
+
+def test_rayleigh_ritz_rates_from_a_timing_record():
+    """The once-per-step kernels' algorithmic bytes per launch: the dual
+    SpMM reads the matrix pair (CSR figure) and W and writes H W, M W; the
+    Gram reads W, H W, M W; the emitting rotation reads them and writes U
+    and the next start's x0, r0, p0.  Gram and rotation stages count two
+    kernels per launch (their finalisers)."""
+    n, nnz, nt = 3000, 42000, 40
+    td = {"stages": {"rr_spmm": {"ms": 2.0, "launches": 5},
+                     "gram": {"ms": 1.0, "launches": 10},
+                     "rotate": {"ms": 3.0, "launches": 10},
+                     "small_eig": {"ms": 1.0, "launches": 5}}}
+    rr = bench.rr_stage_rates(td, n, nnz, nt)
+    assert set(rr) == {"rr_spmm", "gram", "rotate"}
+    assert rr["rr_spmm"]["bytes_per_launch"] == (
+        nnz * 20 + 4 * (n + 1) + 3 * n * nt * 8)
+    assert rr["gram"]["bytes_per_launch"] == 3 * n * nt * 8
+    assert rr["rotate"]["bytes_per_launch"] == 7 * n * nt * 8
+    assert rr["gram"]["launches"] == 5 and rr["rotate"]["launches"] == 5
+    assert abs(rr["rotate"]["us_per_launch"] - 600.0) < 1e-9
+    assert abs(rr["rr_spmm"]["gbs"] - rr["rr_spmm"]["bytes_per_launch"] * 5
+               / 2.0e-3 / 1e9) < 1e-9
+    assert bench.rr_stage_rates(td, n, nnz, nt, emitting=False)[
+        "rotate"]["bytes_per_launch"] == 6 * n * nt * 8
 
 
 def test_z_march_rule_matches_the_library_meshes():
