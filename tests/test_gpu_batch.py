@@ -22,9 +22,10 @@ def _torch():
     return torch
 
 
-def members(precision=pb.PARO_FP64):
+def members(precision=pb.PARO_FP64, reduce=(0.0, 0.0, 0.0, 0.0)):
     """Four small uneven problems: harmonic and soft-Coulomb, cubic and
-    non-cubic meshes, even and odd N + m."""
+    non-cubic meshes, even and odd N + m; `reduce`: each member's
+    pcg_reduce."""
     ws = [
         inputs.harmonic(nc=12, N=4, m=6, seed=21, max_steps=300),
         inputs.molecule(nc=10, N=4, m=2, lo=-6.0, hi=6.0, seed=22,
@@ -34,10 +35,10 @@ def members(precision=pb.PARO_FP64):
                         pot_seed=26, max_steps=300),
     ]
     probs = []
-    for w in ws:
+    for w, eta in zip(ws, reduce):
         probs.append(gu.workload_problem(
             w, max_steps=w.max_steps, lambda_tol=1e-12, resid_tol=1e-9,
-            pcg_rtol=1e-10, precision=precision))
+            pcg_rtol=1e-10, pcg_reduce=eta, precision=precision))
     return ws, probs
 
 
@@ -74,6 +75,32 @@ def test_batch_solve_matches_alone_and_dense(precision):
         assert m_orthonormality_error(M, U_b) < 1e-11, k
         q = closed_prefix(lam_ref, w.N)
         assert subspace_sine(M, U_b[:, :q], U_ref[:, :q]) < 1e-6, k
+
+
+@pytest.mark.parametrize("precision", [pb.PARO_FP64, pb.PARO_FP32_INNER])
+def test_batch_with_inexact_solves_matches_alone(precision):
+    """Members with different pcg_reduce (inexact source solves: each
+    member's own stopping threshold max(rtol ||b||, pcg_reduce ||r0||) from
+    its own descriptor) in one batch: every member bitwise equal to its
+    solve alone, and at the dense eigenpairs."""
+    torch = _torch()
+    ws, probs = members(precision, reduce=(1e-2, 0.0, 1e-1, 1e-2))
+    batch = pb.Batch(len(probs))
+    U0s = [gu.to_dev(w.U0()) for w in ws]
+    lams, Us = outputs(probs)
+    reps = pb.paro_batch_solve(batch, probs, U0s, lams, Us)
+    torch.cuda.synchronize()
+    for k, (w, p, r) in enumerate(zip(ws, probs, reps)):
+        gu.note(f"member {k}: status {r.status}, {r.steps} steps, "
+                f"{r.pcg_iters} CG")
+        assert r.status == pb.PARO_OK, (k, r.as_dict())
+        lam_a, U_a, rep_a = gu.solve(p, w.U0())
+        assert rep_a.steps == r.steps, k
+        assert np.array_equal(lam_a, lams[k].cpu().numpy()), k
+        assert np.array_equal(U_a, Us[k].cpu().numpy()), k
+        H, M, _ = gu.oracle_matrices(w.nc, w.lo, w.hi, w.V)
+        lam_ref, _ = reference.dense_lowest(H, M, w.Nt + 1)
+        assert rel_lambda_err(lam_a[:w.N], lam_ref[:w.N]) < 1e-8, k
 
 
 def test_batch_steps_match_single_steps():
