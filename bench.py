@@ -119,6 +119,12 @@ def parse():
                     help="run warmup + timed solves only (for rocprofv3)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="FP32 inner CG residual reduction per refinement")
+    ap.add_argument("--pcg-rtol", type=float, default=PCG_RTOL,
+                    help="source solves' floor relative to ||b|| (the linear "
+                         "workloads; the Kohn-Sham leg keeps 1e-7)")
+    ap.add_argument("--pcg-reduce", type=float, default=PCG_REDUCE,
+                    help="source solves also stop at this fraction of their "
+                         "start's residual (0: to pcg-rtol only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="with --profile-only: first copy a 256 MiB buffer "
                          "(a plain copy kernel of known size, the reference "
@@ -412,6 +418,8 @@ class Solver:
 
 def main():
     args = parse()
+    global PCG_RTOL, PCG_REDUCE
+    PCG_RTOL, PCG_REDUCE = args.pcg_rtol, args.pcg_reduce
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} "
               "is not supported (the multi-GPU sharding is a design note, "
