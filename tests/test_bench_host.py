@@ -155,6 +155,20 @@ def test_member_golden_format(tmp_path):
     assert set(bench.member_errors(str(g), lams, ws)) == {"a"}
 
 
+def test_source_solve_tolerances_default_and_flags(monkeypatch):
+    """The linear workloads' inner tolerances: pcg_rtol one decade below
+    resid_tol and pcg_reduce 1e-2 by default; the flags override both."""
+    assert bench.PCG_RTOL == pytest.approx(bench.RESID_TOL / 10)
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.pcg_rtol, a.pcg_reduce) == (bench.PCG_RTOL, bench.PCG_REDUCE)
+    assert bench.PCG_REDUCE == 1e-2
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--pcg-reduce", "0",
+                                      "--pcg-rtol", "1e-10"])
+    a = bench.parse()
+    assert (a.pcg_rtol, a.pcg_reduce) == (1e-10, 0.0)
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
                         "--gpus", "2"], capture_output=True, text=True,
